@@ -1,0 +1,302 @@
+"""FP64 CPU oracle for the DARB-Splatting rasterizer.
+
+TEST INFRASTRUCTURE ONLY: the test-suite, the smoke check and the benchmark's
+CPU-baseline leg may import this package; the product path never does.  It
+shares no code with the HIP implementation (see ``oracle.c``); both sides only
+consume the same seeded inputs.
+
+Functions here are thin ctypes marshalling around ``liboracle.so`` (plain C,
+double precision) plus two pure-Python helpers that the paper fixes:
+
+* :func:`fd_grad` -- central finite differences of a scalar loss computed by
+  the oracle's forward (checks the analytic backward against the forward);
+* :func:`psi_closed_form` in ``psi.py`` -- the covariance ratio of a 3D radial
+  kernel's 2D marginal, which reproduces the paper's correction factors.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "oracle.c")
+
+GAUSS, HALF_COS, RAISED_COS, SINC, IMQ, IMQ_SQRT, PARABOLA = range(7)
+
+
+def build(force: bool = True) -> str:
+    """Compile ``oracle.c`` with gcc (-O2, OpenMP, strict IEEE: no fast-math)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        cmd = ["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-fno-fast-math", "-ffp-contract=off",
+               "-std=c11", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("viewmat", ctypes.c_double * 16), ("campos", ctypes.c_double * 3),
+                ("fx", ctypes.c_double), ("fy", ctypes.c_double), ("cx", ctypes.c_double),
+                ("cy", ctypes.c_double), ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("near_z", ctypes.c_double), ("jac_clamp", ctypes.c_double), ("dilation", ctypes.c_double)]
+
+
+class Kernel(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("xi", ctypes.c_double), ("psi", ctypes.c_double),
+                ("e_max", ctypes.c_double)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("alpha_min", ctypes.c_double), ("alpha_max", ctypes.c_double), ("t_min", ctypes.c_double),
+                ("bg", ctypes.c_double * 3)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=True)
+        L = ctypes.CDLL(_LIB_PATH)
+        d, i32, i64, vp = ctypes.c_double, ctypes.c_int32, ctypes.c_long, ctypes.c_void_p
+        L.orc_kernel_value.restype = d
+        L.orc_kernel_value.argtypes = [i32, d, d]
+        L.orc_kernel_deriv.restype = d
+        L.orc_kernel_deriv.argtypes = [i32, d, d]
+        L.orc_sh_basis.argtypes = [vp, vp, vp]
+        L.orc_quat_to_rot.argtypes = [vp, vp]
+        L.orc_preprocess.argtypes = [vp, vp, i64, vp, vp, vp, vp, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_composite.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, i64, vp,
+                                    ctypes.c_int, vp, vp, vp, vp, vp]
+        L.orc_composite_bwd.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, i64, vp,
+                                        vp, ctypes.c_int, vp, vp, vp, vp]
+        L.orc_preprocess_bwd.argtypes = [vp, vp, i64, vp, vp, vp, vp, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp,
+                                         vp, vp]
+        L.orc_bin.restype = i64
+        L.orc_bin.argtypes = [i64, vp, vp, vp, ctypes.c_int, ctypes.c_int, i64, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+# --------------------------------------------------------------------------
+# parameter structs
+# --------------------------------------------------------------------------
+
+@dataclass
+class KernelSpec:
+    kind: int
+    xi: float
+    psi: float
+    e_max: float
+
+    def c(self) -> Kernel:
+        return Kernel(self.kind, self.xi, self.psi, self.e_max)
+
+
+def make_camera(viewmat, campos, fx, fy, cx, cy, width, height, near_z=0.2, jac_clamp=1.3, dilation=0.3) -> Camera:
+    c = Camera()
+    vm = np.asarray(viewmat, dtype=np.float64).reshape(16)
+    for k in range(16):
+        c.viewmat[k] = float(vm[k])
+    for k in range(3):
+        c.campos[k] = float(campos[k])
+    c.fx, c.fy, c.cx, c.cy = float(fx), float(fy), float(cx), float(cy)
+    c.width, c.height = int(width), int(height)
+    c.near_z, c.jac_clamp, c.dilation = float(near_z), float(jac_clamp), float(dilation)
+    return c
+
+
+def make_opts(alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4, bg=(0.0, 0.0, 0.0)) -> Opts:
+    o = Opts()
+    o.alpha_min, o.alpha_max, o.t_min = float(alpha_min), float(alpha_max), float(t_min)
+    for k in range(3):
+        o.bg[k] = float(bg[k])
+    return o
+
+
+def camera_from_scene(cam: dict) -> Camera:
+    """Camera struct from a scene-generator camera dict (values as FP32 -> FP64)."""
+    return make_camera(np.asarray(cam["viewmat"], np.float32).astype(np.float64),
+                       np.asarray(cam["campos"], np.float32).astype(np.float64),
+                       np.float32(cam["fx"]), np.float32(cam["fy"]), np.float32(cam["cx"]),
+                       np.float32(cam["cy"]), cam["width"], cam["height"], np.float32(cam["near_z"]),
+                       np.float32(cam["jac_clamp"]), np.float32(cam["dilation"]))
+
+
+# --------------------------------------------------------------------------
+# wrappers
+# --------------------------------------------------------------------------
+
+def kernel_value(kind: int, xi: float, E) -> np.ndarray:
+    L = lib()
+    E = np.atleast_1d(np.asarray(E, dtype=np.float64))
+    return np.array([L.orc_kernel_value(kind, xi, float(e)) for e in E])
+
+
+def kernel_deriv(kind: int, xi: float, E) -> np.ndarray:
+    L = lib()
+    E = np.atleast_1d(np.asarray(E, dtype=np.float64))
+    return np.array([L.orc_kernel_deriv(kind, xi, float(e)) for e in E])
+
+
+def sh_basis(d):
+    d = _f64(d)
+    Y = np.zeros(16)
+    dY = np.zeros((16, 3))
+    lib().orc_sh_basis(_p(d), _p(Y), _p(dY))
+    return Y, dY
+
+
+def quat_to_rot(q):
+    q = _f64(q)
+    R = np.zeros(9)
+    lib().orc_quat_to_rot(_p(q), _p(R))
+    return R.reshape(3, 3)
+
+
+def preprocess(cam: Camera, k: KernelSpec, means, scales, quats, sh, deg: int) -> dict:
+    """means/scales [3,n], quats [4,n], sh [(deg+1)^2, 3, n]."""
+    means, scales, quats, sh = _f64(means), _f64(scales), _f64(quats), _f64(sh)
+    n = means.shape[1]
+    out = dict(xy=np.zeros((n, 2)), depth=np.zeros(n), radius=np.zeros(n, np.int32), conic=np.zeros((n, 3)),
+               rgb=np.zeros((n, 3)), clamped=np.zeros(n, np.uint8), visible=np.zeros(n, np.int32),
+               cov2d=np.zeros((n, 3)))
+    kc = k.c()
+    lib().orc_preprocess(ctypes.byref(cam), ctypes.byref(kc), n, _p(means), _p(scales), _p(quats), _p(sh), deg,
+                         _p(out["xy"]), _p(out["depth"]), _p(out["radius"]), _p(out["conic"]), _p(out["rgb"]),
+                         _p(out["clamped"]), _p(out["visible"]), _p(out["cov2d"]))
+    return out
+
+
+def full_pixels(width: int, height: int) -> np.ndarray:
+    ys, xs = np.meshgrid(np.arange(height, dtype=np.int32), np.arange(width, dtype=np.int32), indexing="ij")
+    return np.ascontiguousarray(np.stack([xs.ravel(), ys.ravel()], axis=1).astype(np.int32))
+
+
+def composite(proj: dict, opac, k: KernelSpec, opts: Opts, width: int, height: int, pix=None,
+              use_grid: bool = True) -> dict:
+    """Render the listed pixels ([m,2] int (x, y)); all pixels when pix is None.
+
+    ``proj`` holds xy [n,2], conic [n,3], rgb [n,3], depth [n], and either
+    ``visible`` or ``valid`` [n] (nonzero = rendered)."""
+    xy, conic, rgb, depth = _f64(proj["xy"]), _f64(proj["conic"]), _f64(proj["rgb"]), _f64(proj["depth"])
+    valid = np.ascontiguousarray(np.asarray(proj.get("visible", proj.get("valid")), dtype=np.int32))
+    opac = _f64(opac)
+    n = xy.shape[0]
+    if pix is None:
+        pix = full_pixels(width, height)
+    pix = np.ascontiguousarray(np.asarray(pix, dtype=np.int32))
+    m = pix.shape[0]
+    out = dict(rgb=np.zeros((m, 3)), T=np.zeros(m), last=np.zeros(m, np.int64), ncontrib=np.zeros(m, np.int32),
+               margin=np.zeros(m))
+    kc = k.c()
+    lib().orc_composite(n, _p(xy), _p(conic), _p(opac), _p(rgb), _p(depth), _p(valid), ctypes.byref(kc),
+                        ctypes.byref(opts), width, height, m, _p(pix), int(use_grid), _p(out["rgb"]), _p(out["T"]),
+                        _p(out["last"]), _p(out["ncontrib"]), _p(out["margin"]))
+    return out
+
+
+def composite_bwd(proj: dict, opac, k: KernelSpec, opts: Opts, width: int, height: int, G, pix=None,
+                  use_grid: bool = True) -> dict:
+    """Gradients of sum_p G_p . I_p w.r.t. xy [n,2], conic [n,3] (a, scalar b, c), opacity [n], rgb [n,3]."""
+    xy, conic, rgb, depth = _f64(proj["xy"]), _f64(proj["conic"]), _f64(proj["rgb"]), _f64(proj["depth"])
+    valid = np.ascontiguousarray(np.asarray(proj.get("visible", proj.get("valid")), dtype=np.int32))
+    opac = _f64(opac)
+    n = xy.shape[0]
+    if pix is None:
+        pix = full_pixels(width, height)
+    pix = np.ascontiguousarray(np.asarray(pix, dtype=np.int32))
+    G = _f64(G).reshape(pix.shape[0], 3)
+    out = dict(xy=np.zeros((n, 2)), conic=np.zeros((n, 3)), opacity=np.zeros(n), rgb=np.zeros((n, 3)))
+    kc = k.c()
+    lib().orc_composite_bwd(n, _p(xy), _p(conic), _p(opac), _p(rgb), _p(depth), _p(valid), ctypes.byref(kc),
+                            ctypes.byref(opts), width, height, pix.shape[0], _p(pix), _p(G), int(use_grid),
+                            _p(out["xy"]), _p(out["conic"]), _p(out["opacity"]), _p(out["rgb"]))
+    return out
+
+
+def preprocess_bwd(cam: Camera, k: KernelSpec, means, scales, quats, sh, deg: int, g2d: dict) -> dict:
+    means, scales, quats, sh = _f64(means), _f64(scales), _f64(quats), _f64(sh)
+    n = means.shape[1]
+    gxy, gcon, gop, grgb = _f64(g2d["xy"]), _f64(g2d["conic"]), _f64(g2d["opacity"]), _f64(g2d["rgb"])
+    out = dict(means=np.zeros((3, n)), scales=np.zeros((3, n)), quats=np.zeros((4, n)), opacity=np.zeros(n),
+               sh=np.zeros(sh.shape))
+    kc = k.c()
+    lib().orc_preprocess_bwd(ctypes.byref(cam), ctypes.byref(kc), n, _p(means), _p(scales), _p(quats), _p(sh), deg,
+                             _p(gxy), _p(gcon), _p(gop), _p(grgb), _p(out["means"]), _p(out["scales"]),
+                             _p(out["quats"]), _p(out["opacity"]), _p(out["sh"]))
+    return out
+
+
+def bin_sort(xy, radius, depth, width: int, height: int, cap: int | None = None):
+    """Binning reference on FP32 xy [n,2], int32 radius [n], FP32 depth [n].
+
+    Returns (K, keys u64[K], vals u32[K], ranges u32[tiles,2])."""
+    xy = np.ascontiguousarray(np.asarray(xy, dtype=np.float32))
+    radius = np.ascontiguousarray(np.asarray(radius, dtype=np.int32))
+    depth = np.ascontiguousarray(np.asarray(depth, dtype=np.float32))
+    n = xy.shape[0]
+    gx, gy = (width + 15) // 16, (height + 15) // 16
+    ranges = np.zeros((gx * gy, 2), np.uint32)
+    K = lib().orc_bin(n, _p(xy), _p(radius), _p(depth), width, height, 0, None, None, _p(ranges))
+    if cap is None:
+        cap = K
+    keys = np.zeros(max(K, 1), np.uint64)
+    vals = np.zeros(max(K, 1), np.uint32)
+    K = lib().orc_bin(n, _p(xy), _p(radius), _p(depth), width, height, cap, _p(keys), _p(vals), _p(ranges))
+    return K, keys[:K], vals[:K], ranges
+
+
+# --------------------------------------------------------------------------
+# end-to-end helpers
+# --------------------------------------------------------------------------
+
+def render(cam: Camera, k: KernelSpec, opts: Opts, params: dict, pix=None, use_grid=True):
+    """preprocess + composite.  params: means, scales, quats, opacity, sh, sh_degree."""
+    proj = preprocess(cam, k, params["means"], params["scales"], params["quats"], params["sh"],
+                      params["sh_degree"])
+    img = composite(proj, params["opacity"], k, opts, cam.width, cam.height, pix=pix, use_grid=use_grid)
+    return proj, img
+
+
+def render_bwd(cam: Camera, k: KernelSpec, opts: Opts, params: dict, G, pix=None, use_grid=True):
+    proj = preprocess(cam, k, params["means"], params["scales"], params["quats"], params["sh"],
+                      params["sh_degree"])
+    g2d = composite_bwd(proj, params["opacity"], k, opts, cam.width, cam.height, G, pix=pix, use_grid=use_grid)
+    g3d = preprocess_bwd(cam, k, params["means"], params["scales"], params["quats"], params["sh"],
+                         params["sh_degree"], g2d)
+    return proj, g2d, g3d
+
+
+def loss_linear(cam: Camera, k: KernelSpec, opts: Opts, params: dict, G, pix=None) -> float:
+    """L = sum_p G_p . I_p rendered by the oracle (the scalar the FD driver differentiates)."""
+    _, img = render(cam, k, opts, params, pix=pix)
+    return float(np.sum(np.asarray(G, dtype=np.float64).reshape(-1, 3) * img["rgb"]))
+
+
+def fd_grad(fun, x: np.ndarray, index: tuple, rel_h: float = 1e-6) -> float:
+    """Central difference of scalar ``fun(x)`` w.r.t. ``x[index]``, h = rel_h * max(1, |x|)."""
+    x = np.array(x, dtype=np.float64, copy=True)
+    x0 = float(x[index])
+    h = rel_h * max(1.0, abs(x0))
+    x[index] = x0 + h
+    fp = fun(x)
+    x[index] = x0 - h
+    fm = fun(x)
+    return (fp - fm) / (2.0 * h)

@@ -1,0 +1,172 @@
+"""Pins of the oracle's per-pixel composite and binning reference against
+closed forms, invariants and brute force (no GPU)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2501_12369_amd import scenes
+
+PI = math.pi
+HC = oracle.KernelSpec(oracle.HALF_COS, 18.0 / PI, 1.36, 9.0)
+GA = oracle.KernelSpec(oracle.GAUSS, 2.0, 1.0, 9.0)
+
+
+def _proj(xy, conic, rgb, depth):
+    n = len(depth)
+    return dict(xy=np.asarray(xy, float).reshape(n, 2), conic=np.asarray(conic, float).reshape(n, 3),
+                rgb=np.asarray(rgb, float).reshape(n, 3), depth=np.asarray(depth, float), valid=np.ones(n, np.int32))
+
+
+def _E(px, py, xy, q):
+    dx, dy = xy[0] - px, xy[1] - py
+    return q[0] * dx * dx + 2 * q[1] * dx * dy + q[2] * dy * dy
+
+
+@pytest.mark.parametrize("kname", ["HC", "G"])
+def test_single_splat_closed_form(orc, kname):
+    k = HC if kname == "HC" else GA
+    W, H = 48, 40
+    xy, q, rgb, o = (20.3, 17.8), (0.05, 0.012, 0.08), (0.2, 0.5, 0.9), 0.7
+    out = orc.composite(_proj(xy, q, rgb, [3.0]), [o], k, orc.make_opts(), W, H)
+    pix = orc.full_pixels(W, H)
+    for p in range(pix.shape[0]):
+        E = _E(pix[p, 0], pix[p, 1], xy, q)
+        w = math.cos(E * PI / 18) if kname == "HC" else math.exp(-E / 2)
+        a = min(0.99, o * w) if E <= 9.0 else 0.0
+        if a < 1 / 255:
+            a = 0.0
+        assert out["rgb"][p] == pytest.approx(np.array(rgb) * a, abs=1e-15)
+        assert out["T"][p] == pytest.approx(1.0 - a, abs=1e-15)
+        assert out["last"][p] == (0 if a > 0 else -1)
+
+
+def test_two_splats_order_by_depth(orc):
+    W, H = 32, 32
+    xy = [(15.0, 16.0), (17.0, 15.0)]
+    q = [(0.02, 0.0, 0.02), (0.03, 0.01, 0.025)]
+    rgb = [(1.0, 0.0, 0.2), (0.0, 1.0, 0.6)]
+    o = [0.6, 0.8]
+    pix = np.array([[16, 16], [10, 12], [20, 18]], np.int32)
+    for d0, d1 in ((1.0, 2.0), (2.0, 1.0)):
+        out = orc.composite(_proj(xy, q, rgb, [d0, d1]), o, HC, orc.make_opts(), W, H, pix=pix)
+        for p in range(3):
+            a = [min(0.99, o[j] * math.cos(_E(pix[p, 0], pix[p, 1], xy[j], q[j]) * PI / 18)) for j in range(2)]
+            order = (0, 1) if d0 < d1 else (1, 0)
+            f, b = order
+            want = a[f] * np.array(rgb[f]) + (1 - a[f]) * a[b] * np.array(rgb[b])
+            assert out["rgb"][p] == pytest.approx(want, abs=1e-15)
+            assert out["T"][p] == pytest.approx((1 - a[0]) * (1 - a[1]), abs=1e-15)
+            assert out["last"][p] == b
+
+
+def test_weights_sum_to_one_minus_T(orc):
+    ps = scenes.projected(11, 400, 96, 80, culled_frac=0.0)
+    proj = dict(xy=ps["xy"], conic=ps["conic_o"][:, :3], rgb=np.ones((400, 3)), depth=ps["depth"],
+                valid=np.ones(400, np.int32))
+    for k in (HC, GA):
+        out = orc.composite(proj, ps["conic_o"][:, 3], k, orc.make_opts(), 96, 80)
+        assert np.allclose(out["rgb"], (1.0 - out["T"])[:, None], atol=1e-12)
+        assert np.all(out["T"] >= 1e-4) and np.all(out["T"] <= 1.0)
+        assert np.all(out["rgb"] <= 1.0 + 1e-12)
+        assert out["ncontrib"].max() > 3
+
+
+def test_support_cut_is_exact(orc):
+    # Gaussian at high opacity: just outside E = 9 contributes nothing, just inside it does
+    xy, q = (10.0, 10.0), (1.0, 0.0, 1.0)
+    pix = np.array([[13, 10]], np.int32)  # E = 9 exactly: inside (inclusive)
+    out = orc.composite(_proj(xy, q, (1, 1, 1), [1.0]), [0.9], GA, orc.make_opts(), 32, 32, pix=pix)
+    assert out["rgb"][0, 0] == pytest.approx(0.9 * math.exp(-4.5), rel=1e-14)
+    q2 = (1.0 + 1e-6, 0.0, 1.0)  # E just above 9
+    out = orc.composite(_proj(xy, q2, (1, 1, 1), [1.0]), [0.9], GA, orc.make_opts(), 32, 32, pix=pix)
+    assert out["rgb"][0, 0] == 0.0 and out["T"][0] == 1.0 and out["last"][0] == -1
+    assert out["margin"][0] < 1e-5  # flagged as a decision-ambiguous pixel
+
+
+def test_transmittance_cutoff(orc):
+    # identical fully-covering splats with alpha 0.95: T = 0.05^k; the 4th would drop T below 1e-4
+    n = 6
+    xy = [(8.0, 8.0)] * n
+    q = [(1e-6, 0.0, 1e-6)] * n
+    rgb = [(1.0, 0.5, 0.25)] * n
+    out = orc.composite(_proj(xy, q, rgb, np.arange(1, n + 1) * 1.0), [0.95] * n, GA,
+                        orc.make_opts(), 16, 16, pix=np.array([[8, 8]], np.int32))
+    a = 0.95 * math.exp(-0.0)
+    assert out["ncontrib"][0] == 3
+    assert out["last"][0] == 2
+    assert out["T"][0] == pytest.approx((1 - a) ** 3, rel=1e-14)
+    assert out["rgb"][0, 0] == pytest.approx(1 - (1 - a) ** 3, rel=1e-14)
+
+
+def test_grid_prefilter_equals_brute_force(orc):
+    ps = scenes.projected(12, 3000, 200, 150, sigma_range=(0.5, 20.0))
+    proj = dict(xy=ps["xy"], conic=ps["conic_o"][:, :3], rgb=ps["rgb"], depth=ps["depth"],
+                valid=(ps["radius"] > 0).astype(np.int32))
+    for k in (HC, GA):
+        a = orc.composite(proj, ps["conic_o"][:, 3], k, orc.make_opts(), 200, 150, use_grid=True)
+        b = orc.composite(proj, ps["conic_o"][:, 3], k, orc.make_opts(), 200, 150, use_grid=False)
+        for key in ("rgb", "T", "last", "ncontrib"):
+            assert np.array_equal(a[key], b[key]), key
+
+
+def _brute_bin(ps, W, H):
+    """Every (splat, tile) pair tested directly: tile column tx is covered iff
+    16 tx <= fl(u + R) and fl(u - R) < 16 (tx + 1) (FP32), likewise rows."""
+    gx, gy = (W + 15) // 16, (H + 15) // 16
+    ent = []
+    f32 = np.float32
+    for i in range(len(ps["radius"])):
+        R = ps["radius"][i]
+        if R <= 0:
+            continue
+        u, v = ps["xy"][i]
+        lo_x, hi_x = f32(u) - f32(R), f32(u) + f32(R)
+        lo_y, hi_y = f32(v) - f32(R), f32(v) + f32(R)
+        dbits = int(np.float32(ps["depth"][i]).view(np.uint32))
+        for ty in range(gy):
+            if not (f32(16 * ty) <= hi_y and lo_y < f32(16 * (ty + 1))):
+                continue
+            for tx in range(gx):
+                if f32(16 * tx) <= hi_x and lo_x < f32(16 * (tx + 1)):
+                    ent.append((ty * gx + tx, dbits, i))
+    ent.sort()
+    return ent, gx * gy
+
+
+@pytest.mark.parametrize("W,H", [(200, 150), (64, 64), (37, 21)])
+def test_binning_reference_matches_brute_force(orc, W, H):
+    ps = scenes.projected(13, 500, W, H, sigma_range=(0.3, 15.0))
+    ps["depth"][::7] = ps["depth"][3]  # equal depths: ties must keep index order
+    K, keys, vals, ranges = orc.bin_sort(ps["xy"], ps["radius"], ps["depth"], W, H)
+    ent, ntile = _brute_bin(ps, W, H)
+    assert K == len(ent)
+    want_keys = np.array([(t << 32) | d for t, d, _ in ent], np.uint64)
+    want_vals = np.array([i for _, _, i in ent], np.uint32)
+    assert np.array_equal(keys, want_keys)
+    assert np.array_equal(vals, want_vals)
+    tiles = np.array([t for t, _, _ in ent], np.int64)
+    for t in range(ntile):
+        assert ranges[t, 0] == np.sum(tiles < t) and ranges[t, 1] == np.sum(tiles <= t)
+
+
+def test_binning_covers_support(orc):
+    W, H = 120, 90
+    ps = scenes.projected(14, 200, W, H, culled_frac=0.0)
+    K, keys, vals, ranges = orc.bin_sort(ps["xy"], ps["radius"], ps["depth"], W, H)
+    gx = (W + 15) // 16
+    covered = set((int(k >> np.uint64(32)), int(v)) for k, v in zip(keys, vals))
+    for i in range(200):
+        q = ps["conic_o"][i, :3].astype(np.float64)
+        for py in range(H):
+            for px in range(W):
+                if _E(px, py, ps["xy"][i].astype(np.float64), q) <= 9.0:
+                    assert ((py // 16) * gx + px // 16, i) in covered
+
+
+def test_binning_capacity_overflow(orc):
+    ps = scenes.projected(15, 100, 64, 64)
+    K, _, _, _ = orc.bin_sort(ps["xy"], ps["radius"], ps["depth"], 64, 64)
+    K2, keys, vals, ranges = orc.bin_sort(ps["xy"], ps["radius"], ps["depth"], 64, 64, cap=K - 1)
+    assert K2 == K  # K is still reported; nothing is written beyond capacity

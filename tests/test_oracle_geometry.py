@@ -1,0 +1,204 @@
+"""Pins of the oracle's preprocess (rotation, SH colour, EWA projection,
+radius) against library routines and numerical integration (no GPU)."""
+import math
+
+import numpy as np
+import pytest
+from scipy.integrate import simpson
+from scipy.spatial.transform import Rotation
+
+import oracle
+from paper_2501_12369_amd import scenes
+
+PI = math.pi
+
+
+def test_quat_to_rot_matches_scipy(orc):
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        q = rng.standard_normal(4) * rng.uniform(0.1, 3.0)  # unnormalised
+        R = orc.quat_to_rot(q)
+        Rs = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()  # scipy order (x, y, z, w)
+        assert np.allclose(R, Rs, atol=1e-14)
+        assert np.allclose(R @ R.T, np.eye(3), atol=1e-14)
+        assert np.linalg.det(R) == pytest.approx(1.0, abs=1e-14)
+
+
+def _real_sh_scipy(d):
+    """Real SH (degree <= 3) from scipy's complex harmonics (Condon-Shortley phase):
+    m > 0: sqrt(2) Re Y_l^m, m < 0: sqrt(2) Im Y_l^|m|, m = 0: Y_l^0."""
+    from scipy.special import sph_harm_y
+
+    x, y, z = d
+    theta = math.acos(max(-1.0, min(1.0, z)))
+    phi = math.atan2(y, x)
+    out = []
+    for l in range(4):
+        for m in range(-l, l + 1):
+            c = sph_harm_y(l, abs(m), theta, phi)
+            if m > 0:
+                out.append(math.sqrt(2) * c.real)
+            elif m < 0:
+                out.append(math.sqrt(2) * c.imag)
+            else:
+                out.append(c.real)
+    return np.array(out)
+
+
+def test_sh_basis_matches_scipy(orc):
+    rng = np.random.default_rng(1)
+    for _ in range(30):
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        Y, _ = orc.sh_basis(d)
+        assert np.allclose(Y, _real_sh_scipy(d), atol=1e-13)
+    # known axis values: Y_1,1 = -sqrt(3/4pi) x at +x
+    Y, _ = orc.sh_basis([1.0, 0.0, 0.0])
+    assert Y[3] == pytest.approx(-math.sqrt(3 / (4 * PI)), rel=1e-14)
+    assert Y[0] == pytest.approx(0.5 / math.sqrt(PI), rel=1e-14)
+
+
+def test_sh_basis_gradient_fd(orc):
+    rng = np.random.default_rng(2)
+    d = rng.standard_normal(3)
+    _, dY = orc.sh_basis(d)
+    h = 1e-6
+    for c in range(3):
+        e = np.zeros(3)
+        e[c] = h
+        fd = (orc.sh_basis(d + e)[0] - orc.sh_basis(d - e)[0]) / (2 * h)
+        assert np.allclose(dY[:, c], fd, atol=1e-8)
+
+
+def _single_splat_params(mu, scale, quat, sh=None, deg=0, opacity=0.8):
+    n = 1
+    if sh is None:
+        sh = np.zeros(((deg + 1) ** 2, 3, n))
+    return dict(means=np.asarray(mu, float).reshape(3, 1), scales=np.asarray(scale, float).reshape(3, 1),
+                quats=np.asarray(quat, float).reshape(4, 1), opacity=np.array([opacity]), sh=sh, sh_degree=deg)
+
+
+def _pinhole(cam_d, x):
+    W = cam_d["viewmat"].astype(np.float64)
+    t = W[:3, :3] @ x + W[:3, 3]
+    return np.array([cam_d["fx"] * t[0] / t[2] + cam_d["cx"], cam_d["fy"] * t[1] / t[2] + cam_d["cy"]]), t
+
+
+def _camera(seed):
+    rng = np.random.default_rng(seed)
+    campos = rng.standard_normal(3)
+    campos = 6.0 * campos / np.linalg.norm(campos)
+    target = rng.uniform(-0.3, 0.3, 3)
+    return scenes.camera(scenes.look_at(campos, target), campos, 500.0, 520.0, 320.0, 240.0, 640, 480,
+                         jac_clamp=0.0, dilation=0.0)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_gaussian_projection_matches_integral_of_3d_kernel(orc, seed):
+    """EWA closure: integrating the 3D Gaussian along the direction that the
+    affine (first-order) projection collapses gives a 2D Gaussian whose conic is
+    the oracle's Q (psi = 1, no dilation, no Jacobian clamp)."""
+    cam_d = _camera(seed)
+    rng = np.random.default_rng(100 + seed)
+    mu = rng.uniform(-0.5, 0.5, 3)
+    scale = np.exp(rng.uniform(math.log(0.05), math.log(0.3), 3))
+    q = rng.standard_normal(4)
+    cam = orc.camera_from_scene(cam_d)
+    k = orc.KernelSpec(oracle.GAUSS, 2.0, 1.0, 9.0)
+    proj = orc.preprocess(cam, k, **{kk: v for kk, v in _single_splat_params(mu, scale, q).items()
+                                    if kk in ("means", "scales", "quats", "sh")}, deg=0)
+    assert proj["visible"][0] == 1
+    # mean and depth against the pinhole model evaluated directly
+    u0, t = _pinhole(cam_d, mu)
+    assert np.allclose(proj["xy"][0], u0, rtol=1e-13)
+    assert proj["depth"][0] == pytest.approx(t[2], rel=1e-13)
+    # A = d(pixel)/d(world point) at mu, by central differences of the pinhole model
+    A = np.zeros((2, 3))
+    for c in range(3):
+        e = np.zeros(3)
+        e[c] = 1e-6
+        A[:, c] = (_pinhole(cam_d, mu + e)[0] - _pinhole(cam_d, mu - e)[0]) / 2e-6
+    # 3D covariance from scipy's rotation (independent of the oracle's quaternion code)
+    Rm = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+    Sigma = Rm @ np.diag(scale ** 2) @ Rm.T
+    Sinv = np.linalg.inv(Sigma)
+    _, _, Vt = np.linalg.svd(A)
+    nvec = Vt[2]
+    Apinv = np.linalg.pinv(A)
+    a, b, c_ = proj["conic"][0]
+    Q = np.array([[a, b], [b, c_]])
+    # 2D density on an image-plane grid: integrate N(x) over the line {A x = u}
+    cov2 = np.linalg.inv(Q)
+    span = 3.5 * math.sqrt(np.max(np.linalg.eigvalsh(cov2)))
+    g = np.linspace(-span, span, 41)
+    smax = 6.0 * np.max(scale) / np.linalg.norm(nvec)
+    s = np.linspace(-smax, smax, 801)
+    dens = np.zeros((41, 41))
+    for i, du in enumerate(g):
+        for j, dv in enumerate(g):
+            x0 = Apinv @ np.array([du, dv])
+            pts = x0[None, :] + s[:, None] * nvec[None, :]
+            e = np.einsum("ni,ij,nj->n", pts, Sinv, pts)
+            dens[i, j] = simpson(np.exp(-0.5 * e), x=s)
+    dens /= dens[20, 20]
+    U, V = np.meshgrid(g, g, indexing="ij")
+    model = np.exp(-0.5 * (a * U * U + 2 * b * U * V + c_ * V * V))
+    assert np.max(np.abs(dens - model)) < 1e-6
+
+
+def test_psi_and_dilation_enter_linearly(orc):
+    sc = scenes.object_scale(seed=5, n=200, width=320, height=320)
+    sp = sc["splats"]
+    cam = orc.camera_from_scene(dict(sc["camera"], dilation=0.0))
+    cam_e = orc.camera_from_scene(dict(sc["camera"], dilation=0.3))
+    args = dict(means=sp["means"], scales=sp["scales"], quats=sp["quats"], sh=sp["sh"], deg=3)
+    p1 = orc.preprocess(cam, orc.KernelSpec(oracle.GAUSS, 2.0, 1.0, 9.0), **args)
+    p2 = orc.preprocess(cam_e, orc.KernelSpec(oracle.HALF_COS, 18 / PI, 1.36, 9.0), **args)
+    vis = (p1["visible"] == 1) & (p2["visible"] == 1)
+    assert vis.sum() > 50
+    eps = float(np.float32(0.3))  # the camera's FP32 dilation
+    want = 1.36 * p1["cov2d"][vis] + np.array([eps, 0.0, eps])
+    assert np.allclose(p2["cov2d"][vis], want, rtol=1e-12, atol=1e-12)
+    # conic is the inverse of the 2D covariance
+    for i in np.flatnonzero(vis)[:20]:
+        C = np.array([[p2["cov2d"][i, 0], p2["cov2d"][i, 1]], [p2["cov2d"][i, 1], p2["cov2d"][i, 2]]])
+        Q = np.array([[p2["conic"][i, 0], p2["conic"][i, 1]], [p2["conic"][i, 1], p2["conic"][i, 2]]])
+        assert np.allclose(Q @ C, np.eye(2), atol=1e-10)
+        # radius = ceil(3 sqrt(lambda_max)) with the eigenvalue from LAPACK
+        lam = np.max(np.linalg.eigvalsh(C))
+        assert p2["radius"][i] == math.ceil(3 * math.sqrt(lam))
+
+
+def test_sh_colour_matches_scipy_basis(orc):
+    sc = scenes.object_scale(seed=6, n=64, width=320, height=320)
+    sp = sc["splats"]
+    cam = orc.camera_from_scene(sc["camera"])
+    p = orc.preprocess(cam, orc.KernelSpec(oracle.HALF_COS, 18 / PI, 1.36, 9.0), sp["means"], sp["scales"],
+                       sp["quats"], sp["sh"], 3)
+    campos = sc["camera"]["campos"].astype(np.float64)
+    checked = 0
+    for i in np.flatnonzero(p["visible"]):
+        v = sp["means"][:, i].astype(np.float64) - campos
+        Y = _real_sh_scipy(v / np.linalg.norm(v))
+        col = Y @ sp["sh"][:, :, i].astype(np.float64) + 0.5
+        assert np.allclose(p["rgb"][i], np.maximum(col, 0.0), atol=1e-12)
+        assert p["clamped"][i] == sum(1 << c for c in range(3) if col[c] < 0)
+        checked += 1
+    assert checked > 10
+
+
+def test_degree0_colour_and_culling(orc):
+    sc = scenes.tiny(seed=1)
+    sp = sc["splats"]
+    cam = orc.camera_from_scene(sc["camera"])
+    p = orc.preprocess(cam, orc.KernelSpec(oracle.GAUSS, 2.0, 1.0, 9.0), sp["means"], sp["scales"], sp["quats"],
+                       sp["sh"], 0)
+    y00 = 0.5 / math.sqrt(PI)
+    want = np.maximum(y00 * sp["sh"][0].T.astype(np.float64) + 0.5, 0)
+    assert np.allclose(p["rgb"][p["visible"] == 1], want[p["visible"] == 1], atol=1e-14)
+    # a splat behind the near plane is culled
+    means = sp["means"].copy()
+    means[2, 0] = 0.1
+    p2 = orc.preprocess(cam, orc.KernelSpec(oracle.GAUSS, 2.0, 1.0, 9.0), means, sp["scales"], sp["quats"],
+                        sp["sh"], 0)
+    assert p2["visible"][0] == 0 and p2["radius"][0] == 0
