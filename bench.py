@@ -1,0 +1,226 @@
+"""Benchmark: forward + backward of the DARBF rasterizer on one MI355X.
+
+Workload: the scene-scale view -- 3M clustered splats (SH degree 3), one
+1297x840 view, half-cosine DARBF (psi = 1.36, xi = 18/pi).  One step is the
+whole hot path over that view with inputs resident in HBM:
+preprocess -> bin/sort -> raster forward -> raster backward -> preprocess
+backward.  The upstream gradient dL/dimage (mean-L1 to a random target) is
+formed once before timing.  Prints one JSON line (metric: Mpix/s).
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--kernel half_cos]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# per-unit algorithmic work (see the design notes for the derivations)
+FLOPS_PER_PAIR_FWD = 23     # d, Q d, E, F(E), alpha, T update, colour blend
+FLOPS_PER_PAIR_BWD = 66     # recompute alpha, T recovery, dL/dalpha, 9 partial sums, colour-behind update
+PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
+PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 vector (packed FMA)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def stage_bytes(n, n_vis, K, P, ntile, sh_coeffs=48, chunks=0):
+    """Algorithmic HBM bytes per stage (one read of each needed input, one write of each output)."""
+    pre = 12 * n + (236 - 12) * n_vis + 52 * n_vis + 4 * n      # params in; xy,depth,radius,conic_o,rgb,clamp out
+    binsort = 16 * n + 4 * K + 8 * ntile + 8 * n                 # (xy, r, depth) in; vals out; ranges; depth keys
+    return dict(preprocess=pre, bin_sort=binsort)
+
+
+def cpu_baseline(sc, kernel_name, rows_every: int, log_fn=log):
+    """The FP64 oracle (as is) on a bounded sample: preprocess and its backward over
+    all splats, composite forward+backward over every ``rows_every``-th image row."""
+    import oracle
+    from paper_2501_12369_amd import scenes
+
+    sp, camd = sc["splats"], sc["camera"]
+    W, H = camd["width"], camd["height"]
+    f32 = lambda v: float(np.float32(v))
+    presets = {"half_cos": (oracle.HALF_COS, 18.0 / np.pi, 1.36), "gauss": (oracle.GAUSS, 2.0, 1.0)}
+    kind, xi, psi = presets[kernel_name]
+    k = oracle.KernelSpec(kind, f32(xi), f32(psi), 9.0)
+    cam = oracle.camera_from_scene(camd)
+    opts = oracle.make_opts(f32(1 / 255), f32(0.99), f32(1e-4))
+    rows = np.arange(0, H, rows_every)
+    ys, xs = np.meshgrid(rows, np.arange(W), indexing="ij")
+    pix = np.stack([xs.ravel(), ys.ravel()], 1).astype(np.int32)
+    G = scenes.upstream_grad(99, W, H).transpose(1, 2, 0).reshape(-1, 3)
+    Gs = G[pix[:, 1] * W + pix[:, 0]].astype(np.float64)
+    t0 = time.perf_counter()
+    proj = oracle.preprocess(cam, k, sp["means"], sp["scales"], sp["quats"], sp["sh"], sp["sh_degree"])
+    t1 = time.perf_counter()
+    oracle.composite(proj, sp["opacity"], k, opts, W, H, pix=pix)
+    t2 = time.perf_counter()
+    g2d = oracle.composite_bwd(proj, sp["opacity"], k, opts, W, H, Gs, pix=pix)
+    t3 = time.perf_counter()
+    oracle.preprocess_bwd(cam, k, sp["means"], sp["scales"], sp["quats"], sp["sh"], sp["sh_degree"], g2d)
+    t4 = time.perf_counter()
+    frac = len(pix) / (W * H)
+    per_splat = (t1 - t0) + (t4 - t3)
+    per_pixel = (t3 - t1) / frac
+    total = per_splat + per_pixel
+    log_fn(f"cpu oracle: preprocess {t1-t0:.2f}s composite {t2-t1:.2f}s composite_bwd {t3-t2:.2f}s "
+           f"preprocess_bwd {t4-t3:.2f}s on {len(pix)} px; full-view estimate {total:.1f}s")
+    return dict(value=round(W * H / total / 1e6, 6), unit="Mpix/s", cores=oracle.num_threads(), kind="oracle",
+                sample=f"FP64 oracle: preprocess + preprocess backward over all {sp['means'].shape[1]} splats, "
+                       f"composite forward + backward over every {rows_every}th row ({len(pix)} of {W*H} pixels); "
+                       f"per-pixel time scaled to the full view; measured {t4 - t0:.1f}s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--kernel", default="half_cos", choices=["half_cos", "gauss"])
+    ap.add_argument("--n", type=int, default=3_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rows-every", type=int, default=16)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (requested --gpus {args.gpus}); "
+              f"run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2501_12369_amd import native, pipeline, scenes
+
+    if not torch.cuda.is_available():
+        print("no GPU visible: bench.py needs an MI355X", file=sys.stderr)
+        sys.exit(3)
+    native.lib()  # fails loudly when the HIP library is missing
+
+    t0 = time.time()
+    sc = scenes.scene(seed=3, n=args.n)
+    log(f"scene generated in {time.time()-t0:.1f}s")
+    cam = sc["camera"]
+    W, H = cam["width"], cam["height"]
+    P = W * H
+    kern = pipeline.KERNELS[args.kernel]
+    spd = pipeline.splats_to_device(sc["splats"])
+    n = args.n
+
+    # sizing pass: K read back once, then every timed step runs without host syncs
+    fr = pipeline.render(spd, cam, kern, k_capacity=1)
+    K = fr.K
+    frame = pipeline.alloc_frame(n, W, H, int(K * 1.02) + 4096, "cuda")
+    pipeline.render(spd, cam, kern, frame=frame, read_k=True)
+    del fr
+    n_vis = int((frame.proj["radius"] > 0).sum())
+    target = torch.rand((3, H, W), device="cuda", generator=torch.Generator("cuda").manual_seed(7))
+    G = (torch.sign(frame.image - target) / (3 * P)).contiguous()
+    grads = pipeline.alloc_grads(n, 3)
+    log(f"N={n} visible={n_vis} K={K} tiles={pipeline.n_tiles(W, H)}")
+
+    stages = ["preprocess", "bin_sort", "raster_fwd", "raster_bwd", "preprocess_bwd"]
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record()
+        native.darb_preprocess(cam, kern, n, spd, frame.proj)
+        if ev is not None:
+            ev[1].record()
+        native.darb_bin_sort(frame.proj, n, W, H, frame.capacity, frame.ws, None, frame.vals, frame.ranges,
+                             frame.k_dev, frame.overflow)
+        if ev is not None:
+            ev[2].record()
+        native.darb_raster_fwd(frame.proj, n, frame.vals, frame.ranges, frame.overflow, W, H, kern,
+                               pipeline.DEFAULT_OPTS, frame.image, frame.final_T, frame.last)
+        if ev is not None:
+            ev[3].record()
+        native.darb_raster_bwd(frame.proj, n, frame.vals, frame.ranges, frame.overflow, W, H, kern,
+                               pipeline.DEFAULT_OPTS, G, frame.final_T, frame.last, grads[0])
+        if ev is not None:
+            ev[4].record()
+        native.darb_preprocess_bwd(cam, kern, n, spd, grads[0], grads[1])
+        if ev is not None:
+            ev[5].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        step(evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    assert int(frame.overflow[0].item()) == 0, "instance capacity overflow during timing"
+    per_stage = {s: float(np.mean([e[j].elapsed_time(e[j + 1]) for e in evs])) for j, s in enumerate(stages)}
+    ms_per_step = wall * 1e3 / args.steps
+    mpix = P * args.steps / wall / 1e6
+    log("per-stage ms: " + ", ".join(f"{k}={v:.3f}" for k, v in per_stage.items()) + f"; step {ms_per_step:.3f} ms")
+
+    # algorithmic work of the raster stages from the checkpoint
+    last = frame.last.to(torch.int64) & 0xFFFFFFFF
+    ranges = frame.ranges.to(torch.int64)
+    gx = (W + 15) // 16
+    yy, xx = torch.meshgrid(torch.arange(H, device="cuda"), torch.arange(W, device="cuda"), indexing="ij")
+    tile = (yy // 16) * gx + (xx // 16)
+    start = ranges[tile, 0]
+    has = last != 0xFFFFFFFF
+    pairs_bwd = int(torch.where(has, last - start + 1, torch.zeros_like(last)).sum())
+    chunks = 0
+    bytes_ = stage_bytes(n, n_vis, K, P, pipeline.n_tiles(W, H))
+    roof = {
+        "preprocess": dict(bound="hbm", achieved=bytes_["preprocess"] / (per_stage["preprocess"] * 1e-3) / 1e9,
+                           peak=PEAK_HBM_GBS, unit="GB/s"),
+        "bin_sort": dict(bound="hbm", achieved=bytes_["bin_sort"] / (per_stage["bin_sort"] * 1e-3) / 1e9,
+                         peak=PEAK_HBM_GBS, unit="GB/s"),
+        "raster_bwd": dict(bound="alu", achieved=pairs_bwd * FLOPS_PER_PAIR_BWD / (per_stage["raster_bwd"] * 1e-3)
+                           / 1e12, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s"),
+    }
+    dominant = max(per_stage, key=per_stage.get)
+    log(f"dominant stage {dominant}; bwd pairs {pairs_bwd}; roofline: " +
+        ", ".join(f"{k}: {v['achieved']:.2f}/{v['peak']} {v['unit']}" for k, v in roof.items()))
+    r = roof.get(dominant)
+    if r is None:
+        r = roof["raster_bwd"]
+    roofline = dict(bound=r["bound"], achieved=round(r["achieved"], 4), peak=r["peak"], unit=r["unit"],
+                    frac=round(r["achieved"] / r["peak"], 5), traffic=None, kernel=dominant)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(sc, args.kernel, args.cpu_rows_every)
+
+    out = {
+        "metric": "fwd+bwd Mpix/s at 3M splats 1297x840",
+        "value": round(mpix, 3),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"scene: {n} clustered splats (SH degree 3), one {W}x{H} view, {args.kernel} DARBF, "
+                               f"preprocess+bin/sort+raster fwd+raster bwd+preprocess bwd",
+                   "n_splats": n, "width": W, "height": H, "kernel": args.kernel, "visible": n_vis, "instances": K,
+                   "splats_per_s": round(n * args.steps / wall, 1),
+                   "stage_ms": {k: round(v, 4) for k, v in per_stage.items()}},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

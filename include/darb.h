@@ -1,0 +1,263 @@
+/*
+ * darb.h -- C ABI of libdarb, an MI355X (gfx950) implementation of the
+ * differentiable tile rasterizer of DARB-Splatting (arXiv 2501.12369):
+ * anisotropic splats whose footprint is a decaying anisotropic radial basis
+ * function (DARBF) F of the squared Mahalanobis distance E = d_M^2.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every buffer is a DEVICE pointer owned by the caller; the library never
+ *   allocates device memory.  Scratch space comes in through a workspace
+ *   argument whose size a *_workspace query returns.
+ * - Every call is asynchronous on `stream` (a hipStream_t passed as void*;
+ *   NULL = the null stream) unless stated otherwise.  Arguments are validated
+ *   on the host before anything is enqueued; on an error nothing is enqueued.
+ * - Every device pointer must be 16-byte aligned.
+ * - Counts are int64_t; indices into the sorted instance list are uint32_t, so
+ *   the number of (tile, splat) instances must stay below 2^32.
+ * - Errors: a darb_status code; darb_last_error() returns a message for the
+ *   last failing call on the calling thread.  No C++ exception crosses the ABI.
+ * - Thread safety: no global mutable state besides the per-thread error text;
+ *   calls on different streams may run concurrently.
+ * - Geometry: camera frame x right, y down, z forward; pixel (i, j) (column i,
+ *   row j) is evaluated at image coordinates (i, j).  Images are planar
+ *   [3][H][W] FP32; per-pixel buffers are [H][W].
+ * - The 2D footprint is rasterised on 16x16-pixel tiles.
+ */
+#ifndef DARB_H
+#define DARB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__) || defined(__clang__)
+#define DARB_API __attribute__((visibility("default")))
+#else
+#define DARB_API
+#endif
+
+#define DARB_ABI_VERSION 1
+#define DARB_TILE 16
+
+typedef enum {
+    DARB_OK = 0,
+    DARB_ERR_INVALID_ARG = 1, /* null/misaligned pointer, negative count, bad size, unknown kind */
+    DARB_ERR_CAPACITY = 2,    /* instance count exceeds the capacity (only reported by a blocking call) */
+    DARB_ERR_HIP = 3,         /* a HIP runtime call failed; darb_last_error() names it */
+    DARB_ERR_UNSUPPORTED = 4  /* valid request outside what this build implements */
+} darb_status;
+
+/* Kernel profiles F(E), E = d_M^2 (Table 1 and the per-kernel supplementary
+ * sections).  xi is the scaling factor of Table 2. */
+typedef enum {
+    DARB_GAUSS = 0,      /* exp(-E/xi)                  (modified Gaussian, beta = 2; xi = 2)       */
+    DARB_HALF_COS = 1,   /* cos(E/xi), E/xi <= pi/2     (half-cosine squared; xi = 18/pi)          */
+    DARB_RAISED_COS = 2, /* 0.5 + 0.5 cos(sqrt(E)/xi)   (raised cosine, beta = 1; xi = 2.5/pi)      */
+    DARB_SINC = 3,       /* |sin u|/u, u = sqrt(E)/xi   (modular sinc, beta = 1; xi = 3/pi)         */
+    DARB_IMQ = 4,        /* 1/(E/xi + 1)                (inverse quadric of the supplementary code) */
+    DARB_IMQ_SQRT = 5,   /* 1/sqrt(E/xi + 1)            (inverse multiquadric of Table 1)           */
+    DARB_PARABOLA = 6    /* 1 - E/xi                    (parabola; xi = 9)                          */
+} darb_kernel_kind;
+
+/* A DARBF: profile, scale, correction factor and support.
+ * psi multiplies the projected 2x2 covariance (Eq. of the 2x2 covariance
+ * projection; Table 2).  A pixel is inside the footprint iff 0 <= E <= e_max
+ * (boundaries of DARBFs: one main lobe).  Requires 0 < e_max <= 9, because the
+ * binning radius is 3 sqrt(lambda_max) (DARB-Splatting section). */
+typedef struct {
+    int32_t kind; /* darb_kernel_kind */
+    float xi;
+    float psi;
+    float e_max;
+} darb_kernel;
+
+/* Pinhole camera.  viewmat: world -> camera, row-major 4x4 (rotation R_cw in
+ * the upper 3x3, translation t_cw in the last column).  campos: camera centre
+ * in world coordinates (used for the SH view direction).  A splat with camera
+ * depth t_z <= near_z is culled.  jac_clamp limits |t_x/t_z| to
+ * jac_clamp * (width/2) / fx (and likewise y) inside the projection Jacobian;
+ * <= 0 disables the clamp.  dilation is added to the diagonal of the 2D
+ * covariance after the psi scaling. */
+typedef struct {
+    float viewmat[16];
+    float campos[3];
+    float fx, fy, cx, cy;
+    int32_t width, height;
+    float near_z;
+    float jac_clamp;
+    float dilation;
+} darb_camera;
+
+/* Compositing options (front-to-back alpha blending): alpha = min(alpha_max,
+ * opacity * F(E)); a pair with alpha < alpha_min is skipped; a pixel stops
+ * (without blending the splat) when the transmittance would fall below t_min;
+ * the background colour bg is blended with the final transmittance. */
+typedef struct {
+    float alpha_min; /* 1/255 */
+    float alpha_max; /* 0.99  */
+    float t_min;     /* 1e-4  */
+    float bg[3];
+} darb_raster_opts;
+
+/* Splat parameters (the 3DGS parameterisation kept by the paper, DARB
+ * Representation), structure-of-arrays, FP32, read-only:
+ *   means    [3][n]                 world position
+ *   scales   [3][n]                 positive (already activated) axis scales
+ *   quats    [4][n]                 (w, x, y, z), any nonzero norm
+ *   opacity  [n]                    in (0, 1) (already activated)
+ *   sh       [(deg+1)^2][3][n]      real SH coefficients per colour channel */
+typedef struct {
+    const float *means;
+    const float *scales;
+    const float *quats;
+    const float *opacity;
+    const float *sh;
+    int32_t sh_degree; /* 0..3 */
+} darb_splats;
+
+/* Projected splats (preprocess output, binning/raster input):
+ *   xy       [n][2]   projected mean mu' in pixels
+ *   depth    [n]      camera-space t_z
+ *   radius   [n]      ceil(3 sqrt(lambda_max)) in pixels; 0 = culled (other fields undefined)
+ *   conic_o  [n][4]   (a, b, c, opacity) with Q = [[a, b], [b, c]] = inverse 2D covariance
+ *   rgb      [n][3]   colour after the SH evaluation and the clamp at 0
+ *   clamped  [n]      bit c set when channel c was clamped at 0                       */
+typedef struct {
+    float *xy;
+    float *depth;
+    int32_t *radius;
+    float *conic_o;
+    float *rgb;
+    uint8_t *clamped;
+} darb_projected;
+
+/* Gradients with respect to the projected quantities (raster backward output):
+ *   xy [n][2], conic [n][3] (d/da, d/db with b the single off-diagonal scalar,
+ *   d/dc), opacity [n], rgb [n][3]. */
+typedef struct {
+    float *xy;
+    float *conic;
+    float *opacity;
+    float *rgb;
+} darb_grads2d;
+
+/* Gradients with respect to the splat parameters, same layouts as darb_splats. */
+typedef struct {
+    float *means;
+    float *scales;
+    float *quats;
+    float *opacity;
+    float *sh;
+} darb_grads3d;
+
+DARB_API int32_t darb_version(void);
+DARB_API const char *darb_status_string(int32_t status);
+DARB_API const char *darb_last_error(void);
+
+/*
+ * darb_preprocess -- per-splat projection (DARB Projection; Eq. of the 2x2
+ * covariance projection; bounding radius of the DARBF boundaries section).
+ * For each splat: q/|q| -> R; Sigma = R diag(s^2) R^T; t = R_cw mu + t_cw
+ * (cull t_z <= near_z); affine Jacobian J at t; Sigma'_2x2 = psi [J R_cw Sigma
+ * R_cw^T J^T]_2x2 + dilation I (cull det <= 0); Q = Sigma'_2x2^-1;
+ * mu' = (fx t_x/t_z + cx, fy t_y/t_z + cy); radius = ceil(3 sqrt(lambda_max));
+ * cull when the radius box covers no tile; rgb = max(0, sum SH * Y(dir) + 0.5)
+ * with dir = (mu - campos)/|mu - campos|.  `in` fields are read; every `out`
+ * field is written.  n = 0 is a no-op.
+ */
+DARB_API darb_status darb_preprocess(const darb_camera *cam, const darb_kernel *kernel, int64_t n, const darb_splats *in,
+                            const darb_projected *out, void *stream);
+
+/*
+ * darb_bin_sort_workspace -- bytes of device workspace darb_bin_sort needs for
+ * n splats and a width x height image.  Returns 0 for invalid sizes.
+ */
+DARB_API size_t darb_bin_sort_workspace(int64_t n, int32_t width, int32_t height);
+
+/*
+ * darb_bin_sort -- tile binning and depth sort ("tile-based rasterization"
+ * with the radius box, DARBF boundaries section).  Every splat with
+ * radius > 0 is duplicated into every 16x16 tile of the box
+ *   x in [clamp(floor((u - R)/16)), clamp(floor((u + R)/16) + 1)),  same for y,
+ * (FP32, clamped to the tile grid); each instance has key (tile << 32) |
+ * bits(depth) and value = splat index.  Instances are ordered by (key, index):
+ * per tile, front to back, equal depths by index -- a unique order.
+ *   keys      [k_capacity] u64, nullable (the raster stages do not need keys)
+ *   vals      [k_capacity] u32 splat indices in sorted order
+ *   ranges    [tiles][2]  u32: ranges[t] = (#instances with tile < t, #instances with tile <= t)
+ *   k_dev     [1] int64 device: K, the number of instances (always written)
+ *   overflow_dev [1] int32 device: 1 when K > k_capacity, else 0 (always written);
+ *             with overflow set keys/vals are not written and the raster
+ *             calls given the same flag do nothing
+ *   k_host    nullable host pointer: when given, the call blocks on `stream`
+ *             and stores K there (not capturable in a graph); it then returns
+ *             DARB_ERR_CAPACITY on overflow
+ *   ws/ws_bytes  workspace of at least darb_bin_sort_workspace(n, width, height) bytes
+ * tiles = ceil(width/16) * ceil(height/16) must be <= 16384.
+ */
+DARB_API darb_status darb_bin_sort(const darb_projected *proj, int64_t n, int32_t width, int32_t height, int64_t k_capacity,
+                          void *ws, size_t ws_bytes, uint64_t *keys, uint32_t *vals, uint32_t *ranges, int64_t *k_dev,
+                          int32_t *overflow_dev, int64_t *k_host, void *stream);
+
+/*
+ * darb_raster_fwd -- per-pixel DARBF evaluation and front-to-back alpha
+ * compositing (DARB-Splatting section: footprint and alpha blending; the
+ * per-kernel forward listings).  For each pixel p of the tile, for the tile's
+ * instances in order: d = mu' - p, E = d^T Q d; skip unless 0 <= E <= e_max;
+ * alpha = min(alpha_max, o F(E)); skip if alpha < alpha_min; T' = T (1 - alpha);
+ * stop if T' < t_min; C += alpha T rgb; T = T'.
+ *   image     [3][H][W]  C + T bg
+ *   final_T   [H][W]     transmittance after the last blended splat (checkpoint)
+ *   last      [H][W]     u32 position in `vals` of the last blended instance,
+ *                        0xFFFFFFFF when none (checkpoint)
+ *   n_contrib [H][W]     nullable: number of blended splats
+ *   overflow_dev nullable: when it points at a nonzero flag the kernel writes nothing
+ */
+DARB_API darb_status darb_raster_fwd(const darb_projected *proj, int64_t n, const uint32_t *vals, const uint32_t *ranges,
+                            const int32_t *overflow_dev, int32_t width, int32_t height, const darb_kernel *kernel,
+                            const darb_raster_opts *opts, float *image, float *final_T, uint32_t *last,
+                            uint32_t *n_contrib, void *stream);
+
+/*
+ * darb_raster_bwd -- reverse-order compositing gradients (Backpropagation
+ * and Error Calculation; the per-kernel backward listings) from the
+ * checkpoint of darb_raster_fwd: each pixel walks its list back from `last`,
+ * recomputing alpha exactly as the forward did and recovering the
+ * transmittance by division by (1 - alpha).  Per pair:
+ *   dL/drgb += alpha T G;  dL/dalpha = G . (rgb T - S / (1 - alpha)), S = colour behind + T_final bg;
+ *   dL/do += F(E) dL/dalpha  (passed straight through the alpha_max clamp);
+ *   dL/dE = o F'(E) dL/dalpha;  dL/dmu' += 2 dL/dE Q d;  dL/d(a,b,c) += dL/dE (dx^2, 2 dx dy, dy^2).
+ * Per-splat sums are reduced across each wavefront before one set of atomic
+ * adds per (tile, splat); g2d is zeroed by the call first.
+ *   dL_dimage [3][H][W]
+ *   g2d       required output
+ *   cam, in, g3d: when g3d is non-null the call continues with the chain of
+ *             darb_preprocess_bwd (cam and in then required) and writes g3d.
+ */
+DARB_API darb_status darb_raster_bwd(const darb_projected *proj, int64_t n, const uint32_t *vals, const uint32_t *ranges,
+                            const int32_t *overflow_dev, int32_t width, int32_t height, const darb_kernel *kernel,
+                            const darb_raster_opts *opts, const float *dL_dimage, const float *final_T,
+                            const uint32_t *last, const darb_grads2d *g2d, const darb_camera *cam,
+                            const darb_splats *in, const darb_grads3d *g3d, void *stream);
+
+/*
+ * darb_preprocess_bwd -- chain rule through darb_preprocess (psi enters the
+ * 2D covariance gradient for every kernel): conic -> 2D covariance -> psi ->
+ * J R_cw Sigma R_cw^T J^T -> Sigma -> scale and rotation -> quaternion
+ * (through the normalisation); the mean through mu', through J (zero across
+ * an active Jacobian clamp) and through the SH view direction; SH
+ * coefficients (zero for clamped channels); opacity passed through.
+ * g3d is overwritten for every splat (zeros for culled splats).
+ */
+DARB_API darb_status darb_preprocess_bwd(const darb_camera *cam, const darb_kernel *kernel, int64_t n, const darb_splats *in,
+                                const darb_grads2d *g2d, const darb_grads3d *g3d, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DARB_H */

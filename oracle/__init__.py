@@ -80,10 +80,15 @@ def lib():
                                         vp, ctypes.c_int, vp, vp, vp, vp]
         L.orc_preprocess_bwd.argtypes = [vp, vp, i64, vp, vp, vp, vp, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp,
                                          vp, vp]
+        L.orc_num_threads.restype = ctypes.c_int
         L.orc_bin.restype = i64
         L.orc_bin.argtypes = [i64, vp, vp, vp, ctypes.c_int, ctypes.c_int, i64, vp, vp, vp]
         _lib = L
     return _lib
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
 
 
 def _p(a: np.ndarray):

@@ -914,3 +914,15 @@ long orc_bin(long n, const float *xy, const int32_t *radius, const float *depth,
     free(rect);
     return K;
 }
+
+/* number of OpenMP threads the oracle's parallel loops use */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

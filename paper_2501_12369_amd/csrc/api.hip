@@ -1,0 +1,310 @@
+// api.hip -- the extern "C" entry points of libdarb: host-side argument
+// validation, derivation of the per-launch constants, dispatch to the stage
+// launchers.  Nothing here allocates device memory.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "common.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+darb_status fail(darb_status st, const char *fmt, const char *what) {
+    snprintf(g_err, sizeof(g_err), fmt, what);
+    return st;
+}
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+#define REQUIRE_PTR(p)                                                                          \
+    do {                                                                                        \
+        if (!(p)) return fail(DARB_ERR_INVALID_ARG, "null pointer: %s", #p);                    \
+        if (!aligned16(p)) return fail(DARB_ERR_INVALID_ARG, "pointer not 16-byte aligned: %s", #p); \
+    } while (0)
+
+#define OPT_PTR(p)                                                                              \
+    do {                                                                                        \
+        if ((p) && !aligned16(p)) return fail(DARB_ERR_INVALID_ARG, "pointer not 16-byte aligned: %s", #p); \
+    } while (0)
+
+darb_status hip_status(hipError_t e, const char *where) {
+    if (e == hipSuccess) return DARB_OK;
+    snprintf(g_err, sizeof(g_err), "%s: %s", where, hipGetErrorString(e));
+    return DARB_ERR_HIP;
+}
+
+darb_status check_kernel(const darb_kernel *k, darb::KParams *kp) {
+    if (!k) return fail(DARB_ERR_INVALID_ARG, "null pointer: %s", "kernel");
+    if (k->kind < DARB_GAUSS || k->kind > DARB_PARABOLA) return fail(DARB_ERR_INVALID_ARG, "%s", "unknown kernel kind");
+    if (!(k->xi > 0.0f) || !isfinite(k->xi)) return fail(DARB_ERR_INVALID_ARG, "%s", "kernel xi must be > 0");
+    if (!(k->psi > 0.0f) || !isfinite(k->psi)) return fail(DARB_ERR_INVALID_ARG, "%s", "kernel psi must be > 0");
+    if (!(k->e_max > 0.0f) || !(k->e_max <= 9.0f))
+        return fail(DARB_ERR_INVALID_ARG, "%s", "kernel e_max must be in (0, 9] (binning radius is 3 sqrt(lambda_max))");
+    kp->inv_xi = 1.0f / k->xi;
+    kp->inv_xi2 = kp->inv_xi * kp->inv_xi;
+    kp->exp2_c = (float)(-1.4426950408889634 / (double)k->xi);
+    kp->e_max = k->e_max;
+    kp->psi = k->psi;
+    return DARB_OK;
+}
+
+darb_status check_camera(const darb_camera *c, darb::Cam *cam) {
+    if (!c) return fail(DARB_ERR_INVALID_ARG, "null pointer: %s", "camera");
+    if (c->width <= 0 || c->height <= 0) return fail(DARB_ERR_INVALID_ARG, "%s", "camera width/height must be > 0");
+    if (!(c->fx > 0.0f) || !(c->fy > 0.0f)) return fail(DARB_ERR_INVALID_ARG, "%s", "camera fx/fy must be > 0");
+    if (!(c->near_z > 0.0f)) return fail(DARB_ERR_INVALID_ARG, "%s", "camera near_z must be > 0");
+    if (!(c->dilation >= 0.0f)) return fail(DARB_ERR_INVALID_ARG, "%s", "camera dilation must be >= 0");
+    for (int r = 0; r < 3; r++) {
+        for (int k = 0; k < 3; k++) cam->R[r * 3 + k] = c->viewmat[r * 4 + k];
+        cam->t[r] = c->viewmat[r * 4 + 3];
+        cam->campos[r] = c->campos[r];
+    }
+    cam->fx = c->fx;
+    cam->fy = c->fy;
+    cam->cx = c->cx;
+    cam->cy = c->cy;
+    cam->width = c->width;
+    cam->height = c->height;
+    cam->near_z = c->near_z;
+    if (c->jac_clamp > 0.0f) {
+        cam->lim_x = c->jac_clamp * (0.5f * (float)c->width) / c->fx;
+        cam->lim_y = c->jac_clamp * (0.5f * (float)c->height) / c->fy;
+    } else {
+        cam->lim_x = cam->lim_y = 0.0f;
+    }
+    cam->dilation = c->dilation;
+    return DARB_OK;
+}
+
+darb_status check_opts(const darb_raster_opts *o, darb::ROpts *ro) {
+    if (!o) return fail(DARB_ERR_INVALID_ARG, "null pointer: %s", "opts");
+    if (!(o->alpha_min >= 0.0f) || !(o->alpha_max > 0.0f) || !(o->alpha_max < 1.0f) || !(o->alpha_min <= o->alpha_max))
+        return fail(DARB_ERR_INVALID_ARG, "%s", "opts need 0 <= alpha_min <= alpha_max < 1");
+    if (!(o->t_min >= 0.0f) || !(o->t_min < 1.0f)) return fail(DARB_ERR_INVALID_ARG, "%s", "opts t_min must be in [0, 1)");
+    *ro = darb::ROpts{o->alpha_min, o->alpha_max, o->t_min, o->bg[0], o->bg[1], o->bg[2]};
+    return DARB_OK;
+}
+
+darb_status check_n(int64_t n) {
+    if (n < 0) return fail(DARB_ERR_INVALID_ARG, "%s", "n must be >= 0");
+    if (n > 0x7FFFFFFFll) return fail(DARB_ERR_UNSUPPORTED, "%s", "n must be < 2^31");
+    return DARB_OK;
+}
+
+darb_status check_size(int32_t width, int32_t height) {
+    if (width <= 0 || height <= 0) return fail(DARB_ERR_INVALID_ARG, "%s", "width/height must be > 0");
+    int64_t gx = (width + darb::kTile - 1) / darb::kTile, gy = (height + darb::kTile - 1) / darb::kTile;
+    if (gx * gy > darb::kMaxTiles) return fail(DARB_ERR_UNSUPPORTED, "%s", "more than 16384 tiles");
+    return DARB_OK;
+}
+
+darb_status check_splats(const darb_splats *in, int64_t n) {
+    if (!in) return fail(DARB_ERR_INVALID_ARG, "null pointer: %s", "splats");
+    if (in->sh_degree < 0 || in->sh_degree > 3) return fail(DARB_ERR_INVALID_ARG, "%s", "sh_degree must be 0..3");
+    if (n == 0) return DARB_OK;
+    REQUIRE_PTR(in->means);
+    REQUIRE_PTR(in->scales);
+    REQUIRE_PTR(in->quats);
+    REQUIRE_PTR(in->opacity);
+    REQUIRE_PTR(in->sh);
+    return DARB_OK;
+}
+
+darb_status check_projected(const darb_projected *p, int64_t n, bool need_all) {
+    if (!p) return fail(DARB_ERR_INVALID_ARG, "null pointer: %s", "projected");
+    if (n == 0) return DARB_OK;
+    REQUIRE_PTR(p->xy);
+    REQUIRE_PTR(p->depth);
+    REQUIRE_PTR(p->radius);
+    if (need_all) {
+        REQUIRE_PTR(p->conic_o);
+        REQUIRE_PTR(p->rgb);
+        REQUIRE_PTR(p->clamped);
+    }
+    return DARB_OK;
+}
+
+darb_status check_g2d(const darb_grads2d *g, int64_t n) {
+    if (!g) return fail(DARB_ERR_INVALID_ARG, "null pointer: %s", "grads2d");
+    if (n == 0) return DARB_OK;
+    REQUIRE_PTR(g->xy);
+    REQUIRE_PTR(g->conic);
+    REQUIRE_PTR(g->opacity);
+    REQUIRE_PTR(g->rgb);
+    return DARB_OK;
+}
+
+darb_status check_g3d(const darb_grads3d *g, int64_t n) {
+    if (!g) return fail(DARB_ERR_INVALID_ARG, "null pointer: %s", "grads3d");
+    if (n == 0) return DARB_OK;
+    REQUIRE_PTR(g->means);
+    REQUIRE_PTR(g->scales);
+    REQUIRE_PTR(g->quats);
+    REQUIRE_PTR(g->opacity);
+    REQUIRE_PTR(g->sh);
+    return DARB_OK;
+}
+
+#define TRY(x)                                  \
+    do {                                        \
+        darb_status _st = (x);                  \
+        if (_st != DARB_OK) return _st;         \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+int32_t darb_version(void) { return DARB_ABI_VERSION; }
+
+const char *darb_status_string(int32_t st) {
+    switch (st) {
+    case DARB_OK: return "ok";
+    case DARB_ERR_INVALID_ARG: return "invalid argument";
+    case DARB_ERR_CAPACITY: return "instance capacity exceeded";
+    case DARB_ERR_HIP: return "HIP runtime error";
+    case DARB_ERR_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+    }
+}
+
+const char *darb_last_error(void) { return g_err; }
+
+darb_status darb_preprocess(const darb_camera *cam, const darb_kernel *kernel, int64_t n, const darb_splats *in,
+                            const darb_projected *out, void *stream) {
+    darb::Cam c;
+    darb::KParams kp;
+    TRY(check_n(n));
+    TRY(check_camera(cam, &c));
+    TRY(check_kernel(kernel, &kp));
+    TRY(check_size(cam->width, cam->height));
+    TRY(check_splats(in, n));
+    TRY(check_projected(out, n, true));
+    g_err[0] = 0;
+    return hip_status(darb::launch_preprocess(c, kp, (int)n, *in, *out, (hipStream_t)stream), "darb_preprocess");
+}
+
+size_t darb_bin_sort_workspace(int64_t n, int32_t width, int32_t height) {
+    if (n < 0 || n > 0x7FFFFFFFll || width <= 0 || height <= 0) return 0;
+    int64_t gx = (width + darb::kTile - 1) / darb::kTile, gy = (height + darb::kTile - 1) / darb::kTile;
+    if (gx * gy > darb::kMaxTiles) return 0;
+    return darb::binsort_workspace((int)n, width, height);
+}
+
+darb_status darb_bin_sort(const darb_projected *proj, int64_t n, int32_t width, int32_t height, int64_t k_capacity,
+                          void *ws, size_t ws_bytes, uint64_t *keys, uint32_t *vals, uint32_t *ranges, int64_t *k_dev,
+                          int32_t *overflow_dev, int64_t *k_host, void *stream) {
+    TRY(check_n(n));
+    TRY(check_size(width, height));
+    TRY(check_projected(proj, n, false));
+    if (k_capacity < 0) return fail(DARB_ERR_INVALID_ARG, "%s", "k_capacity must be >= 0");
+    if (k_capacity >= 0xFFFFFFFFll) return fail(DARB_ERR_UNSUPPORTED, "%s", "k_capacity must be < 2^32 - 1");
+    REQUIRE_PTR(ws);
+    REQUIRE_PTR(ranges);
+    REQUIRE_PTR(k_dev);
+    REQUIRE_PTR(overflow_dev);
+    OPT_PTR(keys);
+    if (k_capacity > 0) REQUIRE_PTR(vals);
+    size_t need = darb::binsort_workspace((int)n, width, height);
+    if (ws_bytes < need) {
+        snprintf(g_err, sizeof(g_err), "workspace too small: %zu < %zu bytes", ws_bytes, need);
+        return DARB_ERR_INVALID_ARG;
+    }
+    g_err[0] = 0;
+    hipStream_t s = (hipStream_t)stream;
+    TRY(hip_status(darb::launch_bin_sort(*proj, (int)n, width, height, k_capacity, ws, keys, vals, ranges, k_dev,
+                                         overflow_dev, s),
+                   "darb_bin_sort"));
+    if (k_host) {
+        TRY(hip_status(hipMemcpyAsync(k_host, k_dev, sizeof(int64_t), hipMemcpyDeviceToHost, s), "darb_bin_sort readback"));
+        TRY(hip_status(hipStreamSynchronize(s), "darb_bin_sort sync"));
+        if (*k_host > k_capacity) {
+            snprintf(g_err, sizeof(g_err), "instance count %lld exceeds capacity %lld", (long long)*k_host,
+                     (long long)k_capacity);
+            return DARB_ERR_CAPACITY;
+        }
+    }
+    return DARB_OK;
+}
+
+darb_status darb_raster_fwd(const darb_projected *proj, int64_t n, const uint32_t *vals, const uint32_t *ranges,
+                            const int32_t *overflow_dev, int32_t width, int32_t height, const darb_kernel *kernel,
+                            const darb_raster_opts *opts, float *image, float *final_T, uint32_t *last,
+                            uint32_t *n_contrib, void *stream) {
+    darb::KParams kp;
+    darb::ROpts ro;
+    TRY(check_n(n));
+    TRY(check_size(width, height));
+    TRY(check_kernel(kernel, &kp));
+    TRY(check_opts(opts, &ro));
+    TRY(check_projected(proj, n, true));
+    if (n > 0) REQUIRE_PTR(vals);
+    REQUIRE_PTR(ranges);
+    OPT_PTR(overflow_dev);
+    REQUIRE_PTR(image);
+    REQUIRE_PTR(final_T);
+    REQUIRE_PTR(last);
+    OPT_PTR(n_contrib);
+    g_err[0] = 0;
+    return hip_status(darb::launch_raster_fwd(kernel->kind, *proj, (int)n, vals, ranges, overflow_dev, width, height, kp, ro,
+                                              image, final_T, last, n_contrib, (hipStream_t)stream),
+                      "darb_raster_fwd");
+}
+
+darb_status darb_preprocess_bwd(const darb_camera *cam, const darb_kernel *kernel, int64_t n, const darb_splats *in,
+                                const darb_grads2d *g2d, const darb_grads3d *g3d, void *stream) {
+    darb::Cam c;
+    darb::KParams kp;
+    TRY(check_n(n));
+    TRY(check_camera(cam, &c));
+    TRY(check_kernel(kernel, &kp));
+    TRY(check_size(cam->width, cam->height));
+    TRY(check_splats(in, n));
+    TRY(check_g2d(g2d, n));
+    TRY(check_g3d(g3d, n));
+    g_err[0] = 0;
+    return hip_status(darb::launch_preprocess_bwd(c, kp, (int)n, *in, *g2d, *g3d, (hipStream_t)stream),
+                      "darb_preprocess_bwd");
+}
+
+darb_status darb_raster_bwd(const darb_projected *proj, int64_t n, const uint32_t *vals, const uint32_t *ranges,
+                            const int32_t *overflow_dev, int32_t width, int32_t height, const darb_kernel *kernel,
+                            const darb_raster_opts *opts, const float *dL_dimage, const float *final_T,
+                            const uint32_t *last, const darb_grads2d *g2d, const darb_camera *cam,
+                            const darb_splats *in, const darb_grads3d *g3d, void *stream) {
+    darb::KParams kp;
+    darb::ROpts ro;
+    darb::Cam c;
+    TRY(check_n(n));
+    TRY(check_size(width, height));
+    TRY(check_kernel(kernel, &kp));
+    TRY(check_opts(opts, &ro));
+    TRY(check_projected(proj, n, true));
+    if (n > 0) REQUIRE_PTR(vals);
+    REQUIRE_PTR(ranges);
+    OPT_PTR(overflow_dev);
+    REQUIRE_PTR(dL_dimage);
+    REQUIRE_PTR(final_T);
+    REQUIRE_PTR(last);
+    TRY(check_g2d(g2d, n));
+    if (g3d) {
+        TRY(check_camera(cam, &c));
+        if (cam->width != width || cam->height != height)
+            return fail(DARB_ERR_INVALID_ARG, "%s", "camera size differs from the raster size");
+        TRY(check_splats(in, n));
+        TRY(check_g3d(g3d, n));
+    }
+    g_err[0] = 0;
+    hipStream_t s = (hipStream_t)stream;
+    TRY(hip_status(darb::launch_raster_bwd(kernel->kind, *proj, (int)n, vals, ranges, overflow_dev, width, height, kp,
+                                           ro, dL_dimage, final_T, last, *g2d, s),
+                   "darb_raster_bwd"));
+    if (g3d) TRY(hip_status(darb::launch_preprocess_bwd(c, kp, (int)n, *in, *g2d, *g3d, s), "darb_raster_bwd chain"));
+    return DARB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,253 @@
+// common.h -- device helpers shared by the libdarb kernels (gfx950, wave64).
+//
+// The library is compiled with -ffp-contract=off: every fused multiply-add is
+// written explicitly with fmaf, so the forward and the backward raster kernels
+// evaluate alpha with bit-identical arithmetic (the backward recovers the
+// transmittance by dividing by (1 - alpha) and must see the same alpha).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "darb.h"
+
+namespace darb {
+
+constexpr int kTile = 16;
+constexpr int kWave = 64;
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr int kMaxTiles = 16384;
+
+// Per-launch constants of a DARBF (host-derived from darb_kernel).
+struct KParams {
+    float inv_xi;   // 1/xi
+    float inv_xi2;  // 1/xi^2 (profiles of sqrt(E)/xi written as series in E/xi^2)
+    float exp2_c;   // -log2(e)/xi  (Gaussian: exp(-E/xi) = exp2(E * exp2_c))
+    float e_max;
+    float psi;
+};
+
+struct ROpts {
+    float alpha_min, alpha_max, t_min;
+    float bg0, bg1, bg2;
+};
+
+// ---------------------------------------------------------------------------
+// Profiles F(E) and dF/dE.  Trigonometric profiles are evaluated as truncated
+// Taylor series in the squared argument (Horner form, explicit FMA); on the
+// supports used (E/xi <= pi/2, or (sqrt(E)/xi)^2 <= pi^2) the truncation error
+// stays below 1e-9 and the FP32 rounding dominates.  Values for E outside the
+// support are never consumed (callers select on the support test).
+// ---------------------------------------------------------------------------
+
+// cos x as a series in u = x^2, valid for x in [0, pi/2]: sum_k (-1)^k u^k / (2k)!
+__device__ __forceinline__ float cos_series_half(float u) {
+    // sum_{k=0}^{7} (-1)^k u^k / (2k)!
+    float p = -1.1470745597729725e-11f;  // -1/14!
+    p = fmaf(p, u, 2.08767569878681e-09f);  // +1/12!
+    p = fmaf(p, u, -2.755731922398589e-07f);  // -1/10!
+    p = fmaf(p, u, 2.48015873015873e-05f);  // +1/8!
+    p = fmaf(p, u, -0.001388888888888889f);  // -1/6!
+    p = fmaf(p, u, 0.041666666666666664f);  // +1/4!
+    p = fmaf(p, u, -0.5f);  // -1/2!
+    return fmaf(p, u, 1.0f);  // +1/0!
+}
+
+// sin x / x as a series in u = x^2, valid for x in [0, pi/2]: sum_k (-1)^k u^k / (2k+1)!
+__device__ __forceinline__ float sinc_series_half(float u) {
+    // sum_{k=0}^{7} (-1)^k u^k / (2k+1)!
+    float p = -7.647163731819816e-13f;  // -1/15!
+    p = fmaf(p, u, 1.6059043836821613e-10f);  // +1/13!
+    p = fmaf(p, u, -2.505210838544172e-08f);  // -1/11!
+    p = fmaf(p, u, 2.7557319223985893e-06f);  // +1/9!
+    p = fmaf(p, u, -0.0001984126984126984f);  // -1/7!
+    p = fmaf(p, u, 0.008333333333333333f);  // +1/5!
+    p = fmaf(p, u, -0.16666666666666666f);  // -1/3!
+    return fmaf(p, u, 1.0f);  // +1/1!
+}
+
+// cos x, sin x / x and (x cos x - sin x) / x^3 as series in v = x^2, valid for x in [0, pi].
+__device__ __forceinline__ float cos_series_full(float v) {
+    // sum_{k=0}^{12} (-1)^k v^k / (2k)!
+    float p = 1.6117375710961184e-24f;  // +1/24!
+    p = fmaf(p, v, -8.896791392450574e-22f);  // -1/22!
+    p = fmaf(p, v, 4.110317623312165e-19f);  // +1/20!
+    p = fmaf(p, v, -1.5619206968586225e-16f);  // -1/18!
+    p = fmaf(p, v, 4.779477332387385e-14f);  // +1/16!
+    p = fmaf(p, v, -1.1470745597729725e-11f);  // -1/14!
+    p = fmaf(p, v, 2.08767569878681e-09f);  // +1/12!
+    p = fmaf(p, v, -2.755731922398589e-07f);  // -1/10!
+    p = fmaf(p, v, 2.48015873015873e-05f);  // +1/8!
+    p = fmaf(p, v, -0.001388888888888889f);  // -1/6!
+    p = fmaf(p, v, 0.041666666666666664f);  // +1/4!
+    p = fmaf(p, v, -0.5f);  // -1/2!
+    return fmaf(p, v, 1.0f);  // +1/0!
+}
+
+__device__ __forceinline__ float sinc_series_full(float v) {
+    // sum_{k=0}^{12} (-1)^k v^k / (2k+1)!
+    float p = 6.446950284384474e-26f;  // +1/25!
+    p = fmaf(p, v, -3.868170170630684e-23f);  // -1/23!
+    p = fmaf(p, v, 1.9572941063391263e-20f);  // +1/21!
+    p = fmaf(p, v, -8.22063524662433e-18f);  // -1/19!
+    p = fmaf(p, v, 2.8114572543455206e-15f);  // +1/17!
+    p = fmaf(p, v, -7.647163731819816e-13f);  // -1/15!
+    p = fmaf(p, v, 1.6059043836821613e-10f);  // +1/13!
+    p = fmaf(p, v, -2.505210838544172e-08f);  // -1/11!
+    p = fmaf(p, v, 2.7557319223985893e-06f);  // +1/9!
+    p = fmaf(p, v, -0.0001984126984126984f);  // -1/7!
+    p = fmaf(p, v, 0.008333333333333333f);  // +1/5!
+    p = fmaf(p, v, -0.16666666666666666f);  // -1/3!
+    return fmaf(p, v, 1.0f);  // +1/1!
+}
+
+__device__ __forceinline__ float sincd_series_full(float v) {
+    // (x cos x - sin x) / x^3 = sum_{j=0}^{11} (-1)^(j+1) (2j+2) / (2j+3)! v^j
+    float p = 1.5472680682522736e-24f;  // +24/25!
+    p = fmaf(p, v, -8.509974375387505e-22f);  // -22/23!
+    p = fmaf(p, v, 3.9145882126782523e-19f);  // +20/21!
+    p = fmaf(p, v, -1.4797143443923793e-16f);  // -18/19!
+    p = fmaf(p, v, 4.498331606952833e-14f);  // +16/17!
+    p = fmaf(p, v, -1.0706029224547743e-11f);  // -14/15!
+    p = fmaf(p, v, 1.9270852604185937e-09f);  // +12/13!
+    p = fmaf(p, v, -2.505210838544172e-07f);  // -10/11!
+    p = fmaf(p, v, 2.2045855379188714e-05f);  // +8/9!
+    p = fmaf(p, v, -0.0011904761904761906f);  // -6/7!
+    p = fmaf(p, v, 0.03333333333333333f);  // +4/5!
+    return fmaf(p, v, -0.3333333333333333f);  // -2/3!
+}
+
+template <int KIND>
+__device__ __forceinline__ float profile(float E, const KParams &kp) {
+    if constexpr (KIND == DARB_GAUSS) {
+        return __builtin_amdgcn_exp2f(E * kp.exp2_c);
+    } else if constexpr (KIND == DARB_HALF_COS) {
+        float x = E * kp.inv_xi;
+        return cos_series_half(x * x);
+    } else if constexpr (KIND == DARB_RAISED_COS) {
+        return fmaf(0.5f, cos_series_full(E * kp.inv_xi2), 0.5f);
+    } else if constexpr (KIND == DARB_SINC) {
+        return sinc_series_full(E * kp.inv_xi2);
+    } else if constexpr (KIND == DARB_IMQ) {
+        return __builtin_amdgcn_rcpf(fmaf(E, kp.inv_xi, 1.0f));
+    } else if constexpr (KIND == DARB_IMQ_SQRT) {
+        return __builtin_amdgcn_rsqf(fmaf(E, kp.inv_xi, 1.0f));
+    } else {
+        return fmaf(-E, kp.inv_xi, 1.0f);
+    }
+}
+
+// dF/dE given E and the profile value w = F(E).
+template <int KIND>
+__device__ __forceinline__ float profile_deriv(float E, float w, const KParams &kp) {
+    if constexpr (KIND == DARB_GAUSS) {
+        return -w * kp.inv_xi;
+    } else if constexpr (KIND == DARB_HALF_COS) {
+        float x = E * kp.inv_xi;
+        return -(x * sinc_series_half(x * x)) * kp.inv_xi;
+    } else if constexpr (KIND == DARB_RAISED_COS) {
+        return -0.25f * sinc_series_full(E * kp.inv_xi2) * kp.inv_xi2;
+    } else if constexpr (KIND == DARB_SINC) {
+        return 0.5f * sincd_series_full(E * kp.inv_xi2) * kp.inv_xi2;
+    } else if constexpr (KIND == DARB_IMQ) {
+        return -(w * w) * kp.inv_xi;
+    } else if constexpr (KIND == DARB_IMQ_SQRT) {
+        return -0.5f * (w * w * w) * kp.inv_xi;
+    } else {
+        return -kp.inv_xi;
+    }
+}
+
+// One (pixel, splat) pair: offsets, Q d, E, profile, alpha, and the decision.
+// Shared verbatim by the forward and the backward raster kernels.
+struct Pair {
+    float dx, dy, q0, q1, E, w, alpha;
+    bool ok;
+};
+
+template <int KIND>
+__device__ __forceinline__ Pair eval_pair(float sx, float sy, float a, float b, float c, float o, float px, float py,
+                                          const KParams &kp, float amin, float amax) {
+    Pair p;
+    p.dx = sx - px;
+    p.dy = sy - py;
+    p.q0 = fmaf(a, p.dx, b * p.dy);
+    p.q1 = fmaf(b, p.dx, c * p.dy);
+    p.E = fmaf(p.q0, p.dx, p.q1 * p.dy);
+    bool inside = (p.E >= 0.0f) & (p.E <= kp.e_max);
+    // outside the support the profile value is never used: every consumer
+    // selects on `ok`, so no clamp of E is needed here
+    p.w = profile<KIND>(p.E, kp);
+    p.alpha = fminf(amax, o * p.w);
+    p.ok = inside & (p.alpha >= amin);
+    return p;
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront helpers (wave64).
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float readlane_f(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+__device__ __forceinline__ int readlane_i(int v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+
+// Sum over the 64 lanes with DPP row operations; the total lands in lane 63.
+__device__ __forceinline__ float wave_sum_to_lane63(float v) {
+    // within rows of 16: shr 1, 2, 4 (bound_ctrl=false keeps lanes without a source unchanged... use adds of zero)
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, false));  // row_shr:1
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xf, 0xf, false));  // row_shr:2
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xf, 0xf, false));  // row_shr:4
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xf, 0xf, false));  // row_shr:8
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xa, 0xf, false));  // row_bcast:15
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xc, 0xf, false));  // row_bcast:31
+    return v;
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// Inclusive prefix sum over the 64 lanes (u32), via LDS-free shuffles.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t t = __shfl_up(v, off, 64);
+        if (lane >= off) v += t;
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Internal launchers (implemented per stage).
+// ---------------------------------------------------------------------------
+
+struct Cam {
+    float R[9];  // R_cw
+    float t[3];  // t_cw
+    float campos[3];
+    float fx, fy, cx, cy;
+    int width, height;
+    float near_z, lim_x, lim_y;  // lim <= 0 disables the Jacobian clamp
+    float dilation;
+};
+
+hipError_t launch_preprocess(const Cam &cam, const KParams &kp, int n, const darb_splats &in,
+                             const darb_projected &out, hipStream_t s);
+hipError_t launch_preprocess_bwd(const Cam &cam, const KParams &kp, int n, const darb_splats &in,
+                                 const darb_grads2d &g2d, const darb_grads3d &g3d, hipStream_t s);
+
+size_t binsort_workspace(int n, int width, int height);
+hipError_t launch_bin_sort(const darb_projected &p, int n, int width, int height, int64_t k_capacity, void *ws,
+                           uint64_t *keys, uint32_t *vals, uint32_t *ranges, int64_t *k_dev, int32_t *overflow_dev,
+                           hipStream_t s);
+
+hipError_t launch_raster_fwd(int kind, const darb_projected &p, int n, const uint32_t *vals, const uint32_t *ranges,
+                             const int32_t *overflow, int width, int height, const KParams &kp, const ROpts &o,
+                             float *image, float *final_T, uint32_t *last, uint32_t *n_contrib, hipStream_t s);
+hipError_t launch_raster_bwd(int kind, const darb_projected &p, int n, const uint32_t *vals, const uint32_t *ranges,
+                             const int32_t *overflow, int width, int height, const KParams &kp, const ROpts &o,
+                             const float *dL_dimage, const float *final_T, const uint32_t *last,
+                             const darb_grads2d &g2d, hipStream_t s);
+
+}  // namespace darb

@@ -1,0 +1,448 @@
+// preprocess.hip -- per-splat projection of 3D DARBFs to 2D footprints and its
+// chain-rule backward (DARB Projection; Eq. of the 2x2 covariance projection
+// with the correction factor psi; bounding radius of the DARBF boundaries
+// section; SH colour of the 3DGS parameterisation kept by the paper).
+//
+// One thread per splat.  Parameters are structure-of-arrays, so each field
+// load of a wavefront is one coalesced 256-byte transaction; culled splats
+// stop after the 12-byte mean load.  HBM-bound.
+#include "common.h"
+
+namespace darb {
+
+namespace {
+
+// Real SH basis up to degree 3 (Condon-Shortley phase; index l^2 + l + m).
+struct SH {
+    float Y[16];
+};
+
+template <int NB>
+__device__ __forceinline__ void sh_eval(float x, float y, float z, float *Y) {
+    const float c0 = 0.28209479177387814f;   // 1/(2 sqrt(pi))
+    const float c1 = 0.4886025119029199f;    // sqrt(3/(4 pi))
+    const float c2a = 1.0925484305920792f;   // sqrt(15/pi)/2
+    const float c2b = 0.31539156525252005f;  // sqrt(5/pi)/4
+    const float c2c = 0.5462742152960396f;   // sqrt(15/pi)/4
+    const float c3a = 0.5900435899266435f;   // sqrt(35/(2 pi))/4
+    const float c3b = 2.890611442640554f;    // sqrt(105/pi)/2
+    const float c3c = 0.4570457994644658f;   // sqrt(21/(2 pi))/4
+    const float c3d = 0.3731763325901154f;   // sqrt(7/pi)/4
+    const float c3e = 1.445305721320277f;    // sqrt(105/pi)/4
+    Y[0] = c0;
+    if constexpr (NB > 1) {
+        Y[1] = -c1 * y;
+        Y[2] = c1 * z;
+        Y[3] = -c1 * x;
+    }
+    if constexpr (NB > 4) {
+        float xx = x * x, yy = y * y, zz = z * z;
+        Y[4] = c2a * (x * y);
+        Y[5] = -c2a * (y * z);
+        Y[6] = c2b * (2.0f * zz - xx - yy);
+        Y[7] = -c2a * (x * z);
+        Y[8] = c2c * (xx - yy);
+        if constexpr (NB > 9) {
+            Y[9] = -c3a * y * (3.0f * xx - yy);
+            Y[10] = c3b * (x * y) * z;
+            Y[11] = -c3c * y * (4.0f * zz - xx - yy);
+            Y[12] = c3d * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+            Y[13] = -c3c * x * (4.0f * zz - xx - yy);
+            Y[14] = c3e * z * (xx - yy);
+            Y[15] = -c3a * x * (xx - 3.0f * yy);
+        }
+    }
+}
+
+// Gradient of sum_b g_b Y_b(d) with respect to d (unnormalised direction).
+template <int NB>
+__device__ __forceinline__ void sh_grad(float x, float y, float z, const float *g, float *out) {
+    const float c1 = 0.4886025119029199f;
+    const float c2a = 1.0925484305920792f;
+    const float c2b = 0.31539156525252005f;
+    const float c2c = 0.5462742152960396f;
+    const float c3a = 0.5900435899266435f;
+    const float c3b = 2.890611442640554f;
+    const float c3c = 0.4570457994644658f;
+    const float c3d = 0.3731763325901154f;
+    const float c3e = 1.445305721320277f;
+    float gx = 0.f, gy = 0.f, gz = 0.f;
+    if constexpr (NB > 1) {
+        gy += -c1 * g[1];
+        gz += c1 * g[2];
+        gx += -c1 * g[3];
+    }
+    if constexpr (NB > 4) {
+        float xx = x * x, yy = y * y, zz = z * z;
+        gx += c2a * y * g[4];
+        gy += c2a * x * g[4];
+        gy += -c2a * z * g[5];
+        gz += -c2a * y * g[5];
+        gx += -2.0f * c2b * x * g[6];
+        gy += -2.0f * c2b * y * g[6];
+        gz += 4.0f * c2b * z * g[6];
+        gx += -c2a * z * g[7];
+        gz += -c2a * x * g[7];
+        gx += 2.0f * c2c * x * g[8];
+        gy += -2.0f * c2c * y * g[8];
+        if constexpr (NB > 9) {
+            gx += -c3a * 6.0f * x * y * g[9];
+            gy += -c3a * (3.0f * xx - 3.0f * yy) * g[9];
+            gx += c3b * y * z * g[10];
+            gy += c3b * x * z * g[10];
+            gz += c3b * x * y * g[10];
+            gx += c3c * 2.0f * x * y * g[11];
+            gy += -c3c * (4.0f * zz - xx - 3.0f * yy) * g[11];
+            gz += -c3c * 8.0f * y * z * g[11];
+            gx += -c3d * 6.0f * x * z * g[12];
+            gy += -c3d * 6.0f * y * z * g[12];
+            gz += c3d * (6.0f * zz - 3.0f * xx - 3.0f * yy) * g[12];
+            gx += -c3c * (4.0f * zz - 3.0f * xx - yy) * g[13];
+            gy += c3c * 2.0f * x * y * g[13];
+            gz += -c3c * 8.0f * x * z * g[13];
+            gx += c3e * 2.0f * x * z * g[14];
+            gy += -c3e * 2.0f * y * z * g[14];
+            gz += c3e * (xx - yy) * g[14];
+            gx += -c3a * (3.0f * xx - 3.0f * yy) * g[15];
+            gy += c3a * 6.0f * x * y * g[15];
+        }
+    }
+    out[0] = gx;
+    out[1] = gy;
+    out[2] = gz;
+}
+
+// Everything the forward computes for one splat and the backward needs again.
+struct Proj {
+    float t[3];
+    float xt, yt;
+    bool cx_, cy_;       // Jacobian clamp active in x / y
+    float J00, J02, J11, J12;
+    float A[6];          // J R_cw, 2x3
+    float Rq[9];         // rotation of the splat
+    float qn[4], qinv;   // unit quaternion, 1/|q|
+    float s[3];
+    float Sig[6];        // 3D covariance (xx, xy, xz, yy, yz, zz)
+    float c00, c01, c11; // 2D covariance
+    float det;
+    float a, b, c;       // conic
+    float u, v;          // mean2D
+    int radius;
+};
+
+// Projection of splat i; returns false when culled.
+__device__ __forceinline__ bool project(const Cam &cam, const KParams &kp, int n, int i, const darb_splats &in,
+                                        Proj &P) {
+    float mx = in.means[i], my = in.means[n + i], mz = in.means[2 * n + i];
+    const float *R = cam.R;
+    P.t[0] = fmaf(R[0], mx, fmaf(R[1], my, fmaf(R[2], mz, cam.t[0])));
+    P.t[1] = fmaf(R[3], mx, fmaf(R[4], my, fmaf(R[5], mz, cam.t[1])));
+    P.t[2] = fmaf(R[6], mx, fmaf(R[7], my, fmaf(R[8], mz, cam.t[2])));
+    if (!(P.t[2] > cam.near_z)) return false;
+
+    float qw = in.quats[i], qx = in.quats[n + i], qy = in.quats[2 * n + i], qz = in.quats[3 * n + i];
+    float qq = fmaf(qw, qw, fmaf(qx, qx, fmaf(qy, qy, qz * qz)));
+    if (!(qq > 0.0f)) return false;
+    float qnorm = sqrtf(qq);
+    P.qinv = 1.0f / qnorm;
+    float w = qw * P.qinv, x = qx * P.qinv, y = qy * P.qinv, z = qz * P.qinv;
+    P.qn[0] = w; P.qn[1] = x; P.qn[2] = y; P.qn[3] = z;
+    float *Rq = P.Rq;
+    Rq[0] = 1.0f - 2.0f * (y * y + z * z);
+    Rq[1] = 2.0f * (x * y - w * z);
+    Rq[2] = 2.0f * (x * z + w * y);
+    Rq[3] = 2.0f * (x * y + w * z);
+    Rq[4] = 1.0f - 2.0f * (x * x + z * z);
+    Rq[5] = 2.0f * (y * z - w * x);
+    Rq[6] = 2.0f * (x * z - w * y);
+    Rq[7] = 2.0f * (y * z + w * x);
+    Rq[8] = 1.0f - 2.0f * (x * x + y * y);
+
+    P.s[0] = in.scales[i]; P.s[1] = in.scales[n + i]; P.s[2] = in.scales[2 * n + i];
+    float s2[3] = {P.s[0] * P.s[0], P.s[1] * P.s[1], P.s[2] * P.s[2]};
+    // Sigma = Rq diag(s^2) Rq^T (upper triangle)
+    int k = 0;
+    for (int r = 0; r < 3; r++)
+        for (int cc = r; cc < 3; cc++) {
+            P.Sig[k++] = fmaf(Rq[r * 3 + 0] * s2[0], Rq[cc * 3 + 0],
+                              fmaf(Rq[r * 3 + 1] * s2[1], Rq[cc * 3 + 1], Rq[r * 3 + 2] * s2[2] * Rq[cc * 3 + 2]));
+        }
+
+    float tz = P.t[2], itz = 1.0f / tz;
+    P.xt = P.t[0] * itz;
+    P.yt = P.t[1] * itz;
+    P.cx_ = P.cy_ = false;
+    if (cam.lim_x > 0.0f) {
+        if (P.xt > cam.lim_x) { P.xt = cam.lim_x; P.cx_ = true; }
+        if (P.xt < -cam.lim_x) { P.xt = -cam.lim_x; P.cx_ = true; }
+        if (P.yt > cam.lim_y) { P.yt = cam.lim_y; P.cy_ = true; }
+        if (P.yt < -cam.lim_y) { P.yt = -cam.lim_y; P.cy_ = true; }
+    }
+    P.J00 = cam.fx * itz;
+    P.J02 = -cam.fx * P.xt * itz;
+    P.J11 = cam.fy * itz;
+    P.J12 = -cam.fy * P.yt * itz;
+    // A = J R_cw
+    for (int cc = 0; cc < 3; cc++) {
+        P.A[cc] = fmaf(P.J00, R[cc], P.J02 * R[6 + cc]);
+        P.A[3 + cc] = fmaf(P.J11, R[3 + cc], P.J12 * R[6 + cc]);
+    }
+    // M = A Sigma A^T
+    const float *S = P.Sig;  // xx xy xz yy yz zz
+    float AS0[3], AS1[3];
+    for (int r = 0; r < 2; r++) {
+        const float *a = P.A + 3 * r;
+        float *o = r ? AS1 : AS0;
+        o[0] = fmaf(a[0], S[0], fmaf(a[1], S[1], a[2] * S[2]));
+        o[1] = fmaf(a[0], S[1], fmaf(a[1], S[3], a[2] * S[4]));
+        o[2] = fmaf(a[0], S[2], fmaf(a[1], S[4], a[2] * S[5]));
+    }
+    float M00 = fmaf(AS0[0], P.A[0], fmaf(AS0[1], P.A[1], AS0[2] * P.A[2]));
+    float M01 = fmaf(AS0[0], P.A[3], fmaf(AS0[1], P.A[4], AS0[2] * P.A[5]));
+    float M11 = fmaf(AS1[0], P.A[3], fmaf(AS1[1], P.A[4], AS1[2] * P.A[5]));
+    P.c00 = fmaf(kp.psi, M00, cam.dilation);
+    P.c01 = kp.psi * M01;
+    P.c11 = fmaf(kp.psi, M11, cam.dilation);
+    P.det = fmaf(P.c00, P.c11, -(P.c01 * P.c01));
+    if (!(P.det > 0.0f)) return false;
+    float idet = 1.0f / P.det;
+    P.a = P.c11 * idet;
+    P.b = -P.c01 * idet;
+    P.c = P.c00 * idet;
+    P.u = fmaf(cam.fx, P.t[0] * itz, cam.cx);
+    P.v = fmaf(cam.fy, P.t[1] * itz, cam.cy);
+    float mid = 0.5f * (P.c00 + P.c11);
+    float disc = fmaf(mid, mid, -P.det);
+    float lam = mid + sqrtf(fmaxf(disc, 0.0f));
+    P.radius = (int)ceilf(3.0f * sqrtf(lam));
+    // radius box on the tile grid (same FP32 expression as the binning)
+    int gx = (cam.width + kTile - 1) / kTile, gy = (cam.height + kTile - 1) / kTile;
+    float r = (float)P.radius;
+    float x0 = fminf(fmaxf(floorf((P.u - r) * 0.0625f), 0.0f), (float)gx);
+    float x1 = fminf(fmaxf(floorf((P.u + r) * 0.0625f) + 1.0f, 0.0f), (float)gx);
+    float y0 = fminf(fmaxf(floorf((P.v - r) * 0.0625f), 0.0f), (float)gy);
+    float y1 = fminf(fmaxf(floorf((P.v + r) * 0.0625f) + 1.0f, 0.0f), (float)gy);
+    if (!((x1 > x0) & (y1 > y0))) return false;
+    return true;
+}
+
+// SH coefficients of splat i, all loads issued before any use: c[b][ch]
+template <int NB>
+__device__ __forceinline__ void load_sh(const float *sh, int n, int i, float (&c)[NB][3]) {
+#pragma unroll
+    for (int b = 0; b < NB; b++)
+#pragma unroll
+        for (int ch = 0; ch < 3; ch++) c[b][ch] = sh[(size_t)(b * 3 + ch) * n + i];
+}
+
+template <int DEG>
+__global__ __launch_bounds__(256) void k_preprocess(Cam cam, KParams kp, int n, darb_splats in, darb_projected out) {
+    constexpr int NB = (DEG + 1) * (DEG + 1);
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    Proj P;
+    if (!project(cam, kp, n, i, in, P)) {
+        out.radius[i] = 0;
+        return;
+    }
+    float c[NB][3];
+    load_sh<NB>(in.sh, n, i, c);
+    float op = in.opacity[i];
+    // colour
+    float dx = in.means[i] - cam.campos[0], dy = in.means[n + i] - cam.campos[1], dz = in.means[2 * n + i] - cam.campos[2];
+    float il = rsqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+    float Y[NB];
+    sh_eval<NB>(dx * il, dy * il, dz * il, Y);
+    float col[3];
+    uint8_t cl = 0;
+#pragma unroll
+    for (int ch = 0; ch < 3; ch++) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int b = 0; b < NB; b++) acc = fmaf(Y[b], c[b][ch], acc);
+        acc += 0.5f;
+        if (acc < 0.0f) cl |= (uint8_t)(1u << ch);
+        col[ch] = fmaxf(acc, 0.0f);
+    }
+    reinterpret_cast<float2 *>(out.xy)[i] = make_float2(P.u, P.v);
+    out.depth[i] = P.t[2];
+    out.radius[i] = P.radius;
+    reinterpret_cast<float4 *>(out.conic_o)[i] = make_float4(P.a, P.b, P.c, op);
+    out.rgb[3 * i] = col[0];
+    out.rgb[3 * i + 1] = col[1];
+    out.rgb[3 * i + 2] = col[2];
+    out.clamped[i] = cl;
+}
+
+template <int DEG>
+__global__ __launch_bounds__(256) void k_preprocess_bwd(Cam cam, KParams kp, int n, darb_splats in, darb_grads2d g2,
+                                                        darb_grads3d g3) {
+    constexpr int NB = (DEG + 1) * (DEG + 1);
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    Proj P;
+    bool vis = project(cam, kp, n, i, in, P);
+    if (!vis) {
+        for (int c = 0; c < 3; c++) {
+            g3.means[(size_t)c * n + i] = 0.0f;
+            g3.scales[(size_t)c * n + i] = 0.0f;
+        }
+        for (int c = 0; c < 4; c++) g3.quats[(size_t)c * n + i] = 0.0f;
+        g3.opacity[i] = 0.0f;
+#pragma unroll
+        for (int b = 0; b < NB * 3; b++) g3.sh[(size_t)b * n + i] = 0.0f;
+        return;
+    }
+    float csh[NB][3];
+    load_sh<NB>(in.sh, n, i, csh);
+    float grgb[3] = {g2.rgb[3 * i], g2.rgb[3 * i + 1], g2.rgb[3 * i + 2]};
+    float dmu[3] = {0.f, 0.f, 0.f};
+    g3.opacity[i] = g2.opacity[i];
+
+    // ---- colour -> SH coefficients and view direction
+    float vx = in.means[i] - cam.campos[0], vy = in.means[n + i] - cam.campos[1], vz = in.means[2 * n + i] - cam.campos[2];
+    float il = rsqrtf(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
+    float dx = vx * il, dy = vy * il, dz = vz * il;
+    float Y[NB];
+    sh_eval<NB>(dx, dy, dz, Y);
+    float gdir[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ch = 0; ch < 3; ch++) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int b = 0; b < NB; b++) acc = fmaf(Y[b], csh[b][ch], acc);
+        acc += 0.5f;
+        float gv = (acc < 0.0f) ? 0.0f : grgb[ch];
+        float gsh[NB];
+#pragma unroll
+        for (int b = 0; b < NB; b++) {
+            g3.sh[(size_t)(b * 3 + ch) * n + i] = Y[b] * gv;
+            gsh[b] = gv * csh[b][ch];
+        }
+        if constexpr (NB > 1) {
+            float gd[3];
+            sh_grad<NB>(dx, dy, dz, gsh, gd);
+            gdir[0] += gd[0];
+            gdir[1] += gd[1];
+            gdir[2] += gd[2];
+        }
+    }
+    float dd = fmaf(gdir[0], dx, fmaf(gdir[1], dy, gdir[2] * dz));
+    dmu[0] += (gdir[0] - dx * dd) * il;
+    dmu[1] += (gdir[1] - dy * dd) * il;
+    dmu[2] += (gdir[2] - dz * dd) * il;
+
+    // ---- conic -> 2D covariance: dL/dcov = -Q Ghat Q, Ghat = [[ga, gb/2], [gb/2, gc]]
+    float ga = g2.conic[3 * i], gb = 0.5f * g2.conic[3 * i + 1], gc = g2.conic[3 * i + 2];
+    float a = P.a, b = P.b, c = P.c;
+    // Q Ghat
+    float t00 = fmaf(a, ga, b * gb), t01 = fmaf(a, gb, b * gc);
+    float t10 = fmaf(b, ga, c * gb), t11 = fmaf(b, gb, c * gc);
+    float d00 = -fmaf(t00, a, t01 * b);
+    float d01 = -fmaf(t00, b, t01 * c);
+    float d11 = -fmaf(t10, b, t11 * c);
+    // psi: M -> psi M + eps I
+    float m00 = kp.psi * d00, m01 = kp.psi * d01, m11 = kp.psi * d11;
+    // M = A Sigma A^T: dSigma = A^T dM A, dA = 2 dM A Sigma
+    const float *A = P.A;
+    float dMA0[3], dMA1[3];  // dM A (2x3)
+    for (int cc = 0; cc < 3; cc++) {
+        dMA0[cc] = fmaf(m00, A[cc], m01 * A[3 + cc]);
+        dMA1[cc] = fmaf(m01, A[cc], m11 * A[3 + cc]);
+    }
+    float dS[9];
+    for (int r = 0; r < 3; r++)
+        for (int cc = 0; cc < 3; cc++) dS[r * 3 + cc] = fmaf(A[r], dMA0[cc], A[3 + r] * dMA1[cc]);
+    const float *Sg = P.Sig;
+    float Sf[9] = {Sg[0], Sg[1], Sg[2], Sg[1], Sg[3], Sg[4], Sg[2], Sg[4], Sg[5]};
+    float dA[6];
+    for (int cc = 0; cc < 3; cc++) {
+        dA[cc] = 2.0f * fmaf(dMA0[0], Sf[cc], fmaf(dMA0[1], Sf[3 + cc], dMA0[2] * Sf[6 + cc]));
+        dA[3 + cc] = 2.0f * fmaf(dMA1[0], Sf[cc], fmaf(dMA1[1], Sf[3 + cc], dMA1[2] * Sf[6 + cc]));
+    }
+    // A = J R_cw: dJ = dA R_cw^T
+    const float *R = cam.R;
+    float dJ00 = fmaf(dA[0], R[0], fmaf(dA[1], R[1], dA[2] * R[2]));
+    float dJ02 = fmaf(dA[0], R[6], fmaf(dA[1], R[7], dA[2] * R[8]));
+    float dJ11 = fmaf(dA[3], R[3], fmaf(dA[4], R[4], dA[5] * R[5]));
+    float dJ12 = fmaf(dA[3], R[6], fmaf(dA[4], R[7], dA[5] * R[8]));
+    float tx = P.t[0], ty = P.t[1], tz = P.t[2];
+    float itz = 1.0f / tz, itz2 = itz * itz;
+    float fx = cam.fx, fy = cam.fy;
+    float dxt_dtx = P.cx_ ? 0.0f : itz, dxt_dtz = P.cx_ ? 0.0f : -tx * itz2;
+    float dyt_dty = P.cy_ ? 0.0f : itz, dyt_dtz = P.cy_ ? 0.0f : -ty * itz2;
+    float dtx = dJ02 * (-fx * dxt_dtx * itz);
+    float dty = dJ12 * (-fy * dyt_dty * itz);
+    float dtz = dJ00 * (-fx * itz2) + dJ11 * (-fy * itz2);
+    dtz += dJ02 * (-fx * fmaf(dxt_dtz, tz, -P.xt) * itz2);
+    dtz += dJ12 * (-fy * fmaf(dyt_dtz, tz, -P.yt) * itz2);
+    // mean2D
+    float gu = g2.xy[2 * i], gvv = g2.xy[2 * i + 1];
+    dtx += gu * fx * itz;
+    dty += gvv * fy * itz;
+    dtz -= (gu * fx * tx + gvv * fy * ty) * itz2;
+    // t = R_cw mu + t_cw
+    dmu[0] += fmaf(R[0], dtx, fmaf(R[3], dty, R[6] * dtz));
+    dmu[1] += fmaf(R[1], dtx, fmaf(R[4], dty, R[7] * dtz));
+    dmu[2] += fmaf(R[2], dtx, fmaf(R[5], dty, R[8] * dtz));
+    g3.means[i] = dmu[0];
+    g3.means[(size_t)n + i] = dmu[1];
+    g3.means[(size_t)2 * n + i] = dmu[2];
+
+    // ---- Sigma = Mq Mq^T, Mq = Rq diag(s): dMq = 2 dSigma Mq; ds_j = sum_r dMq_rj Rq_rj; dRq_rj = dMq_rj s_j
+    const float *Rq = P.Rq;
+    float dR[9];
+    for (int cc = 0; cc < 3; cc++) {
+        float acc = 0.0f;
+        for (int r = 0; r < 3; r++) {
+            float dm = 2.0f * fmaf(dS[r * 3 + 0], Rq[0 * 3 + cc] * P.s[cc],
+                                   fmaf(dS[r * 3 + 1], Rq[1 * 3 + cc] * P.s[cc], dS[r * 3 + 2] * Rq[2 * 3 + cc] * P.s[cc]));
+            acc = fmaf(dm, Rq[r * 3 + cc], acc);
+            dR[r * 3 + cc] = dm * P.s[cc];
+        }
+        g3.scales[(size_t)cc * n + i] = acc;
+    }
+    float w = P.qn[0], x = P.qn[1], y = P.qn[2], z = P.qn[3];
+    float dq0 = 2.0f * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
+    float dq1 = 2.0f * (y * dR[1] + z * dR[2] + y * dR[3] - 2.0f * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] -
+                        2.0f * x * dR[8]);
+    float dq2 = 2.0f * (-2.0f * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7] -
+                        2.0f * y * dR[8]);
+    float dq3 = 2.0f * (-2.0f * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.0f * z * dR[4] + y * dR[5] +
+                        x * dR[6] + y * dR[7]);
+    float qd = fmaf(dq0, w, fmaf(dq1, x, fmaf(dq2, y, dq3 * z)));
+    g3.quats[i] = (dq0 - w * qd) * P.qinv;
+    g3.quats[(size_t)n + i] = (dq1 - x * qd) * P.qinv;
+    g3.quats[(size_t)2 * n + i] = (dq2 - y * qd) * P.qinv;
+    g3.quats[(size_t)3 * n + i] = (dq3 - z * qd) * P.qinv;
+}
+
+}  // namespace
+
+hipError_t launch_preprocess(const Cam &cam, const KParams &kp, int n, const darb_splats &in,
+                             const darb_projected &out, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    dim3 grid((n + 255) / 256);
+    switch (in.sh_degree) {
+    case 0: hipLaunchKernelGGL(k_preprocess<0>, grid, dim3(256), 0, s, cam, kp, n, in, out); break;
+    case 1: hipLaunchKernelGGL(k_preprocess<1>, grid, dim3(256), 0, s, cam, kp, n, in, out); break;
+    case 2: hipLaunchKernelGGL(k_preprocess<2>, grid, dim3(256), 0, s, cam, kp, n, in, out); break;
+    default: hipLaunchKernelGGL(k_preprocess<3>, grid, dim3(256), 0, s, cam, kp, n, in, out); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_preprocess_bwd(const Cam &cam, const KParams &kp, int n, const darb_splats &in,
+                                 const darb_grads2d &g2d, const darb_grads3d &g3d, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    dim3 grid((n + 255) / 256);
+    switch (in.sh_degree) {
+    case 0: hipLaunchKernelGGL(k_preprocess_bwd<0>, grid, dim3(256), 0, s, cam, kp, n, in, g2d, g3d); break;
+    case 1: hipLaunchKernelGGL(k_preprocess_bwd<1>, grid, dim3(256), 0, s, cam, kp, n, in, g2d, g3d); break;
+    case 2: hipLaunchKernelGGL(k_preprocess_bwd<2>, grid, dim3(256), 0, s, cam, kp, n, in, g2d, g3d); break;
+    default: hipLaunchKernelGGL(k_preprocess_bwd<3>, grid, dim3(256), 0, s, cam, kp, n, in, g2d, g3d); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace darb

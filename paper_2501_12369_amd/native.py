@@ -1,0 +1,249 @@
+"""ctypes binding of libdarb (``include/darb.h``): argument marshalling only.
+
+Each function has the name of the C entry point it calls and takes torch
+tensors (device memory) instead of raw pointers; every step of the rasterizer
+runs in the HIP library.  There is no fallback: if ``libdarb.so`` is missing
+or fails to load, :func:`lib` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdarb.so")
+
+c_float, c_int32, c_int64, c_void_p, c_size_t = (ctypes.c_float, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p,
+                                                  ctypes.c_size_t)
+
+DARB_OK, DARB_ERR_INVALID_ARG, DARB_ERR_CAPACITY, DARB_ERR_HIP, DARB_ERR_UNSUPPORTED = range(5)
+GAUSS, HALF_COS, RAISED_COS, SINC, IMQ, IMQ_SQRT, PARABOLA = range(7)
+
+EXPORTED = ("darb_version", "darb_status_string", "darb_last_error", "darb_preprocess", "darb_bin_sort_workspace",
+            "darb_bin_sort", "darb_raster_fwd", "darb_raster_bwd", "darb_preprocess_bwd")
+
+
+class DarbError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(message)
+        self.status = status
+
+
+class darb_camera(ctypes.Structure):
+    _fields_ = [("viewmat", c_float * 16), ("campos", c_float * 3), ("fx", c_float), ("fy", c_float),
+                ("cx", c_float), ("cy", c_float), ("width", c_int32), ("height", c_int32), ("near_z", c_float),
+                ("jac_clamp", c_float), ("dilation", c_float)]
+
+
+class darb_kernel(ctypes.Structure):
+    _fields_ = [("kind", c_int32), ("xi", c_float), ("psi", c_float), ("e_max", c_float)]
+
+
+class darb_raster_opts(ctypes.Structure):
+    _fields_ = [("alpha_min", c_float), ("alpha_max", c_float), ("t_min", c_float), ("bg", c_float * 3)]
+
+
+class darb_splats(ctypes.Structure):
+    _fields_ = [("means", c_void_p), ("scales", c_void_p), ("quats", c_void_p), ("opacity", c_void_p),
+                ("sh", c_void_p), ("sh_degree", c_int32)]
+
+
+class darb_projected(ctypes.Structure):
+    _fields_ = [("xy", c_void_p), ("depth", c_void_p), ("radius", c_void_p), ("conic_o", c_void_p),
+                ("rgb", c_void_p), ("clamped", c_void_p)]
+
+
+class darb_grads2d(ctypes.Structure):
+    _fields_ = [("xy", c_void_p), ("conic", c_void_p), ("opacity", c_void_p), ("rgb", c_void_p)]
+
+
+class darb_grads3d(ctypes.Structure):
+    _fields_ = [("means", c_void_p), ("scales", c_void_p), ("quats", c_void_p), ("opacity", c_void_p),
+                ("sh", c_void_p)]
+
+
+_lib = None
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """The loaded library; raises if it is not built (there is no CPU fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise DarbError(DARB_ERR_UNSUPPORTED,
+                            f"{_LIB_PATH} is not built; run `python -m paper_2501_12369_amd.build`")
+        L = ctypes.CDLL(_LIB_PATH)
+        L.darb_version.restype = c_int32
+        L.darb_status_string.restype = ctypes.c_char_p
+        L.darb_status_string.argtypes = [c_int32]
+        L.darb_last_error.restype = ctypes.c_char_p
+        P = ctypes.POINTER
+        L.darb_preprocess.restype = c_int32
+        L.darb_preprocess.argtypes = [P(darb_camera), P(darb_kernel), c_int64, P(darb_splats), P(darb_projected),
+                                      c_void_p]
+        L.darb_bin_sort_workspace.restype = c_size_t
+        L.darb_bin_sort_workspace.argtypes = [c_int64, c_int32, c_int32]
+        L.darb_bin_sort.restype = c_int32
+        L.darb_bin_sort.argtypes = [P(darb_projected), c_int64, c_int32, c_int32, c_int64, c_void_p, c_size_t,
+                                    c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, P(c_int64), c_void_p]
+        L.darb_raster_fwd.restype = c_int32
+        L.darb_raster_fwd.argtypes = [P(darb_projected), c_int64, c_void_p, c_void_p, c_void_p, c_int32, c_int32,
+                                      P(darb_kernel), P(darb_raster_opts), c_void_p, c_void_p, c_void_p, c_void_p,
+                                      c_void_p]
+        L.darb_raster_bwd.restype = c_int32
+        L.darb_raster_bwd.argtypes = [P(darb_projected), c_int64, c_void_p, c_void_p, c_void_p, c_int32, c_int32,
+                                      P(darb_kernel), P(darb_raster_opts), c_void_p, c_void_p, c_void_p,
+                                      P(darb_grads2d), P(darb_camera), P(darb_splats), P(darb_grads3d), c_void_p]
+        L.darb_preprocess_bwd.restype = c_int32
+        L.darb_preprocess_bwd.argtypes = [P(darb_camera), P(darb_kernel), c_int64, P(darb_splats), P(darb_grads2d),
+                                          P(darb_grads3d), c_void_p]
+        _lib = L
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status != DARB_OK:
+        L = lib()
+        msg = L.darb_last_error().decode()
+        raise DarbError(status, f"{where}: {L.darb_status_string(status).decode()}: {msg}")
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"tensor must live on the GPU, got {t.device}")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+# ---------------------------------------------------------------------------
+# struct builders
+# ---------------------------------------------------------------------------
+
+def camera_struct(cam: dict) -> darb_camera:
+    c = darb_camera()
+    vm = [float(v) for v in torch.as_tensor(cam["viewmat"], dtype=torch.float64).reshape(16).tolist()]
+    for i in range(16):
+        c.viewmat[i] = vm[i]
+    cp = [float(v) for v in torch.as_tensor(cam["campos"], dtype=torch.float64).reshape(3).tolist()]
+    for i in range(3):
+        c.campos[i] = cp[i]
+    c.fx, c.fy, c.cx, c.cy = float(cam["fx"]), float(cam["fy"]), float(cam["cx"]), float(cam["cy"])
+    c.width, c.height = int(cam["width"]), int(cam["height"])
+    c.near_z = float(cam.get("near_z", 0.2))
+    c.jac_clamp = float(cam.get("jac_clamp", 1.3))
+    c.dilation = float(cam.get("dilation", 0.3))
+    return c
+
+
+def kernel_struct(k) -> darb_kernel:
+    return darb_kernel(int(k.kind), float(k.xi), float(k.psi), float(k.e_max))
+
+
+def opts_struct(o: dict | None = None) -> darb_raster_opts:
+    o = o or {}
+    s = darb_raster_opts()
+    s.alpha_min = float(o.get("alpha_min", 1.0 / 255.0))
+    s.alpha_max = float(o.get("alpha_max", 0.99))
+    s.t_min = float(o.get("t_min", 1e-4))
+    bg = o.get("bg", (0.0, 0.0, 0.0))
+    for i in range(3):
+        s.bg[i] = float(bg[i])
+    return s
+
+
+def splats_struct(sp: dict) -> darb_splats:
+    return darb_splats(_ptr(sp["means"]), _ptr(sp["scales"]), _ptr(sp["quats"]), _ptr(sp["opacity"]),
+                       _ptr(sp["sh"]), int(sp["sh_degree"]))
+
+
+def projected_struct(p: dict) -> darb_projected:
+    return darb_projected(_ptr(p["xy"]), _ptr(p["depth"]), _ptr(p["radius"]), _ptr(p.get("conic_o")),
+                          _ptr(p.get("rgb")), _ptr(p.get("clamped")))
+
+
+def grads2d_struct(g: dict) -> darb_grads2d:
+    return darb_grads2d(_ptr(g["xy"]), _ptr(g["conic"]), _ptr(g["opacity"]), _ptr(g["rgb"]))
+
+
+def grads3d_struct(g: dict) -> darb_grads3d:
+    return darb_grads3d(_ptr(g["means"]), _ptr(g["scales"]), _ptr(g["quats"]), _ptr(g["opacity"]), _ptr(g["sh"]))
+
+
+# ---------------------------------------------------------------------------
+# entry points (same names as the C ABI)
+# ---------------------------------------------------------------------------
+
+def darb_version() -> int:
+    return int(lib().darb_version())
+
+
+def darb_preprocess(cam: dict, kernel, n: int, splats: dict, proj: dict, stream=None):
+    c, k, s, p = camera_struct(cam), kernel_struct(kernel), splats_struct(splats), projected_struct(proj)
+    _check(lib().darb_preprocess(ctypes.byref(c), ctypes.byref(k), n, ctypes.byref(s), ctypes.byref(p),
+                                 _stream(stream)), "darb_preprocess")
+
+
+def darb_bin_sort_workspace(n: int, width: int, height: int) -> int:
+    return int(lib().darb_bin_sort_workspace(n, width, height))
+
+
+def darb_bin_sort(proj: dict, n: int, width: int, height: int, k_capacity: int, ws, keys, vals, ranges, k_dev,
+                  overflow_dev, read_k: bool = False, stream=None):
+    """Returns K when ``read_k`` (blocking readback), else None."""
+    p = projected_struct(proj)
+    kh = c_int64(0)
+    st = lib().darb_bin_sort(ctypes.byref(p), n, width, height, k_capacity, _ptr(ws), ws.numel() * ws.element_size(),
+                             _ptr(keys), _ptr(vals), _ptr(ranges), _ptr(k_dev), _ptr(overflow_dev),
+                             ctypes.byref(kh) if read_k else None, _stream(stream))
+    if read_k and st == DARB_ERR_CAPACITY:
+        return int(kh.value)
+    _check(st, "darb_bin_sort")
+    return int(kh.value) if read_k else None
+
+
+def darb_raster_fwd(proj: dict, n: int, vals, ranges, overflow_dev, width: int, height: int, kernel, opts: dict,
+                    image, final_T, last, n_contrib=None, stream=None):
+    p, k, o = projected_struct(proj), kernel_struct(kernel), opts_struct(opts)
+    _check(lib().darb_raster_fwd(ctypes.byref(p), n, _ptr(vals), _ptr(ranges), _ptr(overflow_dev), width, height,
+                                 ctypes.byref(k), ctypes.byref(o), _ptr(image), _ptr(final_T), _ptr(last),
+                                 _ptr(n_contrib), _stream(stream)), "darb_raster_fwd")
+
+
+def darb_raster_bwd(proj: dict, n: int, vals, ranges, overflow_dev, width: int, height: int, kernel, opts: dict,
+                    dL_dimage, final_T, last, g2d: dict, cam: dict | None = None, splats: dict | None = None,
+                    g3d: dict | None = None, stream=None):
+    p, k, o = projected_struct(proj), kernel_struct(kernel), opts_struct(opts)
+    g2 = grads2d_struct(g2d)
+    if g3d is not None:
+        c, s, g3 = camera_struct(cam), splats_struct(splats), grads3d_struct(g3d)
+        cref, sref, g3ref = ctypes.byref(c), ctypes.byref(s), ctypes.byref(g3)
+    else:
+        cref = sref = g3ref = None
+    _check(lib().darb_raster_bwd(ctypes.byref(p), n, _ptr(vals), _ptr(ranges), _ptr(overflow_dev), width, height,
+                                 ctypes.byref(k), ctypes.byref(o), _ptr(dL_dimage), _ptr(final_T), _ptr(last),
+                                 ctypes.byref(g2), cref, sref, g3ref, _stream(stream)), "darb_raster_bwd")
+
+
+def darb_preprocess_bwd(cam: dict, kernel, n: int, splats: dict, g2d: dict, g3d: dict, stream=None):
+    c, k, s = camera_struct(cam), kernel_struct(kernel), splats_struct(splats)
+    g2, g3 = grads2d_struct(g2d), grads3d_struct(g3d)
+    _check(lib().darb_preprocess_bwd(ctypes.byref(c), ctypes.byref(k), n, ctypes.byref(s), ctypes.byref(g2),
+                                     ctypes.byref(g3), _stream(stream)), "darb_preprocess_bwd")

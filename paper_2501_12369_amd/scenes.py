@@ -117,13 +117,15 @@ def scene_splats(seed: int, n: int, n_clusters: int = 64, box: float = 10.0) -> 
         rots.append(qm)
     rots = np.stack(rots)
     which = rng.integers(0, n_clusters, size=n)
-    z = rng.standard_normal((n, 3)) * stds[which]
-    pts = np.einsum("nij,nj->ni", rots[which], z) + centres[which]
+    z = rng.standard_normal((n, 3, 1), dtype=np.float32) * stds[which][:, :, None].astype(np.float32)
+    pts = np.matmul(rots[which].astype(np.float32), z)[:, :, 0] + centres[which].astype(np.float32)
     means = np.clip(pts, -box, box).T
     scales = _log_uniform(rng, 0.002, 0.5, (3, n))
-    quats = _random_quats(rng, n)
+    q = rng.standard_normal((4, n), dtype=np.float32)
+    quats = q / np.linalg.norm(q, axis=0, keepdims=True)
     opacity = rng.beta(2.0, 2.0, size=n)
-    sh = rng.normal(0.0, 0.3, size=(16, 3, n)).astype(np.float32)
+    sh = rng.standard_normal((16, 3, n), dtype=np.float32)
+    sh *= np.float32(0.3)
     return _splats(means, scales, quats, opacity, sh, 3)
 
 

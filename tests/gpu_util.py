@@ -1,0 +1,109 @@
+"""Helpers shared by the GPU parity tests: run the HIP path (through the C ABI)
+on seeded numpy inputs and return numpy results, and the comparison rules."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+import oracle
+from paper_2501_12369_amd import native, pipeline
+
+PI = math.pi
+
+# Kernel definitions for the oracle, written from the paper (Table 2 xi, the
+# listings' psi and support); the HIP side has its own presets.
+ORACLE_KERNELS = {
+    "gauss": oracle.KernelSpec(oracle.GAUSS, 2.0, 1.0, 9.0),
+    "half_cos": oracle.KernelSpec(oracle.HALF_COS, 18.0 / PI, 1.36, 9.0),
+    "raised_cos": oracle.KernelSpec(oracle.RAISED_COS, 2.5 / PI, 0.655, 6.25),
+    "sinc": oracle.KernelSpec(oracle.SINC, 3.0 / PI, 1.18, 9.0),
+    "imq": oracle.KernelSpec(oracle.IMQ, 1.0, 1.38, 9.0),
+    "imq_sqrt": oracle.KernelSpec(oracle.IMQ_SQRT, 1.0, 1.61, 9.0),
+    "parabola": oracle.KernelSpec(oracle.PARABOLA, 9.0, 1.3, 9.0),
+}
+
+
+def oracle_kernel_fp32(name: str) -> oracle.KernelSpec:
+    """The oracle's kernel with xi/psi/e_max rounded to FP32, as the GPU receives them."""
+    k = ORACLE_KERNELS[name]
+    f = lambda v: float(np.float32(v))
+    return oracle.KernelSpec(k.kind, f(k.xi), f(k.psi), f(k.e_max))
+
+
+def oracle_opts_fp32(opts=None):
+    o = dict(pipeline.DEFAULT_OPTS)
+    o.update(opts or {})
+    f = lambda v: float(np.float32(v))
+    return oracle.make_opts(f(o["alpha_min"]), f(o["alpha_max"]), f(o["t_min"]), tuple(f(b) for b in o["bg"]))
+
+
+def dev(a, dtype=None):
+    t = torch.as_tensor(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda().contiguous()
+
+
+def projected_to_device(ps: dict) -> dict:
+    n = len(ps["radius"])
+    return dict(xy=dev(ps["xy"]), depth=dev(ps["depth"]), radius=dev(ps["radius"]), conic_o=dev(ps["conic_o"]),
+                rgb=dev(ps["rgb"]), clamped=torch.zeros(max(n, 1), dtype=torch.uint8, device="cuda")[:n])
+
+
+def oracle_projected(ps: dict) -> dict:
+    return dict(xy=ps["xy"].astype(np.float64), conic=ps["conic_o"][:, :3].astype(np.float64),
+                rgb=ps["rgb"].astype(np.float64), depth=ps["depth"].astype(np.float64),
+                valid=(ps["radius"] > 0).astype(np.int32))
+
+
+def gpu_bin_raster(ps: dict, kernel_name: str, opts=None, keys=True, cap=None):
+    """bin/sort + raster forward of synthetic projected splats on the GPU."""
+    n = len(ps["radius"])
+    W, H = ps["width"], ps["height"]
+    proj = projected_to_device(ps)
+    fr = pipeline.alloc_frame(n, W, H, cap if cap is not None else max(1, 64 * n), "cuda", keys=keys,
+                              n_contrib=True, proj=proj)
+    K = pipeline.bin_sort(fr, read_k=True)
+    k = pipeline.KERNELS[kernel_name]
+    native.darb_raster_fwd(fr.proj, n, fr.vals, fr.ranges, fr.overflow, W, H, k, opts or pipeline.DEFAULT_OPTS,
+                           fr.image, fr.final_T, fr.last, fr.n_contrib)
+    torch.cuda.synchronize()
+    return fr, K
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+def image_pixels(img_chw: np.ndarray) -> np.ndarray:
+    """[3, H, W] -> [H*W, 3] in the oracle's pixel order (row-major, x fastest)."""
+    return img_chw.reshape(3, -1).T
+
+
+def last_ids(fr) -> np.ndarray:
+    """Per-pixel splat id of the last blended instance (-1 if none)."""
+    last = to_np(fr.last).reshape(-1).astype(np.int64) & 0xFFFFFFFF
+    vals = to_np(fr.vals).astype(np.int64)
+    out = np.full(last.shape, -1, np.int64)
+    m = last != 0xFFFFFFFF
+    out[m] = vals[last[m]]
+    return out
+
+
+def grad_compare(g_gpu: np.ndarray, g_orc: np.ndarray, rel_l2=1e-3, rel_el=1e-3, abs_frac=1e-4, mask=None):
+    """Relative L2 error and the elementwise rule |d| <= rel_el |g| + abs_frac max|g|.
+    Returns (ok, rel_l2_error, worst_elementwise_ratio)."""
+    a = np.asarray(g_gpu, np.float64)
+    b = np.asarray(g_orc, np.float64)
+    if mask is not None:
+        a = a[mask]
+        b = b[mask]
+    if b.size == 0:
+        return True, 0.0, 0.0
+    nb = np.linalg.norm(b)
+    l2 = np.linalg.norm(a - b) / nb if nb > 0 else np.linalg.norm(a - b)
+    tol = rel_el * np.abs(b) + abs_frac * np.max(np.abs(b))
+    ratio = np.max(np.abs(a - b) / np.maximum(tol, 1e-30))
+    return (l2 <= rel_l2) and (ratio <= 1.0), float(l2), float(ratio)
