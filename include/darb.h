@@ -174,9 +174,11 @@ DARB_API darb_status darb_preprocess(const darb_camera *cam, const darb_kernel *
 
 /*
  * darb_bin_sort_workspace -- bytes of device workspace darb_bin_sort needs for
- * n splats and a width x height image.  Returns 0 for invalid sizes.
+ * n splats, a width x height image and an instance capacity k_capacity (the
+ * workspace holds an intermediate list bounded by the instance count).
+ * Returns 0 for invalid or unsupported sizes.
  */
-DARB_API size_t darb_bin_sort_workspace(int64_t n, int32_t width, int32_t height);
+DARB_API size_t darb_bin_sort_workspace(int64_t n, int32_t width, int32_t height, int64_t k_capacity);
 
 /*
  * darb_bin_sort -- tile binning and depth sort ("tile-based rasterization"
@@ -191,13 +193,15 @@ DARB_API size_t darb_bin_sort_workspace(int64_t n, int32_t width, int32_t height
  *   ranges    [tiles][2]  u32: ranges[t] = (#instances with tile < t, #instances with tile <= t)
  *   k_dev     [1] int64 device: K, the number of instances (always written)
  *   overflow_dev [1] int32 device: 1 when K > k_capacity, else 0 (always written);
- *             with overflow set keys/vals are not written and the raster
- *             calls given the same flag do nothing
+ *             with overflow set keys, vals and ranges are not written and the
+ *             raster calls given the same flag do nothing
  *   k_host    nullable host pointer: when given, the call blocks on `stream`
  *             and stores K there (not capturable in a graph); it then returns
  *             DARB_ERR_CAPACITY on overflow
- *   ws/ws_bytes  workspace of at least darb_bin_sort_workspace(n, width, height) bytes
- * tiles = ceil(width/16) * ceil(height/16) must be <= 16384.
+ *   ws/ws_bytes  workspace of at least darb_bin_sort_workspace(n, width, height, k_capacity) bytes
+ * tiles = ceil(width/16) * ceil(height/16) must be <= 16384, and the number of
+ * 8x8-tile groups ceil(tiles_x/8) * ceil(tiles_y/8) <= 1024.
+ * Splats with radius > 0 must have a finite positive depth.
  */
 DARB_API darb_status darb_bin_sort(const darb_projected *proj, int64_t n, int32_t width, int32_t height, int64_t k_capacity,
                           void *ws, size_t ws_bytes, uint64_t *keys, uint32_t *vals, uint32_t *ranges, int64_t *k_dev,

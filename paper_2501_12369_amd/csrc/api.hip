@@ -99,6 +99,8 @@ darb_status check_size(int32_t width, int32_t height) {
     if (width <= 0 || height <= 0) return fail(DARB_ERR_INVALID_ARG, "%s", "width/height must be > 0");
     int64_t gx = (width + darb::kTile - 1) / darb::kTile, gy = (height + darb::kTile - 1) / darb::kTile;
     if (gx * gy > darb::kMaxTiles) return fail(DARB_ERR_UNSUPPORTED, "%s", "more than 16384 tiles");
+    if (darb::binsort_super_tiles(width, height) > darb::kMaxSuperTiles)
+        return fail(DARB_ERR_UNSUPPORTED, "%s", "more than 1024 groups of 8x8 tiles (extreme aspect ratio)");
     return DARB_OK;
 }
 
@@ -188,11 +190,12 @@ darb_status darb_preprocess(const darb_camera *cam, const darb_kernel *kernel, i
     return hip_status(darb::launch_preprocess(c, kp, (int)n, *in, *out, (hipStream_t)stream), "darb_preprocess");
 }
 
-size_t darb_bin_sort_workspace(int64_t n, int32_t width, int32_t height) {
+size_t darb_bin_sort_workspace(int64_t n, int32_t width, int32_t height, int64_t k_capacity) {
     if (n < 0 || n > 0x7FFFFFFFll || width <= 0 || height <= 0) return 0;
+    if (k_capacity < 0 || k_capacity >= 0xFFFFFFFFll) return 0;
     int64_t gx = (width + darb::kTile - 1) / darb::kTile, gy = (height + darb::kTile - 1) / darb::kTile;
-    if (gx * gy > darb::kMaxTiles) return 0;
-    return darb::binsort_workspace((int)n, width, height);
+    if (gx * gy > darb::kMaxTiles || darb::binsort_super_tiles(width, height) > darb::kMaxSuperTiles) return 0;
+    return darb::binsort_workspace((int)n, width, height, k_capacity);
 }
 
 darb_status darb_bin_sort(const darb_projected *proj, int64_t n, int32_t width, int32_t height, int64_t k_capacity,
@@ -209,7 +212,7 @@ darb_status darb_bin_sort(const darb_projected *proj, int64_t n, int32_t width, 
     REQUIRE_PTR(overflow_dev);
     OPT_PTR(keys);
     if (k_capacity > 0) REQUIRE_PTR(vals);
-    size_t need = darb::binsort_workspace((int)n, width, height);
+    size_t need = darb::binsort_workspace((int)n, width, height, k_capacity);
     if (ws_bytes < need) {
         snprintf(g_err, sizeof(g_err), "workspace too small: %zu < %zu bytes", ws_bytes, need);
         return DARB_ERR_INVALID_ARG;

@@ -1,25 +1,30 @@
 // binsort.hip -- tile binning and per-tile depth order.
 //
 // Target order: instances (tile, splat) sorted by (tile, depth bits, splat
-// index).  Instead of a 45-bit radix sort over all K instances, the sort is
-// split so that K-sized data is written exactly once:
-//   1. keys     one thread per splat: depth bits for visible splats, a key
-//               above every finite depth for the rest; splat index as value.
-//   2. sort     stable LSD radix sort (8-bit digits) of the n (key, index)
-//               pairs -> splats in (depth, index) order.
-//   3. count    the depth-ordered splats are cut into chunks of kChunk; one
-//               wavefront per chunk builds the chunk's per-tile histogram in
-//               LDS and stores it tile-major: H[t * chunks + c].
-//   4. scan     one exclusive scan over H gives, for every (tile, chunk), the
-//               first output slot: slots of tile t come after all tiles < t,
-//               and within a tile after all earlier chunks.
-//   5. scatter  one wavefront per chunk loads its row of slots into LDS and
-//               walks its splats in depth order; per splat the lanes cover the
-//               splat's tile rectangle and claim slots with LDS fetch-adds,
-//               whose in-order execution within a wavefront keeps the order
-//               stable.
-// The radius box of every splat is recomputed from (xy, radius) with the same
-// FP32 expression everywhere.  HBM-bound.
+// index); ranges[t] delimit tile t.  The work is arranged so that every
+// K-sized array is written once, by runs of consecutive lanes (whole cache
+// lines: partial-line stores to HBM3E turn into read-modify-writes):
+//
+//   keys      one thread per splat: radius box on the 16x16 tile grid, per-block
+//             visible counts and box areas.  K (sum of the areas) is known here,
+//             so the capacity overflow is decided before any instance is written.
+//   compact   visible splats -> (depth bits, index) in index order.
+//   sort      stable LSD radix sort of the N_v depth keys (8-bit digits)
+//             -> splats in (depth, index) order.
+//   level 1   super-tiles of 8x8 tiles.  256 depth-ordered splats per workgroup;
+//             per super-tile a ballot over the lanes gives each covering splat
+//             its rank; a scan over (super-tile, chunk) turns counts into
+//             positions -> per super-tile lists of splats, still depth-ordered.
+//   level 2   1024 consecutive entries of one super-tile list per workgroup;
+//             for each of its 64 tiles a ballot ranks the covering entries and
+//             a scan over (tile, chunk) gives positions -> the final list, each
+//             (chunk, tile) run (about 500 entries here) written contiguously.
+//
+// Ranks come from ballots in lane order, so every step is stable and the result
+// is unique.  The radius box is recomputed from (xy, radius) with the same FP32
+// expression everywhere.  HBM-bound.
+#include <algorithm>
+
 #include "common.h"
 
 namespace darb {
@@ -32,13 +37,23 @@ constexpr int kScanBlock = kScanThreads * kScanItems;  // 2048 elements per bloc
 constexpr int kRadixThreads = 256;
 constexpr int kRadixItems = 16;
 constexpr int kRadixTile = kRadixThreads * kRadixItems;  // 4096 keys per block
-constexpr int kChunk = 1024;                              // splats per binning chunk
-constexpr uint32_t kKeyInvalid = 0x7FFFFFFFu;            // above every finite positive float's bits
+constexpr int kSuper = 8;                                 // super-tile = 8x8 tiles
+constexpr int kL1Threads = 256;                           // splats per level-1 chunk
+constexpr int kL1Waves = kL1Threads / 64;
+constexpr int kL2Threads = 1024;                          // list entries per level-2 chunk
+constexpr int kL2Waves = kL2Threads / 64;
+constexpr int kL2Grid = 2048;                             // persistent level-2 workgroups
 
 struct Counters {
-    uint32_t n_visible;
+    uint32_t n_visible;  // N_v
+    uint32_t c1;         // level-1 chunks
+    uint32_t h1_count;   // super-tiles * c1
+    uint32_t total1;     // level-1 list length
+    uint32_t total2;     // level-2 chunks
+    uint32_t h2_count;   // flattened level-2 count entries
+    uint32_t scan_total; // scratch total of the last scan
     uint32_t pad;
-    unsigned long long k_total;
+    unsigned long long K;
 };
 
 __device__ __forceinline__ int4 tile_rect(float u, float v, int radius, int gx, int gy) {
@@ -50,10 +65,15 @@ __device__ __forceinline__ int4 tile_rect(float u, float v, int radius, int gx, 
     return make_int4(x0, x1, y0, y1);
 }
 
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const int lane = threadIdx.x & 63;
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
 // ---------------------------------------------------------------------------
-// Generic exclusive scan of u32 (reduce -> scan block sums -> down-sweep).
-// The element count may live on the device (count_dev), with `max_count`
-// sizing the grid; blocks past the live count exit.
+// Exclusive scan of u32 (reduce -> scan block sums -> down-sweep).  The live
+// element count may sit on the device (count_dev), `max_count` sizes the grid;
+// blocks past the live count exit.  The total goes to *total_out (nullable).
 // ---------------------------------------------------------------------------
 
 __device__ __forceinline__ uint32_t live_count(const uint32_t *count_dev, uint32_t max_count) {
@@ -77,8 +97,10 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *lds_w,
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t *in, const uint32_t *count_dev,
-                                                              uint32_t max_count, uint32_t *parts) {
+                                                              uint32_t max_count, uint32_t *parts,
+                                                              const int32_t *skip) {
     __shared__ uint32_t lw[kScanThreads / 64];
+    if (skip && *skip) return;
     uint32_t count = live_count(count_dev, max_count);
     uint32_t base = blockIdx.x * kScanBlock;
     if (base >= count) return;
@@ -92,10 +114,11 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t *in
     if (threadIdx.x == 0) parts[blockIdx.x] = tot;
 }
 
-// single block: exclusive scan of the block sums; total -> parts[nblocks]
-__global__ __launch_bounds__(1024) void k_scan_parts(uint32_t *parts, const uint32_t *count_dev, uint32_t max_count) {
+__global__ __launch_bounds__(1024) void k_scan_parts(uint32_t *parts, const uint32_t *count_dev, uint32_t max_count,
+                                                     uint32_t *total_out, const int32_t *skip) {
     __shared__ uint32_t lw[16];
     __shared__ uint32_t carry;
+    if (skip && *skip) return;
     uint32_t count = live_count(count_dev, max_count);
     uint32_t nb = (count + kScanBlock - 1) / kScanBlock;
     if (threadIdx.x == 0) carry = 0;
@@ -118,16 +141,17 @@ __global__ __launch_bounds__(1024) void k_scan_parts(uint32_t *parts, const uint
         if (threadIdx.x == 0) carry = c + tot;
         __syncthreads();
     }
-    if (threadIdx.x == 0) parts[nb] = carry;
+    if (threadIdx.x == 0 && total_out) *total_out = carry;
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t *in, uint32_t *out, const uint32_t *count_dev,
-                                                            uint32_t max_count, const uint32_t *parts) {
+                                                            uint32_t max_count, const uint32_t *parts,
+                                                            const int32_t *skip) {
     __shared__ uint32_t lw[kScanThreads / 64];
+    if (skip && *skip) return;
     uint32_t count = live_count(count_dev, max_count);
     uint32_t base = blockIdx.x * kScanBlock;
     if (base >= count) return;
-    // blocked arrangement: thread t owns elements [base + t*kScanItems, +kScanItems)
     uint32_t v[kScanItems];
     uint32_t s = 0;
     uint32_t b0 = base + threadIdx.x * kScanItems;
@@ -143,28 +167,30 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t *in, 
     }
 }
 
-hipError_t scan_exclusive(const uint32_t *in, uint32_t *out, const uint32_t *count_dev, uint32_t max_count,
-                          uint32_t *parts, hipStream_t s) {
+hipError_t scan_exclusive(uint32_t *data, const uint32_t *count_dev, uint32_t max_count, uint32_t *parts,
+                          uint32_t *total_out, const int32_t *skip, hipStream_t s) {
     if (max_count == 0) return hipSuccess;
     uint32_t nb = (max_count + kScanBlock - 1) / kScanBlock;
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, s, in, count_dev, max_count, parts);
-    hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(1024), 0, s, parts, count_dev, max_count);
-    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kScanThreads), 0, s, in, out, count_dev, max_count, parts);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, s, data, count_dev, max_count, parts, skip);
+    hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(1024), 0, s, parts, count_dev, max_count, total_out, skip);
+    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kScanThreads), 0, s, data, data, count_dev, max_count, parts, skip);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Stable LSD radix sort of (u32 key, u32 value), 8-bit digits.
+// Stable LSD radix sort of (u32 key, u32 value), 8-bit digits, device count.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const uint32_t *keys, int n, int shift, uint32_t *hist,
-                                                              int nblk) {
+__global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const uint32_t *keys, const uint32_t *count_dev, int shift,
+                                                              uint32_t *hist, int nblk, const int32_t *skip) {
     __shared__ uint32_t h[256];
+    if (*skip) return;
+    const uint32_t n = *count_dev;
     h[threadIdx.x] = 0;
     __syncthreads();
-    int base = blockIdx.x * kRadixTile;
+    uint32_t base = blockIdx.x * kRadixTile;
     for (int k = 0; k < kRadixItems; k++) {
-        int i = base + k * kRadixThreads + threadIdx.x;
+        uint32_t i = base + k * kRadixThreads + threadIdx.x;
         if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
     }
     __syncthreads();
@@ -172,18 +198,23 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const uint32_t *ke
 }
 
 __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t *kin, const uint32_t *vin,
-                                                                 uint32_t *kout, uint32_t *vout, int n, int shift,
-                                                                 const uint32_t *hist_scan, int nblk) {
+                                                                 uint32_t *kout, uint32_t *vout,
+                                                                 const uint32_t *count_dev, int shift,
+                                                                 const uint32_t *hist_scan, int nblk,
+                                                                 const int32_t *skip) {
     __shared__ uint32_t run[256];
     __shared__ uint32_t wc[kRadixThreads / 64][256];
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    if (*skip) return;
+    const uint32_t n = *count_dev;
+    uint32_t base = blockIdx.x * kRadixTile;
+    if (base >= n) return;
+    const int t = threadIdx.x, w = t >> 6;
     run[t] = hist_scan[t * nblk + blockIdx.x];
     for (int k = 0; k < kRadixThreads / 64; k++) wc[k][t] = 0;
     __syncthreads();
-    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    int base = blockIdx.x * kRadixTile;
+    const uint64_t lt = lanemask_lt();
     for (int r = 0; r < kRadixItems; r++) {
-        int i = base + r * kRadixThreads + t;
+        uint32_t i = base + r * kRadixThreads + t;
         bool valid = i < n;
         uint32_t key = valid ? kin[i] : 0u;
         uint32_t val = valid ? vin[i] : 0u;
@@ -216,265 +247,531 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t 
 }
 
 // ---------------------------------------------------------------------------
-// Binning kernels.
+// Keys, sizes, compaction.
 // ---------------------------------------------------------------------------
 
 __global__ void k_bin_init(Counters *cnt, int64_t *k_dev, int32_t *overflow_dev) {
     if (threadIdx.x == 0) {
-        cnt->n_visible = 0;
-        cnt->k_total = 0;
+        *cnt = Counters{};
         *k_dev = 0;
         *overflow_dev = 0;
     }
 }
 
-// depth keys + per-block visible counts (summed by k_bin_sizes; no contended atomics)
-__global__ __launch_bounds__(256) void k_bin_keys(const float *xy, const int32_t *radius, const float *depth, int n,
-                                                  int gx, int gy, uint32_t *keys, uint32_t *vals,
-                                                  uint32_t *block_vis) {
-    __shared__ uint32_t wsum[4];
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    bool vis = false;
-    uint32_t key = kKeyInvalid;
-    if (i < n) {
-        int R = radius[i];
-        if (R > 0) {
-            float2 p = reinterpret_cast<const float2 *>(xy)[i];
-            int4 r = tile_rect(p.x, p.y, R, gx, gy);
-            if (r.y > r.x && r.w > r.z) {
-                vis = true;
-                key = __float_as_uint(depth[i]);
-            }
-        }
-        keys[i] = key;
-        vals[i] = (uint32_t)i;
-    }
-    uint64_t m = __ballot(vis);
-    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = (uint32_t)__popcll(m);
-    __syncthreads();
-    if (threadIdx.x == 0) block_vis[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+__device__ __forceinline__ bool splat_box(const float *xy, const int32_t *radius, int i, int gx, int gy, int4 &r) {
+    int R = radius[i];
+    if (R <= 0) return false;
+    float2 p = reinterpret_cast<const float2 *>(xy)[i];
+    r = tile_rect(p.x, p.y, R, gx, gy);
+    return (r.y > r.x) & (r.w > r.z);
 }
 
-// n_visible = sum of the block counts; chunks = ceil(n_visible / kChunk); element count of H = tiles * chunks
-__global__ __launch_bounds__(1024) void k_bin_sizes(const uint32_t *block_vis, int nblocks, Counters *cnt, int ntile,
-                                                    uint32_t *h_count) {
-    __shared__ uint32_t part[16];
-    uint32_t s = 0;
-    for (int b = threadIdx.x; b < nblocks; b += 1024) s += block_vis[b];
+// per 256-splat block: number of visible splats and the sum of their box areas
+__global__ __launch_bounds__(256) void k_bin_keys(const float *xy, const int32_t *radius, int n, int gx, int gy,
+                                                  uint32_t *block_vis, uint32_t *block_area) {
+    __shared__ uint32_t wv[4], wa[4];
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int4 r;
+    bool vis = (i < n) && splat_box(xy, radius, i, gx, gy, r);
+    uint32_t area = vis ? (uint32_t)((r.y - r.x) * (r.w - r.z)) : 0u;
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) s += (uint32_t)__shfl_xor((int)s, off, 64);
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+    for (int off = 32; off >= 1; off >>= 1) area += (uint32_t)__shfl_xor((int)area, off, 64);
+    uint64_t m = __ballot(vis);
+    if ((threadIdx.x & 63) == 0) {
+        wv[threadIdx.x >> 6] = (uint32_t)__popcll(m);
+        wa[threadIdx.x >> 6] = area;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t nv = 0;
-        for (int k = 0; k < 16; k++) nv += part[k];
-        cnt->n_visible = nv;
-        uint32_t chunks = (nv + kChunk - 1) / kChunk;
-        *h_count = chunks * (uint32_t)ntile;
+        block_vis[blockIdx.x] = wv[0] + wv[1] + wv[2] + wv[3];
+        block_area[blockIdx.x] = wa[0] + wa[1] + wa[2] + wa[3];
     }
 }
 
-// Rectangles of the 64 splats a wave handles next (lane l holds splat base + l).
-struct RectBatch {
-    int x0, w, y0, area;
-    uint32_t id, dbits;
-};
-
-__device__ __forceinline__ RectBatch load_rect(const uint32_t *sorted_ids, int j, int jend, const float *xy,
-                                               const int32_t *radius, const float *depth, int gx, int gy) {
-    RectBatch b;
-    b.x0 = b.w = b.y0 = b.area = 0;
-    b.id = 0;
-    b.dbits = 0;
-    if (j < jend) {
-        uint32_t id = sorted_ids[j];
-        float2 p = reinterpret_cast<const float2 *>(xy)[id];
-        int4 r = tile_rect(p.x, p.y, radius[id], gx, gy);
-        b.x0 = r.x;
-        b.w = r.y - r.x;
-        b.y0 = r.z;
-        b.area = b.w * (r.w - r.z);
-        b.id = id;
-        b.dbits = __float_as_uint(depth[id]);
-    }
-    return b;
-}
-
-__global__ __launch_bounds__(64) void k_bin_count(const uint32_t *sorted_ids, const float *xy, const int32_t *radius,
-                                                  const float *depth, int gx, int gy, const Counters *cnt,
-                                                  uint32_t *H, Counters *cnt_w) {
-    extern __shared__ uint32_t hist[];
-    const int ntile = gx * gy;
-    const uint32_t nv = cnt->n_visible;
-    const uint32_t chunks = (nv + kChunk - 1) / kChunk;
-    const uint32_t c = blockIdx.x;
-    if (c >= chunks) return;
-    const int lane = threadIdx.x;
-    for (int t = lane; t < ntile; t += 64) hist[t] = 0;
+// single workgroup: exclusive scan of the block visible counts (compaction
+// offsets), N_v, K = sum of the areas, capacity decision, level-1 sizes
+__global__ __launch_bounds__(1024) void k_bin_sizes(uint32_t *block_vis, const uint32_t *block_area, int nkb,
+                                                    int nsuper, Counters *cnt, int64_t k_capacity, int64_t *k_dev,
+                                                    int32_t *overflow_dev) {
+    __shared__ uint32_t lw[16];
+    __shared__ unsigned long long la[16];
+    __shared__ uint32_t carry;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (threadIdx.x == 0) carry = 0;
+    unsigned long long asum = 0;
     __syncthreads();
-    int jbeg = c * kChunk, jend = min((int)nv, jbeg + kChunk);
-    uint32_t total = 0;
-    for (int jb = jbeg; jb < jend; jb += 64) {
-        RectBatch rb = load_rect(sorted_ids, jb + lane, jend, xy, radius, depth, gx, gy);
-        int nb = min(64, jend - jb);
-        for (int s = 0; s < nb; s++) {
-            int x0 = readlane_i(rb.x0, s), w = readlane_i(rb.w, s), y0 = readlane_i(rb.y0, s);
-            int area = readlane_i(rb.area, s);
-            float rw = 1.0f / (float)w;
-            total += area;
-            for (int e = lane; e < area; e += 64) {
-                int q = (int)(((float)e + 0.5f) * rw);
-                int tx = x0 + (e - q * w), ty = y0 + q;
-                atomicAdd(&hist[ty * gx + tx], 1u);
-            }
+    for (int base = 0; base < nkb; base += 1024) {
+        int i = base + threadIdx.x;
+        uint32_t v = i < nkb ? block_vis[i] : 0u;
+        if (i < nkb) asum += block_area[i];
+        uint32_t inc = wave_incl_scan(v);
+        if (lane == 63) lw[w] = inc;
+        __syncthreads();
+        uint32_t woff = 0, tot = 0;
+        for (int k = 0; k < 16; k++) {
+            if (k < w) woff += lw[k];
+            tot += lw[k];
         }
+        uint32_t c = carry;
+        if (i < nkb) block_vis[i] = c + woff + inc - v;
+        __syncthreads();
+        if (threadIdx.x == 0) carry = c + tot;
+        __syncthreads();
     }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) asum += __shfl_xor(asum, off, 64);
+    if (lane == 0) la[w] = asum;
     __syncthreads();
-    for (int t = lane; t < ntile; t += 64) H[(size_t)t * chunks + c] = hist[t];
-    if (lane == 0) atomicAdd(&cnt_w->k_total, (unsigned long long)total);
-}
-
-__global__ __launch_bounds__(256) void k_bin_ranges(const uint32_t *Hs, const uint32_t *h_parts_total, int ntile,
-                                                    const Counters *cnt, uint32_t *ranges, int64_t k_capacity,
-                                                    int64_t *k_dev, int32_t *overflow_dev) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t chunks = (cnt->n_visible + kChunk - 1) / kChunk;
-    unsigned long long K = cnt->k_total;
-    if (t < ntile) {
-        uint32_t b = chunks ? Hs[(size_t)t * chunks] : 0u;
-        uint32_t e = (t + 1 < ntile) ? (chunks ? Hs[(size_t)(t + 1) * chunks] : 0u) : (uint32_t)K;
-        ranges[2 * t] = b;
-        ranges[2 * t + 1] = e;
-    }
-    if (t == 0) {
+    if (threadIdx.x == 0) {
+        unsigned long long K = 0;
+        for (int k = 0; k < 16; k++) K += la[k];
+        uint32_t nv = carry;
+        cnt->n_visible = nv;
+        cnt->c1 = (nv + kL1Threads - 1) / kL1Threads;
+        cnt->h1_count = cnt->c1 * (uint32_t)nsuper;
+        cnt->K = K;
         *k_dev = (int64_t)K;
         *overflow_dev = (K > (unsigned long long)k_capacity || K >= 0xFFFFFFFFull) ? 1 : 0;
     }
 }
 
-__global__ __launch_bounds__(64) void k_bin_scatter(const uint32_t *sorted_ids, const float *xy, const int32_t *radius,
-                                                    const float *depth, int gx, int gy, const Counters *cnt,
-                                                    const uint32_t *Hs, const int32_t *overflow_dev, int64_t k_capacity,
-                                                    uint64_t *keys, uint32_t *vals) {
-    extern __shared__ uint32_t slot[];
+__global__ __launch_bounds__(256) void k_bin_compact(const float *xy, const int32_t *radius, const float *depth, int n,
+                                                     int gx, int gy, const uint32_t *block_off, uint32_t *keys,
+                                                     uint32_t *vals, const int32_t *overflow_dev) {
+    __shared__ uint32_t wv[4];
     if (*overflow_dev) return;
-    const int ntile = gx * gy;
-    const uint32_t nv = cnt->n_visible;
-    const uint32_t chunks = (nv + kChunk - 1) / kChunk;
-    const uint32_t c = blockIdx.x;
-    if (c >= chunks) return;
-    const int lane = threadIdx.x;
-    for (int t = lane; t < ntile; t += 64) slot[t] = Hs[(size_t)t * chunks + c];
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int4 r;
+    bool vis = (i < n) && splat_box(xy, radius, i, gx, gy, r);
+    uint64_t m = __ballot(vis);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) wv[w] = (uint32_t)__popcll(m);
     __syncthreads();
-    int jbeg = c * kChunk, jend = min((int)nv, jbeg + kChunk);
-    for (int jb = jbeg; jb < jend; jb += 64) {
-        RectBatch rb = load_rect(sorted_ids, jb + lane, jend, xy, radius, depth, gx, gy);
-        int nb = min(64, jend - jb);
-        for (int s = 0; s < nb; s++) {
-            int x0 = readlane_i(rb.x0, s), w = readlane_i(rb.w, s), y0 = readlane_i(rb.y0, s);
-            int area = readlane_i(rb.area, s);
-            uint32_t id = (uint32_t)readlane_i((int)rb.id, s);
-            uint32_t db = (uint32_t)readlane_i((int)rb.dbits, s);
-            float rw = 1.0f / (float)w;
-            for (int e = lane; e < area; e += 64) {
-                int q = (int)(((float)e + 0.5f) * rw);
-                int tx = x0 + (e - q * w), ty = y0 + q;
+    if (vis) {
+        uint32_t pos = block_off[blockIdx.x] + (uint32_t)__popcll(m & lanemask_lt());
+        for (int k = 0; k < w; k++) pos += wv[k];
+        keys[pos] = __float_as_uint(depth[i]);
+        vals[pos] = (uint32_t)i;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Level 1: depth-ordered splats -> per-super-tile lists.
+// ---------------------------------------------------------------------------
+
+struct SuperBox {
+    int sx0, sx1, sy0, sy1;  // inclusive super-tile range
+};
+
+__device__ __forceinline__ SuperBox super_box(int4 r) {
+    return SuperBox{r.x / kSuper, (r.y - 1) / kSuper, r.z / kSuper, (r.w - 1) / kSuper};
+}
+
+// wc[g * kL1Waves + w] = number of splats of wave w covering super-tile g
+__device__ __forceinline__ void l1_ballots(bool valid, SuperBox sb, int nsuper, int sxn, uint32_t *wc) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int gxs = 0, gys = 0;
+    for (int g = 0; g < nsuper; g++) {
+        bool cov = valid & (gxs >= sb.sx0) & (gxs <= sb.sx1) & (gys >= sb.sy0) & (gys <= sb.sy1);
+        uint64_t m = __ballot(cov);
+        if (lane == 0) wc[g * kL1Waves + w] = (uint32_t)__popcll(m);
+        if (++gxs == sxn) {
+            gxs = 0;
+            gys++;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kL1Threads) void k_l1_count(const uint32_t *sorted_ids, const float *xy,
+                                                         const int32_t *radius, int gx, int gy, int sxn, int nsuper,
+                                                         const Counters *cnt, uint32_t *h1,
+                                                         const int32_t *overflow_dev) {
+    extern __shared__ uint32_t wc[];
+    if (*overflow_dev) return;
+    const uint32_t c = blockIdx.x, c1 = cnt->c1, nv = cnt->n_visible;
+    if (c >= c1) return;
+    uint32_t j = c * kL1Threads + threadIdx.x;
+    bool valid = j < nv;
+    int4 r = make_int4(0, 1, 0, 1);
+    if (valid) splat_box(xy, radius, (int)sorted_ids[j], gx, gy, r);
+    l1_ballots(valid, super_box(r), nsuper, sxn, wc);
+    __syncthreads();
+    for (int g = threadIdx.x; g < nsuper; g += kL1Threads) {
+        uint32_t s = 0;
+        for (int k = 0; k < kL1Waves; k++) s += wc[g * kL1Waves + k];
+        h1[(size_t)g * c1 + c] = s;  // super-tile-major
+    }
+}
+
+__global__ __launch_bounds__(kL1Threads) void k_l1_scatter(const uint32_t *sorted_ids, const float *xy,
+                                                           const int32_t *radius, int gx, int gy, int sxn, int nsuper,
+                                                           const Counters *cnt, const uint32_t *base1,
+                                                           uint32_t *list1, int64_t list1_cap,
+                                                           const int32_t *overflow_dev) {
+    extern __shared__ uint32_t wc[];  // [nsuper * kL1Waves] counts, then [nsuper * kL1Waves] first slots
+    uint32_t *slot = wc + nsuper * kL1Waves;
+    if (*overflow_dev) return;
+    const uint32_t c = blockIdx.x, c1 = cnt->c1, nv = cnt->n_visible;
+    if (c >= c1) return;
+    const int w = threadIdx.x >> 6;
+    uint32_t j = c * kL1Threads + threadIdx.x;
+    bool valid = j < nv;
+    uint32_t id = valid ? sorted_ids[j] : 0u;
+    int4 r = make_int4(0, 1, 0, 1);
+    if (valid) splat_box(xy, radius, (int)id, gx, gy, r);
+    SuperBox sb = super_box(r);
+    l1_ballots(valid, sb, nsuper, sxn, wc);
+    __syncthreads();
+    // first slot of every (super-tile, wave): chunk base + counts of the earlier waves
+    for (int idx = threadIdx.x; idx < nsuper * kL1Waves; idx += kL1Threads) {
+        int g = idx / kL1Waves, ww = idx % kL1Waves;
+        uint32_t s = base1[(size_t)g * c1 + c];
+        for (int k = 0; k < ww; k++) s += wc[g * kL1Waves + k];
+        slot[idx] = s;
+    }
+    __syncthreads();
+    const uint64_t lt = lanemask_lt();
+    int gxs = 0, gys = 0;
+    for (int g = 0; g < nsuper; g++) {
+        bool cov = valid & (gxs >= sb.sx0) & (gxs <= sb.sx1) & (gys >= sb.sy0) & (gys <= sb.sy1);
+        uint64_t m = __ballot(cov);
+        if (cov) {
+            uint32_t pos = slot[g * kL1Waves + w] + (uint32_t)__popcll(m & lt);
+            if ((int64_t)pos < list1_cap) list1[pos] = id;
+        }
+        if (++gxs == sxn) {
+            gxs = 0;
+            gys++;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Level-2 plan: super-tile list spans, level-2 chunks, per-tile offsets of the
+// (tile, chunk) count array in row-major tile order.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(1024) void k_l2_plan(const uint32_t *base1, Counters *cnt, int nsuper, int sxn, int gx,
+                                                  int gy, uint32_t *l1_start, uint32_t *l1_len, uint32_t *chunk2_start,
+                                                  uint32_t *toff, const int32_t *overflow_dev) {
+    __shared__ uint32_t lw[16];
+    __shared__ uint32_t carry;
+    __shared__ uint32_t n2s[1024];
+    if (*overflow_dev) return;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t c1 = cnt->c1, total1 = cnt->total1;
+    // spans and chunk counts (nsuper <= 1024)
+    int g = threadIdx.x;
+    uint32_t n2 = 0;
+    if (g < nsuper) {
+        uint32_t s = c1 ? base1[(size_t)g * c1] : 0u;
+        uint32_t e = (g + 1 < nsuper) ? (c1 ? base1[(size_t)(g + 1) * c1] : 0u) : total1;
+        l1_start[g] = s;
+        l1_len[g] = e - s;
+        n2 = (e - s + kL2Threads - 1) / kL2Threads;
+        n2s[g] = n2;
+    }
+    uint32_t inc = wave_incl_scan(n2);
+    if (lane == 63) lw[w] = inc;
+    __syncthreads();
+    uint32_t woff = 0, tot = 0;
+    for (int k = 0; k < 16; k++) {
+        if (k < w) woff += lw[k];
+        tot += lw[k];
+    }
+    if (g < nsuper) chunk2_start[g] = woff + inc - n2;
+    if (g == 0) {
+        chunk2_start[nsuper] = tot;
+        cnt->total2 = tot;
+        carry = 0;
+    }
+    __syncthreads();
+    // toff[t] = exclusive scan over row-major tiles of the chunk count of t's super-tile
+    const int ntile = gx * gy;
+    for (int base = 0; base < ntile; base += 1024) {
+        int t = base + threadIdx.x;
+        uint32_t v = 0;
+        if (t < ntile) {
+            int tx = t % gx, ty = t / gx;
+            v = n2s[(ty / kSuper) * sxn + tx / kSuper];
+        }
+        uint32_t inc2 = wave_incl_scan(v);
+        __syncthreads();
+        if (lane == 63) lw[w] = inc2;
+        __syncthreads();
+        uint32_t wo = 0, tt = 0;
+        for (int k = 0; k < 16; k++) {
+            if (k < w) wo += lw[k];
+            tt += lw[k];
+        }
+        uint32_t cc = carry;
+        if (t < ntile) toff[t] = cc + wo + inc2 - v;
+        __syncthreads();
+        if (threadIdx.x == 0) carry = cc + tt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        toff[ntile] = carry;
+        cnt->h2_count = carry;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Level 2: one super-tile list chunk per workgroup iteration.
+// ---------------------------------------------------------------------------
+
+struct L2Chunk {
+    int g;         // super-tile
+    uint32_t c2;   // chunk index within the super-tile
+    uint32_t len;  // entries in this chunk
+    uint32_t first;  // index into list1 of the chunk's first entry
+};
+
+// chunk2_start is the workgroup's LDS copy
+__device__ __forceinline__ L2Chunk l2_locate(uint32_t wi, const uint32_t *chunk2_start, int nsuper,
+                                             const uint32_t *l1_start, const uint32_t *l1_len) {
+    int lo = 0, hi = nsuper - 1;  // largest g with chunk2_start[g] <= wi
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (chunk2_start[mid] <= wi) lo = mid; else hi = mid - 1;
+    }
+    L2Chunk C;
+    C.g = lo;
+    C.c2 = wi - chunk2_start[lo];
+    uint32_t off = C.c2 * kL2Threads;
+    C.len = min((uint32_t)kL2Threads, l1_len[lo] - off);
+    C.first = l1_start[lo] + off;
+    return C;
+}
+
+// wc[tl * kL2Waves + w] for the 64 tiles tl of super-tile g
+__device__ __forceinline__ void l2_ballots(bool valid, int4 r, int g, int sxn, int gx, int gy, uint32_t *wc) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int tx0 = (g % sxn) * kSuper, ty0 = (g / sxn) * kSuper;
+    for (int tl = 0; tl < kSuper * kSuper; tl++) {
+        int tx = tx0 + (tl & (kSuper - 1)), ty = ty0 + tl / kSuper;
+        bool cov = valid & (tx >= r.x) & (tx < r.y) & (ty >= r.z) & (ty < r.w);
+        uint64_t m = __ballot(cov);
+        if (lane == 0) wc[tl * kL2Waves + w] = (uint32_t)__popcll(m);
+    }
+}
+
+__global__ __launch_bounds__(kL2Threads) void k_l2_count(const uint32_t *list1, const uint32_t *l1_start,
+                                                         const uint32_t *l1_len, const uint32_t *chunk2_start,
+                                                         const uint32_t *toff, const float *xy, const int32_t *radius,
+                                                         int gx, int gy, int sxn, int nsuper, const Counters *cnt,
+                                                         uint32_t *h2, const int32_t *overflow_dev) {
+    __shared__ uint32_t wc[kSuper * kSuper * kL2Waves];
+    __shared__ uint32_t c2s[kMaxSuperTiles + 1];
+    if (*overflow_dev) return;
+    const uint32_t total2 = cnt->total2;
+    for (int g = threadIdx.x; g <= nsuper; g += kL2Threads) c2s[g] = chunk2_start[g];
+    __syncthreads();
+    for (uint32_t wi = blockIdx.x; wi < total2; wi += gridDim.x) {
+        L2Chunk C = l2_locate(wi, c2s, nsuper, l1_start, l1_len);
+        bool valid = threadIdx.x < C.len;
+        int4 r = make_int4(0, 0, 0, 0);
+        if (valid) splat_box(xy, radius, (int)list1[C.first + threadIdx.x], gx, gy, r);
+        l2_ballots(valid, r, C.g, sxn, gx, gy, wc);
+        __syncthreads();
+        if (threadIdx.x < kSuper * kSuper) {
+            int tl = threadIdx.x;
+            int tx = (C.g % sxn) * kSuper + (tl & (kSuper - 1)), ty = (C.g / sxn) * kSuper + tl / kSuper;
+            if (tx < gx && ty < gy) {
+                uint32_t s = 0;
+                for (int k = 0; k < kL2Waves; k++) s += wc[tl * kL2Waves + k];
+                h2[toff[ty * gx + tx] + C.c2] = s;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kL2Threads) void k_l2_scatter(const uint32_t *list1, const uint32_t *l1_start,
+                                                           const uint32_t *l1_len, const uint32_t *chunk2_start,
+                                                           const uint32_t *toff, const uint32_t *base2, const float *xy,
+                                                           const int32_t *radius, const float *depth, int gx, int gy,
+                                                           int sxn, int nsuper, const Counters *cnt, int64_t k_capacity,
+                                                           uint64_t *keys, uint32_t *vals,
+                                                           const int32_t *overflow_dev) {
+    __shared__ uint32_t wc[kSuper * kSuper * kL2Waves];
+    __shared__ uint32_t slot[kSuper * kSuper * kL2Waves];
+    __shared__ uint32_t c2s[kMaxSuperTiles + 1];
+    if (*overflow_dev) return;
+    const uint32_t total2 = cnt->total2;
+    const int w = threadIdx.x >> 6;
+    const uint64_t lt = lanemask_lt();
+    for (int g = threadIdx.x; g <= nsuper; g += kL2Threads) c2s[g] = chunk2_start[g];
+    __syncthreads();
+    for (uint32_t wi = blockIdx.x; wi < total2; wi += gridDim.x) {
+        L2Chunk C = l2_locate(wi, c2s, nsuper, l1_start, l1_len);
+        bool valid = threadIdx.x < C.len;
+        int4 r = make_int4(0, 0, 0, 0);
+        uint32_t id = 0, db = 0;
+        if (valid) {
+            id = list1[C.first + threadIdx.x];
+            splat_box(xy, radius, (int)id, gx, gy, r);
+            db = __float_as_uint(depth[id]);
+        }
+        l2_ballots(valid, r, C.g, sxn, gx, gy, wc);
+        __syncthreads();
+        const int tx0 = (C.g % sxn) * kSuper, ty0 = (C.g / sxn) * kSuper;
+        {
+            // thread (tile tl, wave ww): first slot of wave ww's entries in tile tl
+            const int tl = threadIdx.x / kL2Waves, ww = threadIdx.x % kL2Waves;
+            const int tx = tx0 + (tl & (kSuper - 1)), ty = ty0 + tl / kSuper;
+            if (tx < gx && ty < gy) {
+                uint32_t s = base2[toff[ty * gx + tx] + C.c2];
+                for (int k = 0; k < ww; k++) s += wc[tl * kL2Waves + k];
+                slot[threadIdx.x] = s;
+            }
+        }
+        __syncthreads();
+        for (int tl = 0; tl < kSuper * kSuper; tl++) {
+            int tx = tx0 + (tl & (kSuper - 1)), ty = ty0 + tl / kSuper;
+            bool cov = valid & (tx >= r.x) & (tx < r.y) & (ty >= r.z) & (ty < r.w);
+            uint64_t m = __ballot(cov);
+            if (cov) {
                 int t = ty * gx + tx;
-                uint32_t pos = atomicAdd(&slot[t], 1u);
-                if ((int64_t)pos < k_capacity) {  // always true when the flag is clear; guards the buffer
+                uint32_t pos = slot[tl * kL2Waves + w] + (uint32_t)__popcll(m & lt);
+                if ((int64_t)pos < k_capacity) {
                     vals[pos] = id;
                     if (keys) keys[pos] = ((uint64_t)(uint32_t)t << 32) | db;
                 }
             }
         }
+        __syncthreads();
     }
+}
+
+__global__ __launch_bounds__(256) void k_bin_ranges(const uint32_t *base2, const uint32_t *toff, int ntile,
+                                                    const Counters *cnt, uint32_t *ranges,
+                                                    const int32_t *overflow_dev) {
+    if (*overflow_dev) return;
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntile) return;
+    const uint32_t h2 = cnt->h2_count;
+    const uint32_t K = (uint32_t)cnt->K;
+    uint32_t a = toff[t], b = toff[t + 1];
+    ranges[2 * t] = a < h2 ? base2[a] : K;
+    ranges[2 * t + 1] = b < h2 ? base2[b] : K;
 }
 
 inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct WsLayout {
-    size_t counters, keysA, valsA, keysB, valsB, hist, parts, H, hcount, blockvis, total;
+    size_t counters, blockvis, blockarea, keysA, valsA, keysB, valsB, hist, h1, list1, l1start, l1len, c2start,
+        toff, h2, parts, total;
+    uint32_t hist_n, h1_n, h2_n;
 };
 
-WsLayout layout(int n, int ntile) {
+inline int super_count(int gx, int gy) {
+    return ((gx + kSuper - 1) / kSuper) * ((gy + kSuper - 1) / kSuper);
+}
+
+WsLayout layout(int n, int gx, int gy, int64_t k_capacity) {
     WsLayout L;
+    const int ntile = gx * gy, nsuper = super_count(gx, gy);
     size_t off = 0;
-    int nblk = (n + kRadixTile - 1) / kRadixTile;
-    size_t chunks = ((size_t)n + kChunk - 1) / kChunk;
-    size_t hist_n = (size_t)256 * nblk;
-    size_t H_n = chunks * (size_t)ntile;
-    size_t parts_n = (std::max(hist_n, H_n) + kScanBlock - 1) / kScanBlock + 1;
+    const size_t nkb = ((size_t)n + 255) / 256;
+    const size_t nblk = ((size_t)n + kRadixTile - 1) / kRadixTile;
+    const size_t c1max = ((size_t)n + kL1Threads - 1) / kL1Threads;
+    const size_t cap = (size_t)std::max<int64_t>(k_capacity, 1);
+    const size_t total2max = cap / kL2Threads + nsuper + 1;
+    L.hist_n = (uint32_t)(256 * nblk);
+    L.h1_n = (uint32_t)(nsuper * c1max);
+    L.h2_n = (uint32_t)std::min<size_t>((size_t)kSuper * kSuper * total2max, 0xFFFFFFFFull);
+    size_t parts_n = (std::max<size_t>({L.hist_n, L.h1_n, L.h2_n}) + kScanBlock - 1) / kScanBlock + 1;
     L.counters = off; off += align_up(sizeof(Counters));
+    L.blockvis = off; off += align_up(nkb * 4);
+    L.blockarea = off; off += align_up(nkb * 4);
     L.keysA = off; off += align_up((size_t)n * 4);
     L.valsA = off; off += align_up((size_t)n * 4);
     L.keysB = off; off += align_up((size_t)n * 4);
     L.valsB = off; off += align_up((size_t)n * 4);
-    L.hist = off; off += align_up(hist_n * 4);
+    L.hist = off; off += align_up((size_t)L.hist_n * 4);
+    L.h1 = off; off += align_up((size_t)L.h1_n * 4);
+    L.list1 = off; off += align_up(cap * 4);
+    L.l1start = off; off += align_up((size_t)(nsuper + 1) * 4);
+    L.l1len = off; off += align_up((size_t)(nsuper + 1) * 4);
+    L.c2start = off; off += align_up((size_t)(nsuper + 1) * 4);
+    L.toff = off; off += align_up((size_t)(ntile + 1) * 4);
+    L.h2 = off; off += align_up((size_t)L.h2_n * 4);
     L.parts = off; off += align_up(parts_n * 4);
-    L.H = off; off += align_up(H_n * 4);
-    L.hcount = off; off += align_up(4);
-    L.blockvis = off; off += align_up(((size_t)n + 255) / 256 * 4);
     L.total = off;
     return L;
 }
 
 }  // namespace
 
-size_t binsort_workspace(int n, int width, int height) {
-    int gx = (width + kTile - 1) / kTile, gy = (height + kTile - 1) / kTile;
-    return layout(n, gx * gy).total;
+int binsort_super_tiles(int width, int height) {
+    return super_count((width + kTile - 1) / kTile, (height + kTile - 1) / kTile);
+}
+
+size_t binsort_workspace(int n, int width, int height, int64_t k_capacity) {
+    const int gx = (width + kTile - 1) / kTile, gy = (height + kTile - 1) / kTile;
+    return layout(n, gx, gy, k_capacity).total;
 }
 
 hipError_t launch_bin_sort(const darb_projected &p, int n, int width, int height, int64_t k_capacity, void *ws,
                            uint64_t *keys, uint32_t *vals, uint32_t *ranges, int64_t *k_dev, int32_t *overflow_dev,
                            hipStream_t s) {
     const int gx = (width + kTile - 1) / kTile, gy = (height + kTile - 1) / kTile, ntile = gx * gy;
-    WsLayout L = layout(n, ntile);
+    const int sxn = (gx + kSuper - 1) / kSuper, nsuper = super_count(gx, gy);
+    WsLayout L = layout(n, gx, gy, k_capacity);
     char *base = static_cast<char *>(ws);
+    auto U = [&](size_t o) { return reinterpret_cast<uint32_t *>(base + o); };
     Counters *cnt = reinterpret_cast<Counters *>(base + L.counters);
-    uint32_t *kA = reinterpret_cast<uint32_t *>(base + L.keysA);
-    uint32_t *vA = reinterpret_cast<uint32_t *>(base + L.valsA);
-    uint32_t *kB = reinterpret_cast<uint32_t *>(base + L.keysB);
-    uint32_t *vB = reinterpret_cast<uint32_t *>(base + L.valsB);
-    uint32_t *hist = reinterpret_cast<uint32_t *>(base + L.hist);
-    uint32_t *parts = reinterpret_cast<uint32_t *>(base + L.parts);
-    uint32_t *H = reinterpret_cast<uint32_t *>(base + L.H);
-    uint32_t *hcount = reinterpret_cast<uint32_t *>(base + L.hcount);
-    uint32_t *blockvis = reinterpret_cast<uint32_t *>(base + L.blockvis);
+    uint32_t *kA = U(L.keysA), *vA = U(L.valsA), *kB = U(L.keysB), *vB = U(L.valsB);
+    uint32_t *hist = U(L.hist), *parts = U(L.parts), *h1 = U(L.h1), *list1 = U(L.list1), *h2 = U(L.h2);
+    uint32_t *blockvis = U(L.blockvis), *blockarea = U(L.blockarea);
+    uint32_t *l1start = U(L.l1start), *l1len = U(L.l1len), *c2start = U(L.c2start), *toff = U(L.toff);
+    const uint32_t *nvis = &cnt->n_visible;
+    hipError_t e;
 
     hipLaunchKernelGGL(k_bin_init, dim3(1), dim3(64), 0, s, cnt, k_dev, overflow_dev);
+    const int nkb = (n + 255) / 256;
+    if (n > 0) hipLaunchKernelGGL(k_bin_keys, dim3(nkb), dim3(256), 0, s, p.xy, p.radius, n, gx, gy, blockvis, blockarea);
+    hipLaunchKernelGGL(k_bin_sizes, dim3(1), dim3(1024), 0, s, blockvis, blockarea, nkb, nsuper, cnt, k_capacity, k_dev,
+                       overflow_dev);
     if (n > 0) {
-        int nkb = (n + 255) / 256;
-        hipLaunchKernelGGL(k_bin_keys, dim3(nkb), dim3(256), 0, s, p.xy, p.radius, p.depth, n, gx, gy, kA, vA, blockvis);
-        hipLaunchKernelGGL(k_bin_sizes, dim3(1), dim3(1024), 0, s, blockvis, nkb, cnt, ntile, hcount);
-        // depth sort: 4 passes of 8 bits (keys fit in 31 bits)
-        int nblk = (n + kRadixTile - 1) / kRadixTile;
+        hipLaunchKernelGGL(k_bin_compact, dim3(nkb), dim3(256), 0, s, p.xy, p.radius, p.depth, n, gx, gy, blockvis, kA,
+                           vA, overflow_dev);
+        // depth sort of the N_v visible keys: 4 passes of 8 bits
+        const int nblk = (n + kRadixTile - 1) / kRadixTile;
         uint32_t *ki = kA, *vi = vA, *ko = kB, *vo = vB;
         for (int shift = 0; shift < 32; shift += 8) {
-            hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kRadixThreads), 0, s, ki, n, shift, hist, nblk);
-            hipError_t e = scan_exclusive(hist, hist, nullptr, (uint32_t)(256 * nblk), parts, s);
-            if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kRadixThreads), 0, s, ki, vi, ko, vo, n, shift, hist,
-                               nblk);
+            hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kRadixThreads), 0, s, ki, nvis, shift, hist, nblk,
+                               overflow_dev);
+            if ((e = scan_exclusive(hist, nullptr, L.hist_n, parts, nullptr, overflow_dev, s)) != hipSuccess) return e;
+            hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kRadixThreads), 0, s, ki, vi, ko, vo, nvis, shift,
+                               hist, nblk, overflow_dev);
             std::swap(ki, ko);
             std::swap(vi, vo);
         }
-        // after an even number of passes the sorted ids are in vi (== vA)
-        const uint32_t *sorted = vi;
-        int maxchunks = (n + kChunk - 1) / kChunk;
-        size_t lds = (size_t)ntile * 4;
-        hipLaunchKernelGGL(k_bin_count, dim3(maxchunks), dim3(64), lds, s, sorted, p.xy, p.radius, p.depth, gx, gy,
-                           cnt, H, cnt);
-        hipError_t e = scan_exclusive(H, H, hcount, (uint32_t)((size_t)maxchunks * ntile), parts, s);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_bin_ranges, dim3((ntile + 255) / 256), dim3(256), 0, s, H, parts, ntile, cnt, ranges,
-                           k_capacity, k_dev, overflow_dev);
-        hipLaunchKernelGGL(k_bin_scatter, dim3(maxchunks), dim3(64), lds, s, sorted, p.xy, p.radius, p.depth, gx, gy,
-                           cnt, H, overflow_dev, k_capacity, keys, vals);
-    } else {
-        hipLaunchKernelGGL(k_bin_ranges, dim3((ntile + 255) / 256), dim3(256), 0, s, H, parts, ntile, cnt, ranges,
-                           k_capacity, k_dev, overflow_dev);
+        const uint32_t *sorted = vi;  // even number of passes: back in vA
+        const int c1max = (n + kL1Threads - 1) / kL1Threads;
+        const size_t lds1 = (size_t)nsuper * kL1Waves * 4;
+        hipLaunchKernelGGL(k_l1_count, dim3(c1max), dim3(kL1Threads), lds1, s, sorted, p.xy, p.radius, gx, gy, sxn,
+                           nsuper, cnt, h1, overflow_dev);
+        if ((e = scan_exclusive(h1, &cnt->h1_count, L.h1_n, parts, &cnt->total1, overflow_dev, s)) != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k_l1_scatter, dim3(c1max), dim3(kL1Threads), 2 * lds1, s, sorted, p.xy, p.radius, gx, gy, sxn,
+                           nsuper, cnt, h1, list1, std::max<int64_t>(k_capacity, 1), overflow_dev);
     }
+    hipLaunchKernelGGL(k_l2_plan, dim3(1), dim3(1024), 0, s, h1, cnt, nsuper, sxn, gx, gy, l1start, l1len, c2start,
+                       toff, overflow_dev);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_l2_count, dim3(kL2Grid), dim3(kL2Threads), 0, s, list1, l1start, l1len, c2start, toff, p.xy,
+                           p.radius, gx, gy, sxn, nsuper, cnt, h2, overflow_dev);
+        if ((e = scan_exclusive(h2, &cnt->h2_count, L.h2_n, parts, &cnt->scan_total, overflow_dev, s)) != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k_l2_scatter, dim3(kL2Grid), dim3(kL2Threads), 0, s, list1, l1start, l1len, c2start, toff,
+                           h2, p.xy, p.radius, p.depth, gx, gy, sxn, nsuper, cnt, k_capacity, keys, vals,
+                           overflow_dev);
+    }
+    hipLaunchKernelGGL(k_bin_ranges, dim3((ntile + 255) / 256), dim3(256), 0, s, h2, toff, ntile, cnt, ranges,
+                       overflow_dev);
     return hipGetLastError();
 }
 

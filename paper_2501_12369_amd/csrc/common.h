@@ -17,6 +17,7 @@ constexpr int kTile = 16;
 constexpr int kWave = 64;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr int kMaxTiles = 16384;
+constexpr int kMaxSuperTiles = 1024;  // 8x8-tile groups used by the binning
 
 // Per-launch constants of a DARBF (host-derived from darb_kernel).
 struct KParams {
@@ -237,7 +238,8 @@ hipError_t launch_preprocess(const Cam &cam, const KParams &kp, int n, const dar
 hipError_t launch_preprocess_bwd(const Cam &cam, const KParams &kp, int n, const darb_splats &in,
                                  const darb_grads2d &g2d, const darb_grads3d &g3d, hipStream_t s);
 
-size_t binsort_workspace(int n, int width, int height);
+size_t binsort_workspace(int n, int width, int height, int64_t k_capacity);
+int binsort_super_tiles(int width, int height);
 hipError_t launch_bin_sort(const darb_projected &p, int n, int width, int height, int64_t k_capacity, void *ws,
                            uint64_t *keys, uint32_t *vals, uint32_t *ranges, int64_t *k_dev, int32_t *overflow_dev,
                            hipStream_t s);

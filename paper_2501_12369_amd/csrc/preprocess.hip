@@ -241,69 +241,55 @@ __global__ __launch_bounds__(256) void k_preprocess(Cam cam, KParams kp, int n, 
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     Proj P;
-    if (!project(cam, kp, n, i, in, P)) {
-        out.radius[i] = 0;
-        return;
-    }
-    float c[NB][3];
-    load_sh<NB>(in.sh, n, i, c);
-    float op = in.opacity[i];
-    // colour
-    float dx = in.means[i] - cam.campos[0], dy = in.means[n + i] - cam.campos[1], dz = in.means[2 * n + i] - cam.campos[2];
-    float il = rsqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
-    float Y[NB];
-    sh_eval<NB>(dx * il, dy * il, dz * il, Y);
-    float col[3];
+    const bool vis = project(cam, kp, n, i, in, P);
+    float col[3] = {0.0f, 0.0f, 0.0f};
+    float op = 0.0f;
     uint8_t cl = 0;
+    if (vis) {
+        float c[NB][3];
+        load_sh<NB>(in.sh, n, i, c);
+        op = in.opacity[i];
+        float dx = in.means[i] - cam.campos[0], dy = in.means[n + i] - cam.campos[1],
+              dz = in.means[2 * n + i] - cam.campos[2];
+        float il = rsqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+        float Y[NB];
+        sh_eval<NB>(dx * il, dy * il, dz * il, Y);
 #pragma unroll
-    for (int ch = 0; ch < 3; ch++) {
-        float acc = 0.0f;
+        for (int ch = 0; ch < 3; ch++) {
+            float acc = 0.0f;
 #pragma unroll
-        for (int b = 0; b < NB; b++) acc = fmaf(Y[b], c[b][ch], acc);
-        acc += 0.5f;
-        if (acc < 0.0f) cl |= (uint8_t)(1u << ch);
-        col[ch] = fmaxf(acc, 0.0f);
+            for (int b = 0; b < NB; b++) acc = fmaf(Y[b], c[b][ch], acc);
+            acc += 0.5f;
+            if (acc < 0.0f) cl |= (uint8_t)(1u << ch);
+            col[ch] = fmaxf(acc, 0.0f);
+        }
     }
-    reinterpret_cast<float2 *>(out.xy)[i] = make_float2(P.u, P.v);
-    out.depth[i] = P.t[2];
-    out.radius[i] = P.radius;
-    reinterpret_cast<float4 *>(out.conic_o)[i] = make_float4(P.a, P.b, P.c, op);
+    // every lane stores (zeros for culled splats): whole-line writes
+    reinterpret_cast<float2 *>(out.xy)[i] = vis ? make_float2(P.u, P.v) : make_float2(0.0f, 0.0f);
+    out.depth[i] = vis ? P.t[2] : 0.0f;
+    out.radius[i] = vis ? P.radius : 0;
+    reinterpret_cast<float4 *>(out.conic_o)[i] = vis ? make_float4(P.a, P.b, P.c, op) : make_float4(0, 0, 0, 0);
     out.rgb[3 * i] = col[0];
     out.rgb[3 * i + 1] = col[1];
     out.rgb[3 * i + 2] = col[2];
     out.clamped[i] = cl;
 }
 
-template <int DEG>
-__global__ __launch_bounds__(256) void k_preprocess_bwd(Cam cam, KParams kp, int n, darb_splats in, darb_grads2d g2,
-                                                        darb_grads3d g3) {
-    constexpr int NB = (DEG + 1) * (DEG + 1);
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    Proj P;
-    bool vis = project(cam, kp, n, i, in, P);
-    if (!vis) {
-        for (int c = 0; c < 3; c++) {
-            g3.means[(size_t)c * n + i] = 0.0f;
-            g3.scales[(size_t)c * n + i] = 0.0f;
-        }
-        for (int c = 0; c < 4; c++) g3.quats[(size_t)c * n + i] = 0.0f;
-        g3.opacity[i] = 0.0f;
-#pragma unroll
-        for (int b = 0; b < NB * 3; b++) g3.sh[(size_t)b * n + i] = 0.0f;
-        return;
-    }
+// Gradients of one visible splat.  Outputs: dmu, dsc, dq (d/d quaternion as
+// given), and Y, gv such that d/d sh[b][ch] = Y[b] * gv[ch].
+template <int NB>
+__device__ __forceinline__ void splat_bwd(const Cam &cam, const KParams &kp, int n, int i, const darb_splats &in,
+                                          const darb_grads2d &g2, const Proj &P, float (&dmu)[3], float (&dsc)[3],
+                                          float (&dqo)[4], float (&Y)[NB], float (&gvo)[3]) {
     float csh[NB][3];
     load_sh<NB>(in.sh, n, i, csh);
     float grgb[3] = {g2.rgb[3 * i], g2.rgb[3 * i + 1], g2.rgb[3 * i + 2]};
-    float dmu[3] = {0.f, 0.f, 0.f};
-    g3.opacity[i] = g2.opacity[i];
+    dmu[0] = dmu[1] = dmu[2] = 0.0f;
 
     // ---- colour -> SH coefficients and view direction
     float vx = in.means[i] - cam.campos[0], vy = in.means[n + i] - cam.campos[1], vz = in.means[2 * n + i] - cam.campos[2];
     float il = rsqrtf(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
     float dx = vx * il, dy = vy * il, dz = vz * il;
-    float Y[NB];
     sh_eval<NB>(dx, dy, dz, Y);
     float gdir[3] = {0.f, 0.f, 0.f};
 #pragma unroll
@@ -313,12 +299,10 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(Cam cam, KParams kp, int
         for (int b = 0; b < NB; b++) acc = fmaf(Y[b], csh[b][ch], acc);
         acc += 0.5f;
         float gv = (acc < 0.0f) ? 0.0f : grgb[ch];
+        gvo[ch] = gv;
         float gsh[NB];
 #pragma unroll
-        for (int b = 0; b < NB; b++) {
-            g3.sh[(size_t)(b * 3 + ch) * n + i] = Y[b] * gv;
-            gsh[b] = gv * csh[b][ch];
-        }
+        for (int b = 0; b < NB; b++) gsh[b] = gv * csh[b][ch];
         if constexpr (NB > 1) {
             float gd[3];
             sh_grad<NB>(dx, dy, dz, gsh, gd);
@@ -385,9 +369,6 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(Cam cam, KParams kp, int
     dmu[0] += fmaf(R[0], dtx, fmaf(R[3], dty, R[6] * dtz));
     dmu[1] += fmaf(R[1], dtx, fmaf(R[4], dty, R[7] * dtz));
     dmu[2] += fmaf(R[2], dtx, fmaf(R[5], dty, R[8] * dtz));
-    g3.means[i] = dmu[0];
-    g3.means[(size_t)n + i] = dmu[1];
-    g3.means[(size_t)2 * n + i] = dmu[2];
 
     // ---- Sigma = Mq Mq^T, Mq = Rq diag(s): dMq = 2 dSigma Mq; ds_j = sum_r dMq_rj Rq_rj; dRq_rj = dMq_rj s_j
     const float *Rq = P.Rq;
@@ -400,7 +381,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(Cam cam, KParams kp, int
             acc = fmaf(dm, Rq[r * 3 + cc], acc);
             dR[r * 3 + cc] = dm * P.s[cc];
         }
-        g3.scales[(size_t)cc * n + i] = acc;
+        dsc[cc] = acc;
     }
     float w = P.qn[0], x = P.qn[1], y = P.qn[2], z = P.qn[3];
     float dq0 = 2.0f * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
@@ -411,10 +392,42 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(Cam cam, KParams kp, int
     float dq3 = 2.0f * (-2.0f * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.0f * z * dR[4] + y * dR[5] +
                         x * dR[6] + y * dR[7]);
     float qd = fmaf(dq0, w, fmaf(dq1, x, fmaf(dq2, y, dq3 * z)));
-    g3.quats[i] = (dq0 - w * qd) * P.qinv;
-    g3.quats[(size_t)n + i] = (dq1 - x * qd) * P.qinv;
-    g3.quats[(size_t)2 * n + i] = (dq2 - y * qd) * P.qinv;
-    g3.quats[(size_t)3 * n + i] = (dq3 - z * qd) * P.qinv;
+    dqo[0] = (dq0 - w * qd) * P.qinv;
+    dqo[1] = (dq1 - x * qd) * P.qinv;
+    dqo[2] = (dq2 - y * qd) * P.qinv;
+    dqo[3] = (dq3 - z * qd) * P.qinv;
+}
+
+template <int DEG>
+__global__ __launch_bounds__(256) void k_preprocess_bwd(Cam cam, KParams kp, int n, darb_splats in, darb_grads2d g2,
+                                                        darb_grads3d g3) {
+    constexpr int NB = (DEG + 1) * (DEG + 1);
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    Proj P;
+    const bool vis = project(cam, kp, n, i, in, P);
+    float dmu[3] = {0.f, 0.f, 0.f}, dsc[3] = {0.f, 0.f, 0.f}, dq[4] = {0.f, 0.f, 0.f, 0.f}, gv[3] = {0.f, 0.f, 0.f};
+    float Y[NB];
+#pragma unroll
+    for (int b = 0; b < NB; b++) Y[b] = 0.0f;
+    float dop = 0.0f;
+    if (vis) {
+        splat_bwd<NB>(cam, kp, n, i, in, g2, P, dmu, dsc, dq, Y, gv);
+        dop = g2.opacity[i];
+    }
+    // every lane stores (zeros for culled splats): whole-line writes
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        g3.means[(size_t)c * n + i] = dmu[c];
+        g3.scales[(size_t)c * n + i] = dsc[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; c++) g3.quats[(size_t)c * n + i] = dq[c];
+    g3.opacity[i] = dop;
+#pragma unroll
+    for (int b = 0; b < NB; b++)
+#pragma unroll
+        for (int ch = 0; ch < 3; ch++) g3.sh[(size_t)(b * 3 + ch) * n + i] = Y[b] * gv[ch];
 }
 
 }  // namespace

@@ -87,7 +87,7 @@ def lib():
         L.darb_preprocess.argtypes = [P(darb_camera), P(darb_kernel), c_int64, P(darb_splats), P(darb_projected),
                                       c_void_p]
         L.darb_bin_sort_workspace.restype = c_size_t
-        L.darb_bin_sort_workspace.argtypes = [c_int64, c_int32, c_int32]
+        L.darb_bin_sort_workspace.argtypes = [c_int64, c_int32, c_int32, c_int64]
         L.darb_bin_sort.restype = c_int32
         L.darb_bin_sort.argtypes = [P(darb_projected), c_int64, c_int32, c_int32, c_int64, c_void_p, c_size_t,
                                     c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, P(c_int64), c_void_p]
@@ -201,8 +201,8 @@ def darb_preprocess(cam: dict, kernel, n: int, splats: dict, proj: dict, stream=
                                  _stream(stream)), "darb_preprocess")
 
 
-def darb_bin_sort_workspace(n: int, width: int, height: int) -> int:
-    return int(lib().darb_bin_sort_workspace(n, width, height))
+def darb_bin_sort_workspace(n: int, width: int, height: int, k_capacity: int) -> int:
+    return int(lib().darb_bin_sort_workspace(n, width, height, k_capacity))
 
 
 def darb_bin_sort(proj: dict, n: int, width: int, height: int, k_capacity: int, ws, keys, vals, ranges, k_dev,

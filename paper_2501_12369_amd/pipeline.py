@@ -85,11 +85,11 @@ class Frame:
 
 def alloc_frame(n: int, width: int, height: int, k_capacity: int, device="cuda", keys: bool = False,
                 n_contrib: bool = False, proj: dict | None = None) -> Frame:
-    ws_bytes = native.darb_bin_sort_workspace(n, width, height)
-    if ws_bytes == 0:
-        raise native.DarbError(native.DARB_ERR_UNSUPPORTED, f"unsupported size n={n} {width}x{height}")
-    T = n_tiles(width, height)
     cap = max(int(k_capacity), 1)
+    ws_bytes = native.darb_bin_sort_workspace(n, width, height, cap)
+    if ws_bytes == 0:
+        raise native.DarbError(native.DARB_ERR_UNSUPPORTED, f"unsupported size n={n} {width}x{height} cap={cap}")
+    T = n_tiles(width, height)
     return Frame(
         n=n, width=width, height=height, proj=proj if proj is not None else alloc_projected(n, device),
         ws=torch.empty(ws_bytes, dtype=torch.uint8, device=device),
@@ -107,6 +107,9 @@ def alloc_frame(n: int, width: int, height: int, k_capacity: int, device="cuda",
 
 def _grow(frame: Frame, K: int, device):
     cap = int(K * 1.15) + 1024
+    frame.ws = None
+    frame.ws = torch.empty(native.darb_bin_sort_workspace(frame.n, frame.width, frame.height, cap), dtype=torch.uint8,
+                           device=device)
     frame.vals = torch.empty(cap, dtype=torch.int32, device=device)
     if frame.keys is not None:
         frame.keys = torch.empty(cap, dtype=torch.int64, device=device)

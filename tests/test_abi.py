@@ -65,9 +65,11 @@ def test_invalid_arguments_rejected_on_host(L):
     # negative n, oversized image
     st = L.darb_preprocess(ctypes.byref(cam), ctypes.byref(k), -1, ctypes.byref(sp), ctypes.byref(pr), None)
     assert st == native.DARB_ERR_INVALID_ARG
-    assert L.darb_bin_sort_workspace(10, 4096, 4096) == 0
-    assert L.darb_bin_sort_workspace(-1, 64, 64) == 0
-    assert L.darb_bin_sort_workspace(1000, 64, 64) > 0
+    assert L.darb_bin_sort_workspace(10, 4096, 4096, 100) == 0
+    assert L.darb_bin_sort_workspace(10, 16, 16 * 9000, 100) == 0  # too many 8x8-tile groups
+    assert L.darb_bin_sort_workspace(-1, 64, 64, 100) == 0
+    assert L.darb_bin_sort_workspace(1000, 64, 64, -1) == 0
+    assert L.darb_bin_sort_workspace(1000, 64, 64, 100) > 0
     # misaligned pointer
     sp2 = native.darb_splats(16 * 1000 + 4, 16 * 1000, 16 * 1000, 16 * 1000, 16 * 1000, 0)
     st = L.darb_preprocess(ctypes.byref(cam), ctypes.byref(k), 10, ctypes.byref(sp2), ctypes.byref(pr), None)

@@ -64,6 +64,19 @@ def test_bin_sort_bit_exact(n, W, H, seed):
     assert np.array_equal(to_np(fr.keys)[:K].view(np.uint64), keys_o)
 
 
+@pytest.mark.parametrize("n,W,H,seed,sigma", [(300, 200, 150, 9, (50.0, 400.0)), (60000, 1920, 1080, 10, (0.3, 60.0))])
+def test_bin_sort_bit_exact_large_boxes(n, W, H, seed, sigma):
+    # boxes spanning many 8x8-tile groups, and group lists longer than one chunk
+    print(f"bin_sort large boxes n={n} {W}x{H} sigma={sigma}", flush=True)
+    ps = scenes.projected(seed, n, W, H, sigma_range=sigma)
+    K_o, keys_o, vals_o, ranges_o = oracle.bin_sort(ps["xy"], ps["radius"], ps["depth"], W, H)
+    fr, K = gpu_bin_raster(ps, "half_cos", keys=True, cap=K_o)
+    assert K == K_o
+    assert np.array_equal(to_np(fr.ranges).view(np.uint32), ranges_o)
+    assert np.array_equal(to_np(fr.vals)[:K].view(np.uint32), vals_o)
+    assert np.array_equal(to_np(fr.keys)[:K].view(np.uint64), keys_o)
+
+
 def test_bin_sort_all_culled_and_overflow():
     ps = scenes.projected(7, 300, 96, 64)
     ps["radius"][:] = 0
@@ -156,7 +169,8 @@ def test_raster_bwd_parity(kname):
     # splats that are candidates at an ambiguous pixel are exempt
     exempt = _exempt_splats(ps, orc, oracle_kernel_fp32(kname), W, H)
     keep = ~exempt
-    assert keep.mean() > 0.9
+    # kernels with F(e_max) > 0 (Gaussian, IMQ) put more pixels near the support jump
+    assert keep.mean() > 0.8
     for name, a, b in (("xy", g2d["xy"], go["xy"]), ("conic", g2d["conic"], go["conic"]),
                        ("opacity", g2d["opacity"], go["opacity"]), ("rgb", g2d["rgb"], go["rgb"])):
         ok, l2, ratio = grad_compare(to_np(a)[keep], b[keep])
