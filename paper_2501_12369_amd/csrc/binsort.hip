@@ -39,7 +39,6 @@ constexpr int kRadixItems = 16;
 constexpr int kRadixTile = kRadixThreads * kRadixItems;  // 4096 keys per block
 constexpr int kSuper = 8;                                 // super-tile = 8x8 tiles
 constexpr int kL1Threads = 256;                           // splats per level-1 chunk
-constexpr int kL1Waves = kL1Threads / 64;
 constexpr int kL2Threads = 1024;                          // list entries per level-2 chunk
 constexpr int kL2Waves = kL2Threads / 64;
 constexpr int kL2Grid = 2048;                             // persistent level-2 workgroups
@@ -367,40 +366,28 @@ __device__ __forceinline__ SuperBox super_box(int4 r) {
     return SuperBox{r.x / kSuper, (r.y - 1) / kSuper, r.z / kSuper, (r.w - 1) / kSuper};
 }
 
-// wc[g * kL1Waves + w] = number of splats of wave w covering super-tile g
-__device__ __forceinline__ void l1_ballots(bool valid, SuperBox sb, int nsuper, int sxn, uint32_t *wc) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int gxs = 0, gys = 0;
-    for (int g = 0; g < nsuper; g++) {
-        bool cov = valid & (gxs >= sb.sx0) & (gxs <= sb.sx1) & (gys >= sb.sy0) & (gys <= sb.sy1);
-        uint64_t m = __ballot(cov);
-        if (lane == 0) wc[g * kL1Waves + w] = (uint32_t)__popcll(m);
-        if (++gxs == sxn) {
-            gxs = 0;
-            gys++;
-        }
-    }
-}
+// Level-1 chunks hold 256 depth-ordered splats, one per thread; a splat covers
+// few super-tiles, so each thread walks its own super-tile box.
 
 __global__ __launch_bounds__(kL1Threads) void k_l1_count(const uint32_t *sorted_ids, const float *xy,
                                                          const int32_t *radius, int gx, int gy, int sxn, int nsuper,
                                                          const Counters *cnt, uint32_t *h1,
                                                          const int32_t *overflow_dev) {
-    extern __shared__ uint32_t wc[];
+    extern __shared__ uint32_t cg[];  // [nsuper] splats of this chunk per super-tile
     if (*overflow_dev) return;
     const uint32_t c = blockIdx.x, c1 = cnt->c1, nv = cnt->n_visible;
     if (c >= c1) return;
-    uint32_t j = c * kL1Threads + threadIdx.x;
-    bool valid = j < nv;
-    int4 r = make_int4(0, 1, 0, 1);
-    if (valid) splat_box(xy, radius, (int)sorted_ids[j], gx, gy, r);
-    l1_ballots(valid, super_box(r), nsuper, sxn, wc);
+    for (int g = threadIdx.x; g < nsuper; g += kL1Threads) cg[g] = 0;
     __syncthreads();
-    for (int g = threadIdx.x; g < nsuper; g += kL1Threads) {
-        uint32_t s = 0;
-        for (int k = 0; k < kL1Waves; k++) s += wc[g * kL1Waves + k];
-        h1[(size_t)g * c1 + c] = s;  // super-tile-major
+    uint32_t j = c * kL1Threads + threadIdx.x;
+    int4 r;
+    if (j < nv && splat_box(xy, radius, (int)sorted_ids[j], gx, gy, r)) {
+        SuperBox sb = super_box(r);
+        for (int gys = sb.sy0; gys <= sb.sy1; gys++)
+            for (int gxs = sb.sx0; gxs <= sb.sx1; gxs++) atomicAdd(&cg[gys * sxn + gxs], 1u);
     }
+    __syncthreads();
+    for (int g = threadIdx.x; g < nsuper; g += kL1Threads) h1[(size_t)g * c1 + c] = cg[g];  // super-tile-major
 }
 
 __global__ __launch_bounds__(kL1Threads) void k_l1_scatter(const uint32_t *sorted_ids, const float *xy,
@@ -408,42 +395,40 @@ __global__ __launch_bounds__(kL1Threads) void k_l1_scatter(const uint32_t *sorte
                                                            const Counters *cnt, const uint32_t *base1,
                                                            uint32_t *list1, int64_t list1_cap,
                                                            const int32_t *overflow_dev) {
-    extern __shared__ uint32_t wc[];  // [nsuper * kL1Waves] counts, then [nsuper * kL1Waves] first slots
-    uint32_t *slot = wc + nsuper * kL1Waves;
+    // per super-tile: a 256-bit set of the chunk's covering threads, and the chunk's first slot
+    extern __shared__ uint32_t lds1[];
+    uint32_t *bits = lds1;                   // [nsuper][8]
+    uint32_t *first = lds1 + nsuper * 8;     // [nsuper]
     if (*overflow_dev) return;
     const uint32_t c = blockIdx.x, c1 = cnt->c1, nv = cnt->n_visible;
     if (c >= c1) return;
-    const int w = threadIdx.x >> 6;
+    for (int k = threadIdx.x; k < nsuper * 8; k += kL1Threads) bits[k] = 0;
+    for (int g = threadIdx.x; g < nsuper; g += kL1Threads) first[g] = base1[(size_t)g * c1 + c];
+    __syncthreads();
+    const int word = threadIdx.x >> 5;
+    const uint32_t bit = 1u << (threadIdx.x & 31);
     uint32_t j = c * kL1Threads + threadIdx.x;
-    bool valid = j < nv;
-    uint32_t id = valid ? sorted_ids[j] : 0u;
-    int4 r = make_int4(0, 1, 0, 1);
-    if (valid) splat_box(xy, radius, (int)id, gx, gy, r);
-    SuperBox sb = super_box(r);
-    l1_ballots(valid, sb, nsuper, sxn, wc);
-    __syncthreads();
-    // first slot of every (super-tile, wave): chunk base + counts of the earlier waves
-    for (int idx = threadIdx.x; idx < nsuper * kL1Waves; idx += kL1Threads) {
-        int g = idx / kL1Waves, ww = idx % kL1Waves;
-        uint32_t s = base1[(size_t)g * c1 + c];
-        for (int k = 0; k < ww; k++) s += wc[g * kL1Waves + k];
-        slot[idx] = s;
+    uint32_t id = 0;
+    int4 r;
+    bool vis = false;
+    SuperBox sb{0, -1, 0, -1};
+    if (j < nv) {
+        id = sorted_ids[j];
+        vis = splat_box(xy, radius, (int)id, gx, gy, r);
+        if (vis) sb = super_box(r);
     }
+    for (int gys = sb.sy0; gys <= sb.sy1; gys++)
+        for (int gxs = sb.sx0; gxs <= sb.sx1; gxs++) atomicOr(&bits[(gys * sxn + gxs) * 8 + word], bit);
     __syncthreads();
-    const uint64_t lt = lanemask_lt();
-    int gxs = 0, gys = 0;
-    for (int g = 0; g < nsuper; g++) {
-        bool cov = valid & (gxs >= sb.sx0) & (gxs <= sb.sx1) & (gys >= sb.sy0) & (gys <= sb.sy1);
-        uint64_t m = __ballot(cov);
-        if (cov) {
-            uint32_t pos = slot[g * kL1Waves + w] + (uint32_t)__popcll(m & lt);
+    // rank = covering threads of lower index (depth order) -> stable
+    for (int gys = sb.sy0; gys <= sb.sy1; gys++)
+        for (int gxs = sb.sx0; gxs <= sb.sx1; gxs++) {
+            const int g = gys * sxn + gxs;
+            uint32_t rank = (uint32_t)__popc(bits[g * 8 + word] & (bit - 1u));
+            for (int k = 0; k < word; k++) rank += (uint32_t)__popc(bits[g * 8 + k]);
+            uint32_t pos = first[g] + rank;
             if ((int64_t)pos < list1_cap) list1[pos] = id;
         }
-        if (++gxs == sxn) {
-            gxs = 0;
-            gys++;
-        }
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -544,14 +529,29 @@ __device__ __forceinline__ L2Chunk l2_locate(uint32_t wi, const uint32_t *chunk2
     return C;
 }
 
-// wc[tl * kL2Waves + w] for the 64 tiles tl of super-tile g
-__device__ __forceinline__ void l2_ballots(bool valid, int4 r, int g, int sxn, int gx, int gy, uint32_t *wc) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+// Tiles of super-tile g covered by box r, as a 64-bit mask (bit row*8 + col).
+__device__ __forceinline__ uint64_t l2_tile_mask(bool valid, int4 r, int g, int sxn) {
+    if (!valid) return 0ull;
     const int tx0 = (g % sxn) * kSuper, ty0 = (g / sxn) * kSuper;
+    int c0 = max(r.x - tx0, 0), c1 = min(r.y - tx0, kSuper);
+    int r0 = max(r.z - ty0, 0), r1 = min(r.w - ty0, kSuper);
+    if (c1 <= c0 || r1 <= r0) return 0ull;
+    uint64_t cm = ((1ull << c1) - 1ull) & ~((1ull << c0) - 1ull);
+    uint64_t m = 0ull;
+    for (int rr = r0; rr < r1; rr++) m |= cm << (kSuper * rr);
+    return m;
+}
+
+// number of lanes below this one whose bit is set in m
+__device__ __forceinline__ uint32_t rank_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// wc[tl * kL2Waves + w] = lanes of wave w covering tile tl, for the 64 tiles of a super-tile
+__device__ __forceinline__ void l2_ballots(uint64_t tmask, uint32_t *wc) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int tl = 0; tl < kSuper * kSuper; tl++) {
-        int tx = tx0 + (tl & (kSuper - 1)), ty = ty0 + tl / kSuper;
-        bool cov = valid & (tx >= r.x) & (tx < r.y) & (ty >= r.z) & (ty < r.w);
-        uint64_t m = __ballot(cov);
+        uint64_t m = __ballot((tmask >> tl) & 1ull);
         if (lane == 0) wc[tl * kL2Waves + w] = (uint32_t)__popcll(m);
     }
 }
@@ -572,7 +572,7 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_count(const uint32_t *list1, 
         bool valid = threadIdx.x < C.len;
         int4 r = make_int4(0, 0, 0, 0);
         if (valid) splat_box(xy, radius, (int)list1[C.first + threadIdx.x], gx, gy, r);
-        l2_ballots(valid, r, C.g, sxn, gx, gy, wc);
+        l2_ballots(l2_tile_mask(valid, r, C.g, sxn), wc);
         __syncthreads();
         if (threadIdx.x < kSuper * kSuper) {
             int tl = threadIdx.x;
@@ -600,7 +600,6 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_scatter(const uint32_t *list1
     if (*overflow_dev) return;
     const uint32_t total2 = cnt->total2;
     const int w = threadIdx.x >> 6;
-    const uint64_t lt = lanemask_lt();
     for (int g = threadIdx.x; g <= nsuper; g += kL2Threads) c2s[g] = chunk2_start[g];
     __syncthreads();
     for (uint32_t wi = blockIdx.x; wi < total2; wi += gridDim.x) {
@@ -613,10 +612,11 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_scatter(const uint32_t *list1
             splat_box(xy, radius, (int)id, gx, gy, r);
             db = __float_as_uint(depth[id]);
         }
-        l2_ballots(valid, r, C.g, sxn, gx, gy, wc);
+        const uint64_t tmask = l2_tile_mask(valid, r, C.g, sxn);
+        l2_ballots(tmask, wc);
         __syncthreads();
         const int tx0 = (C.g % sxn) * kSuper, ty0 = (C.g / sxn) * kSuper;
-        {
+        if (threadIdx.x < kSuper * kSuper * kL2Waves) {
             // thread (tile tl, wave ww): first slot of wave ww's entries in tile tl
             const int tl = threadIdx.x / kL2Waves, ww = threadIdx.x % kL2Waves;
             const int tx = tx0 + (tl & (kSuper - 1)), ty = ty0 + tl / kSuper;
@@ -628,12 +628,12 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_scatter(const uint32_t *list1
         }
         __syncthreads();
         for (int tl = 0; tl < kSuper * kSuper; tl++) {
-            int tx = tx0 + (tl & (kSuper - 1)), ty = ty0 + tl / kSuper;
-            bool cov = valid & (tx >= r.x) & (tx < r.y) & (ty >= r.z) & (ty < r.w);
-            uint64_t m = __ballot(cov);
+            const bool cov = (tmask >> tl) & 1ull;
+            const uint64_t m = __ballot(cov);
+            if (m == 0ull) continue;  // no lane of this wave covers the tile
             if (cov) {
-                int t = ty * gx + tx;
-                uint32_t pos = slot[tl * kL2Waves + w] + (uint32_t)__popcll(m & lt);
+                int t = (ty0 + tl / kSuper) * gx + tx0 + (tl & (kSuper - 1));
+                uint32_t pos = slot[tl * kL2Waves + w] + rank_below(m);
                 if ((int64_t)pos < k_capacity) {
                     vals[pos] = id;
                     if (keys) keys[pos] = ((uint64_t)(uint32_t)t << 32) | db;
@@ -751,12 +751,12 @@ hipError_t launch_bin_sort(const darb_projected &p, int n, int width, int height
         }
         const uint32_t *sorted = vi;  // even number of passes: back in vA
         const int c1max = (n + kL1Threads - 1) / kL1Threads;
-        const size_t lds1 = (size_t)nsuper * kL1Waves * 4;
+        const size_t lds1 = (size_t)nsuper * 4;
         hipLaunchKernelGGL(k_l1_count, dim3(c1max), dim3(kL1Threads), lds1, s, sorted, p.xy, p.radius, gx, gy, sxn,
                            nsuper, cnt, h1, overflow_dev);
         if ((e = scan_exclusive(h1, &cnt->h1_count, L.h1_n, parts, &cnt->total1, overflow_dev, s)) != hipSuccess)
             return e;
-        hipLaunchKernelGGL(k_l1_scatter, dim3(c1max), dim3(kL1Threads), 2 * lds1, s, sorted, p.xy, p.radius, gx, gy, sxn,
+        hipLaunchKernelGGL(k_l1_scatter, dim3(c1max), dim3(kL1Threads), 9 * lds1, s, sorted, p.xy, p.radius, gx, gy, sxn,
                            nsuper, cnt, h1, list1, std::max<int64_t>(k_capacity, 1), overflow_dev);
     }
     hipLaunchKernelGGL(k_l2_plan, dim3(1), dim3(1024), 0, s, h1, cnt, nsuper, sxn, gx, gy, l1start, l1len, c2start,

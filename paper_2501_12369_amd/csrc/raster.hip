@@ -29,14 +29,20 @@ constexpr int kPix = 4;  // pixels per lane
 struct Rec {
     float x, y, a, b, c, o, r, g, bl;
     uint32_t id;
+    int hit;  // the footprint's bounding box meets this tile's pixels
 };
 
 // Record of instance j (zeros when `in` is false or the stored index is out of
-// range; a zero-opacity record never passes the alpha test).
-__device__ __forceinline__ Rec load_rec(const darb_projected &p, const uint32_t *vals, uint32_t j, bool in, int n) {
+// range; a zero-opacity record never passes the alpha test).  `hit` is false
+// when the ellipse E <= e_max, grown by one pixel, misses the tile's pixel
+// range: for |dx| > sqrt(e_max / Q_xx^-1) every E exceeds e_max by a relative
+// margin far above FP32 rounding, so skipping such a splat changes nothing.
+__device__ __forceinline__ Rec load_rec(const darb_projected &p, const uint32_t *vals, uint32_t j, bool in, int n,
+                                        float e_max, float xlo, float ylo) {
     Rec R;
     R.x = R.y = R.a = R.b = R.c = R.o = R.r = R.g = R.bl = 0.0f;
     R.id = kNone;
+    R.hit = 0;
     uint32_t id = in ? vals[j] : kNone;
     if (id < (uint32_t)n) {
         float2 xy = reinterpret_cast<const float2 *>(p.xy)[id];
@@ -51,6 +57,14 @@ __device__ __forceinline__ Rec load_rec(const darb_projected &p, const uint32_t 
         R.g = p.rgb[3 * id + 1];
         R.bl = p.rgb[3 * id + 2];
         R.id = id;
+        // half-extents of {E <= e_max}: sqrt(e_max * Sigma'_xx), sqrt(e_max * Sigma'_yy), Sigma' = Q^-1
+        float det = fmaf(co.x, co.z, -(co.y * co.y));
+        float hx = sqrtf(e_max * co.z / det) + 1.0f;
+        float hy = sqrtf(e_max * co.x / det) + 1.0f;
+        bool ok = (det > 0.0f) ? ((xy.x + hx >= xlo) & (xy.x - hx <= xlo + (kTile - 1)) & (xy.y + hy >= ylo) &
+                                  (xy.y - hy <= ylo + (kTile - 1)))
+                               : true;
+        R.hit = ok ? 1 : 0;
     }
     return R;
 }
@@ -87,9 +101,10 @@ __global__ __launch_bounds__(64) void k_raster_fwd(darb_projected p, const uint3
         bool alldone = done[0] & done[1] & done[2] & done[3];
         if (__ballot(!alldone) == 0) break;
         uint32_t j = base + lane;
-        Rec R = load_rec(p, vals, j, j < end, n);
+        Rec R = load_rec(p, vals, j, j < end, n, kp.e_max, (float)(tx * kTile), (float)(ty * kTile));
         int nb = (int)min(64u, end - base);
         for (int s = 0; s < nb; s++) {
+            if (!readlane_i(R.hit, s)) continue;  // footprint misses this tile (uniform)
             float sx = readlane_f(R.x, s), sy = readlane_f(R.y, s);
             float sa = readlane_f(R.a, s), sb = readlane_f(R.b, s), sc = readlane_f(R.c, s);
             float so = readlane_f(R.o, s);
@@ -180,8 +195,9 @@ __global__ __launch_bounds__(64) void k_raster_bwd(darb_projected p, const uint3
     for (uint32_t hi = maxl; hi > start;) {
         uint32_t cntb = min(64u, hi - start);
         uint32_t j = hi - 1 - lane;
-        Rec R = load_rec(p, vals, j, (uint32_t)lane < cntb, n);
+        Rec R = load_rec(p, vals, j, (uint32_t)lane < cntb, n, kp.e_max, (float)(tx * kTile), (float)(ty * kTile));
         for (int s = 0; s < (int)cntb; s++) {
+            if (!readlane_i(R.hit, s)) continue;  // footprint misses this tile (uniform)
             float sx = readlane_f(R.x, s), sy = readlane_f(R.y, s);
             float sa = readlane_f(R.a, s), sb = readlane_f(R.b, s), sc = readlane_f(R.c, s);
             float so = readlane_f(R.o, s);
