@@ -173,6 +173,17 @@ DARB_API darb_status darb_preprocess(const darb_camera *cam, const darb_kernel *
                             const darb_projected *out, void *stream);
 
 /*
+ * darb_preprocess_cam_dev -- darb_preprocess with the camera read from DEVICE
+ * memory (one darb_camera at cam_dev), so that a captured graph of the render
+ * can be replayed for a new pose after the caller rewrites that buffer.
+ * width/height size the tile grid (use the camera's).  The camera values are
+ * not validated on the host: non-positive fx, fy or near_z cull every splat.
+ */
+DARB_API darb_status darb_preprocess_cam_dev(const darb_camera *cam_dev, int32_t width, int32_t height,
+                                             const darb_kernel *kernel, int64_t n, const darb_splats *in,
+                                             const darb_projected *out, void *stream);
+
+/*
  * darb_bin_sort_workspace -- bytes of device workspace darb_bin_sort needs for
  * n splats, a width x height image and an instance capacity k_capacity (the
  * workspace holds an intermediate list bounded by the instance count).

@@ -187,7 +187,26 @@ darb_status darb_preprocess(const darb_camera *cam, const darb_kernel *kernel, i
     TRY(check_splats(in, n));
     TRY(check_projected(out, n, true));
     g_err[0] = 0;
-    return hip_status(darb::launch_preprocess(c, kp, (int)n, *in, *out, (hipStream_t)stream), "darb_preprocess");
+    return hip_status(darb::launch_preprocess(c, nullptr, kp, (int)n, *in, *out, (hipStream_t)stream),
+                      "darb_preprocess");
+}
+
+darb_status darb_preprocess_cam_dev(const darb_camera *cam_dev, int32_t width, int32_t height,
+                                    const darb_kernel *kernel, int64_t n, const darb_splats *in,
+                                    const darb_projected *out, void *stream) {
+    darb::KParams kp;
+    TRY(check_n(n));
+    REQUIRE_PTR(cam_dev);
+    TRY(check_kernel(kernel, &kp));
+    TRY(check_size(width, height));
+    TRY(check_splats(in, n));
+    TRY(check_projected(out, n, true));
+    darb::Cam c{};
+    c.width = width;
+    c.height = height;
+    g_err[0] = 0;
+    return hip_status(darb::launch_preprocess(c, cam_dev, kp, (int)n, *in, *out, (hipStream_t)stream),
+                      "darb_preprocess_cam_dev");
 }
 
 size_t darb_bin_sort_workspace(int64_t n, int32_t width, int32_t height, int64_t k_capacity) {

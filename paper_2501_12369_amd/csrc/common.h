@@ -233,8 +233,10 @@ struct Cam {
     float dilation;
 };
 
-hipError_t launch_preprocess(const Cam &cam, const KParams &kp, int n, const darb_splats &in,
-                             const darb_projected &out, hipStream_t s);
+// cam_dev (nullable): camera read from device memory instead of `cam`
+// (whose width/height still size the tile grid)
+hipError_t launch_preprocess(const Cam &cam, const darb_camera *cam_dev, const KParams &kp, int n,
+                             const darb_splats &in, const darb_projected &out, hipStream_t s);
 hipError_t launch_preprocess_bwd(const Cam &cam, const KParams &kp, int n, const darb_splats &in,
                                  const darb_grads2d &g2d, const darb_grads3d &g3d, hipStream_t s);
 

@@ -235,11 +235,41 @@ __device__ __forceinline__ void load_sh(const float *sh, int n, int i, float (&c
         for (int ch = 0; ch < 3; ch++) c[b][ch] = sh[(size_t)(b * 3 + ch) * n + i];
 }
 
+// Camera constants from a darb_camera in device memory (same derivation as the
+// host path); the tile grid keeps the caller's width/height.  A camera with
+// non-positive focal lengths or near plane culls every splat.
+__device__ __forceinline__ Cam cam_from_device(const darb_camera *c, int width, int height) {
+    Cam m;
+    for (int r = 0; r < 3; r++) {
+        for (int k = 0; k < 3; k++) m.R[r * 3 + k] = c->viewmat[r * 4 + k];
+        m.t[r] = c->viewmat[r * 4 + 3];
+        m.campos[r] = c->campos[r];
+    }
+    m.fx = c->fx;
+    m.fy = c->fy;
+    m.cx = c->cx;
+    m.cy = c->cy;
+    m.width = width;
+    m.height = height;
+    m.near_z = c->near_z;
+    if (!(m.fx > 0.0f) || !(m.fy > 0.0f) || !(m.near_z > 0.0f)) m.near_z = INFINITY;
+    if (c->jac_clamp > 0.0f && m.near_z < INFINITY) {
+        m.lim_x = c->jac_clamp * (0.5f * (float)width) / m.fx;
+        m.lim_y = c->jac_clamp * (0.5f * (float)height) / m.fy;
+    } else {
+        m.lim_x = m.lim_y = 0.0f;
+    }
+    m.dilation = fmaxf(c->dilation, 0.0f);
+    return m;
+}
+
 template <int DEG>
-__global__ __launch_bounds__(256) void k_preprocess(Cam cam, KParams kp, int n, darb_splats in, darb_projected out) {
+__global__ __launch_bounds__(256) void k_preprocess(Cam cam_arg, const darb_camera *cam_dev, KParams kp, int n,
+                                                    darb_splats in, darb_projected out) {
     constexpr int NB = (DEG + 1) * (DEG + 1);
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const Cam cam = cam_dev ? cam_from_device(cam_dev, cam_arg.width, cam_arg.height) : cam_arg;
     Proj P;
     const bool vis = project(cam, kp, n, i, in, P);
     float col[3] = {0.0f, 0.0f, 0.0f};
@@ -432,15 +462,15 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(Cam cam, KParams kp, int
 
 }  // namespace
 
-hipError_t launch_preprocess(const Cam &cam, const KParams &kp, int n, const darb_splats &in,
-                             const darb_projected &out, hipStream_t s) {
+hipError_t launch_preprocess(const Cam &cam, const darb_camera *cam_dev, const KParams &kp, int n,
+                             const darb_splats &in, const darb_projected &out, hipStream_t s) {
     if (n == 0) return hipSuccess;
     dim3 grid((n + 255) / 256);
     switch (in.sh_degree) {
-    case 0: hipLaunchKernelGGL(k_preprocess<0>, grid, dim3(256), 0, s, cam, kp, n, in, out); break;
-    case 1: hipLaunchKernelGGL(k_preprocess<1>, grid, dim3(256), 0, s, cam, kp, n, in, out); break;
-    case 2: hipLaunchKernelGGL(k_preprocess<2>, grid, dim3(256), 0, s, cam, kp, n, in, out); break;
-    default: hipLaunchKernelGGL(k_preprocess<3>, grid, dim3(256), 0, s, cam, kp, n, in, out); break;
+    case 0: hipLaunchKernelGGL(k_preprocess<0>, grid, dim3(256), 0, s, cam, cam_dev, kp, n, in, out); break;
+    case 1: hipLaunchKernelGGL(k_preprocess<1>, grid, dim3(256), 0, s, cam, cam_dev, kp, n, in, out); break;
+    case 2: hipLaunchKernelGGL(k_preprocess<2>, grid, dim3(256), 0, s, cam, cam_dev, kp, n, in, out); break;
+    default: hipLaunchKernelGGL(k_preprocess<3>, grid, dim3(256), 0, s, cam, cam_dev, kp, n, in, out); break;
     }
     return hipGetLastError();
 }

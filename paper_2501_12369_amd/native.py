@@ -20,8 +20,8 @@ c_float, c_int32, c_int64, c_void_p, c_size_t = (ctypes.c_float, ctypes.c_int32,
 DARB_OK, DARB_ERR_INVALID_ARG, DARB_ERR_CAPACITY, DARB_ERR_HIP, DARB_ERR_UNSUPPORTED = range(5)
 GAUSS, HALF_COS, RAISED_COS, SINC, IMQ, IMQ_SQRT, PARABOLA = range(7)
 
-EXPORTED = ("darb_version", "darb_status_string", "darb_last_error", "darb_preprocess", "darb_bin_sort_workspace",
-            "darb_bin_sort", "darb_raster_fwd", "darb_raster_bwd", "darb_preprocess_bwd")
+EXPORTED = ("darb_version", "darb_status_string", "darb_last_error", "darb_preprocess", "darb_preprocess_cam_dev",
+            "darb_bin_sort_workspace", "darb_bin_sort", "darb_raster_fwd", "darb_raster_bwd", "darb_preprocess_bwd")
 
 
 class DarbError(RuntimeError):
@@ -86,6 +86,9 @@ def lib():
         L.darb_preprocess.restype = c_int32
         L.darb_preprocess.argtypes = [P(darb_camera), P(darb_kernel), c_int64, P(darb_splats), P(darb_projected),
                                       c_void_p]
+        L.darb_preprocess_cam_dev.restype = c_int32
+        L.darb_preprocess_cam_dev.argtypes = [c_void_p, c_int32, c_int32, P(darb_kernel), c_int64, P(darb_splats),
+                                              P(darb_projected), c_void_p]
         L.darb_bin_sort_workspace.restype = c_size_t
         L.darb_bin_sort_workspace.argtypes = [c_int64, c_int32, c_int32, c_int64]
         L.darb_bin_sort.restype = c_int32
@@ -199,6 +202,24 @@ def darb_preprocess(cam: dict, kernel, n: int, splats: dict, proj: dict, stream=
     c, k, s, p = camera_struct(cam), kernel_struct(kernel), splats_struct(splats), projected_struct(proj)
     _check(lib().darb_preprocess(ctypes.byref(c), ctypes.byref(k), n, ctypes.byref(s), ctypes.byref(p),
                                  _stream(stream)), "darb_preprocess")
+
+
+def camera_bytes(cam: dict) -> bytes:
+    """The darb_camera struct of ``cam`` as raw bytes (for a device camera buffer)."""
+    return bytes(camera_struct(cam))
+
+
+CAMERA_NBYTES = ctypes.sizeof(darb_camera)
+
+
+def darb_preprocess_cam_dev(cam_dev, width: int, height: int, kernel, n: int, splats: dict, proj: dict,
+                            stream=None):
+    """``cam_dev``: a device uint8 tensor of CAMERA_NBYTES holding a darb_camera."""
+    if cam_dev.numel() * cam_dev.element_size() < CAMERA_NBYTES:
+        raise ValueError("camera buffer too small")
+    k, s, p = kernel_struct(kernel), splats_struct(splats), projected_struct(proj)
+    _check(lib().darb_preprocess_cam_dev(_ptr(cam_dev), width, height, ctypes.byref(k), n, ctypes.byref(s),
+                                         ctypes.byref(p), _stream(stream)), "darb_preprocess_cam_dev")
 
 
 def darb_bin_sort_workspace(n: int, width: int, height: int, k_capacity: int) -> int:

@@ -1,0 +1,135 @@
+"""Host-side tests of the serving scheduler (no GPU): admission by memory,
+FIFO order, concurrency, eviction, capacity-overflow retry."""
+import pytest
+
+from paper_2501_12369_amd.serving import Request, Scheduler
+
+
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def sleep(self, dt):
+        self.t += max(dt, 1e-5)
+
+
+class FakeSlot:
+    def __init__(self, key, nbytes, clock, service, overflow_once, log):
+        self.key, self.nbytes, self.clock, self.service = key, nbytes, clock, service
+        self.overflow_once, self.log = overflow_once, log
+        self.t_end = None
+        self.req = None
+        self.freed = False
+
+    def launch(self, req):
+        assert not self.freed
+        self.req = req
+        self.t_end = self.clock.t + self.service
+        self.log.append(("start", req.rid, self.clock.t, self.key))
+
+    def poll(self):
+        return self.clock.t >= self.t_end
+
+    def finish(self):
+        if self.req.rid in self.overflow_once:
+            self.overflow_once.discard(self.req.rid)
+            return False, 999
+        return True, 10
+
+    def rerun(self, req, K):
+        self.nbytes += 1
+        self.log.append(("rerun", req.rid, self.clock.t, self.key))
+
+    def image_copy(self):
+        return None
+
+    def free(self):
+        self.freed = True
+        self.log.append(("free", None, self.clock.t, self.key))
+
+
+def make(budget, max_slots=8, service=0.010, per_key_bytes=None, overflow_once=()):
+    clock = FakeClock()
+    log = []
+    per_key_bytes = per_key_bytes or {}
+    ov = set(overflow_once)
+
+    def need(key):
+        return per_key_bytes.get(key, 100)
+
+    def factory(key, hint):
+        return FakeSlot(key, need(key), clock, service, ov, log)
+
+    return Scheduler(factory, need, budget, max_slots, clock=clock, sleep=clock.sleep), clock, log
+
+
+def req(i, t, scene=0, w=64, h=64):
+    return Request(i, t, scene, dict(width=w, height=h))
+
+
+def test_all_complete_and_fifo_per_key():
+    s, clock, log = make(budget=1000, max_slots=1)
+    rs = [req(i, 0.001 * i) for i in range(10)]
+    results, st = s.run(rs)
+    assert sorted(r.rid for r in results) == list(range(10))
+    starts = [e[1] for e in log if e[0] == "start"]
+    assert starts == list(range(10))
+    assert st.peak_slots == 1 and st.n == 10
+    # one at a time: each request waits for the previous one
+    for a, b in zip(results, results[1:]):
+        assert b.start >= a.end - 1e-9
+
+
+def test_concurrent_admission_overlaps_work():
+    s, clock, log = make(budget=1000, max_slots=4, service=0.010)
+    rs = [req(0, 0.0), req(1, 0.002)]
+    results, st = s.run(rs)
+    r0, r1 = sorted(results, key=lambda r: r.rid)
+    assert r1.start < r0.end  # admitted while the first one is on the GPU
+    assert st.peak_slots == 2
+
+
+def test_memory_budget_is_respected_and_queues():
+    # each slot needs 400 bytes; budget 1000 -> at most 2 slots
+    s, clock, log = make(budget=1000, max_slots=8, per_key_bytes={(0, 64, 64): 400})
+    rs = [req(i, 0.0) for i in range(6)]
+    results, st = s.run(rs)
+    assert st.peak_bytes <= 1000 and st.peak_slots == 2
+    assert len(results) == 6
+
+
+def test_idle_slots_of_other_keys_are_evicted():
+    kb = {(0, 64, 64): 600, (1, 64, 64): 600}
+    s, clock, log = make(budget=1000, max_slots=8, per_key_bytes=kb)
+    rs = [req(0, 0.0, scene=0), req(1, 0.050, scene=1), req(2, 0.100, scene=0)]
+    results, st = s.run(rs)
+    assert len(results) == 3 and st.evictions >= 2
+    # the slot freed before request 1 belongs to scene 0, the one before request 2 to scene 1
+    frees = [e[3] for e in log if e[0] == "free"]
+    assert frees[:2] == [(0, 64, 64), (1, 64, 64)]
+    assert st.peak_bytes <= 1000
+
+
+def test_request_above_budget_is_rejected():
+    s, clock, log = make(budget=100, per_key_bytes={(0, 64, 64): 101})
+    with pytest.raises(MemoryError):
+        s.run([req(0, 0.0)])
+
+
+def test_capacity_overflow_is_rerun():
+    s, clock, log = make(budget=1000, overflow_once={3})
+    results, st = s.run([req(i, 0.001 * i) for i in range(5)])
+    assert st.retries == 1
+    assert [r.retried for r in sorted(results, key=lambda r: r.rid)] == [False, False, False, True, False]
+    assert any(e[0] == "rerun" and e[1] == 3 for e in log)
+
+
+def test_latency_statistics():
+    s, clock, log = make(budget=1000, max_slots=1, service=0.004)
+    rs = [req(i, 0.005 * i) for i in range(50)]
+    results, st = s.run(rs)
+    assert 3.9 <= st.p50_ms <= 5.0 and st.p99_ms >= st.p50_ms
+    assert st.req_per_s == pytest.approx(50 / st.wall_s)
