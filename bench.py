@@ -80,6 +80,46 @@ def cpu_baseline(sc, kernel_name, rows_every: int, log_fn=log):
                        f"per-pixel time scaled to the full view; measured {t4 - t0:.1f}s")
 
 
+def serving_bench(kernel_name: str, seconds: float, rate_hz: float, mem_budget_gb: float, max_slots: int):
+    """Forward-only serving of Poisson requests over four resident scenes."""
+    import torch
+
+    from paper_2501_12369_amd import pipeline, scenes, serving
+
+    t0 = time.time()
+    sc = [pipeline.splats_to_device(scenes.scene_splats(41 + i, n))
+          for i, n in enumerate(scenes.SERVING_SCENE_SIZES)]
+    log(f"serving scenes generated in {time.time() - t0:.1f}s")
+    kern = pipeline.KERNELS[kernel_name]
+    srv = serving.RenderServer(sc, kern, mem_budget=int(mem_budget_gb * (1 << 30)), max_slots=max_slots)
+    # warm-up: every (scene, resolution) key sized and captured before the measured session
+    warm = []
+    rng = np.random.Generator(np.random.PCG64(1234))
+    for s in range(len(sc)):
+        for (w, h) in scenes.SERVING_RESOLUTIONS:
+            warm.append(serving.Request(len(warm), 0.0, s, scenes.orbit_camera(rng, w, h)))
+    srv.serve(warm)
+    torch.cuda.synchronize()
+    n_req = max(1, int(seconds * rate_hz))
+    reqs = serving.make_requests(77, n_req, rate_hz, len(sc))
+    _, st = srv.serve(reqs)
+    log(f"serving: {st.n} requests at {rate_hz}/s: p50 {st.p50_ms:.2f} ms p99 {st.p99_ms:.2f} ms, "
+        f"{st.mpix_per_s:.1f} Mpix/s, peak slots {st.peak_slots}, peak in flight {st.peak_inflight}, "
+        f"retries {st.retries}")
+    _, seq = serving.sequential_baseline(srv, reqs)
+    log(f"one-at-a-time: p50 {seq.p50_ms:.2f} ms p99 {seq.p99_ms:.2f} ms, {seq.mpix_per_s:.1f} Mpix/s, "
+        f"retries {seq.retries}")
+    return dict(workload=f"4 resident scenes {list(scenes.SERVING_SCENE_SIZES)} splats, Poisson {rate_hz} req/s "
+                         f"for {seconds}s, resolutions {[f'{w}x{h}' for w, h in scenes.SERVING_RESOLUTIONS]}, "
+                         f"forward only, {kernel_name}",
+                p50_ms=round(st.p50_ms, 3), p99_ms=round(st.p99_ms, 3), mean_ms=round(st.mean_ms, 3),
+                mpix_per_s=round(st.mpix_per_s, 2), req_per_s=round(st.req_per_s, 2), requests=st.n,
+                peak_slots=st.peak_slots, peak_inflight=st.peak_inflight, peak_gb=round(st.peak_bytes / 2**30, 2),
+                retries=st.retries,
+                one_at_a_time=dict(p50_ms=round(seq.p50_ms, 3), p99_ms=round(seq.p99_ms, 3),
+                                   mpix_per_s=round(seq.mpix_per_s, 2)))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +129,10 @@ def main():
     ap.add_argument("--n", type=int, default=3_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rows-every", type=int, default=16)
+    ap.add_argument("--serve-seconds", type=float, default=5.0, help="0 disables the serving leg")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-mem-gb", type=float, default=24.0)
+    ap.add_argument("--serve-slots", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (requested --gpus {args.gpus}); "
@@ -197,9 +241,15 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(sc, args.kernel, args.cpu_rows_every)
+    del frame, grads, spd
+    torch.cuda.empty_cache()
+    serving_stats = None
+    if args.serve_seconds > 0:
+        serving_stats = serving_bench(args.kernel, args.serve_seconds, args.serve_rate, args.serve_mem_gb,
+                                      args.serve_slots)
 
     out = {
-        "metric": "fwd+bwd Mpix/s at 3M splats 1297x840",
+        "metric": "fwd+bwd Mpix/s at 3M splats 1297x840; serving p50/p99 render latency",
         "value": round(mpix, 3),
         "unit": "Mpix/s",
         "n_gpus": 1,
@@ -218,6 +268,7 @@ def main():
                    "stage_ms": {k: round(v, 4) for k, v in per_stage.items()}},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "serving": serving_stats,
     }
     print(json.dumps(out), flush=True)
 

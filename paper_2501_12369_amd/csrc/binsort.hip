@@ -547,13 +547,19 @@ __device__ __forceinline__ uint32_t rank_below(uint64_t m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// wc[tl * kL2Waves + w] = lanes of wave w covering tile tl, for the 64 tiles of a super-tile
+static_assert(kSuper * kSuper == 64, "a super-tile has one tile per lane");
+
+// wc[tl * kL2Waves + w] = lanes of wave w covering tile tl, for the 64 tiles of a
+// super-tile: lane tl collects tile tl's count in a register
 __device__ __forceinline__ void l2_ballots(uint64_t tmask, uint32_t *wc) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int tl = 0; tl < kSuper * kSuper; tl++) {
+    uint32_t cnt = 0;
+#pragma unroll 8
+    for (int tl = 0; tl < 64; tl++) {
         uint64_t m = __ballot((tmask >> tl) & 1ull);
-        if (lane == 0) wc[tl * kL2Waves + w] = (uint32_t)__popcll(m);
+        cnt = (lane == tl) ? (uint32_t)__popcll(m) : cnt;
     }
+    wc[lane * kL2Waves + w] = cnt;
 }
 
 __global__ __launch_bounds__(kL2Threads) void k_l2_count(const uint32_t *list1, const uint32_t *l1_start,
@@ -627,14 +633,18 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_scatter(const uint32_t *list1
             }
         }
         __syncthreads();
-        for (int tl = 0; tl < kSuper * kSuper; tl++) {
+        // lane tl holds this wave's first slot in tile tl; broadcast per tile with v_readlane
+        const uint32_t myslot = slot[(threadIdx.x & 63) * kL2Waves + w];
+        const uint32_t cap32 = (uint32_t)min(k_capacity, (int64_t)0xFFFFFFFFll);
+        for (int tl = 0; tl < 64; tl++) {
             const bool cov = (tmask >> tl) & 1ull;
             const uint64_t m = __ballot(cov);
             if (m == 0ull) continue;  // no lane of this wave covers the tile
+            const uint32_t s0 = (uint32_t)__builtin_amdgcn_readlane((int)myslot, tl);
             if (cov) {
                 int t = (ty0 + tl / kSuper) * gx + tx0 + (tl & (kSuper - 1));
-                uint32_t pos = slot[tl * kL2Waves + w] + rank_below(m);
-                if ((int64_t)pos < k_capacity) {
+                uint32_t pos = s0 + rank_below(m);
+                if (pos < cap32) {
                     vals[pos] = id;
                     if (keys) keys[pos] = ((uint64_t)(uint32_t)t << 32) | db;
                 }

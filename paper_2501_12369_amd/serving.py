@@ -75,6 +75,7 @@ class Stats:
     peak_slots: int
     peak_bytes: int
     evictions: int
+    peak_inflight: int = 0
     extra: dict = field(default_factory=dict)
 
     def as_dict(self):
@@ -84,13 +85,13 @@ class Stats:
         return d
 
 
-def summarize(results, wall_s, retries, peak_slots, peak_bytes, evictions) -> Stats:
+def summarize(results, wall_s, retries, peak_slots, peak_bytes, evictions, peak_inflight=0) -> Stats:
     lat = np.array([r.latency for r in results]) * 1e3
     pix = sum(r.pixels for r in results)
     return Stats(n=len(results), p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                  mean_ms=float(lat.mean()), max_ms=float(lat.max()), mpix_per_s=pix / wall_s / 1e6,
                  req_per_s=len(results) / wall_s, wall_s=wall_s, retries=retries, peak_slots=peak_slots,
-                 peak_bytes=peak_bytes, evictions=evictions)
+                 peak_bytes=peak_bytes, evictions=evictions, peak_inflight=peak_inflight)
 
 
 class Scheduler:
@@ -104,11 +105,12 @@ class Scheduler:
     """
 
     def __init__(self, factory, need, mem_budget: int, max_slots: int = 8, clock=time.perf_counter,
-                 sleep=time.sleep):
+                 sleep=time.sleep, max_inflight: int | None = None):
         self.factory = factory
         self.need = need
         self.budget = int(mem_budget)
         self.max_slots = int(max_slots)
+        self.max_inflight = int(max_inflight) if max_inflight is not None else self.max_slots
         self.clock = clock
         self.sleep = sleep
         self.idle = OrderedDict()  # key -> list of idle slots (LRU order of keys)
@@ -162,19 +164,24 @@ class Scheduler:
         pending = deque(sorted(requests, key=lambda r: r.arrival))
         queue = deque()
         results = []
+        # statistics of this run only
+        retries0, evictions0 = self.retries, self.evictions
+        self.peak_slots, self.peak_bytes = self.n_slots, self.mem_used
+        peak_inflight = 0
         t0 = self.clock()
         while pending or queue or self.busy:
             now = self.clock() - t0
             while pending and pending[0].arrival <= now:
                 queue.append(pending.popleft())
             progressed = False
-            while queue:
+            while queue and len(self.busy) < self.max_inflight:
                 s = self.acquire(queue[0])
                 if s is None:
                     break
                 req = queue.popleft()
                 s.launch(req)
                 self.busy.append((s, req, self.clock() - t0))
+                peak_inflight = max(peak_inflight, len(self.busy))
                 progressed = True
             still = []
             for s, req, start in self.busy:
@@ -202,8 +209,8 @@ class Scheduler:
                 else:
                     self.sleep(poll_sleep)
         wall = max(r.end for r in results) - min(r.arrival for r in results) if results else 0.0
-        return results, summarize(results, max(wall, 1e-9), self.retries, self.peak_slots, self.peak_bytes,
-                                  self.evictions)
+        return results, summarize(results, max(wall, 1e-9), self.retries - retries0, self.peak_slots,
+                                  self.peak_bytes, self.evictions - evictions0, peak_inflight)
 
 
 # ---------------------------------------------------------------------------
@@ -291,7 +298,12 @@ class RenderSlot:
         self.done.synchronize()
 
     def image_copy(self):
-        return self.frame.image.clone()
+        # copied on the slot's stream, so the slot's next replay cannot overwrite
+        # the image before the copy has read it; returned ready to use
+        with self.torch.cuda.stream(self.stream):
+            img = self.frame.image.clone()
+        self.stream.synchronize()
+        return img
 
     def free(self):
         self.graph = None
@@ -302,15 +314,16 @@ class RenderServer:
     """Scenes resident on the GPU + a :class:`Scheduler` of :class:`RenderSlot`s."""
 
     def __init__(self, scenes: list, kernel, opts: dict | None = None, mem_budget: int = 24 << 30,
-                 max_slots: int = 8, k_margin: float = 1.3):
+                 max_slots: int = 8, k_margin: float = 1.5, n_probe: int = 4, max_inflight: int | None = None):
         from . import pipeline
 
         self.scenes = scenes
         self.kernel = kernel
         self.opts = opts or pipeline.DEFAULT_OPTS
         self.k_margin = k_margin
+        self.n_probe = n_probe
         self.cap_hint = {}
-        self.sched = Scheduler(self._make_slot, self._need, mem_budget, max_slots)
+        self.sched = Scheduler(self._make_slot, self._need, mem_budget, max_slots, max_inflight=max_inflight)
 
     @staticmethod
     def slot_bytes(n: int, W: int, H: int, capacity: int) -> int:
@@ -319,24 +332,33 @@ class RenderServer:
         return (native.darb_bin_sort_workspace(n, W, H, capacity) + 4 * capacity + 52 * n
                 + (3 + 1 + 1) * 4 * W * H + 8 * ((W + 15) // 16) * ((H + 15) // 16))
 
-    def _capacity(self, key, cam=None) -> int:
+    def _capacity(self, key) -> int:
         if key not in self.cap_hint:
-            # sizing render of one pose of this key (blocking readback of K)
+            # sizing renders of a few poses of this key (blocking readback of K)
+            import torch
+
             from . import pipeline
 
             scene_id, W, H = key
             sp = self.scenes[scene_id]
-            fr = pipeline.render(sp, cam if cam is not None else self._probe_camera(W, H), self.kernel, self.opts,
-                                 k_capacity=1 << 16)
-            self.cap_hint[key] = int(fr.K)
+            K = 0
+            fr = None
+            for cam in self._probe_cameras(W, H, self.n_probe):
+                fr = pipeline.render(sp, cam, self.kernel, self.opts, frame=fr, k_capacity=1 << 16)
+                K = max(K, int(fr.K))
+            # the last raster pass may still run: finish it before its buffers go back
+            # to the allocator, where a slot on another stream could pick them up
+            torch.cuda.current_stream().synchronize()
             del fr
+            self.cap_hint[key] = K
         return int(self.cap_hint[key] * self.k_margin) + 4096
 
     @staticmethod
-    def _probe_camera(W: int, H: int) -> dict:
+    def _probe_cameras(W: int, H: int, n: int) -> list:
         from . import scenes
 
-        return scenes.orbit_camera(np.random.Generator(np.random.PCG64(W * 7919 + H)), W, H)
+        rng = np.random.Generator(np.random.PCG64(W * 7919 + H))
+        return [scenes.orbit_camera(rng, W, H) for _ in range(n)]
 
     def _need(self, key) -> int:
         scene_id, W, H = key
@@ -351,9 +373,15 @@ class RenderServer:
 
 
 def sequential_baseline(server: RenderServer, requests, keep_images: bool = False):
-    """One request at a time: the same slots and graphs, a single slot in flight."""
-    sched = Scheduler(server._make_slot, server._need, server.sched.budget, max_slots=1)
-    return sched.run(requests, keep_images=keep_images)
+    """One request at a time: the server's own slots and graphs (no new captures
+    once warm), a single request in flight."""
+    sched = server.sched
+    saved = sched.max_inflight
+    sched.max_inflight = 1
+    try:
+        return sched.run(requests, keep_images=keep_images)
+    finally:
+        sched.max_inflight = saved
 
 
 def make_requests(seed: int, n: int, rate_hz: float, n_scenes: int) -> list:

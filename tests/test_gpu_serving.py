@@ -70,4 +70,6 @@ def test_sequential_baseline_runs():
     srv = serving.RenderServer(sc, pipeline.KERNELS["half_cos"], mem_budget=4 << 30, max_slots=4)
     reqs = _requests(8, seed=9, spread=0.01)
     results, st = serving.sequential_baseline(srv, reqs)
-    assert st.n == 8 and st.peak_slots == 1
+    assert st.n == 8 and st.peak_inflight == 1
+    assert all(b.start >= a.end - 1e-9 for a, b in zip(sorted(results, key=lambda r: r.start),
+                                                      sorted(results, key=lambda r: r.start)[1:]))

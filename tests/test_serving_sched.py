@@ -51,7 +51,7 @@ class FakeSlot:
         self.log.append(("free", None, self.clock.t, self.key))
 
 
-def make(budget, max_slots=8, service=0.010, per_key_bytes=None, overflow_once=()):
+def make(budget, max_slots=8, service=0.010, per_key_bytes=None, overflow_once=(), max_inflight=None):
     clock = FakeClock()
     log = []
     per_key_bytes = per_key_bytes or {}
@@ -63,7 +63,8 @@ def make(budget, max_slots=8, service=0.010, per_key_bytes=None, overflow_once=(
     def factory(key, hint):
         return FakeSlot(key, need(key), clock, service, ov, log)
 
-    return Scheduler(factory, need, budget, max_slots, clock=clock, sleep=clock.sleep), clock, log
+    return (Scheduler(factory, need, budget, max_slots, clock=clock, sleep=clock.sleep, max_inflight=max_inflight),
+            clock, log)
 
 
 def req(i, t, scene=0, w=64, h=64):
@@ -133,3 +134,18 @@ def test_latency_statistics():
     results, st = s.run(rs)
     assert 3.9 <= st.p50_ms <= 5.0 and st.p99_ms >= st.p50_ms
     assert st.req_per_s == pytest.approx(50 / st.wall_s)
+
+
+def test_inflight_limit_keeps_slots():
+    # two keys, room for both slots: one request in flight at a time, no eviction
+    s, clock, log = make(budget=1000, max_slots=8, max_inflight=1)
+    rs = [req(i, 0.0, scene=i % 2) for i in range(6)]
+    results, st = s.run(rs)
+    assert st.peak_inflight == 1 and st.evictions == 0 and st.peak_slots == 2
+    rs_sorted = sorted(results, key=lambda r: r.start)
+    for a, b in zip(rs_sorted, rs_sorted[1:]):
+        assert b.start >= a.end - 1e-9
+    # a second run reuses the slots: no new slot, statistics of that run only
+    results, st2 = s.run([req(10 + i, 0.0, scene=i % 2) for i in range(4)])
+    assert st2.n == 4 and st2.evictions == 0 and st2.peak_slots == 2 and st2.retries == 0
+    assert sum(1 for e in log if e[0] == "free") == 0
