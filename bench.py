@@ -120,6 +120,60 @@ def serving_bench(kernel_name: str, seconds: float, rate_hz: float, mem_budget_g
                                    mpix_per_s=round(seq.mpix_per_s, 2)))
 
 
+def multiview_bench(kernel_name: str, n: int, n_views: int, steps: int, warmup: int):
+    """Batched multi-view training step: n clustered splats, n_views views at uneven
+    resolutions, mean-L1 loss to random targets.  The multi-view step (one
+    preprocess launch, a bin/sort per view, one fused forward+loss+backward launch
+    over all views' tiles, one summed preprocess backward) against the same step
+    as single-view calls made view after view."""
+    import torch
+
+    from paper_2501_12369_amd import native, pipeline, scenes
+
+    t0 = time.time()
+    spd = pipeline.splats_to_device(scenes.scene_splats(5, n))
+    cams = scenes.multiview_cameras(5, n_views)
+    log(f"multiview scene generated in {time.time() - t0:.1f}s; views "
+        + " ".join(f"{c['width']}x{c['height']}" for c in cams))
+    kern = pipeline.KERNELS[kernel_name]
+    gen = torch.Generator("cuda").manual_seed(11)
+    targets = [torch.rand((3, c["height"], c["width"]), device="cuda", generator=gen) for c in cams]
+    caps = []
+    for c in cams:
+        fr = pipeline.render(spd, c, kern, k_capacity=1 << 20)
+        caps.append(int(fr.K * 1.05) + 4096)
+    del fr
+    mf = pipeline.alloc_multiview(n, cams, caps)
+    _, g3d = pipeline.alloc_grads(n, int(spd["sh_degree"]))
+    pix = sum(c["width"] * c["height"] for c in cams)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / steps
+        assert not pipeline.multiview_overflowed(mf), "instance capacity overflow during timing"
+        return dt
+
+    fused = timed(lambda: pipeline.multiview_step(spd, mf, targets, kern, g3d, fused=True))
+    split = timed(lambda: pipeline.multiview_step(spd, mf, targets, kern, g3d, fused=False))
+    seq = timed(lambda: pipeline.sequential_step(spd, mf, targets, kern, g3d))
+    K = sum(fr.K for fr in mf.frames)
+    log(f"multiview {n_views} views, {pix/1e6:.2f} Mpix, K={K}: fused {fused*1e3:.3f} ms, "
+        f"multi (separate launches) {split*1e3:.3f} ms, sequential single-view {seq*1e3:.3f} ms")
+    sizes = [f"{c['width']}x{c['height']}" for c in cams]
+    return dict(workload=f"{n} clustered splats (SH degree 3), {n_views} views at uneven resolutions "
+                         f"{sizes}, {kernel_name} DARBF, mean-L1 loss, fwd+bwd training step",
+                pixels=pix, instances=int(K),
+                fused_ms=round(fused * 1e3, 4), multi_ms=round(split * 1e3, 4), sequential_ms=round(seq * 1e3, 4),
+                fused_mpix_per_s=round(pix / fused / 1e6, 2), sequential_mpix_per_s=round(pix / seq / 1e6, 2),
+                speedup_vs_sequential=round(seq / fused, 3))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +187,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-mem-gb", type=float, default=24.0)
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--multiview-views", type=int, default=8, help="0 disables the multi-view leg")
+    ap.add_argument("--multiview-n", type=int, default=2_000_000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (requested --gpus {args.gpus}); "
@@ -166,7 +222,8 @@ def main():
     del fr
     n_vis = int((frame.proj["radius"] > 0).sum())
     target = torch.rand((3, H, W), device="cuda", generator=torch.Generator("cuda").manual_seed(7))
-    G = (torch.sign(frame.image - target) / (3 * P)).contiguous()
+    G = torch.empty((3, H, W), dtype=torch.float32, device="cuda")
+    native.darb_image_loss(frame.image, target, W, H, native.LOSS_L1, dL_dimage=G)  # mean-L1 gradient
     grads = pipeline.alloc_grads(n, 3)
     log(f"N={n} visible={n_vis} K={K} tiles={pipeline.n_tiles(W, H)}")
 
@@ -243,6 +300,11 @@ def main():
         cpu = cpu_baseline(sc, args.kernel, args.cpu_rows_every)
     del frame, grads, spd
     torch.cuda.empty_cache()
+    multiview_stats = None
+    if args.multiview_views > 0:
+        multiview_stats = multiview_bench(args.kernel, args.multiview_n, args.multiview_views, max(3, args.steps // 2),
+                                          2)
+        torch.cuda.empty_cache()
     serving_stats = None
     if args.serve_seconds > 0:
         serving_stats = serving_bench(args.kernel, args.serve_seconds, args.serve_rate, args.serve_mem_gb,
@@ -268,6 +330,7 @@ def main():
                    "stage_ms": {k: round(v, 4) for k, v in per_stage.items()}},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "multiview": multiview_stats,
         "serving": serving_stats,
     }
     print(json.dumps(out), flush=True)

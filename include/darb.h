@@ -40,8 +40,10 @@ extern "C" {
 #define DARB_API
 #endif
 
-#define DARB_ABI_VERSION 1
+#define DARB_ABI_VERSION 2
 #define DARB_TILE 16
+#define DARB_MAX_VIEWS 16       /* views per multi-view call */
+#define DARB_LOSS_WS_BYTES 4096 /* workspace of darb_image_loss */
 
 typedef enum {
     DARB_OK = 0,
@@ -62,6 +64,14 @@ typedef enum {
     DARB_IMQ_SQRT = 5,   /* 1/sqrt(E/xi + 1)            (inverse multiquadric of Table 1)           */
     DARB_PARABOLA = 6    /* 1 - E/xi                    (parabola; xi = 9)                          */
 } darb_kernel_kind;
+
+/* Image losses with a per-pixel gradient, each the mean over the 3 W H values
+ * of a view (the photometric L1 term of the 3DGS objective the paper trains
+ * with, and the squared error). */
+typedef enum {
+    DARB_LOSS_L1 = 0, /* mean |I - I_target|;  dL/dI = sign(I - I_target) / (3 W H), 0 where equal */
+    DARB_LOSS_L2 = 1  /* mean (I - I_target)^2; dL/dI = 2 (I - I_target) / (3 W H) */
+} darb_loss_kind;
 
 /* A DARBF: profile, scale, correction factor and support.
  * psi multiplies the projected 2x2 covariance (Eq. of the 2x2 covariance
@@ -153,6 +163,26 @@ typedef struct {
     float *opacity;
     float *sh;
 } darb_grads3d;
+
+/* One view of a multi-view call: its camera, its own projected splats and
+ * sorted instance list (from darb_preprocess_multi and darb_bin_sort), and its
+ * per-view images and gradient buffers.  Fields a call does not use may be
+ * NULL; each call lists what it reads and writes.  width/height come from cam. */
+typedef struct {
+    darb_camera cam;
+    darb_projected proj;         /* [n] per view */
+    int64_t k_capacity;          /* capacity of vals (as given to darb_bin_sort) */
+    const uint32_t *vals;        /* sorted instance list */
+    const uint32_t *ranges;      /* [tiles][2] */
+    const int32_t *overflow_dev; /* nullable: nonzero flag = this view is skipped */
+    float *image;                /* [3][H][W] */
+    float *final_T;              /* [H][W] checkpoint */
+    uint32_t *last;              /* [H][W] checkpoint */
+    uint32_t *n_contrib;         /* [H][W] nullable */
+    const float *dL_dimage;      /* [3][H][W] upstream gradient (darb_raster_bwd_multi) */
+    const float *target;         /* [3][H][W] target image (darb_raster_fwdbwd_multi) */
+    darb_grads2d grads2d;        /* [n] per-view gradients w.r.t. the projected splats */
+} darb_view;
 
 DARB_API int32_t darb_version(void);
 DARB_API const char *darb_status_string(int32_t status);
@@ -246,18 +276,35 @@ DARB_API darb_status darb_raster_fwd(const darb_projected *proj, int64_t n, cons
  *   dL/drgb += alpha T G;  dL/dalpha = G . (rgb T - S / (1 - alpha)), S = colour behind + T_final bg;
  *   dL/do += F(E) dL/dalpha  (passed straight through the alpha_max clamp);
  *   dL/dE = o F'(E) dL/dalpha;  dL/dmu' += 2 dL/dE Q d;  dL/d(a,b,c) += dL/dE (dx^2, 2 dx dy, dy^2).
- * Per-splat sums are reduced across each wavefront before one set of atomic
- * adds per (tile, splat); g2d is zeroed by the call first.
+ * Per (tile, splat) the partial sums are reduced across the wavefront.  Then:
+ *   deterministic = 0: one set of float atomic adds per (tile, splat) (summation
+ *                      order, and so the last bits, may vary between runs);
+ *   deterministic = 1: two passes: every (tile, splat) partial is stored, the
+ *                      partials are sorted by splat (stable) and each splat's
+ *                      are summed in tile order -- bit-reproducible.  Needs
+ *                      k_capacity (the capacity of vals given to darb_bin_sort)
+ *                      and ws of darb_raster_bwd_workspace() bytes; otherwise
+ *                      k_capacity is ignored and ws may be NULL.
+ * g2d is zeroed by the call first.
  *   dL_dimage [3][H][W]
  *   g2d       required output
  *   cam, in, g3d: when g3d is non-null the call continues with the chain of
- *             darb_preprocess_bwd (cam and in then required) and writes g3d.
+ *             darb_preprocess_bwd (cam and in then required) and overwrites g3d.
  */
 DARB_API darb_status darb_raster_bwd(const darb_projected *proj, int64_t n, const uint32_t *vals, const uint32_t *ranges,
                             const int32_t *overflow_dev, int32_t width, int32_t height, const darb_kernel *kernel,
                             const darb_raster_opts *opts, const float *dL_dimage, const float *final_T,
                             const uint32_t *last, const darb_grads2d *g2d, const darb_camera *cam,
-                            const darb_splats *in, const darb_grads3d *g3d, void *stream);
+                            const darb_splats *in, const darb_grads3d *g3d, int32_t deterministic,
+                            int64_t k_capacity, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * darb_raster_bwd_workspace -- bytes of workspace of the deterministic
+ * darb_raster_bwd for n splats, a width x height image and the instance
+ * capacity k_capacity of its list (the stored partials are bounded by the
+ * instance count).  Returns 0 for invalid or unsupported sizes.
+ */
+DARB_API size_t darb_raster_bwd_workspace(int64_t n, int32_t width, int32_t height, int64_t k_capacity);
 
 /*
  * darb_preprocess_bwd -- chain rule through darb_preprocess (psi enters the
@@ -266,10 +313,76 @@ DARB_API darb_status darb_raster_bwd(const darb_projected *proj, int64_t n, cons
  * (through the normalisation); the mean through mu', through J (zero across
  * an active Jacobian clamp) and through the SH view direction; SH
  * coefficients (zero for clamped channels); opacity passed through.
- * g3d is overwritten for every splat (zeros for culled splats).
+ * accumulate = 0: g3d is overwritten for every splat (zeros for culled splats);
+ * accumulate = 1: the gradients are added to g3d (several views in turn).
  */
 DARB_API darb_status darb_preprocess_bwd(const darb_camera *cam, const darb_kernel *kernel, int64_t n, const darb_splats *in,
-                                const darb_grads2d *g2d, const darb_grads3d *g3d, void *stream);
+                                const darb_grads2d *g2d, const darb_grads3d *g3d, int32_t accumulate, void *stream);
+
+/*
+ * darb_image_loss -- per-pixel image loss of a rendered view against a target
+ * (the photometric term that drives the backward pass):
+ *   loss_dev  nullable [1]: the loss value (mean over 3 W H), summed in a fixed
+ *             order (reproducible); needs ws of DARB_LOSS_WS_BYTES bytes
+ *   dL_dimage nullable [3][H][W]: the gradient of that loss
+ * image and target are [3][H][W].
+ */
+DARB_API darb_status darb_image_loss(const float *image, const float *target, int32_t width, int32_t height,
+                                     int32_t loss_kind, float *dL_dimage, float *loss_dev, void *ws, size_t ws_bytes,
+                                     void *stream);
+
+/*
+ * Multi-view calls: nv views (1 <= nv <= DARB_MAX_VIEWS) of the same n splats
+ * in one launch per stage (a training step over several views, or a batch of
+ * renders of one scene).  Each view keeps its own projected splats, instance
+ * list, images and 2D gradients; darb_bin_sort runs per view between
+ * darb_preprocess_multi and the raster calls.
+ *
+ * darb_preprocess_multi -- darb_preprocess for every view; the splat
+ * parameters are read once.  Writes views[v].proj.
+ */
+DARB_API darb_status darb_preprocess_multi(const darb_view *views, int32_t nv, const darb_kernel *kernel, int64_t n,
+                                           const darb_splats *in, void *stream);
+
+/*
+ * darb_raster_fwd_multi -- darb_raster_fwd of every view in one launch over
+ * all views' tiles.  Reads proj, vals, ranges, overflow_dev; writes image,
+ * final_T, last (and n_contrib when non-NULL).
+ */
+DARB_API darb_status darb_raster_fwd_multi(const darb_view *views, int32_t nv, int64_t n, const darb_kernel *kernel,
+                                           const darb_raster_opts *opts, void *stream);
+
+/*
+ * darb_raster_bwd_multi -- darb_raster_bwd (without the chain) of every view
+ * in one launch over all views' tiles.  Reads the forward's inputs, final_T,
+ * last and dL_dimage; zeroes and writes grads2d of every view.
+ * deterministic as in darb_raster_bwd, with ws of
+ * darb_raster_bwd_multi_workspace() bytes; it needs nv * n < 2^32.
+ */
+DARB_API darb_status darb_raster_bwd_multi(const darb_view *views, int32_t nv, int64_t n, const darb_kernel *kernel,
+                                           const darb_raster_opts *opts, int32_t deterministic, void *ws,
+                                           size_t ws_bytes, void *stream);
+DARB_API size_t darb_raster_bwd_multi_workspace(const darb_view *views, int32_t nv, int64_t n);
+
+/*
+ * darb_raster_fwdbwd_multi -- forward, per-pixel loss gradient and backward
+ * of every view in ONE launch: each tile composites its pixels, takes
+ * dL/dI of `loss_kind` against views[v].target in registers and walks its
+ * list backwards right away, with no checkpoint round trip through memory.
+ * Writes image (and final_T, last, n_contrib when non-NULL) and zeroes and
+ * accumulates grads2d with atomics.  Equal, up to the atomic summation order,
+ * to darb_raster_fwd + darb_image_loss + darb_raster_bwd per view.
+ */
+DARB_API darb_status darb_raster_fwdbwd_multi(const darb_view *views, int32_t nv, int64_t n, const darb_kernel *kernel,
+                                              const darb_raster_opts *opts, int32_t loss_kind, void *stream);
+
+/*
+ * darb_preprocess_bwd_multi -- darb_preprocess_bwd summed over the views:
+ * g3d = sum_v chain(views[v].cam, views[v].grads2d), views in order, with the
+ * splat parameters read once and g3d written once (overwritten).
+ */
+DARB_API darb_status darb_preprocess_bwd_multi(const darb_view *views, int32_t nv, const darb_kernel *kernel, int64_t n,
+                                               const darb_splats *in, const darb_grads3d *g3d, void *stream);
 
 #ifdef __cplusplus
 }

@@ -27,6 +27,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "oracle.c")
 
 GAUSS, HALF_COS, RAISED_COS, SINC, IMQ, IMQ_SQRT, PARABOLA = range(7)
+LOSS_L1, LOSS_L2 = 0, 1
 
 
 def build(force: bool = True) -> str:
@@ -305,3 +306,26 @@ def fd_grad(fun, x: np.ndarray, index: tuple, rel_h: float = 1e-6) -> float:
     x[index] = x0 - h
     fm = fun(x)
     return (fp - fm) / (2.0 * h)
+
+
+def image_loss(image, target, kind: int):
+    """Photometric loss of a rendered image, the mean over all its values of
+    |I - I_t| (L1, the 3DGS photometric term the paper trains with) or
+    (I - I_t)^2 (L2), and its gradient dL/dI (same shape; sign(0) = 0), FP64."""
+    d = _f64(image) - _f64(target)
+    m = d.size
+    if kind == LOSS_L1:
+        return float(np.sum(np.abs(d)) / m), np.sign(d) / m
+    return float(np.sum(d * d) / m), 2.0 * d / m
+
+
+def render_bwd_views(cams: list, k: KernelSpec, opts: Opts, params: dict, Gs: list, use_grid=True):
+    """Gradients of sum_v sum_p G_v,p . I_v,p: every view's render_bwd, summed
+    over the views (the parameters are shared)."""
+    total = None
+    per_view = []
+    for cam, G in zip(cams, Gs):
+        _, g2d, g3d = render_bwd(cam, k, opts, params, G, use_grid=use_grid)
+        per_view.append(g2d)
+        total = {kk: v.copy() for kk, v in g3d.items()} if total is None else {kk: total[kk] + g3d[kk] for kk in total}
+    return per_view, total

@@ -151,11 +151,111 @@ darb_status check_g3d(const darb_grads3d *g, int64_t n) {
     return DARB_OK;
 }
 
+darb::RView make_rview(const darb_projected &p, const uint32_t *vals, const uint32_t *ranges,
+                        const int32_t *overflow, int width, int height) {
+    darb::RView v{};
+    v.p = p;
+    v.vals = vals;
+    v.ranges = ranges;
+    v.overflow = overflow;
+    v.W = width;
+    v.H = height;
+    v.gx = (width + darb::kTile - 1) / darb::kTile;
+    v.loss_scale = 1.0f / (float)(3.0 * (double)width * (double)height);
+    return v;
+}
+
+uint32_t tile_count(int width, int height) {
+    return (uint32_t)(((width + darb::kTile - 1) / darb::kTile) * ((height + darb::kTile - 1) / darb::kTile));
+}
+
 #define TRY(x)                                  \
     do {                                        \
         darb_status _st = (x);                  \
         if (_st != DARB_OK) return _st;         \
     } while (0)
+
+
+enum ViewNeed : unsigned {
+    kNeedProj = 1u,      // projected splats (all fields)
+    kNeedList = 2u,      // vals, ranges
+    kNeedFwdOut = 4u,    // image, final_T, last
+    kNeedImage = 8u,     // image only (final_T, last optional)
+    kNeedBwdIn = 16u,    // final_T, last, dL_dimage
+    kNeedTarget = 32u,   // target
+    kNeedG2 = 64u,       // grads2d
+};
+
+// Validates views[0..nv) for what a call needs and builds the device view table.
+darb_status check_views(const darb_view *views, int32_t nv, int64_t n, unsigned need, darb::RViews *rv,
+                        darb::Cams *cams, uint32_t *items, uint64_t *cap_total) {
+    if (!views) return fail(DARB_ERR_INVALID_ARG, "null pointer: %s", "views");
+    if (nv < 1 || nv > DARB_MAX_VIEWS) return fail(DARB_ERR_INVALID_ARG, "%s", "nv must be in [1, DARB_MAX_VIEWS]");
+    uint32_t it = 0;
+    uint64_t cap = 0;
+    if (rv) *rv = darb::RViews{};
+    if (cams) *cams = darb::Cams{};
+    for (int v = 0; v < nv; v++) {
+        const darb_view &V = views[v];
+        darb::Cam c;
+        TRY(check_camera(&V.cam, &c));
+        TRY(check_size(V.cam.width, V.cam.height));
+        if (need & kNeedProj) TRY(check_projected(&V.proj, n, true));
+        if (need & kNeedList) {
+            if (n > 0) REQUIRE_PTR(V.vals);
+            REQUIRE_PTR(V.ranges);
+            OPT_PTR(V.overflow_dev);
+            if (V.k_capacity < 0) return fail(DARB_ERR_INVALID_ARG, "%s", "view k_capacity must be >= 0");
+            cap += (uint64_t)V.k_capacity;
+        }
+        if (need & kNeedFwdOut) {
+            REQUIRE_PTR(V.image);
+            REQUIRE_PTR(V.final_T);
+            REQUIRE_PTR(V.last);
+            OPT_PTR(V.n_contrib);
+        }
+        if (need & kNeedImage) {
+            REQUIRE_PTR(V.image);
+            OPT_PTR(V.final_T);
+            OPT_PTR(V.last);
+            OPT_PTR(V.n_contrib);
+        }
+        if (need & kNeedBwdIn) {
+            REQUIRE_PTR(V.final_T);
+            REQUIRE_PTR(V.last);
+            REQUIRE_PTR(V.dL_dimage);
+        }
+        if (need & kNeedTarget) REQUIRE_PTR(V.target);
+        if (need & kNeedG2) TRY(check_g2d(&V.grads2d, n));
+        if (rv) {
+            darb::RView r = make_rview(V.proj, V.vals, V.ranges, V.overflow_dev, V.cam.width, V.cam.height);
+            r.image = V.image;
+            r.final_T = V.final_T;
+            r.last = V.last;
+            r.n_contrib = V.n_contrib;
+            r.dL = V.dL_dimage;
+            r.target = V.target;
+            r.g2 = V.grads2d;
+            r.item0 = it;
+            r.key0 = (uint32_t)((uint64_t)v * (uint64_t)n);
+            rv->v[v] = r;
+        }
+        if (cams) cams->c[v] = c;
+        it += tile_count(V.cam.width, V.cam.height);
+    }
+    if (rv) rv->nv = nv;
+    if (cams) cams->nv = nv;
+    if (items) *items = it;
+    if (cap_total) *cap_total = cap;
+    return DARB_OK;
+}
+
+darb_status check_det(int64_t n, int32_t nv, uint64_t cap) {
+    if ((uint64_t)nv * (uint64_t)n >= 0xFFFFFFFFull)
+        return fail(DARB_ERR_UNSUPPORTED, "%s", "deterministic mode needs nv * n < 2^32 - 1");
+    if (cap >= 0xFFFFFFFFull) return fail(DARB_ERR_UNSUPPORTED, "%s", "deterministic mode needs capacity < 2^32 - 1");
+    return DARB_OK;
+}
 
 }  // namespace
 
@@ -272,13 +372,20 @@ darb_status darb_raster_fwd(const darb_projected *proj, int64_t n, const uint32_
     REQUIRE_PTR(last);
     OPT_PTR(n_contrib);
     g_err[0] = 0;
-    return hip_status(darb::launch_raster_fwd(kernel->kind, *proj, (int)n, vals, ranges, overflow_dev, width, height, kp, ro,
-                                              image, final_T, last, n_contrib, (hipStream_t)stream),
+    darb::RViews rv{};
+    rv.nv = 1;
+    rv.v[0] = make_rview(*proj, vals, ranges, overflow_dev, width, height);
+    rv.v[0].image = image;
+    rv.v[0].final_T = final_T;
+    rv.v[0].last = last;
+    rv.v[0].n_contrib = n_contrib;
+    return hip_status(darb::launch_raster_fwd(kernel->kind, rv, tile_count(width, height), (int)n, kp, ro,
+                                              (hipStream_t)stream),
                       "darb_raster_fwd");
 }
 
 darb_status darb_preprocess_bwd(const darb_camera *cam, const darb_kernel *kernel, int64_t n, const darb_splats *in,
-                                const darb_grads2d *g2d, const darb_grads3d *g3d, void *stream) {
+                                const darb_grads2d *g2d, const darb_grads3d *g3d, int32_t accumulate, void *stream) {
     darb::Cam c;
     darb::KParams kp;
     TRY(check_n(n));
@@ -289,7 +396,7 @@ darb_status darb_preprocess_bwd(const darb_camera *cam, const darb_kernel *kerne
     TRY(check_g2d(g2d, n));
     TRY(check_g3d(g3d, n));
     g_err[0] = 0;
-    return hip_status(darb::launch_preprocess_bwd(c, kp, (int)n, *in, *g2d, *g3d, (hipStream_t)stream),
+    return hip_status(darb::launch_preprocess_bwd(c, kp, (int)n, *in, *g2d, *g3d, accumulate != 0, (hipStream_t)stream),
                       "darb_preprocess_bwd");
 }
 
@@ -297,7 +404,8 @@ darb_status darb_raster_bwd(const darb_projected *proj, int64_t n, const uint32_
                             const int32_t *overflow_dev, int32_t width, int32_t height, const darb_kernel *kernel,
                             const darb_raster_opts *opts, const float *dL_dimage, const float *final_T,
                             const uint32_t *last, const darb_grads2d *g2d, const darb_camera *cam,
-                            const darb_splats *in, const darb_grads3d *g3d, void *stream) {
+                            const darb_splats *in, const darb_grads3d *g3d, int32_t deterministic,
+                            int64_t k_capacity, void *ws, size_t ws_bytes, void *stream) {
     darb::KParams kp;
     darb::ROpts ro;
     darb::Cam c;
@@ -320,13 +428,162 @@ darb_status darb_raster_bwd(const darb_projected *proj, int64_t n, const uint32_
         TRY(check_splats(in, n));
         TRY(check_g3d(g3d, n));
     }
+    const uint32_t items = tile_count(width, height);
+    if (deterministic) {
+        if (k_capacity < 0) return fail(DARB_ERR_INVALID_ARG, "%s", "k_capacity must be >= 0");
+        TRY(check_det(n, 1, (uint64_t)k_capacity));
+        REQUIRE_PTR(ws);
+        size_t need = darb::det_workspace(items, (uint64_t)k_capacity);
+        if (ws_bytes < need) {
+            snprintf(g_err, sizeof(g_err), "workspace too small: %zu < %zu bytes", ws_bytes, need);
+            return DARB_ERR_INVALID_ARG;
+        }
+    }
     g_err[0] = 0;
     hipStream_t s = (hipStream_t)stream;
-    TRY(hip_status(darb::launch_raster_bwd(kernel->kind, *proj, (int)n, vals, ranges, overflow_dev, width, height, kp,
-                                           ro, dL_dimage, final_T, last, *g2d, s),
+    darb::RViews rv{};
+    rv.nv = 1;
+    rv.v[0] = make_rview(*proj, vals, ranges, overflow_dev, width, height);
+    rv.v[0].final_T = const_cast<float *>(final_T);
+    rv.v[0].last = const_cast<uint32_t *>(last);
+    rv.v[0].dL = dL_dimage;
+    rv.v[0].g2 = *g2d;
+    TRY(hip_status(darb::launch_raster_bwd(kernel->kind, rv, items, (int)n, kp, ro, deterministic ? ws : nullptr,
+                                           deterministic ? (uint64_t)k_capacity : 0, s),
                    "darb_raster_bwd"));
-    if (g3d) TRY(hip_status(darb::launch_preprocess_bwd(c, kp, (int)n, *in, *g2d, *g3d, s), "darb_raster_bwd chain"));
+    if (g3d)
+        TRY(hip_status(darb::launch_preprocess_bwd(c, kp, (int)n, *in, *g2d, *g3d, false, s), "darb_raster_bwd chain"));
     return DARB_OK;
+}
+
+size_t darb_raster_bwd_workspace(int64_t n, int32_t width, int32_t height, int64_t k_capacity) {
+    if (n < 0 || n > 0x7FFFFFFFll || width <= 0 || height <= 0) return 0;
+    if (k_capacity < 0 || k_capacity >= 0xFFFFFFFFll || (uint64_t)n >= 0xFFFFFFFFull) return 0;
+    int64_t gx = (width + darb::kTile - 1) / darb::kTile, gy = (height + darb::kTile - 1) / darb::kTile;
+    if (gx * gy > darb::kMaxTiles) return 0;
+    return darb::det_workspace((uint32_t)(gx * gy), (uint64_t)k_capacity);
+}
+
+darb_status darb_image_loss(const float *image, const float *target, int32_t width, int32_t height, int32_t loss_kind,
+                            float *dL_dimage, float *loss_dev, void *ws, size_t ws_bytes, void *stream) {
+    if (width <= 0 || height <= 0) return fail(DARB_ERR_INVALID_ARG, "%s", "width/height must be > 0");
+    if (loss_kind != DARB_LOSS_L1 && loss_kind != DARB_LOSS_L2)
+        return fail(DARB_ERR_INVALID_ARG, "%s", "unknown loss kind");
+    REQUIRE_PTR(image);
+    REQUIRE_PTR(target);
+    OPT_PTR(dL_dimage);
+    OPT_PTR(loss_dev);
+    if (loss_dev) {
+        REQUIRE_PTR(ws);
+        if (ws_bytes < DARB_LOSS_WS_BYTES)
+            return fail(DARB_ERR_INVALID_ARG, "%s", "workspace smaller than DARB_LOSS_WS_BYTES");
+    }
+    g_err[0] = 0;
+    const darb::RView r = make_rview(darb_projected{}, nullptr, nullptr, nullptr, width, height);
+    return hip_status(darb::launch_image_loss(loss_kind, image, target, width, height, r.loss_scale, dL_dimage,
+                                              loss_dev, static_cast<float *>(ws), (hipStream_t)stream),
+                      "darb_image_loss");
+}
+
+darb_status darb_preprocess_multi(const darb_view *views, int32_t nv, const darb_kernel *kernel, int64_t n,
+                                  const darb_splats *in, void *stream) {
+    darb::KParams kp;
+    darb::Cams cams;
+    TRY(check_n(n));
+    TRY(check_kernel(kernel, &kp));
+    TRY(check_splats(in, n));
+    TRY(check_views(views, nv, n, kNeedProj, nullptr, &cams, nullptr, nullptr));
+    darb::Projs outs{};
+    for (int v = 0; v < nv; v++) outs.p[v] = views[v].proj;
+    g_err[0] = 0;
+    return hip_status(darb::launch_preprocess_multi(cams, kp, (int)n, *in, outs, (hipStream_t)stream),
+                      "darb_preprocess_multi");
+}
+
+darb_status darb_raster_fwd_multi(const darb_view *views, int32_t nv, int64_t n, const darb_kernel *kernel,
+                                  const darb_raster_opts *opts, void *stream) {
+    darb::KParams kp;
+    darb::ROpts ro;
+    darb::RViews rv;
+    uint32_t items;
+    TRY(check_n(n));
+    TRY(check_kernel(kernel, &kp));
+    TRY(check_opts(opts, &ro));
+    TRY(check_views(views, nv, n, kNeedProj | kNeedList | kNeedFwdOut, &rv, nullptr, &items, nullptr));
+    g_err[0] = 0;
+    return hip_status(darb::launch_raster_fwd(kernel->kind, rv, items, (int)n, kp, ro, (hipStream_t)stream),
+                      "darb_raster_fwd_multi");
+}
+
+size_t darb_raster_bwd_multi_workspace(const darb_view *views, int32_t nv, int64_t n) {
+    uint32_t items;
+    uint64_t cap;
+    if (n < 0 || n > 0x7FFFFFFFll) return 0;
+    if (check_views(views, nv, n, kNeedList, nullptr, nullptr, &items, &cap) != DARB_OK) return 0;
+    if (check_det(n, nv, cap) != DARB_OK) return 0;
+    return darb::det_workspace(items, cap);
+}
+
+darb_status darb_raster_bwd_multi(const darb_view *views, int32_t nv, int64_t n, const darb_kernel *kernel,
+                                  const darb_raster_opts *opts, int32_t deterministic, void *ws, size_t ws_bytes,
+                                  void *stream) {
+    darb::KParams kp;
+    darb::ROpts ro;
+    darb::RViews rv;
+    uint32_t items;
+    uint64_t cap;
+    TRY(check_n(n));
+    TRY(check_kernel(kernel, &kp));
+    TRY(check_opts(opts, &ro));
+    TRY(check_views(views, nv, n, kNeedProj | kNeedList | kNeedBwdIn | kNeedG2, &rv, nullptr, &items, &cap));
+    if (deterministic) {
+        TRY(check_det(n, nv, cap));
+        REQUIRE_PTR(ws);
+        size_t need = darb::det_workspace(items, cap);
+        if (ws_bytes < need) {
+            snprintf(g_err, sizeof(g_err), "workspace too small: %zu < %zu bytes", ws_bytes, need);
+            return DARB_ERR_INVALID_ARG;
+        }
+    }
+    g_err[0] = 0;
+    return hip_status(darb::launch_raster_bwd(kernel->kind, rv, items, (int)n, kp, ro, deterministic ? ws : nullptr,
+                                              deterministic ? cap : 0, (hipStream_t)stream),
+                      "darb_raster_bwd_multi");
+}
+
+darb_status darb_raster_fwdbwd_multi(const darb_view *views, int32_t nv, int64_t n, const darb_kernel *kernel,
+                                     const darb_raster_opts *opts, int32_t loss_kind, void *stream) {
+    darb::KParams kp;
+    darb::ROpts ro;
+    darb::RViews rv;
+    uint32_t items;
+    TRY(check_n(n));
+    TRY(check_kernel(kernel, &kp));
+    TRY(check_opts(opts, &ro));
+    if (loss_kind != DARB_LOSS_L1 && loss_kind != DARB_LOSS_L2)
+        return fail(DARB_ERR_INVALID_ARG, "%s", "unknown loss kind");
+    TRY(check_views(views, nv, n, kNeedProj | kNeedList | kNeedImage | kNeedTarget | kNeedG2, &rv, nullptr, &items,
+                    nullptr));
+    g_err[0] = 0;
+    return hip_status(darb::launch_raster_fwdbwd(kernel->kind, loss_kind, rv, items, (int)n, kp, ro,
+                                                 (hipStream_t)stream),
+                      "darb_raster_fwdbwd_multi");
+}
+
+darb_status darb_preprocess_bwd_multi(const darb_view *views, int32_t nv, const darb_kernel *kernel, int64_t n,
+                                      const darb_splats *in, const darb_grads3d *g3d, void *stream) {
+    darb::KParams kp;
+    darb::Cams cams;
+    TRY(check_n(n));
+    TRY(check_kernel(kernel, &kp));
+    TRY(check_splats(in, n));
+    TRY(check_g3d(g3d, n));
+    TRY(check_views(views, nv, n, kNeedG2, nullptr, &cams, nullptr, nullptr));
+    darb::G2s g2{};
+    for (int v = 0; v < nv; v++) g2.g[v] = views[v].grads2d;
+    g_err[0] = 0;
+    return hip_status(darb::launch_preprocess_bwd_multi(cams, kp, (int)n, *in, g2, *g3d, (hipStream_t)stream),
+                      "darb_preprocess_bwd_multi");
 }
 
 }  // extern "C"

@@ -714,6 +714,36 @@ WsLayout layout(int n, int gx, int gy, int64_t k_capacity) {
 
 }  // namespace
 
+size_t scan_parts_words(uint32_t max_count) { return (size_t)(max_count + kScanBlock - 1) / kScanBlock + 1; }
+
+size_t radix_hist_words(uint32_t max_count) {
+    return 256 * ((size_t)(max_count + kRadixTile - 1) / kRadixTile);
+}
+
+hipError_t scan_u32(uint32_t *data, const uint32_t *count_dev, uint32_t max_count, uint32_t *parts,
+                    uint32_t *total_out, const int32_t *skip, hipStream_t s) {
+    return scan_exclusive(data, count_dev, max_count, parts, total_out, skip, s);
+}
+
+hipError_t radix_sort_pairs(uint32_t *kA, uint32_t *vA, uint32_t *kB, uint32_t *vB, const uint32_t *count_dev,
+                            uint32_t max_count, int bits, uint32_t *hist, uint32_t *parts, const int32_t *skip,
+                            hipStream_t s) {
+    if (max_count == 0) return hipSuccess;
+    const int nblk = (int)((max_count + kRadixTile - 1) / kRadixTile);
+    const uint32_t hist_n = (uint32_t)(256 * (size_t)nblk);
+    uint32_t *ki = kA, *vi = vA, *ko = kB, *vo = vB;
+    hipError_t e;
+    for (int shift = 0; shift < bits; shift += 8) {
+        hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kRadixThreads), 0, s, ki, count_dev, shift, hist, nblk, skip);
+        if ((e = scan_exclusive(hist, nullptr, hist_n, parts, nullptr, skip, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kRadixThreads), 0, s, ki, vi, ko, vo, count_dev, shift,
+                           hist, nblk, skip);
+        std::swap(ki, ko);
+        std::swap(vi, vo);
+    }
+    return hipGetLastError();
+}
+
 int binsort_super_tiles(int width, int height) {
     return super_count((width + kTile - 1) / kTile, (height + kTile - 1) / kTile);
 }

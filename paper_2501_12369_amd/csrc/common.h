@@ -220,6 +220,26 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
 }
 
 // ---------------------------------------------------------------------------
+// Image losses whose gradient is per pixel (shared by the loss kernel and the
+// fused forward+backward raster kernel, so both produce the same bits).
+// scale = 1 / (3 W H): the loss is the mean over the three colour planes.
+// ---------------------------------------------------------------------------
+
+template <int LOSS>
+__device__ __forceinline__ float loss_value(float img, float tgt) {
+    float d = img - tgt;
+    if constexpr (LOSS == DARB_LOSS_L1) return fabsf(d);
+    else return d * d;
+}
+
+template <int LOSS>
+__device__ __forceinline__ float loss_grad(float img, float tgt, float scale) {
+    float d = img - tgt;
+    if constexpr (LOSS == DARB_LOSS_L1) return d > 0.0f ? scale : (d < 0.0f ? -scale : 0.0f);
+    else return (2.0f * scale) * d;
+}
+
+// ---------------------------------------------------------------------------
 // Internal launchers (implemented per stage).
 // ---------------------------------------------------------------------------
 
@@ -233,12 +253,54 @@ struct Cam {
     float dilation;
 };
 
+constexpr int kMaxViews = DARB_MAX_VIEWS;
+
+// One view as the raster kernels see it (device pointers; nullable where the
+// entry point allows it).  item0 is the first work item (tile) of the view in a
+// launch over several views; key0 = view index * n keys the deterministic
+// reduction.
+struct RView {
+    darb_projected p;
+    const uint32_t *vals, *ranges;
+    const int32_t *overflow;
+    float *image, *final_T;
+    uint32_t *last, *n_contrib;
+    const float *dL;      // upstream gradient [3][H][W] (backward from a checkpoint)
+    const float *target;  // target image [3][H][W] (fused forward+backward)
+    darb_grads2d g2;
+    float loss_scale;     // 1 / (3 W H)
+    int W, H, gx;
+    uint32_t item0, key0;
+};
+
+struct RViews {
+    RView v[kMaxViews];
+    int nv;
+};
+
+struct Cams {
+    Cam c[kMaxViews];
+    int nv;
+};
+
+struct Projs {
+    darb_projected p[kMaxViews];
+};
+
+struct G2s {
+    darb_grads2d g[kMaxViews];
+};
+
 // cam_dev (nullable): camera read from device memory instead of `cam`
 // (whose width/height still size the tile grid)
 hipError_t launch_preprocess(const Cam &cam, const darb_camera *cam_dev, const KParams &kp, int n,
                              const darb_splats &in, const darb_projected &out, hipStream_t s);
 hipError_t launch_preprocess_bwd(const Cam &cam, const KParams &kp, int n, const darb_splats &in,
-                                 const darb_grads2d &g2d, const darb_grads3d &g3d, hipStream_t s);
+                                 const darb_grads2d &g2d, const darb_grads3d &g3d, bool accumulate, hipStream_t s);
+hipError_t launch_preprocess_multi(const Cams &cams, const KParams &kp, int n, const darb_splats &in,
+                                   const Projs &outs, hipStream_t s);
+hipError_t launch_preprocess_bwd_multi(const Cams &cams, const KParams &kp, int n, const darb_splats &in,
+                                       const G2s &g2, const darb_grads3d &g3d, hipStream_t s);
 
 size_t binsort_workspace(int n, int width, int height, int64_t k_capacity);
 int binsort_super_tiles(int width, int height);
@@ -246,12 +308,32 @@ hipError_t launch_bin_sort(const darb_projected &p, int n, int width, int height
                            uint64_t *keys, uint32_t *vals, uint32_t *ranges, int64_t *k_dev, int32_t *overflow_dev,
                            hipStream_t s);
 
-hipError_t launch_raster_fwd(int kind, const darb_projected &p, int n, const uint32_t *vals, const uint32_t *ranges,
-                             const int32_t *overflow, int width, int height, const KParams &kp, const ROpts &o,
-                             float *image, float *final_T, uint32_t *last, uint32_t *n_contrib, hipStream_t s);
-hipError_t launch_raster_bwd(int kind, const darb_projected &p, int n, const uint32_t *vals, const uint32_t *ranges,
-                             const int32_t *overflow, int width, int height, const KParams &kp, const ROpts &o,
-                             const float *dL_dimage, const float *final_T, const uint32_t *last,
-                             const darb_grads2d &g2d, hipStream_t s);
+// Device-count exclusive scan and stable LSD radix sort of (u32 key, u32 value)
+// pairs (8-bit digits over the low `bits` key bits), shared by the binning and
+// the deterministic gradient reduction.  `skip` must point at a device int
+// (nonzero: every kernel returns at once).
+size_t scan_parts_words(uint32_t max_count);
+size_t radix_hist_words(uint32_t max_count);
+hipError_t scan_u32(uint32_t *data, const uint32_t *count_dev, uint32_t max_count, uint32_t *parts,
+                    uint32_t *total_out, const int32_t *skip, hipStream_t s);
+// Sorted pairs end in (kA, vA) when the pass count ceil(bits/8) is even, else in (kB, vB).
+hipError_t radix_sort_pairs(uint32_t *kA, uint32_t *vA, uint32_t *kB, uint32_t *vB, const uint32_t *count_dev,
+                            uint32_t max_count, int bits, uint32_t *hist, uint32_t *parts, const int32_t *skip,
+                            hipStream_t s);
+
+// Raster launchers take one view (nv == 1) or several; `items` = tiles summed
+// over the views.  Deterministic backward: `det_ws` of det_workspace() bytes.
+hipError_t launch_raster_fwd(int kind, const RViews &V, uint32_t items, int n, const KParams &kp, const ROpts &o,
+                             hipStream_t s);
+size_t det_workspace(uint32_t items, uint64_t capacity);
+hipError_t launch_raster_bwd(int kind, const RViews &V, uint32_t items, int n, const KParams &kp, const ROpts &o,
+                             void *det_ws, uint64_t det_capacity, hipStream_t s);
+hipError_t launch_raster_fwdbwd(int kind, int loss, const RViews &V, uint32_t items, int n, const KParams &kp,
+                                const ROpts &o, hipStream_t s);
+hipError_t launch_zero(float *a, size_t n, hipStream_t s);
+
+constexpr uint32_t kLossBlocks = 1024;  // partial sums of the image loss (fixed, so the total is reproducible)
+hipError_t launch_image_loss(int loss, const float *image, const float *target, int width, int height, float scale,
+                             float *dL_dimage, float *loss_dev, float *partials, hipStream_t s);
 
 }  // namespace darb

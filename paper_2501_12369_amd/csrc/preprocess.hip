@@ -112,17 +112,22 @@ __device__ __forceinline__ void sh_grad(float x, float y, float z, const float *
     out[2] = gz;
 }
 
-// Everything the forward computes for one splat and the backward needs again.
+// View-independent geometry of a splat: unit quaternion, rotation, 3D covariance.
+struct Geom {
+    float Rq[9];         // rotation of the splat
+    float qn[4], qinv;   // unit quaternion, 1/|q|
+    float s[3];
+    float Sig[6];        // 3D covariance (xx, xy, xz, yy, yz, zz)
+};
+
+// Everything the forward computes for one splat in one view and the backward
+// needs again.
 struct Proj {
     float t[3];
     float xt, yt;
     bool cx_, cy_;       // Jacobian clamp active in x / y
     float J00, J02, J11, J12;
     float A[6];          // J R_cw, 2x3
-    float Rq[9];         // rotation of the splat
-    float qn[4], qinv;   // unit quaternion, 1/|q|
-    float s[3];
-    float Sig[6];        // 3D covariance (xx, xy, xz, yy, yz, zz)
     float c00, c01, c11; // 2D covariance
     float det;
     float a, b, c;       // conic
@@ -130,24 +135,32 @@ struct Proj {
     int radius;
 };
 
-// Projection of splat i; returns false when culled.
-__device__ __forceinline__ bool project(const Cam &cam, const KParams &kp, int n, int i, const darb_splats &in,
-                                        Proj &P) {
-    float mx = in.means[i], my = in.means[n + i], mz = in.means[2 * n + i];
-    const float *R = cam.R;
-    P.t[0] = fmaf(R[0], mx, fmaf(R[1], my, fmaf(R[2], mz, cam.t[0])));
-    P.t[1] = fmaf(R[3], mx, fmaf(R[4], my, fmaf(R[5], mz, cam.t[1])));
-    P.t[2] = fmaf(R[6], mx, fmaf(R[7], my, fmaf(R[8], mz, cam.t[2])));
-    if (!(P.t[2] > cam.near_z)) return false;
+__device__ __forceinline__ void load_mean(const darb_splats &in, int n, int i, float (&m)[3]) {
+    m[0] = in.means[i];
+    m[1] = in.means[n + i];
+    m[2] = in.means[2 * n + i];
+}
 
+// t = R_cw mu + t_cw; false when the splat is not in front of the near plane.
+__device__ __forceinline__ bool view_depth(const Cam &cam, const float (&m)[3], Proj &P) {
+    const float *R = cam.R;
+    P.t[0] = fmaf(R[0], m[0], fmaf(R[1], m[1], fmaf(R[2], m[2], cam.t[0])));
+    P.t[1] = fmaf(R[3], m[0], fmaf(R[4], m[1], fmaf(R[5], m[2], cam.t[1])));
+    P.t[2] = fmaf(R[6], m[0], fmaf(R[7], m[1], fmaf(R[8], m[2], cam.t[2])));
+    return P.t[2] > cam.near_z;
+}
+
+// Rotation and covariance of splat i; false for a zero quaternion.
+__device__ __forceinline__ bool splat_geom(int n, int i, const darb_splats &in, Geom &G) {
     float qw = in.quats[i], qx = in.quats[n + i], qy = in.quats[2 * n + i], qz = in.quats[3 * n + i];
     float qq = fmaf(qw, qw, fmaf(qx, qx, fmaf(qy, qy, qz * qz)));
+    G.s[0] = in.scales[i]; G.s[1] = in.scales[n + i]; G.s[2] = in.scales[2 * n + i];
     if (!(qq > 0.0f)) return false;
     float qnorm = sqrtf(qq);
-    P.qinv = 1.0f / qnorm;
-    float w = qw * P.qinv, x = qx * P.qinv, y = qy * P.qinv, z = qz * P.qinv;
-    P.qn[0] = w; P.qn[1] = x; P.qn[2] = y; P.qn[3] = z;
-    float *Rq = P.Rq;
+    G.qinv = 1.0f / qnorm;
+    float w = qw * G.qinv, x = qx * G.qinv, y = qy * G.qinv, z = qz * G.qinv;
+    G.qn[0] = w; G.qn[1] = x; G.qn[2] = y; G.qn[3] = z;
+    float *Rq = G.Rq;
     Rq[0] = 1.0f - 2.0f * (y * y + z * z);
     Rq[1] = 2.0f * (x * y - w * z);
     Rq[2] = 2.0f * (x * z + w * y);
@@ -157,17 +170,20 @@ __device__ __forceinline__ bool project(const Cam &cam, const KParams &kp, int n
     Rq[6] = 2.0f * (x * z - w * y);
     Rq[7] = 2.0f * (y * z + w * x);
     Rq[8] = 1.0f - 2.0f * (x * x + y * y);
-
-    P.s[0] = in.scales[i]; P.s[1] = in.scales[n + i]; P.s[2] = in.scales[2 * n + i];
-    float s2[3] = {P.s[0] * P.s[0], P.s[1] * P.s[1], P.s[2] * P.s[2]};
+    float s2[3] = {G.s[0] * G.s[0], G.s[1] * G.s[1], G.s[2] * G.s[2]};
     // Sigma = Rq diag(s^2) Rq^T (upper triangle)
     int k = 0;
     for (int r = 0; r < 3; r++)
         for (int cc = r; cc < 3; cc++) {
-            P.Sig[k++] = fmaf(Rq[r * 3 + 0] * s2[0], Rq[cc * 3 + 0],
+            G.Sig[k++] = fmaf(Rq[r * 3 + 0] * s2[0], Rq[cc * 3 + 0],
                               fmaf(Rq[r * 3 + 1] * s2[1], Rq[cc * 3 + 1], Rq[r * 3 + 2] * s2[2] * Rq[cc * 3 + 2]));
         }
+    return true;
+}
 
+// Projection of a splat in front of the camera (P.t set); false when culled.
+__device__ __forceinline__ bool project_rest(const Cam &cam, const KParams &kp, const Geom &G, Proj &P) {
+    const float *R = cam.R;
     float tz = P.t[2], itz = 1.0f / tz;
     P.xt = P.t[0] * itz;
     P.yt = P.t[1] * itz;
@@ -188,7 +204,7 @@ __device__ __forceinline__ bool project(const Cam &cam, const KParams &kp, int n
         P.A[3 + cc] = fmaf(P.J11, R[3 + cc], P.J12 * R[6 + cc]);
     }
     // M = A Sigma A^T
-    const float *S = P.Sig;  // xx xy xz yy yz zz
+    const float *S = G.Sig;  // xx xy xz yy yz zz
     float AS0[3], AS1[3];
     for (int r = 0; r < 2; r++) {
         const float *a = P.A + 3 * r;
@@ -224,6 +240,17 @@ __device__ __forceinline__ bool project(const Cam &cam, const KParams &kp, int n
     float y1 = fminf(fmaxf(floorf((P.v + r) * 0.0625f) + 1.0f, 0.0f), (float)gy);
     if (!((x1 > x0) & (y1 > y0))) return false;
     return true;
+}
+
+// Projection of splat i in one view (depth test first: a culled splat reads
+// only its mean); false when culled.
+__device__ __forceinline__ bool project(const Cam &cam, const KParams &kp, int n, int i, const darb_splats &in,
+                                        Geom &G, Proj &P) {
+    float m[3];
+    load_mean(in, n, i, m);
+    if (!view_depth(cam, m, P)) return false;
+    if (!splat_geom(n, i, in, G)) return false;
+    return project_rest(cam, kp, G, P);
 }
 
 // SH coefficients of splat i, all loads issued before any use: c[b][ch]
@@ -263,38 +290,29 @@ __device__ __forceinline__ Cam cam_from_device(const darb_camera *c, int width, 
     return m;
 }
 
-template <int DEG>
-__global__ __launch_bounds__(256) void k_preprocess(Cam cam_arg, const darb_camera *cam_dev, KParams kp, int n,
-                                                    darb_splats in, darb_projected out) {
-    constexpr int NB = (DEG + 1) * (DEG + 1);
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const Cam cam = cam_dev ? cam_from_device(cam_dev, cam_arg.width, cam_arg.height) : cam_arg;
-    Proj P;
-    const bool vis = project(cam, kp, n, i, in, P);
-    float col[3] = {0.0f, 0.0f, 0.0f};
-    float op = 0.0f;
-    uint8_t cl = 0;
-    if (vis) {
-        float c[NB][3];
-        load_sh<NB>(in.sh, n, i, c);
-        op = in.opacity[i];
-        float dx = in.means[i] - cam.campos[0], dy = in.means[n + i] - cam.campos[1],
-              dz = in.means[2 * n + i] - cam.campos[2];
-        float il = rsqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
-        float Y[NB];
-        sh_eval<NB>(dx * il, dy * il, dz * il, Y);
+// Colour of a visible splat from its loaded SH coefficients; sets the clamp bits.
+template <int NB>
+__device__ __forceinline__ void sh_colour(const Cam &cam, const float (&m)[3], const float (&c)[NB][3], float (&col)[3],
+                                          uint8_t &cl) {
+    float dx = m[0] - cam.campos[0], dy = m[1] - cam.campos[1], dz = m[2] - cam.campos[2];
+    float il = rsqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+    float Y[NB];
+    sh_eval<NB>(dx * il, dy * il, dz * il, Y);
+    cl = 0;
 #pragma unroll
-        for (int ch = 0; ch < 3; ch++) {
-            float acc = 0.0f;
+    for (int ch = 0; ch < 3; ch++) {
+        float acc = 0.0f;
 #pragma unroll
-            for (int b = 0; b < NB; b++) acc = fmaf(Y[b], c[b][ch], acc);
-            acc += 0.5f;
-            if (acc < 0.0f) cl |= (uint8_t)(1u << ch);
-            col[ch] = fmaxf(acc, 0.0f);
-        }
+        for (int b = 0; b < NB; b++) acc = fmaf(Y[b], c[b][ch], acc);
+        acc += 0.5f;
+        if (acc < 0.0f) cl |= (uint8_t)(1u << ch);
+        col[ch] = fmaxf(acc, 0.0f);
     }
-    // every lane stores (zeros for culled splats): whole-line writes
+}
+
+// Every lane stores (zeros for culled splats): whole-line writes.
+__device__ __forceinline__ void store_proj(const darb_projected &out, int i, bool vis, const Proj &P, float op,
+                                           const float (&col)[3], uint8_t cl) {
     reinterpret_cast<float2 *>(out.xy)[i] = vis ? make_float2(P.u, P.v) : make_float2(0.0f, 0.0f);
     out.depth[i] = vis ? P.t[2] : 0.0f;
     out.radius[i] = vis ? P.radius : 0;
@@ -305,19 +323,70 @@ __global__ __launch_bounds__(256) void k_preprocess(Cam cam_arg, const darb_came
     out.clamped[i] = cl;
 }
 
-// Gradients of one visible splat.  Outputs: dmu, dsc, dq (d/d quaternion as
-// given), and Y, gv such that d/d sh[b][ch] = Y[b] * gv[ch].
+template <int DEG>
+__global__ __launch_bounds__(256) void k_preprocess(Cam cam_arg, const darb_camera *cam_dev, KParams kp, int n,
+                                                    darb_splats in, darb_projected out) {
+    constexpr int NB = (DEG + 1) * (DEG + 1);
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const Cam cam = cam_dev ? cam_from_device(cam_dev, cam_arg.width, cam_arg.height) : cam_arg;
+    Geom G;
+    Proj P;
+    const bool vis = project(cam, kp, n, i, in, G, P);
+    float col[3] = {0.0f, 0.0f, 0.0f};
+    float op = 0.0f;
+    uint8_t cl = 0;
+    if (vis) {
+        float c[NB][3];
+        load_sh<NB>(in.sh, n, i, c);
+        op = in.opacity[i];
+        float m[3];
+        load_mean(in, n, i, m);
+        sh_colour<NB>(cam, m, c, col, cl);
+    }
+    store_proj(out, i, vis, P, op, col, cl);
+}
+
+// Several views: the parameters are read once, the geometry computed once.
+template <int DEG>
+__global__ __launch_bounds__(256) void k_preprocess_multi(Cams cams, KParams kp, int n, darb_splats in, Projs outs) {
+    constexpr int NB = (DEG + 1) * (DEG + 1);
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float m[3];
+    load_mean(in, n, i, m);
+    Geom G;
+    const bool geom = splat_geom(n, i, in, G);
+    float c[NB][3];
+    float op = 0.0f;
+    if (geom) {
+        load_sh<NB>(in.sh, n, i, c);
+        op = in.opacity[i];
+    }
+    for (int v = 0; v < cams.nv; v++) {
+        const Cam &cam = cams.c[v];
+        Proj P;
+        const bool vis = geom && view_depth(cam, m, P) && project_rest(cam, kp, G, P);
+        float col[3] = {0.0f, 0.0f, 0.0f};
+        uint8_t cl = 0;
+        if (vis) sh_colour<NB>(cam, m, c, col, cl);
+        store_proj(outs.p[v], i, vis, P, vis ? op : 0.0f, col, cl);
+    }
+}
+
+// Per-view part of the gradient of one visible splat: the mean (through mu',
+// J and the SH direction), dL/dSigma (full 3x3), and Y, gv such that
+// d/d sh[b][ch] = Y[b] * gv[ch].
 template <int NB>
-__device__ __forceinline__ void splat_bwd(const Cam &cam, const KParams &kp, int n, int i, const darb_splats &in,
-                                          const darb_grads2d &g2, const Proj &P, float (&dmu)[3], float (&dsc)[3],
-                                          float (&dqo)[4], float (&Y)[NB], float (&gvo)[3]) {
-    float csh[NB][3];
-    load_sh<NB>(in.sh, n, i, csh);
+__device__ __forceinline__ void splat_bwd_view(const Cam &cam, const KParams &kp, int i, const float (&m)[3],
+                                               const float (&csh)[NB][3], const darb_grads2d &g2, const Geom &G,
+                                               const Proj &P, float (&dmu)[3], float (&dS)[9], float (&Y)[NB],
+                                               float (&gvo)[3]) {
     float grgb[3] = {g2.rgb[3 * i], g2.rgb[3 * i + 1], g2.rgb[3 * i + 2]};
     dmu[0] = dmu[1] = dmu[2] = 0.0f;
 
     // ---- colour -> SH coefficients and view direction
-    float vx = in.means[i] - cam.campos[0], vy = in.means[n + i] - cam.campos[1], vz = in.means[2 * n + i] - cam.campos[2];
+    float vx = m[0] - cam.campos[0], vy = m[1] - cam.campos[1], vz = m[2] - cam.campos[2];
     float il = rsqrtf(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
     float dx = vx * il, dy = vy * il, dz = vz * il;
     sh_eval<NB>(dx, dy, dz, Y);
@@ -364,10 +433,9 @@ __device__ __forceinline__ void splat_bwd(const Cam &cam, const KParams &kp, int
         dMA0[cc] = fmaf(m00, A[cc], m01 * A[3 + cc]);
         dMA1[cc] = fmaf(m01, A[cc], m11 * A[3 + cc]);
     }
-    float dS[9];
     for (int r = 0; r < 3; r++)
         for (int cc = 0; cc < 3; cc++) dS[r * 3 + cc] = fmaf(A[r], dMA0[cc], A[3 + r] * dMA1[cc]);
-    const float *Sg = P.Sig;
+    const float *Sg = G.Sig;
     float Sf[9] = {Sg[0], Sg[1], Sg[2], Sg[1], Sg[3], Sg[4], Sg[2], Sg[4], Sg[5]};
     float dA[6];
     for (int cc = 0; cc < 3; cc++) {
@@ -399,21 +467,25 @@ __device__ __forceinline__ void splat_bwd(const Cam &cam, const KParams &kp, int
     dmu[0] += fmaf(R[0], dtx, fmaf(R[3], dty, R[6] * dtz));
     dmu[1] += fmaf(R[1], dtx, fmaf(R[4], dty, R[7] * dtz));
     dmu[2] += fmaf(R[2], dtx, fmaf(R[5], dty, R[8] * dtz));
+}
 
-    // ---- Sigma = Mq Mq^T, Mq = Rq diag(s): dMq = 2 dSigma Mq; ds_j = sum_r dMq_rj Rq_rj; dRq_rj = dMq_rj s_j
-    const float *Rq = P.Rq;
+// Sigma = Mq Mq^T, Mq = Rq diag(s): dMq = 2 dSigma Mq; ds_j = sum_r dMq_rj Rq_rj;
+// dRq_rj = dMq_rj s_j; then the rotation-matrix gradient to the quaternion
+// (through the normalisation).
+__device__ __forceinline__ void geom_bwd(const Geom &G, const float (&dS)[9], float (&dsc)[3], float (&dqo)[4]) {
+    const float *Rq = G.Rq;
     float dR[9];
     for (int cc = 0; cc < 3; cc++) {
         float acc = 0.0f;
         for (int r = 0; r < 3; r++) {
-            float dm = 2.0f * fmaf(dS[r * 3 + 0], Rq[0 * 3 + cc] * P.s[cc],
-                                   fmaf(dS[r * 3 + 1], Rq[1 * 3 + cc] * P.s[cc], dS[r * 3 + 2] * Rq[2 * 3 + cc] * P.s[cc]));
+            float dm = 2.0f * fmaf(dS[r * 3 + 0], Rq[0 * 3 + cc] * G.s[cc],
+                                   fmaf(dS[r * 3 + 1], Rq[1 * 3 + cc] * G.s[cc], dS[r * 3 + 2] * Rq[2 * 3 + cc] * G.s[cc]));
             acc = fmaf(dm, Rq[r * 3 + cc], acc);
-            dR[r * 3 + cc] = dm * P.s[cc];
+            dR[r * 3 + cc] = dm * G.s[cc];
         }
         dsc[cc] = acc;
     }
-    float w = P.qn[0], x = P.qn[1], y = P.qn[2], z = P.qn[3];
+    float w = G.qn[0], x = G.qn[1], y = G.qn[2], z = G.qn[3];
     float dq0 = 2.0f * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
     float dq1 = 2.0f * (y * dR[1] + z * dR[2] + y * dR[3] - 2.0f * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] -
                         2.0f * x * dR[8]);
@@ -422,69 +494,152 @@ __device__ __forceinline__ void splat_bwd(const Cam &cam, const KParams &kp, int
     float dq3 = 2.0f * (-2.0f * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.0f * z * dR[4] + y * dR[5] +
                         x * dR[6] + y * dR[7]);
     float qd = fmaf(dq0, w, fmaf(dq1, x, fmaf(dq2, y, dq3 * z)));
-    dqo[0] = (dq0 - w * qd) * P.qinv;
-    dqo[1] = (dq1 - x * qd) * P.qinv;
-    dqo[2] = (dq2 - y * qd) * P.qinv;
-    dqo[3] = (dq3 - z * qd) * P.qinv;
+    dqo[0] = (dq0 - w * qd) * G.qinv;
+    dqo[1] = (dq1 - x * qd) * G.qinv;
+    dqo[2] = (dq2 - y * qd) * G.qinv;
+    dqo[3] = (dq3 - z * qd) * G.qinv;
+}
+
+// Gradients of one splat, accumulated over views by the callers.
+struct Grad3 {
+    float dmu[3], dsc[3], dq[4], dop;
+};
+
+template <int NB>
+__device__ __forceinline__ void store_grads(const darb_grads3d &g3, int n, int i, const Grad3 &g,
+                                            const float (&gsh)[NB][3], bool accumulate) {
+    // every lane stores (zeros for culled splats): whole-line writes
+    auto put = [&](float *p, size_t idx, float v) { p[idx] = accumulate ? p[idx] + v : v; };
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        put(g3.means, (size_t)c * n + i, g.dmu[c]);
+        put(g3.scales, (size_t)c * n + i, g.dsc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; c++) put(g3.quats, (size_t)c * n + i, g.dq[c]);
+    put(g3.opacity, i, g.dop);
+#pragma unroll
+    for (int b = 0; b < NB; b++)
+#pragma unroll
+        for (int ch = 0; ch < 3; ch++) put(g3.sh, (size_t)(b * 3 + ch) * n + i, gsh[b][ch]);
 }
 
 template <int DEG>
 __global__ __launch_bounds__(256) void k_preprocess_bwd(Cam cam, KParams kp, int n, darb_splats in, darb_grads2d g2,
-                                                        darb_grads3d g3) {
+                                                        darb_grads3d g3, int accumulate) {
     constexpr int NB = (DEG + 1) * (DEG + 1);
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    Geom G;
     Proj P;
-    const bool vis = project(cam, kp, n, i, in, P);
-    float dmu[3] = {0.f, 0.f, 0.f}, dsc[3] = {0.f, 0.f, 0.f}, dq[4] = {0.f, 0.f, 0.f, 0.f}, gv[3] = {0.f, 0.f, 0.f};
-    float Y[NB];
+    const bool vis = project(cam, kp, n, i, in, G, P);
+    Grad3 g = {};
+    float gsh[NB][3];
 #pragma unroll
-    for (int b = 0; b < NB; b++) Y[b] = 0.0f;
-    float dop = 0.0f;
+    for (int b = 0; b < NB; b++) gsh[b][0] = gsh[b][1] = gsh[b][2] = 0.0f;
     if (vis) {
-        splat_bwd<NB>(cam, kp, n, i, in, g2, P, dmu, dsc, dq, Y, gv);
-        dop = g2.opacity[i];
+        float m[3];
+        load_mean(in, n, i, m);
+        float csh[NB][3];
+        load_sh<NB>(in.sh, n, i, csh);
+        float dS[9], Y[NB], gv[3];
+        splat_bwd_view<NB>(cam, kp, i, m, csh, g2, G, P, g.dmu, dS, Y, gv);
+        geom_bwd(G, dS, g.dsc, g.dq);
+        g.dop = g2.opacity[i];
+#pragma unroll
+        for (int b = 0; b < NB; b++)
+#pragma unroll
+            for (int ch = 0; ch < 3; ch++) gsh[b][ch] = Y[b] * gv[ch];
     }
-    // every lane stores (zeros for culled splats): whole-line writes
+    store_grads<NB>(g3, n, i, g, gsh, accumulate != 0);
+}
+
+// Sum over views, in view order, of the single-view gradients (each view's
+// contribution computed exactly as the single-view kernel computes it, then
+// added), with the parameters read once and the result written once.
+template <int DEG>
+__global__ __launch_bounds__(256) void k_preprocess_bwd_multi(Cams cams, KParams kp, int n, darb_splats in, G2s g2,
+                                                              darb_grads3d g3) {
+    constexpr int NB = (DEG + 1) * (DEG + 1);
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float m[3];
+    load_mean(in, n, i, m);
+    Geom G;
+    const bool geom = splat_geom(n, i, in, G);
+    Grad3 tot = {};
+    float gsh[NB][3];
 #pragma unroll
-    for (int c = 0; c < 3; c++) {
-        g3.means[(size_t)c * n + i] = dmu[c];
-        g3.scales[(size_t)c * n + i] = dsc[c];
+    for (int b = 0; b < NB; b++) gsh[b][0] = gsh[b][1] = gsh[b][2] = 0.0f;
+    if (geom) {
+        float csh[NB][3];
+        load_sh<NB>(in.sh, n, i, csh);
+        for (int v = 0; v < cams.nv; v++) {
+            const Cam &cam = cams.c[v];
+            Proj P;
+            if (!(view_depth(cam, m, P) && project_rest(cam, kp, G, P))) continue;
+            Grad3 g;
+            float dS[9], Y[NB], gv[3];
+            splat_bwd_view<NB>(cam, kp, i, m, csh, g2.g[v], G, P, g.dmu, dS, Y, gv);
+            geom_bwd(G, dS, g.dsc, g.dq);
+            g.dop = g2.g[v].opacity[i];
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                tot.dmu[c] += g.dmu[c];
+                tot.dsc[c] += g.dsc[c];
+            }
+#pragma unroll
+            for (int c = 0; c < 4; c++) tot.dq[c] += g.dq[c];
+            tot.dop += g.dop;
+#pragma unroll
+            for (int b = 0; b < NB; b++)
+#pragma unroll
+                for (int ch = 0; ch < 3; ch++) gsh[b][ch] += Y[b] * gv[ch];
+        }
     }
-#pragma unroll
-    for (int c = 0; c < 4; c++) g3.quats[(size_t)c * n + i] = dq[c];
-    g3.opacity[i] = dop;
-#pragma unroll
-    for (int b = 0; b < NB; b++)
-#pragma unroll
-        for (int ch = 0; ch < 3; ch++) g3.sh[(size_t)(b * 3 + ch) * n + i] = Y[b] * gv[ch];
+    store_grads<NB>(g3, n, i, tot, gsh, false);
 }
 
 }  // namespace
+
+#define DARB_DEG_SWITCH(deg, K, grid, s, ...)                                          \
+    switch (deg) {                                                                    \
+    case 0: hipLaunchKernelGGL(K<0>, grid, dim3(256), 0, s, __VA_ARGS__); break;      \
+    case 1: hipLaunchKernelGGL(K<1>, grid, dim3(256), 0, s, __VA_ARGS__); break;      \
+    case 2: hipLaunchKernelGGL(K<2>, grid, dim3(256), 0, s, __VA_ARGS__); break;      \
+    default: hipLaunchKernelGGL(K<3>, grid, dim3(256), 0, s, __VA_ARGS__); break;     \
+    }
 
 hipError_t launch_preprocess(const Cam &cam, const darb_camera *cam_dev, const KParams &kp, int n,
                              const darb_splats &in, const darb_projected &out, hipStream_t s) {
     if (n == 0) return hipSuccess;
     dim3 grid((n + 255) / 256);
-    switch (in.sh_degree) {
-    case 0: hipLaunchKernelGGL(k_preprocess<0>, grid, dim3(256), 0, s, cam, cam_dev, kp, n, in, out); break;
-    case 1: hipLaunchKernelGGL(k_preprocess<1>, grid, dim3(256), 0, s, cam, cam_dev, kp, n, in, out); break;
-    case 2: hipLaunchKernelGGL(k_preprocess<2>, grid, dim3(256), 0, s, cam, cam_dev, kp, n, in, out); break;
-    default: hipLaunchKernelGGL(k_preprocess<3>, grid, dim3(256), 0, s, cam, cam_dev, kp, n, in, out); break;
-    }
+    DARB_DEG_SWITCH(in.sh_degree, k_preprocess, grid, s, cam, cam_dev, kp, n, in, out)
+    return hipGetLastError();
+}
+
+hipError_t launch_preprocess_multi(const Cams &cams, const KParams &kp, int n, const darb_splats &in,
+                                   const Projs &outs, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    dim3 grid((n + 255) / 256);
+    DARB_DEG_SWITCH(in.sh_degree, k_preprocess_multi, grid, s, cams, kp, n, in, outs)
     return hipGetLastError();
 }
 
 hipError_t launch_preprocess_bwd(const Cam &cam, const KParams &kp, int n, const darb_splats &in,
-                                 const darb_grads2d &g2d, const darb_grads3d &g3d, hipStream_t s) {
+                                 const darb_grads2d &g2d, const darb_grads3d &g3d, bool accumulate, hipStream_t s) {
     if (n == 0) return hipSuccess;
     dim3 grid((n + 255) / 256);
-    switch (in.sh_degree) {
-    case 0: hipLaunchKernelGGL(k_preprocess_bwd<0>, grid, dim3(256), 0, s, cam, kp, n, in, g2d, g3d); break;
-    case 1: hipLaunchKernelGGL(k_preprocess_bwd<1>, grid, dim3(256), 0, s, cam, kp, n, in, g2d, g3d); break;
-    case 2: hipLaunchKernelGGL(k_preprocess_bwd<2>, grid, dim3(256), 0, s, cam, kp, n, in, g2d, g3d); break;
-    default: hipLaunchKernelGGL(k_preprocess_bwd<3>, grid, dim3(256), 0, s, cam, kp, n, in, g2d, g3d); break;
-    }
+    const int acc = accumulate ? 1 : 0;
+    DARB_DEG_SWITCH(in.sh_degree, k_preprocess_bwd, grid, s, cam, kp, n, in, g2d, g3d, acc)
+    return hipGetLastError();
+}
+
+hipError_t launch_preprocess_bwd_multi(const Cams &cams, const KParams &kp, int n, const darb_splats &in,
+                                       const G2s &g2, const darb_grads3d &g3d, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    dim3 grid((n + 255) / 256);
+    DARB_DEG_SWITCH(in.sh_degree, k_preprocess_bwd_multi, grid, s, cams, kp, n, in, g2, g3d)
     return hipGetLastError();
 }
 

@@ -17,7 +17,18 @@
 // largest checkpointed position down, recomputing alpha with the same device
 // function, T <- T / (1 - alpha), and accumulating the per-splat partial
 // gradients of its four pixels in registers; per splat the wave sums the nine
-// partials with DPP row reductions and one lane issues nine float atomics.
+// partials with DPP row reductions and lane s of the batch keeps the sums of
+// the batch's s-th instance.  At the end of a batch the lanes either issue
+// their float atomics together (nine atomic instructions per 64 instances), or,
+// in the deterministic mode, store them as one partial per (tile, splat); a
+// stable sort by splat and a per-splat sum in tile order finish the reduction.
+//
+// Several views run in one launch over the concatenated tiles of all views
+// (work item -> view by the views' first items); the fused kernel composites a
+// tile, takes the per-pixel loss gradient in registers and runs the backward
+// walk of the same tile at once.
+#include <algorithm>
+
 #include "common.h"
 
 namespace darb {
@@ -69,39 +80,64 @@ __device__ __forceinline__ Rec load_rec(const darb_projected &p, const uint32_t 
     return R;
 }
 
+// A launch over one view (small kernel arguments) or over several.
+struct OneView {
+    RView v;
+    __device__ __forceinline__ const RView &get(uint32_t item, int &tile) const {
+        tile = (int)item;
+        return v;
+    }
+    __device__ __forceinline__ darb_grads2d grads(uint32_t) const { return v.g2; }
+};
+
+struct ManyViews {
+    RViews a;
+    __device__ __forceinline__ const RView &get(uint32_t item, int &tile) const {
+        int vi = 0;
+        for (int k = 1; k < a.nv; k++) vi = (item >= a.v[k].item0) ? k : vi;
+        tile = (int)(item - a.v[vi].item0);
+        return a.v[vi];
+    }
+    // per-lane view index: select among the views (uniform loads only)
+    __device__ __forceinline__ darb_grads2d grads(uint32_t vi) const {
+        darb_grads2d g = a.v[0].g2;
+        for (int k = 1; k < a.nv; k++)
+            if ((uint32_t)k == vi) g = a.v[k].g2;
+        return g;
+    }
+};
+
+// Forward state of a lane's four pixels.
+struct PixF {
+    float T[kPix], C0[kPix], C1[kPix], C2[kPix];
+    uint32_t lst[kPix], cnt[kPix];
+};
+
 template <int KIND>
-__global__ __launch_bounds__(64) void k_raster_fwd(darb_projected p, const uint32_t *__restrict__ vals,
-                                                   const uint32_t *__restrict__ ranges, const int32_t *overflow, int n,
-                                                   int W, int H, int gx, KParams kp, ROpts o, float *__restrict__ image,
-                                                   float *__restrict__ final_T, uint32_t *__restrict__ last,
-                                                   uint32_t *__restrict__ n_contrib) {
-    if (overflow && *overflow) return;
-    const int tile = blockIdx.x;
-    const int tx = tile % gx, ty = tile / gx;
+__device__ __forceinline__ void tile_fwd(const RView &V, int tile, int n, const KParams &kp, const ROpts &o, PixF &F) {
+    const int tx = tile % V.gx, ty = tile / V.gx;
     const int lane = threadIdx.x;
     const int ix = tx * kTile + (lane & 15);
     const int iy0 = ty * kTile + (lane >> 4);
     const float px = (float)ix;
     float py[kPix];
     bool done[kPix];
-    float T[kPix], C0[kPix], C1[kPix], C2[kPix];
-    uint32_t lst[kPix], cnt[kPix];
 #pragma unroll
     for (int k = 0; k < kPix; k++) {
         int iy = iy0 + 4 * k;
         py[k] = (float)iy;
-        done[k] = !(ix < W && iy < H);
-        T[k] = 1.0f;
-        C0[k] = C1[k] = C2[k] = 0.0f;
-        lst[k] = kNone;
-        cnt[k] = 0;
+        done[k] = !(ix < V.W && iy < V.H);
+        F.T[k] = 1.0f;
+        F.C0[k] = F.C1[k] = F.C2[k] = 0.0f;
+        F.lst[k] = kNone;
+        F.cnt[k] = 0;
     }
-    const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+    const uint32_t start = V.ranges[2 * tile], end = V.ranges[2 * tile + 1];
     for (uint32_t base = start; base < end; base += 64) {
         bool alldone = done[0] & done[1] & done[2] & done[3];
         if (__ballot(!alldone) == 0) break;
         uint32_t j = base + lane;
-        Rec R = load_rec(p, vals, j, j < end, n, kp.e_max, (float)(tx * kTile), (float)(ty * kTile));
+        Rec R = load_rec(V.p, V.vals, j, j < end, n, kp.e_max, (float)(tx * kTile), (float)(ty * kTile));
         int nb = (int)min(64u, end - base);
         for (int s = 0; s < nb; s++) {
             if (!readlane_i(R.hit, s)) continue;  // footprint misses this tile (uniform)
@@ -114,88 +150,123 @@ __global__ __launch_bounds__(64) void k_raster_fwd(darb_projected p, const uint3
             for (int k = 0; k < kPix; k++) {
                 Pair q = eval_pair<KIND>(sx, sy, sa, sb, sc, so, px, py[k], kp, o.alpha_min, o.alpha_max);
                 bool ok = q.ok & !done[k];
-                float Tn = T[k] * (1.0f - q.alpha);
+                float Tn = F.T[k] * (1.0f - q.alpha);
                 bool stop = ok & (Tn < o.t_min);
                 ok = ok & !stop;
                 done[k] = done[k] | stop;
-                float aT = ok ? q.alpha * T[k] : 0.0f;
-                C0[k] = fmaf(aT, sr, C0[k]);
-                C1[k] = fmaf(aT, sg, C1[k]);
-                C2[k] = fmaf(aT, sbl, C2[k]);
-                T[k] = ok ? Tn : T[k];
-                lst[k] = ok ? pos : lst[k];
-                cnt[k] += ok ? 1u : 0u;
+                float aT = ok ? q.alpha * F.T[k] : 0.0f;
+                F.C0[k] = fmaf(aT, sr, F.C0[k]);
+                F.C1[k] = fmaf(aT, sg, F.C1[k]);
+                F.C2[k] = fmaf(aT, sbl, F.C2[k]);
+                F.T[k] = ok ? Tn : F.T[k];
+                F.lst[k] = ok ? pos : F.lst[k];
+                F.cnt[k] += ok ? 1u : 0u;
             }
-        }
-    }
-    const size_t plane = (size_t)W * H;
-#pragma unroll
-    for (int k = 0; k < kPix; k++) {
-        int iy = iy0 + 4 * k;
-        if (ix < W && iy < H) {
-            size_t pidx = (size_t)iy * W + ix;
-            image[pidx] = fmaf(T[k], o.bg0, C0[k]);
-            image[plane + pidx] = fmaf(T[k], o.bg1, C1[k]);
-            image[2 * plane + pidx] = fmaf(T[k], o.bg2, C2[k]);
-            final_T[pidx] = T[k];
-            last[pidx] = lst[k];
-            if (n_contrib) n_contrib[pidx] = cnt[k];
         }
     }
 }
 
-template <int KIND>
-__global__ __launch_bounds__(64) void k_raster_bwd(darb_projected p, const uint32_t *__restrict__ vals,
-                                                   const uint32_t *__restrict__ ranges, const int32_t *overflow, int n,
-                                                   int W, int H, int gx, KParams kp, ROpts o,
-                                                   const float *__restrict__ dL_dimg,
-                                                   const float *__restrict__ final_T,
-                                                   const uint32_t *__restrict__ last, darb_grads2d g2) {
-    if (overflow && *overflow) return;
-    const int tile = blockIdx.x;
-    const int tx = tile % gx, ty = tile / gx;
+__device__ __forceinline__ void store_fwd(const RView &V, int tile, const PixF &F, const ROpts &o) {
+    const int tx = tile % V.gx, ty = tile / V.gx;
+    const int lane = threadIdx.x;
+    const int ix = tx * kTile + (lane & 15);
+    const int iy0 = ty * kTile + (lane >> 4);
+    const size_t plane = (size_t)V.W * V.H;
+#pragma unroll
+    for (int k = 0; k < kPix; k++) {
+        int iy = iy0 + 4 * k;
+        if (ix < V.W && iy < V.H) {
+            size_t pidx = (size_t)iy * V.W + ix;
+            V.image[pidx] = fmaf(F.T[k], o.bg0, F.C0[k]);
+            V.image[plane + pidx] = fmaf(F.T[k], o.bg1, F.C1[k]);
+            V.image[2 * plane + pidx] = fmaf(F.T[k], o.bg2, F.C2[k]);
+            if (V.final_T) V.final_T[pidx] = F.T[k];
+            if (V.last) V.last[pidx] = F.lst[k];
+            if (V.n_contrib) V.n_contrib[pidx] = F.cnt[k];
+        }
+    }
+}
+
+// Storage of the deterministic mode: partial c of 9 planes (stride cap), its
+// key (view * n + splat) and its own index; trav_off[item] = first partial of
+// the work item.
+struct DetOut {
+    float *parts;
+    uint32_t *ekey, *eval;
+    const uint32_t *trav_off;
+    uint32_t cap;
+};
+
+// End (last position + 1) of the tile's walk: the largest checkpointed
+// position of its pixels, clamped to the tile's range.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off, 64));
+    return v;
+}
+
+// Writes nine wave-uniform values into lane `lane` of nine per-lane
+// accumulators (v_writelane_b32, independent of EXEC).  Written as one asm block
+// so that the reductions producing the values stay in wave-uniform code: a
+// select on (lane == s) may be turned into a one-lane branch, and cross-lane
+// operations sunk into it would see a single active lane.
+__device__ __forceinline__ void writelane9(float (&m)[9], const float (&u)[9], int lane) {
+    // the lane select goes through M0: one VALU instruction reads one SGPR
+    asm volatile(
+        "s_mov_b32 m0, %18\n\t"
+        "s_nop 4\n\t"
+        "v_writelane_b32 %0, %9, m0\n\t"
+        "v_writelane_b32 %1, %10, m0\n\t"
+        "v_writelane_b32 %2, %11, m0\n\t"
+        "v_writelane_b32 %3, %12, m0\n\t"
+        "v_writelane_b32 %4, %13, m0\n\t"
+        "v_writelane_b32 %5, %14, m0\n\t"
+        "v_writelane_b32 %6, %15, m0\n\t"
+        "v_writelane_b32 %7, %16, m0\n\t"
+        "v_writelane_b32 %8, %17, m0"
+        : "+v"(m[0]), "+v"(m[1]), "+v"(m[2]), "+v"(m[3]), "+v"(m[4]), "+v"(m[5]), "+v"(m[6]), "+v"(m[7]),
+          "+v"(m[8])
+        : "s"(u[0]), "s"(u[1]), "s"(u[2]), "s"(u[3]), "s"(u[4]), "s"(u[5]), "s"(u[6]), "s"(u[7]), "s"(u[8]),
+          "s"(lane)
+        : "m0");
+}
+
+// Backward walk of one tile.  T: final transmittance per pixel (running, so
+// modified); lp: last blended position + 1 (0 = none); G: dL/dI per pixel.
+template <int KIND, bool DET>
+__device__ __forceinline__ void tile_bwd(const RView &V, int tile, uint32_t item, int n, const KParams &kp,
+                                         const ROpts &o, float (&T)[kPix], const uint32_t (&lp)[kPix],
+                                         const float (&G0)[kPix], const float (&G1)[kPix], const float (&G2)[kPix],
+                                         const DetOut &d) {
+    const int tx = tile % V.gx, ty = tile / V.gx;
     const int lane = threadIdx.x;
     const int ix = tx * kTile + (lane & 15);
     const int iy0 = ty * kTile + (lane >> 4);
     const float px = (float)ix;
-    const size_t plane = (size_t)W * H;
-    float py[kPix], T[kPix], S0[kPix], S1[kPix], S2[kPix], G0[kPix], G1[kPix], G2[kPix];
-    uint32_t lp[kPix];  // last position + 1 (0 = no contributor or no pixel)
+    float py[kPix], S0[kPix], S1[kPix], S2[kPix];
     uint32_t maxl = 0;
 #pragma unroll
     for (int k = 0; k < kPix; k++) {
-        int iy = iy0 + 4 * k;
-        py[k] = (float)iy;
-        lp[k] = 0;
-        T[k] = 0.0f;
-        S0[k] = S1[k] = S2[k] = G0[k] = G1[k] = G2[k] = 0.0f;
-        if (ix < W && iy < H) {
-            size_t pidx = (size_t)iy * W + ix;
-            uint32_t l = last[pidx];
-            if (l != kNone) {
-                lp[k] = l + 1;
-                T[k] = final_T[pidx];
-                S0[k] = T[k] * o.bg0;
-                S1[k] = T[k] * o.bg1;
-                S2[k] = T[k] * o.bg2;
-                G0[k] = dL_dimg[pidx];
-                G1[k] = dL_dimg[plane + pidx];
-                G2[k] = dL_dimg[2 * plane + pidx];
-            }
-        }
+        py[k] = (float)(iy0 + 4 * k);
+        S0[k] = T[k] * o.bg0;
+        S1[k] = T[k] * o.bg1;
+        S2[k] = T[k] * o.bg2;
         maxl = max(maxl, lp[k]);
     }
-    // wave maximum of the end positions
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) maxl = max(maxl, (uint32_t)__shfl_xor((int)maxl, off, 64));
-    const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+    maxl = wave_max_u32(maxl);
+    const uint32_t start = V.ranges[2 * tile], end = V.ranges[2 * tile + 1];
     maxl = min(maxl, end);  // a checkpoint always points inside its tile's range
     if (maxl == 0 || maxl <= start) return;
+    uint32_t c0 = 0;
+    if constexpr (DET) c0 = d.trav_off[item];
     // walk positions maxl-1 down to start in batches of 64
     for (uint32_t hi = maxl; hi > start;) {
         uint32_t cntb = min(64u, hi - start);
         uint32_t j = hi - 1 - lane;
-        Rec R = load_rec(p, vals, j, (uint32_t)lane < cntb, n, kp.e_max, (float)(tx * kTile), (float)(ty * kTile));
+        Rec R = load_rec(V.p, V.vals, j, (uint32_t)lane < cntb, n, kp.e_max, (float)(tx * kTile), (float)(ty * kTile));
+        // lane s keeps the reduced partials of the batch's s-th instance
+        float m[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        uint64_t touched = 0;  // lanes whose instance received a contribution (uniform)
         for (int s = 0; s < (int)cntb; s++) {
             if (!readlane_i(R.hit, s)) continue;  // footprint misses this tile (uniform)
             float sx = readlane_f(R.x, s), sy = readlane_f(R.y, s);
@@ -233,30 +304,185 @@ __global__ __launch_bounds__(64) void k_raster_bwd(darb_projected p, const uint3
                 T[k] = ok ? Tb : T[k];
             }
             if (__ballot(any) != 0) {
-                gxy0 = wave_sum_to_lane63(gxy0);
-                gxy1 = wave_sum_to_lane63(gxy1);
-                gca = wave_sum_to_lane63(gca);
-                gcb = wave_sum_to_lane63(gcb);
-                gcc = wave_sum_to_lane63(gcc);
-                gop = wave_sum_to_lane63(gop);
-                gr = wave_sum_to_lane63(gr);
-                gg = wave_sum_to_lane63(gg);
-                gbl = wave_sum_to_lane63(gbl);
-                uint32_t id = (uint32_t)readlane_i((int)R.id, s);
-                if (lane == 63 && id < (uint32_t)n) {
-                    atomicAdd(&g2.xy[2 * id], gxy0);
-                    atomicAdd(&g2.xy[2 * id + 1], gxy1);
-                    atomicAdd(&g2.conic[3 * id], gca);
-                    atomicAdd(&g2.conic[3 * id + 1], gcb);
-                    atomicAdd(&g2.conic[3 * id + 2], gcc);
-                    atomicAdd(&g2.opacity[id], gop);
-                    atomicAdd(&g2.rgb[3 * id], gr);
-                    atomicAdd(&g2.rgb[3 * id + 1], gg);
-                    atomicAdd(&g2.rgb[3 * id + 2], gbl);
-                }
+                const float u[9] = {readlane_f(wave_sum_to_lane63(gxy0), 63), readlane_f(wave_sum_to_lane63(gxy1), 63),
+                                    readlane_f(wave_sum_to_lane63(gca), 63),  readlane_f(wave_sum_to_lane63(gcb), 63),
+                                    readlane_f(wave_sum_to_lane63(gcc), 63),  readlane_f(wave_sum_to_lane63(gop), 63),
+                                    readlane_f(wave_sum_to_lane63(gr), 63),   readlane_f(wave_sum_to_lane63(gg), 63),
+                                    readlane_f(wave_sum_to_lane63(gbl), 63)};
+                writelane9(m, u, s);
+                touched |= 1ull << s;
+            }
+        }
+        if constexpr (DET) {
+            if ((uint32_t)lane < cntb) {
+                const uint32_t c = c0 + (j - start);
+                const size_t C = d.cap;
+#pragma unroll
+                for (int k = 0; k < 9; k++) d.parts[k * C + c] = m[k];
+                d.ekey[c] = R.id < (uint32_t)n ? V.key0 + R.id : kNone;
+                d.eval[c] = c;
+            }
+        } else {
+            const uint32_t id = R.id;
+            if (((touched >> lane) & 1ull) && id < (uint32_t)n) {
+                atomicAdd(&V.g2.xy[2 * id], m[0]);
+                atomicAdd(&V.g2.xy[2 * id + 1], m[1]);
+                atomicAdd(&V.g2.conic[3 * id], m[2]);
+                atomicAdd(&V.g2.conic[3 * id + 1], m[3]);
+                atomicAdd(&V.g2.conic[3 * id + 2], m[4]);
+                atomicAdd(&V.g2.opacity[id], m[5]);
+                atomicAdd(&V.g2.rgb[3 * id], m[6]);
+                atomicAdd(&V.g2.rgb[3 * id + 1], m[7]);
+                atomicAdd(&V.g2.rgb[3 * id + 2], m[8]);
             }
         }
         hi -= cntb;
+    }
+}
+
+// Checkpoint of a lane's four pixels: final T, last + 1, dL/dI.
+__device__ __forceinline__ void load_checkpoint(const RView &V, int tile, float (&T)[kPix], uint32_t (&lp)[kPix],
+                                                float (&G0)[kPix], float (&G1)[kPix], float (&G2)[kPix]) {
+    const int tx = tile % V.gx, ty = tile / V.gx;
+    const int lane = threadIdx.x;
+    const int ix = tx * kTile + (lane & 15);
+    const int iy0 = ty * kTile + (lane >> 4);
+    const size_t plane = (size_t)V.W * V.H;
+#pragma unroll
+    for (int k = 0; k < kPix; k++) {
+        int iy = iy0 + 4 * k;
+        lp[k] = 0;
+        T[k] = 0.0f;
+        G0[k] = G1[k] = G2[k] = 0.0f;
+        if (ix < V.W && iy < V.H) {
+            size_t pidx = (size_t)iy * V.W + ix;
+            uint32_t l = V.last[pidx];
+            if (l != kNone) {
+                lp[k] = l + 1;
+                T[k] = V.final_T[pidx];
+                G0[k] = V.dL[pidx];
+                G1[k] = V.dL[plane + pidx];
+                G2[k] = V.dL[2 * plane + pidx];
+            }
+        }
+    }
+}
+
+template <int KIND, class VS>
+__global__ __launch_bounds__(64) void k_raster_fwd(VS A, int n, KParams kp, ROpts o) {
+    int tile;
+    const RView &V = A.get(blockIdx.x, tile);
+    if (V.overflow && *V.overflow) return;
+    PixF F;
+    tile_fwd<KIND>(V, tile, n, kp, o, F);
+    store_fwd(V, tile, F, o);
+}
+
+template <int KIND, bool DET, class VS>
+__global__ __launch_bounds__(64) void k_raster_bwd(VS A, int n, KParams kp, ROpts o, DetOut d) {
+    int tile;
+    const RView &V = A.get(blockIdx.x, tile);
+    if (V.overflow && *V.overflow) return;
+    float T[kPix], G0[kPix], G1[kPix], G2[kPix];
+    uint32_t lp[kPix];
+    load_checkpoint(V, tile, T, lp, G0, G1, G2);
+    tile_bwd<KIND, DET>(V, tile, blockIdx.x, n, kp, o, T, lp, G0, G1, G2, d);
+}
+
+// Forward, per-pixel loss gradient and backward of one tile in one workgroup.
+template <int KIND, int LOSS, class VS>
+__global__ __launch_bounds__(64) void k_raster_fwdbwd(VS A, int n, KParams kp, ROpts o) {
+    int tile;
+    const RView &V = A.get(blockIdx.x, tile);
+    if (V.overflow && *V.overflow) return;
+    PixF F;
+    tile_fwd<KIND>(V, tile, n, kp, o, F);
+    store_fwd(V, tile, F, o);
+    const int tx = tile % V.gx, ty = tile / V.gx;
+    const int lane = threadIdx.x;
+    const int ix = tx * kTile + (lane & 15);
+    const int iy0 = ty * kTile + (lane >> 4);
+    const size_t plane = (size_t)V.W * V.H;
+    float G0[kPix], G1[kPix], G2[kPix];
+    uint32_t lp[kPix];
+#pragma unroll
+    for (int k = 0; k < kPix; k++) {
+        int iy = iy0 + 4 * k;
+        G0[k] = G1[k] = G2[k] = 0.0f;
+        lp[k] = F.lst[k] == kNone ? 0u : F.lst[k] + 1u;
+        if (ix < V.W && iy < V.H) {
+            size_t pidx = (size_t)iy * V.W + ix;
+            // the image values exactly as stored above
+            G0[k] = loss_grad<LOSS>(fmaf(F.T[k], o.bg0, F.C0[k]), V.target[pidx], V.loss_scale);
+            G1[k] = loss_grad<LOSS>(fmaf(F.T[k], o.bg1, F.C1[k]), V.target[plane + pidx], V.loss_scale);
+            G2[k] = loss_grad<LOSS>(fmaf(F.T[k], o.bg2, F.C2[k]), V.target[2 * plane + pidx], V.loss_scale);
+        }
+    }
+    tile_bwd<KIND, false>(V, tile, blockIdx.x, n, kp, o, F.T, lp, G0, G1, G2, DetOut{});
+}
+
+// Deterministic mode, pass 0: number of partials of each work item (the same
+// walk end as the backward computes).
+template <class VS>
+__global__ __launch_bounds__(64) void k_trav_len(VS A, uint32_t *len) {
+    int tile;
+    const RView &V = A.get(blockIdx.x, tile);
+    uint32_t out = 0;
+    if (!(V.overflow && *V.overflow)) {
+        float T[kPix], G0[kPix], G1[kPix], G2[kPix];
+        uint32_t lp[kPix];
+        load_checkpoint(V, tile, T, lp, G0, G1, G2);
+        uint32_t maxl = max(max(lp[0], lp[1]), max(lp[2], lp[3]));
+        maxl = wave_max_u32(maxl);
+        const uint32_t start = V.ranges[2 * tile], end = V.ranges[2 * tile + 1];
+        maxl = min(maxl, end);
+        out = maxl > start ? maxl - start : 0u;
+    }
+    if (threadIdx.x == 0) len[blockIdx.x] = out;
+}
+
+struct DetHdr {
+    uint32_t total;  // number of stored partials
+    int32_t zero;    // always 0 (the "skip" flag of the scan and sort kernels)
+};
+
+__global__ void k_det_init(DetHdr *h) {
+    if (threadIdx.x == 0) {
+        h->total = 0;
+        h->zero = 0;
+    }
+}
+
+// Deterministic mode, pass 2: per splat (run of equal keys in the stably
+// sorted list) the sum of its partials in tile order.
+template <class VS>
+__global__ __launch_bounds__(256) void k_det_reduce(VS A, uint32_t n, const uint32_t *skey, const uint32_t *sval,
+                                                    const float *parts, uint32_t cap, const DetHdr *hdr,
+                                                    uint32_t limit) {
+    const uint32_t total = hdr->total;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+        const uint32_t key = skey[i];
+        if (key >= limit) continue;
+        if (i > 0 && skey[i - 1] == key) continue;
+        float acc[9];
+#pragma unroll
+        for (int k = 0; k < 9; k++) acc[k] = 0.0f;
+        for (uint32_t j = i; j < total && skey[j] == key; j++) {
+            const size_t c = sval[j];
+#pragma unroll
+            for (int k = 0; k < 9; k++) acc[k] += parts[(size_t)k * cap + c];
+        }
+        const uint32_t vi = key / n, id = key - vi * n;
+        const darb_grads2d g = A.grads(vi);
+        g.xy[2 * id] = acc[0];
+        g.xy[2 * id + 1] = acc[1];
+        g.conic[3 * id] = acc[2];
+        g.conic[3 * id + 1] = acc[3];
+        g.conic[3 * id + 2] = acc[4];
+        g.opacity[id] = acc[5];
+        g.rgb[3 * id] = acc[6];
+        g.rgb[3 * id + 1] = acc[7];
+        g.rgb[3 * id + 2] = acc[8];
     }
 }
 
@@ -266,14 +492,47 @@ __global__ __launch_bounds__(256) void k_zero(float *a, size_t n) {
     for (; i < n; i += stride) a[i] = 0.0f;
 }
 
-hipError_t zero(float *a, size_t n, hipStream_t s) {
+inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct DetLayout {
+    size_t hdr, trav, sparts, parts, kA, vA, kB, vB, hist, total;
+};
+
+DetLayout det_layout(uint32_t items, uint64_t cap) {
+    DetLayout L;
+    size_t off = 0;
+    const uint32_t cap32 = (uint32_t)cap;
+    const size_t hist_n = radix_hist_words(cap32);
+    const size_t sp = std::max(scan_parts_words(items), scan_parts_words((uint32_t)std::min<size_t>(hist_n, 0xFFFFFFFFu)));
+    L.hdr = off; off += align_up(sizeof(DetHdr));
+    L.trav = off; off += align_up(((size_t)items + 1) * 4);
+    L.sparts = off; off += align_up(sp * 4);
+    L.parts = off; off += align_up((size_t)9 * cap * 4);
+    L.kA = off; off += align_up((size_t)cap * 4);
+    L.vA = off; off += align_up((size_t)cap * 4);
+    L.kB = off; off += align_up((size_t)cap * 4);
+    L.vB = off; off += align_up((size_t)cap * 4);
+    L.hist = off; off += align_up(hist_n * 4);
+    L.total = off;
+    return L;
+}
+
+int bits_for(uint64_t v) {
+    int b = 0;
+    while (b < 32 && (v >> b) != 0) b++;
+    return b;
+}
+
+}  // namespace
+
+size_t det_workspace(uint32_t items, uint64_t capacity) { return det_layout(items, capacity).total; }
+
+hipError_t launch_zero(float *a, size_t n, hipStream_t s) {
     if (n == 0) return hipSuccess;
     size_t blocks = std::min<size_t>((n + 255) / 256, 4096);
     hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, a, n);
     return hipGetLastError();
 }
-
-}  // namespace
 
 #define DARB_KIND_SWITCH(kind, F, ...)                     \
     switch (kind) {                                        \
@@ -286,45 +545,117 @@ hipError_t zero(float *a, size_t n, hipStream_t s) {
     default: F<DARB_PARABOLA> __VA_ARGS__; break;          \
     }
 
+namespace {
+
 template <int KIND>
-static void fwd_launch(dim3 g, hipStream_t s, const darb_projected &p, const uint32_t *vals, const uint32_t *ranges,
-                       const int32_t *ov, int n, int W, int H, int gx, const KParams &kp, const ROpts &o, float *image,
-                       float *fT, uint32_t *last, uint32_t *nc) {
-    hipLaunchKernelGGL(k_raster_fwd<KIND>, g, dim3(64), 0, s, p, vals, ranges, ov, n, W, H, gx, kp, o, image, fT, last,
-                       nc);
+void fwd_launch(const RViews &V, uint32_t items, int n, const KParams &kp, const ROpts &o, hipStream_t s) {
+    if (V.nv == 1)
+        hipLaunchKernelGGL((k_raster_fwd<KIND, OneView>), dim3(items), dim3(64), 0, s, OneView{V.v[0]}, n, kp, o);
+    else
+        hipLaunchKernelGGL((k_raster_fwd<KIND, ManyViews>), dim3(items), dim3(64), 0, s, ManyViews{V}, n, kp, o);
 }
 
 template <int KIND>
-static void bwd_launch(dim3 g, hipStream_t s, const darb_projected &p, const uint32_t *vals, const uint32_t *ranges,
-                       const int32_t *ov, int n, int W, int H, int gx, const KParams &kp, const ROpts &o,
-                       const float *dl, const float *fT, const uint32_t *last, const darb_grads2d &g2) {
-    hipLaunchKernelGGL(k_raster_bwd<KIND>, g, dim3(64), 0, s, p, vals, ranges, ov, n, W, H, gx, kp, o, dl, fT, last,
-                       g2);
+void bwd_launch(const RViews &V, uint32_t items, int n, const KParams &kp, const ROpts &o, bool det, const DetOut &d,
+                hipStream_t s) {
+    if (V.nv == 1) {
+        if (det)
+            hipLaunchKernelGGL((k_raster_bwd<KIND, true, OneView>), dim3(items), dim3(64), 0, s, OneView{V.v[0]}, n,
+                               kp, o, d);
+        else
+            hipLaunchKernelGGL((k_raster_bwd<KIND, false, OneView>), dim3(items), dim3(64), 0, s, OneView{V.v[0]}, n,
+                               kp, o, d);
+    } else {
+        if (det)
+            hipLaunchKernelGGL((k_raster_bwd<KIND, true, ManyViews>), dim3(items), dim3(64), 0, s, ManyViews{V}, n, kp,
+                               o, d);
+        else
+            hipLaunchKernelGGL((k_raster_bwd<KIND, false, ManyViews>), dim3(items), dim3(64), 0, s, ManyViews{V}, n,
+                               kp, o, d);
+    }
 }
 
-hipError_t launch_raster_fwd(int kind, const darb_projected &p, int n, const uint32_t *vals, const uint32_t *ranges,
-                             const int32_t *overflow, int width, int height, const KParams &kp, const ROpts &o,
-                             float *image, float *final_T, uint32_t *last, uint32_t *n_contrib, hipStream_t s) {
-    int gx = (width + kTile - 1) / kTile, gy = (height + kTile - 1) / kTile;
-    dim3 g(gx * gy);
-    DARB_KIND_SWITCH(kind, fwd_launch, (g, s, p, vals, ranges, overflow, n, width, height, gx, kp, o, image, final_T,
-                                        last, n_contrib))
+template <int KIND>
+void fwdbwd_launch(int loss, const RViews &V, uint32_t items, int n, const KParams &kp, const ROpts &o,
+                   hipStream_t s) {
+    if (loss == DARB_LOSS_L1)
+        hipLaunchKernelGGL((k_raster_fwdbwd<KIND, DARB_LOSS_L1, ManyViews>), dim3(items), dim3(64), 0, s, ManyViews{V},
+                           n, kp, o);
+    else
+        hipLaunchKernelGGL((k_raster_fwdbwd<KIND, DARB_LOSS_L2, ManyViews>), dim3(items), dim3(64), 0, s, ManyViews{V},
+                           n, kp, o);
+}
+
+hipError_t zero_grads(const RViews &V, int n, hipStream_t s) {
+    hipError_t e;
+    for (int v = 0; v < V.nv; v++) {
+        const darb_grads2d &g = V.v[v].g2;
+        if ((e = launch_zero(g.xy, (size_t)n * 2, s)) != hipSuccess) return e;
+        if ((e = launch_zero(g.conic, (size_t)n * 3, s)) != hipSuccess) return e;
+        if ((e = launch_zero(g.opacity, (size_t)n, s)) != hipSuccess) return e;
+        if ((e = launch_zero(g.rgb, (size_t)n * 3, s)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_raster_fwd(int kind, const RViews &V, uint32_t items, int n, const KParams &kp, const ROpts &o,
+                             hipStream_t s) {
+    if (items == 0) return hipSuccess;
+    DARB_KIND_SWITCH(kind, fwd_launch, (V, items, n, kp, o, s))
     return hipGetLastError();
 }
 
-hipError_t launch_raster_bwd(int kind, const darb_projected &p, int n, const uint32_t *vals, const uint32_t *ranges,
-                             const int32_t *overflow, int width, int height, const KParams &kp, const ROpts &o,
-                             const float *dL_dimage, const float *final_T, const uint32_t *last,
-                             const darb_grads2d &g2d, hipStream_t s) {
+hipError_t launch_raster_bwd(int kind, const RViews &V, uint32_t items, int n, const KParams &kp, const ROpts &o,
+                             void *det_ws, uint64_t det_capacity, hipStream_t s) {
     hipError_t e;
-    if ((e = zero(g2d.xy, (size_t)n * 2, s)) != hipSuccess) return e;
-    if ((e = zero(g2d.conic, (size_t)n * 3, s)) != hipSuccess) return e;
-    if ((e = zero(g2d.opacity, (size_t)n, s)) != hipSuccess) return e;
-    if ((e = zero(g2d.rgb, (size_t)n * 3, s)) != hipSuccess) return e;
-    int gx = (width + kTile - 1) / kTile, gy = (height + kTile - 1) / kTile;
-    dim3 g(gx * gy);
-    DARB_KIND_SWITCH(kind, bwd_launch, (g, s, p, vals, ranges, overflow, n, width, height, gx, kp, o, dL_dimage,
-                                        final_T, last, g2d))
+    if ((e = zero_grads(V, n, s)) != hipSuccess) return e;
+    if (items == 0 || n == 0) return hipGetLastError();
+    if (!det_ws) {
+        DARB_KIND_SWITCH(kind, bwd_launch, (V, items, n, kp, o, false, DetOut{}, s))
+        return hipGetLastError();
+    }
+    const DetLayout L = det_layout(items, det_capacity);
+    char *base = static_cast<char *>(det_ws);
+    auto U = [&](size_t off) { return reinterpret_cast<uint32_t *>(base + off); };
+    DetHdr *hdr = reinterpret_cast<DetHdr *>(base + L.hdr);
+    const uint32_t cap = (uint32_t)det_capacity;
+    uint32_t *trav = U(L.trav), *sparts = U(L.sparts), *kA = U(L.kA), *vA = U(L.vA), *kB = U(L.kB), *vB = U(L.vB);
+    float *parts = reinterpret_cast<float *>(base + L.parts);
+    hipLaunchKernelGGL(k_det_init, dim3(1), dim3(64), 0, s, hdr);
+    if (V.nv == 1)
+        hipLaunchKernelGGL((k_trav_len<OneView>), dim3(items), dim3(64), 0, s, OneView{V.v[0]}, trav);
+    else
+        hipLaunchKernelGGL((k_trav_len<ManyViews>), dim3(items), dim3(64), 0, s, ManyViews{V}, trav);
+    if ((e = scan_u32(trav, nullptr, items, sparts, &hdr->total, &hdr->zero, s)) != hipSuccess) return e;
+    const DetOut d{parts, kA, vA, trav, cap};
+    DARB_KIND_SWITCH(kind, bwd_launch, (V, items, n, kp, o, true, d, s))
+    const uint64_t limit = (uint64_t)V.nv * (uint64_t)n;
+    const int bits = bits_for(limit);  // 2^bits > limit: kNone keys sort after every valid key
+    if ((e = radix_sort_pairs(kA, vA, kB, vB, &hdr->total, cap, bits, U(L.hist), sparts, &hdr->zero, s)) !=
+        hipSuccess)
+        return e;
+    const bool in_b = ((bits + 7) / 8) % 2 == 1;
+    const uint32_t *sk = in_b ? kB : kA, *sv = in_b ? vB : vA;
+    const unsigned blocks = (unsigned)std::min<uint64_t>((det_capacity + 255) / 256, 8192);
+    if (blocks > 0) {
+        if (V.nv == 1)
+            hipLaunchKernelGGL((k_det_reduce<OneView>), dim3(blocks), dim3(256), 0, s, OneView{V.v[0]}, (uint32_t)n,
+                               sk, sv, parts, cap, hdr, (uint32_t)limit);
+        else
+            hipLaunchKernelGGL((k_det_reduce<ManyViews>), dim3(blocks), dim3(256), 0, s, ManyViews{V}, (uint32_t)n, sk,
+                               sv, parts, cap, hdr, (uint32_t)limit);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_raster_fwdbwd(int kind, int loss, const RViews &V, uint32_t items, int n, const KParams &kp,
+                                const ROpts &o, hipStream_t s) {
+    hipError_t e;
+    if ((e = zero_grads(V, n, s)) != hipSuccess) return e;
+    if (items == 0) return hipGetLastError();
+    DARB_KIND_SWITCH(kind, fwdbwd_launch, (loss, V, items, n, kp, o, s))
     return hipGetLastError();
 }
 

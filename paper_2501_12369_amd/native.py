@@ -19,9 +19,15 @@ c_float, c_int32, c_int64, c_void_p, c_size_t = (ctypes.c_float, ctypes.c_int32,
 
 DARB_OK, DARB_ERR_INVALID_ARG, DARB_ERR_CAPACITY, DARB_ERR_HIP, DARB_ERR_UNSUPPORTED = range(5)
 GAUSS, HALF_COS, RAISED_COS, SINC, IMQ, IMQ_SQRT, PARABOLA = range(7)
+LOSS_L1, LOSS_L2 = 0, 1
+MAX_VIEWS = 16
+LOSS_WS_BYTES = 4096
 
 EXPORTED = ("darb_version", "darb_status_string", "darb_last_error", "darb_preprocess", "darb_preprocess_cam_dev",
-            "darb_bin_sort_workspace", "darb_bin_sort", "darb_raster_fwd", "darb_raster_bwd", "darb_preprocess_bwd")
+            "darb_bin_sort_workspace", "darb_bin_sort", "darb_raster_fwd", "darb_raster_bwd",
+            "darb_raster_bwd_workspace", "darb_preprocess_bwd", "darb_image_loss", "darb_preprocess_multi",
+            "darb_raster_fwd_multi", "darb_raster_bwd_multi", "darb_raster_bwd_multi_workspace",
+            "darb_raster_fwdbwd_multi", "darb_preprocess_bwd_multi")
 
 
 class DarbError(RuntimeError):
@@ -63,6 +69,13 @@ class darb_grads3d(ctypes.Structure):
                 ("sh", c_void_p)]
 
 
+class darb_view(ctypes.Structure):
+    _fields_ = [("cam", darb_camera), ("proj", darb_projected), ("k_capacity", c_int64), ("vals", c_void_p),
+                ("ranges", c_void_p), ("overflow_dev", c_void_p), ("image", c_void_p), ("final_T", c_void_p),
+                ("last", c_void_p), ("n_contrib", c_void_p), ("dL_dimage", c_void_p), ("target", c_void_p),
+                ("grads2d", darb_grads2d)]
+
+
 _lib = None
 
 
@@ -101,10 +114,32 @@ def lib():
         L.darb_raster_bwd.restype = c_int32
         L.darb_raster_bwd.argtypes = [P(darb_projected), c_int64, c_void_p, c_void_p, c_void_p, c_int32, c_int32,
                                       P(darb_kernel), P(darb_raster_opts), c_void_p, c_void_p, c_void_p,
-                                      P(darb_grads2d), P(darb_camera), P(darb_splats), P(darb_grads3d), c_void_p]
+                                      P(darb_grads2d), P(darb_camera), P(darb_splats), P(darb_grads3d), c_int32,
+                                      c_int64, c_void_p, c_size_t, c_void_p]
+        L.darb_raster_bwd_workspace.restype = c_size_t
+        L.darb_raster_bwd_workspace.argtypes = [c_int64, c_int32, c_int32, c_int64]
         L.darb_preprocess_bwd.restype = c_int32
         L.darb_preprocess_bwd.argtypes = [P(darb_camera), P(darb_kernel), c_int64, P(darb_splats), P(darb_grads2d),
-                                          P(darb_grads3d), c_void_p]
+                                          P(darb_grads3d), c_int32, c_void_p]
+        L.darb_image_loss.restype = c_int32
+        L.darb_image_loss.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p,
+                                      c_size_t, c_void_p]
+        L.darb_preprocess_multi.restype = c_int32
+        L.darb_preprocess_multi.argtypes = [P(darb_view), c_int32, P(darb_kernel), c_int64, P(darb_splats), c_void_p]
+        L.darb_raster_fwd_multi.restype = c_int32
+        L.darb_raster_fwd_multi.argtypes = [P(darb_view), c_int32, c_int64, P(darb_kernel), P(darb_raster_opts),
+                                            c_void_p]
+        L.darb_raster_bwd_multi.restype = c_int32
+        L.darb_raster_bwd_multi.argtypes = [P(darb_view), c_int32, c_int64, P(darb_kernel), P(darb_raster_opts),
+                                            c_int32, c_void_p, c_size_t, c_void_p]
+        L.darb_raster_bwd_multi_workspace.restype = c_size_t
+        L.darb_raster_bwd_multi_workspace.argtypes = [P(darb_view), c_int32, c_int64]
+        L.darb_raster_fwdbwd_multi.restype = c_int32
+        L.darb_raster_fwdbwd_multi.argtypes = [P(darb_view), c_int32, c_int64, P(darb_kernel), P(darb_raster_opts),
+                                               c_int32, c_void_p]
+        L.darb_preprocess_bwd_multi.restype = c_int32
+        L.darb_preprocess_bwd_multi.argtypes = [P(darb_view), c_int32, P(darb_kernel), c_int64, P(darb_splats),
+                                                P(darb_grads3d), c_void_p]
         _lib = L
     return _lib
 
@@ -248,9 +283,14 @@ def darb_raster_fwd(proj: dict, n: int, vals, ranges, overflow_dev, width: int, 
                                  _ptr(n_contrib), _stream(stream)), "darb_raster_fwd")
 
 
+def _nbytes(t) -> int:
+    return 0 if t is None else t.numel() * t.element_size()
+
+
 def darb_raster_bwd(proj: dict, n: int, vals, ranges, overflow_dev, width: int, height: int, kernel, opts: dict,
                     dL_dimage, final_T, last, g2d: dict, cam: dict | None = None, splats: dict | None = None,
-                    g3d: dict | None = None, stream=None):
+                    g3d: dict | None = None, deterministic: bool = False, k_capacity: int = 0, ws=None,
+                    stream=None):
     p, k, o = projected_struct(proj), kernel_struct(kernel), opts_struct(opts)
     g2 = grads2d_struct(g2d)
     if g3d is not None:
@@ -260,11 +300,81 @@ def darb_raster_bwd(proj: dict, n: int, vals, ranges, overflow_dev, width: int, 
         cref = sref = g3ref = None
     _check(lib().darb_raster_bwd(ctypes.byref(p), n, _ptr(vals), _ptr(ranges), _ptr(overflow_dev), width, height,
                                  ctypes.byref(k), ctypes.byref(o), _ptr(dL_dimage), _ptr(final_T), _ptr(last),
-                                 ctypes.byref(g2), cref, sref, g3ref, _stream(stream)), "darb_raster_bwd")
+                                 ctypes.byref(g2), cref, sref, g3ref, 1 if deterministic else 0, int(k_capacity),
+                                 _ptr(ws), _nbytes(ws), _stream(stream)), "darb_raster_bwd")
 
 
-def darb_preprocess_bwd(cam: dict, kernel, n: int, splats: dict, g2d: dict, g3d: dict, stream=None):
+def darb_raster_bwd_workspace(n: int, width: int, height: int, k_capacity: int) -> int:
+    return int(lib().darb_raster_bwd_workspace(n, width, height, k_capacity))
+
+
+def darb_preprocess_bwd(cam: dict, kernel, n: int, splats: dict, g2d: dict, g3d: dict, accumulate: bool = False,
+                        stream=None):
     c, k, s = camera_struct(cam), kernel_struct(kernel), splats_struct(splats)
     g2, g3 = grads2d_struct(g2d), grads3d_struct(g3d)
     _check(lib().darb_preprocess_bwd(ctypes.byref(c), ctypes.byref(k), n, ctypes.byref(s), ctypes.byref(g2),
-                                     ctypes.byref(g3), _stream(stream)), "darb_preprocess_bwd")
+                                     ctypes.byref(g3), 1 if accumulate else 0, _stream(stream)), "darb_preprocess_bwd")
+
+
+def darb_image_loss(image, target, width: int, height: int, loss_kind: int, dL_dimage=None, loss_dev=None, ws=None,
+                    stream=None):
+    _check(lib().darb_image_loss(_ptr(image), _ptr(target), width, height, int(loss_kind), _ptr(dL_dimage),
+                                 _ptr(loss_dev), _ptr(ws), _nbytes(ws), _stream(stream)), "darb_image_loss")
+
+
+def view_struct(v: dict) -> darb_view:
+    """``v``: camera dict under "cam" plus any of the darb_view buffers (tensors)."""
+    s = darb_view()
+    s.cam = camera_struct(v["cam"])
+    if v.get("proj") is not None:
+        s.proj = projected_struct(v["proj"])
+    s.k_capacity = int(v.get("k_capacity", 0))
+    for name in ("vals", "ranges", "overflow_dev", "image", "final_T", "last", "n_contrib", "dL_dimage", "target"):
+        setattr(s, name, _ptr(v.get(name)))
+    if v.get("grads2d") is not None:
+        s.grads2d = grads2d_struct(v["grads2d"])
+    return s
+
+
+def views_array(views: list):
+    if not 1 <= len(views) <= MAX_VIEWS:
+        raise ValueError(f"between 1 and {MAX_VIEWS} views")
+    arr = (darb_view * len(views))()
+    for i, v in enumerate(views):
+        arr[i] = view_struct(v)
+    return arr
+
+
+def darb_preprocess_multi(views: list, kernel, n: int, splats: dict, stream=None):
+    a, k, s = views_array(views), kernel_struct(kernel), splats_struct(splats)
+    _check(lib().darb_preprocess_multi(a, len(views), ctypes.byref(k), n, ctypes.byref(s), _stream(stream)),
+           "darb_preprocess_multi")
+
+
+def darb_raster_fwd_multi(views: list, n: int, kernel, opts: dict, stream=None):
+    a, k, o = views_array(views), kernel_struct(kernel), opts_struct(opts)
+    _check(lib().darb_raster_fwd_multi(a, len(views), n, ctypes.byref(k), ctypes.byref(o), _stream(stream)),
+           "darb_raster_fwd_multi")
+
+
+def darb_raster_bwd_multi_workspace(views: list, n: int) -> int:
+    return int(lib().darb_raster_bwd_multi_workspace(views_array(views), len(views), n))
+
+
+def darb_raster_bwd_multi(views: list, n: int, kernel, opts: dict, deterministic: bool = False, ws=None,
+                          stream=None):
+    a, k, o = views_array(views), kernel_struct(kernel), opts_struct(opts)
+    _check(lib().darb_raster_bwd_multi(a, len(views), n, ctypes.byref(k), ctypes.byref(o), 1 if deterministic else 0,
+                                       _ptr(ws), _nbytes(ws), _stream(stream)), "darb_raster_bwd_multi")
+
+
+def darb_raster_fwdbwd_multi(views: list, n: int, kernel, opts: dict, loss_kind: int, stream=None):
+    a, k, o = views_array(views), kernel_struct(kernel), opts_struct(opts)
+    _check(lib().darb_raster_fwdbwd_multi(a, len(views), n, ctypes.byref(k), ctypes.byref(o), int(loss_kind),
+                                          _stream(stream)), "darb_raster_fwdbwd_multi")
+
+
+def darb_preprocess_bwd_multi(views: list, kernel, n: int, splats: dict, g3d: dict, stream=None):
+    a, k, s, g3 = views_array(views), kernel_struct(kernel), splats_struct(splats), grads3d_struct(g3d)
+    _check(lib().darb_preprocess_bwd_multi(a, len(views), ctypes.byref(k), n, ctypes.byref(s), ctypes.byref(g3),
+                                           _stream(stream)), "darb_preprocess_bwd_multi")

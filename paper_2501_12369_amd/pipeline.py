@@ -159,15 +159,139 @@ def alloc_grads(n: int, sh_degree: int, device="cuda"):
     return g2d, g3d
 
 
+def det_workspace(frame: Frame) -> torch.Tensor:
+    """Workspace of the deterministic raster backward of ``frame``."""
+    nb = native.darb_raster_bwd_workspace(frame.n, frame.width, frame.height, frame.capacity)
+    if nb == 0:
+        raise native.DarbError(native.DARB_ERR_UNSUPPORTED, "no deterministic workspace for this size")
+    return torch.empty(nb, dtype=torch.uint8, device=frame.vals.device)
+
+
 def render_backward(frame: Frame, dL_dimage: torch.Tensor, splats: dict, cam: dict, kernel: KernelSpec,
-                    opts: dict | None = None, grads=None, chain: bool = True, stream=None):
+                    opts: dict | None = None, grads=None, chain: bool = True, stream=None, deterministic: bool = False,
+                    det_ws: torch.Tensor | None = None):
     """raster backward (+ the preprocess chain when ``chain``) from the checkpoint."""
     opts = opts or DEFAULT_OPTS
     n = frame.n
     if grads is None:
         grads = alloc_grads(n, int(splats["sh_degree"]), frame.image.device)
     g2d, g3d = grads
+    if deterministic and det_ws is None:
+        det_ws = det_workspace(frame)
     native.darb_raster_bwd(frame.proj, n, frame.vals, frame.ranges, frame.overflow, frame.width, frame.height, kernel,
                            opts, dL_dimage.contiguous(), frame.final_T, frame.last, g2d,
-                           cam if chain else None, splats if chain else None, g3d if chain else None, stream=stream)
+                           cam if chain else None, splats if chain else None, g3d if chain else None,
+                           deterministic=deterministic, k_capacity=frame.capacity,
+                           ws=det_ws if deterministic else None, stream=stream)
     return g2d, g3d
+
+
+# ---------------------------------------------------------------------------
+# Several views of one scene per step (batched training).
+# ---------------------------------------------------------------------------
+
+@dataclass
+class MultiFrame:
+    """Per-view buffers of a multi-view step (one Frame, 2D-gradient set and
+    upstream-gradient image per view)."""
+    cams: list
+    frames: list
+    g2d: list
+    dL: list
+    det_ws: torch.Tensor | None = None
+
+    @property
+    def n(self) -> int:
+        return self.frames[0].n
+
+
+def alloc_multiview(n: int, cams: list, capacities: list, device="cuda") -> MultiFrame:
+    frames = [alloc_frame(n, int(c["width"]), int(c["height"]), cap, device) for c, cap in zip(cams, capacities)]
+    g2d = [alloc_grads(n, 0, device)[0] for _ in cams]
+    dL = [torch.empty((3, int(c["height"]), int(c["width"])), dtype=torch.float32, device=device) for c in cams]
+    return MultiFrame(cams=list(cams), frames=frames, g2d=g2d, dL=dL)
+
+
+def multiview_views(mf: MultiFrame, targets: list | None = None, with_dL: bool = False) -> list:
+    out = []
+    for v, (cam, fr) in enumerate(zip(mf.cams, mf.frames)):
+        out.append(dict(cam=cam, proj=fr.proj, k_capacity=fr.capacity, vals=fr.vals, ranges=fr.ranges,
+                        overflow_dev=fr.overflow, image=fr.image, final_T=fr.final_T, last=fr.last,
+                        n_contrib=fr.n_contrib, dL_dimage=mf.dL[v] if with_dL else None,
+                        target=targets[v] if targets is not None else None, grads2d=mf.g2d[v]))
+    return out
+
+
+def multiview_det_workspace(mf: MultiFrame) -> torch.Tensor:
+    nb = native.darb_raster_bwd_multi_workspace(multiview_views(mf), mf.n)
+    if nb == 0:
+        raise native.DarbError(native.DARB_ERR_UNSUPPORTED, "no deterministic workspace for these views")
+    return torch.empty(nb, dtype=torch.uint8, device=mf.frames[0].vals.device)
+
+
+def multiview_overflowed(mf: MultiFrame) -> bool:
+    """Reads every view's instance count back (blocking); grows the lists of the
+    views that overflowed and returns True when the step must be repeated."""
+    again = False
+    for fr in mf.frames:
+        K = int(fr.k_dev[0].item())
+        fr.K = K
+        if K > fr.capacity:
+            _grow(fr, K, fr.vals.device)
+            again = True
+    if again:
+        mf.det_ws = None
+    return again
+
+
+def multiview_step(splats: dict, mf: MultiFrame, targets: list, kernel: KernelSpec, g3d: dict,
+                   opts: dict | None = None, loss_kind: int = native.LOSS_L1, fused: bool = True,
+                   deterministic: bool = False, stream=None):
+    """One training step over all views: preprocess (one launch) -> bin/sort per
+    view -> raster forward + loss + backward (one fused launch, or forward launch,
+    per-view loss and backward launch) -> preprocess backward summed over the
+    views (one launch) into ``g3d``.  Nothing is read back; a view whose list
+    overflowed is skipped (check with :func:`multiview_overflowed`)."""
+    opts = opts or DEFAULT_OPTS
+    n = mf.n
+    views = multiview_views(mf, targets=targets, with_dL=not fused or deterministic)
+    native.darb_preprocess_multi(views, kernel, n, splats, stream=stream)
+    for fr in mf.frames:
+        native.darb_bin_sort(fr.proj, n, fr.width, fr.height, fr.capacity, fr.ws, None, fr.vals, fr.ranges, fr.k_dev,
+                             fr.overflow, stream=stream)
+    if fused and not deterministic:
+        native.darb_raster_fwdbwd_multi(views, n, kernel, opts, loss_kind, stream=stream)
+    else:
+        native.darb_raster_fwd_multi(views, n, kernel, opts, stream=stream)
+        for v, fr in enumerate(mf.frames):
+            native.darb_image_loss(fr.image, targets[v], fr.width, fr.height, loss_kind, dL_dimage=mf.dL[v],
+                                   stream=stream)
+        if deterministic and mf.det_ws is None:
+            mf.det_ws = multiview_det_workspace(mf)
+        native.darb_raster_bwd_multi(views, n, kernel, opts, deterministic=deterministic,
+                                     ws=mf.det_ws if deterministic else None, stream=stream)
+    native.darb_preprocess_bwd_multi(views, kernel, n, splats, g3d, stream=stream)
+
+
+def sequential_step(splats: dict, mf: MultiFrame, targets: list, kernel: KernelSpec, g3d: dict,
+                    opts: dict | None = None, loss_kind: int = native.LOSS_L1, deterministic: bool = False,
+                    det_ws: list | None = None, stream=None):
+    """The same step as single-view calls, view after view: preprocess ->
+    bin/sort -> raster forward -> loss -> raster backward -> preprocess backward
+    accumulated into ``g3d``."""
+    opts = opts or DEFAULT_OPTS
+    n = mf.n
+    for v, (cam, fr) in enumerate(zip(mf.cams, mf.frames)):
+        native.darb_preprocess(cam, kernel, n, splats, fr.proj, stream=stream)
+        native.darb_bin_sort(fr.proj, n, fr.width, fr.height, fr.capacity, fr.ws, None, fr.vals, fr.ranges, fr.k_dev,
+                             fr.overflow, stream=stream)
+        native.darb_raster_fwd(fr.proj, n, fr.vals, fr.ranges, fr.overflow, fr.width, fr.height, kernel, opts,
+                               fr.image, fr.final_T, fr.last, fr.n_contrib, stream=stream)
+        native.darb_image_loss(fr.image, targets[v], fr.width, fr.height, loss_kind, dL_dimage=mf.dL[v], stream=stream)
+        ws = None
+        if deterministic:
+            ws = det_ws[v] if det_ws is not None else det_workspace(fr)
+        native.darb_raster_bwd(fr.proj, n, fr.vals, fr.ranges, fr.overflow, fr.width, fr.height, kernel, opts,
+                               mf.dL[v], fr.final_T, fr.last, mf.g2d[v], deterministic=deterministic,
+                               k_capacity=fr.capacity, ws=ws, stream=stream)
+        native.darb_preprocess_bwd(cam, kernel, n, splats, mf.g2d[v], g3d, accumulate=v > 0, stream=stream)

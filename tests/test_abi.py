@@ -30,6 +30,12 @@ def test_header_declares_the_four_stages():
         assert n in names
 
 
+def test_binding_names_match_the_header():
+    from paper_2501_12369_amd import native
+
+    assert sorted(native.EXPORTED) == _declared()
+
+
 def test_library_exports_every_declared_symbol(L):
     for name in _declared():
         assert hasattr(L, name), name
@@ -38,7 +44,7 @@ def test_library_exports_every_declared_symbol(L):
 def test_version_and_status_strings(L):
     from paper_2501_12369_amd import native
 
-    assert native.darb_version() == 1
+    assert native.darb_version() == 2
     assert L.darb_status_string(0) == b"ok"
     assert L.darb_status_string(2) == b"instance capacity exceeded"
 
@@ -74,3 +80,61 @@ def test_invalid_arguments_rejected_on_host(L):
     sp2 = native.darb_splats(16 * 1000 + 4, 16 * 1000, 16 * 1000, 16 * 1000, 16 * 1000, 0)
     st = L.darb_preprocess(ctypes.byref(cam), ctypes.byref(k), 10, ctypes.byref(sp2), ctypes.byref(pr), None)
     assert st == native.DARB_ERR_INVALID_ARG and b"aligned" in L.darb_last_error()
+
+
+def _view(native, w=64, h=64):
+    v = native.darb_view()
+    v.cam.width, v.cam.height, v.cam.fx, v.cam.fy, v.cam.near_z = w, h, 64.0, 64.0, 0.2
+    return v
+
+
+def test_multiview_and_loss_arguments_rejected_on_host(L):
+    from paper_2501_12369_amd import native
+
+    k = native.darb_kernel(1, 18 / 3.141592653589793, 1.36, 9.0)
+    o = native.darb_raster_opts(1 / 255, 0.99, 1e-4)
+    sp = native.darb_splats()
+    arr = (native.darb_view * 17)()
+    for i in range(17):
+        arr[i] = _view(native)
+    # view count outside [1, 16]
+    for nv in (0, 17):
+        st = L.darb_preprocess_multi(arr, nv, ctypes.byref(k), 0, ctypes.byref(sp), None)
+        assert st == native.DARB_ERR_INVALID_ARG
+    # views without projected buffers / lists / outputs
+    st = L.darb_preprocess_multi(arr, 2, ctypes.byref(k), 10, ctypes.byref(sp), None)
+    assert st == native.DARB_ERR_INVALID_ARG
+    st = L.darb_raster_fwd_multi(arr, 2, 10, ctypes.byref(k), ctypes.byref(o), None)
+    assert st == native.DARB_ERR_INVALID_ARG and b"null pointer" in L.darb_last_error()
+    st = L.darb_raster_fwdbwd_multi(arr, 2, 10, ctypes.byref(k), ctypes.byref(o), 7, None)
+    assert st == native.DARB_ERR_INVALID_ARG and b"loss" in L.darb_last_error()
+    # a view with an invalid camera
+    bad = (native.darb_view * 1)()
+    bad[0] = _view(native, w=0)
+    st = L.darb_raster_bwd_multi(bad, 1, 0, ctypes.byref(k), ctypes.byref(o), 0, None, 0, None)
+    assert st == native.DARB_ERR_INVALID_ARG
+    # image loss: bad kind, null image, loss value without workspace
+    st = L.darb_image_loss(None, None, 8, 8, 0, None, None, None, 0, None)
+    assert st == native.DARB_ERR_INVALID_ARG
+    st = L.darb_image_loss(16, 32, 8, 8, 3, None, None, None, 0, None)
+    assert st == native.DARB_ERR_INVALID_ARG
+    st = L.darb_image_loss(16, 32, 8, 8, 0, None, 48, None, 0, None)
+    assert st == native.DARB_ERR_INVALID_ARG
+
+
+def test_deterministic_workspace_queries(L):
+    from paper_2501_12369_amd import native
+
+    assert L.darb_raster_bwd_workspace(1000, 64, 64, 5000) > L.darb_raster_bwd_workspace(1000, 64, 64, 100) > 0
+    assert L.darb_raster_bwd_workspace(1000, 64, 64, -1) == 0
+    assert L.darb_raster_bwd_workspace(1000, 4096, 4096, 10) == 0
+    arr = (native.darb_view * 3)()
+    for i in range(3):
+        arr[i] = _view(native)
+        arr[i].vals, arr[i].ranges, arr[i].k_capacity = 4096, 8192, 1000
+    one = L.darb_raster_bwd_multi_workspace(arr, 1, 100)
+    two = L.darb_raster_bwd_multi_workspace(arr, 2, 100)
+    assert two > one > 0
+    # nv * n beyond 32-bit keys
+    assert L.darb_raster_bwd_multi_workspace(arr, 2, 0x7FFFFFFF) > 0
+    assert L.darb_raster_bwd_multi_workspace(arr, 3, 0x7FFFFFFF) == 0

@@ -159,10 +159,17 @@ def test_raster_bwd_parity(kname):
     opts = dict(pipeline.DEFAULT_OPTS, bg=(0.3, 0.1, 0.2))
     ps, fr, orc = _forward_case(kname, n, W, H, seed, opts=opts)
     G = scenes.upstream_grad(seed + 1, W, H)
-    g2d, _ = pipeline.alloc_grads(n, 0)
-    native.darb_raster_bwd(fr.proj, n, fr.vals, fr.ranges, fr.overflow, W, H, pipeline.KERNELS[kname], opts, dev(G),
-                           fr.final_T, fr.last, g2d)
-    torch.cuda.synchronize()
+    runs = {}
+    for det in (False, True, True):
+        g2d, _ = pipeline.alloc_grads(n, 0)
+        ws = pipeline.det_workspace(fr) if det else None
+        native.darb_raster_bwd(fr.proj, n, fr.vals, fr.ranges, fr.overflow, W, H, pipeline.KERNELS[kname], opts,
+                               dev(G), fr.final_T, fr.last, g2d, deterministic=det, k_capacity=fr.capacity, ws=ws)
+        torch.cuda.synchronize()
+        runs.setdefault(det, []).append({k: to_np(v) for k, v in g2d.items()})
+    # the deterministic reduction gives the same bits every run
+    for k in runs[True][0]:
+        assert np.array_equal(runs[True][0][k], runs[True][1][k]), k
     Go = G.reshape(3, -1).T.astype(np.float64)
     go = oracle.composite_bwd(oracle_projected(ps), ps["conic_o"][:, 3].astype(np.float64),
                               oracle_kernel_fp32(kname), oracle_opts_fp32(opts), W, H, Go)
@@ -171,11 +178,12 @@ def test_raster_bwd_parity(kname):
     keep = ~exempt
     # kernels with F(e_max) > 0 (Gaussian, IMQ) put more pixels near the support jump
     assert keep.mean() > 0.8
-    for name, a, b in (("xy", g2d["xy"], go["xy"]), ("conic", g2d["conic"], go["conic"]),
-                       ("opacity", g2d["opacity"], go["opacity"]), ("rgb", g2d["rgb"], go["rgb"])):
-        ok, l2, ratio = grad_compare(to_np(a)[keep], b[keep])
-        print(f"  {name:8s} relL2={l2:.2e} worst={ratio:.3f}")
-        assert ok, (name, l2, ratio)
+    for det in (False, True):
+        g2d = runs[det][0]
+        for name in ("xy", "conic", "opacity", "rgb"):
+            ok, l2, ratio = grad_compare(g2d[name][keep], go[name][keep])
+            print(f"  det={int(det)} {name:8s} relL2={l2:.2e} worst={ratio:.3f}")
+            assert ok, (det, name, l2, ratio)
 
 
 # ---------------------------------------------------------------- preprocess
@@ -270,14 +278,16 @@ def test_end_to_end_tiny(kname, dilation):
     print(f"end-to-end tiny {kname} eps={dilation}", flush=True)
     spd = _splats_dev(sp)
     fr = pipeline.render(spd, cam, pipeline.KERNELS[kname], n_contrib=True)
-    target = np.random.default_rng(5).uniform(0, 1, (3, H, W)).astype(np.float32)
-    G = (np.sign(to_np(fr.image) - target) / (3 * H * W)).astype(np.float32)  # mean-L1 gradient
-    g2d, g3d = pipeline.render_backward(fr, dev(G), spd, cam, pipeline.KERNELS[kname])
-    torch.cuda.synchronize()
     ocam = oracle.camera_from_scene(cam)
     ko = oracle_kernel_fp32(kname)
     params = {k: v for k, v in sp.items()}
     _, img_o = oracle.render(ocam, ko, oracle_opts_fp32(), params)
+    # upstream gradient: the mean-L1 gradient of the oracle's image against a random target
+    target = np.random.default_rng(5).uniform(0, 1, (3, H, W)).astype(np.float32)
+    _, Go = oracle.image_loss(img_o["rgb"], image_pixels(target), oracle.LOSS_L1)
+    G = Go.T.reshape(3, H, W).astype(np.float32)
+    g2d, g3d = pipeline.render_backward(fr, dev(G), spd, cam, pipeline.KERNELS[kname])
+    torch.cuda.synchronize()
     Go = G.reshape(3, -1).T.astype(np.float64)
     _, g2o, g3o = oracle.render_bwd(ocam, ko, oracle_opts_fp32(), params, Go)
     # end-to-end tolerance (FP32 projection feeds the composite): 1e-4 relative + 1e-5
