@@ -366,6 +366,16 @@ __device__ __forceinline__ SuperBox super_box(int4 r) {
     return SuperBox{r.x / kSuper, (r.y - 1) / kSuper, r.z / kSuper, (r.w - 1) / kSuper};
 }
 
+// The part of box r inside super-tile (gxs, gys), in the super-tile's local
+// tile coordinates, packed as c0 | c1 << 4 | r0 << 8 | r1 << 12 (each 0..8).
+// Level 2 reads it with the entry instead of gathering the splat's record.
+__device__ __forceinline__ uint32_t pack_local_rect(int4 r, int gxs, int gys) {
+    const int tx0 = gxs * kSuper, ty0 = gys * kSuper;
+    const int c0 = max(r.x - tx0, 0), c1 = min(r.y - tx0, kSuper);
+    const int r0 = max(r.z - ty0, 0), r1 = min(r.w - ty0, kSuper);
+    return (uint32_t)c0 | ((uint32_t)c1 << 4) | ((uint32_t)r0 << 8) | ((uint32_t)r1 << 12);
+}
+
 // Level-1 chunks hold 256 depth-ordered splats, one per thread; a splat covers
 // few super-tiles, so each thread walks its own super-tile box.
 
@@ -393,7 +403,7 @@ __global__ __launch_bounds__(kL1Threads) void k_l1_count(const uint32_t *sorted_
 __global__ __launch_bounds__(kL1Threads) void k_l1_scatter(const uint32_t *sorted_ids, const float *xy,
                                                            const int32_t *radius, int gx, int gy, int sxn, int nsuper,
                                                            const Counters *cnt, const uint32_t *base1,
-                                                           uint32_t *list1, int64_t list1_cap,
+                                                           uint32_t *list1, uint32_t *list1r, int64_t list1_cap,
                                                            const int32_t *overflow_dev) {
     // per super-tile: a 256-bit set of the chunk's covering threads, and the chunk's first slot
     extern __shared__ uint32_t lds1[];
@@ -427,7 +437,10 @@ __global__ __launch_bounds__(kL1Threads) void k_l1_scatter(const uint32_t *sorte
             uint32_t rank = (uint32_t)__popc(bits[g * 8 + word] & (bit - 1u));
             for (int k = 0; k < word; k++) rank += (uint32_t)__popc(bits[g * 8 + k]);
             uint32_t pos = first[g] + rank;
-            if ((int64_t)pos < list1_cap) list1[pos] = id;
+            if ((int64_t)pos < list1_cap) {
+                list1[pos] = id;
+                list1r[pos] = pack_local_rect(r, gxs, gys);
+            }
         }
 }
 
@@ -529,17 +542,18 @@ __device__ __forceinline__ L2Chunk l2_locate(uint32_t wi, const uint32_t *chunk2
     return C;
 }
 
-// Tiles of super-tile g covered by box r, as a 64-bit mask (bit row*8 + col).
-__device__ __forceinline__ uint64_t l2_tile_mask(bool valid, int4 r, int g, int sxn) {
-    if (!valid) return 0ull;
-    const int tx0 = (g % sxn) * kSuper, ty0 = (g / sxn) * kSuper;
-    int c0 = max(r.x - tx0, 0), c1 = min(r.y - tx0, kSuper);
-    int r0 = max(r.z - ty0, 0), r1 = min(r.w - ty0, kSuper);
-    if (c1 <= c0 || r1 <= r0) return 0ull;
-    uint64_t cm = ((1ull << c1) - 1ull) & ~((1ull << c0) - 1ull);
-    uint64_t m = 0ull;
-    for (int rr = r0; rr < r1; rr++) m |= cm << (kSuper * rr);
-    return m;
+// Columns [c0, c1) and rows [r0, r1) of super-tile g covered by box r, in the
+// super-tile's local coordinates (empty when invalid).
+struct LRect {
+    int c0, c1, r0, r1;
+};
+
+__device__ __forceinline__ LRect l2_local_rect(bool valid, uint32_t packed) {
+    LRect L{0, 0, 0, 0};
+    if (!valid) return L;
+    const int c0 = packed & 15u, c1 = (packed >> 4) & 15u, r0 = (packed >> 8) & 15u, r1 = (packed >> 12) & 15u;
+    if (c1 <= c0 || r1 <= r0) return L;
+    return LRect{c0, c1, r0, r1};
 }
 
 // number of lanes below this one whose bit is set in m
@@ -548,37 +562,54 @@ __device__ __forceinline__ uint32_t rank_below(uint64_t m) {
 }
 
 static_assert(kSuper * kSuper == 64, "a super-tile has one tile per lane");
+static_assert(kSuper == 8, "column and row masks are 8 ballots each");
 
-// wc[tl * kL2Waves + w] = lanes of wave w covering tile tl, for the 64 tiles of a
-// super-tile: lane tl collects tile tl's count in a register
-__device__ __forceinline__ void l2_ballots(uint64_t tmask, uint32_t *wc) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint32_t cnt = 0;
-#pragma unroll 8
-    for (int tl = 0; tl < 64; tl++) {
-        uint64_t m = __ballot((tmask >> tl) & 1ull);
-        cnt = (lane == tl) ? (uint32_t)__popcll(m) : cnt;
+// A lane covers tile (c, r) iff it covers column c and row r, so the wave's
+// lanes covering the tile are colB[c] & rowB[r]: sixteen ballots give all 64
+// tile masks.  The masks are also stored to the wave's LDS slots (every lane
+// writes the same value: no lane-dependent branch next to the ballots).
+__device__ __forceinline__ void l2_colrow(const LRect &L, uint64_t (&colB)[kSuper], uint64_t (&rowB)[kSuper],
+                                          uint64_t *lds_masks) {
+#pragma unroll
+    for (int c = 0; c < kSuper; c++) colB[c] = __ballot((c >= L.c0) & (c < L.c1));
+#pragma unroll
+    for (int r = 0; r < kSuper; r++) rowB[r] = __ballot((r >= L.r0) & (r < L.r1));
+#pragma unroll
+    for (int k = 0; k < kSuper; k++) {
+        lds_masks[k] = colB[k];
+        lds_masks[kSuper + k] = rowB[k];
     }
-    wc[lane * kL2Waves + w] = cnt;
 }
 
-__global__ __launch_bounds__(kL2Threads) void k_l2_count(const uint32_t *list1, const uint32_t *l1_start,
+// wc[tl * kL2Waves + w] = lanes of wave w covering tile tl (lane tl computes it
+// from the wave's masks in LDS).  Needs a barrier between l2_colrow and this.
+__device__ __forceinline__ void l2_counts(const uint64_t *lds_masks, uint32_t *wc) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t m = lds_masks[lane & (kSuper - 1)] & lds_masks[kSuper + lane / kSuper];
+    wc[lane * kL2Waves + w] = (uint32_t)__popcll(m);
+}
+
+__global__ __launch_bounds__(kL2Threads) void k_l2_count(const uint32_t *list1r, const uint32_t *l1_start,
                                                          const uint32_t *l1_len, const uint32_t *chunk2_start,
-                                                         const uint32_t *toff, const float *xy, const int32_t *radius,
-                                                         int gx, int gy, int sxn, int nsuper, const Counters *cnt,
-                                                         uint32_t *h2, const int32_t *overflow_dev) {
+                                                         const uint32_t *toff, int gx, int gy, int sxn, int nsuper,
+                                                         const Counters *cnt, uint32_t *h2,
+                                                         const int32_t *overflow_dev) {
     __shared__ uint32_t wc[kSuper * kSuper * kL2Waves];
     __shared__ uint32_t c2s[kMaxSuperTiles + 1];
+    __shared__ uint64_t masks[kL2Waves][2 * kSuper];
     if (*overflow_dev) return;
     const uint32_t total2 = cnt->total2;
+    const int w = threadIdx.x >> 6;
     for (int g = threadIdx.x; g <= nsuper; g += kL2Threads) c2s[g] = chunk2_start[g];
     __syncthreads();
     for (uint32_t wi = blockIdx.x; wi < total2; wi += gridDim.x) {
         L2Chunk C = l2_locate(wi, c2s, nsuper, l1_start, l1_len);
         bool valid = threadIdx.x < C.len;
-        int4 r = make_int4(0, 0, 0, 0);
-        if (valid) splat_box(xy, radius, (int)list1[C.first + threadIdx.x], gx, gy, r);
-        l2_ballots(l2_tile_mask(valid, r, C.g, sxn), wc);
+        const uint32_t packed = valid ? list1r[C.first + threadIdx.x] : 0u;
+        uint64_t colB[kSuper], rowB[kSuper];
+        l2_colrow(l2_local_rect(valid, packed), colB, rowB, masks[w]);
+        __syncthreads();
+        l2_counts(masks[w], wc);
         __syncthreads();
         if (threadIdx.x < kSuper * kSuper) {
             int tl = threadIdx.x;
@@ -593,33 +624,36 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_count(const uint32_t *list1, 
     }
 }
 
-__global__ __launch_bounds__(kL2Threads) void k_l2_scatter(const uint32_t *list1, const uint32_t *l1_start,
-                                                           const uint32_t *l1_len, const uint32_t *chunk2_start,
-                                                           const uint32_t *toff, const uint32_t *base2, const float *xy,
-                                                           const int32_t *radius, const float *depth, int gx, int gy,
+__global__ __launch_bounds__(kL2Threads) void k_l2_scatter(const uint32_t *list1, const uint32_t *list1r,
+                                                           const uint32_t *l1_start, const uint32_t *l1_len,
+                                                           const uint32_t *chunk2_start, const uint32_t *toff,
+                                                           const uint32_t *base2, const float *depth, int gx, int gy,
                                                            int sxn, int nsuper, const Counters *cnt, int64_t k_capacity,
                                                            uint64_t *keys, uint32_t *vals,
                                                            const int32_t *overflow_dev) {
     __shared__ uint32_t wc[kSuper * kSuper * kL2Waves];
     __shared__ uint32_t slot[kSuper * kSuper * kL2Waves];
     __shared__ uint32_t c2s[kMaxSuperTiles + 1];
+    __shared__ uint64_t masks[kL2Waves][2 * kSuper];
     if (*overflow_dev) return;
     const uint32_t total2 = cnt->total2;
-    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int g = threadIdx.x; g <= nsuper; g += kL2Threads) c2s[g] = chunk2_start[g];
     __syncthreads();
+    const uint32_t cap32 = (uint32_t)min(k_capacity, (int64_t)0xFFFFFFFFll);
     for (uint32_t wi = blockIdx.x; wi < total2; wi += gridDim.x) {
         L2Chunk C = l2_locate(wi, c2s, nsuper, l1_start, l1_len);
         bool valid = threadIdx.x < C.len;
-        int4 r = make_int4(0, 0, 0, 0);
-        uint32_t id = 0, db = 0;
+        uint32_t id = 0, db = 0, packed = 0;
         if (valid) {
             id = list1[C.first + threadIdx.x];
-            splat_box(xy, radius, (int)id, gx, gy, r);
-            db = __float_as_uint(depth[id]);
+            packed = list1r[C.first + threadIdx.x];
+            if (keys) db = __float_as_uint(depth[id]);  // keys are optional: gather the depth only for them
         }
-        const uint64_t tmask = l2_tile_mask(valid, r, C.g, sxn);
-        l2_ballots(tmask, wc);
+        uint64_t colB[kSuper], rowB[kSuper];
+        l2_colrow(l2_local_rect(valid, packed), colB, rowB, masks[w]);
+        __syncthreads();
+        l2_counts(masks[w], wc);
         __syncthreads();
         const int tx0 = (C.g % sxn) * kSuper, ty0 = (C.g / sxn) * kSuper;
         if (threadIdx.x < kSuper * kSuper * kL2Waves) {
@@ -634,19 +668,20 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_scatter(const uint32_t *list1
         }
         __syncthreads();
         // lane tl holds this wave's first slot in tile tl; broadcast per tile with v_readlane
-        const uint32_t myslot = slot[(threadIdx.x & 63) * kL2Waves + w];
-        const uint32_t cap32 = (uint32_t)min(k_capacity, (int64_t)0xFFFFFFFFll);
-        for (int tl = 0; tl < 64; tl++) {
-            const bool cov = (tmask >> tl) & 1ull;
-            const uint64_t m = __ballot(cov);
-            if (m == 0ull) continue;  // no lane of this wave covers the tile
-            const uint32_t s0 = (uint32_t)__builtin_amdgcn_readlane((int)myslot, tl);
-            if (cov) {
-                int t = (ty0 + tl / kSuper) * gx + tx0 + (tl & (kSuper - 1));
-                uint32_t pos = s0 + rank_below(m);
-                if (pos < cap32) {
-                    vals[pos] = id;
-                    if (keys) keys[pos] = ((uint64_t)(uint32_t)t << 32) | db;
+        const uint32_t myslot = slot[lane * kL2Waves + w];
+        for (int rr = 0; rr < kSuper; rr++) {
+            if (rowB[rr] == 0ull) continue;  // no lane of this wave covers the row (uniform)
+            for (int cc = 0; cc < kSuper; cc++) {
+                const uint64_t m = colB[cc] & rowB[rr];
+                if (m == 0ull) continue;
+                const int tl = rr * kSuper + cc;
+                const uint32_t s0 = (uint32_t)__builtin_amdgcn_readlane((int)myslot, tl);
+                if ((m >> lane) & 1ull) {
+                    const uint32_t pos = s0 + rank_below(m);
+                    if (pos < cap32) {
+                        vals[pos] = id;
+                        if (keys) keys[pos] = ((uint64_t)(uint32_t)((ty0 + rr) * gx + tx0 + cc) << 32) | db;
+                    }
                 }
             }
         }
@@ -670,7 +705,7 @@ __global__ __launch_bounds__(256) void k_bin_ranges(const uint32_t *base2, const
 inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct WsLayout {
-    size_t counters, blockvis, blockarea, keysA, valsA, keysB, valsB, hist, h1, list1, l1start, l1len, c2start,
+    size_t counters, blockvis, blockarea, keysA, valsA, keysB, valsB, hist, h1, list1, list1r, l1start, l1len, c2start,
         toff, h2, parts, total;
     uint32_t hist_n, h1_n, h2_n;
 };
@@ -702,6 +737,7 @@ WsLayout layout(int n, int gx, int gy, int64_t k_capacity) {
     L.hist = off; off += align_up((size_t)L.hist_n * 4);
     L.h1 = off; off += align_up((size_t)L.h1_n * 4);
     L.list1 = off; off += align_up(cap * 4);
+    L.list1r = off; off += align_up(cap * 4);
     L.l1start = off; off += align_up((size_t)(nsuper + 1) * 4);
     L.l1len = off; off += align_up((size_t)(nsuper + 1) * 4);
     L.c2start = off; off += align_up((size_t)(nsuper + 1) * 4);
@@ -763,7 +799,7 @@ hipError_t launch_bin_sort(const darb_projected &p, int n, int width, int height
     auto U = [&](size_t o) { return reinterpret_cast<uint32_t *>(base + o); };
     Counters *cnt = reinterpret_cast<Counters *>(base + L.counters);
     uint32_t *kA = U(L.keysA), *vA = U(L.valsA), *kB = U(L.keysB), *vB = U(L.valsB);
-    uint32_t *hist = U(L.hist), *parts = U(L.parts), *h1 = U(L.h1), *list1 = U(L.list1), *h2 = U(L.h2);
+    uint32_t *hist = U(L.hist), *parts = U(L.parts), *h1 = U(L.h1), *list1 = U(L.list1), *list1r = U(L.list1r), *h2 = U(L.h2);
     uint32_t *blockvis = U(L.blockvis), *blockarea = U(L.blockarea);
     uint32_t *l1start = U(L.l1start), *l1len = U(L.l1len), *c2start = U(L.c2start), *toff = U(L.toff);
     const uint32_t *nvis = &cnt->n_visible;
@@ -797,18 +833,17 @@ hipError_t launch_bin_sort(const darb_projected &p, int n, int width, int height
         if ((e = scan_exclusive(h1, &cnt->h1_count, L.h1_n, parts, &cnt->total1, overflow_dev, s)) != hipSuccess)
             return e;
         hipLaunchKernelGGL(k_l1_scatter, dim3(c1max), dim3(kL1Threads), 9 * lds1, s, sorted, p.xy, p.radius, gx, gy, sxn,
-                           nsuper, cnt, h1, list1, std::max<int64_t>(k_capacity, 1), overflow_dev);
+                           nsuper, cnt, h1, list1, list1r, std::max<int64_t>(k_capacity, 1), overflow_dev);
     }
     hipLaunchKernelGGL(k_l2_plan, dim3(1), dim3(1024), 0, s, h1, cnt, nsuper, sxn, gx, gy, l1start, l1len, c2start,
                        toff, overflow_dev);
     if (n > 0) {
-        hipLaunchKernelGGL(k_l2_count, dim3(kL2Grid), dim3(kL2Threads), 0, s, list1, l1start, l1len, c2start, toff, p.xy,
-                           p.radius, gx, gy, sxn, nsuper, cnt, h2, overflow_dev);
+        hipLaunchKernelGGL(k_l2_count, dim3(kL2Grid), dim3(kL2Threads), 0, s, list1r, l1start, l1len, c2start, toff, gx,
+                           gy, sxn, nsuper, cnt, h2, overflow_dev);
         if ((e = scan_exclusive(h2, &cnt->h2_count, L.h2_n, parts, &cnt->scan_total, overflow_dev, s)) != hipSuccess)
             return e;
-        hipLaunchKernelGGL(k_l2_scatter, dim3(kL2Grid), dim3(kL2Threads), 0, s, list1, l1start, l1len, c2start, toff,
-                           h2, p.xy, p.radius, p.depth, gx, gy, sxn, nsuper, cnt, k_capacity, keys, vals,
-                           overflow_dev);
+        hipLaunchKernelGGL(k_l2_scatter, dim3(kL2Grid), dim3(kL2Threads), 0, s, list1, list1r, l1start, l1len, c2start,
+                           toff, h2, p.depth, gx, gy, sxn, nsuper, cnt, k_capacity, keys, vals, overflow_dev);
     }
     hipLaunchKernelGGL(k_bin_ranges, dim3((ntile + 255) / 256), dim3(256), 0, s, h2, toff, ntile, cnt, ranges,
                        overflow_dev);

@@ -114,7 +114,8 @@ struct PixF {
 };
 
 template <int KIND>
-__device__ __forceinline__ void tile_fwd(const RView &V, int tile, int n, const KParams &kp, const ROpts &o, PixF &F) {
+__device__ __forceinline__ void tile_fwd(const RView &V, int tile, int n, const KParams &kp, const ROpts &o, PixF &Fout) {
+    PixF F;  // local state, copied out at the end (keeps the loop at 64 VGPRs)
     const int tx = tile % V.gx, ty = tile / V.gx;
     const int lane = threadIdx.x;
     const int ix = tx * kTile + (lane & 15);
@@ -164,6 +165,7 @@ __device__ __forceinline__ void tile_fwd(const RView &V, int tile, int n, const 
             }
         }
     }
+    Fout = F;
 }
 
 __device__ __forceinline__ void store_fwd(const RView &V, int tile, const PixF &F, const ROpts &o) {
