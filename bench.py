@@ -33,11 +33,44 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def stage_bytes(n, n_vis, K, P, ntile, sh_coeffs=48, chunks=0):
-    """Algorithmic HBM bytes per stage (one read of each needed input, one write of each output)."""
-    pre = 12 * n + (236 - 12) * n_vis + 52 * n_vis + 4 * n      # params in; xy,depth,radius,conic_o,rgb,clamp out
-    binsort = 16 * n + 4 * K + 8 * ntile + 8 * n                 # (xy, r, depth) in; vals out; ranges; depth keys
-    return dict(preprocess=pre, bin_sort=binsort)
+def stage_bytes(n, n_vis):
+    """Algorithmic HBM bytes per launch of the single-kernel stages (one read of
+    each needed input, one write of each output), per splat / per visible splat:
+      preprocess      12 B mean + 4 B cull data of every splat; 224 B of parameters
+                      (scale, quaternion, opacity, 48 SH) read and 48 B of projected
+                      record written per visible splat:           16 N + 272 N_v
+      preprocess_bwd  parameters and 2D gradients of the visible splats read (308 B),
+                      the full gradient written for every splat:   308 N_v + 236 N
+    """
+    return dict(preprocess=16 * n + 272 * n_vis, preprocess_bwd=308 * n_vis + 236 * n)
+
+
+# kernel of each single-kernel stage, and the sources it is built from
+STAGE_KERNEL = {"preprocess": ("k_preprocess<3>", ("preprocess.hip", "common.h")),
+                "preprocess_bwd": ("k_preprocess_bwd<3>", ("preprocess.hip", "common.h"))}
+
+
+def sources_digest(files) -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2501_12369_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(stage: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    (profiles/traffic.json), or None when the kernel's sources changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh).get(STAGE_KERNEL[stage][0])
+    if not rec or rec.get("sources_sha256") != sources_digest(STAGE_KERNEL[stage][1]):
+        return None
+    return int(rec["fetch_bytes"] + rec["write_bytes"])
 
 
 def cpu_baseline(sc, kernel_name, rows_every: int, log_fn=log):
@@ -189,6 +222,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--multiview-views", type=int, default=8, help="0 disables the multi-view leg")
     ap.add_argument("--multiview-n", type=int, default=2_000_000)
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="run a plain elementwise copy of this size (counter calibration for profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (requested --gpus {args.gpus}); "
@@ -277,23 +312,33 @@ def main():
     has = last != 0xFFFFFFFF
     pairs_bwd = int(torch.where(has, last - start + 1, torch.zeros_like(last)).sum())
     chunks = 0
-    bytes_ = stage_bytes(n, n_vis, K, P, pipeline.n_tiles(W, H))
-    roof = {
-        "preprocess": dict(bound="hbm", achieved=bytes_["preprocess"] / (per_stage["preprocess"] * 1e-3) / 1e9,
-                           peak=PEAK_HBM_GBS, unit="GB/s"),
-        "bin_sort": dict(bound="hbm", achieved=bytes_["bin_sort"] / (per_stage["bin_sort"] * 1e-3) / 1e9,
-                         peak=PEAK_HBM_GBS, unit="GB/s"),
-        "raster_bwd": dict(bound="alu", achieved=pairs_bwd * FLOPS_PER_PAIR_BWD / (per_stage["raster_bwd"] * 1e-3)
-                           / 1e12, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s"),
-    }
-    dominant = max(per_stage, key=per_stage.get)
-    log(f"dominant stage {dominant}; bwd pairs {pairs_bwd}; roofline: " +
-        ", ".join(f"{k}: {v['achieved']:.2f}/{v['peak']} {v['unit']}" for k, v in roof.items()))
-    r = roof.get(dominant)
-    if r is None:
-        r = roof["raster_bwd"]
-    roofline = dict(bound=r["bound"], achieved=round(r["achieved"], 4), peak=r["peak"], unit=r["unit"],
-                    frac=round(r["achieved"] / r["peak"], 5), traffic=None, kernel=dominant)
+    bytes_ = stage_bytes(n, n_vis)
+    roof = {st: dict(bound="hbm", achieved=bytes_[st] / (per_stage[st] * 1e-3) / 1e9, peak=PEAK_HBM_GBS, unit="GB/s")
+            for st in ("preprocess", "preprocess_bwd")}
+    roof["raster_bwd"] = dict(bound="alu", achieved=pairs_bwd * FLOPS_PER_PAIR_BWD / (per_stage["raster_bwd"] * 1e-3)
+                              / 1e12, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s")
+    log(f"bwd pairs {pairs_bwd}; " + ", ".join(f"{k}: {v['achieved']:.2f}/{v['peak']} {v['unit']}"
+                                                for k, v in roof.items()))
+    # the dominant kernel: the longest single-kernel stage (the rocprofv3 summary in profiles/
+    # lists every kernel of the step, those inside the bin/sort stage included)
+    dominant = max(STAGE_KERNEL, key=lambda st: per_stage[st])
+    r = roof[dominant]
+    traffic = measured_traffic(dominant)
+    roofline = dict(bound=r["bound"], achieved=round(r["achieved"], 2), peak=r["peak"], unit=r["unit"],
+                    frac=round(r["achieved"] / r["peak"], 4), traffic=traffic, kernel=STAGE_KERNEL[dominant][0],
+                    kernel_us=round(per_stage[dominant] * 1e3, 2), algorithmic_bytes=int(bytes_[dominant]))
+    log(f"dominant kernel {roofline['kernel']}: {roofline['kernel_us']} us, {roofline['achieved']} GB/s "
+        f"({roofline['frac']:.3f} of peak), traffic {traffic}")
+
+    if args.calibrate_copy_mib > 0:
+        # a plain elementwise copy of known size: what the HBM counters read for it
+        # calibrates the per-kernel FETCH_SIZE / WRITE_SIZE of a counter run
+        xc = torch.ones(args.calibrate_copy_mib << 18, device="cuda")
+        yc = torch.empty_like(xc)
+        for _ in range(3):
+            torch.neg(xc, out=yc)
+        torch.cuda.synchronize()
+        del xc, yc
 
     cpu = None
     if not args.no_cpu_baseline:
