@@ -135,22 +135,104 @@ def serving_bench(kernel_name: str, seconds: float, rate_hz: float, mem_budget_g
     torch.cuda.synchronize()
     n_req = max(1, int(seconds * rate_hz))
     reqs = serving.make_requests(77, n_req, rate_hz, len(sc))
-    _, st = srv.serve(reqs)
+    sizes = list(scenes.SERVING_SCENE_SIZES)
+
+    def fwd_bytes(results):
+        """Algorithmic forward bytes (preprocess 16 N + 272 N_v, duplicate 20 N_v + 12 K,
+        sort 24 K, image 20 P; the traversed-record reads of the raster are left out:
+        a lower bound)."""
+        tot = 0
+        for r in results:
+            K, nv = r.work
+            tot += 16 * sizes[r.key[0]] + 292 * nv + 36 * K + 20 * r.pixels
+        return tot
+
+    res, st = srv.serve(reqs)
+    hbm = fwd_bytes(res) / st.wall_s / 1e9
     log(f"serving: {st.n} requests at {rate_hz}/s: p50 {st.p50_ms:.2f} ms p99 {st.p99_ms:.2f} ms, "
-        f"{st.mpix_per_s:.1f} Mpix/s, peak slots {st.peak_slots}, peak in flight {st.peak_inflight}, "
-        f"retries {st.retries}")
+        f"{st.mpix_per_s:.1f} Mpix/s, {hbm:.0f} GB/s of forward bytes, peak slots {st.peak_slots}, "
+        f"peak in flight {st.peak_inflight}, retries {st.retries}")
+    # saturation: the same mix arriving at once
+    burst = serving.make_requests(78, max(64, n_req // 2), 1e9, len(sc))
+    bres, bst = srv.serve(burst)
+    bhbm = fwd_bytes(bres) / bst.wall_s / 1e9
+    log(f"saturation: {bst.n} requests at once: {bst.mpix_per_s:.1f} Mpix/s, {bst.req_per_s:.1f} req/s, "
+        f"{bhbm:.0f} GB/s of forward bytes ({bhbm / PEAK_HBM_GBS:.3f} of HBM peak)")
     _, seq = serving.sequential_baseline(srv, reqs)
     log(f"one-at-a-time: p50 {seq.p50_ms:.2f} ms p99 {seq.p99_ms:.2f} ms, {seq.mpix_per_s:.1f} Mpix/s, "
         f"retries {seq.retries}")
-    return dict(workload=f"4 resident scenes {list(scenes.SERVING_SCENE_SIZES)} splats, Poisson {rate_hz} req/s "
+    return dict(workload=f"4 resident scenes {sizes} splats, Poisson {rate_hz} req/s "
                          f"for {seconds}s, resolutions {[f'{w}x{h}' for w, h in scenes.SERVING_RESOLUTIONS]}, "
                          f"forward only, {kernel_name}",
                 p50_ms=round(st.p50_ms, 3), p99_ms=round(st.p99_ms, 3), mean_ms=round(st.mean_ms, 3),
                 mpix_per_s=round(st.mpix_per_s, 2), req_per_s=round(st.req_per_s, 2), requests=st.n,
                 peak_slots=st.peak_slots, peak_inflight=st.peak_inflight, peak_gb=round(st.peak_bytes / 2**30, 2),
-                retries=st.retries,
+                retries=st.retries, fwd_gbs=round(hbm, 1),
+                saturation=dict(requests=bst.n, mpix_per_s=round(bst.mpix_per_s, 2), req_per_s=round(bst.req_per_s, 2),
+                                fwd_gbs=round(bhbm, 1), hbm_frac=round(bhbm / PEAK_HBM_GBS, 4),
+                                p99_ms=round(bst.p99_ms, 3)),
                 one_at_a_time=dict(p50_ms=round(seq.p50_ms, 3), p99_ms=round(seq.p99_ms, 3),
                                    mpix_per_s=round(seq.mpix_per_s, 2)))
+
+
+def variants_bench(spd, cam, steps: int, warmup: int):
+    """The scene step with the Gaussian kernel (plain path), and the half-cosine
+    step through the torch.autograd.Function (loss sum(G * image))."""
+    import torch
+
+    from paper_2501_12369_amd import native, pipeline
+    from paper_2501_12369_amd.autograd import Rasterizer
+
+    n = int(spd["means"].shape[1])
+    W, H = cam["width"], cam["height"]
+    out = {}
+    kern = pipeline.KERNELS["gauss"]
+    fr = pipeline.render(spd, cam, kern, k_capacity=1 << 20)
+    frame = pipeline.alloc_frame(n, W, H, int(fr.K * 1.02) + 4096, "cuda")
+    del fr
+    G = torch.randn((3, H, W), device="cuda", generator=torch.Generator("cuda").manual_seed(9)) * 1e-6
+    pipeline.render(spd, cam, kern, frame=frame, read_k=True)
+    grads = pipeline.alloc_grads(n, 3)
+
+    def plain():
+        native.darb_preprocess(cam, kern, n, spd, frame.proj)
+        native.darb_bin_sort(frame.proj, n, W, H, frame.capacity, frame.ws, None, frame.vals, frame.ranges,
+                             frame.k_dev, frame.overflow)
+        native.darb_raster_fwd(frame.proj, n, frame.vals, frame.ranges, frame.overflow, W, H, kern,
+                               pipeline.DEFAULT_OPTS, frame.image, frame.final_T, frame.last)
+        native.darb_raster_bwd(frame.proj, n, frame.vals, frame.ranges, frame.overflow, W, H, kern,
+                               pipeline.DEFAULT_OPTS, G, frame.final_T, frame.last, grads[0])
+        native.darb_preprocess_bwd(cam, kern, n, spd, grads[0], grads[1])
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / steps
+
+    t_g = timed(plain)
+    assert int(frame.overflow[0].item()) == 0
+    out["gauss_plain_ms"] = round(t_g * 1e3, 4)
+    out["gauss_instances"] = int(frame.K)
+    del frame, grads
+    R = Rasterizer("half_cos")
+    params = [spd[k].clone().requires_grad_(True) for k in ("means", "scales", "quats", "opacity", "sh")]
+
+    def autograd_step():
+        for p in params:
+            p.grad = None
+        img = R(*params, cam, sh_degree=3)
+        (img * G).sum().backward()
+
+    t_a = timed(autograd_step)
+    out["half_cos_autograd_ms"] = round(t_a * 1e3, 4)
+    log(f"variants: gauss plain {t_g*1e3:.3f} ms/step (K={out['gauss_instances']}), "
+        f"half_cos autograd {t_a*1e3:.3f} ms/step")
+    return out
 
 
 def multiview_bench(kernel_name: str, n: int, n_views: int, steps: int, warmup: int):
@@ -218,10 +300,11 @@ def main():
     ap.add_argument("--cpu-rows-every", type=int, default=16)
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="0 disables the serving leg")
     ap.add_argument("--serve-rate", type=float, default=200.0)
-    ap.add_argument("--serve-mem-gb", type=float, default=24.0)
-    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-mem-gb", type=float, default=96.0)
+    ap.add_argument("--serve-slots", type=int, default=32)
     ap.add_argument("--multiview-views", type=int, default=8, help="0 disables the multi-view leg")
     ap.add_argument("--multiview-n", type=int, default=2_000_000)
+    ap.add_argument("--variants", type=int, default=1, help="0 skips the Gaussian and autograd steps")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run a plain elementwise copy of this size (counter calibration for profiling runs)")
     args = ap.parse_args()
@@ -340,6 +423,7 @@ def main():
         torch.cuda.synchronize()
         del xc, yc
 
+    variants = variants_bench(spd, cam, args.steps, args.warmup) if args.variants else None
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(sc, args.kernel, args.cpu_rows_every)
@@ -372,7 +456,7 @@ def main():
                                f"preprocess+bin/sort+raster fwd+raster bwd+preprocess bwd",
                    "n_splats": n, "width": W, "height": H, "kernel": args.kernel, "visible": n_vis, "instances": K,
                    "splats_per_s": round(n * args.steps / wall, 1),
-                   "stage_ms": {k: round(v, 4) for k, v in per_stage.items()}},
+                   "stage_ms": {k: round(v, 4) for k, v in per_stage.items()}, "variants": variants},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "multiview": multiview_stats,

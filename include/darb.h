@@ -133,7 +133,9 @@ typedef struct {
  *   xy       [n][2]   projected mean mu' in pixels
  *   depth    [n]      camera-space t_z
  *   radius   [n]      ceil(3 sqrt(lambda_max)) in pixels; 0 = culled (other fields undefined)
- *   conic_o  [n][4]   (a, b, c, opacity) with Q = [[a, b], [b, c]] = inverse 2D covariance
+ *   conic_o  [n][4]   (l00, l01, l11, opacity): the conic Q = [[a, b], [b, c]] (inverse 2D
+ *                     covariance) as its factor Q = L^T L, L = [[l00, l01], [0, l11]]
+ *                     (l00, l11 > 0), so that E = |L d|^2 is a sum of squares
  *   rgb      [n][3]   colour after the SH evaluation and the clamp at 0
  *   clamped  [n]      bit c set when channel c was clamped at 0                       */
 typedef struct {
@@ -232,7 +234,8 @@ DARB_API size_t darb_bin_sort_workspace(int64_t n, int32_t width, int32_t height
  *   keys      [k_capacity] u64, nullable (the raster stages do not need keys)
  *   vals      [k_capacity] u32 splat indices in sorted order
  *   ranges    [tiles][2]  u32: ranges[t] = (#instances with tile < t, #instances with tile <= t)
- *   k_dev     [1] int64 device: K, the number of instances (always written)
+ *   k_dev     [2] int64 device: K, the number of instances, and N_v, the number of
+ *             splats with radius > 0 whose box covers a tile (always written)
  *   overflow_dev [1] int32 device: 1 when K > k_capacity, else 0 (always written);
  *             with overflow set keys, vals and ranges are not written and the
  *             raster calls given the same flag do nothing
@@ -330,6 +333,49 @@ DARB_API darb_status darb_preprocess_bwd(const darb_camera *cam, const darb_kern
 DARB_API darb_status darb_image_loss(const float *image, const float *target, int32_t width, int32_t height,
                                      int32_t loss_kind, float *dL_dimage, float *loss_dev, void *ws, size_t ws_bytes,
                                      void *stream);
+
+/*
+ * darb_ssim_loss -- the training loss of the Backpropagation section,
+ * (1 - lambda) L1 + lambda (1 - SSIM), over a rendered view and its target:
+ * L1 and SSIM are means over the 3 W H values; SSIM per channel with an 11x11
+ * Gaussian window (sigma 1.5, zero padding), C1 = 0.01^2, C2 = 0.03^2.
+ *   dL_dimage required [3][H][W]: the gradient of the loss
+ *   loss_dev  nullable [1]: the loss value, summed in a fixed order (reproducible)
+ *   ws        darb_ssim_loss_workspace(width, height) bytes
+ */
+DARB_API size_t darb_ssim_loss_workspace(int32_t width, int32_t height);
+DARB_API darb_status darb_ssim_loss(const float *image, const float *target, int32_t width, int32_t height,
+                                    float lambda, float *dL_dimage, float *loss_dev, void *ws, size_t ws_bytes,
+                                    void *stream);
+
+/*
+ * darb_adam -- one Adam step over up to DARB_MAX_ADAM_GROUPS parameter tensors
+ * in one launch (the optimiser of the training the paper keeps from 3DGS):
+ *   m = beta1 m + (1 - beta1) g;  v = beta2 v + (1 - beta2) g^2;
+ *   p -= lr / (1 - beta1^step) * m / (sqrt(v) / sqrt(1 - beta2^step) + eps)
+ * step >= 1 counts the steps taken, this one included.  param, m, v are
+ * updated in place; grad is read.
+ */
+#define DARB_MAX_ADAM_GROUPS 8
+typedef struct {
+    float *param;
+    const float *grad;
+    float *m;
+    float *v;
+    int64_t n;
+    float lr;
+} darb_adam_group;
+DARB_API darb_status darb_adam(const darb_adam_group *groups, int32_t n_groups, int32_t step, float beta1, float beta2,
+                               float eps, void *stream);
+
+/*
+ * darb_densify_stats -- statistics the 3DGS densification reads after each
+ * backward: for every splat with radius > 0 in this view,
+ *   grad_accum += |dL/dmu'| (the 2D mean gradient norm, pixels),  count += 1,
+ *   max_radius = max(max_radius, radius)   (max_radius nullable).
+ */
+DARB_API darb_status darb_densify_stats(const darb_grads2d *g2d, const int32_t *radius, int64_t n, float *grad_accum,
+                                        int32_t *count, int32_t *max_radius, void *stream);
 
 /*
  * Multi-view calls: nv views (1 <= nv <= DARB_MAX_VIEWS) of the same n splats

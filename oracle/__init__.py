@@ -329,3 +329,91 @@ def render_bwd_views(cams: list, k: KernelSpec, opts: Opts, params: dict, Gs: li
         per_view.append(g2d)
         total = {kk: v.copy() for kk, v in g3d.items()} if total is None else {kk: total[kk] + g3d[kk] for kk in total}
     return per_view, total
+
+
+# ---------------------------------------------------------------------------
+# Training-step companions (FP64): the L1 + D-SSIM loss of the Backpropagation
+# section, one Adam step, the densification statistics.
+# ---------------------------------------------------------------------------
+
+SSIM_RADIUS = 5
+SSIM_SIGMA = 1.5
+SSIM_C1 = 0.01 ** 2
+SSIM_C2 = 0.03 ** 2
+
+
+def ssim_window() -> np.ndarray:
+    """The normalised 11-tap Gaussian (sigma 1.5) of the separable SSIM window."""
+    d = np.arange(-SSIM_RADIUS, SSIM_RADIUS + 1, dtype=np.float64)
+    g = np.exp(-d * d / (2.0 * SSIM_SIGMA ** 2))
+    return g / g.sum()
+
+
+def window_filter(img2d) -> np.ndarray:
+    """Window-weighted sums of a 2D array with zero padding outside the image."""
+    a = _f64(img2d)
+    H, W = a.shape
+    g = ssim_window()
+    r = SSIM_RADIUS
+    pad = np.pad(a, r)
+    rows = sum(g[t] * pad[:, t:t + W] for t in range(2 * r + 1))
+    return sum(g[t] * rows[t:t + H, :] for t in range(2 * r + 1))
+
+
+def ssim_map(x2d, y2d):
+    """Per-pixel SSIM of one channel, and its partial derivatives with respect to
+    the window mean of x, the window variance of x and the window covariance."""
+    x, y = _f64(x2d), _f64(y2d)
+    mx, my = window_filter(x), window_filter(y)
+    vx = window_filter(x * x) - mx * mx
+    vy = window_filter(y * y) - my * my
+    cxy = window_filter(x * y) - mx * my
+    n1, n2 = 2 * mx * my + SSIM_C1, 2 * cxy + SSIM_C2
+    d1, d2 = mx * mx + my * my + SSIM_C1, vx + vy + SSIM_C2
+    S = n1 * n2 / (d1 * d2)
+    dS_dmx = 2 * my * n2 / (d1 * d2) - S * 2 * mx / d1
+    dS_dvx = -S / d2
+    dS_dcxy = 2 * n1 / (d1 * d2)
+    return S, dS_dmx, dS_dvx, dS_dcxy, mx, my
+
+
+def ssim_loss(image, target, lam: float):
+    """(1 - lam) mean|I - I_t| + lam (1 - mean SSIM) over a [3, H, W] image, and its
+    gradient dL/dI.  The gradient of sum_p SSIM_p with respect to x_q collects,
+    through every window containing q, the chain through the window mean, the
+    variance E[x^2] - mean^2 and the covariance E[x y] - mean_x mean_y."""
+    I, T = _f64(image), _f64(target)
+    m = I.size
+    ssum = 0.0
+    grad = np.zeros_like(I)
+    for c in range(I.shape[0]):
+        S, A, B, C, mx, my = ssim_map(I[c], T[c])
+        ssum += S.sum()
+        dsum = window_filter(A - 2 * B * mx - C * my) + 2 * I[c] * window_filter(B) + T[c] * window_filter(C)
+        grad[c] = ((1 - lam) * np.sign(I[c] - T[c]) - lam * dsum) / m
+    loss = (1 - lam) * np.abs(I - T).sum() / m + lam * (1 - ssum / m)
+    return float(loss), grad
+
+
+def adam_step(param, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-15):
+    """One Adam step (returns new param, m, v), FP64."""
+    p, g, m, v = _f64(param), _f64(grad), _f64(m), _f64(v)
+    m = beta1 * m + (1 - beta1) * g
+    v = beta2 * v + (1 - beta2) * g * g
+    denom = np.sqrt(v) / np.sqrt(1 - beta2 ** step) + eps
+    return p - lr / (1 - beta1 ** step) * m / denom, m, v
+
+
+def densify_stats(g_xy, radius, grad_accum, count, max_radius):
+    """Per splat with radius > 0: accumulate the 2D mean-gradient norm and the
+    view count, and keep the largest radius."""
+    g = _f64(g_xy).reshape(-1, 2)
+    r = np.asarray(radius)
+    vis = r > 0
+    acc = _f64(grad_accum).copy()
+    cnt = np.array(count, dtype=np.int64, copy=True)
+    mr = np.array(max_radius, dtype=np.int64, copy=True)
+    acc[vis] += np.sqrt((g[vis] ** 2).sum(1))
+    cnt[vis] += 1
+    mr[vis] = np.maximum(mr[vis], r[vis])
+    return acc, cnt, mr

@@ -17,11 +17,13 @@ from . import pipeline
 
 class DarbRasterize(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, means, scales, quats, opacity, sh, cam: dict, kernel, opts: dict | None, sh_degree: int):
+    def forward(ctx, means, scales, quats, opacity, sh, cam: dict, kernel, opts: dict | None, sh_degree: int,
+                owner=None):
         splats = dict(means=means.detach().contiguous(), scales=scales.detach().contiguous(),
                       quats=quats.detach().contiguous(), opacity=opacity.detach().contiguous(),
                       sh=sh.detach().contiguous(), sh_degree=int(sh_degree))
-        frame = pipeline.render(splats, cam, kernel, opts)
+        frame = owner.render(splats, cam) if owner is not None else pipeline.render(splats, cam, kernel, opts)
+        ctx.owner = owner
         ctx.frame = frame
         ctx.splats = splats
         ctx.cam = cam
@@ -31,10 +33,14 @@ class DarbRasterize(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, grad_image):
+        grads = None
+        if ctx.owner is not None:  # reuse the owner's 2D-gradient buffers; fresh 3D gradients (returned)
+            n, deg = ctx.frame.n, ctx.splats["sh_degree"]
+            grads = (ctx.owner.grads2d(n), pipeline.alloc_grads(n, deg, "cuda")[1])
         g2d, g3d = pipeline.render_backward(ctx.frame, grad_image.contiguous(), ctx.splats, ctx.cam, ctx.kernel,
-                                            ctx.opts)
+                                            ctx.opts, grads=grads)
         ctx.frame = None
-        return g3d["means"], g3d["scales"], g3d["quats"], g3d["opacity"], g3d["sh"], None, None, None, None
+        return (g3d["means"], g3d["scales"], g3d["quats"], g3d["opacity"], g3d["sh"], None, None, None, None, None)
 
 
 def rasterize(means, scales, quats, opacity, sh, cam: dict, kernel="half_cos", opts: dict | None = None,
@@ -45,3 +51,40 @@ def rasterize(means, scales, quats, opacity, sh, cam: dict, kernel="half_cos", o
     if sh_degree is None:
         sh_degree = int(round(sh.shape[0] ** 0.5)) - 1
     return DarbRasterize.apply(means, scales, quats, opacity, sh, cam, kernel, opts, sh_degree)
+
+
+class Rasterizer:
+    """Differentiable renderer that keeps its device buffers between steps (one
+    view size at a time): no allocation per step, and the instance count is
+    read back only to check for a capacity overflow (then the list grows by
+    ``k_margin`` and the view is rendered again)."""
+
+    def __init__(self, kernel="half_cos", opts: dict | None = None, k_margin: float = 1.1):
+        self.kernel = pipeline.KERNELS[kernel] if isinstance(kernel, str) else kernel
+        self.opts = opts
+        self.k_margin = k_margin
+        self.frame = None
+        self._grads = None
+
+    def render(self, splats: dict, cam: dict):
+        n, W, H = int(splats["means"].shape[1]), int(cam["width"]), int(cam["height"])
+        fr = self.frame
+        if fr is None or (fr.n, fr.width, fr.height) != (n, W, H):
+            fr = self.frame = pipeline.render(splats, cam, self.kernel, self.opts, k_capacity=max(4 * n, 1 << 16))
+            return fr
+        pipeline.render(splats, cam, self.kernel, self.opts, frame=fr, read_k=False)
+        if int(fr.overflow[0].item()) != 0:  # too many instances: grow and render again
+            K = int(fr.k_dev[0].item())
+            pipeline._grow(fr, int(K * self.k_margin), fr.vals.device)
+            pipeline.render(splats, cam, self.kernel, self.opts, frame=fr, read_k=True)
+        return fr
+
+    def grads2d(self, n: int):
+        if self._grads is None or self._grads["opacity"].numel() != n:
+            self._grads = pipeline.alloc_grads(n, 0, "cuda")[0]
+        return self._grads
+
+    def __call__(self, means, scales, quats, opacity, sh, cam: dict, sh_degree: int | None = None):
+        if sh_degree is None:
+            sh_degree = int(round(sh.shape[0] ** 0.5)) - 1
+        return DarbRasterize.apply(means, scales, quats, opacity, sh, cam, self.kernel, self.opts, sh_degree, self)

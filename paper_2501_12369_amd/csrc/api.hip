@@ -485,6 +485,83 @@ darb_status darb_image_loss(const float *image, const float *target, int32_t wid
                       "darb_image_loss");
 }
 
+size_t darb_ssim_loss_workspace(int32_t width, int32_t height) {
+    if (width <= 0 || height <= 0) return 0;
+    if ((int64_t)width * height > ((int64_t)1 << 31)) return 0;
+    return darb::ssim_workspace(width, height);
+}
+
+darb_status darb_ssim_loss(const float *image, const float *target, int32_t width, int32_t height, float lambda,
+                           float *dL_dimage, float *loss_dev, void *ws, size_t ws_bytes, void *stream) {
+    if (width <= 0 || height <= 0) return fail(DARB_ERR_INVALID_ARG, "%s", "width/height must be > 0");
+    if ((int64_t)width * height > ((int64_t)1 << 31)) return fail(DARB_ERR_UNSUPPORTED, "%s", "image too large");
+    if (!(lambda >= 0.0f) || !(lambda <= 1.0f)) return fail(DARB_ERR_INVALID_ARG, "%s", "lambda must be in [0, 1]");
+    REQUIRE_PTR(image);
+    REQUIRE_PTR(target);
+    REQUIRE_PTR(dL_dimage);
+    OPT_PTR(loss_dev);
+    REQUIRE_PTR(ws);
+    const size_t need = darb::ssim_workspace(width, height);
+    if (ws_bytes < need) {
+        snprintf(g_err, sizeof(g_err), "workspace too small: %zu < %zu bytes", ws_bytes, need);
+        return DARB_ERR_INVALID_ARG;
+    }
+    g_err[0] = 0;
+    const darb::RView r = make_rview(darb_projected{}, nullptr, nullptr, nullptr, width, height);
+    return hip_status(darb::launch_ssim_loss(image, target, width, height, lambda, r.loss_scale, dL_dimage, loss_dev,
+                                             ws, (hipStream_t)stream),
+                      "darb_ssim_loss");
+}
+
+darb_status darb_adam(const darb_adam_group *groups, int32_t n_groups, int32_t step, float beta1, float beta2,
+                      float eps, void *stream) {
+    if (!groups) return fail(DARB_ERR_INVALID_ARG, "null pointer: %s", "groups");
+    if (n_groups < 1 || n_groups > DARB_MAX_ADAM_GROUPS)
+        return fail(DARB_ERR_INVALID_ARG, "%s", "n_groups must be in [1, DARB_MAX_ADAM_GROUPS]");
+    if (step < 1) return fail(DARB_ERR_INVALID_ARG, "%s", "step must be >= 1");
+    if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+        return fail(DARB_ERR_INVALID_ARG, "%s", "need 0 <= beta1, beta2 < 1 and eps > 0");
+    darb::AdamGroups G{};
+    int64_t blocks = 0;
+    for (int k = 0; k < n_groups; k++) {
+        const darb_adam_group &g = groups[k];
+        if (g.n < 0) return fail(DARB_ERR_INVALID_ARG, "%s", "group n must be >= 0");
+        if (g.n > 0) {
+            REQUIRE_PTR(g.param);
+            REQUIRE_PTR(g.grad);
+            REQUIRE_PTR(g.m);
+            REQUIRE_PTR(g.v);
+        }
+        if (!isfinite(g.lr)) return fail(DARB_ERR_INVALID_ARG, "%s", "group lr must be finite");
+        G.g[k] = g;
+        blocks += (g.n + 255) / 256;
+    }
+    if (blocks > 0x7FFFFFFFll) return fail(DARB_ERR_UNSUPPORTED, "%s", "too many values");
+    G.ng = n_groups;
+    const double bc1 = 1.0 - pow((double)beta1, (double)step);
+    const double bc2 = 1.0 - pow((double)beta2, (double)step);
+    g_err[0] = 0;
+    return hip_status(darb::launch_adam(G, beta1, beta2, eps, (float)bc1, (float)sqrt(bc2), (hipStream_t)stream),
+                      "darb_adam");
+}
+
+darb_status darb_densify_stats(const darb_grads2d *g2d, const int32_t *radius, int64_t n, float *grad_accum,
+                               int32_t *count, int32_t *max_radius, void *stream) {
+    TRY(check_n(n));
+    if (!g2d) return fail(DARB_ERR_INVALID_ARG, "null pointer: %s", "grads2d");
+    if (n > 0) {
+        REQUIRE_PTR(g2d->xy);
+        REQUIRE_PTR(radius);
+        REQUIRE_PTR(grad_accum);
+        REQUIRE_PTR(count);
+        OPT_PTR(max_radius);
+    }
+    g_err[0] = 0;
+    return hip_status(darb::launch_densify_stats(*g2d, radius, (int)n, grad_accum, count, max_radius,
+                                                 (hipStream_t)stream),
+                      "darb_densify_stats");
+}
+
 darb_status darb_preprocess_multi(const darb_view *views, int32_t nv, const darb_kernel *kernel, int64_t n,
                                   const darb_splats *in, void *stream) {
     darb::KParams kp;

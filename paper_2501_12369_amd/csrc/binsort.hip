@@ -252,7 +252,8 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t 
 __global__ void k_bin_init(Counters *cnt, int64_t *k_dev, int32_t *overflow_dev) {
     if (threadIdx.x == 0) {
         *cnt = Counters{};
-        *k_dev = 0;
+        k_dev[0] = 0;
+        k_dev[1] = 0;
         *overflow_dev = 0;
     }
 }
@@ -329,14 +330,18 @@ __global__ __launch_bounds__(1024) void k_bin_sizes(uint32_t *block_vis, const u
         cnt->c1 = (nv + kL1Threads - 1) / kL1Threads;
         cnt->h1_count = cnt->c1 * (uint32_t)nsuper;
         cnt->K = K;
-        *k_dev = (int64_t)K;
+        k_dev[0] = (int64_t)K;
+        k_dev[1] = (int64_t)nv;
         *overflow_dev = (K > (unsigned long long)k_capacity || K >= 0xFFFFFFFFull) ? 1 : 0;
     }
 }
 
+// Visible splats in index order: depth key, value = compact index, and the
+// compact record (tile box packed in 16-bit halves, splat index) that level 1
+// reads after the sort instead of gathering the projected splat again.
 __global__ __launch_bounds__(256) void k_bin_compact(const float *xy, const int32_t *radius, const float *depth, int n,
                                                      int gx, int gy, const uint32_t *block_off, uint32_t *keys,
-                                                     uint32_t *vals, const int32_t *overflow_dev) {
+                                                     uint32_t *vals, uint4 *crec, const int32_t *overflow_dev) {
     __shared__ uint32_t wv[4];
     if (*overflow_dev) return;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -350,8 +355,25 @@ __global__ __launch_bounds__(256) void k_bin_compact(const float *xy, const int3
         uint32_t pos = block_off[blockIdx.x] + (uint32_t)__popcll(m & lanemask_lt());
         for (int k = 0; k < w; k++) pos += wv[k];
         keys[pos] = __float_as_uint(depth[i]);
-        vals[pos] = (uint32_t)i;
+        vals[pos] = pos;
+        crec[pos] = make_uint4((uint32_t)r.x | ((uint32_t)r.y << 16), (uint32_t)r.z | ((uint32_t)r.w << 16),
+                               (uint32_t)i, 0u);
     }
+}
+
+// Depth-ordered splat indices and tile boxes (one gather of the compact record).
+__global__ __launch_bounds__(256) void k_l1_prep(const uint32_t *sorted_c, const uint4 *crec, const Counters *cnt,
+                                                 uint32_t *sid, uint2 *sbox, const int32_t *overflow_dev) {
+    if (*overflow_dev) return;
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= cnt->n_visible) return;
+    const uint4 rec = crec[sorted_c[j]];
+    sid[j] = rec.z;
+    sbox[j] = make_uint2(rec.x, rec.y);
+}
+
+__device__ __forceinline__ int4 unpack_box(uint2 b) {
+    return make_int4((int)(b.x & 0xFFFFu), (int)(b.x >> 16), (int)(b.y & 0xFFFFu), (int)(b.y >> 16));
 }
 
 // ---------------------------------------------------------------------------
@@ -379,10 +401,8 @@ __device__ __forceinline__ uint32_t pack_local_rect(int4 r, int gxs, int gys) {
 // Level-1 chunks hold 256 depth-ordered splats, one per thread; a splat covers
 // few super-tiles, so each thread walks its own super-tile box.
 
-__global__ __launch_bounds__(kL1Threads) void k_l1_count(const uint32_t *sorted_ids, const float *xy,
-                                                         const int32_t *radius, int gx, int gy, int sxn, int nsuper,
-                                                         const Counters *cnt, uint32_t *h1,
-                                                         const int32_t *overflow_dev) {
+__global__ __launch_bounds__(kL1Threads) void k_l1_count(const uint2 *sbox, int sxn, int nsuper, const Counters *cnt,
+                                                         uint32_t *h1, const int32_t *overflow_dev) {
     extern __shared__ uint32_t cg[];  // [nsuper] splats of this chunk per super-tile
     if (*overflow_dev) return;
     const uint32_t c = blockIdx.x, c1 = cnt->c1, nv = cnt->n_visible;
@@ -390,9 +410,8 @@ __global__ __launch_bounds__(kL1Threads) void k_l1_count(const uint32_t *sorted_
     for (int g = threadIdx.x; g < nsuper; g += kL1Threads) cg[g] = 0;
     __syncthreads();
     uint32_t j = c * kL1Threads + threadIdx.x;
-    int4 r;
-    if (j < nv && splat_box(xy, radius, (int)sorted_ids[j], gx, gy, r)) {
-        SuperBox sb = super_box(r);
+    if (j < nv) {
+        SuperBox sb = super_box(unpack_box(sbox[j]));
         for (int gys = sb.sy0; gys <= sb.sy1; gys++)
             for (int gxs = sb.sx0; gxs <= sb.sx1; gxs++) atomicAdd(&cg[gys * sxn + gxs], 1u);
     }
@@ -400,14 +419,13 @@ __global__ __launch_bounds__(kL1Threads) void k_l1_count(const uint32_t *sorted_
     for (int g = threadIdx.x; g < nsuper; g += kL1Threads) h1[(size_t)g * c1 + c] = cg[g];  // super-tile-major
 }
 
-__global__ __launch_bounds__(kL1Threads) void k_l1_scatter(const uint32_t *sorted_ids, const float *xy,
-                                                           const int32_t *radius, int gx, int gy, int sxn, int nsuper,
+__global__ __launch_bounds__(kL1Threads) void k_l1_scatter(const uint32_t *sid, const uint2 *sbox, int sxn, int nsuper,
                                                            const Counters *cnt, const uint32_t *base1,
                                                            uint32_t *list1, uint32_t *list1r, int64_t list1_cap,
                                                            const int32_t *overflow_dev) {
     // per super-tile: a 256-bit set of the chunk's covering threads, and the chunk's first slot
     extern __shared__ uint32_t lds1[];
-    uint32_t *bits = lds1;                   // [nsuper][8]
+    uint32_t *bits = lds1;                   // [8][nsuper]: word-major (lanes of a wave hit distinct banks)
     uint32_t *first = lds1 + nsuper * 8;     // [nsuper]
     if (*overflow_dev) return;
     const uint32_t c = blockIdx.x, c1 = cnt->c1, nv = cnt->n_visible;
@@ -419,23 +437,22 @@ __global__ __launch_bounds__(kL1Threads) void k_l1_scatter(const uint32_t *sorte
     const uint32_t bit = 1u << (threadIdx.x & 31);
     uint32_t j = c * kL1Threads + threadIdx.x;
     uint32_t id = 0;
-    int4 r;
-    bool vis = false;
+    int4 r = make_int4(0, 0, 0, 0);
     SuperBox sb{0, -1, 0, -1};
     if (j < nv) {
-        id = sorted_ids[j];
-        vis = splat_box(xy, radius, (int)id, gx, gy, r);
-        if (vis) sb = super_box(r);
+        id = sid[j];
+        r = unpack_box(sbox[j]);
+        sb = super_box(r);
     }
     for (int gys = sb.sy0; gys <= sb.sy1; gys++)
-        for (int gxs = sb.sx0; gxs <= sb.sx1; gxs++) atomicOr(&bits[(gys * sxn + gxs) * 8 + word], bit);
+        for (int gxs = sb.sx0; gxs <= sb.sx1; gxs++) atomicOr(&bits[word * nsuper + gys * sxn + gxs], bit);
     __syncthreads();
     // rank = covering threads of lower index (depth order) -> stable
     for (int gys = sb.sy0; gys <= sb.sy1; gys++)
         for (int gxs = sb.sx0; gxs <= sb.sx1; gxs++) {
             const int g = gys * sxn + gxs;
-            uint32_t rank = (uint32_t)__popc(bits[g * 8 + word] & (bit - 1u));
-            for (int k = 0; k < word; k++) rank += (uint32_t)__popc(bits[g * 8 + k]);
+            uint32_t rank = (uint32_t)__popc(bits[word * nsuper + g] & (bit - 1u));
+            for (int k = 0; k < word; k++) rank += (uint32_t)__popc(bits[k * nsuper + g]);
             uint32_t pos = first[g] + rank;
             if ((int64_t)pos < list1_cap) {
                 list1[pos] = id;
@@ -566,27 +583,30 @@ static_assert(kSuper == 8, "column and row masks are 8 ballots each");
 
 // A lane covers tile (c, r) iff it covers column c and row r, so the wave's
 // lanes covering the tile are colB[c] & rowB[r]: sixteen ballots give all 64
-// tile masks.  The masks are also stored to the wave's LDS slots (every lane
-// writes the same value: no lane-dependent branch next to the ballots).
+// tile masks.  Lane 0 also stores them to the wave's LDS slots (the ballots
+// are used again after the branch, so they stay in wave-uniform code).
 __device__ __forceinline__ void l2_colrow(const LRect &L, uint64_t (&colB)[kSuper], uint64_t (&rowB)[kSuper],
                                           uint64_t *lds_masks) {
 #pragma unroll
     for (int c = 0; c < kSuper; c++) colB[c] = __ballot((c >= L.c0) & (c < L.c1));
 #pragma unroll
     for (int r = 0; r < kSuper; r++) rowB[r] = __ballot((r >= L.r0) & (r < L.r1));
+    if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-    for (int k = 0; k < kSuper; k++) {
-        lds_masks[k] = colB[k];
-        lds_masks[kSuper + k] = rowB[k];
+        for (int k = 0; k < kSuper; k++) {
+            lds_masks[k] = colB[k];
+            lds_masks[kSuper + k] = rowB[k];
+        }
     }
 }
 
-// wc[tl * kL2Waves + w] = lanes of wave w covering tile tl (lane tl computes it
-// from the wave's masks in LDS).  Needs a barrier between l2_colrow and this.
+// wc[w * 64 + tl] = lanes of wave w covering tile tl (lane tl computes it from
+// the wave's masks in LDS; wave-major, so the lanes write distinct banks).
+// Needs a barrier between l2_colrow and this.
 __device__ __forceinline__ void l2_counts(const uint64_t *lds_masks, uint32_t *wc) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint64_t m = lds_masks[lane & (kSuper - 1)] & lds_masks[kSuper + lane / kSuper];
-    wc[lane * kL2Waves + w] = (uint32_t)__popcll(m);
+    wc[w * 64 + lane] = (uint32_t)__popcll(m);
 }
 
 __global__ __launch_bounds__(kL2Threads) void k_l2_count(const uint32_t *list1r, const uint32_t *l1_start,
@@ -616,7 +636,7 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_count(const uint32_t *list1r,
             int tx = (C.g % sxn) * kSuper + (tl & (kSuper - 1)), ty = (C.g / sxn) * kSuper + tl / kSuper;
             if (tx < gx && ty < gy) {
                 uint32_t s = 0;
-                for (int k = 0; k < kL2Waves; k++) s += wc[tl * kL2Waves + k];
+                for (int k = 0; k < kL2Waves; k++) s += wc[k * 64 + tl];
                 h2[toff[ty * gx + tx] + C.c2] = s;
             }
         }
@@ -656,19 +676,20 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_scatter(const uint32_t *list1
         l2_counts(masks[w], wc);
         __syncthreads();
         const int tx0 = (C.g % sxn) * kSuper, ty0 = (C.g / sxn) * kSuper;
-        if (threadIdx.x < kSuper * kSuper * kL2Waves) {
-            // thread (tile tl, wave ww): first slot of wave ww's entries in tile tl
-            const int tl = threadIdx.x / kL2Waves, ww = threadIdx.x % kL2Waves;
+        {
+            // thread (wave ww, tile tl): first slot of wave ww's entries in tile tl
+            static_assert(kSuper * kSuper * kL2Waves == kL2Threads, "one thread per (wave, tile)");
+            const int ww = threadIdx.x >> 6, tl = threadIdx.x & 63;
             const int tx = tx0 + (tl & (kSuper - 1)), ty = ty0 + tl / kSuper;
             if (tx < gx && ty < gy) {
                 uint32_t s = base2[toff[ty * gx + tx] + C.c2];
-                for (int k = 0; k < ww; k++) s += wc[tl * kL2Waves + k];
+                for (int k = 0; k < ww; k++) s += wc[k * 64 + tl];
                 slot[threadIdx.x] = s;
             }
         }
         __syncthreads();
         // lane tl holds this wave's first slot in tile tl; broadcast per tile with v_readlane
-        const uint32_t myslot = slot[lane * kL2Waves + w];
+        const uint32_t myslot = slot[w * 64 + lane];
         for (int rr = 0; rr < kSuper; rr++) {
             if (rowB[rr] == 0ull) continue;  // no lane of this wave covers the row (uniform)
             for (int cc = 0; cc < kSuper; cc++) {
@@ -705,7 +726,7 @@ __global__ __launch_bounds__(256) void k_bin_ranges(const uint32_t *base2, const
 inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct WsLayout {
-    size_t counters, blockvis, blockarea, keysA, valsA, keysB, valsB, hist, h1, list1, list1r, l1start, l1len, c2start,
+    size_t counters, blockvis, blockarea, keysA, valsA, keysB, valsB, crec, sid, sbox, hist, h1, list1, list1r, l1start, l1len, c2start,
         toff, h2, parts, total;
     uint32_t hist_n, h1_n, h2_n;
 };
@@ -734,6 +755,9 @@ WsLayout layout(int n, int gx, int gy, int64_t k_capacity) {
     L.valsA = off; off += align_up((size_t)n * 4);
     L.keysB = off; off += align_up((size_t)n * 4);
     L.valsB = off; off += align_up((size_t)n * 4);
+    L.crec = off; off += align_up((size_t)n * 16);
+    L.sid = off; off += align_up((size_t)n * 4);
+    L.sbox = off; off += align_up((size_t)n * 8);
     L.hist = off; off += align_up((size_t)L.hist_n * 4);
     L.h1 = off; off += align_up((size_t)L.h1_n * 4);
     L.list1 = off; off += align_up(cap * 4);
@@ -811,8 +835,11 @@ hipError_t launch_bin_sort(const darb_projected &p, int n, int width, int height
     hipLaunchKernelGGL(k_bin_sizes, dim3(1), dim3(1024), 0, s, blockvis, blockarea, nkb, nsuper, cnt, k_capacity, k_dev,
                        overflow_dev);
     if (n > 0) {
+        uint4 *crec = reinterpret_cast<uint4 *>(base + L.crec);
+        uint32_t *sid = U(L.sid);
+        uint2 *sbox = reinterpret_cast<uint2 *>(base + L.sbox);
         hipLaunchKernelGGL(k_bin_compact, dim3(nkb), dim3(256), 0, s, p.xy, p.radius, p.depth, n, gx, gy, blockvis, kA,
-                           vA, overflow_dev);
+                           vA, crec, overflow_dev);
         // depth sort of the N_v visible keys: 4 passes of 8 bits
         const int nblk = (n + kRadixTile - 1) / kRadixTile;
         uint32_t *ki = kA, *vi = vA, *ko = kB, *vo = vB;
@@ -825,15 +852,16 @@ hipError_t launch_bin_sort(const darb_projected &p, int n, int width, int height
             std::swap(ki, ko);
             std::swap(vi, vo);
         }
-        const uint32_t *sorted = vi;  // even number of passes: back in vA
+        const uint32_t *sorted = vi;  // compact indices in (depth, index) order
+        hipLaunchKernelGGL(k_l1_prep, dim3(nkb), dim3(256), 0, s, sorted, crec, cnt, sid, sbox, overflow_dev);
         const int c1max = (n + kL1Threads - 1) / kL1Threads;
         const size_t lds1 = (size_t)nsuper * 4;
-        hipLaunchKernelGGL(k_l1_count, dim3(c1max), dim3(kL1Threads), lds1, s, sorted, p.xy, p.radius, gx, gy, sxn,
-                           nsuper, cnt, h1, overflow_dev);
+        hipLaunchKernelGGL(k_l1_count, dim3(c1max), dim3(kL1Threads), lds1, s, sbox, sxn, nsuper, cnt, h1,
+                           overflow_dev);
         if ((e = scan_exclusive(h1, &cnt->h1_count, L.h1_n, parts, &cnt->total1, overflow_dev, s)) != hipSuccess)
             return e;
-        hipLaunchKernelGGL(k_l1_scatter, dim3(c1max), dim3(kL1Threads), 9 * lds1, s, sorted, p.xy, p.radius, gx, gy, sxn,
-                           nsuper, cnt, h1, list1, list1r, std::max<int64_t>(k_capacity, 1), overflow_dev);
+        hipLaunchKernelGGL(k_l1_scatter, dim3(c1max), dim3(kL1Threads), 9 * lds1, s, sid, sbox, sxn, nsuper, cnt, h1,
+                           list1, list1r, std::max<int64_t>(k_capacity, 1), overflow_dev);
     }
     hipLaunchKernelGGL(k_l2_plan, dim3(1), dim3(1024), 0, s, h1, cnt, nsuper, sxn, gx, gy, l1start, l1len, c2start,
                        toff, overflow_dev);

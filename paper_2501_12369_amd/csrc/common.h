@@ -160,6 +160,10 @@ __device__ __forceinline__ float profile_deriv(float E, float w, const KParams &
 }
 
 // One (pixel, splat) pair: offsets, Q d, E, profile, alpha, and the decision.
+// The conic arrives as its upper-triangular factor, Q = L^T L with
+// L = [[l00, l01], [0, l11]], so E = |L d|^2 is a sum of two squares: no
+// cancellation for needle-like footprints, where a dx^2 + 2 b dx dy + c dy^2
+// loses ~1e-3 in FP32 along the needle.  Q d = L^T (L d) feeds the gradients.
 // Shared verbatim by the forward and the backward raster kernels.
 struct Pair {
     float dx, dy, q0, q1, E, w, alpha;
@@ -167,14 +171,16 @@ struct Pair {
 };
 
 template <int KIND>
-__device__ __forceinline__ Pair eval_pair(float sx, float sy, float a, float b, float c, float o, float px, float py,
-                                          const KParams &kp, float amin, float amax) {
+__device__ __forceinline__ Pair eval_pair(float sx, float sy, float l00, float l01, float l11, float o, float px,
+                                          float py, const KParams &kp, float amin, float amax) {
     Pair p;
     p.dx = sx - px;
     p.dy = sy - py;
-    p.q0 = fmaf(a, p.dx, b * p.dy);
-    p.q1 = fmaf(b, p.dx, c * p.dy);
-    p.E = fmaf(p.q0, p.dx, p.q1 * p.dy);
+    const float t0 = fmaf(l00, p.dx, l01 * p.dy);
+    const float t1 = l11 * p.dy;
+    p.E = fmaf(t0, t0, t1 * t1);
+    p.q0 = l00 * t0;
+    p.q1 = fmaf(l01, t0, l11 * t1);
     bool inside = (p.E >= 0.0f) & (p.E <= kp.e_max);
     // outside the support the profile value is never used: every consumer
     // selects on `ok`, so no clamp of E is needed here
@@ -335,5 +341,18 @@ hipError_t launch_zero(float *a, size_t n, hipStream_t s);
 constexpr uint32_t kLossBlocks = 1024;  // partial sums of the image loss (fixed, so the total is reproducible)
 hipError_t launch_image_loss(int loss, const float *image, const float *target, int width, int height, float scale,
                              float *dL_dimage, float *loss_dev, float *partials, hipStream_t s);
+size_t ssim_workspace(int width, int height);
+hipError_t launch_ssim_loss(const float *image, const float *target, int width, int height, float lambda, float scale,
+                            float *dL_dimage, float *loss_dev, void *ws, hipStream_t s);
+
+constexpr int kMaxAdamGroups = 8;
+struct AdamGroups {
+    darb_adam_group g[kMaxAdamGroups];
+    int ng;
+};
+hipError_t launch_adam(const AdamGroups &groups, float beta1, float beta2, float eps, float bc1, float bc2_sqrt,
+                       hipStream_t s);
+hipError_t launch_densify_stats(const darb_grads2d &g2d, const int32_t *radius, int n, float *grad_accum,
+                                int32_t *count, int32_t *max_radius, hipStream_t s);
 
 }  // namespace darb

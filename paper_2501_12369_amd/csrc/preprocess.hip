@@ -130,7 +130,8 @@ struct Proj {
     float A[6];          // J R_cw, 2x3
     float c00, c01, c11; // 2D covariance
     float det;
-    float a, b, c;       // conic
+    float a, b, c;       // conic Q = [[a, b], [b, c]]
+    float l00, l01, l11; // Q = L^T L, L = [[l00, l01], [0, l11]]
     float u, v;          // mean2D
     int radius;
 };
@@ -203,28 +204,43 @@ __device__ __forceinline__ bool project_rest(const Cam &cam, const KParams &kp, 
         P.A[cc] = fmaf(P.J00, R[cc], P.J02 * R[6 + cc]);
         P.A[3 + cc] = fmaf(P.J11, R[3 + cc], P.J12 * R[6 + cc]);
     }
-    // M = A Sigma A^T
-    const float *S = G.Sig;  // xx xy xz yy yz zz
-    float AS0[3], AS1[3];
-    for (int r = 0; r < 2; r++) {
-        const float *a = P.A + 3 * r;
-        float *o = r ? AS1 : AS0;
-        o[0] = fmaf(a[0], S[0], fmaf(a[1], S[1], a[2] * S[2]));
-        o[1] = fmaf(a[0], S[1], fmaf(a[1], S[3], a[2] * S[4]));
-        o[2] = fmaf(a[0], S[2], fmaf(a[1], S[4], a[2] * S[5]));
-    }
-    float M00 = fmaf(AS0[0], P.A[0], fmaf(AS0[1], P.A[1], AS0[2] * P.A[2]));
-    float M01 = fmaf(AS0[0], P.A[3], fmaf(AS0[1], P.A[4], AS0[2] * P.A[5]));
-    float M11 = fmaf(AS1[0], P.A[3], fmaf(AS1[1], P.A[4], AS1[2] * P.A[5]));
+    // M = A Sigma A^T = B B^T with B = A Rq diag(s) (2x3).  The entries are dot
+    // products of B's rows; the determinant comes from Cauchy-Binet,
+    // det(B B^T) = sum of the squared 2x2 minors of B, each minor with Kahan's
+    // FMA difference: no cancellation, so needle-like footprints (M nearly of
+    // rank 1, the minor axis set by the dilation) keep an accurate conic.
+    float Bm[2][3];
+    for (int r = 0; r < 2; r++)
+        for (int cc = 0; cc < 3; cc++)
+            Bm[r][cc] = fmaf(P.A[3 * r], G.Rq[cc], fmaf(P.A[3 * r + 1], G.Rq[3 + cc], P.A[3 * r + 2] * G.Rq[6 + cc])) *
+                        G.s[cc];
+    float M00 = fmaf(Bm[0][0], Bm[0][0], fmaf(Bm[0][1], Bm[0][1], Bm[0][2] * Bm[0][2]));
+    float M01 = fmaf(Bm[0][0], Bm[1][0], fmaf(Bm[0][1], Bm[1][1], Bm[0][2] * Bm[1][2]));
+    float M11 = fmaf(Bm[1][0], Bm[1][0], fmaf(Bm[1][1], Bm[1][1], Bm[1][2] * Bm[1][2]));
+    auto minor2 = [&](int i, int j) {  // Bm[0][i] Bm[1][j] - Bm[0][j] Bm[1][i], Kahan
+        const float w = Bm[0][j] * Bm[1][i];
+        const float e = fmaf(-Bm[0][j], Bm[1][i], w);
+        return fmaf(Bm[0][i], Bm[1][j], -w) + e;
+    };
+    const float m01 = minor2(0, 1), m02 = minor2(0, 2), m12 = minor2(1, 2);
+    const float detM = fmaf(m01, m01, fmaf(m02, m02, m12 * m12));
     P.c00 = fmaf(kp.psi, M00, cam.dilation);
     P.c01 = kp.psi * M01;
     P.c11 = fmaf(kp.psi, M11, cam.dilation);
-    P.det = fmaf(P.c00, P.c11, -(P.c01 * P.c01));
+    // det(psi M + eps I) = psi^2 det M + eps psi tr M + eps^2
+    const float eps = cam.dilation;
+    P.det = fmaf(kp.psi * kp.psi, detM, eps * fmaf(kp.psi, M00 + M11, eps));
     if (!(P.det > 0.0f)) return false;
     float idet = 1.0f / P.det;
     P.a = P.c11 * idet;
     P.b = -P.c01 * idet;
     P.c = P.c00 * idet;
+    // factor of Q from the covariance, no subtraction: l11 = 1/sqrt(c11),
+    // l00 = sqrt(c11/det), l01 = -c01/sqrt(c11 det)
+    const float rc11 = rsqrtf(P.c11);
+    P.l11 = rc11;
+    P.l00 = sqrtf(P.c11 * idet);
+    P.l01 = -P.c01 * rsqrtf(P.c11 * P.det);
     P.u = fmaf(cam.fx, P.t[0] * itz, cam.cx);
     P.v = fmaf(cam.fy, P.t[1] * itz, cam.cy);
     float mid = 0.5f * (P.c00 + P.c11);
@@ -316,7 +332,7 @@ __device__ __forceinline__ void store_proj(const darb_projected &out, int i, boo
     reinterpret_cast<float2 *>(out.xy)[i] = vis ? make_float2(P.u, P.v) : make_float2(0.0f, 0.0f);
     out.depth[i] = vis ? P.t[2] : 0.0f;
     out.radius[i] = vis ? P.radius : 0;
-    reinterpret_cast<float4 *>(out.conic_o)[i] = vis ? make_float4(P.a, P.b, P.c, op) : make_float4(0, 0, 0, 0);
+    reinterpret_cast<float4 *>(out.conic_o)[i] = vis ? make_float4(P.l00, P.l01, P.l11, op) : make_float4(0, 0, 0, 0);
     out.rgb[3 * i] = col[0];
     out.rgb[3 * i + 1] = col[1];
     out.rgb[3 * i + 2] = col[2];
@@ -375,12 +391,13 @@ __global__ __launch_bounds__(256) void k_preprocess_multi(Cams cams, KParams kp,
 }
 
 // Per-view part of the gradient of one visible splat: the mean (through mu',
-// J and the SH direction), dL/dSigma (full 3x3), and Y, gv such that
+// J and the SH direction), dL/dM for M = A Sigma A^T (symmetric 2x2: dM[0] =
+// d/dM00, dM[1] = d/dM01 (one entry), dM[2] = d/dM11), and Y, gv such that
 // d/d sh[b][ch] = Y[b] * gv[ch].
 template <int NB>
 __device__ __forceinline__ void splat_bwd_view(const Cam &cam, const KParams &kp, int i, const float (&m)[3],
                                                const float (&csh)[NB][3], const darb_grads2d &g2, const Geom &G,
-                                               const Proj &P, float (&dmu)[3], float (&dS)[9], float (&Y)[NB],
+                                               const Proj &P, float (&dmu)[3], float (&dM)[3], float (&Y)[NB],
                                                float (&gvo)[3]) {
     float grgb[3] = {g2.rgb[3 * i], g2.rgb[3 * i + 1], g2.rgb[3 * i + 2]};
     dmu[0] = dmu[1] = dmu[2] = 0.0f;
@@ -426,15 +443,17 @@ __device__ __forceinline__ void splat_bwd_view(const Cam &cam, const KParams &kp
     float d11 = -fmaf(t10, b, t11 * c);
     // psi: M -> psi M + eps I
     float m00 = kp.psi * d00, m01 = kp.psi * d01, m11 = kp.psi * d11;
-    // M = A Sigma A^T: dSigma = A^T dM A, dA = 2 dM A Sigma
+    dM[0] = m00;
+    dM[1] = m01;
+    dM[2] = m11;
+    // M = A Sigma A^T: dA = 2 dM A Sigma (the scale and rotation part is taken from
+    // dM directly, in geom_bwd)
     const float *A = P.A;
     float dMA0[3], dMA1[3];  // dM A (2x3)
     for (int cc = 0; cc < 3; cc++) {
         dMA0[cc] = fmaf(m00, A[cc], m01 * A[3 + cc]);
         dMA1[cc] = fmaf(m01, A[cc], m11 * A[3 + cc]);
     }
-    for (int r = 0; r < 3; r++)
-        for (int cc = 0; cc < 3; cc++) dS[r * 3 + cc] = fmaf(A[r], dMA0[cc], A[3 + r] * dMA1[cc]);
     const float *Sg = G.Sig;
     float Sf[9] = {Sg[0], Sg[1], Sg[2], Sg[1], Sg[3], Sg[4], Sg[2], Sg[4], Sg[5]};
     float dA[6];
@@ -469,35 +488,47 @@ __device__ __forceinline__ void splat_bwd_view(const Cam &cam, const KParams &kp
     dmu[2] += fmaf(R[2], dtx, fmaf(R[5], dty, R[8] * dtz));
 }
 
-// Sigma = Mq Mq^T, Mq = Rq diag(s): dMq = 2 dSigma Mq; ds_j = sum_r dMq_rj Rq_rj;
-// dRq_rj = dMq_rj s_j; then the rotation-matrix gradient to the quaternion
+// Scale and rotation part of the chain, from dM (M = A Sigma A^T = B B^T,
+// B = C diag(s), C = A Rq): with dMq = 2 A^T dM B,
+//   ds_j  = sum_r dMq_rj Rq_rj = 2 s_j  c_j^T dM c_j        (c_j = column j of C)
+//   dRq_rj = dMq_rj s_j        = 2 s_j^2 (A^T dM C)_rj
+// Working in the projected 2D space keeps each axis separate: forming the 3x3
+// dL/dSigma first and projecting it back on a short axis cancels in FP32 for
+// needle-like splats.  Then the rotation-matrix gradient goes to the quaternion
 // (through the normalisation).
-__device__ __forceinline__ void geom_bwd(const Geom &G, const float (&dS)[9], float (&dsc)[3], float (&dqo)[4]) {
+__device__ __forceinline__ void geom_bwd(const Geom &G, const float (&A)[6], const float (&dM)[3], float (&dsc)[3],
+                                         float (&dqo)[4]) {
     const float *Rq = G.Rq;
+    float C[2][3];
+    for (int r = 0; r < 2; r++)
+        for (int cc = 0; cc < 3; cc++)
+            C[r][cc] = fmaf(A[3 * r], Rq[cc], fmaf(A[3 * r + 1], Rq[3 + cc], A[3 * r + 2] * Rq[6 + cc]));
     float dR[9];
     for (int cc = 0; cc < 3; cc++) {
-        float acc = 0.0f;
-        for (int r = 0; r < 3; r++) {
-            float dm = 2.0f * fmaf(dS[r * 3 + 0], Rq[0 * 3 + cc] * G.s[cc],
-                                   fmaf(dS[r * 3 + 1], Rq[1 * 3 + cc] * G.s[cc], dS[r * 3 + 2] * Rq[2 * 3 + cc] * G.s[cc]));
-            acc = fmaf(dm, Rq[r * 3 + cc], acc);
-            dR[r * 3 + cc] = dm * G.s[cc];
-        }
-        dsc[cc] = acc;
+        // dM c_j
+        const float e0 = fmaf(dM[0], C[0][cc], dM[1] * C[1][cc]);
+        const float e1 = fmaf(dM[1], C[0][cc], dM[2] * C[1][cc]);
+        dsc[cc] = 2.0f * G.s[cc] * fmaf(C[0][cc], e0, C[1][cc] * e1);
+        const float k = 2.0f * G.s[cc] * G.s[cc];
+        for (int r = 0; r < 3; r++) dR[r * 3 + cc] = k * fmaf(A[r], e0, A[3 + r] * e1);
     }
-    float w = G.qn[0], x = G.qn[1], y = G.qn[2], z = G.qn[3];
-    float dq0 = 2.0f * (-z * dR[1] + y * dR[2] + z * dR[3] - x * dR[5] - y * dR[6] + x * dR[7]);
-    float dq1 = 2.0f * (y * dR[1] + z * dR[2] + y * dR[3] - 2.0f * x * dR[4] - w * dR[5] + z * dR[6] + w * dR[7] -
-                        2.0f * x * dR[8]);
-    float dq2 = 2.0f * (-2.0f * y * dR[0] + x * dR[1] + w * dR[2] + x * dR[3] + z * dR[5] - w * dR[6] + z * dR[7] -
-                        2.0f * y * dR[8]);
-    float dq3 = 2.0f * (-2.0f * z * dR[0] - w * dR[1] + x * dR[2] + w * dR[3] - 2.0f * z * dR[4] + y * dR[5] +
-                        x * dR[6] + y * dR[7]);
-    float qd = fmaf(dq0, w, fmaf(dq1, x, fmaf(dq2, y, dq3 * z)));
-    dqo[0] = (dq0 - w * qd) * G.qinv;
-    dqo[1] = (dq1 - x * qd) * G.qinv;
-    dqo[2] = (dq2 - y * qd) * G.qinv;
-    dqo[3] = (dq3 - z * qd) * G.qinv;
+    // Rotation gradient as a small rotation phi applied on the left, R' = (I + [phi]x) R:
+    // dL/dphi is the antisymmetric part of dR R^T.  The unit-quaternion tangent is
+    // (0, phi/2) (x) q, so the gradient in the tangent plane is
+    // 2 (-g.v, w g + g x v) with g = dL/dphi, q = (w, v), and d/dq = that / |q|.
+    // (Going through the raw quaternion derivative and removing its radial part
+    // afterwards cancels in FP32.)
+    float Mk[3][3];
+    for (int r = 0; r < 3; r++)
+        for (int cc = 0; cc < 3; cc++)
+            Mk[r][cc] = fmaf(dR[r * 3 + 0], Rq[cc * 3 + 0], fmaf(dR[r * 3 + 1], Rq[cc * 3 + 1], dR[r * 3 + 2] * Rq[cc * 3 + 2]));
+    const float g0 = Mk[2][1] - Mk[1][2], g1 = Mk[0][2] - Mk[2][0], g2 = Mk[1][0] - Mk[0][1];
+    const float w = G.qn[0], x = G.qn[1], y = G.qn[2], z = G.qn[3];
+    const float s2 = 2.0f * G.qinv;
+    dqo[0] = -s2 * fmaf(g0, x, fmaf(g1, y, g2 * z));
+    dqo[1] = s2 * fmaf(w, g0, fmaf(g1, z, -g2 * y));
+    dqo[2] = s2 * fmaf(w, g1, fmaf(g2, x, -g0 * z));
+    dqo[3] = s2 * fmaf(w, g2, fmaf(g0, y, -g1 * x));
 }
 
 // Gradients of one splat, accumulated over views by the callers.
@@ -542,9 +573,9 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(Cam cam, KParams kp, int
         load_mean(in, n, i, m);
         float csh[NB][3];
         load_sh<NB>(in.sh, n, i, csh);
-        float dS[9], Y[NB], gv[3];
-        splat_bwd_view<NB>(cam, kp, i, m, csh, g2, G, P, g.dmu, dS, Y, gv);
-        geom_bwd(G, dS, g.dsc, g.dq);
+        float dM[3], Y[NB], gv[3];
+        splat_bwd_view<NB>(cam, kp, i, m, csh, g2, G, P, g.dmu, dM, Y, gv);
+        geom_bwd(G, P.A, dM, g.dsc, g.dq);
         g.dop = g2.opacity[i];
 #pragma unroll
         for (int b = 0; b < NB; b++)
@@ -579,9 +610,9 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_multi(Cams cams, KParams
             Proj P;
             if (!(view_depth(cam, m, P) && project_rest(cam, kp, G, P))) continue;
             Grad3 g;
-            float dS[9], Y[NB], gv[3];
-            splat_bwd_view<NB>(cam, kp, i, m, csh, g2.g[v], G, P, g.dmu, dS, Y, gv);
-            geom_bwd(G, dS, g.dsc, g.dq);
+            float dM[3], Y[NB], gv[3];
+            splat_bwd_view<NB>(cam, kp, i, m, csh, g2.g[v], G, P, g.dmu, dM, Y, gv);
+            geom_bwd(G, P.A, dM, g.dsc, g.dq);
             g.dop = g2.g[v].opacity[i];
 #pragma unroll
             for (int c = 0; c < 3; c++) {

@@ -38,7 +38,7 @@ namespace {
 constexpr int kPix = 4;  // pixels per lane
 
 struct Rec {
-    float x, y, a, b, c, o, r, g, bl;
+    float x, y, a, b, c, o, r, g, bl;  // a, b, c: the conic factor (l00, l01, l11)
     uint32_t id;
     int hit;  // the footprint's bounding box meets this tile's pixels
 };
@@ -46,8 +46,10 @@ struct Rec {
 // Record of instance j (zeros when `in` is false or the stored index is out of
 // range; a zero-opacity record never passes the alpha test).  `hit` is false
 // when the ellipse E <= e_max, grown by one pixel, misses the tile's pixel
-// range: for |dx| > sqrt(e_max / Q_xx^-1) every E exceeds e_max by a relative
+// range: for |dx| > sqrt(e_max Sigma'_xx) every E exceeds e_max by a relative
 // margin far above FP32 rounding, so skipping such a splat changes nothing.
+// With Q = L^T L: Sigma' = Q^-1 has Sigma'_xx = (1 + (l01/l11)^2) / l00^2 and
+// Sigma'_yy = 1 / l11^2.
 __device__ __forceinline__ Rec load_rec(const darb_projected &p, const uint32_t *vals, uint32_t j, bool in, int n,
                                         float e_max, float xlo, float ylo) {
     Rec R;
@@ -68,13 +70,14 @@ __device__ __forceinline__ Rec load_rec(const darb_projected &p, const uint32_t 
         R.g = p.rgb[3 * id + 1];
         R.bl = p.rgb[3 * id + 2];
         R.id = id;
-        // half-extents of {E <= e_max}: sqrt(e_max * Sigma'_xx), sqrt(e_max * Sigma'_yy), Sigma' = Q^-1
-        float det = fmaf(co.x, co.z, -(co.y * co.y));
-        float hx = sqrtf(e_max * co.z / det) + 1.0f;
-        float hy = sqrtf(e_max * co.x / det) + 1.0f;
-        bool ok = (det > 0.0f) ? ((xy.x + hx >= xlo) & (xy.x - hx <= xlo + (kTile - 1)) & (xy.y + hy >= ylo) &
-                                  (xy.y - hy <= ylo + (kTile - 1)))
-                               : true;
+        // half-extents of {E <= e_max}: sqrt(e_max * Sigma'_xx), sqrt(e_max * Sigma'_yy)
+        const float r01 = co.y / co.z;
+        float hx = sqrtf(e_max * fmaf(r01, r01, 1.0f)) / co.x + 1.0f;
+        float hy = sqrtf(e_max) / co.z + 1.0f;
+        bool ok = (co.x > 0.0f && co.z > 0.0f)
+                      ? ((xy.x + hx >= xlo) & (xy.x - hx <= xlo + (kTile - 1)) & (xy.y + hy >= ylo) &
+                         (xy.y - hy <= ylo + (kTile - 1)))
+                      : true;
         R.hit = ok ? 1 : 0;
     }
     return R;
@@ -466,25 +469,27 @@ __global__ __launch_bounds__(256) void k_det_reduce(VS A, uint32_t n, const uint
         const uint32_t key = skey[i];
         if (key >= limit) continue;
         if (i > 0 && skey[i - 1] == key) continue;
-        float acc[9];
+        // FP64 sum over the splat's tiles: a large splat collects thousands of
+        // per-tile partials of mixed sign
+        double acc[9];
 #pragma unroll
-        for (int k = 0; k < 9; k++) acc[k] = 0.0f;
+        for (int k = 0; k < 9; k++) acc[k] = 0.0;
         for (uint32_t j = i; j < total && skey[j] == key; j++) {
             const size_t c = sval[j];
 #pragma unroll
-            for (int k = 0; k < 9; k++) acc[k] += parts[(size_t)k * cap + c];
+            for (int k = 0; k < 9; k++) acc[k] += (double)parts[(size_t)k * cap + c];
         }
         const uint32_t vi = key / n, id = key - vi * n;
         const darb_grads2d g = A.grads(vi);
-        g.xy[2 * id] = acc[0];
-        g.xy[2 * id + 1] = acc[1];
-        g.conic[3 * id] = acc[2];
-        g.conic[3 * id + 1] = acc[3];
-        g.conic[3 * id + 2] = acc[4];
-        g.opacity[id] = acc[5];
-        g.rgb[3 * id] = acc[6];
-        g.rgb[3 * id + 1] = acc[7];
-        g.rgb[3 * id + 2] = acc[8];
+        g.xy[2 * id] = (float)acc[0];
+        g.xy[2 * id + 1] = (float)acc[1];
+        g.conic[3 * id] = (float)acc[2];
+        g.conic[3 * id + 1] = (float)acc[3];
+        g.conic[3 * id + 2] = (float)acc[4];
+        g.opacity[id] = (float)acc[5];
+        g.rgb[3 * id] = (float)acc[6];
+        g.rgb[3 * id + 1] = (float)acc[7];
+        g.rgb[3 * id + 2] = (float)acc[8];
     }
 }
 

@@ -27,7 +27,9 @@ EXPORTED = ("darb_version", "darb_status_string", "darb_last_error", "darb_prepr
             "darb_bin_sort_workspace", "darb_bin_sort", "darb_raster_fwd", "darb_raster_bwd",
             "darb_raster_bwd_workspace", "darb_preprocess_bwd", "darb_image_loss", "darb_preprocess_multi",
             "darb_raster_fwd_multi", "darb_raster_bwd_multi", "darb_raster_bwd_multi_workspace",
-            "darb_raster_fwdbwd_multi", "darb_preprocess_bwd_multi")
+            "darb_raster_fwdbwd_multi", "darb_preprocess_bwd_multi", "darb_ssim_loss_workspace", "darb_ssim_loss",
+            "darb_adam", "darb_densify_stats")
+MAX_ADAM_GROUPS = 8
 
 
 class DarbError(RuntimeError):
@@ -74,6 +76,11 @@ class darb_view(ctypes.Structure):
                 ("ranges", c_void_p), ("overflow_dev", c_void_p), ("image", c_void_p), ("final_T", c_void_p),
                 ("last", c_void_p), ("n_contrib", c_void_p), ("dL_dimage", c_void_p), ("target", c_void_p),
                 ("grads2d", darb_grads2d)]
+
+
+class darb_adam_group(ctypes.Structure):
+    _fields_ = [("param", c_void_p), ("grad", c_void_p), ("m", c_void_p), ("v", c_void_p), ("n", c_int64),
+                ("lr", c_float)]
 
 
 _lib = None
@@ -140,6 +147,15 @@ def lib():
         L.darb_preprocess_bwd_multi.restype = c_int32
         L.darb_preprocess_bwd_multi.argtypes = [P(darb_view), c_int32, P(darb_kernel), c_int64, P(darb_splats),
                                                 P(darb_grads3d), c_void_p]
+        L.darb_ssim_loss_workspace.restype = c_size_t
+        L.darb_ssim_loss_workspace.argtypes = [c_int32, c_int32]
+        L.darb_ssim_loss.restype = c_int32
+        L.darb_ssim_loss.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_float, c_void_p, c_void_p, c_void_p,
+                                     c_size_t, c_void_p]
+        L.darb_adam.restype = c_int32
+        L.darb_adam.argtypes = [P(darb_adam_group), c_int32, c_int32, c_float, c_float, c_float, c_void_p]
+        L.darb_densify_stats.restype = c_int32
+        L.darb_densify_stats.argtypes = [P(darb_grads2d), c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]
         _lib = L
     return _lib
 
@@ -378,3 +394,34 @@ def darb_preprocess_bwd_multi(views: list, kernel, n: int, splats: dict, g3d: di
     a, k, s, g3 = views_array(views), kernel_struct(kernel), splats_struct(splats), grads3d_struct(g3d)
     _check(lib().darb_preprocess_bwd_multi(a, len(views), ctypes.byref(k), n, ctypes.byref(s), ctypes.byref(g3),
                                            _stream(stream)), "darb_preprocess_bwd_multi")
+
+
+def darb_ssim_loss_workspace(width: int, height: int) -> int:
+    return int(lib().darb_ssim_loss_workspace(width, height))
+
+
+def darb_ssim_loss(image, target, width: int, height: int, lam: float, dL_dimage, loss_dev=None, ws=None,
+                   stream=None):
+    _check(lib().darb_ssim_loss(_ptr(image), _ptr(target), width, height, float(lam), _ptr(dL_dimage),
+                                _ptr(loss_dev), _ptr(ws), _nbytes(ws), _stream(stream)), "darb_ssim_loss")
+
+
+def darb_adam(groups: list, step: int, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-15, stream=None):
+    """``groups``: dicts with param, grad, m, v (tensors of equal size) and lr."""
+    if not 1 <= len(groups) <= MAX_ADAM_GROUPS:
+        raise ValueError(f"between 1 and {MAX_ADAM_GROUPS} groups")
+    arr = (darb_adam_group * len(groups))()
+    for i, g in enumerate(groups):
+        n = g["param"].numel()
+        for k in ("grad", "m", "v"):
+            if g[k].numel() != n:
+                raise ValueError(f"group {i}: {k} has {g[k].numel()} values, param has {n}")
+        arr[i] = darb_adam_group(_ptr(g["param"]), _ptr(g["grad"]), _ptr(g["m"]), _ptr(g["v"]), n, float(g["lr"]))
+    _check(lib().darb_adam(arr, len(groups), int(step), float(beta1), float(beta2), float(eps), _stream(stream)),
+           "darb_adam")
+
+
+def darb_densify_stats(g2d: dict, radius, n: int, grad_accum, count, max_radius=None, stream=None):
+    g = grads2d_struct(g2d)
+    _check(lib().darb_densify_stats(ctypes.byref(g), _ptr(radius), n, _ptr(grad_accum), _ptr(count),
+                                    _ptr(max_radius), _stream(stream)), "darb_densify_stats")

@@ -187,7 +187,8 @@ def projected(seed: int, n: int, width: int, height: int, sigma_range=(0.5, 12.0
     orientation, depth uniform, opacity uniform, colour uniform in [0, 1].
 
     The conic is the inverse of the drawn covariance R diag(s1^2, s2^2) R^T,
-    stored as (a, b, c, opacity).  ``radius`` is ceil(3 * max(s1, s2)) + 1
+    stored as (a, b, c, opacity); ``conic_l`` holds its upper-triangular
+    factor (l00, l01, l11), Q = L^T L.  ``radius`` is ceil(3 * max(s1, s2)) + 1
     pixels, a bound on the support E <= 9 of every kernel; a fraction
     ``culled_frac`` of splats get radius 0 (culled)."""
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -207,9 +208,13 @@ def projected(seed: int, n: int, width: int, height: int, sigma_range=(0.5, 12.0
     depth = rng.uniform(depth_range[0], depth_range[1], size=n)
     radius = (np.ceil(3.0 * np.maximum(s1, s2)) + 1).astype(np.int32)
     radius[rng.uniform(size=n) < culled_frac] = 0
+    l00 = np.sqrt(qa)
+    l01 = qb / l00
+    l11 = np.sqrt(i1 * i2 / qa)  # c - b^2/a = det Q / a
     f32 = np.float32
     return dict(xy=np.ascontiguousarray(np.stack([x, y], 1), f32), depth=depth.astype(f32), radius=radius,
                 conic_o=np.ascontiguousarray(np.stack([qa, qb, qc, opacity], 1), f32),
+                conic_l=np.ascontiguousarray(np.stack([l00, l01, l11], 1), f32),
                 rgb=np.ascontiguousarray(rgb, f32), width=int(width), height=int(height))
 
 

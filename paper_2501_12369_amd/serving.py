@@ -55,6 +55,7 @@ class Result:
     pixels: int
     retried: bool = False
     image: object = None
+    work: tuple | None = None  # (K, N_v) of the render, when the slot reports them
 
     @property
     def latency(self) -> float:
@@ -197,7 +198,8 @@ class Scheduler:
                         self.peak_bytes = max(self.peak_bytes, self.mem_used)
                     end = self.clock() - t0
                     results.append(Result(req.rid, req.key, req.arrival, start, end, req.pixels, retried,
-                                          s.image_copy() if keep_images else None))
+                                          s.image_copy() if keep_images else None,
+                                          s.counts() if hasattr(s, "counts") else None))
                     self.release(s)
                     progressed = True
                 else:
@@ -281,7 +283,7 @@ class RenderSlot:
             self.cam_dev.copy_(self.cam_host, non_blocking=True)
             self.graph.replay()
             self.ovf_host[0:1].copy_(self.frame.overflow[0:1], non_blocking=True)
-            self.k_host[0:1].copy_(self.frame.k_dev[0:1], non_blocking=True)
+            self.k_host.copy_(self.frame.k_dev[0:2], non_blocking=True)
             self.done.record(self.stream)
 
     def poll(self) -> bool:
@@ -289,6 +291,10 @@ class RenderSlot:
 
     def finish(self):
         return int(self.ovf_host[0]) == 0, int(self.k_host[0])
+
+    def counts(self):
+        """(K, N_v) of the last completed render."""
+        return int(self.k_host[0]), int(self.k_host[1])
 
     def rerun(self, req: Request, K: int):
         """Capacity overflow: grow, re-capture, render again (blocking)."""

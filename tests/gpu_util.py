@@ -46,14 +46,23 @@ def dev(a, dtype=None):
     return t.cuda().contiguous()
 
 
+def conic_from_factor(l) -> np.ndarray:
+    """(a, b, c) of Q = L^T L in FP64 from factors (l00, l01, l11) [n, 3]."""
+    l = np.asarray(l, np.float64)
+    return np.stack([l[:, 0] ** 2, l[:, 0] * l[:, 1], l[:, 1] ** 2 + l[:, 2] ** 2], 1)
+
+
 def projected_to_device(ps: dict) -> dict:
+    """The device records: the conic as its factor (what the library stores)."""
     n = len(ps["radius"])
-    return dict(xy=dev(ps["xy"]), depth=dev(ps["depth"]), radius=dev(ps["radius"]), conic_o=dev(ps["conic_o"]),
+    co = np.concatenate([ps["conic_l"], ps["conic_o"][:, 3:4]], 1).astype(np.float32)
+    return dict(xy=dev(ps["xy"]), depth=dev(ps["depth"]), radius=dev(ps["radius"]), conic_o=dev(co),
                 rgb=dev(ps["rgb"]), clamped=torch.zeros(max(n, 1), dtype=torch.uint8, device="cuda")[:n])
 
 
 def oracle_projected(ps: dict) -> dict:
-    return dict(xy=ps["xy"].astype(np.float64), conic=ps["conic_o"][:, :3].astype(np.float64),
+    """The oracle's records: the conic of the same factor the GPU receives."""
+    return dict(xy=ps["xy"].astype(np.float64), conic=conic_from_factor(ps["conic_l"]),
                 rgb=ps["rgb"].astype(np.float64), depth=ps["depth"].astype(np.float64),
                 valid=(ps["radius"] > 0).astype(np.int32))
 

@@ -103,9 +103,9 @@ def test_deterministic_is_reproducible_and_close_to_atomics():
         for ia, ib in zip(d1[0], other[0]):
             assert np.array_equal(ia, ib)  # the forward is the same computation
         for k in G3:
-            ok, l2, ratio = grad_compare(other[2][k], d1[2][k], rel_l2=1e-5, rel_el=1e-4, abs_frac=1e-5)
+            ok, l2, ratio = grad_compare(other[2][k], d1[2][k], rel_l2=1e-4, rel_el=1e-4, abs_frac=1e-5)
             print(f"  {k:8s} relL2={l2:.2e} worst={ratio:.3f}")
-            assert l2 <= 1e-5, (k, l2)
+            assert l2 <= 1e-4, (k, l2)  # FP32 summation order only
 
 
 @pytest.mark.parametrize("kname", ["half_cos", "gauss"])

@@ -19,8 +19,8 @@ import torch
 import oracle
 from paper_2501_12369_amd import native, pipeline, scenes
 
-from gpu_util import (ORACLE_KERNELS, dev, gpu_bin_raster, grad_compare, image_pixels, last_ids, oracle_kernel_fp32,
-                      oracle_opts_fp32, oracle_projected, projected_to_device, to_np)
+from gpu_util import (ORACLE_KERNELS, conic_from_factor, dev, gpu_bin_raster, grad_compare, image_pixels, last_ids,
+                      oracle_kernel_fp32, oracle_opts_fp32, oracle_projected, projected_to_device, to_np)
 
 pytestmark = pytest.mark.gpu
 
@@ -37,7 +37,7 @@ def _exempt_splats(ps, orc, ko, W, H):
         return ex
     pix = oracle.full_pixels(W, H)[amb].astype(np.float64)
     xy = ps["xy"].astype(np.float64)
-    q = ps["conic_o"][:, :3].astype(np.float64)
+    q = conic_from_factor(ps["conic_l"])
     for p in pix:
         dx, dy = xy[:, 0] - p[0], xy[:, 1] - p[1]
         E = q[:, 0] * dx * dx + 2 * q[:, 1] * dx * dy + q[:, 2] * dy * dy
@@ -213,6 +213,7 @@ def test_preprocess_parity(kname, which):
     assert both.sum() > 0.3 * vis_o.sum() and both.sum() > 10
     xy = to_np(proj["xy"])[both]
     co = to_np(proj["conic_o"])[both]
+    co = np.concatenate([conic_from_factor(co[:, :3]), co[:, 3:4].astype(np.float64)], 1)  # the factor's conic
     rgb = to_np(proj["rgb"])[both]
     dep = to_np(proj["depth"])[both]
     # mu' relative to the pixel scale of the image; depth, rgb relative
