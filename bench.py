@@ -161,6 +161,8 @@ def serving_bench(kernel_name: str, seconds: float, rate_hz: float, mem_budget_g
     _, seq = serving.sequential_baseline(srv, reqs)
     log(f"one-at-a-time: p50 {seq.p50_ms:.2f} ms p99 {seq.p99_ms:.2f} ms, {seq.mpix_per_s:.1f} Mpix/s, "
         f"retries {seq.retries}")
+    _, bseq = serving.sequential_baseline(srv, burst)
+    log(f"one-at-a-time saturation: {bseq.mpix_per_s:.1f} Mpix/s, {bseq.req_per_s:.1f} req/s")
     return dict(workload=f"4 resident scenes {sizes} splats, Poisson {rate_hz} req/s "
                          f"for {seconds}s, resolutions {[f'{w}x{h}' for w, h in scenes.SERVING_RESOLUTIONS]}, "
                          f"forward only, {kernel_name}",
@@ -172,7 +174,9 @@ def serving_bench(kernel_name: str, seconds: float, rate_hz: float, mem_budget_g
                                 fwd_gbs=round(bhbm, 1), hbm_frac=round(bhbm / PEAK_HBM_GBS, 4),
                                 p99_ms=round(bst.p99_ms, 3)),
                 one_at_a_time=dict(p50_ms=round(seq.p50_ms, 3), p99_ms=round(seq.p99_ms, 3),
-                                   mpix_per_s=round(seq.mpix_per_s, 2)))
+                                   mpix_per_s=round(seq.mpix_per_s, 2),
+                                   saturation_mpix_per_s=round(bseq.mpix_per_s, 2),
+                                   saturation_req_per_s=round(bseq.req_per_s, 2)))
 
 
 def variants_bench(spd, cam, steps: int, warmup: int):

@@ -196,43 +196,67 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const uint32_t *ke
     hist[threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];  // digit-major
 }
 
+// The tile is first ordered by digit in LDS (stable: ranks by round, wave and
+// lane), then written out in that order, so each digit's run of the tile is
+// stored by consecutive lanes (about 16 keys per digit per tile) instead of
+// one 4-byte store per key and digit (partial-line writes).
 __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t *kin, const uint32_t *vin,
                                                                  uint32_t *kout, uint32_t *vout,
                                                                  const uint32_t *count_dev, int shift,
                                                                  const uint32_t *hist_scan, int nblk,
                                                                  const int32_t *skip) {
-    __shared__ uint32_t run[256];
+    __shared__ uint32_t run[256];   // global first slot of each digit for this tile
+    __shared__ uint32_t loff[256];  // first LDS slot of each digit
+    __shared__ uint32_t lrun[256];  // keys of each digit placed so far
     __shared__ uint32_t wc[kRadixThreads / 64][256];
+    __shared__ uint32_t lw[kRadixThreads / 64];
+    __shared__ uint32_t sk[kRadixTile], sv[kRadixTile];
     if (*skip) return;
     const uint32_t n = *count_dev;
-    uint32_t base = blockIdx.x * kRadixTile;
+    const uint32_t base = blockIdx.x * kRadixTile;
     if (base >= n) return;
-    const int t = threadIdx.x, w = t >> 6;
+    const uint32_t cnt = min((uint32_t)kRadixTile, n - base);
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     run[t] = hist_scan[t * nblk + blockIdx.x];
+    lrun[t] = 0;
     for (int k = 0; k < kRadixThreads / 64; k++) wc[k][t] = 0;
+    __syncthreads();
+    // this tile's count of each digit -> exclusive scan over the 256 digits
+    for (uint32_t i = t; i < cnt; i += kRadixThreads) atomicAdd(&lrun[(kin[base + i] >> shift) & 255u], 1u);
+    __syncthreads();
+    {
+        const uint32_t c = lrun[t];
+        const uint32_t inc = wave_incl_scan(c);
+        if (lane == 63) lw[w] = inc;
+        __syncthreads();
+        uint32_t woff = 0;
+        for (int k = 0; k < w; k++) woff += lw[k];
+        loff[t] = woff + inc - c;
+        lrun[t] = 0;
+    }
     __syncthreads();
     const uint64_t lt = lanemask_lt();
     for (int r = 0; r < kRadixItems; r++) {
-        uint32_t i = base + r * kRadixThreads + t;
-        bool valid = i < n;
-        uint32_t key = valid ? kin[i] : 0u;
-        uint32_t val = valid ? vin[i] : 0u;
-        uint32_t d = (key >> shift) & 255u;
+        const uint32_t li = r * kRadixThreads + t;
+        const bool valid = li < cnt;
+        const uint32_t key = valid ? kin[base + li] : 0u;
+        const uint32_t val = valid ? vin[base + li] : 0u;
+        const uint32_t d = (key >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; b++) {
-            bool bit = (d >> b) & 1u;
-            uint64_t m = __ballot(bit);
+            const bool bit = (d >> b) & 1u;
+            const uint64_t m = __ballot(bit);
             peers &= bit ? m : ~m;
         }
-        uint32_t rank = __popcll(peers & lt);
+        const uint32_t rank = __popcll(peers & lt);
         if (valid && rank == 0) wc[w][d] = (uint32_t)__popcll(peers);
         __syncthreads();
         if (valid) {
-            uint32_t off = run[d] + rank;
+            uint32_t off = loff[d] + lrun[d] + rank;
             for (int k = 0; k < w; k++) off += wc[k][d];
-            kout[off] = key;
-            vout[off] = val;
+            sk[off] = key;
+            sv[off] = val;
         }
         __syncthreads();
         uint32_t add = 0;
@@ -240,8 +264,16 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t 
             add += wc[k][t];
             wc[k][t] = 0;
         }
-        run[t] += add;
+        lrun[t] += add;
         __syncthreads();
+    }
+    // the tile in digit order: slot i of digit d goes to run[d] + (i - loff[d])
+    for (uint32_t i = t; i < cnt; i += kRadixThreads) {
+        const uint32_t key = sk[i];
+        const uint32_t d = (key >> shift) & 255u;
+        const uint32_t g = run[d] + (i - loff[d]);
+        kout[g] = key;
+        vout[g] = sv[i];
     }
 }
 
