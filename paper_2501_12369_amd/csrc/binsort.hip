@@ -37,6 +37,8 @@ constexpr int kScanBlock = kScanThreads * kScanItems;  // 2048 elements per bloc
 constexpr int kRadixThreads = 256;
 constexpr int kRadixItems = 16;
 constexpr int kRadixTile = kRadixThreads * kRadixItems;  // 4096 keys per block
+constexpr int kRadixWaves = kRadixThreads / 64;
+constexpr int kRadixWaveItems = kRadixTile / kRadixWaves;  // keys per wave (16 rounds of 64)
 constexpr int kSuper = 8;                                 // super-tile = 8x8 tiles
 constexpr int kL1Threads = 256;                           // splats per level-1 chunk
 constexpr int kL2Threads = 1024;                          // list entries per level-2 chunk
@@ -187,29 +189,33 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const uint32_t *ke
     const uint32_t n = *count_dev;
     h[threadIdx.x] = 0;
     __syncthreads();
-    uint32_t base = blockIdx.x * kRadixTile;
+    const uint32_t base = blockIdx.x * kRadixTile;
     for (int k = 0; k < kRadixItems; k++) {
-        uint32_t i = base + k * kRadixThreads + threadIdx.x;
+        const uint32_t i = base + k * kRadixThreads + threadIdx.x;
         if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
     }
     __syncthreads();
     hist[threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];  // digit-major
 }
 
-// The tile is first ordered by digit in LDS (stable: ranks by round, wave and
-// lane), then written out in that order, so each digit's run of the tile is
-// stored by consecutive lanes (about 16 keys per digit per tile) instead of
-// one 4-byte store per key and digit (partial-line writes).
+// One tile of kRadixTile keys per workgroup; wave w owns the contiguous quarter
+// [w * kRadixWaveItems, (w + 1) * kRadixWaveItems) of the tile, held in
+// registers (all loads issued at once).  Each wave ranks its keys by digit on
+// its own (8 ballots per round of 64 keys give the lanes with the same digit;
+// per-wave digit counters in LDS carry the rank across rounds -- one wave's
+// LDS operations complete in order, so no barrier is needed between rounds).
+// One scan over (digit, wave) then places the tile in LDS in digit order,
+// stable (digit, wave, round, lane), and each digit's run is written to its
+// global position by consecutive lanes.  Three workgroup barriers in all.
 __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t *kin, const uint32_t *vin,
                                                                  uint32_t *kout, uint32_t *vout,
                                                                  const uint32_t *count_dev, int shift,
                                                                  const uint32_t *hist_scan, int nblk,
                                                                  const int32_t *skip) {
-    __shared__ uint32_t run[256];   // global first slot of each digit for this tile
-    __shared__ uint32_t loff[256];  // first LDS slot of each digit
-    __shared__ uint32_t lrun[256];  // keys of each digit placed so far
-    __shared__ uint32_t wc[kRadixThreads / 64][256];
-    __shared__ uint32_t lw[kRadixThreads / 64];
+    __shared__ uint32_t run[256];                  // global first slot of each digit for this tile
+    __shared__ uint32_t loff[256];                 // first LDS slot of each digit
+    __shared__ uint32_t wcnt[kRadixWaves][256];    // per-wave digit counts, then per-wave first slots
+    __shared__ uint32_t lw[kRadixWaves];
     __shared__ uint32_t sk[kRadixTile], sv[kRadixTile];
     if (*skip) return;
     const uint32_t n = *count_dev;
@@ -218,30 +224,24 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t 
     const uint32_t cnt = min((uint32_t)kRadixTile, n - base);
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     run[t] = hist_scan[t * nblk + blockIdx.x];
-    lrun[t] = 0;
-    for (int k = 0; k < kRadixThreads / 64; k++) wc[k][t] = 0;
-    __syncthreads();
-    // this tile's count of each digit -> exclusive scan over the 256 digits
-    for (uint32_t i = t; i < cnt; i += kRadixThreads) atomicAdd(&lrun[(kin[base + i] >> shift) & 255u], 1u);
-    __syncthreads();
-    {
-        const uint32_t c = lrun[t];
-        const uint32_t inc = wave_incl_scan(c);
-        if (lane == 63) lw[w] = inc;
-        __syncthreads();
-        uint32_t woff = 0;
-        for (int k = 0; k < w; k++) woff += lw[k];
-        loff[t] = woff + inc - c;
-        lrun[t] = 0;
+#pragma unroll
+    for (int k = 0; k < kRadixWaves; k++) wcnt[k][t] = 0;
+    uint32_t key[kRadixItems], val[kRadixItems];
+    const uint32_t w0 = (uint32_t)w * kRadixWaveItems;
+#pragma unroll
+    for (int r = 0; r < kRadixItems; r++) {
+        const uint32_t li = w0 + r * 64 + lane;
+        key[r] = li < cnt ? kin[base + li] : 0u;
+        val[r] = li < cnt ? vin[base + li] : 0u;
     }
     __syncthreads();
     const uint64_t lt = lanemask_lt();
+    uint32_t rank[kRadixItems];
+    uint32_t *mycnt = wcnt[w];
+#pragma unroll
     for (int r = 0; r < kRadixItems; r++) {
-        const uint32_t li = r * kRadixThreads + t;
-        const bool valid = li < cnt;
-        const uint32_t key = valid ? kin[base + li] : 0u;
-        const uint32_t val = valid ? vin[base + li] : 0u;
-        const uint32_t d = (key >> shift) & 255u;
+        const bool valid = w0 + r * 64 + lane < cnt;
+        const uint32_t d = (key[r] >> shift) & 255u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; b++) {
@@ -249,30 +249,48 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t 
             const uint64_t m = __ballot(bit);
             peers &= bit ? m : ~m;
         }
-        const uint32_t rank = __popcll(peers & lt);
-        if (valid && rank == 0) wc[w][d] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t off = loff[d] + lrun[d] + rank;
-            for (int k = 0; k < w; k++) off += wc[k][d];
-            sk[off] = key;
-            sv[off] = val;
-        }
-        __syncthreads();
-        uint32_t add = 0;
-        for (int k = 0; k < kRadixThreads / 64; k++) {
-            add += wc[k][t];
-            wc[k][t] = 0;
-        }
-        lrun[t] += add;
-        __syncthreads();
+        const uint32_t below = (uint32_t)__popcll(peers & lt);
+        const uint32_t before = valid ? mycnt[d] : 0u;
+        rank[r] = before + below;
+        if (valid && below == 0) mycnt[d] = before + (uint32_t)__popcll(peers);
     }
+    __syncthreads();
+    {
+        // digit t: exclusive scan of the tile's digit totals, then the per-wave firsts
+        uint32_t c[kRadixWaves], tot = 0;
+#pragma unroll
+        for (int k = 0; k < kRadixWaves; k++) {
+            c[k] = wcnt[k][t];
+            tot += c[k];
+        }
+        const uint32_t inc = wave_incl_scan(tot);
+        if (lane == 63) lw[w] = inc;
+        __syncthreads();
+        uint32_t off = inc - tot;
+        for (int k = 0; k < w; k++) off += lw[k];
+        loff[t] = off;
+#pragma unroll
+        for (int k = 0; k < kRadixWaves; k++) {
+            wcnt[k][t] = off;
+            off += c[k];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRadixItems; r++) {
+        if (w0 + r * 64 + lane < cnt) {
+            const uint32_t o = mycnt[(key[r] >> shift) & 255u] + rank[r];
+            sk[o] = key[r];
+            sv[o] = val[r];
+        }
+    }
+    __syncthreads();
     // the tile in digit order: slot i of digit d goes to run[d] + (i - loff[d])
     for (uint32_t i = t; i < cnt; i += kRadixThreads) {
-        const uint32_t key = sk[i];
-        const uint32_t d = (key >> shift) & 255u;
+        const uint32_t k = sk[i];
+        const uint32_t d = (k >> shift) & 255u;
         const uint32_t g = run[d] + (i - loff[d]);
-        kout[g] = key;
+        kout[g] = k;
         vout[g] = sv[i];
     }
 }
