@@ -15,10 +15,12 @@
 //             per super-tile a ballot over the lanes gives each covering splat
 //             its rank; a scan over (super-tile, chunk) turns counts into
 //             positions -> per super-tile lists of splats, still depth-ordered.
-//   level 2   1024 consecutive entries of one super-tile list per workgroup;
-//             for each of its 64 tiles a ballot ranks the covering entries and
-//             a scan over (tile, chunk) gives positions -> the final list, each
-//             (chunk, tile) run (about 500 entries here) written contiguously.
+//   level 2   256 consecutive entries of one super-tile list per workgroup
+//             (small workgroups: the 64-tile store loop of each wave is uneven,
+//             and several workgroups per CU keep it busy across barriers); for
+//             each of its 64 tiles a ballot ranks the covering entries and a scan
+//             over (tile, chunk) gives positions -> the final list, each
+//             (chunk, tile) run written contiguously.
 //
 // Ranks come from ballots in lane order, so every step is stable and the result
 // is unique.  The radius box is recomputed from (xy, radius) with the same FP32
@@ -41,9 +43,9 @@ constexpr int kRadixWaves = kRadixThreads / 64;
 constexpr int kRadixWaveItems = kRadixTile / kRadixWaves;  // keys per wave (16 rounds of 64)
 constexpr int kSuper = 8;                                 // super-tile = 8x8 tiles
 constexpr int kL1Threads = 256;                           // splats per level-1 chunk
-constexpr int kL2Threads = 1024;                          // list entries per level-2 chunk
+constexpr int kL2Threads = 256;                           // list entries per level-2 chunk
 constexpr int kL2Waves = kL2Threads / 64;
-constexpr int kL2Grid = 2048;                             // persistent level-2 workgroups
+constexpr int kL2Grid = 8192;                             // persistent level-2 workgroups
 
 struct Counters {
     uint32_t n_visible;  // N_v
@@ -694,6 +696,30 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_count(const uint32_t *list1r,
     }
 }
 
+// Stores id at byte offset 4 (s0 + rank of this lane among the lanes of m)
+// from base, for the lanes set in m.  exec is narrowed to m around the two
+// mbcnt, the address and the store and restored right after, so the store
+// costs four vector instructions (a compiler-generated lane test adds three
+// more and a second exec update).  The offset is 32-bit: callers keep
+// positions below 2^30.
+__device__ __forceinline__ void store_ranked(uint32_t *base, uint64_t m, uint32_t s0x4, uint32_t id) {
+    uint64_t saved;
+    uint32_t off;
+    asm volatile(
+        "s_and_saveexec_b64 %0, %2\n\t"
+        "v_mbcnt_lo_u32_b32 %1, %3, 0\n\t"
+        "v_mbcnt_hi_u32_b32 %1, %4, %1\n\t"
+        "v_lshl_add_u32 %1, %1, 2, %5\n\t"
+        "global_store_dword %1, %6, %7\n\t"
+        "s_mov_b64 exec, %0"
+        : "=&s"(saved), "=&v"(off)
+        : "s"(m), "s"((uint32_t)m), "s"((uint32_t)(m >> 32)), "s"(s0x4), "v"(id), "s"(base)
+        : "memory");
+}
+
+// FAST: values only, capacity below 2^30 (32-bit byte offsets); otherwise the
+// generic loop, which also writes the optional (tile, depth) keys.
+template <bool FAST>
 __global__ __launch_bounds__(kL2Threads) void k_l2_scatter(const uint32_t *list1, const uint32_t *list1r,
                                                            const uint32_t *l1_start, const uint32_t *l1_len,
                                                            const uint32_t *chunk2_start, const uint32_t *toff,
@@ -747,7 +773,11 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_scatter(const uint32_t *list1
                 if (m == 0ull) continue;
                 const int tl = rr * kSuper + cc;
                 const uint32_t s0 = (uint32_t)__builtin_amdgcn_readlane((int)myslot, tl);
-                if ((m >> lane) & 1ull) {
+                if constexpr (FAST) {
+                    // the run lies inside the capacity (K <= capacity is decided before
+                    // any instance is written; this test only guards the store)
+                    if (s0 + (uint32_t)__popcll(m) <= cap32) store_ranked(vals, m, s0 << 2, id);
+                } else if ((m >> lane) & 1ull) {
                     const uint32_t pos = s0 + rank_below(m);
                     if (pos < cap32) {
                         vals[pos] = id;
@@ -920,8 +950,12 @@ hipError_t launch_bin_sort(const darb_projected &p, int n, int width, int height
                            gy, sxn, nsuper, cnt, h2, overflow_dev);
         if ((e = scan_exclusive(h2, &cnt->h2_count, L.h2_n, parts, &cnt->scan_total, overflow_dev, s)) != hipSuccess)
             return e;
-        hipLaunchKernelGGL(k_l2_scatter, dim3(kL2Grid), dim3(kL2Threads), 0, s, list1, list1r, l1start, l1len, c2start,
-                           toff, h2, p.depth, gx, gy, sxn, nsuper, cnt, k_capacity, keys, vals, overflow_dev);
+        if (!keys && k_capacity < (int64_t)1 << 30)
+            hipLaunchKernelGGL(k_l2_scatter<true>, dim3(kL2Grid), dim3(kL2Threads), 0, s, list1, list1r, l1start, l1len,
+                               c2start, toff, h2, p.depth, gx, gy, sxn, nsuper, cnt, k_capacity, keys, vals, overflow_dev);
+        else
+            hipLaunchKernelGGL(k_l2_scatter<false>, dim3(kL2Grid), dim3(kL2Threads), 0, s, list1, list1r, l1start, l1len,
+                               c2start, toff, h2, p.depth, gx, gy, sxn, nsuper, cnt, k_capacity, keys, vals, overflow_dev);
     }
     hipLaunchKernelGGL(k_bin_ranges, dim3((ntile + 255) / 256), dim3(256), 0, s, h2, toff, ntile, cnt, ranges,
                        overflow_dev);
