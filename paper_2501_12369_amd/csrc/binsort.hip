@@ -33,6 +33,8 @@ namespace darb {
 
 namespace {
 
+constexpr int kKeyItems = 16;                              // splats per thread in keys / compact
+constexpr int kKeyTile = 256 * kKeyItems;                  // splats per keys / compact block
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanBlock = kScanThreads * kScanItems;  // 2048 elements per block
@@ -209,11 +211,18 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const uint32_t *ke
 // One scan over (digit, wave) then places the tile in LDS in digit order,
 // stable (digit, wave, round, lane), and each digit's run is written to its
 // global position by consecutive lanes.  Three workgroup barriers in all.
+//
+// REC (the last pass of the depth sort): instead of (key, value) the output is
+// the compact record the value indexes -- splat index and packed tile box --
+// gathered while the tile is written out (this replaces a separate gather
+// pass over the sorted values).
+template <bool REC>
 __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t *kin, const uint32_t *vin,
                                                                  uint32_t *kout, uint32_t *vout,
                                                                  const uint32_t *count_dev, int shift,
                                                                  const uint32_t *hist_scan, int nblk,
-                                                                 const int32_t *skip) {
+                                                                 const int32_t *skip, const uint4 *crec,
+                                                                 uint32_t *sid, uint2 *sbox) {
     __shared__ uint32_t run[256];                  // global first slot of each digit for this tile
     __shared__ uint32_t loff[256];                 // first LDS slot of each digit
     __shared__ uint32_t wcnt[kRadixWaves][256];    // per-wave digit counts, then per-wave first slots
@@ -288,12 +297,31 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t 
     }
     __syncthreads();
     // the tile in digit order: slot i of digit d goes to run[d] + (i - loff[d])
-    for (uint32_t i = t; i < cnt; i += kRadixThreads) {
-        const uint32_t k = sk[i];
-        const uint32_t d = (k >> shift) & 255u;
-        const uint32_t g = run[d] + (i - loff[d]);
-        kout[g] = k;
-        vout[g] = sv[i];
+    if constexpr (REC) {
+        uint4 rec[kRadixItems];
+#pragma unroll
+        for (int r = 0; r < kRadixItems; r++) {
+            const uint32_t i = r * kRadixThreads + t;
+            if (i < cnt) rec[r] = crec[sv[i]];
+        }
+#pragma unroll
+        for (int r = 0; r < kRadixItems; r++) {
+            const uint32_t i = r * kRadixThreads + t;
+            if (i < cnt) {
+                const uint32_t d = (sk[i] >> shift) & 255u;
+                const uint32_t g = run[d] + (i - loff[d]);
+                sid[g] = rec[r].z;
+                sbox[g] = make_uint2(rec[r].x, rec[r].y);
+            }
+        }
+    } else {
+        for (uint32_t i = t; i < cnt; i += kRadixThreads) {
+            const uint32_t k = sk[i];
+            const uint32_t d = (k >> shift) & 255u;
+            const uint32_t g = run[d] + (i - loff[d]);
+            kout[g] = k;
+            vout[g] = sv[i];
+        }
     }
 }
 
@@ -310,27 +338,37 @@ __global__ void k_bin_init(Counters *cnt, int64_t *k_dev, int32_t *overflow_dev)
     }
 }
 
-__device__ __forceinline__ bool splat_box(const float *xy, const int32_t *radius, int i, int gx, int gy, int4 &r) {
-    int R = radius[i];
-    if (R <= 0) return false;
-    float2 p = reinterpret_cast<const float2 *>(xy)[i];
-    r = tile_rect(p.x, p.y, R, gx, gy);
-    return (r.y > r.x) & (r.w > r.z);
-}
-
-// per 256-splat block: number of visible splats and the sum of their box areas
+// Per block of kKeyTile splats (kKeyItems per thread, all loads issued
+// together): number of visible splats and the sum of their box areas.
 __global__ __launch_bounds__(256) void k_bin_keys(const float *xy, const int32_t *radius, int n, int gx, int gy,
                                                   uint32_t *block_vis, uint32_t *block_area) {
     __shared__ uint32_t wv[4], wa[4];
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int4 r;
-    bool vis = (i < n) && splat_box(xy, radius, i, gx, gy, r);
-    uint32_t area = vis ? (uint32_t)((r.y - r.x) * (r.w - r.z)) : 0u;
+    const int base = blockIdx.x * kKeyTile + threadIdx.x;
+    int R[kKeyItems];
+    float2 p[kKeyItems];
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) area += (uint32_t)__shfl_xor((int)area, off, 64);
-    uint64_t m = __ballot(vis);
+    for (int k = 0; k < kKeyItems; k++) {
+        const int i = base + k * 256;
+        R[k] = i < n ? radius[i] : 0;
+        p[k] = i < n ? reinterpret_cast<const float2 *>(xy)[i] : make_float2(0.0f, 0.0f);
+    }
+    uint32_t vis = 0, area = 0;
+#pragma unroll
+    for (int k = 0; k < kKeyItems; k++) {
+        if (R[k] <= 0) continue;
+        const int4 r = tile_rect(p[k].x, p[k].y, R[k], gx, gy);
+        if ((r.y > r.x) & (r.w > r.z)) {
+            vis++;
+            area += (uint32_t)((r.y - r.x) * (r.w - r.z));
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        area += (uint32_t)__shfl_xor((int)area, off, 64);
+        vis += (uint32_t)__shfl_xor((int)vis, off, 64);
+    }
     if ((threadIdx.x & 63) == 0) {
-        wv[threadIdx.x >> 6] = (uint32_t)__popcll(m);
+        wv[threadIdx.x >> 6] = vis;
         wa[threadIdx.x >> 6] = area;
     }
     __syncthreads();
@@ -390,38 +428,59 @@ __global__ __launch_bounds__(1024) void k_bin_sizes(uint32_t *block_vis, const u
 
 // Visible splats in index order: depth key, value = compact index, and the
 // compact record (tile box packed in 16-bit halves, splat index) that level 1
-// reads after the sort instead of gathering the projected splat again.
+// reads after the sort instead of gathering the projected splat again.  Same
+// blocking as k_bin_keys; a splat's slot is the block's offset plus the
+// visible splats before it in (round, wave, lane) = index order.
 __global__ __launch_bounds__(256) void k_bin_compact(const float *xy, const int32_t *radius, const float *depth, int n,
                                                      int gx, int gy, const uint32_t *block_off, uint32_t *keys,
                                                      uint32_t *vals, uint4 *crec, const int32_t *overflow_dev) {
-    __shared__ uint32_t wv[4];
+    __shared__ uint32_t wv[kKeyItems * 4];  // visible count of each (round, wave), then its first slot
     if (*overflow_dev) return;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int4 r;
-    bool vis = (i < n) && splat_box(xy, radius, i, gx, gy, r);
-    uint64_t m = __ballot(vis);
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) wv[w] = (uint32_t)__popcll(m);
-    __syncthreads();
-    if (vis) {
-        uint32_t pos = block_off[blockIdx.x] + (uint32_t)__popcll(m & lanemask_lt());
-        for (int k = 0; k < w; k++) pos += wv[k];
-        keys[pos] = __float_as_uint(depth[i]);
-        vals[pos] = pos;
-        crec[pos] = make_uint4((uint32_t)r.x | ((uint32_t)r.y << 16), (uint32_t)r.z | ((uint32_t)r.w << 16),
-                               (uint32_t)i, 0u);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int base = blockIdx.x * kKeyTile + threadIdx.x;
+    int R[kKeyItems];
+    float2 p[kKeyItems];
+#pragma unroll
+    for (int k = 0; k < kKeyItems; k++) {
+        const int i = base + k * 256;
+        R[k] = i < n ? radius[i] : 0;
+        p[k] = i < n ? reinterpret_cast<const float2 *>(xy)[i] : make_float2(0.0f, 0.0f);
     }
-}
-
-// Depth-ordered splat indices and tile boxes (one gather of the compact record).
-__global__ __launch_bounds__(256) void k_l1_prep(const uint32_t *sorted_c, const uint4 *crec, const Counters *cnt,
-                                                 uint32_t *sid, uint2 *sbox, const int32_t *overflow_dev) {
-    if (*overflow_dev) return;
-    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= cnt->n_visible) return;
-    const uint4 rec = crec[sorted_c[j]];
-    sid[j] = rec.z;
-    sbox[j] = make_uint2(rec.x, rec.y);
+    uint32_t visbits = 0;
+    int4 rect[kKeyItems];
+#pragma unroll
+    for (int k = 0; k < kKeyItems; k++) {
+        rect[k] = make_int4(0, 0, 0, 0);
+        bool vis = false;
+        if (R[k] > 0) {
+            rect[k] = tile_rect(p[k].x, p[k].y, R[k], gx, gy);
+            vis = (rect[k].y > rect[k].x) & (rect[k].w > rect[k].z);
+        }
+        const uint64_t m = __ballot(vis);
+        if (lane == 0) wv[k * 4 + w] = (uint32_t)__popcll(m);
+        if (vis) visbits |= 1u << k;
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {  // exclusive scan over the kKeyItems * 4 (round, wave) counts, in order
+        const uint32_t c = threadIdx.x < kKeyItems * 4 ? wv[threadIdx.x] : 0u;
+        const uint32_t inc = wave_incl_scan(c);
+        if (threadIdx.x < kKeyItems * 4) wv[threadIdx.x] = block_off[blockIdx.x] + inc - c;
+    }
+    __syncthreads();
+    const uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int k = 0; k < kKeyItems; k++) {
+        const bool vis = (visbits >> k) & 1u;
+        const uint64_t m = __ballot(vis);
+        if (vis) {
+            const int i = base + k * 256;
+            const uint32_t pos = wv[k * 4 + w] + (uint32_t)__popcll(m & lt);
+            keys[pos] = __float_as_uint(depth[i]);
+            vals[pos] = pos;
+            crec[pos] = make_uint4((uint32_t)rect[k].x | ((uint32_t)rect[k].y << 16),
+                                   (uint32_t)rect[k].z | ((uint32_t)rect[k].w << 16), (uint32_t)i, 0u);
+        }
+    }
 }
 
 __device__ __forceinline__ int4 unpack_box(uint2 b) {
@@ -819,7 +878,7 @@ WsLayout layout(int n, int gx, int gy, int64_t k_capacity) {
     WsLayout L;
     const int ntile = gx * gy, nsuper = super_count(gx, gy);
     size_t off = 0;
-    const size_t nkb = ((size_t)n + 255) / 256;
+    const size_t nkb = ((size_t)n + kKeyTile - 1) / kKeyTile;
     const size_t nblk = ((size_t)n + kRadixTile - 1) / kRadixTile;
     const size_t c1max = ((size_t)n + kL1Threads - 1) / kL1Threads;
     const size_t cap = (size_t)std::max<int64_t>(k_capacity, 1);
@@ -876,8 +935,8 @@ hipError_t radix_sort_pairs(uint32_t *kA, uint32_t *vA, uint32_t *kB, uint32_t *
     for (int shift = 0; shift < bits; shift += 8) {
         hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kRadixThreads), 0, s, ki, count_dev, shift, hist, nblk, skip);
         if ((e = scan_exclusive(hist, nullptr, hist_n, parts, nullptr, skip, s)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kRadixThreads), 0, s, ki, vi, ko, vo, count_dev, shift,
-                           hist, nblk, skip);
+        hipLaunchKernelGGL(k_radix_scatter<false>, dim3(nblk), dim3(kRadixThreads), 0, s, ki, vi, ko, vo, count_dev,
+                           shift, hist, nblk, skip, nullptr, nullptr, nullptr);
         std::swap(ki, ko);
         std::swap(vi, vo);
     }
@@ -910,7 +969,7 @@ hipError_t launch_bin_sort(const darb_projected &p, int n, int width, int height
     hipError_t e;
 
     hipLaunchKernelGGL(k_bin_init, dim3(1), dim3(64), 0, s, cnt, k_dev, overflow_dev);
-    const int nkb = (n + 255) / 256;
+    const int nkb = (n + kKeyTile - 1) / kKeyTile;
     if (n > 0) hipLaunchKernelGGL(k_bin_keys, dim3(nkb), dim3(256), 0, s, p.xy, p.radius, n, gx, gy, blockvis, blockarea);
     hipLaunchKernelGGL(k_bin_sizes, dim3(1), dim3(1024), 0, s, blockvis, blockarea, nkb, nsuper, cnt, k_capacity, k_dev,
                        overflow_dev);
@@ -923,17 +982,21 @@ hipError_t launch_bin_sort(const darb_projected &p, int n, int width, int height
         // depth sort of the N_v visible keys: 4 passes of 8 bits
         const int nblk = (n + kRadixTile - 1) / kRadixTile;
         uint32_t *ki = kA, *vi = vA, *ko = kB, *vo = vB;
+        // (the last pass writes the splat index and tile box of each compact
+        // index, in (depth, index) order, instead of the sorted pairs)
         for (int shift = 0; shift < 32; shift += 8) {
             hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kRadixThreads), 0, s, ki, nvis, shift, hist, nblk,
                                overflow_dev);
             if ((e = scan_exclusive(hist, nullptr, L.hist_n, parts, nullptr, overflow_dev, s)) != hipSuccess) return e;
-            hipLaunchKernelGGL(k_radix_scatter, dim3(nblk), dim3(kRadixThreads), 0, s, ki, vi, ko, vo, nvis, shift,
-                               hist, nblk, overflow_dev);
+            if (shift < 24)
+                hipLaunchKernelGGL(k_radix_scatter<false>, dim3(nblk), dim3(kRadixThreads), 0, s, ki, vi, ko, vo, nvis,
+                                   shift, hist, nblk, overflow_dev, nullptr, nullptr, nullptr);
+            else
+                hipLaunchKernelGGL(k_radix_scatter<true>, dim3(nblk), dim3(kRadixThreads), 0, s, ki, vi, ko, vo, nvis,
+                                   shift, hist, nblk, overflow_dev, crec, sid, sbox);
             std::swap(ki, ko);
             std::swap(vi, vo);
         }
-        const uint32_t *sorted = vi;  // compact indices in (depth, index) order
-        hipLaunchKernelGGL(k_l1_prep, dim3(nkb), dim3(256), 0, s, sorted, crec, cnt, sid, sbox, overflow_dev);
         const int c1max = (n + kL1Threads - 1) / kL1Threads;
         const size_t lds1 = (size_t)nsuper * 4;
         hipLaunchKernelGGL(k_l1_count, dim3(c1max), dim3(kL1Threads), lds1, s, sbox, sxn, nsuper, cnt, h1,
