@@ -291,21 +291,26 @@ __device__ __forceinline__ void tile_bwd(const RView &V, int tile, uint32_t item
                 float da = G0[k] * fmaf(sr, Tb, -S0[k] * inv);
                 da = fmaf(G1[k], fmaf(sg, Tb, -S1[k] * inv), da);
                 da = fmaf(G2[k], fmaf(sbl, Tb, -S2[k] * inv), da);
-                float aT = q.alpha * Tb;
-                float dE = so * profile_deriv<KIND>(q.E, q.w, kp) * da;
-                float dE2 = 2.0f * dE;
-                gr += ok ? aT * G0[k] : 0.0f;
-                gg += ok ? aT * G1[k] : 0.0f;
-                gbl += ok ? aT * G2[k] : 0.0f;
-                gop += ok ? q.w * da : 0.0f;
-                gxy0 += ok ? dE2 * q.q0 : 0.0f;
-                gxy1 += ok ? dE2 * q.q1 : 0.0f;
-                gca += ok ? dE * (q.dx * q.dx) : 0.0f;
-                gcb += ok ? dE2 * (q.dx * q.dy) : 0.0f;
-                gcc += ok ? dE * (q.dy * q.dy) : 0.0f;
-                S0[k] = ok ? fmaf(aT, sr, S0[k]) : S0[k];
-                S1[k] = ok ? fmaf(aT, sg, S1[k]) : S1[k];
-                S2[k] = ok ? fmaf(aT, sbl, S2[k]) : S2[k];
+                // the pair's factors, zero where it does not blend (selected, never
+                // multiplied by a mask: outside the support F(E) may be inf)
+                const float aTm = ok ? q.alpha * Tb : 0.0f;
+                const float wm = ok ? q.w : 0.0f;
+                const float dEm = ok ? so * profile_deriv<KIND>(q.E, q.w, kp) * da : 0.0f;
+                gr = fmaf(aTm, G0[k], gr);
+                gg = fmaf(aTm, G1[k], gg);
+                gbl = fmaf(aTm, G2[k], gbl);
+                gop = fmaf(wm, da, gop);
+                // dE/dmu' = 2 Q d and the off-diagonal conic term carry a factor 2,
+                // applied once to the reduced sums (exact)
+                gxy0 = fmaf(dEm, q.q0, gxy0);
+                gxy1 = fmaf(dEm, q.q1, gxy1);
+                const float ex = dEm * q.dx, ey = dEm * q.dy;
+                gca = fmaf(ex, q.dx, gca);
+                gcb = fmaf(ex, q.dy, gcb);
+                gcc = fmaf(ey, q.dy, gcc);
+                S0[k] = fmaf(aTm, sr, S0[k]);  // unchanged where aTm = 0
+                S1[k] = fmaf(aTm, sg, S1[k]);
+                S2[k] = fmaf(aTm, sbl, S2[k]);
                 T[k] = ok ? Tb : T[k];
             }
             if (__ballot(any) != 0) {
@@ -318,6 +323,10 @@ __device__ __forceinline__ void tile_bwd(const RView &V, int tile, uint32_t item
                 touched |= 1ull << s;
             }
         }
+        // the factor 2 of the mean and off-diagonal conic terms
+        m[0] *= 2.0f;
+        m[1] *= 2.0f;
+        m[3] *= 2.0f;
         if constexpr (DET) {
             if ((uint32_t)lane < cntb) {
                 const uint32_t c = c0 + (j - start);
