@@ -1,12 +1,18 @@
 // raster.hip -- per-tile DARBF compositing, forward and backward.
 //
-// One wavefront per 16x16 tile; lane l owns the four pixels of column l % 16
-// in rows l/16, l/16 + 4, l/16 + 8, l/16 + 12.  The tile's instance list is
-// consumed in batches of 64: lane l gathers the projected record of the
-// batch's l-th instance, then the wave walks the batch with the record of
+// One workgroup per 16x16 tile, split into S wavefronts of 16 x (16/S) pixels
+// each; lane l of wave h owns column l % 16 in rows h*16/S + l/16 + 4k,
+// k < 4/S.  The forward uses S = 2: a tile's walk is short (its pixels
+// saturate after a few hundred instances) and serial, so two independent
+// half-tile walks shorten the longest path through the kernel and fill more
+// wave slots.  The backward keeps S = 1: its per-instance wave reductions and
+// atomics would double with S = 2, which costs more than the shorter walks
+// gain.  The instance
+// list is consumed in batches of 64: lane l gathers the projected record of
+// the batch's l-th instance, then the wave walks the batch with the record of
 // instance s broadcast to scalar registers (v_readlane), so every pixel test
 // reads its splat operands from SGPRs.  A ballot over the lanes' "done" bits
-// ends the tile early once every pixel has saturated.
+// ends the walk early once every pixel of the wave has saturated.
 //
 // Forward (DARB-Splatting section, alpha blending; per-kernel forward
 // listings): E = d^T Q d with d = mu' - p, alpha = min(alpha_max, o F(E)),
@@ -35,7 +41,23 @@ namespace darb {
 
 namespace {
 
-constexpr int kPix = 4;  // pixels per lane
+constexpr int kPix = 4;    // pixels per lane with one wavefront per tile
+constexpr int kSplit = 2;  // wavefronts per tile in the forward kernel
+
+// Pixels of this lane: column ix, rows iy0 + 4k for k < kPix / S.
+template <int S>
+struct LanePix {
+    static constexpr int NP = kPix / S;
+    int ix, iy0;
+    float ylo;  // first row of this wave's pixel block
+    __device__ __forceinline__ LanePix(int tile, int gx) {
+        const int tx = tile % gx, ty = tile / gx;
+        const int lane = threadIdx.x & 63, h = threadIdx.x >> 6;
+        ix = tx * kTile + (lane & 15);
+        ylo = (float)(ty * kTile + h * (kTile / S));
+        iy0 = ty * kTile + h * (kTile / S) + (lane >> 4);
+    }
+};
 
 struct Rec {
     float x, y, a, b, c, o, r, g, bl;  // a, b, c: the conic factor (l00, l01, l11)
@@ -45,13 +67,13 @@ struct Rec {
 
 // Record of instance j (zeros when `in` is false or the stored index is out of
 // range; a zero-opacity record never passes the alpha test).  `hit` is false
-// when the ellipse E <= e_max, grown by one pixel, misses the tile's pixel
-// range: for |dx| > sqrt(e_max Sigma'_xx) every E exceeds e_max by a relative
+// when the ellipse E <= e_max, grown by one pixel, misses the wave's pixel
+// block (columns xlo .. xlo + 15, rows ylo .. ylo + yext): for |dx| > sqrt(e_max Sigma'_xx) every E exceeds e_max by a relative
 // margin far above FP32 rounding, so skipping such a splat changes nothing.
 // With Q = L^T L: Sigma' = Q^-1 has Sigma'_xx = (1 + (l01/l11)^2) / l00^2 and
 // Sigma'_yy = 1 / l11^2.
 __device__ __forceinline__ Rec load_rec(const darb_projected &p, const uint32_t *vals, uint32_t j, bool in, int n,
-                                        float e_max, float xlo, float ylo) {
+                                        float e_max, float xlo, float ylo, float yext) {
     Rec R;
     R.x = R.y = R.a = R.b = R.c = R.o = R.r = R.g = R.bl = 0.0f;
     R.id = kNone;
@@ -76,7 +98,7 @@ __device__ __forceinline__ Rec load_rec(const darb_projected &p, const uint32_t 
         float hy = sqrtf(e_max) / co.z + 1.0f;
         bool ok = (co.x > 0.0f && co.z > 0.0f)
                       ? ((xy.x + hx >= xlo) & (xy.x - hx <= xlo + (kTile - 1)) & (xy.y + hy >= ylo) &
-                         (xy.y - hy <= ylo + (kTile - 1)))
+                         (xy.y - hy <= ylo + yext))
                       : true;
         R.hit = ok ? 1 : 0;
     }
@@ -110,24 +132,26 @@ struct ManyViews {
     }
 };
 
-// Forward state of a lane's four pixels.
+// Forward state of a lane's pixels.
+template <int NP>
 struct PixF {
-    float T[kPix], C0[kPix], C1[kPix], C2[kPix];
-    uint32_t lst[kPix], cnt[kPix];
+    float T[NP], C0[NP], C1[NP], C2[NP];
+    uint32_t lst[NP], cnt[NP];
 };
 
-template <int KIND>
-__device__ __forceinline__ void tile_fwd(const RView &V, int tile, int n, const KParams &kp, const ROpts &o, PixF &Fout) {
-    PixF F;  // local state, copied out at the end (keeps the loop at 64 VGPRs)
-    const int tx = tile % V.gx, ty = tile / V.gx;
-    const int lane = threadIdx.x;
-    const int ix = tx * kTile + (lane & 15);
-    const int iy0 = ty * kTile + (lane >> 4);
+template <int KIND, int S>
+__device__ __forceinline__ void tile_fwd(const RView &V, int tile, int n, const KParams &kp, const ROpts &o,
+                                         PixF<kPix / S> &Fout) {
+    constexpr int NP = kPix / S;
+    PixF<NP> F;  // local state, copied out at the end (keeps the loop at 64 VGPRs)
+    const LanePix<S> P(tile, V.gx);
+    const int lane = threadIdx.x & 63;
+    const int ix = P.ix, iy0 = P.iy0;
     const float px = (float)ix;
-    float py[kPix];
-    bool done[kPix];
+    float py[NP];
+    bool done[NP];
 #pragma unroll
-    for (int k = 0; k < kPix; k++) {
+    for (int k = 0; k < NP; k++) {
         int iy = iy0 + 4 * k;
         py[k] = (float)iy;
         done[k] = !(ix < V.W && iy < V.H);
@@ -138,10 +162,13 @@ __device__ __forceinline__ void tile_fwd(const RView &V, int tile, int n, const 
     }
     const uint32_t start = V.ranges[2 * tile], end = V.ranges[2 * tile + 1];
     for (uint32_t base = start; base < end; base += 64) {
-        bool alldone = done[0] & done[1] & done[2] & done[3];
+        bool alldone = true;
+#pragma unroll
+        for (int k = 0; k < NP; k++) alldone &= done[k];
         if (__ballot(!alldone) == 0) break;
         uint32_t j = base + lane;
-        Rec R = load_rec(V.p, V.vals, j, j < end, n, kp.e_max, (float)(tx * kTile), (float)(ty * kTile));
+        Rec R = load_rec(V.p, V.vals, j, j < end, n, kp.e_max, (float)(ix - (lane & 15)), P.ylo,
+                         (float)(kTile / S - 1));
         int nb = (int)min(64u, end - base);
         for (int s = 0; s < nb; s++) {
             if (!readlane_i(R.hit, s)) continue;  // footprint misses this tile (uniform)
@@ -151,7 +178,7 @@ __device__ __forceinline__ void tile_fwd(const RView &V, int tile, int n, const 
             float sr = readlane_f(R.r, s), sg = readlane_f(R.g, s), sbl = readlane_f(R.bl, s);
             uint32_t pos = base + s;
 #pragma unroll
-            for (int k = 0; k < kPix; k++) {
+            for (int k = 0; k < NP; k++) {
                 Pair q = eval_pair<KIND>(sx, sy, sa, sb, sc, so, px, py[k], kp, o.alpha_min, o.alpha_max);
                 bool ok = q.ok & !done[k];
                 float Tn = F.T[k] * (1.0f - q.alpha);
@@ -171,14 +198,13 @@ __device__ __forceinline__ void tile_fwd(const RView &V, int tile, int n, const 
     Fout = F;
 }
 
-__device__ __forceinline__ void store_fwd(const RView &V, int tile, const PixF &F, const ROpts &o) {
-    const int tx = tile % V.gx, ty = tile / V.gx;
-    const int lane = threadIdx.x;
-    const int ix = tx * kTile + (lane & 15);
-    const int iy0 = ty * kTile + (lane >> 4);
+template <int S>
+__device__ __forceinline__ void store_fwd(const RView &V, int tile, const PixF<kPix / S> &F, const ROpts &o) {
+    const LanePix<S> P(tile, V.gx);
+    const int ix = P.ix, iy0 = P.iy0;
     const size_t plane = (size_t)V.W * V.H;
 #pragma unroll
-    for (int k = 0; k < kPix; k++) {
+    for (int k = 0; k < kPix / S; k++) {
         int iy = iy0 + 4 * k;
         if (ix < V.W && iy < V.H) {
             size_t pidx = (size_t)iy * V.W + ix;
@@ -238,20 +264,21 @@ __device__ __forceinline__ void writelane9(float (&m)[9], const float (&u)[9], i
 
 // Backward walk of one tile.  T: final transmittance per pixel (running, so
 // modified); lp: last blended position + 1 (0 = none); G: dL/dI per pixel.
-template <int KIND, bool DET>
+template <int KIND, bool DET, int S>
 __device__ __forceinline__ void tile_bwd(const RView &V, int tile, uint32_t item, int n, const KParams &kp,
-                                         const ROpts &o, float (&T)[kPix], const uint32_t (&lp)[kPix],
-                                         const float (&G0)[kPix], const float (&G1)[kPix], const float (&G2)[kPix],
-                                         const DetOut &d) {
-    const int tx = tile % V.gx, ty = tile / V.gx;
-    const int lane = threadIdx.x;
-    const int ix = tx * kTile + (lane & 15);
-    const int iy0 = ty * kTile + (lane >> 4);
+                                         const ROpts &o, float (&T)[kPix / S], const uint32_t (&lp)[kPix / S],
+                                         const float (&G0)[kPix / S], const float (&G1)[kPix / S],
+                                         const float (&G2)[kPix / S], const DetOut &d) {
+    static_assert(!DET || S == 1, "the deterministic backward keeps one wavefront per tile");
+    constexpr int NP = kPix / S;
+    const LanePix<S> P(tile, V.gx);
+    const int lane = threadIdx.x & 63;
+    const int ix = P.ix, iy0 = P.iy0;
     const float px = (float)ix;
-    float py[kPix], S0[kPix], S1[kPix], S2[kPix];
+    float py[NP], S0[NP], S1[NP], S2[NP];
     uint32_t maxl = 0;
 #pragma unroll
-    for (int k = 0; k < kPix; k++) {
+    for (int k = 0; k < NP; k++) {
         py[k] = (float)(iy0 + 4 * k);
         S0[k] = T[k] * o.bg0;
         S1[k] = T[k] * o.bg1;
@@ -268,7 +295,8 @@ __device__ __forceinline__ void tile_bwd(const RView &V, int tile, uint32_t item
     for (uint32_t hi = maxl; hi > start;) {
         uint32_t cntb = min(64u, hi - start);
         uint32_t j = hi - 1 - lane;
-        Rec R = load_rec(V.p, V.vals, j, (uint32_t)lane < cntb, n, kp.e_max, (float)(tx * kTile), (float)(ty * kTile));
+        Rec R = load_rec(V.p, V.vals, j, (uint32_t)lane < cntb, n, kp.e_max, (float)(ix - (lane & 15)), P.ylo,
+                         (float)(kTile / S - 1));
         // lane s keeps the reduced partials of the batch's s-th instance
         float m[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         uint64_t touched = 0;  // lanes whose instance received a contribution (uniform)
@@ -282,7 +310,7 @@ __device__ __forceinline__ void tile_bwd(const RView &V, int tile, uint32_t item
             float gxy0 = 0.f, gxy1 = 0.f, gca = 0.f, gcb = 0.f, gcc = 0.f, gop = 0.f, gr = 0.f, gg = 0.f, gbl = 0.f;
             bool any = false;
 #pragma unroll
-            for (int k = 0; k < kPix; k++) {
+            for (int k = 0; k < NP; k++) {
                 Pair q = eval_pair<KIND>(sx, sy, sa, sb, sc, so, px, py[k], kp, o.alpha_min, o.alpha_max);
                 bool ok = q.ok & (pos1 <= lp[k]);
                 any |= ok;
@@ -355,15 +383,15 @@ __device__ __forceinline__ void tile_bwd(const RView &V, int tile, uint32_t item
 }
 
 // Checkpoint of a lane's four pixels: final T, last + 1, dL/dI.
-__device__ __forceinline__ void load_checkpoint(const RView &V, int tile, float (&T)[kPix], uint32_t (&lp)[kPix],
-                                                float (&G0)[kPix], float (&G1)[kPix], float (&G2)[kPix]) {
-    const int tx = tile % V.gx, ty = tile / V.gx;
-    const int lane = threadIdx.x;
-    const int ix = tx * kTile + (lane & 15);
-    const int iy0 = ty * kTile + (lane >> 4);
+template <int S>
+__device__ __forceinline__ void load_checkpoint(const RView &V, int tile, float (&T)[kPix / S],
+                                                uint32_t (&lp)[kPix / S], float (&G0)[kPix / S],
+                                                float (&G1)[kPix / S], float (&G2)[kPix / S]) {
+    const LanePix<S> P(tile, V.gx);
+    const int ix = P.ix, iy0 = P.iy0;
     const size_t plane = (size_t)V.W * V.H;
 #pragma unroll
-    for (int k = 0; k < kPix; k++) {
+    for (int k = 0; k < kPix / S; k++) {
         int iy = iy0 + 4 * k;
         lp[k] = 0;
         T[k] = 0.0f;
@@ -383,44 +411,44 @@ __device__ __forceinline__ void load_checkpoint(const RView &V, int tile, float 
 }
 
 template <int KIND, class VS>
-__global__ __launch_bounds__(64) void k_raster_fwd(VS A, int n, KParams kp, ROpts o) {
+__global__ __launch_bounds__(64 * kSplit) void k_raster_fwd(VS A, int n, KParams kp, ROpts o) {
     int tile;
     const RView &V = A.get(blockIdx.x, tile);
     if (V.overflow && *V.overflow) return;
-    PixF F;
-    tile_fwd<KIND>(V, tile, n, kp, o, F);
-    store_fwd(V, tile, F, o);
+    PixF<kPix / kSplit> F;
+    tile_fwd<KIND, kSplit>(V, tile, n, kp, o, F);
+    store_fwd<kSplit>(V, tile, F, o);
 }
 
 template <int KIND, bool DET, class VS>
 __global__ __launch_bounds__(64) void k_raster_bwd(VS A, int n, KParams kp, ROpts o, DetOut d) {
+    constexpr int S = 1;
     int tile;
     const RView &V = A.get(blockIdx.x, tile);
     if (V.overflow && *V.overflow) return;
-    float T[kPix], G0[kPix], G1[kPix], G2[kPix];
-    uint32_t lp[kPix];
-    load_checkpoint(V, tile, T, lp, G0, G1, G2);
-    tile_bwd<KIND, DET>(V, tile, blockIdx.x, n, kp, o, T, lp, G0, G1, G2, d);
+    float T[kPix / S], G0[kPix / S], G1[kPix / S], G2[kPix / S];
+    uint32_t lp[kPix / S];
+    load_checkpoint<S>(V, tile, T, lp, G0, G1, G2);
+    tile_bwd<KIND, DET, S>(V, tile, blockIdx.x, n, kp, o, T, lp, G0, G1, G2, d);
 }
 
-// Forward, per-pixel loss gradient and backward of one tile in one workgroup.
+// Forward, per-pixel loss gradient and backward of one tile in one wavefront.
 template <int KIND, int LOSS, class VS>
 __global__ __launch_bounds__(64) void k_raster_fwdbwd(VS A, int n, KParams kp, ROpts o) {
+    constexpr int S = 1, NP = kPix;
     int tile;
     const RView &V = A.get(blockIdx.x, tile);
     if (V.overflow && *V.overflow) return;
-    PixF F;
-    tile_fwd<KIND>(V, tile, n, kp, o, F);
-    store_fwd(V, tile, F, o);
-    const int tx = tile % V.gx, ty = tile / V.gx;
-    const int lane = threadIdx.x;
-    const int ix = tx * kTile + (lane & 15);
-    const int iy0 = ty * kTile + (lane >> 4);
+    PixF<NP> F;
+    tile_fwd<KIND, S>(V, tile, n, kp, o, F);
+    store_fwd<S>(V, tile, F, o);
+    const LanePix<S> P(tile, V.gx);
+    const int ix = P.ix, iy0 = P.iy0;
     const size_t plane = (size_t)V.W * V.H;
-    float G0[kPix], G1[kPix], G2[kPix];
-    uint32_t lp[kPix];
+    float G0[NP], G1[NP], G2[NP];
+    uint32_t lp[NP];
 #pragma unroll
-    for (int k = 0; k < kPix; k++) {
+    for (int k = 0; k < NP; k++) {
         int iy = iy0 + 4 * k;
         G0[k] = G1[k] = G2[k] = 0.0f;
         lp[k] = F.lst[k] == kNone ? 0u : F.lst[k] + 1u;
@@ -432,7 +460,7 @@ __global__ __launch_bounds__(64) void k_raster_fwdbwd(VS A, int n, KParams kp, R
             G2[k] = loss_grad<LOSS>(fmaf(F.T[k], o.bg2, F.C2[k]), V.target[2 * plane + pidx], V.loss_scale);
         }
     }
-    tile_bwd<KIND, false>(V, tile, blockIdx.x, n, kp, o, F.T, lp, G0, G1, G2, DetOut{});
+    tile_bwd<KIND, false, S>(V, tile, blockIdx.x, n, kp, o, F.T, lp, G0, G1, G2, DetOut{});
 }
 
 // Deterministic mode, pass 0: number of partials of each work item (the same
@@ -445,7 +473,7 @@ __global__ __launch_bounds__(64) void k_trav_len(VS A, uint32_t *len) {
     if (!(V.overflow && *V.overflow)) {
         float T[kPix], G0[kPix], G1[kPix], G2[kPix];
         uint32_t lp[kPix];
-        load_checkpoint(V, tile, T, lp, G0, G1, G2);
+        load_checkpoint<1>(V, tile, T, lp, G0, G1, G2);
         uint32_t maxl = max(max(lp[0], lp[1]), max(lp[2], lp[3]));
         maxl = wave_max_u32(maxl);
         const uint32_t start = V.ranges[2 * tile], end = V.ranges[2 * tile + 1];
@@ -566,9 +594,11 @@ namespace {
 template <int KIND>
 void fwd_launch(const RViews &V, uint32_t items, int n, const KParams &kp, const ROpts &o, hipStream_t s) {
     if (V.nv == 1)
-        hipLaunchKernelGGL((k_raster_fwd<KIND, OneView>), dim3(items), dim3(64), 0, s, OneView{V.v[0]}, n, kp, o);
+        hipLaunchKernelGGL((k_raster_fwd<KIND, OneView>), dim3(items), dim3(64 * kSplit), 0, s, OneView{V.v[0]}, n, kp,
+                           o);
     else
-        hipLaunchKernelGGL((k_raster_fwd<KIND, ManyViews>), dim3(items), dim3(64), 0, s, ManyViews{V}, n, kp, o);
+        hipLaunchKernelGGL((k_raster_fwd<KIND, ManyViews>), dim3(items), dim3(64 * kSplit), 0, s, ManyViews{V}, n, kp,
+                           o);
 }
 
 template <int KIND>
