@@ -202,6 +202,35 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const uint32_t *ke
     hist[threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];  // digit-major
 }
 
+// Per digit (one workgroup per row of the digit-major histogram): exclusive
+// prefix over the blocks, in place, and the digit's total after the 256 rows.
+// The scatter adds the digit's start (a scan over the 256 totals) itself, so
+// the histogram needs no scan over all 256 x nblk entries.
+__global__ __launch_bounds__(kScanThreads) void k_radix_rowscan(uint32_t *hist, int nblk, const int32_t *skip) {
+    __shared__ uint32_t lw[kScanThreads / 64];
+    if (*skip) return;
+    uint32_t *row = hist + (size_t)blockIdx.x * nblk;
+    uint32_t carry = 0;
+    for (int base = 0; base < nblk; base += kScanBlock) {
+        const int b0 = base + threadIdx.x * kScanItems;
+        uint32_t v[kScanItems], sum = 0;
+#pragma unroll
+        for (int k = 0; k < kScanItems; k++) {
+            v[k] = b0 + k < nblk ? row[b0 + k] : 0u;
+            sum += v[k];
+        }
+        uint32_t tot;
+        uint32_t off = carry + block_excl_scan(sum, lw, &tot);
+#pragma unroll
+        for (int k = 0; k < kScanItems; k++) {
+            if (b0 + k < nblk) row[b0 + k] = off;
+            off += v[k];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0) hist[(size_t)256 * nblk + blockIdx.x] = carry;
+}
+
 // One tile of kRadixTile keys per workgroup; wave w owns the contiguous quarter
 // [w * kRadixWaveItems, (w + 1) * kRadixWaveItems) of the tile, held in
 // registers (all loads issued at once).  Each wave ranks its keys by digit on
@@ -234,7 +263,13 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t 
     if (base >= n) return;
     const uint32_t cnt = min((uint32_t)kRadixTile, n - base);
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-    run[t] = hist_scan[t * nblk + blockIdx.x];
+    {
+        // global first slot of digit t for this tile: the digit's start (scan of the
+        // digit totals) plus this tile's prefix within the digit's row
+        uint32_t tot;
+        const uint32_t dstart = block_excl_scan(hist_scan[(size_t)256 * nblk + t], lw, &tot);
+        run[t] = dstart + hist_scan[t * nblk + blockIdx.x];
+    }
 #pragma unroll
     for (int k = 0; k < kRadixWaves; k++) wcnt[k][t] = 0;
     uint32_t key[kRadixItems], val[kRadixItems];
@@ -883,7 +918,7 @@ WsLayout layout(int n, int gx, int gy, int64_t k_capacity) {
     const size_t c1max = ((size_t)n + kL1Threads - 1) / kL1Threads;
     const size_t cap = (size_t)std::max<int64_t>(k_capacity, 1);
     const size_t total2max = cap / kL2Threads + nsuper + 1;
-    L.hist_n = (uint32_t)(256 * nblk);
+    L.hist_n = (uint32_t)(256 * nblk + 256);  // per-block digit counts + the digit totals
     L.h1_n = (uint32_t)(nsuper * c1max);
     L.h2_n = (uint32_t)std::min<size_t>((size_t)kSuper * kSuper * total2max, 0xFFFFFFFFull);
     size_t parts_n = (std::max<size_t>({L.hist_n, L.h1_n, L.h2_n}) + kScanBlock - 1) / kScanBlock + 1;
@@ -916,7 +951,7 @@ WsLayout layout(int n, int gx, int gy, int64_t k_capacity) {
 size_t scan_parts_words(uint32_t max_count) { return (size_t)(max_count + kScanBlock - 1) / kScanBlock + 1; }
 
 size_t radix_hist_words(uint32_t max_count) {
-    return 256 * ((size_t)(max_count + kRadixTile - 1) / kRadixTile);
+    return 256 * ((size_t)(max_count + kRadixTile - 1) / kRadixTile) + 256;  // + the digit totals
 }
 
 hipError_t scan_u32(uint32_t *data, const uint32_t *count_dev, uint32_t max_count, uint32_t *parts,
@@ -925,16 +960,13 @@ hipError_t scan_u32(uint32_t *data, const uint32_t *count_dev, uint32_t max_coun
 }
 
 hipError_t radix_sort_pairs(uint32_t *kA, uint32_t *vA, uint32_t *kB, uint32_t *vB, const uint32_t *count_dev,
-                            uint32_t max_count, int bits, uint32_t *hist, uint32_t *parts, const int32_t *skip,
-                            hipStream_t s) {
+                            uint32_t max_count, int bits, uint32_t *hist, const int32_t *skip, hipStream_t s) {
     if (max_count == 0) return hipSuccess;
     const int nblk = (int)((max_count + kRadixTile - 1) / kRadixTile);
-    const uint32_t hist_n = (uint32_t)(256 * (size_t)nblk);
     uint32_t *ki = kA, *vi = vA, *ko = kB, *vo = vB;
-    hipError_t e;
     for (int shift = 0; shift < bits; shift += 8) {
         hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kRadixThreads), 0, s, ki, count_dev, shift, hist, nblk, skip);
-        if ((e = scan_exclusive(hist, nullptr, hist_n, parts, nullptr, skip, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(kScanThreads), 0, s, hist, nblk, skip);
         hipLaunchKernelGGL(k_radix_scatter<false>, dim3(nblk), dim3(kRadixThreads), 0, s, ki, vi, ko, vo, count_dev,
                            shift, hist, nblk, skip, nullptr, nullptr, nullptr);
         std::swap(ki, ko);
@@ -987,7 +1019,7 @@ hipError_t launch_bin_sort(const darb_projected &p, int n, int width, int height
         for (int shift = 0; shift < 32; shift += 8) {
             hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kRadixThreads), 0, s, ki, nvis, shift, hist, nblk,
                                overflow_dev);
-            if ((e = scan_exclusive(hist, nullptr, L.hist_n, parts, nullptr, overflow_dev, s)) != hipSuccess) return e;
+            hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(kScanThreads), 0, s, hist, nblk, overflow_dev);
             if (shift < 24)
                 hipLaunchKernelGGL(k_radix_scatter<false>, dim3(nblk), dim3(kRadixThreads), 0, s, ki, vi, ko, vo, nvis,
                                    shift, hist, nblk, overflow_dev, nullptr, nullptr, nullptr);

@@ -323,9 +323,9 @@ size_t radix_hist_words(uint32_t max_count);
 hipError_t scan_u32(uint32_t *data, const uint32_t *count_dev, uint32_t max_count, uint32_t *parts,
                     uint32_t *total_out, const int32_t *skip, hipStream_t s);
 // Sorted pairs end in (kA, vA) when the pass count ceil(bits/8) is even, else in (kB, vB).
+// hist holds radix_hist_words(max_count) words.
 hipError_t radix_sort_pairs(uint32_t *kA, uint32_t *vA, uint32_t *kB, uint32_t *vB, const uint32_t *count_dev,
-                            uint32_t max_count, int bits, uint32_t *hist, uint32_t *parts, const int32_t *skip,
-                            hipStream_t s);
+                            uint32_t max_count, int bits, uint32_t *hist, const int32_t *skip, hipStream_t s);
 
 // Raster launchers take one view (nv == 1) or several; `items` = tiles summed
 // over the views.  Deterministic backward: `det_ws` of det_workspace() bytes.

@@ -547,7 +547,7 @@ DetLayout det_layout(uint32_t items, uint64_t cap) {
     size_t off = 0;
     const uint32_t cap32 = (uint32_t)cap;
     const size_t hist_n = radix_hist_words(cap32);
-    const size_t sp = std::max(scan_parts_words(items), scan_parts_words((uint32_t)std::min<size_t>(hist_n, 0xFFFFFFFFu)));
+    const size_t sp = scan_parts_words(items);
     L.hdr = off; off += align_up(sizeof(DetHdr));
     L.trav = off; off += align_up(((size_t)items + 1) * 4);
     L.sparts = off; off += align_up(sp * 4);
@@ -679,8 +679,7 @@ hipError_t launch_raster_bwd(int kind, const RViews &V, uint32_t items, int n, c
     DARB_KIND_SWITCH(kind, bwd_launch, (V, items, n, kp, o, true, d, s))
     const uint64_t limit = (uint64_t)V.nv * (uint64_t)n;
     const int bits = bits_for(limit);  // 2^bits > limit: kNone keys sort after every valid key
-    if ((e = radix_sort_pairs(kA, vA, kB, vB, &hdr->total, cap, bits, U(L.hist), sparts, &hdr->zero, s)) !=
-        hipSuccess)
+    if ((e = radix_sort_pairs(kA, vA, kB, vB, &hdr->total, cap, bits, U(L.hist), &hdr->zero, s)) != hipSuccess)
         return e;
     const bool in_b = ((bits + 7) / 8) % 2 == 1;
     const uint32_t *sk = in_b ? kB : kA, *sv = in_b ? vB : vA;
