@@ -202,14 +202,18 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const uint32_t *ke
     hist[threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];  // digit-major
 }
 
-// Per digit (one workgroup per row of the digit-major histogram): exclusive
-// prefix over the blocks, in place, and the digit's total after the 256 rows.
-// The scatter adds the digit's start (a scan over the 256 totals) itself, so
-// the histogram needs no scan over all 256 x nblk entries.
-__global__ __launch_bounds__(kScanThreads) void k_radix_rowscan(uint32_t *hist, int nblk, const int32_t *skip) {
+// Row-wise exclusive scan, in place, one workgroup per row: rows of `len`
+// counts stored back to back (len from the device when len_dev is set), the
+// row's total to totals[row].  Used where a count array is row-major over a
+// small number of rows (radix digits, super-tiles) and its consumer adds the
+// row's start (a scan over the few totals) itself, instead of one scan over
+// all entries.
+__global__ __launch_bounds__(kScanThreads) void k_rowscan(uint32_t *data, const uint32_t *len_dev, uint32_t len_host,
+                                                          uint32_t *totals, const int32_t *skip) {
     __shared__ uint32_t lw[kScanThreads / 64];
     if (*skip) return;
-    uint32_t *row = hist + (size_t)blockIdx.x * nblk;
+    const int nblk = (int)(len_dev ? *len_dev : len_host);
+    uint32_t *row = data + (size_t)blockIdx.x * nblk;
     uint32_t carry = 0;
     for (int base = 0; base < nblk; base += kScanBlock) {
         const int b0 = base + threadIdx.x * kScanItems;
@@ -228,7 +232,7 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_rowscan(uint32_t *hist, 
         }
         carry += tot;
     }
-    if (threadIdx.x == 0) hist[(size_t)256 * nblk + blockIdx.x] = carry;
+    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
 // One tile of kRadixTile keys per workgroup; wave w owns the contiguous quarter
@@ -565,19 +569,40 @@ __global__ __launch_bounds__(kL1Threads) void k_l1_count(const uint2 *sbox, int 
     for (int g = threadIdx.x; g < nsuper; g += kL1Threads) h1[(size_t)g * c1 + c] = cg[g];  // super-tile-major
 }
 
+// base1: per super-tile row, the exclusive prefix of its chunk counts; gtot:
+// the rows' totals (the list lengths), whose exclusive scan gives each list's
+// start.
 __global__ __launch_bounds__(kL1Threads) void k_l1_scatter(const uint32_t *sid, const uint2 *sbox, int sxn, int nsuper,
                                                            const Counters *cnt, const uint32_t *base1,
-                                                           uint32_t *list1, uint32_t *list1r, int64_t list1_cap,
-                                                           const int32_t *overflow_dev) {
+                                                           const uint32_t *gtot, uint32_t *list1, uint32_t *list1r,
+                                                           int64_t list1_cap, const int32_t *overflow_dev) {
+    static_assert(kL1Threads == kScanThreads && 4 * kL1Threads >= kMaxSuperTiles, "four super-tiles per thread");
     // per super-tile: a 256-bit set of the chunk's covering threads, and the chunk's first slot
     extern __shared__ uint32_t lds1[];
+    __shared__ uint32_t lw[kScanThreads / 64];
     uint32_t *bits = lds1;                   // [8][nsuper]: word-major (lanes of a wave hit distinct banks)
     uint32_t *first = lds1 + nsuper * 8;     // [nsuper]
     if (*overflow_dev) return;
     const uint32_t c = blockIdx.x, c1 = cnt->c1, nv = cnt->n_visible;
     if (c >= c1) return;
     for (int k = threadIdx.x; k < nsuper * 8; k += kL1Threads) bits[k] = 0;
-    for (int g = threadIdx.x; g < nsuper; g += kL1Threads) first[g] = base1[(size_t)g * c1 + c];
+    {
+        // first slot of this chunk in super-tile g: list start + the chunk's prefix in the row
+        const int g0 = 4 * threadIdx.x;
+        uint32_t v[4], sum = 0;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            v[k] = g0 + k < nsuper ? gtot[g0 + k] : 0u;
+            sum += v[k];
+        }
+        uint32_t tot;
+        uint32_t off = block_excl_scan(sum, lw, &tot);
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            if (g0 + k < nsuper) first[g0 + k] = off + base1[(size_t)(g0 + k) * c1 + c];
+            off += v[k];
+        }
+    }
     __syncthreads();
     const int word = threadIdx.x >> 5;
     const uint32_t bit = 1u << (threadIdx.x & 31);
@@ -612,7 +637,7 @@ __global__ __launch_bounds__(kL1Threads) void k_l1_scatter(const uint32_t *sid, 
 // (tile, chunk) count array in row-major tile order.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(1024) void k_l2_plan(const uint32_t *base1, Counters *cnt, int nsuper, int sxn, int gx,
+__global__ __launch_bounds__(1024) void k_l2_plan(const uint32_t *gtot, Counters *cnt, int nsuper, int sxn, int gx,
                                                   int gy, uint32_t *l1_start, uint32_t *l1_len, uint32_t *chunk2_start,
                                                   uint32_t *toff, const int32_t *overflow_dev) {
     __shared__ uint32_t lw[16];
@@ -620,16 +645,28 @@ __global__ __launch_bounds__(1024) void k_l2_plan(const uint32_t *base1, Counter
     __shared__ uint32_t n2s[1024];
     if (*overflow_dev) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const uint32_t c1 = cnt->c1, total1 = cnt->total1;
-    // spans and chunk counts (nsuper <= 1024)
+    // spans (list lengths and their exclusive scan) and chunk counts (nsuper <= 1024)
     int g = threadIdx.x;
+    const uint32_t len = g < nsuper ? gtot[g] : 0u;
+    {
+        const uint32_t inc1 = wave_incl_scan(len);
+        if (lane == 63) lw[w] = inc1;
+        __syncthreads();
+        uint32_t woff = 0, tot = 0;
+        for (int k = 0; k < 16; k++) {
+            if (k < w) woff += lw[k];
+            tot += lw[k];
+        }
+        if (g < nsuper) {
+            l1_start[g] = woff + inc1 - len;
+            l1_len[g] = len;
+        }
+        if (g == 0) cnt->total1 = tot;
+        __syncthreads();
+    }
     uint32_t n2 = 0;
     if (g < nsuper) {
-        uint32_t s = c1 ? base1[(size_t)g * c1] : 0u;
-        uint32_t e = (g + 1 < nsuper) ? (c1 ? base1[(size_t)(g + 1) * c1] : 0u) : total1;
-        l1_start[g] = s;
-        l1_len[g] = e - s;
-        n2 = (e - s + kL2Threads - 1) / kL2Threads;
+        n2 = (len + kL2Threads - 1) / kL2Threads;
         n2s[g] = n2;
     }
     uint32_t inc = wave_incl_scan(n2);
@@ -901,7 +938,7 @@ inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct WsLayout {
     size_t counters, blockvis, blockarea, keysA, valsA, keysB, valsB, crec, sid, sbox, hist, h1, list1, list1r, l1start, l1len, c2start,
-        toff, h2, parts, total;
+        toff, h2, parts, gtot, total;
     uint32_t hist_n, h1_n, h2_n;
 };
 
@@ -942,6 +979,7 @@ WsLayout layout(int n, int gx, int gy, int64_t k_capacity) {
     L.toff = off; off += align_up((size_t)(ntile + 1) * 4);
     L.h2 = off; off += align_up((size_t)L.h2_n * 4);
     L.parts = off; off += align_up(parts_n * 4);
+    L.gtot = off; off += align_up((size_t)(nsuper + 1) * 4);
     L.total = off;
     return L;
 }
@@ -966,7 +1004,8 @@ hipError_t radix_sort_pairs(uint32_t *kA, uint32_t *vA, uint32_t *kB, uint32_t *
     uint32_t *ki = kA, *vi = vA, *ko = kB, *vo = vB;
     for (int shift = 0; shift < bits; shift += 8) {
         hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kRadixThreads), 0, s, ki, count_dev, shift, hist, nblk, skip);
-        hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(kScanThreads), 0, s, hist, nblk, skip);
+        hipLaunchKernelGGL(k_rowscan, dim3(256), dim3(kScanThreads), 0, s, hist, nullptr, (uint32_t)nblk,
+                           hist + (size_t)256 * nblk, skip);
         hipLaunchKernelGGL(k_radix_scatter<false>, dim3(nblk), dim3(kRadixThreads), 0, s, ki, vi, ko, vo, count_dev,
                            shift, hist, nblk, skip, nullptr, nullptr, nullptr);
         std::swap(ki, ko);
@@ -997,6 +1036,7 @@ hipError_t launch_bin_sort(const darb_projected &p, int n, int width, int height
     uint32_t *hist = U(L.hist), *parts = U(L.parts), *h1 = U(L.h1), *list1 = U(L.list1), *list1r = U(L.list1r), *h2 = U(L.h2);
     uint32_t *blockvis = U(L.blockvis), *blockarea = U(L.blockarea);
     uint32_t *l1start = U(L.l1start), *l1len = U(L.l1len), *c2start = U(L.c2start), *toff = U(L.toff);
+    uint32_t *gtot = U(L.gtot);
     const uint32_t *nvis = &cnt->n_visible;
     hipError_t e;
 
@@ -1005,10 +1045,10 @@ hipError_t launch_bin_sort(const darb_projected &p, int n, int width, int height
     if (n > 0) hipLaunchKernelGGL(k_bin_keys, dim3(nkb), dim3(256), 0, s, p.xy, p.radius, n, gx, gy, blockvis, blockarea);
     hipLaunchKernelGGL(k_bin_sizes, dim3(1), dim3(1024), 0, s, blockvis, blockarea, nkb, nsuper, cnt, k_capacity, k_dev,
                        overflow_dev);
+    uint32_t *sid = U(L.sid);
+    uint2 *sbox = reinterpret_cast<uint2 *>(base + L.sbox);
     if (n > 0) {
         uint4 *crec = reinterpret_cast<uint4 *>(base + L.crec);
-        uint32_t *sid = U(L.sid);
-        uint2 *sbox = reinterpret_cast<uint2 *>(base + L.sbox);
         hipLaunchKernelGGL(k_bin_compact, dim3(nkb), dim3(256), 0, s, p.xy, p.radius, p.depth, n, gx, gy, blockvis, kA,
                            vA, crec, overflow_dev);
         // depth sort of the N_v visible keys: 4 passes of 8 bits
@@ -1019,7 +1059,8 @@ hipError_t launch_bin_sort(const darb_projected &p, int n, int width, int height
         for (int shift = 0; shift < 32; shift += 8) {
             hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kRadixThreads), 0, s, ki, nvis, shift, hist, nblk,
                                overflow_dev);
-            hipLaunchKernelGGL(k_radix_rowscan, dim3(256), dim3(kScanThreads), 0, s, hist, nblk, overflow_dev);
+            hipLaunchKernelGGL(k_rowscan, dim3(256), dim3(kScanThreads), 0, s, hist, nullptr, (uint32_t)nblk,
+                               hist + (size_t)256 * nblk, overflow_dev);
             if (shift < 24)
                 hipLaunchKernelGGL(k_radix_scatter<false>, dim3(nblk), dim3(kRadixThreads), 0, s, ki, vi, ko, vo, nvis,
                                    shift, hist, nblk, overflow_dev, nullptr, nullptr, nullptr);
@@ -1033,12 +1074,16 @@ hipError_t launch_bin_sort(const darb_projected &p, int n, int width, int height
         const size_t lds1 = (size_t)nsuper * 4;
         hipLaunchKernelGGL(k_l1_count, dim3(c1max), dim3(kL1Threads), lds1, s, sbox, sxn, nsuper, cnt, h1,
                            overflow_dev);
-        if ((e = scan_exclusive(h1, &cnt->h1_count, L.h1_n, parts, &cnt->total1, overflow_dev, s)) != hipSuccess)
-            return e;
-        hipLaunchKernelGGL(k_l1_scatter, dim3(c1max), dim3(kL1Threads), 9 * lds1, s, sid, sbox, sxn, nsuper, cnt, h1,
-                           list1, list1r, std::max<int64_t>(k_capacity, 1), overflow_dev);
     }
-    hipLaunchKernelGGL(k_l2_plan, dim3(1), dim3(1024), 0, s, h1, cnt, nsuper, sxn, gx, gy, l1start, l1len, c2start,
+    // the level-1 lists' lengths (zeros when nothing is visible: rows of length c1 = 0)
+    hipLaunchKernelGGL(k_rowscan, dim3(nsuper), dim3(kScanThreads), 0, s, h1, &cnt->c1, 0u, gtot, overflow_dev);
+    if (n > 0) {
+        const int c1max = (n + kL1Threads - 1) / kL1Threads;
+        const size_t lds1 = (size_t)nsuper * 4;
+        hipLaunchKernelGGL(k_l1_scatter, dim3(c1max), dim3(kL1Threads), 9 * lds1, s, sid, sbox, sxn, nsuper, cnt, h1,
+                           gtot, list1, list1r, std::max<int64_t>(k_capacity, 1), overflow_dev);
+    }
+    hipLaunchKernelGGL(k_l2_plan, dim3(1), dim3(1024), 0, s, gtot, cnt, nsuper, sxn, gx, gy, l1start, l1len, c2start,
                        toff, overflow_dev);
     if (n > 0) {
         hipLaunchKernelGGL(k_l2_count, dim3(kL2Grid), dim3(kL2Threads), 0, s, list1r, l1start, l1len, c2start, toff, gx,

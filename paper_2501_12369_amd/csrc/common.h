@@ -336,7 +336,6 @@ hipError_t launch_raster_bwd(int kind, const RViews &V, uint32_t items, int n, c
                              void *det_ws, uint64_t det_capacity, hipStream_t s);
 hipError_t launch_raster_fwdbwd(int kind, int loss, const RViews &V, uint32_t items, int n, const KParams &kp,
                                 const ROpts &o, hipStream_t s);
-hipError_t launch_zero(float *a, size_t n, hipStream_t s);
 
 constexpr uint32_t kLossBlocks = 1024;  // partial sums of the image loss (fixed, so the total is reproducible)
 hipError_t launch_image_loss(int loss, const float *image, const float *target, int width, int height, float scale,

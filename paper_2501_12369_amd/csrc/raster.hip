@@ -530,10 +530,26 @@ __global__ __launch_bounds__(256) void k_det_reduce(VS A, uint32_t n, const uint
     }
 }
 
-__global__ __launch_bounds__(256) void k_zero(float *a, size_t n) {
-    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (; i < n; i += stride) a[i] = 0.0f;
+// The four 2D-gradient arrays of a view in one launch (n splats: 2n, 3n, n, 3n
+// floats); each block clears a contiguous stretch of one array.
+__global__ __launch_bounds__(256) void k_zero_grads2d(darb_grads2d g, size_t n) {
+    const size_t chunk = (size_t)256 * 16;
+    const size_t nb0 = (2 * n + chunk - 1) / chunk, nb1 = (3 * n + chunk - 1) / chunk, nb2 = (n + chunk - 1) / chunk;
+    size_t b = blockIdx.x;
+    float *a;
+    size_t len;
+    if (b < nb0) {
+        a = g.xy, len = 2 * n;
+    } else if ((b -= nb0) < nb1) {
+        a = g.conic, len = 3 * n;
+    } else if ((b -= nb1) < nb2) {
+        a = g.opacity, len = n;
+    } else {
+        b -= nb2;
+        a = g.rgb, len = 3 * n;
+    }
+    const size_t end = min(len, (b + 1) * chunk);
+    for (size_t i = b * chunk + threadIdx.x; i < end; i += 256) a[i] = 0.0f;
 }
 
 inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -570,13 +586,6 @@ int bits_for(uint64_t v) {
 }  // namespace
 
 size_t det_workspace(uint32_t items, uint64_t capacity) { return det_layout(items, capacity).total; }
-
-hipError_t launch_zero(float *a, size_t n, hipStream_t s) {
-    if (n == 0) return hipSuccess;
-    size_t blocks = std::min<size_t>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, a, n);
-    return hipGetLastError();
-}
 
 #define DARB_KIND_SWITCH(kind, F, ...)                     \
     switch (kind) {                                        \
@@ -633,15 +642,13 @@ void fwdbwd_launch(int loss, const RViews &V, uint32_t items, int n, const KPara
 }
 
 hipError_t zero_grads(const RViews &V, int n, hipStream_t s) {
-    hipError_t e;
-    for (int v = 0; v < V.nv; v++) {
-        const darb_grads2d &g = V.v[v].g2;
-        if ((e = launch_zero(g.xy, (size_t)n * 2, s)) != hipSuccess) return e;
-        if ((e = launch_zero(g.conic, (size_t)n * 3, s)) != hipSuccess) return e;
-        if ((e = launch_zero(g.opacity, (size_t)n, s)) != hipSuccess) return e;
-        if ((e = launch_zero(g.rgb, (size_t)n * 3, s)) != hipSuccess) return e;
-    }
-    return hipSuccess;
+    if (n <= 0) return hipSuccess;
+    const size_t chunk = (size_t)256 * 16, nn = (size_t)n;
+    const size_t blocks = (2 * nn + chunk - 1) / chunk + (3 * nn + chunk - 1) / chunk + (nn + chunk - 1) / chunk +
+                          (3 * nn + chunk - 1) / chunk;
+    for (int v = 0; v < V.nv; v++)
+        hipLaunchKernelGGL(k_zero_grads2d, dim3((unsigned)blocks), dim3(256), 0, s, V.v[v].g2, nn);
+    return hipGetLastError();
 }
 
 }  // namespace
