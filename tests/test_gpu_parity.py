@@ -47,6 +47,14 @@ def _exempt_splats(ps, orc, ko, W, H):
 
 # ---------------------------------------------------------------- bin / sort
 
+def _values_only_matches(ps, K_o, vals_o, ranges_o):
+    # without the optional keys the last level writes the list with its own store path
+    fr, K = gpu_bin_raster(ps, "half_cos", keys=False, cap=max(K_o, 1))
+    assert K == K_o
+    assert np.array_equal(to_np(fr.ranges).view(np.uint32), ranges_o)
+    assert np.array_equal(to_np(fr.vals)[:K].view(np.uint32), vals_o)
+
+
 @pytest.mark.parametrize("n,W,H,seed", [(0, 64, 48, 1), (1, 16, 16, 2), (500, 200, 150, 3), (3000, 37, 21, 4),
                                         (20000, 640, 360, 5), (5000, 1297, 840, 6)])
 def test_bin_sort_bit_exact(n, W, H, seed):
@@ -62,6 +70,7 @@ def test_bin_sort_bit_exact(n, W, H, seed):
     assert np.array_equal(to_np(fr.ranges).view(np.uint32), ranges_o)
     assert np.array_equal(to_np(fr.vals)[:K].view(np.uint32), vals_o)
     assert np.array_equal(to_np(fr.keys)[:K].view(np.uint64), keys_o)
+    _values_only_matches(ps, K_o, vals_o, ranges_o)
 
 
 @pytest.mark.parametrize("n,W,H,seed,sigma", [(300, 200, 150, 9, (50.0, 400.0)), (60000, 1920, 1080, 10, (0.3, 60.0))])
@@ -75,6 +84,7 @@ def test_bin_sort_bit_exact_large_boxes(n, W, H, seed, sigma):
     assert np.array_equal(to_np(fr.ranges).view(np.uint32), ranges_o)
     assert np.array_equal(to_np(fr.vals)[:K].view(np.uint32), vals_o)
     assert np.array_equal(to_np(fr.keys)[:K].view(np.uint64), keys_o)
+    _values_only_matches(ps, K_o, vals_o, ranges_o)
 
 
 def test_bin_sort_all_culled_and_overflow():
