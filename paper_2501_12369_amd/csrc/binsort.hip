@@ -368,15 +368,6 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t 
 // Keys, sizes, compaction.
 // ---------------------------------------------------------------------------
 
-__global__ void k_bin_init(Counters *cnt, int64_t *k_dev, int32_t *overflow_dev) {
-    if (threadIdx.x == 0) {
-        *cnt = Counters{};
-        k_dev[0] = 0;
-        k_dev[1] = 0;
-        *overflow_dev = 0;
-    }
-}
-
 // Per block of kKeyTile splats (kKeyItems per thread, all loads issued
 // together): number of visible splats and the sum of their box areas.
 __global__ __launch_bounds__(256) void k_bin_keys(const float *xy, const int32_t *radius, int n, int gx, int gy,
@@ -455,6 +446,7 @@ __global__ __launch_bounds__(1024) void k_bin_sizes(uint32_t *block_vis, const u
         unsigned long long K = 0;
         for (int k = 0; k < 16; k++) K += la[k];
         uint32_t nv = carry;
+        *cnt = Counters{};  // every counter of this call starts here (none is read before this kernel)
         cnt->n_visible = nv;
         cnt->c1 = (nv + kL1Threads - 1) / kL1Threads;
         cnt->h1_count = cnt->c1 * (uint32_t)nsuper;
@@ -827,6 +819,27 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_count(const uint32_t *list1r,
     }
 }
 
+// [start, end) of tile t in the final list: the first slot of its first
+// level-2 chunk (or K when the tile has none after it).
+__device__ __forceinline__ void tile_range(const uint32_t *base2, const uint32_t *toff, int t, const Counters *cnt,
+                                           uint32_t *ranges) {
+    const uint32_t h2 = cnt->h2_count;
+    const uint32_t K = (uint32_t)cnt->K;
+    uint32_t a = toff[t], b = toff[t + 1];
+    ranges[2 * t] = a < h2 ? base2[a] : K;
+    ranges[2 * t + 1] = b < h2 ? base2[b] : K;
+}
+
+// (only when there are no splats: otherwise the level-2 scatter writes the ranges)
+__global__ __launch_bounds__(256) void k_bin_ranges(const uint32_t *base2, const uint32_t *toff, int ntile,
+                                                    const Counters *cnt, uint32_t *ranges,
+                                                    const int32_t *overflow_dev) {
+    if (*overflow_dev) return;
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntile) return;
+    tile_range(base2, toff, t, cnt, ranges);
+}
+
 // Stores id at byte offset 4 (s0 + rank of this lane among the lanes of m)
 // from base, for the lanes set in m.  exec is narrowed to m around the two
 // mbcnt, the address and the store and restored right after, so the store
@@ -856,7 +869,7 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_scatter(const uint32_t *list1
                                                            const uint32_t *chunk2_start, const uint32_t *toff,
                                                            const uint32_t *base2, const float *depth, int gx, int gy,
                                                            int sxn, int nsuper, const Counters *cnt, int64_t k_capacity,
-                                                           uint64_t *keys, uint32_t *vals,
+                                                           uint64_t *keys, uint32_t *vals, uint32_t *ranges,
                                                            const int32_t *overflow_dev) {
     __shared__ uint32_t wc[kSuper * kSuper * kL2Waves];
     __shared__ uint32_t slot[kSuper * kSuper * kL2Waves];
@@ -865,6 +878,8 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_scatter(const uint32_t *list1
     if (*overflow_dev) return;
     const uint32_t total2 = cnt->total2;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int t = blockIdx.x * kL2Threads + threadIdx.x; t < gx * gy; t += gridDim.x * kL2Threads)
+        tile_range(base2, toff, t, cnt, ranges);
     for (int g = threadIdx.x; g <= nsuper; g += kL2Threads) c2s[g] = chunk2_start[g];
     __syncthreads();
     const uint32_t cap32 = (uint32_t)min(k_capacity, (int64_t)0xFFFFFFFFll);
@@ -897,17 +912,25 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_scatter(const uint32_t *list1
         __syncthreads();
         // lane tl holds this wave's first slot in tile tl; broadcast per tile with v_readlane
         const uint32_t myslot = slot[w * 64 + lane];
+        bool inside = true;
+        if constexpr (FAST) {
+            // every run of this wave lies inside the capacity (K <= capacity is decided
+            // before any instance is written; this test only guards the stores)
+            const uint32_t myc = wc[w * 64 + lane];
+            uint32_t e = myc ? myslot + myc : 0u;
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) e = max(e, (uint32_t)__shfl_xor((int)e, off, 64));
+            inside = e <= cap32;
+        }
         for (int rr = 0; rr < kSuper; rr++) {
-            if (rowB[rr] == 0ull) continue;  // no lane of this wave covers the row (uniform)
+            if (rowB[rr] == 0ull || !inside) continue;  // no lane of this wave covers the row (uniform)
             for (int cc = 0; cc < kSuper; cc++) {
                 const uint64_t m = colB[cc] & rowB[rr];
                 if (m == 0ull) continue;
                 const int tl = rr * kSuper + cc;
                 const uint32_t s0 = (uint32_t)__builtin_amdgcn_readlane((int)myslot, tl);
                 if constexpr (FAST) {
-                    // the run lies inside the capacity (K <= capacity is decided before
-                    // any instance is written; this test only guards the store)
-                    if (s0 + (uint32_t)__popcll(m) <= cap32) store_ranked(vals, m, s0 << 2, id);
+                    store_ranked(vals, m, s0 << 2, id);
                 } else if ((m >> lane) & 1ull) {
                     const uint32_t pos = s0 + rank_below(m);
                     if (pos < cap32) {
@@ -921,18 +944,7 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_scatter(const uint32_t *list1
     }
 }
 
-__global__ __launch_bounds__(256) void k_bin_ranges(const uint32_t *base2, const uint32_t *toff, int ntile,
-                                                    const Counters *cnt, uint32_t *ranges,
-                                                    const int32_t *overflow_dev) {
-    if (*overflow_dev) return;
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= ntile) return;
-    const uint32_t h2 = cnt->h2_count;
-    const uint32_t K = (uint32_t)cnt->K;
-    uint32_t a = toff[t], b = toff[t + 1];
-    ranges[2 * t] = a < h2 ? base2[a] : K;
-    ranges[2 * t + 1] = b < h2 ? base2[b] : K;
-}
+
 
 inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -1040,7 +1052,6 @@ hipError_t launch_bin_sort(const darb_projected &p, int n, int width, int height
     const uint32_t *nvis = &cnt->n_visible;
     hipError_t e;
 
-    hipLaunchKernelGGL(k_bin_init, dim3(1), dim3(64), 0, s, cnt, k_dev, overflow_dev);
     const int nkb = (n + kKeyTile - 1) / kKeyTile;
     if (n > 0) hipLaunchKernelGGL(k_bin_keys, dim3(nkb), dim3(256), 0, s, p.xy, p.radius, n, gx, gy, blockvis, blockarea);
     hipLaunchKernelGGL(k_bin_sizes, dim3(1), dim3(1024), 0, s, blockvis, blockarea, nkb, nsuper, cnt, k_capacity, k_dev,
@@ -1092,13 +1103,16 @@ hipError_t launch_bin_sort(const darb_projected &p, int n, int width, int height
             return e;
         if (!keys && k_capacity < (int64_t)1 << 30)
             hipLaunchKernelGGL(k_l2_scatter<true>, dim3(kL2Grid), dim3(kL2Threads), 0, s, list1, list1r, l1start, l1len,
-                               c2start, toff, h2, p.depth, gx, gy, sxn, nsuper, cnt, k_capacity, keys, vals, overflow_dev);
+                               c2start, toff, h2, p.depth, gx, gy, sxn, nsuper, cnt, k_capacity, keys, vals, ranges,
+                               overflow_dev);
         else
             hipLaunchKernelGGL(k_l2_scatter<false>, dim3(kL2Grid), dim3(kL2Threads), 0, s, list1, list1r, l1start, l1len,
-                               c2start, toff, h2, p.depth, gx, gy, sxn, nsuper, cnt, k_capacity, keys, vals, overflow_dev);
+                               c2start, toff, h2, p.depth, gx, gy, sxn, nsuper, cnt, k_capacity, keys, vals, ranges,
+                               overflow_dev);
+    } else {
+        hipLaunchKernelGGL(k_bin_ranges, dim3((ntile + 255) / 256), dim3(256), 0, s, h2, toff, ntile, cnt, ranges,
+                           overflow_dev);
     }
-    hipLaunchKernelGGL(k_bin_ranges, dim3((ntile + 255) / 256), dim3(256), 0, s, h2, toff, ntile, cnt, ranges,
-                       overflow_dev);
     return hipGetLastError();
 }
 
