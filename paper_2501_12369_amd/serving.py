@@ -112,10 +112,12 @@ class Scheduler:
         self.budget = int(mem_budget)
         self.max_slots = int(max_slots)
         self.max_inflight = int(max_inflight) if max_inflight is not None else self.max_slots
+        self.lookahead = 64  # queued requests considered per admission round
         self.clock = clock
         self.sleep = sleep
         self.idle = OrderedDict()  # key -> list of idle slots (LRU order of keys)
         self.busy = []              # (slot, request, start)
+        self.key_slots = {}         # key -> slots of that key (idle or busy)
         self.mem_used = 0
         self.n_slots = 0
         self.peak_slots = 0
@@ -133,6 +135,7 @@ class Scheduler:
                 s = self.idle[key].pop()
                 self.mem_used -= s.nbytes
                 self.n_slots -= 1
+                self.key_slots[key] -= 1
                 self.evictions += 1
                 s.free()
             if not self.idle[key]:
@@ -148,11 +151,15 @@ class Scheduler:
         need = self.need(key)
         if need > self.budget:
             raise MemoryError(f"request key {key} needs {need} bytes, above the budget {self.budget}")
+        fits = self.mem_used + need <= self.budget and self.n_slots < self.max_slots
+        if not fits and self.key_slots.get(key, 0) > 0:
+            return None  # wait for a slot of this key rather than evict another key's
         if not self._evict_for(need, key):
             return None
         s = self.factory(key, None)
         self.mem_used += s.nbytes
         self.n_slots += 1
+        self.key_slots[key] = self.key_slots.get(key, 0) + 1
         self.peak_slots = max(self.peak_slots, self.n_slots)
         self.peak_bytes = max(self.peak_bytes, self.mem_used)
         return s
@@ -175,13 +182,20 @@ class Scheduler:
             while pending and pending[0].arrival <= now:
                 queue.append(pending.popleft())
             progressed = False
-            while queue and len(self.busy) < self.max_inflight:
-                s = self.acquire(queue[0])
+            # admission: the oldest waiting request that can get a slot, looking past
+            # requests that wait for a busy slot of their key (order kept per key)
+            i = 0
+            blocked = set()
+            while i < min(len(queue), self.lookahead) and len(self.busy) < self.max_inflight:
+                r = queue[i]
+                s = None if r.key in blocked else self.acquire(r)
                 if s is None:
-                    break
-                req = queue.popleft()
-                s.launch(req)
-                self.busy.append((s, req, self.clock() - t0))
+                    blocked.add(r.key)
+                    i += 1
+                    continue
+                del queue[i]
+                s.launch(r)
+                self.busy.append((s, r, self.clock() - t0))
                 peak_inflight = max(peak_inflight, len(self.busy))
                 progressed = True
             still = []

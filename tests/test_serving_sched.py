@@ -149,3 +149,25 @@ def test_inflight_limit_keeps_slots():
     results, st2 = s.run([req(10 + i, 0.0, scene=i % 2) for i in range(4)])
     assert st2.n == 4 and st2.evictions == 0 and st2.peak_slots == 2 and st2.retries == 0
     assert sum(1 for e in log if e[0] == "free") == 0
+
+
+def test_saturation_waits_for_own_key_without_eviction():
+    # two keys, room for one slot each: under a burst each key waits for its own
+    # slot instead of evicting the other key's idle slot
+    kb = {(0, 64, 64): 400, (1, 64, 64): 400}
+    s, clock, log = make(budget=1000, max_slots=8, per_key_bytes=kb)
+    results, st = s.run([req(i, 0.0, scene=i % 2) for i in range(10)])
+    assert len(results) == 10 and st.evictions == 0 and st.peak_slots == 2
+    for key in (0, 1):  # per key, requests start in arrival order
+        starts = [e[1] for e in log if e[0] == "start" and e[3][0] == key]
+        assert starts == sorted(starts) and len(starts) == 5
+
+
+def test_admission_looks_past_a_waiting_key():
+    # key 0's second request waits for key 0's slot; key 1's request behind it starts at once
+    kb = {(0, 64, 64): 600, (1, 64, 64): 300}
+    s, clock, log = make(budget=1000, max_slots=8, per_key_bytes=kb, service=0.010)
+    results, st = s.run([req(0, 0.0, scene=0), req(1, 0.0, scene=0), req(2, 0.0, scene=1)])
+    by = {r.rid: r for r in results}
+    assert by[2].start < by[0].end <= by[1].start + 1e-9
+    assert st.evictions == 0 and st.peak_slots == 2
