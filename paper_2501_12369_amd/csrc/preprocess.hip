@@ -151,11 +151,23 @@ __device__ __forceinline__ bool view_depth(const Cam &cam, const float (&m)[3], 
     return P.t[2] > cam.near_z;
 }
 
-// Rotation and covariance of splat i; false for a zero quaternion.
-__device__ __forceinline__ bool splat_geom(int n, int i, const darb_splats &in, Geom &G) {
-    float qw = in.quats[i], qx = in.quats[n + i], qy = in.quats[2 * n + i], qz = in.quats[3 * n + i];
+// A splat's rotation and scale parameters as loaded: quaternion (w, x, y, z), scales.
+struct QS {
+    float q[4], s[3];
+};
+
+__device__ __forceinline__ QS load_qs(const darb_splats &in, int n, int i) {
+    QS v;
+    v.q[0] = in.quats[i]; v.q[1] = in.quats[n + i]; v.q[2] = in.quats[2 * n + i]; v.q[3] = in.quats[3 * n + i];
+    v.s[0] = in.scales[i]; v.s[1] = in.scales[n + i]; v.s[2] = in.scales[2 * n + i];
+    return v;
+}
+
+// Rotation and covariance from loaded parameters; false for a zero quaternion.
+__device__ __forceinline__ bool splat_geom_of(const QS &v, Geom &G) {
+    const float qw = v.q[0], qx = v.q[1], qy = v.q[2], qz = v.q[3];
     float qq = fmaf(qw, qw, fmaf(qx, qx, fmaf(qy, qy, qz * qz)));
-    G.s[0] = in.scales[i]; G.s[1] = in.scales[n + i]; G.s[2] = in.scales[2 * n + i];
+    G.s[0] = v.s[0]; G.s[1] = v.s[1]; G.s[2] = v.s[2];
     if (!(qq > 0.0f)) return false;
     float qnorm = sqrtf(qq);
     G.qinv = 1.0f / qnorm;
@@ -180,6 +192,11 @@ __device__ __forceinline__ bool splat_geom(int n, int i, const darb_splats &in, 
                               fmaf(Rq[r * 3 + 1] * s2[1], Rq[cc * 3 + 1], Rq[r * 3 + 2] * s2[2] * Rq[cc * 3 + 2]));
         }
     return true;
+}
+
+// Rotation and covariance of splat i; false for a zero quaternion.
+__device__ __forceinline__ bool splat_geom(int n, int i, const darb_splats &in, Geom &G) {
+    return splat_geom_of(load_qs(in, n, i), G);
 }
 
 // Projection of a splat in front of the camera (P.t set); false when culled.
@@ -390,32 +407,88 @@ __global__ __launch_bounds__(256) void k_preprocess_multi(Cams cams, KParams kp,
     }
 }
 
-// Per-view part of the gradient of one visible splat: the mean (through mu',
-// J and the SH direction), dL/dM for M = A Sigma A^T (symmetric 2x2: dM[0] =
-// d/dM00, dM[1] = d/dM01 (one entry), dM[2] = d/dM11), and Y, gv such that
-// d/d sh[b][ch] = Y[b] * gv[ch].
-template <int NB>
-__device__ __forceinline__ void splat_bwd_view(const Cam &cam, const KParams &kp, int i, const float (&m)[3],
-                                               const float (&csh)[NB][3], const darb_grads2d &g2, const Geom &G,
-                                               const Proj &P, float (&dmu)[3], float (&dM)[3], float (&Y)[NB],
-                                               float (&gvo)[3]) {
-    float grgb[3] = {g2.rgb[3 * i], g2.rgb[3 * i + 1], g2.rgb[3 * i + 2]};
-    dmu[0] = dmu[1] = dmu[2] = 0.0f;
+// FP64 copy of the view-independent geometry (unit quaternion, rotation,
+// scales, 3D covariance), from the FP32 parameters.
+struct Geom64 {
+    double Rq[9], qn[4], qinv, s[3], Sig[6];
+};
 
-    // ---- colour -> SH coefficients and view direction
+// The quaternion is nonzero (the FP32 geometry of a visible splat exists).
+__device__ __forceinline__ void splat_geom64(const QS &v, Geom64 &G) {
+    const double qw = v.q[0], qx = v.q[1], qy = v.q[2], qz = v.q[3];
+    G.s[0] = v.s[0];
+    G.s[1] = v.s[1];
+    G.s[2] = v.s[2];
+    G.qinv = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+    const double w = qw * G.qinv, x = qx * G.qinv, y = qy * G.qinv, z = qz * G.qinv;
+    G.qn[0] = w; G.qn[1] = x; G.qn[2] = y; G.qn[3] = z;
+    double *Rq = G.Rq;
+    Rq[0] = 1.0 - 2.0 * (y * y + z * z);
+    Rq[1] = 2.0 * (x * y - w * z);
+    Rq[2] = 2.0 * (x * z + w * y);
+    Rq[3] = 2.0 * (x * y + w * z);
+    Rq[4] = 1.0 - 2.0 * (x * x + z * z);
+    Rq[5] = 2.0 * (y * z - w * x);
+    Rq[6] = 2.0 * (x * z - w * y);
+    Rq[7] = 2.0 * (y * z + w * x);
+    Rq[8] = 1.0 - 2.0 * (x * x + y * y);
+    const double s2[3] = {G.s[0] * G.s[0], G.s[1] * G.s[1], G.s[2] * G.s[2]};
+    int k = 0;
+    for (int r = 0; r < 3; r++)
+        for (int cc = r; cc < 3; cc++)
+            G.Sig[k++] = Rq[r * 3] * s2[0] * Rq[cc * 3] + Rq[r * 3 + 1] * s2[1] * Rq[cc * 3 + 1] +
+                         Rq[r * 3 + 2] * s2[2] * Rq[cc * 3 + 2];
+}
+
+// Per-view part of the gradient of one visible splat: the mean (through mu',
+// J and the SH direction), the scales and the quaternion, and Y, gv such that
+// d/d sh[b][ch] = Y[b] * gv[ch].
+//
+// The colour part runs in FP32.  The chain from the 2D conic gradient to the
+// covariance, J and the splat's scales and rotation runs in FP64, on a
+// projection recomputed in FP64 from the FP32 inputs with the forward's FP32
+// decisions (Jacobian clamp): for a needle-like footprint the conic's small
+// eigen-direction is a residual of its entries, and the FP32 chain loses it
+// (about eps_32 kappa relative error in the scale and rotation gradients).
+// The kernel is HBM-bound, so the FP64 arithmetic costs little.
+// View direction terms of the colour of a visible splat: the unit direction
+// (dx, dy, dz) and 1/|v| from the camera centre, the SH basis Y, and gv[ch] =
+// dL/dcolour[ch] where the colour is not clamped (else 0).
+template <int NB>
+__device__ __forceinline__ void sh_view(const Cam &cam, const float (&m)[3], const float (&csh)[NB][3],
+                                        const float (&grgb)[3], float (&d)[3], float &il, float (&Y)[NB],
+                                        float (&gvo)[3]) {
     float vx = m[0] - cam.campos[0], vy = m[1] - cam.campos[1], vz = m[2] - cam.campos[2];
-    float il = rsqrtf(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
-    float dx = vx * il, dy = vy * il, dz = vz * il;
-    sh_eval<NB>(dx, dy, dz, Y);
-    float gdir[3] = {0.f, 0.f, 0.f};
+    il = rsqrtf(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
+    d[0] = vx * il;
+    d[1] = vy * il;
+    d[2] = vz * il;
+    sh_eval<NB>(d[0], d[1], d[2], Y);
 #pragma unroll
     for (int ch = 0; ch < 3; ch++) {
         float acc = 0.0f;
 #pragma unroll
         for (int b = 0; b < NB; b++) acc = fmaf(Y[b], csh[b][ch], acc);
         acc += 0.5f;
-        float gv = (acc < 0.0f) ? 0.0f : grgb[ch];
-        gvo[ch] = gv;
+        gvo[ch] = (acc < 0.0f) ? 0.0f : grgb[ch];
+    }
+}
+
+template <int NB>
+__device__ __forceinline__ void splat_bwd_view(const Cam &cam, const KParams &kp, int i, const float (&m)[3],
+                                               const float (&csh)[NB][3], const darb_grads2d &g2, const Geom64 &G,
+                                               const Proj &P, float (&dmu)[3], float (&dsc)[3], float (&dqo)[4],
+                                               float (&Y)[NB], float (&gvo)[3]) {
+    float grgb[3] = {g2.rgb[3 * i], g2.rgb[3 * i + 1], g2.rgb[3 * i + 2]};
+
+    // ---- colour -> SH coefficients and view direction (FP32)
+    float dv[3], il;
+    sh_view<NB>(cam, m, csh, grgb, dv, il, Y, gvo);
+    const float dx = dv[0], dy = dv[1], dz = dv[2];
+    float gdir[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ch = 0; ch < 3; ch++) {
+        const float gv = gvo[ch];
         float gsh[NB];
 #pragma unroll
         for (int b = 0; b < NB; b++) gsh[b] = gv * csh[b][ch];
@@ -428,107 +501,105 @@ __device__ __forceinline__ void splat_bwd_view(const Cam &cam, const KParams &kp
         }
     }
     float dd = fmaf(gdir[0], dx, fmaf(gdir[1], dy, gdir[2] * dz));
-    dmu[0] += (gdir[0] - dx * dd) * il;
-    dmu[1] += (gdir[1] - dy * dd) * il;
-    dmu[2] += (gdir[2] - dz * dd) * il;
+    const float dmu_sh[3] = {(gdir[0] - dx * dd) * il, (gdir[1] - dy * dd) * il, (gdir[2] - dz * dd) * il};
 
-    // ---- conic -> 2D covariance: dL/dcov = -Q Ghat Q, Ghat = [[ga, gb/2], [gb/2, gc]]
-    float ga = g2.conic[3 * i], gb = 0.5f * g2.conic[3 * i + 1], gc = g2.conic[3 * i + 2];
-    float a = P.a, b = P.b, c = P.c;
-    // Q Ghat
-    float t00 = fmaf(a, ga, b * gb), t01 = fmaf(a, gb, b * gc);
-    float t10 = fmaf(b, ga, c * gb), t11 = fmaf(b, gb, c * gc);
-    float d00 = -fmaf(t00, a, t01 * b);
-    float d01 = -fmaf(t00, b, t01 * c);
-    float d11 = -fmaf(t10, b, t11 * c);
-    // psi: M -> psi M + eps I
-    float m00 = kp.psi * d00, m01 = kp.psi * d01, m11 = kp.psi * d11;
-    dM[0] = m00;
-    dM[1] = m01;
-    dM[2] = m11;
-    // M = A Sigma A^T: dA = 2 dM A Sigma (the scale and rotation part is taken from
-    // dM directly, in geom_bwd)
-    const float *A = P.A;
-    float dMA0[3], dMA1[3];  // dM A (2x3)
+    // ---- projection in FP64: t, J (clamped as the forward decided), A = J R_cw,
+    //      2D covariance and conic
+    const float *Rf = cam.R;
+    double R[9];
+    for (int k = 0; k < 9; k++) R[k] = Rf[k];
+    const double t0 = R[0] * m[0] + R[1] * m[1] + R[2] * m[2] + (double)cam.t[0];
+    const double t1 = R[3] * m[0] + R[4] * m[1] + R[5] * m[2] + (double)cam.t[1];
+    const double tz = R[6] * m[0] + R[7] * m[1] + R[8] * m[2] + (double)cam.t[2];
+    const double itz = 1.0 / tz, itz2 = itz * itz;
+    const double fx = cam.fx, fy = cam.fy;
+    const double xt = P.cx_ ? (double)P.xt : t0 * itz;
+    const double yt = P.cy_ ? (double)P.yt : t1 * itz;
+    const double J00 = fx * itz, J02 = -fx * xt * itz, J11 = fy * itz, J12 = -fy * yt * itz;
+    double A[6];
     for (int cc = 0; cc < 3; cc++) {
-        dMA0[cc] = fmaf(m00, A[cc], m01 * A[3 + cc]);
-        dMA1[cc] = fmaf(m01, A[cc], m11 * A[3 + cc]);
+        A[cc] = J00 * R[cc] + J02 * R[6 + cc];
+        A[3 + cc] = J11 * R[3 + cc] + J12 * R[6 + cc];
     }
-    const float *Sg = G.Sig;
-    float Sf[9] = {Sg[0], Sg[1], Sg[2], Sg[1], Sg[3], Sg[4], Sg[2], Sg[4], Sg[5]};
-    float dA[6];
+    const double *Sg = G.Sig;
+    const double Sf[9] = {Sg[0], Sg[1], Sg[2], Sg[1], Sg[3], Sg[4], Sg[2], Sg[4], Sg[5]};
+    double AS0[3], AS1[3];  // A Sigma (2x3)
     for (int cc = 0; cc < 3; cc++) {
-        dA[cc] = 2.0f * fmaf(dMA0[0], Sf[cc], fmaf(dMA0[1], Sf[3 + cc], dMA0[2] * Sf[6 + cc]));
-        dA[3 + cc] = 2.0f * fmaf(dMA1[0], Sf[cc], fmaf(dMA1[1], Sf[3 + cc], dMA1[2] * Sf[6 + cc]));
+        AS0[cc] = A[0] * Sf[cc] + A[1] * Sf[3 + cc] + A[2] * Sf[6 + cc];
+        AS1[cc] = A[3] * Sf[cc] + A[4] * Sf[3 + cc] + A[5] * Sf[6 + cc];
+    }
+    const double psi = kp.psi, eps = cam.dilation;
+    const double c00 = psi * (AS0[0] * A[0] + AS0[1] * A[1] + AS0[2] * A[2]) + eps;
+    const double c01 = psi * (AS0[0] * A[3] + AS0[1] * A[4] + AS0[2] * A[5]);
+    const double c11 = psi * (AS1[0] * A[3] + AS1[1] * A[4] + AS1[2] * A[5]) + eps;
+    const double idet = 1.0 / (c00 * c11 - c01 * c01);
+    const double a = c11 * idet, b = -c01 * idet, c = c00 * idet;
+
+    // ---- conic -> 2D covariance: dL/dcov = -Q Ghat Q, Ghat = [[ga, gb/2], [gb/2, gc]];
+    //      psi: M -> psi M + eps I
+    const double ga = g2.conic[3 * i], gb = 0.5 * (double)g2.conic[3 * i + 1], gc = g2.conic[3 * i + 2];
+    const double q00 = a * ga + b * gb, q01 = a * gb + b * gc;
+    const double q10 = b * ga + c * gb, q11 = b * gb + c * gc;
+    const double m00 = -psi * (q00 * a + q01 * b);
+    const double m01 = -psi * (q00 * b + q01 * c);
+    const double m11 = -psi * (q10 * b + q11 * c);
+    // M = A Sigma A^T: dA = 2 dM A Sigma
+    double dA[6];
+    for (int cc = 0; cc < 3; cc++) {
+        dA[cc] = 2.0 * (m00 * AS0[cc] + m01 * AS1[cc]);
+        dA[3 + cc] = 2.0 * (m01 * AS0[cc] + m11 * AS1[cc]);
     }
     // A = J R_cw: dJ = dA R_cw^T
-    const float *R = cam.R;
-    float dJ00 = fmaf(dA[0], R[0], fmaf(dA[1], R[1], dA[2] * R[2]));
-    float dJ02 = fmaf(dA[0], R[6], fmaf(dA[1], R[7], dA[2] * R[8]));
-    float dJ11 = fmaf(dA[3], R[3], fmaf(dA[4], R[4], dA[5] * R[5]));
-    float dJ12 = fmaf(dA[3], R[6], fmaf(dA[4], R[7], dA[5] * R[8]));
-    float tx = P.t[0], ty = P.t[1], tz = P.t[2];
-    float itz = 1.0f / tz, itz2 = itz * itz;
-    float fx = cam.fx, fy = cam.fy;
-    float dxt_dtx = P.cx_ ? 0.0f : itz, dxt_dtz = P.cx_ ? 0.0f : -tx * itz2;
-    float dyt_dty = P.cy_ ? 0.0f : itz, dyt_dtz = P.cy_ ? 0.0f : -ty * itz2;
-    float dtx = dJ02 * (-fx * dxt_dtx * itz);
-    float dty = dJ12 * (-fy * dyt_dty * itz);
-    float dtz = dJ00 * (-fx * itz2) + dJ11 * (-fy * itz2);
-    dtz += dJ02 * (-fx * fmaf(dxt_dtz, tz, -P.xt) * itz2);
-    dtz += dJ12 * (-fy * fmaf(dyt_dtz, tz, -P.yt) * itz2);
+    const double dJ00 = dA[0] * R[0] + dA[1] * R[1] + dA[2] * R[2];
+    const double dJ02 = dA[0] * R[6] + dA[1] * R[7] + dA[2] * R[8];
+    const double dJ11 = dA[3] * R[3] + dA[4] * R[4] + dA[5] * R[5];
+    const double dJ12 = dA[3] * R[6] + dA[4] * R[7] + dA[5] * R[8];
+    const double dxt_dtx = P.cx_ ? 0.0 : itz, dxt_dtz = P.cx_ ? 0.0 : -t0 * itz2;
+    const double dyt_dty = P.cy_ ? 0.0 : itz, dyt_dtz = P.cy_ ? 0.0 : -t1 * itz2;
+    double dtx = dJ02 * (-fx * dxt_dtx * itz);
+    double dty = dJ12 * (-fy * dyt_dty * itz);
+    double dtz = dJ00 * (-fx * itz2) + dJ11 * (-fy * itz2);
+    dtz += dJ02 * (-fx * (dxt_dtz * tz - xt) * itz2);
+    dtz += dJ12 * (-fy * (dyt_dtz * tz - yt) * itz2);
     // mean2D
-    float gu = g2.xy[2 * i], gvv = g2.xy[2 * i + 1];
+    const double gu = g2.xy[2 * i], gvv = g2.xy[2 * i + 1];
     dtx += gu * fx * itz;
     dty += gvv * fy * itz;
-    dtz -= (gu * fx * tx + gvv * fy * ty) * itz2;
+    dtz -= (gu * fx * t0 + gvv * fy * t1) * itz2;
     // t = R_cw mu + t_cw
-    dmu[0] += fmaf(R[0], dtx, fmaf(R[3], dty, R[6] * dtz));
-    dmu[1] += fmaf(R[1], dtx, fmaf(R[4], dty, R[7] * dtz));
-    dmu[2] += fmaf(R[2], dtx, fmaf(R[5], dty, R[8] * dtz));
-}
+    dmu[0] = dmu_sh[0] + (float)(R[0] * dtx + R[3] * dty + R[6] * dtz);
+    dmu[1] = dmu_sh[1] + (float)(R[1] * dtx + R[4] * dty + R[7] * dtz);
+    dmu[2] = dmu_sh[2] + (float)(R[2] * dtx + R[5] * dty + R[8] * dtz);
 
-// Scale and rotation part of the chain, from dM (M = A Sigma A^T = B B^T,
-// B = C diag(s), C = A Rq): with dMq = 2 A^T dM B,
-//   ds_j  = sum_r dMq_rj Rq_rj = 2 s_j  c_j^T dM c_j        (c_j = column j of C)
-//   dRq_rj = dMq_rj s_j        = 2 s_j^2 (A^T dM C)_rj
-// Working in the projected 2D space keeps each axis separate: forming the 3x3
-// dL/dSigma first and projecting it back on a short axis cancels in FP32 for
-// needle-like splats.  Then the rotation-matrix gradient goes to the quaternion
-// (through the normalisation).
-__device__ __forceinline__ void geom_bwd(const Geom &G, const float (&A)[6], const float (&dM)[3], float (&dsc)[3],
-                                         float (&dqo)[4]) {
-    const float *Rq = G.Rq;
-    float C[2][3];
-    for (int r = 0; r < 2; r++)
-        for (int cc = 0; cc < 3; cc++)
-            C[r][cc] = fmaf(A[3 * r], Rq[cc], fmaf(A[3 * r + 1], Rq[3 + cc], A[3 * r + 2] * Rq[6 + cc]));
-    float dR[9];
+    // ---- scales and rotation from dM (M = B B^T, B = C diag(s), C = A Rq):
+    //   ds_j = 2 s_j c_j^T dM c_j,  dRq_rj = 2 s_j^2 (A^T dM C)_rj
+    const double *Rq = G.Rq;
+    double C0[3], C1[3];
     for (int cc = 0; cc < 3; cc++) {
-        // dM c_j
-        const float e0 = fmaf(dM[0], C[0][cc], dM[1] * C[1][cc]);
-        const float e1 = fmaf(dM[1], C[0][cc], dM[2] * C[1][cc]);
-        dsc[cc] = 2.0f * G.s[cc] * fmaf(C[0][cc], e0, C[1][cc] * e1);
-        const float k = 2.0f * G.s[cc] * G.s[cc];
-        for (int r = 0; r < 3; r++) dR[r * 3 + cc] = k * fmaf(A[r], e0, A[3 + r] * e1);
+        C0[cc] = A[0] * Rq[cc] + A[1] * Rq[3 + cc] + A[2] * Rq[6 + cc];
+        C1[cc] = A[3] * Rq[cc] + A[4] * Rq[3 + cc] + A[5] * Rq[6 + cc];
     }
-    // Rotation gradient as a small rotation phi applied on the left, R' = (I + [phi]x) R:
-    // dL/dphi is the antisymmetric part of dR R^T.  The unit-quaternion tangent is
-    // (0, phi/2) (x) q, so the gradient in the tangent plane is
-    // 2 (-g.v, w g + g x v) with g = dL/dphi, q = (w, v), and d/dq = that / |q|.
-    // (Going through the raw quaternion derivative and removing its radial part
-    // afterwards cancels in FP32.)
-    float Mk[3][3];
+    double dR[9];
+    for (int cc = 0; cc < 3; cc++) {
+        const double e0 = m00 * C0[cc] + m01 * C1[cc];
+        const double e1 = m01 * C0[cc] + m11 * C1[cc];
+        dsc[cc] = (float)(2.0 * G.s[cc] * (C0[cc] * e0 + C1[cc] * e1));
+        const double k = 2.0 * G.s[cc] * G.s[cc];
+        for (int r = 0; r < 3; r++) dR[r * 3 + cc] = k * (A[r] * e0 + A[3 + r] * e1);
+    }
+    // rotation gradient through the rotation vector of dR Rq^T (its antisymmetric
+    // part), then to the quaternion through the normalisation
+    double Mk[3][3];
     for (int r = 0; r < 3; r++)
         for (int cc = 0; cc < 3; cc++)
-            Mk[r][cc] = fmaf(dR[r * 3 + 0], Rq[cc * 3 + 0], fmaf(dR[r * 3 + 1], Rq[cc * 3 + 1], dR[r * 3 + 2] * Rq[cc * 3 + 2]));
-    const float g0 = Mk[2][1] - Mk[1][2], g1 = Mk[0][2] - Mk[2][0], g2 = Mk[1][0] - Mk[0][1];
-    const float w = G.qn[0], x = G.qn[1], y = G.qn[2], z = G.qn[3];
-    const float s2 = 2.0f * G.qinv;
-    dqo[0] = -s2 * fmaf(g0, x, fmaf(g1, y, g2 * z));
-    dqo[1] = s2 * fmaf(w, g0, fmaf(g1, z, -g2 * y));
-    dqo[2] = s2 * fmaf(w, g1, fmaf(g2, x, -g0 * z));
-    dqo[3] = s2 * fmaf(w, g2, fmaf(g0, y, -g1 * x));
+            Mk[r][cc] = dR[r * 3] * Rq[cc * 3] + dR[r * 3 + 1] * Rq[cc * 3 + 1] + dR[r * 3 + 2] * Rq[cc * 3 + 2];
+    const double h0 = Mk[2][1] - Mk[1][2], h1 = Mk[0][2] - Mk[2][0], h2 = Mk[1][0] - Mk[0][1];
+    const double w = G.qn[0], x = G.qn[1], y = G.qn[2], z = G.qn[3];
+    const double s2q = 2.0 * G.qinv;
+    dqo[0] = (float)(-s2q * (h0 * x + h1 * y + h2 * z));
+    dqo[1] = (float)(s2q * (w * h0 + h1 * z - h2 * y));
+    dqo[2] = (float)(s2q * (w * h1 + h2 * x - h0 * z));
+    dqo[3] = (float)(s2q * (w * h2 + h0 * y - h1 * x));
 }
 
 // Gradients of one splat, accumulated over views by the callers.
@@ -573,9 +644,10 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(Cam cam, KParams kp, int
         load_mean(in, n, i, m);
         float csh[NB][3];
         load_sh<NB>(in.sh, n, i, csh);
-        float dM[3], Y[NB], gv[3];
-        splat_bwd_view<NB>(cam, kp, i, m, csh, g2, G, P, g.dmu, dM, Y, gv);
-        geom_bwd(G, P.A, dM, g.dsc, g.dq);
+        Geom64 G64;
+        splat_geom64(load_qs(in, n, i), G64);
+        float Y[NB], gv[3];
+        splat_bwd_view<NB>(cam, kp, i, m, csh, g2, G64, P, g.dmu, g.dsc, g.dq, Y, gv);
         g.dop = g2.opacity[i];
 #pragma unroll
         for (int b = 0; b < NB; b++)
@@ -596,23 +668,30 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_multi(Cams cams, KParams
     if (i >= n) return;
     float m[3];
     load_mean(in, n, i, m);
-    Geom G;
-    const bool geom = splat_geom(n, i, in, G);
+    // the geometry is rebuilt per view from the loaded parameters (FP32 for the
+    // decisions, FP64 for the chain) instead of kept across the loop: fewer
+    // registers live beside the colour accumulators
+    const QS qs = load_qs(in, n, i);
+    const bool geom = fmaf(qs.q[0], qs.q[0], fmaf(qs.q[1], qs.q[1], fmaf(qs.q[2], qs.q[2], qs.q[3] * qs.q[3]))) > 0.0f;
     Grad3 tot = {};
     float gsh[NB][3];
 #pragma unroll
     for (int b = 0; b < NB; b++) gsh[b][0] = gsh[b][1] = gsh[b][2] = 0.0f;
+    uint32_t vmask = 0;  // views where the splat is visible
     if (geom) {
         float csh[NB][3];
         load_sh<NB>(in.sh, n, i, csh);
         for (int v = 0; v < cams.nv; v++) {
             const Cam &cam = cams.c[v];
             Proj P;
-            if (!(view_depth(cam, m, P) && project_rest(cam, kp, G, P))) continue;
+            Geom G;
+            if (!(view_depth(cam, m, P) && splat_geom_of(qs, G) && project_rest(cam, kp, G, P))) continue;
+            vmask |= 1u << v;
+            Geom64 G64;
+            splat_geom64(qs, G64);
             Grad3 g;
-            float dM[3], Y[NB], gv[3];
-            splat_bwd_view<NB>(cam, kp, i, m, csh, g2.g[v], G, P, g.dmu, dM, Y, gv);
-            geom_bwd(G, P.A, dM, g.dsc, g.dq);
+            float Y[NB], gv[3];
+            splat_bwd_view<NB>(cam, kp, i, m, csh, g2.g[v], G64, P, g.dmu, g.dsc, g.dq, Y, gv);
             g.dop = g2.g[v].opacity[i];
 #pragma unroll
             for (int c = 0; c < 3; c++) {
@@ -622,6 +701,15 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_multi(Cams cams, KParams
 #pragma unroll
             for (int c = 0; c < 4; c++) tot.dq[c] += g.dq[c];
             tot.dop += g.dop;
+        }
+        // SH coefficient gradients in a second pass over the visible views (same
+        // terms and order as above; the 48 accumulators are not live beside the
+        // FP64 chain)
+        for (int v = 0; v < cams.nv; v++) {
+            if (!((vmask >> v) & 1u)) continue;
+            const float grgb[3] = {g2.g[v].rgb[3 * i], g2.g[v].rgb[3 * i + 1], g2.g[v].rgb[3 * i + 2]};
+            float d[3], il, Y[NB], gv[3];
+            sh_view<NB>(cams.c[v], m, csh, grgb, d, il, Y, gv);
 #pragma unroll
             for (int b = 0; b < NB; b++)
 #pragma unroll

@@ -13,13 +13,12 @@ times (the plain render + render_backward path):
 Pixels whose oracle decisions sit within 1e-3 (relative) of a threshold are
 left out of the samples, so both sides take the same decisions.
 
-The 3D gradients of scale and rotation of a needle-like footprint are
-ill-conditioned in FP32: they are small residuals of the conic gradient along
-the needle, and their rounding error grows with the footprint's condition
-number kappa = lambda_max / lambda_min of the 2D covariance (~eps_32 kappa).
-Splats with kappa <= 1000 are held to 1e-3; those beyond (measured: 118 of
-1690 half-cosine and 394 of 9057 Gaussian splats that the sampled pixels
-reach; their errors 1e-4 to 2e-3) to 1e-2.
+The 3D gradients of scale and rotation of a needle-like footprint are small
+residuals of the conic gradient along the needle (ill-conditioned: an FP32
+chain errs by about eps_32 kappa, kappa = lambda_max / lambda_min of the 2D
+covariance); the library runs that chain in FP64.  Every splat is held to
+1e-3; the needle-like ones (kappa > 1000: 118 of 1690 half-cosine and 394 of
+9057 Gaussian splats that the sampled pixels reach) are also reported apart.
 """
 import numpy as np
 import pytest
@@ -161,4 +160,4 @@ def test_scene_scale_sampled_image_and_sparse_gradients(kname):
         l2n = np.linalg.norm((a - b)[..., ~well]) / max(np.linalg.norm(b[..., ~well]), 1e-30)
         print(f"  3D {name:8s} relL2 kappa<=1000 {l2w:.2e}, beyond {l2n:.2e}")
         assert l2w <= 1e-3, (name, l2w)
-        assert l2n <= 1e-2, (name, l2n)
+        assert l2n <= 1e-3, (name, l2n)
