@@ -38,16 +38,19 @@ def stage_bytes(n, n_vis):
     each needed input, one write of each output), per splat / per visible splat:
       preprocess      12 B mean + 4 B cull data of every splat; 224 B of parameters
                       (scale, quaternion, opacity, 48 SH) read and 48 B of projected
-                      record written per visible splat:           16 N + 272 N_v
-      preprocess_bwd  parameters and 2D gradients of the visible splats read (308 B),
-                      the full gradient written for every splat:   308 N_v + 236 N
+                      record written per visible splat; the 36 B colour checkpoint
+                      (d colour / d direction) written for every splat:
+                                                                  52 N + 272 N_v
+      preprocess_bwd  per visible splat 113 B read (mean 12, scale 12, quaternion 16,
+                      2D gradients 36, colour checkpoint 36 + clamp bits 1), the full
+                      gradient written for every splat (236 B):   113 N_v + 236 N
     """
-    return dict(preprocess=16 * n + 272 * n_vis, preprocess_bwd=308 * n_vis + 236 * n)
+    return dict(preprocess=52 * n + 272 * n_vis, preprocess_bwd=113 * n_vis + 236 * n)
 
 
 # kernel of each single-kernel stage, and the sources it is built from
 STAGE_KERNEL = {"preprocess": ("k_preprocess<3>", ("preprocess.hip", "common.h")),
-                "preprocess_bwd": ("k_preprocess_bwd<3>", ("preprocess.hip", "common.h"))}
+                "preprocess_bwd": ("k_preprocess_bwd<3, true>", ("preprocess.hip", "common.h"))}
 
 
 def sources_digest(files) -> str:
@@ -209,7 +212,7 @@ def variants_bench(spd, cam, steps: int, warmup: int):
                                pipeline.DEFAULT_OPTS, frame.image, frame.final_T, frame.last)
         native.darb_raster_bwd(frame.proj, n, frame.vals, frame.ranges, frame.overflow, W, H, kern,
                                pipeline.DEFAULT_OPTS, G, frame.final_T, frame.last, grads[0])
-        native.darb_preprocess_bwd(cam, kern, n, spd, grads[0], grads[1])
+        native.darb_preprocess_bwd(cam, kern, n, spd, grads[0], grads[1], proj=frame.proj)
 
     def timed(fn):
         for _ in range(warmup):
@@ -372,7 +375,7 @@ def main():
                                pipeline.DEFAULT_OPTS, G, frame.final_T, frame.last, grads[0])
         if ev is not None:
             ev[4].record()
-        native.darb_preprocess_bwd(cam, kern, n, spd, grads[0], grads[1])
+        native.darb_preprocess_bwd(cam, kern, n, spd, grads[0], grads[1], proj=frame.proj)
         if ev is not None:
             ev[5].record()
 

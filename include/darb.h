@@ -40,7 +40,7 @@ extern "C" {
 #define DARB_API
 #endif
 
-#define DARB_ABI_VERSION 2
+#define DARB_ABI_VERSION 3
 #define DARB_TILE 16
 #define DARB_MAX_VIEWS 16       /* views per multi-view call */
 #define DARB_LOSS_WS_BYTES 4096 /* workspace of darb_image_loss */
@@ -137,7 +137,12 @@ typedef struct {
  *                     covariance) as its factor Q = L^T L, L = [[l00, l01], [0, l11]]
  *                     (l00, l11 > 0), so that E = |L d|^2 is a sum of squares
  *   rgb      [n][3]   colour after the SH evaluation and the clamp at 0
- *   clamped  [n]      bit c set when channel c was clamped at 0                       */
+ *   clamped  [n]      bit c set when channel c was clamped at 0
+ *   dcolor   [9][n]   nullable: d colour / d u, u the unit view direction from the camera
+ *                     centre (plane 3 c + k holds d colour_c / d u_k, before the clamp;
+ *                     zeros for culled splats).  darb_preprocess writes it when non-null;
+ *                     with it darb_preprocess_bwd reads neither the SH coefficients nor
+ *                     recomputes the colour (a checkpoint of the forward).              */
 typedef struct {
     float *xy;
     float *depth;
@@ -145,6 +150,7 @@ typedef struct {
     float *conic_o;
     float *rgb;
     uint8_t *clamped;
+    float *dcolor;
 } darb_projected;
 
 /* Gradients with respect to the projected quantities (raster backward output):
@@ -292,7 +298,8 @@ DARB_API darb_status darb_raster_fwd(const darb_projected *proj, int64_t n, cons
  *   dL_dimage [3][H][W]
  *   g2d       required output
  *   cam, in, g3d: when g3d is non-null the call continues with the chain of
- *             darb_preprocess_bwd (cam and in then required) and overwrites g3d.
+ *             darb_preprocess_bwd (cam and in then required; proj passed on, so its
+ *             dcolor is used when set) and overwrites g3d.
  */
 DARB_API darb_status darb_raster_bwd(const darb_projected *proj, int64_t n, const uint32_t *vals, const uint32_t *ranges,
                             const int32_t *overflow_dev, int32_t width, int32_t height, const darb_kernel *kernel,
@@ -316,11 +323,17 @@ DARB_API size_t darb_raster_bwd_workspace(int64_t n, int32_t width, int32_t heig
  * (through the normalisation); the mean through mu', through J (zero across
  * an active Jacobian clamp) and through the SH view direction; SH
  * coefficients (zero for clamped channels); opacity passed through.
+ * proj nullable: the records darb_preprocess wrote for the same camera and
+ * splats; when proj->dcolor and proj->clamped are set, the colour part of the
+ * chain uses them (the SH coefficients are not read), else it recomputes the
+ * colour from the SH coefficients.  Both give the same gradients up to FP32
+ * rounding.
  * accumulate = 0: g3d is overwritten for every splat (zeros for culled splats);
  * accumulate = 1: the gradients are added to g3d (several views in turn).
  */
 DARB_API darb_status darb_preprocess_bwd(const darb_camera *cam, const darb_kernel *kernel, int64_t n, const darb_splats *in,
-                                const darb_grads2d *g2d, const darb_grads3d *g3d, int32_t accumulate, void *stream);
+                                const darb_projected *proj, const darb_grads2d *g2d, const darb_grads3d *g3d,
+                                int32_t accumulate, void *stream);
 
 /*
  * darb_image_loss -- per-pixel image loss of a rendered view against a target
@@ -425,7 +438,8 @@ DARB_API darb_status darb_raster_fwdbwd_multi(const darb_view *views, int32_t nv
 /*
  * darb_preprocess_bwd_multi -- darb_preprocess_bwd summed over the views:
  * g3d = sum_v chain(views[v].cam, views[v].grads2d), views in order, with the
- * splat parameters read once and g3d written once (overwritten).
+ * splat parameters read once and g3d written once (overwritten).  When every
+ * view's proj has dcolor and clamped set, the colour part uses them.
  */
 DARB_API darb_status darb_preprocess_bwd_multi(const darb_view *views, int32_t nv, const darb_kernel *kernel, int64_t n,
                                                const darb_splats *in, const darb_grads3d *g3d, void *stream);

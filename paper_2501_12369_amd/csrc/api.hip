@@ -385,7 +385,8 @@ darb_status darb_raster_fwd(const darb_projected *proj, int64_t n, const uint32_
 }
 
 darb_status darb_preprocess_bwd(const darb_camera *cam, const darb_kernel *kernel, int64_t n, const darb_splats *in,
-                                const darb_grads2d *g2d, const darb_grads3d *g3d, int32_t accumulate, void *stream) {
+                                const darb_projected *proj, const darb_grads2d *g2d, const darb_grads3d *g3d,
+                                int32_t accumulate, void *stream) {
     darb::Cam c;
     darb::KParams kp;
     TRY(check_n(n));
@@ -396,7 +397,8 @@ darb_status darb_preprocess_bwd(const darb_camera *cam, const darb_kernel *kerne
     TRY(check_g2d(g2d, n));
     TRY(check_g3d(g3d, n));
     g_err[0] = 0;
-    return hip_status(darb::launch_preprocess_bwd(c, kp, (int)n, *in, *g2d, *g3d, accumulate != 0, (hipStream_t)stream),
+    return hip_status(darb::launch_preprocess_bwd(c, kp, (int)n, *in, proj, *g2d, *g3d, accumulate != 0,
+                                                  (hipStream_t)stream),
                       "darb_preprocess_bwd");
 }
 
@@ -452,7 +454,8 @@ darb_status darb_raster_bwd(const darb_projected *proj, int64_t n, const uint32_
                                            deterministic ? (uint64_t)k_capacity : 0, s),
                    "darb_raster_bwd"));
     if (g3d)
-        TRY(hip_status(darb::launch_preprocess_bwd(c, kp, (int)n, *in, *g2d, *g3d, false, s), "darb_raster_bwd chain"));
+        TRY(hip_status(darb::launch_preprocess_bwd(c, kp, (int)n, *in, proj, *g2d, *g3d, false, s),
+                       "darb_raster_bwd chain"));
     return DARB_OK;
 }
 
@@ -657,7 +660,11 @@ darb_status darb_preprocess_bwd_multi(const darb_view *views, int32_t nv, const 
     TRY(check_g3d(g3d, n));
     TRY(check_views(views, nv, n, kNeedG2, nullptr, &cams, nullptr, nullptr));
     darb::G2s g2{};
-    for (int v = 0; v < nv; v++) g2.g[v] = views[v].grads2d;
+    for (int v = 0; v < nv; v++) {
+        g2.g[v] = views[v].grads2d;
+        g2.dcolor[v] = views[v].proj.dcolor;
+        g2.clamped[v] = views[v].proj.clamped;
+    }
     g_err[0] = 0;
     return hip_status(darb::launch_preprocess_bwd_multi(cams, kp, (int)n, *in, g2, *g3d, (hipStream_t)stream),
                       "darb_preprocess_bwd_multi");

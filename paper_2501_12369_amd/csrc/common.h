@@ -293,16 +293,23 @@ struct Projs {
     darb_projected p[kMaxViews];
 };
 
+// Per view: the 2D gradients, and the forward's colour checkpoint (dcolor,
+// clamped; null when not kept).
 struct G2s {
     darb_grads2d g[kMaxViews];
+    const float *dcolor[kMaxViews];
+    const uint8_t *clamped[kMaxViews];
 };
 
 // cam_dev (nullable): camera read from device memory instead of `cam`
 // (whose width/height still size the tile grid)
 hipError_t launch_preprocess(const Cam &cam, const darb_camera *cam_dev, const KParams &kp, int n,
                              const darb_splats &in, const darb_projected &out, hipStream_t s);
+// ckpt (nullable): the forward's records of this view; its dcolor and clamped,
+// when both set, replace the SH coefficients in the colour part of the chain
 hipError_t launch_preprocess_bwd(const Cam &cam, const KParams &kp, int n, const darb_splats &in,
-                                 const darb_grads2d &g2d, const darb_grads3d &g3d, bool accumulate, hipStream_t s);
+                                 const darb_projected *ckpt, const darb_grads2d &g2d, const darb_grads3d &g3d,
+                                 bool accumulate, hipStream_t s);
 hipError_t launch_preprocess_multi(const Cams &cams, const KParams &kp, int n, const darb_splats &in,
                                    const Projs &outs, hipStream_t s);
 hipError_t launch_preprocess_bwd_multi(const Cams &cams, const KParams &kp, int n, const darb_splats &in,

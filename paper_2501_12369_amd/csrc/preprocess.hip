@@ -323,14 +323,17 @@ __device__ __forceinline__ Cam cam_from_device(const darb_camera *c, int width, 
     return m;
 }
 
-// Colour of a visible splat from its loaded SH coefficients; sets the clamp bits.
-template <int NB>
+// Colour of a visible splat from its loaded SH coefficients; sets the clamp
+// bits, and with JAC the derivative of each channel (before the clamp) with
+// respect to the unit view direction u: jac[3 c + k] = d colour_c / d u_k.
+template <int NB, bool JAC>
 __device__ __forceinline__ void sh_colour(const Cam &cam, const float (&m)[3], const float (&c)[NB][3], float (&col)[3],
-                                          uint8_t &cl) {
+                                          uint8_t &cl, float (&jac)[9]) {
     float dx = m[0] - cam.campos[0], dy = m[1] - cam.campos[1], dz = m[2] - cam.campos[2];
     float il = rsqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+    const float ux = dx * il, uy = dy * il, uz = dz * il;
     float Y[NB];
-    sh_eval<NB>(dx * il, dy * il, dz * il, Y);
+    sh_eval<NB>(ux, uy, uz, Y);
     cl = 0;
 #pragma unroll
     for (int ch = 0; ch < 3; ch++) {
@@ -340,12 +343,25 @@ __device__ __forceinline__ void sh_colour(const Cam &cam, const float (&m)[3], c
         acc += 0.5f;
         if (acc < 0.0f) cl |= (uint8_t)(1u << ch);
         col[ch] = fmaxf(acc, 0.0f);
+        if constexpr (JAC) {
+            float g[NB], d[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int b = 0; b < NB; b++) g[b] = c[b][ch];
+            if constexpr (NB > 1) sh_grad<NB>(ux, uy, uz, g, d);
+            jac[3 * ch] = d[0];
+            jac[3 * ch + 1] = d[1];
+            jac[3 * ch + 2] = d[2];
+        }
     }
 }
 
 // Every lane stores (zeros for culled splats): whole-line writes.
-__device__ __forceinline__ void store_proj(const darb_projected &out, int i, bool vis, const Proj &P, float op,
-                                           const float (&col)[3], uint8_t cl) {
+__device__ __forceinline__ void store_proj(const darb_projected &out, int n, int i, bool vis, const Proj &P, float op,
+                                           const float (&col)[3], uint8_t cl, const float (&jac)[9]) {
+    if (out.dcolor) {
+#pragma unroll
+        for (int k = 0; k < 9; k++) out.dcolor[(size_t)k * n + i] = vis ? jac[k] : 0.0f;
+    }
     reinterpret_cast<float2 *>(out.xy)[i] = vis ? make_float2(P.u, P.v) : make_float2(0.0f, 0.0f);
     out.depth[i] = vis ? P.t[2] : 0.0f;
     out.radius[i] = vis ? P.radius : 0;
@@ -367,6 +383,7 @@ __global__ __launch_bounds__(256) void k_preprocess(Cam cam_arg, const darb_came
     Proj P;
     const bool vis = project(cam, kp, n, i, in, G, P);
     float col[3] = {0.0f, 0.0f, 0.0f};
+    float jac[9] = {};
     float op = 0.0f;
     uint8_t cl = 0;
     if (vis) {
@@ -375,9 +392,12 @@ __global__ __launch_bounds__(256) void k_preprocess(Cam cam_arg, const darb_came
         op = in.opacity[i];
         float m[3];
         load_mean(in, n, i, m);
-        sh_colour<NB>(cam, m, c, col, cl);
+        if (out.dcolor)
+            sh_colour<NB, true>(cam, m, c, col, cl, jac);
+        else
+            sh_colour<NB, false>(cam, m, c, col, cl, jac);
     }
-    store_proj(out, i, vis, P, op, col, cl);
+    store_proj(out, n, i, vis, P, op, col, cl, jac);
 }
 
 // Several views: the parameters are read once, the geometry computed once.
@@ -401,9 +421,15 @@ __global__ __launch_bounds__(256) void k_preprocess_multi(Cams cams, KParams kp,
         Proj P;
         const bool vis = geom && view_depth(cam, m, P) && project_rest(cam, kp, G, P);
         float col[3] = {0.0f, 0.0f, 0.0f};
+        float jac[9] = {};
         uint8_t cl = 0;
-        if (vis) sh_colour<NB>(cam, m, c, col, cl);
-        store_proj(outs.p[v], i, vis, P, vis ? op : 0.0f, col, cl);
+        if (vis) {
+            if (outs.p[v].dcolor)
+                sh_colour<NB, true>(cam, m, c, col, cl, jac);
+            else
+                sh_colour<NB, false>(cam, m, c, col, cl, jac);
+        }
+        store_proj(outs.p[v], n, i, vis, P, vis ? op : 0.0f, col, cl, jac);
     }
 }
 
@@ -441,10 +467,9 @@ __device__ __forceinline__ void splat_geom64(const QS &v, Geom64 &G) {
 }
 
 // Per-view part of the gradient of one visible splat: the mean (through mu',
-// J and the SH direction), the scales and the quaternion, and Y, gv such that
-// d/d sh[b][ch] = Y[b] * gv[ch].
-//
-// The colour part runs in FP32.  The chain from the 2D conic gradient to the
+// J and, given as dmu_sh, the SH direction), the scales and the quaternion.
+// The colour part (colour_bwd_*: Y, gv with d/d sh[b][ch] = Y[b] * gv[ch])
+// runs in FP32.  The chain from the 2D conic gradient to the
 // covariance, J and the splat's scales and rotation runs in FP64, on a
 // projection recomputed in FP64 from the FP32 inputs with the forward's FP32
 // decisions (Jacobian clamp): for a needle-like footprint the conic's small
@@ -474,17 +499,23 @@ __device__ __forceinline__ void sh_view(const Cam &cam, const float (&m)[3], con
     }
 }
 
-template <int NB>
-__device__ __forceinline__ void splat_bwd_view(const Cam &cam, const KParams &kp, int i, const float (&m)[3],
-                                               const float (&csh)[NB][3], const darb_grads2d &g2, const Geom64 &G,
-                                               const Proj &P, float (&dmu)[3], float (&dsc)[3], float (&dqo)[4],
-                                               float (&Y)[NB], float (&gvo)[3]) {
-    float grgb[3] = {g2.rgb[3 * i], g2.rgb[3 * i + 1], g2.rgb[3 * i + 2]};
+// The mean's gradient through the view direction, from gdir = d L / d u (u the
+// unit direction): the tangential part divided by |v|.
+__device__ __forceinline__ void dir_to_mean(const float (&d)[3], float il, const float (&gdir)[3], float (&out)[3]) {
+    const float dd = fmaf(gdir[0], d[0], fmaf(gdir[1], d[1], gdir[2] * d[2]));
+    out[0] = (gdir[0] - d[0] * dd) * il;
+    out[1] = (gdir[1] - d[1] * dd) * il;
+    out[2] = (gdir[2] - d[2] * dd) * il;
+}
 
-    // ---- colour -> SH coefficients and view direction (FP32)
-    float dv[3], il;
-    sh_view<NB>(cam, m, csh, grgb, dv, il, Y, gvo);
-    const float dx = dv[0], dy = dv[1], dz = dv[2];
+// Colour part of the chain from the SH coefficients: Y, gv (see sh_view) and
+// the mean's gradient through the view direction.
+template <int NB>
+__device__ __forceinline__ void colour_bwd_sh(const Cam &cam, const float (&m)[3], const float (&csh)[NB][3],
+                                              const float (&grgb)[3], float (&Y)[NB], float (&gvo)[3],
+                                              float (&dmu_sh)[3]) {
+    float d[3], il;
+    sh_view<NB>(cam, m, csh, grgb, d, il, Y, gvo);
     float gdir[3] = {0.f, 0.f, 0.f};
 #pragma unroll
     for (int ch = 0; ch < 3; ch++) {
@@ -494,14 +525,40 @@ __device__ __forceinline__ void splat_bwd_view(const Cam &cam, const KParams &kp
         for (int b = 0; b < NB; b++) gsh[b] = gv * csh[b][ch];
         if constexpr (NB > 1) {
             float gd[3];
-            sh_grad<NB>(dx, dy, dz, gsh, gd);
+            sh_grad<NB>(d[0], d[1], d[2], gsh, gd);
             gdir[0] += gd[0];
             gdir[1] += gd[1];
             gdir[2] += gd[2];
         }
     }
-    float dd = fmaf(gdir[0], dx, fmaf(gdir[1], dy, gdir[2] * dz));
-    const float dmu_sh[3] = {(gdir[0] - dx * dd) * il, (gdir[1] - dy * dd) * il, (gdir[2] - dz * dd) * il};
+    dir_to_mean(d, il, gdir, dmu_sh);
+}
+
+// The same from the forward's checkpoint: clamp bits and d colour / d u; the SH
+// coefficients are not read.
+template <int NB>
+__device__ __forceinline__ void colour_bwd_ckpt(const Cam &cam, const float (&m)[3], uint8_t cl, const float (&jac)[9],
+                                                const float (&grgb)[3], float (&Y)[NB], float (&gvo)[3],
+                                                float (&dmu_sh)[3]) {
+    float vx = m[0] - cam.campos[0], vy = m[1] - cam.campos[1], vz = m[2] - cam.campos[2];
+    const float il = rsqrtf(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
+    const float d[3] = {vx * il, vy * il, vz * il};
+    sh_eval<NB>(d[0], d[1], d[2], Y);
+    float gdir[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ch = 0; ch < 3; ch++) {
+        gvo[ch] = ((cl >> ch) & 1u) ? 0.0f : grgb[ch];
+#pragma unroll
+        for (int k = 0; k < 3; k++) gdir[k] = fmaf(gvo[ch], jac[3 * ch + k], gdir[k]);
+    }
+    dir_to_mean(d, il, gdir, dmu_sh);
+}
+
+// dmu_sh: the mean's gradient through the view direction (colour part, FP32).
+__device__ __forceinline__ void splat_bwd_view(const Cam &cam, const KParams &kp, int i, const float (&m)[3],
+                                               const darb_grads2d &g2, const Geom64 &G, const Proj &P,
+                                               const float (&dmu_sh)[3], float (&dmu)[3], float (&dsc)[3],
+                                               float (&dqo)[4]) {
 
     // ---- projection in FP64: t, J (clamped as the forward decided), A = J R_cw,
     //      2D covariance and conic
@@ -626,9 +683,32 @@ __device__ __forceinline__ void store_grads(const darb_grads3d &g3, int n, int i
         for (int ch = 0; ch < 3; ch++) put(g3.sh, (size_t)(b * 3 + ch) * n + i, gsh[b][ch]);
 }
 
-template <int DEG>
-__global__ __launch_bounds__(256) void k_preprocess_bwd(Cam cam, KParams kp, int n, darb_splats in, darb_grads2d g2,
-                                                        darb_grads3d g3, int accumulate) {
+// CKPT: the colour part from the forward's checkpoint (ck: dcolor [9][n] and
+// clamped of the view) instead of the SH coefficients.
+struct Ckpt {
+    const float *dcolor;
+    const uint8_t *clamped;
+};
+
+template <int NB, bool CKPT>
+__device__ __forceinline__ void colour_bwd(const Cam &cam, const float (&m)[3], const darb_splats &in,
+                                           const Ckpt &ck, int n, int i, const float (&grgb)[3], float (&Y)[NB],
+                                           float (&gv)[3], float (&dmu_sh)[3]) {
+    if constexpr (CKPT) {
+        float jac[9];
+#pragma unroll
+        for (int k = 0; k < 9; k++) jac[k] = ck.dcolor[(size_t)k * n + i];
+        colour_bwd_ckpt<NB>(cam, m, ck.clamped[i], jac, grgb, Y, gv, dmu_sh);
+    } else {
+        float csh[NB][3];
+        load_sh<NB>(in.sh, n, i, csh);
+        colour_bwd_sh<NB>(cam, m, csh, grgb, Y, gv, dmu_sh);
+    }
+}
+
+template <int DEG, bool CKPT>
+__global__ __launch_bounds__(256) void k_preprocess_bwd(Cam cam, KParams kp, int n, darb_splats in, Ckpt ck,
+                                                        darb_grads2d g2, darb_grads3d g3, int accumulate) {
     constexpr int NB = (DEG + 1) * (DEG + 1);
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -642,12 +722,12 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(Cam cam, KParams kp, int
     if (vis) {
         float m[3];
         load_mean(in, n, i, m);
-        float csh[NB][3];
-        load_sh<NB>(in.sh, n, i, csh);
+        const float grgb[3] = {g2.rgb[3 * i], g2.rgb[3 * i + 1], g2.rgb[3 * i + 2]};
+        float Y[NB], gv[3], dmu_sh[3];
+        colour_bwd<NB, CKPT>(cam, m, in, ck, n, i, grgb, Y, gv, dmu_sh);
         Geom64 G64;
         splat_geom64(load_qs(in, n, i), G64);
-        float Y[NB], gv[3];
-        splat_bwd_view<NB>(cam, kp, i, m, csh, g2, G64, P, g.dmu, g.dsc, g.dq, Y, gv);
+        splat_bwd_view(cam, kp, i, m, g2, G64, P, dmu_sh, g.dmu, g.dsc, g.dq);
         g.dop = g2.opacity[i];
 #pragma unroll
         for (int b = 0; b < NB; b++)
@@ -660,7 +740,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(Cam cam, KParams kp, int
 // Sum over views, in view order, of the single-view gradients (each view's
 // contribution computed exactly as the single-view kernel computes it, then
 // added), with the parameters read once and the result written once.
-template <int DEG>
+template <int DEG, bool CKPT>
 __global__ __launch_bounds__(256) void k_preprocess_bwd_multi(Cams cams, KParams kp, int n, darb_splats in, G2s g2,
                                                               darb_grads3d g3) {
     constexpr int NB = (DEG + 1) * (DEG + 1);
@@ -680,19 +760,29 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_multi(Cams cams, KParams
     uint32_t vmask = 0;  // views where the splat is visible
     if (geom) {
         float csh[NB][3];
-        load_sh<NB>(in.sh, n, i, csh);
+        if constexpr (!CKPT) load_sh<NB>(in.sh, n, i, csh);
         for (int v = 0; v < cams.nv; v++) {
             const Cam &cam = cams.c[v];
             Proj P;
             Geom G;
             if (!(view_depth(cam, m, P) && splat_geom_of(qs, G) && project_rest(cam, kp, G, P))) continue;
             vmask |= 1u << v;
+            const darb_grads2d &gg = g2.g[v];
+            const float grgb[3] = {gg.rgb[3 * i], gg.rgb[3 * i + 1], gg.rgb[3 * i + 2]};
+            float Y[NB], gv[3], dmu_sh[3];
+            if constexpr (CKPT) {
+                float jac[9];
+#pragma unroll
+                for (int k = 0; k < 9; k++) jac[k] = g2.dcolor[v][(size_t)k * n + i];
+                colour_bwd_ckpt<NB>(cam, m, g2.clamped[v][i], jac, grgb, Y, gv, dmu_sh);
+            } else {
+                colour_bwd_sh<NB>(cam, m, csh, grgb, Y, gv, dmu_sh);
+            }
             Geom64 G64;
             splat_geom64(qs, G64);
             Grad3 g;
-            float Y[NB], gv[3];
-            splat_bwd_view<NB>(cam, kp, i, m, csh, g2.g[v], G64, P, g.dmu, g.dsc, g.dq, Y, gv);
-            g.dop = g2.g[v].opacity[i];
+            splat_bwd_view(cam, kp, i, m, gg, G64, P, dmu_sh, g.dmu, g.dsc, g.dq);
+            g.dop = gg.opacity[i];
 #pragma unroll
             for (int c = 0; c < 3; c++) {
                 tot.dmu[c] += g.dmu[c];
@@ -703,13 +793,25 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_multi(Cams cams, KParams
             tot.dop += g.dop;
         }
         // SH coefficient gradients in a second pass over the visible views (same
-        // terms and order as above; the 48 accumulators are not live beside the
-        // FP64 chain)
+        // terms and order as the single-view kernel; the 48 accumulators are not
+        // live beside the FP64 chain)
         for (int v = 0; v < cams.nv; v++) {
             if (!((vmask >> v) & 1u)) continue;
-            const float grgb[3] = {g2.g[v].rgb[3 * i], g2.g[v].rgb[3 * i + 1], g2.g[v].rgb[3 * i + 2]};
-            float d[3], il, Y[NB], gv[3];
-            sh_view<NB>(cams.c[v], m, csh, grgb, d, il, Y, gv);
+            const darb_grads2d &gg = g2.g[v];
+            const float grgb[3] = {gg.rgb[3 * i], gg.rgb[3 * i + 1], gg.rgb[3 * i + 2]};
+            float Y[NB], gv[3];
+            if constexpr (CKPT) {
+                const Cam &cam = cams.c[v];
+                float vx = m[0] - cam.campos[0], vy = m[1] - cam.campos[1], vz = m[2] - cam.campos[2];
+                const float il = rsqrtf(fmaf(vx, vx, fmaf(vy, vy, vz * vz)));
+                sh_eval<NB>(vx * il, vy * il, vz * il, Y);
+                const uint8_t cl = g2.clamped[v][i];
+#pragma unroll
+                for (int ch = 0; ch < 3; ch++) gv[ch] = ((cl >> ch) & 1u) ? 0.0f : grgb[ch];
+            } else {
+                float d[3], il;
+                sh_view<NB>(cams.c[v], m, csh, grgb, d, il, Y, gv);
+            }
 #pragma unroll
             for (int b = 0; b < NB; b++)
 #pragma unroll
@@ -745,12 +847,26 @@ hipError_t launch_preprocess_multi(const Cams &cams, const KParams &kp, int n, c
     return hipGetLastError();
 }
 
+#define DARB_DEG_SWITCH_B(deg, K, B, grid, s, ...)                                          \
+    switch (deg) {                                                                          \
+    case 0: hipLaunchKernelGGL((K<0, B>), grid, dim3(256), 0, s, __VA_ARGS__); break;       \
+    case 1: hipLaunchKernelGGL((K<1, B>), grid, dim3(256), 0, s, __VA_ARGS__); break;       \
+    case 2: hipLaunchKernelGGL((K<2, B>), grid, dim3(256), 0, s, __VA_ARGS__); break;       \
+    default: hipLaunchKernelGGL((K<3, B>), grid, dim3(256), 0, s, __VA_ARGS__); break;      \
+    }
+
 hipError_t launch_preprocess_bwd(const Cam &cam, const KParams &kp, int n, const darb_splats &in,
-                                 const darb_grads2d &g2d, const darb_grads3d &g3d, bool accumulate, hipStream_t s) {
+                                 const darb_projected *ckpt, const darb_grads2d &g2d, const darb_grads3d &g3d,
+                                 bool accumulate, hipStream_t s) {
     if (n == 0) return hipSuccess;
     dim3 grid((n + 255) / 256);
     const int acc = accumulate ? 1 : 0;
-    DARB_DEG_SWITCH(in.sh_degree, k_preprocess_bwd, grid, s, cam, kp, n, in, g2d, g3d, acc)
+    const Ckpt ck{ckpt ? ckpt->dcolor : nullptr, ckpt ? ckpt->clamped : nullptr};
+    if (ck.dcolor && ck.clamped) {
+        DARB_DEG_SWITCH_B(in.sh_degree, k_preprocess_bwd, true, grid, s, cam, kp, n, in, ck, g2d, g3d, acc)
+    } else {
+        DARB_DEG_SWITCH_B(in.sh_degree, k_preprocess_bwd, false, grid, s, cam, kp, n, in, ck, g2d, g3d, acc)
+    }
     return hipGetLastError();
 }
 
@@ -758,7 +874,13 @@ hipError_t launch_preprocess_bwd_multi(const Cams &cams, const KParams &kp, int 
                                        const G2s &g2, const darb_grads3d &g3d, hipStream_t s) {
     if (n == 0) return hipSuccess;
     dim3 grid((n + 255) / 256);
-    DARB_DEG_SWITCH(in.sh_degree, k_preprocess_bwd_multi, grid, s, cams, kp, n, in, g2, g3d)
+    bool ckpt = true;
+    for (int v = 0; v < cams.nv; v++) ckpt = ckpt && g2.dcolor[v] && g2.clamped[v];
+    if (ckpt) {
+        DARB_DEG_SWITCH_B(in.sh_degree, k_preprocess_bwd_multi, true, grid, s, cams, kp, n, in, g2, g3d)
+    } else {
+        DARB_DEG_SWITCH_B(in.sh_degree, k_preprocess_bwd_multi, false, grid, s, cams, kp, n, in, g2, g3d)
+    }
     return hipGetLastError();
 }
 

@@ -59,7 +59,7 @@ class darb_splats(ctypes.Structure):
 
 class darb_projected(ctypes.Structure):
     _fields_ = [("xy", c_void_p), ("depth", c_void_p), ("radius", c_void_p), ("conic_o", c_void_p),
-                ("rgb", c_void_p), ("clamped", c_void_p)]
+                ("rgb", c_void_p), ("clamped", c_void_p), ("dcolor", c_void_p)]
 
 
 class darb_grads2d(ctypes.Structure):
@@ -126,8 +126,8 @@ def lib():
         L.darb_raster_bwd_workspace.restype = c_size_t
         L.darb_raster_bwd_workspace.argtypes = [c_int64, c_int32, c_int32, c_int64]
         L.darb_preprocess_bwd.restype = c_int32
-        L.darb_preprocess_bwd.argtypes = [P(darb_camera), P(darb_kernel), c_int64, P(darb_splats), P(darb_grads2d),
-                                          P(darb_grads3d), c_int32, c_void_p]
+        L.darb_preprocess_bwd.argtypes = [P(darb_camera), P(darb_kernel), c_int64, P(darb_splats), P(darb_projected),
+                                          P(darb_grads2d), P(darb_grads3d), c_int32, c_void_p]
         L.darb_image_loss.restype = c_int32
         L.darb_image_loss.argtypes = [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p,
                                       c_size_t, c_void_p]
@@ -230,7 +230,7 @@ def splats_struct(sp: dict) -> darb_splats:
 
 def projected_struct(p: dict) -> darb_projected:
     return darb_projected(_ptr(p["xy"]), _ptr(p["depth"]), _ptr(p["radius"]), _ptr(p.get("conic_o")),
-                          _ptr(p.get("rgb")), _ptr(p.get("clamped")))
+                          _ptr(p.get("rgb")), _ptr(p.get("clamped")), _ptr(p.get("dcolor")))
 
 
 def grads2d_struct(g: dict) -> darb_grads2d:
@@ -325,11 +325,15 @@ def darb_raster_bwd_workspace(n: int, width: int, height: int, k_capacity: int) 
 
 
 def darb_preprocess_bwd(cam: dict, kernel, n: int, splats: dict, g2d: dict, g3d: dict, accumulate: bool = False,
-                        stream=None):
+                        stream=None, proj: dict | None = None):
+    """``proj``: the records darb_preprocess wrote for this camera; with its
+    ``dcolor`` (and ``clamped``) the colour part uses that checkpoint."""
     c, k, s = camera_struct(cam), kernel_struct(kernel), splats_struct(splats)
     g2, g3 = grads2d_struct(g2d), grads3d_struct(g3d)
-    _check(lib().darb_preprocess_bwd(ctypes.byref(c), ctypes.byref(k), n, ctypes.byref(s), ctypes.byref(g2),
-                                     ctypes.byref(g3), 1 if accumulate else 0, _stream(stream)), "darb_preprocess_bwd")
+    p = projected_struct(proj) if proj is not None else None
+    _check(lib().darb_preprocess_bwd(ctypes.byref(c), ctypes.byref(k), n, ctypes.byref(s),
+                                     ctypes.byref(p) if p is not None else None, ctypes.byref(g2), ctypes.byref(g3),
+                                     1 if accumulate else 0, _stream(stream)), "darb_preprocess_bwd")
 
 
 def darb_image_loss(image, target, width: int, height: int, loss_kind: int, dL_dimage=None, loss_dev=None, ws=None,

@@ -51,11 +51,14 @@ def splats_to_device(sp: dict, device="cuda") -> dict:
     return out
 
 
-def alloc_projected(n: int, device="cuda") -> dict:
+def alloc_projected(n: int, device="cuda", dcolor: bool = True) -> dict:
+    """Projected records; ``dcolor`` keeps the colour checkpoint the preprocess
+    backward reads instead of the SH coefficients (forward-only users skip it)."""
     f = dict(dtype=torch.float32, device=device)
     return dict(xy=torch.empty((n, 2), **f), depth=torch.empty(n, **f),
                 radius=torch.empty(n, dtype=torch.int32, device=device), conic_o=torch.empty((n, 4), **f),
-                rgb=torch.empty((n, 3), **f), clamped=torch.empty(n, dtype=torch.uint8, device=device))
+                rgb=torch.empty((n, 3), **f), clamped=torch.empty(n, dtype=torch.uint8, device=device),
+                dcolor=torch.empty((9, n), **f) if dcolor else None)
 
 
 @dataclass
@@ -84,14 +87,14 @@ class Frame:
 
 
 def alloc_frame(n: int, width: int, height: int, k_capacity: int, device="cuda", keys: bool = False,
-                n_contrib: bool = False, proj: dict | None = None) -> Frame:
+                n_contrib: bool = False, proj: dict | None = None, dcolor: bool = True) -> Frame:
     cap = max(int(k_capacity), 1)
     ws_bytes = native.darb_bin_sort_workspace(n, width, height, cap)
     if ws_bytes == 0:
         raise native.DarbError(native.DARB_ERR_UNSUPPORTED, f"unsupported size n={n} {width}x{height} cap={cap}")
     T = n_tiles(width, height)
     return Frame(
-        n=n, width=width, height=height, proj=proj if proj is not None else alloc_projected(n, device),
+        n=n, width=width, height=height, proj=proj if proj is not None else alloc_projected(n, device, dcolor),
         ws=torch.empty(ws_bytes, dtype=torch.uint8, device=device),
         vals=torch.empty(cap, dtype=torch.int32, device=device),
         ranges=torch.empty((T, 2), dtype=torch.int32, device=device),
@@ -294,4 +297,5 @@ def sequential_step(splats: dict, mf: MultiFrame, targets: list, kernel: KernelS
         native.darb_raster_bwd(fr.proj, n, fr.vals, fr.ranges, fr.overflow, fr.width, fr.height, kernel, opts,
                                mf.dL[v], fr.final_T, fr.last, mf.g2d[v], deterministic=deterministic,
                                k_capacity=fr.capacity, ws=ws, stream=stream)
-        native.darb_preprocess_bwd(cam, kernel, n, splats, mf.g2d[v], g3d, accumulate=v > 0, stream=stream)
+        native.darb_preprocess_bwd(cam, kernel, n, splats, mf.g2d[v], g3d, accumulate=v > 0, stream=stream,
+                                   proj=fr.proj)

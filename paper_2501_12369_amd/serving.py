@@ -264,7 +264,7 @@ class RenderSlot:
         torch, pipeline = self.torch, self.pipeline
         self.graph = None
         self.frame = None
-        self.frame = pipeline.alloc_frame(self.n, self.W, self.H, capacity, "cuda")
+        self.frame = pipeline.alloc_frame(self.n, self.W, self.H, capacity, "cuda", dcolor=False)
         self.nbytes = self.server.slot_bytes(self.n, self.W, self.H, capacity)
         self._capture()
 

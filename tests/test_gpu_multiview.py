@@ -159,6 +159,18 @@ def test_multiview_preprocess_equals_single_view():
     torch.cuda.synchronize()
     for k in G3:
         assert torch.equal(gm[k], gs[k]), k
+    # the same with the forward's colour checkpoint of each view, and close to the path without it
+    _, gmc = pipeline.alloc_grads(n, 3)
+    _, gsc = pipeline.alloc_grads(n, 3)
+    native.darb_preprocess_bwd_multi([dict(cam=c, grads2d=g, proj=p) for c, g, p in zip(cams, g2s, projs)], kern, n,
+                                     spd, gmc)
+    for v, (cam, g, p) in enumerate(zip(cams, g2s, projs)):
+        native.darb_preprocess_bwd(cam, kern, n, spd, g, gsc, accumulate=v > 0, proj=p)
+    torch.cuda.synchronize()
+    for k in G3:
+        assert torch.equal(gmc[k], gsc[k]), k
+        ok, l2, ratio = grad_compare(to_np(gmc[k]), to_np(gm[k]), rel_l2=1e-5, rel_el=1e-4, abs_frac=1e-6)
+        assert l2 <= 1e-5, (k, l2)
 
 
 @pytest.mark.parametrize("loss", [native.LOSS_L1, native.LOSS_L2])

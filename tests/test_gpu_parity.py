@@ -246,8 +246,10 @@ def test_preprocess_parity(kname, which):
     assert np.array_equal(rad[both][~near_int], o["radius"][both][~near_int])
 
 
-@pytest.mark.parametrize("kname", ["gauss", "half_cos", "parabola"])
-def test_preprocess_bwd_parity(kname):
+@pytest.mark.parametrize("kname,ckpt", [("gauss", False), ("half_cos", False), ("parabola", False),
+                                        ("half_cos", True), ("gauss", True)])
+def test_preprocess_bwd_parity(kname, ckpt):
+    # ckpt: the colour part from the forward's checkpoint (dcolor, clamped) instead of the SH coefficients
     sc = scenes.object_scale(seed=3, n=5000, width=800, height=800)
     sp, cam = sc["splats"], sc["camera"]
     n = sp["means"].shape[1]
@@ -258,7 +260,11 @@ def test_preprocess_bwd_parity(kname):
               rgb=rng.standard_normal((n, 3)).astype(np.float32))
     g2d_dev = {k: dev(v) for k, v in g2.items()}
     _, g3d = pipeline.alloc_grads(n, 3)
-    native.darb_preprocess_bwd(cam, pipeline.KERNELS[kname], n, _splats_dev(sp), g2d_dev, g3d)
+    proj = None
+    if ckpt:
+        proj = pipeline.alloc_projected(n)
+        native.darb_preprocess(cam, pipeline.KERNELS[kname], n, _splats_dev(sp), proj)
+    native.darb_preprocess_bwd(cam, pipeline.KERNELS[kname], n, _splats_dev(sp), g2d_dev, g3d, proj=proj)
     torch.cuda.synchronize()
     go = oracle.preprocess_bwd(oracle.camera_from_scene(cam), oracle_kernel_fp32(kname), sp["means"], sp["scales"],
                                sp["quats"], sp["sh"], 3, {k: v.astype(np.float64) for k, v in g2.items()})
