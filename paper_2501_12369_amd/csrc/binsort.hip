@@ -52,7 +52,7 @@ constexpr int kL2Grid = 8192;                             // persistent level-2 
 struct Counters {
     uint32_t n_visible;  // N_v
     uint32_t c1;         // level-1 chunks
-    uint32_t h1_count;   // super-tiles * c1
+    uint32_t pad0;
     uint32_t total1;     // level-1 list length
     uint32_t total2;     // level-2 chunks
     uint32_t h2_count;   // flattened level-2 count entries
@@ -411,7 +411,7 @@ __global__ __launch_bounds__(256) void k_bin_keys(const float *xy, const int32_t
 // single workgroup: exclusive scan of the block visible counts (compaction
 // offsets), N_v, K = sum of the areas, capacity decision, level-1 sizes
 __global__ __launch_bounds__(1024) void k_bin_sizes(uint32_t *block_vis, const uint32_t *block_area, int nkb,
-                                                    int nsuper, Counters *cnt, int64_t k_capacity, int64_t *k_dev,
+                                                    Counters *cnt, int64_t k_capacity, int64_t *k_dev,
                                                     int32_t *overflow_dev) {
     __shared__ uint32_t lw[16];
     __shared__ unsigned long long la[16];
@@ -449,7 +449,6 @@ __global__ __launch_bounds__(1024) void k_bin_sizes(uint32_t *block_vis, const u
         *cnt = Counters{};  // every counter of this call starts here (none is read before this kernel)
         cnt->n_visible = nv;
         cnt->c1 = (nv + kL1Threads - 1) / kL1Threads;
-        cnt->h1_count = cnt->c1 * (uint32_t)nsuper;
         cnt->K = K;
         k_dev[0] = (int64_t)K;
         k_dev[1] = (int64_t)nv;
@@ -1054,7 +1053,7 @@ hipError_t launch_bin_sort(const darb_projected &p, int n, int width, int height
 
     const int nkb = (n + kKeyTile - 1) / kKeyTile;
     if (n > 0) hipLaunchKernelGGL(k_bin_keys, dim3(nkb), dim3(256), 0, s, p.xy, p.radius, n, gx, gy, blockvis, blockarea);
-    hipLaunchKernelGGL(k_bin_sizes, dim3(1), dim3(1024), 0, s, blockvis, blockarea, nkb, nsuper, cnt, k_capacity, k_dev,
+    hipLaunchKernelGGL(k_bin_sizes, dim3(1), dim3(1024), 0, s, blockvis, blockarea, nkb, cnt, k_capacity, k_dev,
                        overflow_dev);
     uint32_t *sid = U(L.sid);
     uint2 *sbox = reinterpret_cast<uint2 *>(base + L.sbox);

@@ -23,7 +23,8 @@
 // largest checkpointed position down, recomputing alpha with the same device
 // function, T <- T / (1 - alpha), and accumulating the per-splat partial
 // gradients of its four pixels in registers; per splat the wave sums the nine
-// partials with DPP row reductions and lane s of the batch keeps the sums of
+// partials (lane-half swaps pack them four to a register, then DPP row
+// reductions finish three registers) and lane s of the batch keeps the sums of
 // the batch's s-th instance.  At the end of a batch the lanes either issue
 // their float atomics together (nine atomic instructions per 64 instances), or,
 // in the deterministic mode, store them as one partial per (tile, splat); a
@@ -262,6 +263,45 @@ __device__ __forceinline__ void writelane9(float (&m)[9], const float (&u)[9], i
         : "m0");
 }
 
+// Sum of a and b over lanes l and l ^ 32: lanes 0-31 receive a's, lanes 32-63
+// b's (v_permlane32_swap exchanges a's upper half with b's lower half).
+__device__ __forceinline__ float fold32(float a, float b) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Sum over lanes l and l ^ 16: rows 0 and 2 (lanes 0-15, 32-47) receive a's,
+// rows 1 and 3 b's (v_permlane16_swap exchanges a's odd rows with b's even rows).
+__device__ __forceinline__ float fold16(float a, float b) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Sum within each row of 16 lanes; the row total lands in the row's lane 15.
+__device__ __forceinline__ float row_sum_to_lane15(float v) {
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, false));  // row_shr:1
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xf, 0xf, false));  // row_shr:2
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x114, 0xf, 0xf, false));  // row_shr:4
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x118, 0xf, 0xf, false));  // row_shr:8
+    return v;
+}
+
+// Wave sums of nine per-lane values, written into lane s of m[k].  Two
+// half-swap levels pack the nine values four to a register (one value per
+// row of 16 lanes, already summed over the four lanes l, l^16, l^32, l^48), so
+// three row reductions finish all nine: 8 swaps and 12 DPP adds instead of
+// nine separate 64-lane reductions.
+__device__ __forceinline__ void wave_sum9_to_lane(float (&m)[9], const float (&g)[9], int s) {
+    // rows of w0: g0, g2, g1, g3; of w1: g4, g6, g5, g7; row 0 of w2: g8
+    const float w0 = row_sum_to_lane15(fold16(fold32(g[0], g[1]), fold32(g[2], g[3])));
+    const float w1 = row_sum_to_lane15(fold16(fold32(g[4], g[5]), fold32(g[6], g[7])));
+    const float w2 = row_sum_to_lane15(fold16(fold32(g[8], 0.0f), 0.0f));
+    const float u[9] = {readlane_f(w0, 15), readlane_f(w0, 47), readlane_f(w0, 31), readlane_f(w0, 63),
+                        readlane_f(w1, 15), readlane_f(w1, 47), readlane_f(w1, 31), readlane_f(w1, 63),
+                        readlane_f(w2, 15)};
+    writelane9(m, u, s);
+}
+
 // Backward walk of one tile.  T: final transmittance per pixel (running, so
 // modified); lp: last blended position + 1 (0 = none); G: dL/dI per pixel.
 template <int KIND, bool DET, int S>
@@ -342,12 +382,8 @@ __device__ __forceinline__ void tile_bwd(const RView &V, int tile, uint32_t item
                 T[k] = ok ? Tb : T[k];
             }
             if (__ballot(any) != 0) {
-                const float u[9] = {readlane_f(wave_sum_to_lane63(gxy0), 63), readlane_f(wave_sum_to_lane63(gxy1), 63),
-                                    readlane_f(wave_sum_to_lane63(gca), 63),  readlane_f(wave_sum_to_lane63(gcb), 63),
-                                    readlane_f(wave_sum_to_lane63(gcc), 63),  readlane_f(wave_sum_to_lane63(gop), 63),
-                                    readlane_f(wave_sum_to_lane63(gr), 63),   readlane_f(wave_sum_to_lane63(gg), 63),
-                                    readlane_f(wave_sum_to_lane63(gbl), 63)};
-                writelane9(m, u, s);
+                const float g[9] = {gxy0, gxy1, gca, gcb, gcc, gop, gr, gg, gbl};
+                wave_sum9_to_lane(m, g, s);
                 touched |= 1ull << s;
             }
         }
