@@ -275,15 +275,19 @@ __device__ __forceinline__ bool project_rest(const Cam &cam, const KParams &kp, 
     return true;
 }
 
-// Projection of splat i in one view (depth test first: a culled splat reads
-// only its mean); false when culled.
-__device__ __forceinline__ bool project(const Cam &cam, const KParams &kp, int n, int i, const darb_splats &in,
-                                        Geom &G, Proj &P) {
-    float m[3];
-    load_mean(in, n, i, m);
-    if (!view_depth(cam, m, P)) return false;
-    if (!splat_geom(n, i, in, G)) return false;
-    return project_rest(cam, kp, G, P);
+// Marks a loaded value as used here.  Loads whose values are used only under a
+// later branch would otherwise be moved into that branch, each group behind
+// the previous branch's memory round trip; pinned right after they are issued,
+// a group of loads costs one round trip.
+__device__ __forceinline__ void pin(float v) { asm volatile("" ::"v"(v)); }
+
+__device__ __forceinline__ void pin_geometry(const float (&m)[3], const QS &qs) {
+#pragma unroll
+    for (int k = 0; k < 3; k++) pin(m[k]);
+#pragma unroll
+    for (int k = 0; k < 4; k++) pin(qs.q[k]);
+#pragma unroll
+    for (int k = 0; k < 3; k++) pin(qs.s[k]);
 }
 
 // SH coefficients of splat i, all loads issued before any use: c[b][ch]
@@ -379,9 +383,16 @@ __global__ __launch_bounds__(256) void k_preprocess(Cam cam_arg, const darb_came
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const Cam cam = cam_dev ? cam_from_device(cam_dev, cam_arg.width, cam_arg.height) : cam_arg;
+    // the geometry's loads are issued together (one memory round trip before the
+    // projection), the SH coefficients only for the splats that survive it
+    float m[3];
+    load_mean(in, n, i, m);
+    const QS qs = load_qs(in, n, i);
+    const float op_in = in.opacity[i];
+    pin_geometry(m, qs);
     Geom G;
     Proj P;
-    const bool vis = project(cam, kp, n, i, in, G, P);
+    const bool vis = view_depth(cam, m, P) && splat_geom_of(qs, G) && project_rest(cam, kp, G, P);
     float col[3] = {0.0f, 0.0f, 0.0f};
     float jac[9] = {};
     float op = 0.0f;
@@ -389,9 +400,7 @@ __global__ __launch_bounds__(256) void k_preprocess(Cam cam_arg, const darb_came
     if (vis) {
         float c[NB][3];
         load_sh<NB>(in.sh, n, i, c);
-        op = in.opacity[i];
-        float m[3];
-        load_mean(in, n, i, m);
+        op = op_in;
         if (out.dcolor)
             sh_colour<NB, true>(cam, m, c, col, cl, jac);
         else
@@ -554,9 +563,28 @@ __device__ __forceinline__ void colour_bwd_ckpt(const Cam &cam, const float (&m)
     dir_to_mean(d, il, gdir, dmu_sh);
 }
 
+// Incoming gradients of one splat with respect to its projected quantities.
+struct G2v {
+    float xy[2], conic[3], op, rgb[3];
+};
+
+__device__ __forceinline__ G2v load_g2(const darb_grads2d &g2, int i) {
+    G2v v;
+    v.xy[0] = g2.xy[2 * i];
+    v.xy[1] = g2.xy[2 * i + 1];
+    v.conic[0] = g2.conic[3 * i];
+    v.conic[1] = g2.conic[3 * i + 1];
+    v.conic[2] = g2.conic[3 * i + 2];
+    v.op = g2.opacity[i];
+    v.rgb[0] = g2.rgb[3 * i];
+    v.rgb[1] = g2.rgb[3 * i + 1];
+    v.rgb[2] = g2.rgb[3 * i + 2];
+    return v;
+}
+
 // dmu_sh: the mean's gradient through the view direction (colour part, FP32).
-__device__ __forceinline__ void splat_bwd_view(const Cam &cam, const KParams &kp, int i, const float (&m)[3],
-                                               const darb_grads2d &g2, const Geom64 &G, const Proj &P,
+__device__ __forceinline__ void splat_bwd_view(const Cam &cam, const KParams &kp, const float (&m)[3],
+                                               const G2v &g2, const Geom64 &G, const Proj &P,
                                                const float (&dmu_sh)[3], float (&dmu)[3], float (&dsc)[3],
                                                float (&dqo)[4]) {
 
@@ -594,7 +622,7 @@ __device__ __forceinline__ void splat_bwd_view(const Cam &cam, const KParams &kp
 
     // ---- conic -> 2D covariance: dL/dcov = -Q Ghat Q, Ghat = [[ga, gb/2], [gb/2, gc]];
     //      psi: M -> psi M + eps I
-    const double ga = g2.conic[3 * i], gb = 0.5 * (double)g2.conic[3 * i + 1], gc = g2.conic[3 * i + 2];
+    const double ga = g2.conic[0], gb = 0.5 * (double)g2.conic[1], gc = g2.conic[2];
     const double q00 = a * ga + b * gb, q01 = a * gb + b * gc;
     const double q10 = b * ga + c * gb, q11 = b * gb + c * gc;
     const double m00 = -psi * (q00 * a + q01 * b);
@@ -619,7 +647,7 @@ __device__ __forceinline__ void splat_bwd_view(const Cam &cam, const KParams &kp
     dtz += dJ02 * (-fx * (dxt_dtz * tz - xt) * itz2);
     dtz += dJ12 * (-fy * (dyt_dtz * tz - yt) * itz2);
     // mean2D
-    const double gu = g2.xy[2 * i], gvv = g2.xy[2 * i + 1];
+    const double gu = g2.xy[0], gvv = g2.xy[1];
     dtx += gu * fx * itz;
     dty += gvv * fy * itz;
     dtz -= (gu * fx * t0 + gvv * fy * t1) * itz2;
@@ -690,45 +718,54 @@ struct Ckpt {
     const uint8_t *clamped;
 };
 
-template <int NB, bool CKPT>
-__device__ __forceinline__ void colour_bwd(const Cam &cam, const float (&m)[3], const darb_splats &in,
-                                           const Ckpt &ck, int n, int i, const float (&grgb)[3], float (&Y)[NB],
-                                           float (&gv)[3], float (&dmu_sh)[3]) {
-    if constexpr (CKPT) {
-        float jac[9];
-#pragma unroll
-        for (int k = 0; k < 9; k++) jac[k] = ck.dcolor[(size_t)k * n + i];
-        colour_bwd_ckpt<NB>(cam, m, ck.clamped[i], jac, grgb, Y, gv, dmu_sh);
-    } else {
-        float csh[NB][3];
-        load_sh<NB>(in.sh, n, i, csh);
-        colour_bwd_sh<NB>(cam, m, csh, grgb, Y, gv, dmu_sh);
-    }
-}
-
 template <int DEG, bool CKPT>
 __global__ __launch_bounds__(256) void k_preprocess_bwd(Cam cam, KParams kp, int n, darb_splats in, Ckpt ck,
                                                         darb_grads2d g2, darb_grads3d g3, int accumulate) {
     constexpr int NB = (DEG + 1) * (DEG + 1);
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    // parameters, incoming gradients and the colour checkpoint are loaded
+    // together, one memory round trip before the projection (a culled splat's
+    // gradients are read and not used)
+    float m[3];
+    load_mean(in, n, i, m);
+    const QS qs = load_qs(in, n, i);
+    const G2v gin = load_g2(g2, i);
+    float jac[9];
+    uint8_t cl = 0;
+    if constexpr (CKPT) {
+#pragma unroll
+        for (int k = 0; k < 9; k++) jac[k] = ck.dcolor[(size_t)k * n + i];
+        cl = ck.clamped[i];
+    }
+    pin_geometry(m, qs);
+    pin(gin.xy[0]); pin(gin.xy[1]); pin(gin.conic[0]); pin(gin.conic[1]); pin(gin.conic[2]); pin(gin.op);
+    pin(gin.rgb[0]); pin(gin.rgb[1]); pin(gin.rgb[2]);
+    if constexpr (CKPT) {
+#pragma unroll
+        for (int k = 0; k < 9; k++) pin(jac[k]);
+        pin(__uint_as_float((uint32_t)cl));
+    }
     Geom G;
     Proj P;
-    const bool vis = project(cam, kp, n, i, in, G, P);
+    const bool vis = view_depth(cam, m, P) && splat_geom_of(qs, G) && project_rest(cam, kp, G, P);
     Grad3 g = {};
     float gsh[NB][3];
 #pragma unroll
     for (int b = 0; b < NB; b++) gsh[b][0] = gsh[b][1] = gsh[b][2] = 0.0f;
     if (vis) {
-        float m[3];
-        load_mean(in, n, i, m);
-        const float grgb[3] = {g2.rgb[3 * i], g2.rgb[3 * i + 1], g2.rgb[3 * i + 2]};
         float Y[NB], gv[3], dmu_sh[3];
-        colour_bwd<NB, CKPT>(cam, m, in, ck, n, i, grgb, Y, gv, dmu_sh);
+        if constexpr (CKPT) {
+            colour_bwd_ckpt<NB>(cam, m, cl, jac, gin.rgb, Y, gv, dmu_sh);
+        } else {
+            float csh[NB][3];
+            load_sh<NB>(in.sh, n, i, csh);
+            colour_bwd_sh<NB>(cam, m, csh, gin.rgb, Y, gv, dmu_sh);
+        }
         Geom64 G64;
-        splat_geom64(load_qs(in, n, i), G64);
-        splat_bwd_view(cam, kp, i, m, g2, G64, P, dmu_sh, g.dmu, g.dsc, g.dq);
-        g.dop = g2.opacity[i];
+        splat_geom64(qs, G64);
+        splat_bwd_view(cam, kp, m, gin, G64, P, dmu_sh, g.dmu, g.dsc, g.dq);
+        g.dop = gin.op;
 #pragma unroll
         for (int b = 0; b < NB; b++)
 #pragma unroll
@@ -767,22 +804,21 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_multi(Cams cams, KParams
             Geom G;
             if (!(view_depth(cam, m, P) && splat_geom_of(qs, G) && project_rest(cam, kp, G, P))) continue;
             vmask |= 1u << v;
-            const darb_grads2d &gg = g2.g[v];
-            const float grgb[3] = {gg.rgb[3 * i], gg.rgb[3 * i + 1], gg.rgb[3 * i + 2]};
+            const G2v gin = load_g2(g2.g[v], i);
             float Y[NB], gv[3], dmu_sh[3];
             if constexpr (CKPT) {
                 float jac[9];
 #pragma unroll
                 for (int k = 0; k < 9; k++) jac[k] = g2.dcolor[v][(size_t)k * n + i];
-                colour_bwd_ckpt<NB>(cam, m, g2.clamped[v][i], jac, grgb, Y, gv, dmu_sh);
+                colour_bwd_ckpt<NB>(cam, m, g2.clamped[v][i], jac, gin.rgb, Y, gv, dmu_sh);
             } else {
-                colour_bwd_sh<NB>(cam, m, csh, grgb, Y, gv, dmu_sh);
+                colour_bwd_sh<NB>(cam, m, csh, gin.rgb, Y, gv, dmu_sh);
             }
             Geom64 G64;
             splat_geom64(qs, G64);
             Grad3 g;
-            splat_bwd_view(cam, kp, i, m, gg, G64, P, dmu_sh, g.dmu, g.dsc, g.dq);
-            g.dop = gg.opacity[i];
+            splat_bwd_view(cam, kp, m, gin, G64, P, dmu_sh, g.dmu, g.dsc, g.dq);
+            g.dop = gin.op;
 #pragma unroll
             for (int c = 0; c < 3; c++) {
                 tot.dmu[c] += g.dmu[c];
