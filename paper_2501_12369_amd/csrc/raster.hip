@@ -43,6 +43,11 @@ namespace darb {
 namespace {
 
 constexpr int kPix = 4;    // pixels per lane with one wavefront per tile
+// Row coordinate given to the forward's pixels that are outside the image or
+// have saturated: there E >= (l11 dy)^2 > 1e22 exceeds any e_max (l11 =
+// 1/sqrt(c11) > 5e-20 for every finite conic), or overflows to +inf, so no
+// splat passes their test and the walk needs no separate per-pixel state.
+constexpr float kFar = 3.0e30f;
 constexpr int kSplit = 2;  // wavefronts per tile in the forward kernel
 
 // Pixels of this lane: column ix, rows iy0 + 4k for k < kPix / S.
@@ -140,7 +145,8 @@ struct PixF {
     uint32_t lst[NP], cnt[NP];
 };
 
-template <int KIND, int S>
+// CNT: count the blended splats of each pixel (only when they are stored).
+template <int KIND, int S, bool CNT>
 __device__ __forceinline__ void tile_fwd(const RView &V, int tile, int n, const KParams &kp, const ROpts &o,
                                          PixF<kPix / S> &Fout) {
     constexpr int NP = kPix / S;
@@ -150,12 +156,10 @@ __device__ __forceinline__ void tile_fwd(const RView &V, int tile, int n, const 
     const int ix = P.ix, iy0 = P.iy0;
     const float px = (float)ix;
     float py[NP];
-    bool done[NP];
 #pragma unroll
     for (int k = 0; k < NP; k++) {
         int iy = iy0 + 4 * k;
-        py[k] = (float)iy;
-        done[k] = !(ix < V.W && iy < V.H);
+        py[k] = (ix < V.W && iy < V.H) ? (float)iy : kFar;
         F.T[k] = 1.0f;
         F.C0[k] = F.C1[k] = F.C2[k] = 0.0f;
         F.lst[k] = kNone;
@@ -165,7 +169,7 @@ __device__ __forceinline__ void tile_fwd(const RView &V, int tile, int n, const 
     for (uint32_t base = start; base < end; base += 64) {
         bool alldone = true;
 #pragma unroll
-        for (int k = 0; k < NP; k++) alldone &= done[k];
+        for (int k = 0; k < NP; k++) alldone &= py[k] == kFar;
         if (__ballot(!alldone) == 0) break;
         uint32_t j = base + lane;
         Rec R = load_rec(V.p, V.vals, j, j < end, n, kp.e_max, (float)(ix - (lane & 15)), P.ylo,
@@ -181,18 +185,18 @@ __device__ __forceinline__ void tile_fwd(const RView &V, int tile, int n, const 
 #pragma unroll
             for (int k = 0; k < NP; k++) {
                 Pair q = eval_pair<KIND>(sx, sy, sa, sb, sc, so, px, py[k], kp, o.alpha_min, o.alpha_max);
-                bool ok = q.ok & !done[k];
+                bool ok = q.ok;
                 float Tn = F.T[k] * (1.0f - q.alpha);
                 bool stop = ok & (Tn < o.t_min);
                 ok = ok & !stop;
-                done[k] = done[k] | stop;
+                py[k] = stop ? kFar : py[k];
                 float aT = ok ? q.alpha * F.T[k] : 0.0f;
                 F.C0[k] = fmaf(aT, sr, F.C0[k]);
                 F.C1[k] = fmaf(aT, sg, F.C1[k]);
                 F.C2[k] = fmaf(aT, sbl, F.C2[k]);
                 F.T[k] = ok ? Tn : F.T[k];
                 F.lst[k] = ok ? pos : F.lst[k];
-                F.cnt[k] += ok ? 1u : 0u;
+                if constexpr (CNT) F.cnt[k] += ok ? 1u : 0u;
             }
         }
     }
@@ -446,13 +450,13 @@ __device__ __forceinline__ void load_checkpoint(const RView &V, int tile, float 
     }
 }
 
-template <int KIND, class VS>
+template <int KIND, class VS, bool CNT>
 __global__ __launch_bounds__(64 * kSplit) void k_raster_fwd(VS A, int n, KParams kp, ROpts o) {
     int tile;
     const RView &V = A.get(blockIdx.x, tile);
     if (V.overflow && *V.overflow) return;
     PixF<kPix / kSplit> F;
-    tile_fwd<KIND, kSplit>(V, tile, n, kp, o, F);
+    tile_fwd<KIND, kSplit, CNT>(V, tile, n, kp, o, F);
     store_fwd<kSplit>(V, tile, F, o);
 }
 
@@ -476,7 +480,7 @@ __global__ __launch_bounds__(64) void k_raster_fwdbwd(VS A, int n, KParams kp, R
     const RView &V = A.get(blockIdx.x, tile);
     if (V.overflow && *V.overflow) return;
     PixF<NP> F;
-    tile_fwd<KIND, S>(V, tile, n, kp, o, F);
+    tile_fwd<KIND, S, true>(V, tile, n, kp, o, F);
     store_fwd<S>(V, tile, F, o);
     const LanePix<S> P(tile, V.gx);
     const int ix = P.ix, iy0 = P.iy0;
@@ -638,12 +642,23 @@ namespace {
 
 template <int KIND>
 void fwd_launch(const RViews &V, uint32_t items, int n, const KParams &kp, const ROpts &o, hipStream_t s) {
-    if (V.nv == 1)
-        hipLaunchKernelGGL((k_raster_fwd<KIND, OneView>), dim3(items), dim3(64 * kSplit), 0, s, OneView{V.v[0]}, n, kp,
-                           o);
-    else
-        hipLaunchKernelGGL((k_raster_fwd<KIND, ManyViews>), dim3(items), dim3(64 * kSplit), 0, s, ManyViews{V}, n, kp,
-                           o);
+    bool cnt = false;
+    for (int v = 0; v < V.nv; v++) cnt |= V.v[v].n_contrib != nullptr;
+    if (V.nv == 1) {
+        if (cnt)
+            hipLaunchKernelGGL((k_raster_fwd<KIND, OneView, true>), dim3(items), dim3(64 * kSplit), 0, s,
+                               OneView{V.v[0]}, n, kp, o);
+        else
+            hipLaunchKernelGGL((k_raster_fwd<KIND, OneView, false>), dim3(items), dim3(64 * kSplit), 0, s,
+                               OneView{V.v[0]}, n, kp, o);
+    } else {
+        if (cnt)
+            hipLaunchKernelGGL((k_raster_fwd<KIND, ManyViews, true>), dim3(items), dim3(64 * kSplit), 0, s,
+                               ManyViews{V}, n, kp, o);
+        else
+            hipLaunchKernelGGL((k_raster_fwd<KIND, ManyViews, false>), dim3(items), dim3(64 * kSplit), 0, s,
+                               ManyViews{V}, n, kp, o);
+    }
 }
 
 template <int KIND>
