@@ -209,9 +209,9 @@ def variants_bench(spd, cam, steps: int, warmup: int):
         native.darb_bin_sort(frame.proj, n, W, H, frame.capacity, frame.ws, None, frame.vals, frame.ranges,
                              frame.k_dev, frame.overflow)
         native.darb_raster_fwd(frame.proj, n, frame.vals, frame.ranges, frame.overflow, W, H, kern,
-                               pipeline.DEFAULT_OPTS, frame.image, frame.final_T, frame.last)
+                               pipeline.DEFAULT_OPTS, frame.image, frame.final_T, frame.last, zero_g2d=grads[0])
         native.darb_raster_bwd(frame.proj, n, frame.vals, frame.ranges, frame.overflow, W, H, kern,
-                               pipeline.DEFAULT_OPTS, G, frame.final_T, frame.last, grads[0])
+                               pipeline.DEFAULT_OPTS, G, frame.final_T, frame.last, grads[0], g2d_zeroed=True)
         native.darb_preprocess_bwd(cam, kern, n, spd, grads[0], grads[1], proj=frame.proj)
 
     def timed(fn):
@@ -368,11 +368,11 @@ def main():
         if ev is not None:
             ev[2].record()
         native.darb_raster_fwd(frame.proj, n, frame.vals, frame.ranges, frame.overflow, W, H, kern,
-                               pipeline.DEFAULT_OPTS, frame.image, frame.final_T, frame.last)
+                               pipeline.DEFAULT_OPTS, frame.image, frame.final_T, frame.last, zero_g2d=grads[0])
         if ev is not None:
             ev[3].record()
         native.darb_raster_bwd(frame.proj, n, frame.vals, frame.ranges, frame.overflow, W, H, kern,
-                               pipeline.DEFAULT_OPTS, G, frame.final_T, frame.last, grads[0])
+                               pipeline.DEFAULT_OPTS, G, frame.final_T, frame.last, grads[0], g2d_zeroed=True)
         if ev is not None:
             ev[4].record()
         native.darb_preprocess_bwd(cam, kern, n, spd, grads[0], grads[1], proj=frame.proj)

@@ -40,7 +40,7 @@ extern "C" {
 #define DARB_API
 #endif
 
-#define DARB_ABI_VERSION 3
+#define DARB_ABI_VERSION 4
 #define DARB_TILE 16
 #define DARB_MAX_VIEWS 16       /* views per multi-view call */
 #define DARB_LOSS_WS_BYTES 4096 /* workspace of darb_image_loss */
@@ -269,12 +269,19 @@ DARB_API darb_status darb_bin_sort(const darb_projected *proj, int64_t n, int32_
  *   last      [H][W]     u32 position in `vals` of the last blended instance,
  *                        0xFFFFFFFF when none (checkpoint)
  *   n_contrib [H][W]     nullable: number of blended splats
- *   overflow_dev nullable: when it points at a nonzero flag the kernel writes nothing
+ *   zero_g2d  nullable: 2D-gradient buffers of the n splats ([n] layouts of
+ *             darb_grads2d) that the call also sets to zero, from the same
+ *             launch (the clearing stores use the memory bandwidth the
+ *             compositing leaves idle); a following darb_raster_bwd into them
+ *             can then pass g2d_zeroed = 1.  They must not alias the other
+ *             arguments.
+ *   overflow_dev nullable: when it points at a nonzero flag the kernel writes
+ *             nothing but the zeros of zero_g2d
  */
 DARB_API darb_status darb_raster_fwd(const darb_projected *proj, int64_t n, const uint32_t *vals, const uint32_t *ranges,
                             const int32_t *overflow_dev, int32_t width, int32_t height, const darb_kernel *kernel,
                             const darb_raster_opts *opts, float *image, float *final_T, uint32_t *last,
-                            uint32_t *n_contrib, void *stream);
+                            uint32_t *n_contrib, const darb_grads2d *zero_g2d, void *stream);
 
 /*
  * darb_raster_bwd -- reverse-order compositing gradients (Backpropagation
@@ -294,7 +301,9 @@ DARB_API darb_status darb_raster_fwd(const darb_projected *proj, int64_t n, cons
  *                      k_capacity (the capacity of vals given to darb_bin_sort)
  *                      and ws of darb_raster_bwd_workspace() bytes; otherwise
  *                      k_capacity is ignored and ws may be NULL.
- * g2d is zeroed by the call first.
+ * g2d is zeroed by the call first, unless g2d_zeroed is nonzero: the caller
+ * then guarantees that every element of g2d is zero already (for instance
+ * cleared by darb_raster_fwd's zero_g2d on the same stream).
  *   dL_dimage [3][H][W]
  *   g2d       required output
  *   cam, in, g3d: when g3d is non-null the call continues with the chain of
@@ -304,9 +313,9 @@ DARB_API darb_status darb_raster_fwd(const darb_projected *proj, int64_t n, cons
 DARB_API darb_status darb_raster_bwd(const darb_projected *proj, int64_t n, const uint32_t *vals, const uint32_t *ranges,
                             const int32_t *overflow_dev, int32_t width, int32_t height, const darb_kernel *kernel,
                             const darb_raster_opts *opts, const float *dL_dimage, const float *final_T,
-                            const uint32_t *last, const darb_grads2d *g2d, const darb_camera *cam,
-                            const darb_splats *in, const darb_grads3d *g3d, int32_t deterministic,
-                            int64_t k_capacity, void *ws, size_t ws_bytes, void *stream);
+                            const uint32_t *last, const darb_grads2d *g2d, int32_t g2d_zeroed,
+                            const darb_camera *cam, const darb_splats *in, const darb_grads3d *g3d,
+                            int32_t deterministic, int64_t k_capacity, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * darb_raster_bwd_workspace -- bytes of workspace of the deterministic

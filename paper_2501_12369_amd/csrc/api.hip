@@ -356,7 +356,7 @@ darb_status darb_bin_sort(const darb_projected *proj, int64_t n, int32_t width, 
 darb_status darb_raster_fwd(const darb_projected *proj, int64_t n, const uint32_t *vals, const uint32_t *ranges,
                             const int32_t *overflow_dev, int32_t width, int32_t height, const darb_kernel *kernel,
                             const darb_raster_opts *opts, float *image, float *final_T, uint32_t *last,
-                            uint32_t *n_contrib, void *stream) {
+                            uint32_t *n_contrib, const darb_grads2d *zero_g2d, void *stream) {
     darb::KParams kp;
     darb::ROpts ro;
     TRY(check_n(n));
@@ -371,6 +371,7 @@ darb_status darb_raster_fwd(const darb_projected *proj, int64_t n, const uint32_
     REQUIRE_PTR(final_T);
     REQUIRE_PTR(last);
     OPT_PTR(n_contrib);
+    if (zero_g2d) TRY(check_g2d(zero_g2d, n));
     g_err[0] = 0;
     darb::RViews rv{};
     rv.nv = 1;
@@ -379,6 +380,10 @@ darb_status darb_raster_fwd(const darb_projected *proj, int64_t n, const uint32_
     rv.v[0].final_T = final_T;
     rv.v[0].last = last;
     rv.v[0].n_contrib = n_contrib;
+    if (zero_g2d && n > 0) {
+        rv.v[0].g2 = *zero_g2d;
+        rv.v[0].zero_n = (int)n;
+    }
     return hip_status(darb::launch_raster_fwd(kernel->kind, rv, tile_count(width, height), (int)n, kp, ro,
                                               (hipStream_t)stream),
                       "darb_raster_fwd");
@@ -405,9 +410,9 @@ darb_status darb_preprocess_bwd(const darb_camera *cam, const darb_kernel *kerne
 darb_status darb_raster_bwd(const darb_projected *proj, int64_t n, const uint32_t *vals, const uint32_t *ranges,
                             const int32_t *overflow_dev, int32_t width, int32_t height, const darb_kernel *kernel,
                             const darb_raster_opts *opts, const float *dL_dimage, const float *final_T,
-                            const uint32_t *last, const darb_grads2d *g2d, const darb_camera *cam,
-                            const darb_splats *in, const darb_grads3d *g3d, int32_t deterministic,
-                            int64_t k_capacity, void *ws, size_t ws_bytes, void *stream) {
+                            const uint32_t *last, const darb_grads2d *g2d, int32_t g2d_zeroed,
+                            const darb_camera *cam, const darb_splats *in, const darb_grads3d *g3d,
+                            int32_t deterministic, int64_t k_capacity, void *ws, size_t ws_bytes, void *stream) {
     darb::KParams kp;
     darb::ROpts ro;
     darb::Cam c;
@@ -451,7 +456,7 @@ darb_status darb_raster_bwd(const darb_projected *proj, int64_t n, const uint32_
     rv.v[0].dL = dL_dimage;
     rv.v[0].g2 = *g2d;
     TRY(hip_status(darb::launch_raster_bwd(kernel->kind, rv, items, (int)n, kp, ro, deterministic ? ws : nullptr,
-                                           deterministic ? (uint64_t)k_capacity : 0, s),
+                                           deterministic ? (uint64_t)k_capacity : 0, g2d_zeroed != 0, s),
                    "darb_raster_bwd"));
     if (g3d)
         TRY(hip_status(darb::launch_preprocess_bwd(c, kp, (int)n, *in, proj, *g2d, *g3d, false, s),
@@ -627,7 +632,7 @@ darb_status darb_raster_bwd_multi(const darb_view *views, int32_t nv, int64_t n,
     }
     g_err[0] = 0;
     return hip_status(darb::launch_raster_bwd(kernel->kind, rv, items, (int)n, kp, ro, deterministic ? ws : nullptr,
-                                              deterministic ? cap : 0, (hipStream_t)stream),
+                                              deterministic ? cap : 0, false, (hipStream_t)stream),
                       "darb_raster_bwd_multi");
 }
 

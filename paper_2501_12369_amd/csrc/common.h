@@ -273,7 +273,8 @@ struct RView {
     uint32_t *last, *n_contrib;
     const float *dL;      // upstream gradient [3][H][W] (backward from a checkpoint)
     const float *target;  // target image [3][H][W] (fused forward+backward)
-    darb_grads2d g2;
+    darb_grads2d g2;      // backward: the 2D gradients; forward: the buffers to clear when zero_n > 0
+    int zero_n;           // forward: splat count of g2 to clear (0: none)
     float loss_scale;     // 1 / (3 W H)
     int W, H, gx;
     uint32_t item0, key0;
@@ -339,8 +340,10 @@ hipError_t radix_sort_pairs(uint32_t *kA, uint32_t *vA, uint32_t *kB, uint32_t *
 hipError_t launch_raster_fwd(int kind, const RViews &V, uint32_t items, int n, const KParams &kp, const ROpts &o,
                              hipStream_t s);
 size_t det_workspace(uint32_t items, uint64_t capacity);
+// g2_zeroed: every view's 2D gradients are known to be zero (cleared by the
+// forward), so the backward does not clear them first.
 hipError_t launch_raster_bwd(int kind, const RViews &V, uint32_t items, int n, const KParams &kp, const ROpts &o,
-                             void *det_ws, uint64_t det_capacity, hipStream_t s);
+                             void *det_ws, uint64_t det_capacity, bool g2_zeroed, hipStream_t s);
 hipError_t launch_raster_fwdbwd(int kind, int loss, const RViews &V, uint32_t items, int n, const KParams &kp,
                                 const ROpts &o, hipStream_t s);
 

@@ -450,14 +450,36 @@ __device__ __forceinline__ void load_checkpoint(const RView &V, int tile, float 
     }
 }
 
+// Workgroup `part` of `nparts` clears its share of the four 2D-gradient arrays
+// of n splats (2n, 3n, n, 3n floats, taken as one run of 9n), in runs of
+// consecutive lanes.
+__device__ __forceinline__ void zero_grads_part(const darb_grads2d &g, size_t n, uint32_t part, uint32_t nparts) {
+    const size_t total = 9 * n;
+    const size_t per = ((total + nparts - 1) / nparts + 63) & ~(size_t)63;
+    const size_t lo = (size_t)part * per, hi = min(total, lo + per);
+    float *const arr[4] = {g.xy, g.conic, g.opacity, g.rgb};
+    const size_t beg[5] = {0, 2 * n, 5 * n, 6 * n, 9 * n};
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+        const size_t s = max(lo, beg[a]), e = min(hi, beg[a + 1]);
+        for (size_t k = s + threadIdx.x; k < e; k += blockDim.x) arr[a][k - beg[a]] = 0.0f;
+    }
+}
+
+// With V.zero_n > 0 each workgroup also clears its share of the 2D gradients
+// (single view): the stores go out after the tile's own work, when the wave
+// has no load left to wait for, and fill the memory pipe that the compositing
+// leaves idle.  They are issued on the overflow path as well.
 template <int KIND, class VS, bool CNT>
 __global__ __launch_bounds__(64 * kSplit) void k_raster_fwd(VS A, int n, KParams kp, ROpts o) {
     int tile;
     const RView &V = A.get(blockIdx.x, tile);
-    if (V.overflow && *V.overflow) return;
-    PixF<kPix / kSplit> F;
-    tile_fwd<KIND, kSplit, CNT>(V, tile, n, kp, o, F);
-    store_fwd<kSplit>(V, tile, F, o);
+    if (!(V.overflow && *V.overflow)) {
+        PixF<kPix / kSplit> F;
+        tile_fwd<KIND, kSplit, CNT>(V, tile, n, kp, o, F);
+        store_fwd<kSplit>(V, tile, F, o);
+    }
+    if (V.zero_n > 0) zero_grads_part(V.g2, (size_t)V.zero_n, blockIdx.x, gridDim.x);
 }
 
 template <int KIND, bool DET, class VS>
@@ -712,9 +734,9 @@ hipError_t launch_raster_fwd(int kind, const RViews &V, uint32_t items, int n, c
 }
 
 hipError_t launch_raster_bwd(int kind, const RViews &V, uint32_t items, int n, const KParams &kp, const ROpts &o,
-                             void *det_ws, uint64_t det_capacity, hipStream_t s) {
+                             void *det_ws, uint64_t det_capacity, bool g2_zeroed, hipStream_t s) {
     hipError_t e;
-    if ((e = zero_grads(V, n, s)) != hipSuccess) return e;
+    if (!g2_zeroed && (e = zero_grads(V, n, s)) != hipSuccess) return e;
     if (items == 0 || n == 0) return hipGetLastError();
     if (!det_ws) {
         DARB_KIND_SWITCH(kind, bwd_launch, (V, items, n, kp, o, false, DetOut{}, s))

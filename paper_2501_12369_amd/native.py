@@ -117,12 +117,12 @@ def lib():
         L.darb_raster_fwd.restype = c_int32
         L.darb_raster_fwd.argtypes = [P(darb_projected), c_int64, c_void_p, c_void_p, c_void_p, c_int32, c_int32,
                                       P(darb_kernel), P(darb_raster_opts), c_void_p, c_void_p, c_void_p, c_void_p,
-                                      c_void_p]
+                                      P(darb_grads2d), c_void_p]
         L.darb_raster_bwd.restype = c_int32
         L.darb_raster_bwd.argtypes = [P(darb_projected), c_int64, c_void_p, c_void_p, c_void_p, c_int32, c_int32,
                                       P(darb_kernel), P(darb_raster_opts), c_void_p, c_void_p, c_void_p,
-                                      P(darb_grads2d), P(darb_camera), P(darb_splats), P(darb_grads3d), c_int32,
-                                      c_int64, c_void_p, c_size_t, c_void_p]
+                                      P(darb_grads2d), c_int32, P(darb_camera), P(darb_splats), P(darb_grads3d),
+                                      c_int32, c_int64, c_void_p, c_size_t, c_void_p]
         L.darb_raster_bwd_workspace.restype = c_size_t
         L.darb_raster_bwd_workspace.argtypes = [c_int64, c_int32, c_int32, c_int64]
         L.darb_preprocess_bwd.restype = c_int32
@@ -292,11 +292,13 @@ def darb_bin_sort(proj: dict, n: int, width: int, height: int, k_capacity: int, 
 
 
 def darb_raster_fwd(proj: dict, n: int, vals, ranges, overflow_dev, width: int, height: int, kernel, opts: dict,
-                    image, final_T, last, n_contrib=None, stream=None):
+                    image, final_T, last, n_contrib=None, zero_g2d: dict | None = None, stream=None):
     p, k, o = projected_struct(proj), kernel_struct(kernel), opts_struct(opts)
+    z = grads2d_struct(zero_g2d) if zero_g2d is not None else None
     _check(lib().darb_raster_fwd(ctypes.byref(p), n, _ptr(vals), _ptr(ranges), _ptr(overflow_dev), width, height,
                                  ctypes.byref(k), ctypes.byref(o), _ptr(image), _ptr(final_T), _ptr(last),
-                                 _ptr(n_contrib), _stream(stream)), "darb_raster_fwd")
+                                 _ptr(n_contrib), ctypes.byref(z) if z is not None else None, _stream(stream)),
+           "darb_raster_fwd")
 
 
 def _nbytes(t) -> int:
@@ -306,7 +308,7 @@ def _nbytes(t) -> int:
 def darb_raster_bwd(proj: dict, n: int, vals, ranges, overflow_dev, width: int, height: int, kernel, opts: dict,
                     dL_dimage, final_T, last, g2d: dict, cam: dict | None = None, splats: dict | None = None,
                     g3d: dict | None = None, deterministic: bool = False, k_capacity: int = 0, ws=None,
-                    stream=None):
+                    g2d_zeroed: bool = False, stream=None):
     p, k, o = projected_struct(proj), kernel_struct(kernel), opts_struct(opts)
     g2 = grads2d_struct(g2d)
     if g3d is not None:
@@ -316,7 +318,8 @@ def darb_raster_bwd(proj: dict, n: int, vals, ranges, overflow_dev, width: int, 
         cref = sref = g3ref = None
     _check(lib().darb_raster_bwd(ctypes.byref(p), n, _ptr(vals), _ptr(ranges), _ptr(overflow_dev), width, height,
                                  ctypes.byref(k), ctypes.byref(o), _ptr(dL_dimage), _ptr(final_T), _ptr(last),
-                                 ctypes.byref(g2), cref, sref, g3ref, 1 if deterministic else 0, int(k_capacity),
+                                 ctypes.byref(g2), 1 if g2d_zeroed else 0, cref, sref, g3ref, 1 if deterministic else 0,
+                                 int(k_capacity),
                                  _ptr(ws), _nbytes(ws), _stream(stream)), "darb_raster_bwd")
 
 

@@ -135,9 +135,10 @@ def bin_sort(frame: Frame, read_k: bool = True, stream=None):
 
 def render(splats: dict, cam: dict, kernel: KernelSpec, opts: dict | None = None, frame: Frame | None = None,
            k_capacity: int | None = None, read_k: bool = True, keys: bool = False, n_contrib: bool = False,
-           stream=None) -> Frame:
+           zero_g2d: dict | None = None, stream=None) -> Frame:
     """preprocess -> bin/sort -> raster forward.  Returns the frame with the
-    image and the checkpoint (final T, last position)."""
+    image and the checkpoint (final T, last position).  ``zero_g2d``: 2D-gradient
+    buffers the raster forward also clears (see render_backward's g2d_zeroed)."""
     opts = opts or DEFAULT_OPTS
     n = int(splats["means"].shape[1])
     W, H = int(cam["width"]), int(cam["height"])
@@ -148,7 +149,7 @@ def render(splats: dict, cam: dict, kernel: KernelSpec, opts: dict | None = None
     native.darb_preprocess(cam, kernel, n, splats, frame.proj, stream=stream)
     bin_sort(frame, read_k=read_k, stream=stream)
     native.darb_raster_fwd(frame.proj, n, frame.vals, frame.ranges, frame.overflow, W, H, kernel, opts, frame.image,
-                           frame.final_T, frame.last, frame.n_contrib, stream=stream)
+                           frame.final_T, frame.last, frame.n_contrib, zero_g2d=zero_g2d, stream=stream)
     return frame
 
 
@@ -172,8 +173,9 @@ def det_workspace(frame: Frame) -> torch.Tensor:
 
 def render_backward(frame: Frame, dL_dimage: torch.Tensor, splats: dict, cam: dict, kernel: KernelSpec,
                     opts: dict | None = None, grads=None, chain: bool = True, stream=None, deterministic: bool = False,
-                    det_ws: torch.Tensor | None = None):
-    """raster backward (+ the preprocess chain when ``chain``) from the checkpoint."""
+                    det_ws: torch.Tensor | None = None, g2d_zeroed: bool = False):
+    """raster backward (+ the preprocess chain when ``chain``) from the checkpoint.
+    ``g2d_zeroed``: grads[0] was cleared by the forward (render's zero_g2d)."""
     opts = opts or DEFAULT_OPTS
     n = frame.n
     if grads is None:
@@ -185,7 +187,7 @@ def render_backward(frame: Frame, dL_dimage: torch.Tensor, splats: dict, cam: di
                            opts, dL_dimage.contiguous(), frame.final_T, frame.last, g2d,
                            cam if chain else None, splats if chain else None, g3d if chain else None,
                            deterministic=deterministic, k_capacity=frame.capacity,
-                           ws=det_ws if deterministic else None, stream=stream)
+                           ws=det_ws if deterministic else None, g2d_zeroed=g2d_zeroed, stream=stream)
     return g2d, g3d
 
 
@@ -289,13 +291,13 @@ def sequential_step(splats: dict, mf: MultiFrame, targets: list, kernel: KernelS
         native.darb_bin_sort(fr.proj, n, fr.width, fr.height, fr.capacity, fr.ws, None, fr.vals, fr.ranges, fr.k_dev,
                              fr.overflow, stream=stream)
         native.darb_raster_fwd(fr.proj, n, fr.vals, fr.ranges, fr.overflow, fr.width, fr.height, kernel, opts,
-                               fr.image, fr.final_T, fr.last, fr.n_contrib, stream=stream)
+                               fr.image, fr.final_T, fr.last, fr.n_contrib, zero_g2d=mf.g2d[v], stream=stream)
         native.darb_image_loss(fr.image, targets[v], fr.width, fr.height, loss_kind, dL_dimage=mf.dL[v], stream=stream)
         ws = None
         if deterministic:
             ws = det_ws[v] if det_ws is not None else det_workspace(fr)
         native.darb_raster_bwd(fr.proj, n, fr.vals, fr.ranges, fr.overflow, fr.width, fr.height, kernel, opts,
                                mf.dL[v], fr.final_T, fr.last, mf.g2d[v], deterministic=deterministic,
-                               k_capacity=fr.capacity, ws=ws, stream=stream)
+                               k_capacity=fr.capacity, ws=ws, g2d_zeroed=True, stream=stream)
         native.darb_preprocess_bwd(cam, kernel, n, splats, mf.g2d[v], g3d, accumulate=v > 0, stream=stream,
                                    proj=fr.proj)

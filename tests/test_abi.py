@@ -44,7 +44,7 @@ def test_library_exports_every_declared_symbol(L):
 def test_version_and_status_strings(L):
     from paper_2501_12369_amd import native
 
-    assert native.darb_version() == 3
+    assert native.darb_version() == 4
     assert L.darb_status_string(0) == b"ok"
     assert L.darb_status_string(2) == b"instance capacity exceeded"
 

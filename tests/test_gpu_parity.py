@@ -196,6 +196,51 @@ def test_raster_bwd_parity(kname):
             assert ok, (det, name, l2, ratio)
 
 
+@pytest.mark.parametrize("n", [1200, 7])
+def test_raster_fwd_clears_g2d(n):
+    """zero_g2d: the forward clears the 2D-gradient buffers (also when the
+    overflow flag is set) and its own outputs keep their bits; the backward
+    told that they are zero (g2d_zeroed) gives the bits of the default call
+    (deterministic mode, so that the comparison is exact)."""
+    kname, W, H, seed = "half_cos", 120, 90, 23
+    print(f"zero_g2d n={n} {W}x{H}", flush=True)
+    ps, fr, _ = _forward_case(kname, n, W, H, seed)
+    k, opts = pipeline.KERNELS[kname], pipeline.DEFAULT_OPTS
+    ref = {name: to_np(getattr(fr, name)).copy() for name in ("image", "final_T", "last")}
+    G = dev(scenes.upstream_grad(seed + 1, W, H))
+    ws = pipeline.det_workspace(fr)
+    g_ref, _ = pipeline.alloc_grads(n, 0)
+    native.darb_raster_bwd(fr.proj, n, fr.vals, fr.ranges, fr.overflow, W, H, k, opts, G, fr.final_T, fr.last, g_ref,
+                           deterministic=True, k_capacity=fr.capacity, ws=ws)
+    g2, _ = pipeline.alloc_grads(n, 0)
+    for t in g2.values():
+        t.fill_(float("nan"))
+    native.darb_raster_fwd(fr.proj, n, fr.vals, fr.ranges, fr.overflow, W, H, k, opts, fr.image, fr.final_T,
+                           fr.last, zero_g2d=g2)
+    torch.cuda.synchronize()
+    for name, v in ref.items():
+        assert np.array_equal(to_np(getattr(fr, name)), v), name
+    for name, t in g2.items():
+        assert not to_np(t).any(), name
+    native.darb_raster_bwd(fr.proj, n, fr.vals, fr.ranges, fr.overflow, W, H, k, opts, G, fr.final_T, fr.last, g2,
+                           deterministic=True, k_capacity=fr.capacity, ws=ws, g2d_zeroed=True)
+    torch.cuda.synchronize()
+    for name in g2:
+        assert np.array_equal(to_np(g2[name]), to_np(g_ref[name])), name
+    # with the overflow flag set the forward composites nothing but still clears
+    for t in g2.values():
+        t.fill_(1.0)
+    fr.image.fill_(-1.0)
+    fr.overflow.fill_(1)
+    native.darb_raster_fwd(fr.proj, n, fr.vals, fr.ranges, fr.overflow, W, H, k, opts, fr.image, fr.final_T,
+                           fr.last, zero_g2d=g2)
+    torch.cuda.synchronize()
+    fr.overflow.fill_(0)
+    assert np.all(to_np(fr.image) == -1.0)
+    for name, t in g2.items():
+        assert not to_np(t).any(), name
+
+
 # ---------------------------------------------------------------- preprocess
 
 def _splats_dev(sp):
