@@ -33,7 +33,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def stage_bytes(n, n_vis):
+def stage_bytes(n, n_vis, split=False):
     """Algorithmic HBM bytes per launch of the single-kernel stages (one read of
     each needed input, one write of each output), per splat / per visible splat:
       preprocess      12 B mean + 4 B cull data of every splat; 224 B of parameters
@@ -41,10 +41,18 @@ def stage_bytes(n, n_vis):
                       record written per visible splat; the 36 B colour checkpoint
                       (d colour / d direction) written for every splat:
                                                                   52 N + 272 N_v
+      split in two launches (split=True), the stage is the geometry part: mean,
+      scale, quaternion and opacity read (44 B), xy, depth, radius and conic_o
+      written (32 B), for every splat:                            76 N
+      and the colour part beside the binning reads the radius (4 B) of every splat
+      and the mean and 48 SH (204 B) of each visible one, and writes rgb, clamp
+      bits and the colour checkpoint (49 B) of every splat:       53 N + 204 N_v
       preprocess_bwd  per visible splat 113 B read (mean 12, scale 12, quaternion 16,
                       2D gradients 36, colour checkpoint 36 + clamp bits 1), the full
                       gradient written for every splat (236 B):   113 N_v + 236 N
     """
+    if split:
+        return dict(preprocess=76 * n, colour=53 * n + 204 * n_vis, preprocess_bwd=113 * n_vis + 236 * n)
     return dict(preprocess=52 * n + 272 * n_vis, preprocess_bwd=113 * n_vis + 236 * n)
 
 
@@ -204,12 +212,10 @@ def variants_bench(spd, cam, steps: int, warmup: int):
     pipeline.render(spd, cam, kern, frame=frame, read_k=True)
     grads = pipeline.alloc_grads(n, 3)
 
+    side = torch.cuda.Stream()
+
     def plain():
-        native.darb_preprocess(cam, kern, n, spd, frame.proj)
-        native.darb_bin_sort(frame.proj, n, W, H, frame.capacity, frame.ws, None, frame.vals, frame.ranges,
-                             frame.k_dev, frame.overflow)
-        native.darb_raster_fwd(frame.proj, n, frame.vals, frame.ranges, frame.overflow, W, H, kern,
-                               pipeline.DEFAULT_OPTS, frame.image, frame.final_T, frame.last, zero_g2d=grads[0])
+        pipeline.forward_overlapped(spd, cam, kern, frame, side, zero_g2d=grads[0])
         native.darb_raster_bwd(frame.proj, n, frame.vals, frame.ranges, frame.overflow, W, H, kern,
                                pipeline.DEFAULT_OPTS, G, frame.final_T, frame.last, grads[0], g2d_zeroed=True)
         native.darb_preprocess_bwd(cam, kern, n, spd, grads[0], grads[1], proj=frame.proj)
@@ -307,6 +313,8 @@ def main():
     ap.add_argument("--kernel", default="half_cos", choices=["half_cos", "gauss"])
     ap.add_argument("--n", type=int, default=3_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="run the preprocess as one kernel instead of its colour part beside the binning")
     ap.add_argument("--cpu-rows-every", type=int, default=16)
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="0 disables the serving leg")
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -357,14 +365,34 @@ def main():
 
     stages = ["preprocess", "bin_sort", "raster_fwd", "raster_bwd", "preprocess_bwd"]
 
-    def step(ev=None):
+    # The colour part of the preprocess (SH colour and its checkpoint, most of the
+    # stage's bytes) is not an input of the binning: it runs on a second stream
+    # (default priority) beside the latency-bound bin/sort kernels and is joined
+    # before the raster forward.  Stage "preprocess" is then the geometry part and
+    # "bin_sort" ends at the join; "colour" is timed on the side stream.
+    overlap = not args.no_overlap
+    side = torch.cuda.Stream()
+    main = torch.cuda.current_stream()
+    if overlap:
+        STAGE_KERNEL["preprocess"] = ("k_preprocess_geom", ("preprocess.hip", "common.h"))
+
+    def step(ev=None, evc=None):
         if ev is not None:
             ev[0].record()
-        native.darb_preprocess(cam, kern, n, spd, frame.proj)
+        native.darb_preprocess(cam, kern, n, spd, frame.proj, parts=native.PRE_GEOMETRY if overlap else 3)
         if ev is not None:
             ev[1].record()
+        if overlap:
+            side.wait_stream(main)
+            if evc is not None:
+                evc[0].record(side)
+            native.darb_preprocess(cam, kern, n, spd, frame.proj, parts=native.PRE_COLOUR, stream=side)
+            if evc is not None:
+                evc[1].record(side)
         native.darb_bin_sort(frame.proj, n, W, H, frame.capacity, frame.ws, None, frame.vals, frame.ranges,
                              frame.k_dev, frame.overflow)
+        if overlap:
+            main.wait_stream(side)
         if ev is not None:
             ev[2].record()
         native.darb_raster_fwd(frame.proj, n, frame.vals, frame.ranges, frame.overflow, W, H, kern,
@@ -383,10 +411,11 @@ def main():
         step()
     torch.cuda.synchronize()
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
+    evcs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for i in range(args.steps):
-        step(evs[i])
+        step(evs[i], evcs[i])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     assert int(frame.overflow[0].item()) == 0, "instance capacity overflow during timing"
@@ -394,6 +423,10 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     mpix = P * args.steps / wall / 1e6
     log("per-stage ms: " + ", ".join(f"{k}={v:.3f}" for k, v in per_stage.items()) + f"; step {ms_per_step:.3f} ms")
+    colour_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evcs])) if overlap else None
+    if overlap:
+        log(f"colour part on the side stream (beside bin_sort): {colour_ms:.3f} ms, "
+            f"{stage_bytes(n, n_vis, True)['colour'] / (colour_ms * 1e-3) / 1e9:.1f} GB/s")
 
     # algorithmic work of the raster stages from the checkpoint
     last = frame.last.to(torch.int64) & 0xFFFFFFFF
@@ -405,7 +438,7 @@ def main():
     has = last != 0xFFFFFFFF
     pairs_bwd = int(torch.where(has, last - start + 1, torch.zeros_like(last)).sum())
     chunks = 0
-    bytes_ = stage_bytes(n, n_vis)
+    bytes_ = stage_bytes(n, n_vis, overlap)
     roof = {st: dict(bound="hbm", achieved=bytes_[st] / (per_stage[st] * 1e-3) / 1e9, peak=PEAK_HBM_GBS, unit="GB/s")
             for st in ("preprocess", "preprocess_bwd")}
     roof["raster_bwd"] = dict(bound="alu", achieved=pairs_bwd * FLOPS_PER_PAIR_BWD / (per_stage["raster_bwd"] * 1e-3)
@@ -466,7 +499,8 @@ def main():
                                f"preprocess+bin/sort+raster fwd+raster bwd+preprocess bwd",
                    "n_splats": n, "width": W, "height": H, "kernel": args.kernel, "visible": n_vis, "instances": K,
                    "splats_per_s": round(n * args.steps / wall, 1),
-                   "stage_ms": {k: round(v, 4) for k, v in per_stage.items()}, "variants": variants},
+                   "stage_ms": {k: round(v, 4) for k, v in per_stage.items()},
+                   "colour_side_stream_ms": round(colour_ms, 4) if overlap else None, "variants": variants},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "multiview": multiview_stats,

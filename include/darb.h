@@ -211,6 +211,25 @@ DARB_API darb_status darb_preprocess(const darb_camera *cam, const darb_kernel *
                             const darb_projected *out, void *stream);
 
 /*
+ * darb_preprocess_parts -- darb_preprocess split in two launches with the same
+ * arithmetic (together they write the same bits):
+ *   DARB_PRE_GEOMETRY  reads means, scales, quats, opacity; writes xy, depth,
+ *                      radius and conic_o (what darb_bin_sort reads);
+ *   DARB_PRE_COLOUR    reads radius (written by the geometry part for the same
+ *                      camera and splats: a splat is kept iff radius > 0), means
+ *                      and sh; writes rgb, clamped and dcolor (when non-null).
+ * The colour part is not an input of darb_bin_sort, so a caller may run it on a
+ * second stream (after the geometry part, by an event) while the binning runs,
+ * and join before darb_raster_fwd.  parts = 3 is darb_preprocess; any other
+ * value is DARB_ERR_INVALID_ARG.
+ */
+#define DARB_PRE_GEOMETRY 1
+#define DARB_PRE_COLOUR 2
+DARB_API darb_status darb_preprocess_parts(const darb_camera *cam, const darb_kernel *kernel, int64_t n,
+                                           const darb_splats *in, const darb_projected *out, int32_t parts,
+                                           void *stream);
+
+/*
  * darb_preprocess_cam_dev -- darb_preprocess with the camera read from DEVICE
  * memory (one darb_camera at cam_dev), so that a captured graph of the render
  * can be replayed for a new pose after the caller rewrites that buffer.

@@ -291,6 +291,25 @@ darb_status darb_preprocess(const darb_camera *cam, const darb_kernel *kernel, i
                       "darb_preprocess");
 }
 
+darb_status darb_preprocess_parts(const darb_camera *cam, const darb_kernel *kernel, int64_t n, const darb_splats *in,
+                                  const darb_projected *out, int32_t parts, void *stream) {
+    if (parts < DARB_PRE_GEOMETRY || parts > (DARB_PRE_GEOMETRY | DARB_PRE_COLOUR)) {
+        snprintf(g_err, sizeof(g_err), "parts must be 1, 2 or 3 (got %d)", (int)parts);
+        return DARB_ERR_INVALID_ARG;
+    }
+    darb::Cam c;
+    darb::KParams kp;
+    TRY(check_n(n));
+    TRY(check_camera(cam, &c));
+    TRY(check_kernel(kernel, &kp));
+    TRY(check_size(cam->width, cam->height));
+    TRY(check_splats(in, n));
+    TRY(check_projected(out, n, true));
+    g_err[0] = 0;
+    return hip_status(darb::launch_preprocess_parts(c, kp, (int)n, *in, *out, (int)parts, (hipStream_t)stream),
+                      "darb_preprocess_parts");
+}
+
 darb_status darb_preprocess_cam_dev(const darb_camera *cam_dev, int32_t width, int32_t height,
                                     const darb_kernel *kernel, int64_t n, const darb_splats *in,
                                     const darb_projected *out, void *stream) {

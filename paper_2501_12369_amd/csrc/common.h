@@ -306,6 +306,10 @@ struct G2s {
 // (whose width/height still size the tile grid)
 hipError_t launch_preprocess(const Cam &cam, const darb_camera *cam_dev, const KParams &kp, int n,
                              const darb_splats &in, const darb_projected &out, hipStream_t s);
+// parts: 1 the geometry (xy, depth, radius, conic_o), 2 the colour (rgb,
+// clamped, dcolor; reads the geometry part's radius), 3 both in one kernel.
+hipError_t launch_preprocess_parts(const Cam &cam, const KParams &kp, int n, const darb_splats &in,
+                                   const darb_projected &out, int parts, hipStream_t s);
 // ckpt (nullable): the forward's records of this view; its dcolor and clamped,
 // when both set, replace the SH coefficients in the colour part of the chain
 hipError_t launch_preprocess_bwd(const Cam &cam, const KParams &kp, int n, const darb_splats &in,

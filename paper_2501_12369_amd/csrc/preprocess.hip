@@ -359,21 +359,32 @@ __device__ __forceinline__ void sh_colour(const Cam &cam, const float (&m)[3], c
     }
 }
 
-// Every lane stores (zeros for culled splats): whole-line writes.
-__device__ __forceinline__ void store_proj(const darb_projected &out, int n, int i, bool vis, const Proj &P, float op,
-                                           const float (&col)[3], uint8_t cl, const float (&jac)[9]) {
-    if (out.dcolor) {
-#pragma unroll
-        for (int k = 0; k < 9; k++) out.dcolor[(size_t)k * n + i] = vis ? jac[k] : 0.0f;
-    }
+// Every lane stores (zeros for culled splats): whole-line writes.  The
+// geometry part of the record (what the binning reads) ...
+__device__ __forceinline__ void store_geom(const darb_projected &out, int i, bool vis, const Proj &P, float op) {
     reinterpret_cast<float2 *>(out.xy)[i] = vis ? make_float2(P.u, P.v) : make_float2(0.0f, 0.0f);
     out.depth[i] = vis ? P.t[2] : 0.0f;
     out.radius[i] = vis ? P.radius : 0;
     reinterpret_cast<float4 *>(out.conic_o)[i] = vis ? make_float4(P.l00, P.l01, P.l11, op) : make_float4(0, 0, 0, 0);
+}
+
+// ... and its colour part.
+__device__ __forceinline__ void store_colour(const darb_projected &out, int n, int i, bool vis, const float (&col)[3],
+                                             uint8_t cl, const float (&jac)[9]) {
+    if (out.dcolor) {
+#pragma unroll
+        for (int k = 0; k < 9; k++) out.dcolor[(size_t)k * n + i] = vis ? jac[k] : 0.0f;
+    }
     out.rgb[3 * i] = col[0];
     out.rgb[3 * i + 1] = col[1];
     out.rgb[3 * i + 2] = col[2];
     out.clamped[i] = cl;
+}
+
+__device__ __forceinline__ void store_proj(const darb_projected &out, int n, int i, bool vis, const Proj &P, float op,
+                                           const float (&col)[3], uint8_t cl, const float (&jac)[9]) {
+    store_colour(out, n, i, vis, col, cl, jac);
+    store_geom(out, i, vis, P, op);
 }
 
 template <int DEG>
@@ -407,6 +418,52 @@ __global__ __launch_bounds__(256) void k_preprocess(Cam cam_arg, const darb_came
             sh_colour<NB, false>(cam, m, c, col, cl, jac);
     }
     store_proj(out, n, i, vis, P, op, col, cl, jac);
+}
+
+// The two parts of k_preprocess as separate launches, each with the same
+// arithmetic (so together they give its bits).  Geometry: the record the
+// binning reads (xy, depth, radius, conic and opacity).
+__global__ __launch_bounds__(256) void k_preprocess_geom(Cam cam, KParams kp, int n, darb_splats in,
+                                                         darb_projected out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float m[3];
+    load_mean(in, n, i, m);
+    const QS qs = load_qs(in, n, i);
+    const float op_in = in.opacity[i];
+    pin_geometry(m, qs);
+    Geom G;
+    Proj P;
+    const bool vis = view_depth(cam, m, P) && splat_geom_of(qs, G) && project_rest(cam, kp, G, P);
+    store_geom(out, i, vis, P, vis ? op_in : 0.0f);
+}
+
+// Colour: the SH colour, clamp bits and colour checkpoint of the splats the
+// geometry part kept (radius > 0; a kept splat's radius is at least 1).  It is
+// meant to run beside the binning on a second stream, so it is launched with
+// one workgroup per compute unit looping over the splats: a full grid of
+// memory-bound waves would take the compute units from the latency-bound
+// binning kernels and slow them by about its own duration.
+template <int DEG>
+__global__ __launch_bounds__(256) void k_preprocess_colour(Cam cam, int n, darb_splats in, darb_projected out) {
+    constexpr int NB = (DEG + 1) * (DEG + 1);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const bool vis = out.radius[i] > 0;
+        float col[3] = {0.0f, 0.0f, 0.0f};
+        float jac[9] = {};
+        uint8_t cl = 0;
+        if (vis) {
+            float m[3];
+            load_mean(in, n, i, m);
+            float c[NB][3];
+            load_sh<NB>(in.sh, n, i, c);
+            if (out.dcolor)
+                sh_colour<NB, true>(cam, m, c, col, cl, jac);
+            else
+                sh_colour<NB, false>(cam, m, c, col, cl, jac);
+        }
+        store_colour(out, n, i, vis, col, cl, jac);
+    }
 }
 
 // Several views: the parameters are read once, the geometry computed once.
@@ -872,6 +929,26 @@ hipError_t launch_preprocess(const Cam &cam, const darb_camera *cam_dev, const K
     if (n == 0) return hipSuccess;
     dim3 grid((n + 255) / 256);
     DARB_DEG_SWITCH(in.sh_degree, k_preprocess, grid, s, cam, cam_dev, kp, n, in, out)
+    return hipGetLastError();
+}
+
+hipError_t launch_preprocess_parts(const Cam &cam, const KParams &kp, int n, const darb_splats &in,
+                                   const darb_projected &out, int parts, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    if (parts == 3) return launch_preprocess(cam, nullptr, kp, n, in, out, s);
+    dim3 grid((n + 255) / 256);
+    if (parts & 1) hipLaunchKernelGGL(k_preprocess_geom, grid, dim3(256), 0, s, cam, kp, n, in, out);
+    if (parts & 2) {
+        static int cus = 0;  // compute units of the device (queried once)
+        if (cus == 0) {
+            int dev = 0;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+                cus = 256;
+        }
+        const dim3 gc(std::min<unsigned>(grid.x, (unsigned)cus));
+        DARB_DEG_SWITCH(in.sh_degree, k_preprocess_colour, gc, s, cam, n, in, out)
+    }
     return hipGetLastError();
 }
 

@@ -23,7 +23,7 @@ LOSS_L1, LOSS_L2 = 0, 1
 MAX_VIEWS = 16
 LOSS_WS_BYTES = 4096
 
-EXPORTED = ("darb_version", "darb_status_string", "darb_last_error", "darb_preprocess", "darb_preprocess_cam_dev",
+EXPORTED = ("darb_version", "darb_status_string", "darb_last_error", "darb_preprocess", "darb_preprocess_parts", "darb_preprocess_cam_dev",
             "darb_bin_sort_workspace", "darb_bin_sort", "darb_raster_fwd", "darb_raster_bwd",
             "darb_raster_bwd_workspace", "darb_preprocess_bwd", "darb_image_loss", "darb_preprocess_multi",
             "darb_raster_fwd_multi", "darb_raster_bwd_multi", "darb_raster_bwd_multi_workspace",
@@ -106,6 +106,9 @@ def lib():
         L.darb_preprocess.restype = c_int32
         L.darb_preprocess.argtypes = [P(darb_camera), P(darb_kernel), c_int64, P(darb_splats), P(darb_projected),
                                       c_void_p]
+        L.darb_preprocess_parts.restype = c_int32
+        L.darb_preprocess_parts.argtypes = [P(darb_camera), P(darb_kernel), c_int64, P(darb_splats),
+                                            P(darb_projected), c_int32, c_void_p]
         L.darb_preprocess_cam_dev.restype = c_int32
         L.darb_preprocess_cam_dev.argtypes = [c_void_p, c_int32, c_int32, P(darb_kernel), c_int64, P(darb_splats),
                                               P(darb_projected), c_void_p]
@@ -249,10 +252,18 @@ def darb_version() -> int:
     return int(lib().darb_version())
 
 
-def darb_preprocess(cam: dict, kernel, n: int, splats: dict, proj: dict, stream=None):
+PRE_GEOMETRY, PRE_COLOUR = 1, 2
+
+
+def darb_preprocess(cam: dict, kernel, n: int, splats: dict, proj: dict, stream=None, parts: int = 3):
+    """parts: PRE_GEOMETRY, PRE_COLOUR or both (3, the single-kernel call)."""
     c, k, s, p = camera_struct(cam), kernel_struct(kernel), splats_struct(splats), projected_struct(proj)
-    _check(lib().darb_preprocess(ctypes.byref(c), ctypes.byref(k), n, ctypes.byref(s), ctypes.byref(p),
-                                 _stream(stream)), "darb_preprocess")
+    if parts == 3:
+        _check(lib().darb_preprocess(ctypes.byref(c), ctypes.byref(k), n, ctypes.byref(s), ctypes.byref(p),
+                                     _stream(stream)), "darb_preprocess")
+    else:
+        _check(lib().darb_preprocess_parts(ctypes.byref(c), ctypes.byref(k), n, ctypes.byref(s), ctypes.byref(p),
+                                           int(parts), _stream(stream)), "darb_preprocess_parts")
 
 
 def camera_bytes(cam: dict) -> bytes:

@@ -153,6 +153,27 @@ def render(splats: dict, cam: dict, kernel: KernelSpec, opts: dict | None = None
     return frame
 
 
+def forward_overlapped(splats: dict, cam: dict, kernel: KernelSpec, frame: Frame, side, opts: dict | None = None,
+                       zero_g2d: dict | None = None, main=None):
+    """The forward of a training step into a sized ``frame`` with no host sync:
+    the preprocess geometry on ``main`` (default: the current stream), then its
+    colour part on the ``side`` stream while ``main`` bins and sorts, joined
+    before the raster forward.  The results are the bits of ``render``."""
+    opts = opts or DEFAULT_OPTS
+    main = main if main is not None else torch.cuda.current_stream()
+    n = frame.n
+    native.darb_preprocess(cam, kernel, n, splats, frame.proj, parts=native.PRE_GEOMETRY, stream=main)
+    side.wait_stream(main)
+    native.darb_preprocess(cam, kernel, n, splats, frame.proj, parts=native.PRE_COLOUR, stream=side)
+    native.darb_bin_sort(frame.proj, n, frame.width, frame.height, frame.capacity, frame.ws, frame.keys, frame.vals,
+                         frame.ranges, frame.k_dev, frame.overflow, stream=main)
+    main.wait_stream(side)
+    native.darb_raster_fwd(frame.proj, n, frame.vals, frame.ranges, frame.overflow, frame.width, frame.height, kernel,
+                           opts, frame.image, frame.final_T, frame.last, frame.n_contrib, zero_g2d=zero_g2d,
+                           stream=main)
+    return frame
+
+
 def alloc_grads(n: int, sh_degree: int, device="cuda"):
     f = dict(dtype=torch.float32, device=device)
     g2d = dict(xy=torch.empty((n, 2), **f), conic=torch.empty((n, 3), **f), opacity=torch.empty(n, **f),

@@ -97,6 +97,10 @@ def test_multiview_and_loss_arguments_rejected_on_host(L):
     arr = (native.darb_view * 17)()
     for i in range(17):
         arr[i] = _view(native)
+    # preprocess parts outside {1, 2, 3}
+    for parts in (0, 4, -1):
+        st = L.darb_preprocess_parts(None, ctypes.byref(k), 0, ctypes.byref(sp), None, parts, None)
+        assert st == native.DARB_ERR_INVALID_ARG and b"parts" in L.darb_last_error()
     # view count outside [1, 16]
     for nv in (0, 17):
         st = L.darb_preprocess_multi(arr, nv, ctypes.byref(k), 0, ctypes.byref(sp), None)

@@ -247,6 +247,36 @@ def _splats_dev(sp):
     return pipeline.splats_to_device(sp)
 
 
+@pytest.mark.parametrize("deg", [3, 1])
+def test_preprocess_parts_bits(deg):
+    """The geometry and colour parts (the colour on a second stream after an
+    event, as in the overlapped step) write the bits of the one-kernel call,
+    for every field, culled splats included."""
+    sc = scenes.object_scale(seed=5, n=20000, width=320, height=240)
+    sp, cam = dict(sc["splats"]), sc["camera"]
+    nb = (deg + 1) ** 2
+    sp["sh"], sp["sh_degree"] = np.ascontiguousarray(sp["sh"][:nb]), deg
+    n = sp["means"].shape[1]
+    print(f"preprocess parts deg={deg} n={n}", flush=True)
+    spd = _splats_dev(sp)
+    k = pipeline.KERNELS["half_cos"]
+    one = pipeline.alloc_projected(n)
+    native.darb_preprocess(cam, k, n, spd, one)
+    two = pipeline.alloc_projected(n)
+    for t in two.values():
+        t.fill_(7)  # stale values everywhere: every field must be rewritten
+    main, side = torch.cuda.current_stream(), torch.cuda.Stream()
+    native.darb_preprocess(cam, k, n, spd, two, parts=native.PRE_GEOMETRY)
+    side.wait_stream(main)
+    native.darb_preprocess(cam, k, n, spd, two, parts=native.PRE_COLOUR, stream=side)
+    main.wait_stream(side)
+    torch.cuda.synchronize()
+    vis = to_np(one["radius"]) > 0
+    assert 0.2 < vis.mean() < 1.0  # both kept and culled splats are covered
+    for name in one:
+        assert np.array_equal(to_np(one[name]), to_np(two[name])), name
+
+
 @pytest.mark.parametrize("kname", ["gauss", "half_cos", "raised_cos"])
 @pytest.mark.parametrize("which", ["tiny", "object"])
 def test_preprocess_parity(kname, which):
