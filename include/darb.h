@@ -353,9 +353,10 @@ DARB_API size_t darb_raster_bwd_workspace(int64_t n, int32_t width, int32_t heig
  * coefficients (zero for clamped channels); opacity passed through.
  * proj nullable: the records darb_preprocess wrote for the same camera and
  * splats; when proj->dcolor and proj->clamped are set, the colour part of the
- * chain uses them (the SH coefficients are not read), else it recomputes the
- * colour from the SH coefficients.  Both give the same gradients up to FP32
- * rounding.
+ * chain uses them (the SH coefficients are not read) and the splats with
+ * proj->radius 0 (culled by that forward) get zero gradients without reading
+ * their inputs; else it recomputes the colour from the SH coefficients.  Both
+ * give the same gradients up to FP32 rounding.
  * accumulate = 0: g3d is overwritten for every splat (zeros for culled splats);
  * accumulate = 1: the gradients are added to g3d (several views in turn).
  */

@@ -773,6 +773,7 @@ __device__ __forceinline__ void store_grads(const darb_grads3d &g3, int n, int i
 struct Ckpt {
     const float *dcolor;
     const uint8_t *clamped;
+    const int32_t *radius;  // kept iff radius > 0
 };
 
 template <int DEG, bool CKPT>
@@ -781,52 +782,58 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(Cam cam, KParams kp, int
     constexpr int NB = (DEG + 1) * (DEG + 1);
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    // parameters, incoming gradients and the colour checkpoint are loaded
-    // together, one memory round trip before the projection (a culled splat's
-    // gradients are read and not used)
-    float m[3];
-    load_mean(in, n, i, m);
-    const QS qs = load_qs(in, n, i);
-    const G2v gin = load_g2(g2, i);
-    float jac[9];
-    uint8_t cl = 0;
-    if constexpr (CKPT) {
-#pragma unroll
-        for (int k = 0; k < 9; k++) jac[k] = ck.dcolor[(size_t)k * n + i];
-        cl = ck.clamped[i];
-    }
-    pin_geometry(m, qs);
-    pin(gin.xy[0]); pin(gin.xy[1]); pin(gin.conic[0]); pin(gin.conic[1]); pin(gin.conic[2]); pin(gin.op);
-    pin(gin.rgb[0]); pin(gin.rgb[1]); pin(gin.rgb[2]);
-    if constexpr (CKPT) {
-#pragma unroll
-        for (int k = 0; k < 9; k++) pin(jac[k]);
-        pin(__uint_as_float((uint32_t)cl));
-    }
-    Geom G;
-    Proj P;
-    const bool vis = view_depth(cam, m, P) && splat_geom_of(qs, G) && project_rest(cam, kp, G, P);
     Grad3 g = {};
     float gsh[NB][3];
 #pragma unroll
     for (int b = 0; b < NB; b++) gsh[b][0] = gsh[b][1] = gsh[b][2] = 0.0f;
-    if (vis) {
-        float Y[NB], gv[3], dmu_sh[3];
+    // with the checkpoint the forward's radius tells the culled splats (zero
+    // gradient), which then load nothing else
+    bool kept = true;
+    if constexpr (CKPT) kept = ck.radius[i] > 0;
+    if (kept) {
+        // parameters, incoming gradients and the colour checkpoint are loaded
+        // together, one memory round trip before the projection
+        float m[3];
+        load_mean(in, n, i, m);
+        const QS qs = load_qs(in, n, i);
+        const G2v gin = load_g2(g2, i);
+        float jac[9];
+        uint8_t cl = 0;
         if constexpr (CKPT) {
-            colour_bwd_ckpt<NB>(cam, m, cl, jac, gin.rgb, Y, gv, dmu_sh);
-        } else {
-            float csh[NB][3];
-            load_sh<NB>(in.sh, n, i, csh);
-            colour_bwd_sh<NB>(cam, m, csh, gin.rgb, Y, gv, dmu_sh);
+#pragma unroll
+            for (int k = 0; k < 9; k++) jac[k] = ck.dcolor[(size_t)k * n + i];
+            cl = ck.clamped[i];
         }
-        Geom64 G64;
-        splat_geom64(qs, G64);
-        splat_bwd_view(cam, kp, m, gin, G64, P, dmu_sh, g.dmu, g.dsc, g.dq);
-        g.dop = gin.op;
+        pin_geometry(m, qs);
+        pin(gin.xy[0]); pin(gin.xy[1]); pin(gin.conic[0]); pin(gin.conic[1]); pin(gin.conic[2]); pin(gin.op);
+        pin(gin.rgb[0]); pin(gin.rgb[1]); pin(gin.rgb[2]);
+        if constexpr (CKPT) {
 #pragma unroll
-        for (int b = 0; b < NB; b++)
+            for (int k = 0; k < 9; k++) pin(jac[k]);
+            pin(__uint_as_float((uint32_t)cl));
+        }
+        Geom G;
+        Proj P;
+        // the FP32 decisions of the forward (recomputed: the same expressions on the same inputs)
+        const bool vis = view_depth(cam, m, P) && splat_geom_of(qs, G) && project_rest(cam, kp, G, P);
+        if (vis) {
+            float Y[NB], gv[3], dmu_sh[3];
+            if constexpr (CKPT) {
+                colour_bwd_ckpt<NB>(cam, m, cl, jac, gin.rgb, Y, gv, dmu_sh);
+            } else {
+                float csh[NB][3];
+                load_sh<NB>(in.sh, n, i, csh);
+                colour_bwd_sh<NB>(cam, m, csh, gin.rgb, Y, gv, dmu_sh);
+            }
+            Geom64 G64;
+            splat_geom64(qs, G64);
+            splat_bwd_view(cam, kp, m, gin, G64, P, dmu_sh, g.dmu, g.dsc, g.dq);
+            g.dop = gin.op;
 #pragma unroll
-            for (int ch = 0; ch < 3; ch++) gsh[b][ch] = Y[b] * gv[ch];
+            for (int b = 0; b < NB; b++)
+#pragma unroll
+                for (int ch = 0; ch < 3; ch++) gsh[b][ch] = Y[b] * gv[ch];
+        }
     }
     store_grads<NB>(g3, n, i, g, gsh, accumulate != 0);
 }
@@ -974,8 +981,8 @@ hipError_t launch_preprocess_bwd(const Cam &cam, const KParams &kp, int n, const
     if (n == 0) return hipSuccess;
     dim3 grid((n + 255) / 256);
     const int acc = accumulate ? 1 : 0;
-    const Ckpt ck{ckpt ? ckpt->dcolor : nullptr, ckpt ? ckpt->clamped : nullptr};
-    if (ck.dcolor && ck.clamped) {
+    const Ckpt ck{ckpt ? ckpt->dcolor : nullptr, ckpt ? ckpt->clamped : nullptr, ckpt ? ckpt->radius : nullptr};
+    if (ck.dcolor && ck.clamped && ck.radius) {
         DARB_DEG_SWITCH_B(in.sh_degree, k_preprocess_bwd, true, grid, s, cam, kp, n, in, ck, g2d, g3d, acc)
     } else {
         DARB_DEG_SWITCH_B(in.sh_degree, k_preprocess_bwd, false, grid, s, cam, kp, n, in, ck, g2d, g3d, acc)
