@@ -441,11 +441,13 @@ __global__ __launch_bounds__(256) void k_preprocess_geom(Cam cam, KParams kp, in
 // Colour: the SH colour, clamp bits and colour checkpoint of the splats the
 // geometry part kept (radius > 0; a kept splat's radius is at least 1).  It is
 // meant to run beside the binning on a second stream, so it is launched with
-// one workgroup per compute unit looping over the splats: a full grid of
-// memory-bound waves would take the compute units from the latency-bound
-// binning kernels and slow them by about its own duration.
+// one two-wavefront workgroup per compute unit looping over the splats: a full
+// grid of memory-bound waves would take the compute units from the
+// latency-bound binning kernels and slow them by about its own duration.
+constexpr int kColourThreads = 128;
+
 template <int DEG>
-__global__ __launch_bounds__(256) void k_preprocess_colour(Cam cam, int n, darb_splats in, darb_projected out) {
+__global__ __launch_bounds__(kColourThreads) void k_preprocess_colour(Cam cam, int n, darb_splats in, darb_projected out) {
     constexpr int NB = (DEG + 1) * (DEG + 1);
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const bool vis = out.radius[i] > 0;
@@ -953,8 +955,14 @@ hipError_t launch_preprocess_parts(const Cam &cam, const KParams &kp, int n, con
                 hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
                 cus = 256;
         }
-        const dim3 gc(std::min<unsigned>(grid.x, (unsigned)cus));
-        DARB_DEG_SWITCH(in.sh_degree, k_preprocess_colour, gc, s, cam, n, in, out)
+        const dim3 gc(std::min<unsigned>((unsigned)((n + kColourThreads - 1) / kColourThreads), (unsigned)cus));
+        const dim3 bc(kColourThreads);
+        switch (in.sh_degree) {
+        case 0: hipLaunchKernelGGL(k_preprocess_colour<0>, gc, bc, 0, s, cam, n, in, out); break;
+        case 1: hipLaunchKernelGGL(k_preprocess_colour<1>, gc, bc, 0, s, cam, n, in, out); break;
+        case 2: hipLaunchKernelGGL(k_preprocess_colour<2>, gc, bc, 0, s, cam, n, in, out); break;
+        default: hipLaunchKernelGGL(k_preprocess_colour<3>, gc, bc, 0, s, cam, n, in, out); break;
+        }
     }
     return hipGetLastError();
 }
