@@ -34,11 +34,13 @@ class DarbRasterize(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_image):
         grads = None
+        zeroed = False
         if ctx.owner is not None:  # reuse the owner's 2D-gradient buffers; fresh 3D gradients (returned)
             n, deg = ctx.frame.n, ctx.splats["sh_degree"]
             grads = (ctx.owner.grads2d(n), pipeline.alloc_grads(n, deg, "cuda")[1])
+            zeroed = ctx.owner.take_cleared_grads2d()
         g2d, g3d = pipeline.render_backward(ctx.frame, grad_image.contiguous(), ctx.splats, ctx.cam, ctx.kernel,
-                                            ctx.opts, grads=grads)
+                                            ctx.opts, grads=grads, g2d_zeroed=zeroed)
         ctx.frame = None
         return (g3d["means"], g3d["scales"], g3d["quats"], g3d["opacity"], g3d["sh"], None, None, None, None, None)
 
@@ -57,7 +59,11 @@ class Rasterizer:
     """Differentiable renderer that keeps its device buffers between steps (one
     view size at a time): no allocation per step, and the instance count is
     read back only to check for a capacity overflow (then the list grows by
-    ``k_margin`` and the view is rendered again)."""
+    ``k_margin`` and the view is rendered again).  The forward runs the
+    preprocess's colour part on a second stream beside the binning and clears
+    the backward's 2D-gradient buffers in its raster kernel; the next backward
+    then skips its own clearing (only the first backward after a forward: a
+    second one finds the buffers used and clears them itself)."""
 
     def __init__(self, kernel="half_cos", opts: dict | None = None, k_margin: float = 1.1):
         self.kernel = pipeline.KERNELS[kernel] if isinstance(kernel, str) else kernel
@@ -65,24 +71,38 @@ class Rasterizer:
         self.k_margin = k_margin
         self.frame = None
         self._grads = None
+        self._cleared = False
+        self._side = None
 
     def render(self, splats: dict, cam: dict):
         n, W, H = int(splats["means"].shape[1]), int(cam["width"]), int(cam["height"])
         fr = self.frame
+        g2 = self.grads2d(n)
         if fr is None or (fr.n, fr.width, fr.height) != (n, W, H):
-            fr = self.frame = pipeline.render(splats, cam, self.kernel, self.opts, k_capacity=max(4 * n, 1 << 16))
+            fr = self.frame = pipeline.render(splats, cam, self.kernel, self.opts, k_capacity=max(4 * n, 1 << 16),
+                                              zero_g2d=g2)
+            self._cleared = True
             return fr
-        pipeline.render(splats, cam, self.kernel, self.opts, frame=fr, read_k=False)
+        if self._side is None:
+            self._side = torch.cuda.Stream()
+        pipeline.forward_overlapped(splats, cam, self.kernel, fr, self._side, self.opts, zero_g2d=g2)
         if int(fr.overflow[0].item()) != 0:  # too many instances: grow and render again
             K = int(fr.k_dev[0].item())
             pipeline._grow(fr, int(K * self.k_margin), fr.vals.device)
-            pipeline.render(splats, cam, self.kernel, self.opts, frame=fr, read_k=True)
+            pipeline.render(splats, cam, self.kernel, self.opts, frame=fr, read_k=True, zero_g2d=g2)
+        self._cleared = True
         return fr
 
     def grads2d(self, n: int):
         if self._grads is None or self._grads["opacity"].numel() != n:
             self._grads = pipeline.alloc_grads(n, 0, "cuda")[0]
+            self._cleared = False
         return self._grads
+
+    def take_cleared_grads2d(self) -> bool:
+        """True once after each forward: the 2D-gradient buffers are still zero."""
+        c, self._cleared = self._cleared, False
+        return c
 
     def __call__(self, means, scales, quats, opacity, sh, cam: dict, sh_degree: int | None = None):
         if sh_degree is None:
