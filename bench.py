@@ -33,6 +33,51 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measure_ceilings(reps: int = 5):
+    """Measured ceilings of this GPU (best of ``reps`` after a warm-up, HIP
+    events): a 1 GiB copy (2 GiB moved) and a 1 GiB fill -- the library's probes
+    and torch's elementwise kernels, the faster of the two -- and FMA chains in
+    FP32 (non-packed, as every kernel is built) and FP64 (the library's probe)."""
+    import torch
+
+    from paper_2501_12369_amd import native
+
+    def best(fn):
+        fn()
+        ts = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b) * 1e-3)
+        return min(ts)
+    n = 1 << 28  # floats: 1 GiB
+    src = torch.ones(n, device="cuda")
+    dst = torch.empty_like(src)
+    t_copy = best(lambda: native.darb_probe_copy(src, dst))
+    t_fill = best(lambda: native.darb_probe_fill(dst))
+    # torch's own elementwise kernels as a second opinion: the ceiling is the faster
+    t_neg = best(lambda: torch.neg(src, out=dst))
+    t_zero = best(lambda: dst.zero_())
+    del src, dst
+    lanes, iters = 1 << 21, 1024
+    out32 = torch.empty(lanes, device="cuda")
+    out64 = torch.empty(lanes, dtype=torch.float64, device="cuda")
+    chains = native.darb_probe_fma(out32, iters)
+    t32 = best(lambda: native.darb_probe_fma(out32, iters))
+    t64 = best(lambda: native.darb_probe_fma(out64, iters))
+    flops = 2.0 * chains * iters * lanes
+    props = torch.cuda.get_device_properties(0)
+    copy = dict(probe=round(8.0 * n / t_copy / 1e9, 1), torch_neg=round(8.0 * n / t_neg / 1e9, 1))
+    fill = dict(probe=round(4.0 * n / t_fill / 1e9, 1), torch_zero=round(4.0 * n / t_zero / 1e9, 1))
+    return dict(copy_gbs=max(copy.values()), fill_gbs=max(fill.values()), copy_detail=copy, fill_detail=fill,
+                fma32_tflops=round(flops / t32 / 1e12, 2), fma64_tflops=round(flops / t64 / 1e12, 2),
+                device=getattr(props, "name", ""), compute_units=int(props.multi_processor_count),
+                arch=getattr(props, "gcnArchName", ""))
+
+
 def stage_bytes(n, n_vis, split=False):
     """Algorithmic HBM bytes per launch of the single-kernel stages (one read of
     each needed input, one write of each output), per splat / per visible splat:
@@ -450,11 +495,22 @@ def main():
     dominant = max(STAGE_KERNEL, key=lambda st: per_stage[st])
     r = roof[dominant]
     traffic = measured_traffic(dominant)
+    # fractions against the spec peak and against this GPU's measured ceiling
+    # (the copy probe for an HBM-bound kernel, the FP32 FMA probe for an ALU-bound one)
+    ceilings = measure_ceilings()
+    log("measured ceilings: " + ", ".join(f"{k}={v}" for k, v in ceilings.items()))
+    measured_peak = ceilings["copy_gbs"] if r["bound"] == "hbm" else ceilings["fma32_tflops"]
     roofline = dict(bound=r["bound"], achieved=round(r["achieved"], 2), peak=r["peak"], unit=r["unit"],
                     frac=round(r["achieved"] / r["peak"], 4), traffic=traffic, kernel=STAGE_KERNEL[dominant][0],
-                    kernel_us=round(per_stage[dominant] * 1e3, 2), algorithmic_bytes=int(bytes_[dominant]))
+                    kernel_us=round(per_stage[dominant] * 1e3, 2), algorithmic_bytes=int(bytes_[dominant]),
+                    measured_peak=measured_peak, frac_of_measured=round(r["achieved"] / measured_peak, 4))
     log(f"dominant kernel {roofline['kernel']}: {roofline['kernel_us']} us, {roofline['achieved']} GB/s "
-        f"({roofline['frac']:.3f} of peak), traffic {traffic}")
+        f"({roofline['frac']:.3f} of peak, {roofline['frac_of_measured']:.3f} of the measured copy ceiling), "
+        f"traffic {traffic}")
+    stage_fracs = {k: dict(achieved=round(v["achieved"], 2), unit=v["unit"], frac_of_peak=round(v["achieved"] / v["peak"], 4),
+                           frac_of_measured=round(v["achieved"] / (ceilings["copy_gbs"] if v["bound"] == "hbm"
+                                                                   else ceilings["fma32_tflops"]), 4))
+                   for k, v in roof.items()}
 
     if args.calibrate_copy_mib > 0:
         # a plain elementwise copy of known size: what the HBM counters read for it
@@ -502,6 +558,8 @@ def main():
                    "stage_ms": {k: round(v, 4) for k, v in per_stage.items()},
                    "colour_side_stream_ms": round(colour_ms, 4) if overlap else None, "variants": variants},
         "roofline": roofline,
+        "measured_ceilings": ceilings,
+        "stage_rooflines": stage_fracs,
         "cpu_baseline": cpu,
         "multiview": multiview_stats,
         "serving": serving_stats,

@@ -473,6 +473,24 @@ DARB_API darb_status darb_raster_fwdbwd_multi(const darb_view *views, int32_t nv
 DARB_API darb_status darb_preprocess_bwd_multi(const darb_view *views, int32_t nv, const darb_kernel *kernel, int64_t n,
                                                const darb_splats *in, const darb_grads3d *g3d, void *stream);
 
+/*
+ * Calibration probes: kernels that compute nothing of the method and measure
+ * the ceilings the benchmark reports beside the published peaks.
+ *   darb_probe_copy  dst[i] = src[i] for n floats (n a multiple of 4; both
+ *                    16-byte aligned, not overlapping): 8 n bytes moved.
+ *   darb_probe_fill  dst[i] = 0 for n floats (same conditions): 4 n bytes written.
+ *   darb_probe_fma   `threads` lanes each run *chains (written back, currently 8)
+ *                    independent chains of `iters` fused multiply-adds in FP32
+ *                    (fp64 = 0, out holds threads floats) or FP64 (fp64 = 1, out
+ *                    holds threads doubles), built like every kernel here
+ *                    without packed FP32: 2 * chains * iters * threads flops.
+ * Sizes beyond the buffers are the caller's error; n, threads, iters >= 0.
+ */
+DARB_API darb_status darb_probe_copy(const float *src, float *dst, int64_t n, void *stream);
+DARB_API darb_status darb_probe_fill(float *dst, int64_t n, void *stream);
+DARB_API darb_status darb_probe_fma(void *out, int64_t threads, int32_t iters, int32_t fp64, int32_t *chains,
+                                    void *stream);
+
 #ifdef __cplusplus
 }
 #endif

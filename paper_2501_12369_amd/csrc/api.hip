@@ -9,6 +9,17 @@
 
 #include "common.h"
 
+// Calibration probes (probe.hip): copy and fill of n floats (n a multiple of 4,
+// 16-byte aligned), FMA chains over `threads` lanes (probe_fma_chains() chains
+// of `iters` FMAs each per lane).
+namespace darb {
+int probe_fma_chains();
+hipError_t launch_probe_copy(const float *src, float *dst, int64_t n, hipStream_t s);
+hipError_t launch_probe_fill(float *dst, int64_t n, hipStream_t s);
+hipError_t launch_probe_fma32(float *out, int64_t threads, int iters, hipStream_t s);
+hipError_t launch_probe_fma64(double *out, int64_t threads, int iters, hipStream_t s);
+}  // namespace darb
+
 namespace {
 
 thread_local char g_err[512] = "";
@@ -587,6 +598,39 @@ darb_status darb_densify_stats(const darb_grads2d *g2d, const int32_t *radius, i
     return hip_status(darb::launch_densify_stats(*g2d, radius, (int)n, grad_accum, count, max_radius,
                                                  (hipStream_t)stream),
                       "darb_densify_stats");
+}
+
+darb_status darb_probe_copy(const float *src, float *dst, int64_t n, void *stream) {
+    TRY(check_n(n));
+    if (n % 4 != 0) return fail(DARB_ERR_INVALID_ARG, "%s", "n must be a multiple of 4");
+    if (n > 0) {
+        REQUIRE_PTR(src);
+        REQUIRE_PTR(dst);
+    }
+    g_err[0] = 0;
+    return hip_status(darb::launch_probe_copy(src, dst, n, (hipStream_t)stream), "darb_probe_copy");
+}
+
+darb_status darb_probe_fill(float *dst, int64_t n, void *stream) {
+    TRY(check_n(n));
+    if (n % 4 != 0) return fail(DARB_ERR_INVALID_ARG, "%s", "n must be a multiple of 4");
+    if (n > 0) REQUIRE_PTR(dst);
+    g_err[0] = 0;
+    return hip_status(darb::launch_probe_fill(dst, n, (hipStream_t)stream), "darb_probe_fill");
+}
+
+darb_status darb_probe_fma(void *out, int64_t threads, int32_t iters, int32_t fp64, int32_t *chains, void *stream) {
+    TRY(check_n(threads));
+    if (iters < 0) return fail(DARB_ERR_INVALID_ARG, "%s", "iters must be >= 0");
+    if (threads > 0) REQUIRE_PTR(out);
+    if (chains) *chains = darb::probe_fma_chains();
+    g_err[0] = 0;
+    if (fp64)
+        return hip_status(darb::launch_probe_fma64(static_cast<double *>(out), threads, (int)iters,
+                                                   (hipStream_t)stream),
+                          "darb_probe_fma");
+    return hip_status(darb::launch_probe_fma32(static_cast<float *>(out), threads, (int)iters, (hipStream_t)stream),
+                      "darb_probe_fma");
 }
 
 darb_status darb_preprocess_multi(const darb_view *views, int32_t nv, const darb_kernel *kernel, int64_t n,

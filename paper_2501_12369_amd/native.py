@@ -28,7 +28,7 @@ EXPORTED = ("darb_version", "darb_status_string", "darb_last_error", "darb_prepr
             "darb_raster_bwd_workspace", "darb_preprocess_bwd", "darb_image_loss", "darb_preprocess_multi",
             "darb_raster_fwd_multi", "darb_raster_bwd_multi", "darb_raster_bwd_multi_workspace",
             "darb_raster_fwdbwd_multi", "darb_preprocess_bwd_multi", "darb_ssim_loss_workspace", "darb_ssim_loss",
-            "darb_adam", "darb_densify_stats")
+            "darb_adam", "darb_densify_stats", "darb_probe_copy", "darb_probe_fill", "darb_probe_fma")
 MAX_ADAM_GROUPS = 8
 
 
@@ -128,6 +128,12 @@ def lib():
                                       c_int32, c_int64, c_void_p, c_size_t, c_void_p]
         L.darb_raster_bwd_workspace.restype = c_size_t
         L.darb_raster_bwd_workspace.argtypes = [c_int64, c_int32, c_int32, c_int64]
+        L.darb_probe_copy.restype = c_int32
+        L.darb_probe_copy.argtypes = [c_void_p, c_void_p, c_int64, c_void_p]
+        L.darb_probe_fill.restype = c_int32
+        L.darb_probe_fill.argtypes = [c_void_p, c_int64, c_void_p]
+        L.darb_probe_fma.restype = c_int32
+        L.darb_probe_fma.argtypes = [c_void_p, c_int64, c_int32, c_int32, P(c_int32), c_void_p]
         L.darb_preprocess_bwd.restype = c_int32
         L.darb_preprocess_bwd.argtypes = [P(darb_camera), P(darb_kernel), c_int64, P(darb_splats), P(darb_projected),
                                           P(darb_grads2d), P(darb_grads3d), c_int32, c_void_p]
@@ -443,3 +449,25 @@ def darb_densify_stats(g2d: dict, radius, n: int, grad_accum, count, max_radius=
     g = grads2d_struct(g2d)
     _check(lib().darb_densify_stats(ctypes.byref(g), _ptr(radius), n, _ptr(grad_accum), _ptr(count),
                                     _ptr(max_radius), _stream(stream)), "darb_densify_stats")
+
+
+# ---------------------------------------------------------------------------
+# Calibration probes (measured ceilings beside the published peaks).
+# ---------------------------------------------------------------------------
+
+def darb_probe_copy(src, dst, stream=None):
+    _check(lib().darb_probe_copy(_ptr(src), _ptr(dst), src.numel(), _stream(stream)), "darb_probe_copy")
+
+
+def darb_probe_fill(dst, stream=None):
+    _check(lib().darb_probe_fill(_ptr(dst), dst.numel(), _stream(stream)), "darb_probe_fill")
+
+
+def darb_probe_fma(out, iters: int, stream=None) -> int:
+    """FMA chains over out.numel() lanes (FP64 when out is float64); returns the
+    number of chains per lane."""
+    chains = c_int32(0)
+    _check(lib().darb_probe_fma(_ptr(out), out.numel(), int(iters), 1 if out.dtype == torch.float64 else 0,
+                                ctypes.byref(chains), _stream(stream)), "darb_probe_fma")
+    return int(chains.value)
+

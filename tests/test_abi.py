@@ -97,6 +97,12 @@ def test_multiview_and_loss_arguments_rejected_on_host(L):
     arr = (native.darb_view * 17)()
     for i in range(17):
         arr[i] = _view(native)
+    # calibration probes: sizes that are not whole float4 runs, negative counts
+    assert L.darb_probe_copy(None, None, 6, None) == native.DARB_ERR_INVALID_ARG
+    assert L.darb_probe_fill(None, -4, None) == native.DARB_ERR_INVALID_ARG
+    ch = native.c_int32(0)
+    assert L.darb_probe_fma(None, 8, -1, 0, ctypes.byref(ch), None) == native.DARB_ERR_INVALID_ARG
+    assert L.darb_probe_fma(None, 8, 4, 0, ctypes.byref(ch), None) == native.DARB_ERR_INVALID_ARG  # null out
     # preprocess parts outside {1, 2, 3}
     for parts in (0, 4, -1):
         st = L.darb_preprocess_parts(None, ctypes.byref(k), 0, ctypes.byref(sp), None, parts, None)
