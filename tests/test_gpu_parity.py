@@ -247,6 +247,24 @@ def _splats_dev(sp):
     return pipeline.splats_to_device(sp)
 
 
+@pytest.mark.parametrize("n", [0, 1, 37, 257])
+def test_preprocess_parts_small(n):
+    """Ragged and empty sizes through the two parts (the colour part loops with
+    one workgroup per CU): the one-kernel call's bits, and n = 0 is a no-op."""
+    sc = scenes.object_scale(seed=11, n=max(n, 1), width=320, height=240)
+    sp, cam = sc["splats"], sc["camera"]
+    spd = _splats_dev({k: (v[..., :n] if k != "sh_degree" else v) for k, v in sp.items()})
+    print(f"preprocess parts n={n}", flush=True)
+    k = pipeline.KERNELS["gauss"]
+    one, two = pipeline.alloc_projected(n), pipeline.alloc_projected(n)
+    native.darb_preprocess(cam, k, n, spd, one)
+    native.darb_preprocess(cam, k, n, spd, two, parts=native.PRE_GEOMETRY)
+    native.darb_preprocess(cam, k, n, spd, two, parts=native.PRE_COLOUR)
+    torch.cuda.synchronize()
+    for name in one:
+        assert np.array_equal(to_np(one[name]), to_np(two[name])), name
+
+
 @pytest.mark.parametrize("deg", [3, 1])
 def test_preprocess_parts_bits(deg):
     """The geometry and colour parts (the colour on a second stream after an
