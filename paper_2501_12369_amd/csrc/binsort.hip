@@ -85,13 +85,14 @@ __device__ __forceinline__ uint32_t live_count(const uint32_t *count_dev, uint32
     return count_dev ? min(*count_dev, max_count) : max_count;
 }
 
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *lds_w, uint32_t *total) {
+template <int T>
+__device__ __forceinline__ uint32_t block_excl_scan_n(uint32_t v, uint32_t *lds_w, uint32_t *total) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint32_t inc = wave_incl_scan(v);
     if (lane == 63) lds_w[w] = inc;
     __syncthreads();
     uint32_t woff = 0, tot = 0;
-    for (int i = 0; i < kScanThreads / 64; i++) {
+    for (int i = 0; i < T / 64; i++) {
         uint32_t x = lds_w[i];
         if (i < w) woff += x;
         tot += x;
@@ -99,6 +100,10 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *lds_w,
     __syncthreads();
     *total = tot;
     return woff + inc - v;
+}
+
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *lds_w, uint32_t *total) {
+    return block_excl_scan_n<kScanThreads>(v, lds_w, total);
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t *in, const uint32_t *count_dev,
@@ -202,20 +207,23 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const uint32_t *ke
     hist[threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];  // digit-major
 }
 
-// Row-wise exclusive scan, in place, one workgroup per row: rows of `len`
-// counts stored back to back (len from the device when len_dev is set), the
-// row's total to totals[row].  Used where a count array is row-major over a
+// Row-wise exclusive scan, in place, one workgroup of T threads per row: rows of
+// `len` counts stored back to back (len from the device when len_dev is set),
+// the row's total to totals[row].  Long rows (the level-1 chunk counts) take
+// T = 1024, so that a row is one round of loads, one scan and one round of
+// stores.  Used where a count array is row-major over a
 // small number of rows (radix digits, super-tiles) and its consumer adds the
 // row's start (a scan over the few totals) itself, instead of one scan over
 // all entries.
-__global__ __launch_bounds__(kScanThreads) void k_rowscan(uint32_t *data, const uint32_t *len_dev, uint32_t len_host,
-                                                          uint32_t *totals, const int32_t *skip) {
-    __shared__ uint32_t lw[kScanThreads / 64];
+template <int T>
+__global__ __launch_bounds__(T) void k_rowscan(uint32_t *data, const uint32_t *len_dev, uint32_t len_host,
+                                               uint32_t *totals, const int32_t *skip) {
+    __shared__ uint32_t lw[T / 64];
     if (*skip) return;
     const int nblk = (int)(len_dev ? *len_dev : len_host);
     uint32_t *row = data + (size_t)blockIdx.x * nblk;
     uint32_t carry = 0;
-    for (int base = 0; base < nblk; base += kScanBlock) {
+    for (int base = 0; base < nblk; base += T * kScanItems) {
         const int b0 = base + threadIdx.x * kScanItems;
         uint32_t v[kScanItems], sum = 0;
 #pragma unroll
@@ -224,7 +232,7 @@ __global__ __launch_bounds__(kScanThreads) void k_rowscan(uint32_t *data, const 
             sum += v[k];
         }
         uint32_t tot;
-        uint32_t off = carry + block_excl_scan(sum, lw, &tot);
+        uint32_t off = carry + block_excl_scan_n<T>(sum, lw, &tot);
 #pragma unroll
         for (int k = 0; k < kScanItems; k++) {
             if (b0 + k < nblk) row[b0 + k] = off;
@@ -1015,7 +1023,7 @@ hipError_t radix_sort_pairs(uint32_t *kA, uint32_t *vA, uint32_t *kB, uint32_t *
     uint32_t *ki = kA, *vi = vA, *ko = kB, *vo = vB;
     for (int shift = 0; shift < bits; shift += 8) {
         hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kRadixThreads), 0, s, ki, count_dev, shift, hist, nblk, skip);
-        hipLaunchKernelGGL(k_rowscan, dim3(256), dim3(kScanThreads), 0, s, hist, nullptr, (uint32_t)nblk,
+        hipLaunchKernelGGL(k_rowscan<kScanThreads>, dim3(256), dim3(kScanThreads), 0, s, hist, nullptr, (uint32_t)nblk,
                            hist + (size_t)256 * nblk, skip);
         hipLaunchKernelGGL(k_radix_scatter<false>, dim3(nblk), dim3(kRadixThreads), 0, s, ki, vi, ko, vo, count_dev,
                            shift, hist, nblk, skip, nullptr, nullptr, nullptr);
@@ -1069,7 +1077,7 @@ hipError_t launch_bin_sort(const darb_projected &p, int n, int width, int height
         for (int shift = 0; shift < 32; shift += 8) {
             hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kRadixThreads), 0, s, ki, nvis, shift, hist, nblk,
                                overflow_dev);
-            hipLaunchKernelGGL(k_rowscan, dim3(256), dim3(kScanThreads), 0, s, hist, nullptr, (uint32_t)nblk,
+            hipLaunchKernelGGL(k_rowscan<kScanThreads>, dim3(256), dim3(kScanThreads), 0, s, hist, nullptr, (uint32_t)nblk,
                                hist + (size_t)256 * nblk, overflow_dev);
             if (shift < 24)
                 hipLaunchKernelGGL(k_radix_scatter<false>, dim3(nblk), dim3(kRadixThreads), 0, s, ki, vi, ko, vo, nvis,
@@ -1086,7 +1094,7 @@ hipError_t launch_bin_sort(const darb_projected &p, int n, int width, int height
                            overflow_dev);
     }
     // the level-1 lists' lengths (zeros when nothing is visible: rows of length c1 = 0)
-    hipLaunchKernelGGL(k_rowscan, dim3(nsuper), dim3(kScanThreads), 0, s, h1, &cnt->c1, 0u, gtot, overflow_dev);
+    hipLaunchKernelGGL(k_rowscan<1024>, dim3(nsuper), dim3(1024), 0, s, h1, &cnt->c1, 0u, gtot, overflow_dev);
     if (n > 0) {
         const int c1max = (n + kL1Threads - 1) / kL1Threads;
         const size_t lds1 = (size_t)nsuper * 4;
