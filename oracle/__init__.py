@@ -27,6 +27,8 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _SRC = os.path.join(_HERE, "oracle.c")
 
 GAUSS, HALF_COS, RAISED_COS, SINC, IMQ, IMQ_SQRT, PARABOLA = range(7)
+# Table 1's modified forms with a generic roll-off beta (u = d_M^beta / xi)
+GAUSS_BETA, HALF_COS_BETA, RAISED_COS_BETA, SINC_BETA = range(7, 11)
 LOSS_L1, LOSS_L2 = 0, 1
 
 
@@ -50,7 +52,7 @@ class Camera(ctypes.Structure):
 
 class Kernel(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("xi", ctypes.c_double), ("psi", ctypes.c_double),
-                ("e_max", ctypes.c_double)]
+                ("e_max", ctypes.c_double), ("beta", ctypes.c_double)]
 
 
 class Opts(ctypes.Structure):
@@ -72,6 +74,11 @@ def lib():
         L.orc_kernel_value.argtypes = [i32, d, d]
         L.orc_kernel_deriv.restype = d
         L.orc_kernel_deriv.argtypes = [i32, d, d]
+        L.orc_kernel_value_beta.restype = d
+        L.orc_kernel_value_beta.argtypes = [i32, d, d, d]
+        L.orc_kernel_deriv_beta.restype = d
+        L.orc_kernel_deriv_beta.argtypes = [i32, d, d, d]
+        L.orc_kernel_values.argtypes = [i32, d, d, i64, vp, vp]
         L.orc_sh_basis.argtypes = [vp, vp, vp]
         L.orc_quat_to_rot.argtypes = [vp, vp]
         L.orc_preprocess.argtypes = [vp, vp, i64, vp, vp, vp, vp, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -110,9 +117,10 @@ class KernelSpec:
     xi: float
     psi: float
     e_max: float
+    beta: float = 0.0  # roll-off of the modified forms (kinds GAUSS_BETA..SINC_BETA)
 
     def c(self) -> Kernel:
-        return Kernel(self.kind, self.xi, self.psi, self.e_max)
+        return Kernel(self.kind, self.xi, self.psi, self.e_max, self.beta)
 
 
 def make_camera(viewmat, campos, fx, fy, cx, cy, width, height, near_z=0.2, jac_clamp=1.3, dilation=0.3) -> Camera:
@@ -149,16 +157,24 @@ def camera_from_scene(cam: dict) -> Camera:
 # wrappers
 # --------------------------------------------------------------------------
 
-def kernel_value(kind: int, xi: float, E) -> np.ndarray:
+def kernel_value(kind: int, xi: float, E, beta: float = 0.0) -> np.ndarray:
     L = lib()
     E = np.atleast_1d(np.asarray(E, dtype=np.float64))
-    return np.array([L.orc_kernel_value(kind, xi, float(e)) for e in E])
+    return np.array([L.orc_kernel_value_beta(kind, xi, beta, float(e)) for e in E])
 
 
-def kernel_deriv(kind: int, xi: float, E) -> np.ndarray:
+def kernel_deriv(kind: int, xi: float, E, beta: float = 0.0) -> np.ndarray:
     L = lib()
     E = np.atleast_1d(np.asarray(E, dtype=np.float64))
-    return np.array([L.orc_kernel_deriv(kind, xi, float(e)) for e in E])
+    return np.array([L.orc_kernel_deriv_beta(kind, xi, beta, float(e)) for e in E])
+
+
+def kernel_values(kind: int, xi: float, E, beta: float = 0.0) -> np.ndarray:
+    """F at every entry of the array E (same shape)."""
+    E = _f64(E)
+    out = np.empty_like(E)
+    lib().orc_kernel_values(kind, xi, beta, E.size, _p(E), _p(out))
+    return out
 
 
 def sh_basis(d):

@@ -34,6 +34,11 @@
 #define ORC_IMQ 4      /* 1 / (E/xi + 1)        (supplementary IMQ section)   */
 #define ORC_IMQ_SQRT 5 /* 1 / sqrt(E/xi + 1)    (Table 1, inverse multiquadric) */
 #define ORC_PARABOLA 6
+/* Table 1's "modified" forms with a generic roll-off beta, u = d_M^beta / xi = E^(beta/2) / xi */
+#define ORC_GAUSS_BETA 7      /* exp(-u)                                                */
+#define ORC_HALF_COS_BETA 8   /* cos(u),            main lobe u <= pi/2                 */
+#define ORC_RAISED_COS_BETA 9 /* 0.5 + 0.5 cos(u),  n pulses: u <= n pi                 */
+#define ORC_SINC_BETA 10      /* |sin(u)| / u,      n pulses: u <= (n + 1) pi / 2       */
 
 typedef struct {
     double viewmat[16]; /* world -> camera, row-major 4x4 */
@@ -50,6 +55,7 @@ typedef struct {
     double xi;    /* scaling factor xi of Table 1 / Table 2 */
     double psi;   /* correction factor psi of Eq. (2x2 covariance projection) */
     double e_max; /* support limit on E = d_M^2 (boundaries of DARBFs) */
+    double beta;  /* roll-off of the modified forms (kinds 7..10); unused otherwise */
 } orc_kernel;
 
 typedef struct {
@@ -129,6 +135,64 @@ double orc_kernel_deriv(int32_t kind, double xi, double E) {
     default:
         return NAN;
     }
+}
+
+/* Modified forms of Table 1 with a generic roll-off beta: with d_M = sqrt(E),
+ * u = d_M^beta / xi.  dF/dE = dF/du * du/dE, du/dE = (beta/2) u / E for E > 0.
+ * At E = 0 the limit of du/dE is 1/xi for beta = 2 and 0 for beta > 2; for
+ * beta < 2 it diverges while every gradient it feeds (dE/d mu' = 2 Q d,
+ * dE/dQ = d d^T) vanishes at least as fast, so the derivative is taken as 0
+ * there. */
+static double modified_u(double xi, double beta, double E) { return pow(E, 0.5 * beta) / xi; }
+
+double orc_kernel_value_beta(int32_t kind, double xi, double beta, double E) {
+    if (kind < ORC_GAUSS_BETA) return orc_kernel_value(kind, xi, E);
+    double u = modified_u(xi, beta, E);
+    switch (kind) {
+    case ORC_GAUSS_BETA:
+        return exp(-u);
+    case ORC_HALF_COS_BETA:
+        return cos(u);
+    case ORC_RAISED_COS_BETA:
+        return 0.5 + 0.5 * cos(u);
+    case ORC_SINC_BETA:
+        return fabs(sinc_u(u));
+    default:
+        return NAN;
+    }
+}
+
+double orc_kernel_deriv_beta(int32_t kind, double xi, double beta, double E) {
+    if (kind < ORC_GAUSS_BETA) return orc_kernel_deriv(kind, xi, E);
+    double u = modified_u(xi, beta, E);
+    double du = E > 0.0 ? 0.5 * beta * u / E : (beta == 2.0 ? 1.0 / xi : 0.0);
+    double dF; /* dF/du */
+    switch (kind) {
+    case ORC_GAUSS_BETA:
+        dF = -exp(-u);
+        break;
+    case ORC_HALF_COS_BETA:
+        dF = -sin(u);
+        break;
+    case ORC_RAISED_COS_BETA:
+        dF = -0.5 * sin(u);
+        break;
+    case ORC_SINC_BETA: {
+        /* F = |sin u| / u: dF/du = sgn(sin u) (u cos u - sin u) / u^2 */
+        double g = u < 1e-3 ? -u / 3.0 + u * u * u / 30.0 : (u * cos(u) - sin(u)) / (u * u);
+        dF = (u < 1e-3 || sin(u) >= 0.0) ? g : -g;
+        break;
+    }
+    default:
+        return NAN;
+    }
+    return dF * du;
+}
+
+/* F at n values of E (vectorised for the correction-factor experiment) */
+void orc_kernel_values(int32_t kind, double xi, double beta, long n, const double *E, double *out) {
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < n; i++) out[i] = orc_kernel_value_beta(kind, xi, beta, E[i]);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -328,11 +392,13 @@ static void project_one(const orc_camera *cam, const orc_kernel *k, long n, long
     s->xy[1] = cam->fy * s->t[1] / tz + cam->cy;
     s->depth = tz;
 
-    /* R = ceil(3 sqrt(lambda_max)) of the 2D covariance */
+    /* R = ceil(3 sqrt(lambda_max)) of the 2D covariance; a support beyond
+     * E = 9 (several pulses) widens the box to ceil(sqrt(e_max lambda_max)) */
     double mid = 0.5 * (s->cov[0] + s->cov[3]);
     double disc = mid * mid - s->det;
     double lam = mid + sqrt(disc > 0.0 ? disc : 0.0);
-    s->radius = (int)ceil(3.0 * sqrt(lam));
+    double rf = k->e_max > 9.0 ? sqrt(k->e_max) : 3.0;
+    s->radius = (int)ceil(rf * sqrt(lam));
 
     /* bounding rectangle on the 16x16 tile grid; empty => not visible */
     int gx = (cam->width + 15) / 16, gy = (cam->height + 15) / 16;
@@ -543,7 +609,7 @@ static long composite_pixel(const comp_ctx *c, int px, int py, double out[3], do
     for (long t = 0; t < m; t++) {
         long j = v[t].id;
         double E = v[t].E;
-        double w = orc_kernel_value(k->kind, k->xi, E);
+        double w = orc_kernel_value_beta(k->kind, k->xi, k->beta, E);
         double a = c->opac[j] * w;
         if (a > o->alpha_max) a = o->alpha_max;
         /* decision margins: support cut (only if it changes the outcome), alpha cut */
@@ -600,7 +666,7 @@ static double outside_margin(const comp_ctx *c, int px, int py) {
         if (!(E > c->k->e_max)) continue;
         double me = rel_margin(E, c->k->e_max);
         if (me > 1e-2) continue;
-        double w = orc_kernel_value(c->k->kind, c->k->xi, c->k->e_max);
+        double w = orc_kernel_value_beta(c->k->kind, c->k->xi, c->k->beta, c->k->e_max);
         double a = c->opac[j] * w;
         if (a >= c->o->alpha_min * (1.0 - 1e-3) && me < mg) mg = me;
     }
@@ -685,7 +751,7 @@ void orc_composite_bwd(long n, const double *xy, const double *conic, const doub
             double dx = xy[2 * j] - px, dy = xy[2 * j + 1] - py;
             const double *q = conic + 3 * j;
             /* alpha = min(alpha_max, o w): gradient passed straight through the clamp */
-            double dE = opac[j] * orc_kernel_deriv(k->kind, k->xi, r[t].E) * dalpha;
+            double dE = opac[j] * orc_kernel_deriv_beta(k->kind, k->xi, k->beta, r[t].E) * dalpha;
             double *pt = part + 9 * t;
             pt[0] = dE * 2.0 * (q[0] * dx + q[1] * dy);
             pt[1] = dE * 2.0 * (q[1] * dx + q[2] * dy);
@@ -865,13 +931,19 @@ static int clamp_tile(float v, int hi) {
  * evaluated in FP32; one entry per covered tile with key (tile << 32) | bits(depth)
  * and value = splat index.  Entries are ordered by (key, index).  ranges[t] =
  * (#entries with tile < t, #entries with tile <= t).  Returns K; keys/vals are
- * written only when K <= cap.
+ * written only when vals is given and K <= cap (ranges need no sort).
+ *
+ * The order is produced by a sort on (key, index); the entries are first
+ * grouped by tile (the high half of the key) and each tile's group is then
+ * sorted on its own, which is the same total order.
  */
 long orc_bin(long n, const float *xy, const int32_t *radius, const float *depth, int width, int height, long cap,
              uint64_t *keys, uint32_t *vals, uint32_t *ranges) {
     int gx = (width + 15) / 16, gy = (height + 15) / 16;
+    long ntile = (long)gx * gy;
     long K = 0;
     int *rect = (int *)malloc(sizeof(int) * 4 * (n > 0 ? n : 1));
+    long *cnt = (long *)calloc(ntile + 1, sizeof(long));
     for (long i = 0; i < n; i++) {
         rect[4 * i] = rect[4 * i + 1] = rect[4 * i + 2] = rect[4 * i + 3] = 0;
         if (radius[i] <= 0) continue;
@@ -881,36 +953,39 @@ long orc_bin(long n, const float *xy, const int32_t *radius, const float *depth,
         rect[4 * i + 2] = clamp_tile(floorf((v - r) * 0.0625f), gy);
         rect[4 * i + 3] = clamp_tile(floorf((v + r) * 0.0625f) + 1.0f, gy);
         long w = rect[4 * i + 1] - rect[4 * i], h = rect[4 * i + 3] - rect[4 * i + 2];
-        if (w > 0 && h > 0) K += w * h;
-    }
-    bin_entry *e = (bin_entry *)malloc(sizeof(bin_entry) * (K > 0 ? K : 1));
-    long m = 0;
-    for (long i = 0; i < n; i++) {
-        uint32_t db;
-        memcpy(&db, &depth[i], 4);
+        if (w <= 0 || h <= 0) continue;
+        K += w * h;
         for (int ty = rect[4 * i + 2]; ty < rect[4 * i + 3]; ty++)
-            for (int tx = rect[4 * i]; tx < rect[4 * i + 1]; tx++) {
-                e[m].key = ((uint64_t)(ty * gx + tx) << 32) | db;
-                e[m].id = (uint32_t)i;
-                m++;
-            }
+            for (int tx = rect[4 * i]; tx < rect[4 * i + 1]; tx++) cnt[(long)ty * gx + tx + 1]++;
     }
-    qsort(e, m, sizeof(bin_entry), bin_cmp);
-    long ntile = (long)gx * gy;
-    for (long t = 0; t < ntile; t++) { ranges[2 * t] = 0; ranges[2 * t + 1] = 0; }
-    /* ranges from counts */
-    long *cnt = (long *)calloc(ntile + 1, sizeof(long));
-    for (long t = 0; t < m; t++) cnt[(e[t].key >> 32) + 1]++;
+    /* ranges from the per-tile counts */
     for (long t = 0; t < ntile; t++) cnt[t + 1] += cnt[t];
     for (long t = 0; t < ntile; t++) { ranges[2 * t] = (uint32_t)cnt[t]; ranges[2 * t + 1] = (uint32_t)cnt[t + 1]; }
-    if (K <= cap) {
-        for (long t = 0; t < m; t++) {
+    if (vals && K <= cap && K > 0) {
+        bin_entry *e = (bin_entry *)malloc(sizeof(bin_entry) * K);
+        long *pos = (long *)malloc(sizeof(long) * (ntile > 0 ? ntile : 1));
+        for (long t = 0; t < ntile; t++) pos[t] = cnt[t];
+        for (long i = 0; i < n; i++) {
+            uint32_t db;
+            memcpy(&db, &depth[i], 4);
+            for (int ty = rect[4 * i + 2]; ty < rect[4 * i + 3]; ty++)
+                for (int tx = rect[4 * i]; tx < rect[4 * i + 1]; tx++) {
+                    long t = (long)ty * gx + tx;
+                    e[pos[t]].key = ((uint64_t)t << 32) | db;
+                    e[pos[t]].id = (uint32_t)i;
+                    pos[t]++;
+                }
+        }
+#pragma omp parallel for schedule(dynamic, 16)
+        for (long t = 0; t < ntile; t++) qsort(e + cnt[t], cnt[t + 1] - cnt[t], sizeof(bin_entry), bin_cmp);
+        for (long t = 0; t < K; t++) {
             if (keys) keys[t] = e[t].key;
             vals[t] = e[t].id;
         }
+        free(pos);
+        free(e);
     }
     free(cnt);
-    free(e);
     free(rect);
     return K;
 }

@@ -181,7 +181,7 @@ def multiview_cameras(seed: int, n_views: int = 8) -> list:
 # --------------------------------------------------------------------------
 
 def projected(seed: int, n: int, width: int, height: int, sigma_range=(0.5, 12.0), opacity_range=(0.05, 0.99),
-              margin: float = 20.0, depth_range=(1.0, 20.0), culled_frac: float = 0.1) -> dict:
+              margin: float = 20.0, depth_range=(1.0, 20.0), culled_frac: float = 0.1, e_max: float = 9.0) -> dict:
     """Random screen-space splats: centre uniform over the image grown by ``margin``,
     footprint std-devs log-uniform in ``sigma_range`` pixels with a random
     orientation, depth uniform, opacity uniform, colour uniform in [0, 1].
@@ -189,7 +189,8 @@ def projected(seed: int, n: int, width: int, height: int, sigma_range=(0.5, 12.0
     The conic is the inverse of the drawn covariance R diag(s1^2, s2^2) R^T,
     stored as (a, b, c, opacity); ``conic_l`` holds its upper-triangular
     factor (l00, l01, l11), Q = L^T L.  ``radius`` is ceil(3 * max(s1, s2)) + 1
-    pixels, a bound on the support E <= 9 of every kernel; a fraction
+    pixels, a bound on the support E <= 9 of the one-lobe kernels (with a
+    larger support ``e_max``: sqrt(e_max) instead of 3); a fraction
     ``culled_frac`` of splats get radius 0 (culled)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     x = rng.uniform(-margin, width + margin, size=n)
@@ -206,7 +207,7 @@ def projected(seed: int, n: int, width: int, height: int, sigma_range=(0.5, 12.0
     opacity = rng.uniform(opacity_range[0], opacity_range[1], size=n)
     rgb = rng.uniform(0.0, 1.0, size=(n, 3))
     depth = rng.uniform(depth_range[0], depth_range[1], size=n)
-    radius = (np.ceil(3.0 * np.maximum(s1, s2)) + 1).astype(np.int32)
+    radius = (np.ceil(math.sqrt(max(9.0, e_max)) * np.maximum(s1, s2)) + 1).astype(np.int32)
     radius[rng.uniform(size=n) < culled_frac] = 0
     l00 = np.sqrt(qa)
     l01 = qb / l00
@@ -236,3 +237,19 @@ def upstream_grad(seed: int, width: int, height: int, kind: str = "normal", spar
     G = G * mask.reshape(1, height, width)
     ys, xs = np.divmod(np.sort(idx), width)
     return G.astype(np.float32), np.stack([xs, ys], 1).astype(np.int32)
+
+
+def covariances(seed: int, m: int, scale_range=(0.5, 2.0)) -> np.ndarray:
+    """m random 3D covariances R diag(s^2) R^T of the scale-and-rotation form
+    splats use (random rotation, per-axis scales log-uniform in ``scale_range``),
+    as [m, 6] FP64 rows (xx, xy, xz, yy, yz, zz)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = np.zeros((m, 6))
+    for i in range(m):
+        a = rng.standard_normal((3, 3))
+        q, r = np.linalg.qr(a)
+        q *= np.sign(np.diag(r))
+        s = np.exp(rng.uniform(math.log(scale_range[0]), math.log(scale_range[1]), 3))
+        S = (q * s ** 2) @ q.T
+        out[i] = [S[0, 0], S[0, 1], S[0, 2], S[1, 1], S[1, 2], S[2, 2]]
+    return out

@@ -162,3 +162,73 @@ def test_psi_marginal_by_simpson_matches_closed_form(orc):
     ratio = cov / Sigma[:2, :2]
     c = psimod.psi_closed_form(kind, xi, e_max)
     assert np.allclose(ratio, c, rtol=0.01)
+
+
+# ---------------------------------------------------------------- modified forms (Table 1, generic beta)
+
+MODIFIED = {  # modified kind -> the fixed kind it reduces to, and that kind's beta
+    oracle.GAUSS_BETA: (oracle.GAUSS, 2.0),
+    oracle.HALF_COS_BETA: (oracle.HALF_COS, 2.0),
+    oracle.RAISED_COS_BETA: (oracle.RAISED_COS, 1.0),
+    oracle.SINC_BETA: (oracle.SINC, 1.0),
+}
+
+
+@pytest.mark.parametrize("mkind", list(MODIFIED))
+def test_modified_forms_reduce_to_the_fixed_kernels(orc, mkind):
+    """At the roll-off the listings use (beta = 2 for the Gaussian and the
+    half-cosine, beta = 1 for the raised cosine and the sinc) the modified form
+    of Table 1 is the fixed kernel: values and derivatives agree (two code paths:
+    pow(E, beta/2) against the fixed forms in E or sqrt(E))."""
+    kind, beta = MODIFIED[mkind]
+    name = {oracle.GAUSS: "G", oracle.HALF_COS: "HC", oracle.RAISED_COS: "RC", oracle.SINC: "Sinc"}[kind]
+    _, xi, e_max = KERNELS[name]
+    E = np.concatenate([[0.0, 1e-9, 1e-4], np.linspace(0.01, e_max, 57)])
+    assert np.allclose(orc.kernel_value(mkind, xi, E, beta), orc.kernel_value(kind, xi, E), rtol=1e-13, atol=1e-15)
+    Ed = E[1:]
+    assert np.allclose(orc.kernel_deriv(mkind, xi, Ed, beta), orc.kernel_deriv(kind, xi, Ed), rtol=1e-9, atol=1e-12)
+
+
+def test_modified_closed_values(orc):
+    # modified Gaussian, beta = 4, xi = 2: exp(-d_M^4 / 2)
+    assert orc.kernel_value(oracle.GAUSS_BETA, 2.0, 1.0, 4.0)[0] == pytest.approx(math.exp(-0.5), rel=1e-14)
+    assert orc.kernel_value(oracle.GAUSS_BETA, 2.0, 4.0, 4.0)[0] == pytest.approx(math.exp(-8.0), rel=1e-14)
+    # modified half-cosine, beta = 1: zero at the end of the main lobe d_M / xi = pi / 2
+    xi = 2.0
+    assert orc.kernel_value(oracle.HALF_COS_BETA, xi, (xi * PI / 2) ** 2, 1.0)[0] == pytest.approx(0.0, abs=1e-15)
+    assert orc.kernel_value(oracle.HALF_COS_BETA, xi, (xi * PI / 3) ** 2, 1.0)[0] == pytest.approx(0.5, rel=1e-14)
+    # raised cosine with n pulses (u <= n pi): 0 at the end of odd pulses, 1 at the end of even ones
+    xi = 2.5 / PI
+    for npulse, val in ((1, 0.0), (2, 1.0), (3, 0.0)):
+        E = (xi * npulse * PI) ** 2
+        assert orc.kernel_value(oracle.RAISED_COS_BETA, xi, E, 1.0)[0] == pytest.approx(val, abs=1e-14)
+    # modular sinc with n pulses (u <= (n + 1) pi / 2): |sin u| / u
+    xi = 3.0 / PI
+    assert orc.kernel_value(oracle.SINC_BETA, xi, (xi * PI) ** 2, 1.0)[0] == pytest.approx(0.0, abs=1e-15)
+    assert orc.kernel_value(oracle.SINC_BETA, xi, (xi * 1.5 * PI) ** 2, 1.0)[0] == pytest.approx(2 / (3 * PI),
+                                                                                                  rel=1e-13)
+    # a generic beta moves the lobe: beta = 3, half-cosine: cos(d_M^3 / xi)
+    assert orc.kernel_value(oracle.HALF_COS_BETA, 4.0, 2.0 ** 2, 3.0)[0] == pytest.approx(math.cos(2.0), rel=1e-14)
+
+
+@pytest.mark.parametrize("mkind", list(MODIFIED))
+@pytest.mark.parametrize("beta", [1.0, 1.5, 3.0, 4.0])
+def test_modified_derivative_matches_central_difference(orc, mkind, beta):
+    xi = 1.3
+    E = np.linspace(0.05, 8.0, 41)
+    an = orc.kernel_deriv(mkind, xi, E, beta)
+    h = 1e-6
+    fd = (orc.kernel_value(mkind, xi, E + h, beta) - orc.kernel_value(mkind, xi, E - h, beta)) / (2 * h)
+    assert np.allclose(an, fd, rtol=1e-6, atol=1e-9)
+
+
+def test_modified_derivative_at_centre(orc):
+    # beta = 2: dF/dE(0) = F'(0) / xi; beta > 2: 0; beta < 2: taken as 0 (every gradient it feeds vanishes)
+    assert orc.kernel_deriv(oracle.GAUSS_BETA, 2.0, 0.0, 2.0)[0] == pytest.approx(-0.5, rel=1e-15)
+    assert orc.kernel_deriv(oracle.GAUSS_BETA, 2.0, 0.0, 4.0)[0] == 0.0
+    assert orc.kernel_deriv(oracle.HALF_COS_BETA, 2.0, 0.0, 1.0)[0] == 0.0
+    assert orc.kernel_deriv(oracle.SINC_BETA, 1.0, 0.0, 1.0)[0] == 0.0
+    # beta = 1 near the centre: dF/dE ~ F'(u) / (2 xi sqrt(E)) -- finite for E > 0
+    E = 1e-10
+    d = orc.kernel_deriv(oracle.GAUSS_BETA, 2.0, E, 1.0)[0]
+    assert d == pytest.approx(-1.0 / (2 * 2.0 * math.sqrt(E)), rel=1e-4)
