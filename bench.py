@@ -22,11 +22,16 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# per-unit algorithmic work (see the design notes for the derivations)
-FLOPS_PER_PAIR_FWD = 23     # d, Q d, E, F(E), alpha, T update, colour blend
-FLOPS_PER_PAIR_BWD = 66     # recompute alpha, T recovery, dL/dalpha, 9 partial sums, colour-behind update
-PEAK_HBM_GBS = 8000.0       # MI355X HBM3E
-PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 vector (packed FMA)
+# Per-unit algorithmic work of the survey's measurement plan: VALU lane-operations
+# per (pixel, splat) pair -- E (5 FMA), the support and alpha tests, one
+# transcendental, the 3 colour FMAs and the T update in the forward; the
+# backward adds the T recovery division, the 9 partial sums and the reduction.
+LANE_OPS_PER_PAIR_FWD = 25
+LANE_OPS_PER_PAIR_BWD = 60
+PEAK_HBM_GBS = 8000.0            # MI355X HBM3E
+PEAK_FP32_TFLOPS = 157.3         # MI355X FP32 vector, packed FMA (2 flops x 2 lanes per lane-op)
+PEAK_FP32_NONPACKED_TFLOPS = 78.6  # the same without packed FP32 (how every kernel here is built)
+PEAK_LANE_OPS = 39.3e12          # 256 CU x 64 lanes x 2.4 GHz: VALU lane-operations per second
 
 
 def log(*a):
@@ -78,9 +83,27 @@ def measure_ceilings(reps: int = 5):
                 arch=getattr(props, "gcnArchName", ""))
 
 
+def survey_bytes(n, n_vis, K, P, pairs):
+    """Algorithmic bytes per stage as the survey's measurement plan counts them
+    (one read of each needed input, one write of each output; the sort as one
+    read + write pass of K keys and values):
+      a1 preprocess        12 N + 224 N_v + 48 N_v + 4 N
+      a2 duplicate         20 N_v + 12 K
+      a3 sort              24 K
+      a4 raster forward    40 K_trav + 20 P
+      a5 raster backward   76 K_trav + 32 P
+      a6 preprocess bwd    308 N_v + 236 N
+    K_trav, the instances a tile list traverses, is taken as the pairs up to each
+    pixel's last blend divided by the 256 pixels of a tile."""
+    k_trav = pairs / 256.0
+    return dict(preprocess=16 * n + 272 * n_vis, bin_sort=20 * n_vis + 36 * K, raster_fwd=40 * k_trav + 20 * P,
+                raster_bwd=76 * k_trav + 32 * P, preprocess_bwd=308 * n_vis + 236 * n)
+
+
 def stage_bytes(n, n_vis, split=False):
-    """Algorithmic HBM bytes per launch of the single-kernel stages (one read of
-    each needed input, one write of each output), per splat / per visible splat:
+    """This build's own algorithmic HBM bytes per launch of the single-kernel
+    stages (one read of each input it needs, one write of each output), per
+    splat / per visible splat:
       preprocess      12 B mean + 4 B cull data of every splat; 224 B of parameters
                       (scale, quaternion, opacity, 48 SH) read and 48 B of projected
                       record written per visible splat; the 36 B colour checkpoint
@@ -92,13 +115,14 @@ def stage_bytes(n, n_vis, split=False):
       and the colour part beside the binning reads the radius (4 B) of every splat
       and the mean and 48 SH (204 B) of each visible one, and writes rgb, clamp
       bits and the colour checkpoint (49 B) of every splat:       53 N + 204 N_v
-      preprocess_bwd  per visible splat 113 B read (mean 12, scale 12, quaternion 16,
-                      2D gradients 36, colour checkpoint 36 + clamp bits 1), the full
-                      gradient written for every splat (236 B):   113 N_v + 236 N
+      preprocess_bwd  the radius (4 B) of every splat; per visible splat 113 B read
+                      (mean 12, scale 12, quaternion 16, 2D gradients 36, colour
+                      checkpoint 36 + clamp bits 1); the full gradient written for
+                      every splat (236 B):                        113 N_v + 240 N
     """
     if split:
-        return dict(preprocess=76 * n, colour=53 * n + 204 * n_vis, preprocess_bwd=113 * n_vis + 236 * n)
-    return dict(preprocess=52 * n + 272 * n_vis, preprocess_bwd=113 * n_vis + 236 * n)
+        return dict(preprocess=76 * n, colour=53 * n + 204 * n_vis, preprocess_bwd=113 * n_vis + 240 * n)
+    return dict(preprocess=52 * n + 272 * n_vis, preprocess_bwd=113 * n_vis + 240 * n)
 
 
 # kernel of each single-kernel stage, and the sources it is built from
@@ -129,12 +153,26 @@ def measured_traffic(stage: str):
     return int(rec["fetch_bytes"] + rec["write_bytes"])
 
 
-def cpu_baseline(sc, kernel_name, rows_every: int, log_fn=log):
-    """The FP64 oracle (as is) on a bounded sample: preprocess and its backward over
-    all splats, composite forward+backward over every ``rows_every``-th image row."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_oracle_run(sc, kernel_name, rows_every: int, threads: int, log_fn=log):
+    """The FP64 oracle (as is) on a bounded sample of the scene step on ``threads``
+    host threads: preprocess and its backward over all splats, composite
+    forward+backward over every ``rows_every``-th image row; the per-pixel time
+    is scaled to the full view.  Returns (Mpix/s, sample text, seconds)."""
     import oracle
     from paper_2501_12369_amd import scenes
 
+    oracle.set_num_threads(threads)
     sp, camd = sc["splats"], sc["camera"]
     W, H = camd["width"], camd["height"]
     f32 = lambda v: float(np.float32(v))
@@ -158,19 +196,38 @@ def cpu_baseline(sc, kernel_name, rows_every: int, log_fn=log):
     oracle.preprocess_bwd(cam, k, sp["means"], sp["scales"], sp["quats"], sp["sh"], sp["sh_degree"], g2d)
     t4 = time.perf_counter()
     frac = len(pix) / (W * H)
-    per_splat = (t1 - t0) + (t4 - t3)
-    per_pixel = (t3 - t1) / frac
-    total = per_splat + per_pixel
-    log_fn(f"cpu oracle: preprocess {t1-t0:.2f}s composite {t2-t1:.2f}s composite_bwd {t3-t2:.2f}s "
-           f"preprocess_bwd {t4-t3:.2f}s on {len(pix)} px; full-view estimate {total:.1f}s")
-    return dict(value=round(W * H / total / 1e6, 6), unit="Mpix/s", cores=oracle.num_threads(), kind="oracle",
-                sample=f"FP64 oracle: preprocess + preprocess backward over all {sp['means'].shape[1]} splats, "
-                       f"composite forward + backward over every {rows_every}th row ({len(pix)} of {W*H} pixels); "
-                       f"per-pixel time scaled to the full view; measured {t4 - t0:.1f}s")
+    total = (t1 - t0) + (t4 - t3) + (t3 - t1) / frac
+    log_fn(f"cpu oracle on {threads} threads: preprocess {t1-t0:.2f}s composite {t2-t1:.2f}s composite_bwd "
+           f"{t3-t2:.2f}s preprocess_bwd {t4-t3:.2f}s on {len(pix)} px; full-view estimate {total:.1f}s")
+    sample = (f"FP64 oracle: preprocess + preprocess backward over all {sp['means'].shape[1]} splats, composite "
+              f"forward + backward over every {rows_every}th row ({len(pix)} of {W*H} pixels); per-pixel time "
+              f"scaled to the full view; measured {t4 - t0:.1f}s")
+    return W * H / total / 1e6, sample, t4 - t0
 
 
-def serving_bench(kernel_name: str, seconds: float, rate_hz: float, mem_budget_gb: float, max_slots: int):
-    """Forward-only serving of Poisson requests over four resident scenes."""
+def cpu_baseline(sc, kernel_name, rows_every: int, log_fn=log):
+    """The oracle on all host threads (the reported baseline) and on one thread
+    (a sparser row sample), with the host CPU named."""
+    import oracle
+
+    all_threads = oracle.num_threads()
+    v, sample, _ = cpu_oracle_run(sc, kernel_name, rows_every, all_threads, log_fn)
+    v1, sample1, _ = cpu_oracle_run(sc, kernel_name, rows_every * 8, 1, log_fn)
+    oracle.set_num_threads(all_threads)
+    model = cpu_model()
+    log_fn(f"cpu: {model}; oracle {v:.5f} Mpix/s on {all_threads} threads, {v1:.5f} Mpix/s on 1 thread")
+    return dict(value=round(v, 6), unit="Mpix/s", cores=all_threads, kind="oracle", sample=sample, cpu_model=model,
+                one_core=dict(value=round(v1, 6), unit="Mpix/s", cores=1, sample=sample1))
+
+
+def serving_bench(kernel_name: str, seconds: float, rate_hz: float, mem_budget_gb: float, max_slots: int,
+                  max_batch: int = 4, sweep=(100.0, 200.0, 400.0, 800.0, 1600.0, 3200.0), sweep_seconds: float = 2.0,
+                  slo_p99_ms: float = 10.0):
+    """Forward-only serving of Poisson requests over four resident scenes, with
+    requests of one (scene, resolution) batched into multi-view graph replays;
+    a sweep of arrival rates (p50/p99, Mpix/s and the forward's HBM fraction at
+    each), the highest rate whose p99 meets ``slo_p99_ms``, and the same
+    requests one at a time through the same slots."""
     import torch
 
     from paper_2501_12369_amd import pipeline, scenes, serving
@@ -180,8 +237,9 @@ def serving_bench(kernel_name: str, seconds: float, rate_hz: float, mem_budget_g
           for i, n in enumerate(scenes.SERVING_SCENE_SIZES)]
     log(f"serving scenes generated in {time.time() - t0:.1f}s")
     kern = pipeline.KERNELS[kernel_name]
-    srv = serving.RenderServer(sc, kern, mem_budget=int(mem_budget_gb * (1 << 30)), max_slots=max_slots)
-    # warm-up: every (scene, resolution) key sized and captured before the measured session
+    srv = serving.RenderServer(sc, kern, mem_budget=int(mem_budget_gb * (1 << 30)), max_slots=max_slots,
+                               max_batch=max_batch)
+    # warm-up: every (scene, resolution) key sized and captured before the measured sessions
     warm = []
     rng = np.random.Generator(np.random.PCG64(1234))
     for s in range(len(sc)):
@@ -189,8 +247,6 @@ def serving_bench(kernel_name: str, seconds: float, rate_hz: float, mem_budget_g
             warm.append(serving.Request(len(warm), 0.0, s, scenes.orbit_camera(rng, w, h)))
     srv.serve(warm)
     torch.cuda.synchronize()
-    n_req = max(1, int(seconds * rate_hz))
-    reqs = serving.make_requests(77, n_req, rate_hz, len(sc))
     sizes = list(scenes.SERVING_SCENE_SIZES)
 
     def fwd_bytes(results):
@@ -203,39 +259,51 @@ def serving_bench(kernel_name: str, seconds: float, rate_hz: float, mem_budget_g
             tot += 16 * sizes[r.key[0]] + 292 * nv + 36 * K + 20 * r.pixels
         return tot
 
+    def point(res, st):
+        hbm = fwd_bytes(res) / st.wall_s / 1e9
+        return dict(p50_ms=round(st.p50_ms, 3), p99_ms=round(st.p99_ms, 3), mean_ms=round(st.mean_ms, 3),
+                    mpix_per_s=round(st.mpix_per_s, 2), req_per_s=round(st.req_per_s, 2), requests=st.n,
+                    fwd_gbs=round(hbm, 1), hbm_frac=round(hbm / PEAK_HBM_GBS, 4), peak_batch=st.extra["peak_batch"],
+                    peak_inflight=st.peak_inflight, retries=st.retries)
+
+    n_req = max(1, int(seconds * rate_hz))
+    reqs = serving.make_requests(77, n_req, rate_hz, len(sc))
     res, st = srv.serve(reqs)
-    hbm = fwd_bytes(res) / st.wall_s / 1e9
+    main_pt = point(res, st)
     log(f"serving: {st.n} requests at {rate_hz}/s: p50 {st.p50_ms:.2f} ms p99 {st.p99_ms:.2f} ms, "
-        f"{st.mpix_per_s:.1f} Mpix/s, {hbm:.0f} GB/s of forward bytes, peak slots {st.peak_slots}, "
-        f"peak in flight {st.peak_inflight}, retries {st.retries}")
-    # saturation: the same mix arriving at once (a first, untimed burst creates the
-    # extra slots that many requests of one key in flight need)
+        f"{st.mpix_per_s:.1f} Mpix/s, {main_pt['fwd_gbs']:.0f} GB/s of forward bytes, peak batch "
+        f"{main_pt['peak_batch']}, peak slots {st.peak_slots}, peak in flight {st.peak_inflight}, retries {st.retries}")
+    sweep_pts = []
+    for i, rate in enumerate(sweep):
+        rq = serving.make_requests(500 + i, max(16, int(sweep_seconds * rate)), rate, len(sc))
+        pt = dict(rate_hz=rate, **point(*srv.serve(rq)))
+        sweep_pts.append(pt)
+        log(f"  sweep {rate:7.0f} req/s: p50 {pt['p50_ms']:.2f} p99 {pt['p99_ms']:.2f} ms, {pt['mpix_per_s']:.0f} "
+            f"Mpix/s, {pt['fwd_gbs']:.0f} GB/s ({pt['hbm_frac']:.3f} of HBM), peak batch {pt['peak_batch']}")
+    meets = [p for p in sweep_pts if p["p99_ms"] <= slo_p99_ms]
+    best = max(meets, key=lambda p: p["rate_hz"]) if meets else None
+    # saturation: a burst of the same mix arriving at once (a first, untimed burst
+    # creates the slots that many requests of one key in flight need)
     srv.serve(serving.make_requests(79, max(64, n_req // 2), 1e9, len(sc)))
     torch.cuda.synchronize()
     burst = serving.make_requests(78, max(64, n_req // 2), 1e9, len(sc))
-    bres, bst = srv.serve(burst)
-    bhbm = fwd_bytes(bres) / bst.wall_s / 1e9
-    log(f"saturation: {bst.n} requests at once: {bst.mpix_per_s:.1f} Mpix/s, {bst.req_per_s:.1f} req/s, "
-        f"{bhbm:.0f} GB/s of forward bytes ({bhbm / PEAK_HBM_GBS:.3f} of HBM peak)")
-    _, seq = serving.sequential_baseline(srv, reqs)
-    log(f"one-at-a-time: p50 {seq.p50_ms:.2f} ms p99 {seq.p99_ms:.2f} ms, {seq.mpix_per_s:.1f} Mpix/s, "
-        f"retries {seq.retries}")
-    _, bseq = serving.sequential_baseline(srv, burst)
-    log(f"one-at-a-time saturation: {bseq.mpix_per_s:.1f} Mpix/s, {bseq.req_per_s:.1f} req/s")
-    return dict(workload=f"4 resident scenes {sizes} splats, Poisson {rate_hz} req/s "
-                         f"for {seconds}s, resolutions {[f'{w}x{h}' for w, h in scenes.SERVING_RESOLUTIONS]}, "
-                         f"forward only, {kernel_name}",
-                p50_ms=round(st.p50_ms, 3), p99_ms=round(st.p99_ms, 3), mean_ms=round(st.mean_ms, 3),
-                mpix_per_s=round(st.mpix_per_s, 2), req_per_s=round(st.req_per_s, 2), requests=st.n,
-                peak_slots=st.peak_slots, peak_inflight=st.peak_inflight, peak_gb=round(st.peak_bytes / 2**30, 2),
-                retries=st.retries, fwd_gbs=round(hbm, 1),
-                saturation=dict(requests=bst.n, mpix_per_s=round(bst.mpix_per_s, 2), req_per_s=round(bst.req_per_s, 2),
-                                fwd_gbs=round(bhbm, 1), hbm_frac=round(bhbm / PEAK_HBM_GBS, 4),
-                                p99_ms=round(bst.p99_ms, 3)),
+    sat = point(*srv.serve(burst))
+    log(f"saturation: {sat['requests']} requests at once: {sat['mpix_per_s']:.1f} Mpix/s, {sat['req_per_s']:.1f} "
+        f"req/s, {sat['fwd_gbs']:.0f} GB/s of forward bytes ({sat['hbm_frac']:.3f} of HBM peak)")
+    seq_res, seq = serving.sequential_baseline(srv, reqs)
+    log(f"one-at-a-time: p50 {seq.p50_ms:.2f} ms p99 {seq.p99_ms:.2f} ms, {seq.mpix_per_s:.1f} Mpix/s")
+    bseq = point(*serving.sequential_baseline(srv, burst))
+    log(f"one-at-a-time saturation: {bseq['mpix_per_s']:.1f} Mpix/s, {bseq['req_per_s']:.1f} req/s")
+    return dict(workload=f"4 resident scenes {sizes} splats, Poisson {rate_hz} req/s for {seconds}s, resolutions "
+                         f"{[f'{w}x{h}' for w, h in scenes.SERVING_RESOLUTIONS]}, forward only, {kernel_name}, "
+                         f"batches of up to {max_batch} requests per graph replay",
+                **main_pt, peak_slots=st.peak_slots, peak_gb=round(st.peak_bytes / 2**30, 2),
+                rate_sweep=sweep_pts, slo_p99_ms=slo_p99_ms,
+                max_rate_meeting_slo=best["rate_hz"] if best else None,
+                at_max_rate=best, saturation=sat,
                 one_at_a_time=dict(p50_ms=round(seq.p50_ms, 3), p99_ms=round(seq.p99_ms, 3),
-                                   mpix_per_s=round(seq.mpix_per_s, 2),
-                                   saturation_mpix_per_s=round(bseq.mpix_per_s, 2),
-                                   saturation_req_per_s=round(bseq.req_per_s, 2)))
+                                   mpix_per_s=round(seq.mpix_per_s, 2), saturation_mpix_per_s=bseq["mpix_per_s"],
+                                   saturation_req_per_s=bseq["req_per_s"]))
 
 
 def variants_bench(spd, cam, steps: int, warmup: int):
@@ -365,6 +433,7 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-mem-gb", type=float, default=96.0)
     ap.add_argument("--serve-slots", type=int, default=32)
+    ap.add_argument("--serve-batch", type=int, default=4, help="requests per multi-view graph replay")
     ap.add_argument("--multiview-views", type=int, default=8, help="0 disables the multi-view leg")
     ap.add_argument("--multiview-n", type=int, default=2_000_000)
     ap.add_argument("--variants", type=int, default=1, help="0 skips the Gaussian and autograd steps")
@@ -473,7 +542,8 @@ def main():
         log(f"colour part on the side stream (beside bin_sort): {colour_ms:.3f} ms, "
             f"{stage_bytes(n, n_vis, True)['colour'] / (colour_ms * 1e-3) / 1e9:.1f} GB/s")
 
-    # algorithmic work of the raster stages from the checkpoint
+    # pairs up to each pixel's last blended splat (the backward walks exactly these;
+    # the forward at least these), from the checkpoint
     last = frame.last.to(torch.int64) & 0xFFFFFFFF
     ranges = frame.ranges.to(torch.int64)
     gx = (W + 15) // 16
@@ -481,36 +551,73 @@ def main():
     tile = (yy // 16) * gx + (xx // 16)
     start = ranges[tile, 0]
     has = last != 0xFFFFFFFF
-    pairs_bwd = int(torch.where(has, last - start + 1, torch.zeros_like(last)).sum())
-    chunks = 0
-    bytes_ = stage_bytes(n, n_vis, overlap)
-    roof = {st: dict(bound="hbm", achieved=bytes_[st] / (per_stage[st] * 1e-3) / 1e9, peak=PEAK_HBM_GBS, unit="GB/s")
-            for st in ("preprocess", "preprocess_bwd")}
-    roof["raster_bwd"] = dict(bound="alu", achieved=pairs_bwd * FLOPS_PER_PAIR_BWD / (per_stage["raster_bwd"] * 1e-3)
-                              / 1e12, peak=PEAK_FP32_TFLOPS, unit="TFLOP/s")
-    log(f"bwd pairs {pairs_bwd}; " + ", ".join(f"{k}: {v['achieved']:.2f}/{v['peak']} {v['unit']}"
-                                                for k, v in roof.items()))
-    # the dominant kernel: the longest single-kernel stage (the rocprofv3 summary in profiles/
-    # lists every kernel of the step, those inside the bin/sort stage included)
-    dominant = max(STAGE_KERNEL, key=lambda st: per_stage[st])
-    r = roof[dominant]
-    traffic = measured_traffic(dominant)
-    # fractions against the spec peak and against this GPU's measured ceiling
-    # (the copy probe for an HBM-bound kernel, the FP32 FMA probe for an ALU-bound one)
+    pairs = int(torch.where(has, last - start + 1, torch.zeros_like(last)).sum())
+    own = stage_bytes(n, n_vis, overlap)
+    svy = survey_bytes(n, n_vis, K, P, pairs)
     ceilings = measure_ceilings()
     log("measured ceilings: " + ", ".join(f"{k}={v}" for k, v in ceilings.items()))
-    measured_peak = ceilings["copy_gbs"] if r["bound"] == "hbm" else ceilings["fma32_tflops"]
-    roofline = dict(bound=r["bound"], achieved=round(r["achieved"], 2), peak=r["peak"], unit=r["unit"],
-                    frac=round(r["achieved"] / r["peak"], 4), traffic=traffic, kernel=STAGE_KERNEL[dominant][0],
-                    kernel_us=round(per_stage[dominant] * 1e3, 2), algorithmic_bytes=int(bytes_[dominant]),
-                    measured_peak=measured_peak, frac_of_measured=round(r["achieved"] / measured_peak, 4))
-    log(f"dominant kernel {roofline['kernel']}: {roofline['kernel_us']} us, {roofline['achieved']} GB/s "
-        f"({roofline['frac']:.3f} of peak, {roofline['frac_of_measured']:.3f} of the measured copy ceiling), "
-        f"traffic {traffic}")
-    stage_fracs = {k: dict(achieved=round(v["achieved"], 2), unit=v["unit"], frac_of_peak=round(v["achieved"] / v["peak"], 4),
-                           frac_of_measured=round(v["achieved"] / (ceilings["copy_gbs"] if v["bound"] == "hbm"
-                                                                   else ceilings["fma32_tflops"]), 4))
-                   for k, v in roof.items()}
+
+    def hbm(stage, t_ms, kernel, own_bytes=None):
+        b = svy.get(stage, own_bytes)
+        r = dict(bound="hbm", kernel=kernel, us=round(t_ms * 1e3, 2), algorithmic_bytes=int(b),
+                 achieved=round(b / (t_ms * 1e-3) / 1e9, 2), peak=PEAK_HBM_GBS, unit="GB/s")
+        r["frac"] = round(r["achieved"] / PEAK_HBM_GBS, 4)
+        r["frac_of_measured"] = round(r["achieved"] / ceilings["copy_gbs"], 4)
+        if own_bytes is not None and stage in svy:
+            r["own_bytes"] = int(own_bytes)
+            r["own_frac"] = round(own_bytes / (t_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
+        return r
+
+    def valu(stage, t_ms, kernel, ops_per_pair):
+        ops = pairs * ops_per_pair
+        rate = ops / (t_ms * 1e-3)
+        return dict(bound="alu", kernel=kernel, us=round(t_ms * 1e3, 2), pairs=pairs, lane_ops_per_pair=ops_per_pair,
+                    achieved=round(2 * rate / 1e12, 2), unit="TFLOP/s (FMA-equivalent: 2 x lane-ops)",
+                    peak=PEAK_FP32_NONPACKED_TFLOPS, frac=round(rate / PEAK_LANE_OPS, 4),
+                    frac_of_packed=round(2 * rate / 1e12 / PEAK_FP32_TFLOPS, 4),
+                    frac_of_measured=round(2 * rate / 1e12 / ceilings["fma32_tflops"], 4))
+
+    pre_kernel = "k_preprocess_geom" if overlap else "k_preprocess<3>"
+    stage_roofs = {
+        "preprocess": hbm("preprocess", per_stage["preprocess"], pre_kernel, own["preprocess"]),
+        "bin_sort": hbm("bin_sort", per_stage["bin_sort"], "20 launches (keys .. level-2 scatter)"),
+        "raster_fwd": valu("raster_fwd", per_stage["raster_fwd"], "k_raster_fwd<1, OneView, false>",
+                           LANE_OPS_PER_PAIR_FWD),
+        "raster_bwd": valu("raster_bwd", per_stage["raster_bwd"], "k_raster_bwd<1, false, OneView>",
+                           LANE_OPS_PER_PAIR_BWD),
+        "preprocess_bwd": hbm("preprocess_bwd", per_stage["preprocess_bwd"], "k_preprocess_bwd<3, true>",
+                              own["preprocess_bwd"]),
+    }
+    if overlap:
+        stage_roofs["colour_side_stream"] = hbm("colour", colour_ms, "k_preprocess_colour<3>", own["colour"])
+    # the dominant kernel: the longest single kernel on the step's critical path
+    # (the bin/sort stage is ~20 launches, none longer than the stages below;
+    # the colour part runs on the side stream, hidden behind bin/sort)
+    single = ("preprocess", "raster_fwd", "raster_bwd", "preprocess_bwd")
+    dominant = max(single, key=lambda st: per_stage[st])
+    r = dict(stage_roofs[dominant])
+    traffic = measured_traffic(dominant) if dominant in STAGE_KERNEL else None
+    if r["bound"] == "hbm":
+        roofline = dict(bound="hbm", achieved=r["achieved"], peak=PEAK_HBM_GBS, unit="GB/s", frac=r["frac"],
+                        traffic=traffic, kernel=r["kernel"], kernel_us=r["us"],
+                        algorithmic_bytes=r["algorithmic_bytes"], bytes_rule="survey per-unit counts",
+                        own_bytes=r.get("own_bytes"), own_frac=r.get("own_frac"),
+                        measured_peak=ceilings["copy_gbs"], frac_of_measured=r["frac_of_measured"])
+    else:
+        roofline = dict(bound="alu", achieved=r["achieved"], peak=PEAK_FP32_NONPACKED_TFLOPS,
+                        unit="TFLOP/s", frac=r["frac"], traffic=traffic, kernel=r["kernel"], kernel_us=r["us"],
+                        pairs=pairs, frac_of_packed=r["frac_of_packed"], measured_peak=ceilings["fma32_tflops"],
+                        frac_of_measured=r["frac_of_measured"])
+    step_bytes = sum(svy.values())
+    step_roof = dict(algorithmic_bytes=int(step_bytes), achieved=round(step_bytes / (ms_per_step * 1e-3) / 1e9, 2),
+                     frac=round(step_bytes / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS, 4))
+    ranked = sorted(stage_roofs, key=lambda st: -stage_roofs[st]["us"])
+    log("stages by time: " + "; ".join(f"{st} {stage_roofs[st]['us']} us {stage_roofs[st]['achieved']} "
+                                      f"{stage_roofs[st]['unit'].split(' ')[0]} (frac {stage_roofs[st]['frac']})"
+                                      for st in ranked))
+    log(f"dominant kernel {roofline['kernel']}: {roofline['kernel_us']} us, {roofline['achieved']} {roofline['unit']} "
+        f"({roofline['frac']:.3f} of peak, {roofline['frac_of_measured']:.3f} of the measured ceiling), "
+        f"traffic {traffic}; whole step {step_roof['achieved']} GB/s ({step_roof['frac']:.3f})")
 
     if args.calibrate_copy_mib > 0:
         # a plain elementwise copy of known size: what the HBM counters read for it
@@ -536,7 +643,7 @@ def main():
     serving_stats = None
     if args.serve_seconds > 0:
         serving_stats = serving_bench(args.kernel, args.serve_seconds, args.serve_rate, args.serve_mem_gb,
-                                      args.serve_slots)
+                                      args.serve_slots, args.serve_batch)
 
     out = {
         "metric": "fwd+bwd Mpix/s at 3M splats 1297x840; serving p50/p99 render latency",
@@ -559,7 +666,8 @@ def main():
                    "colour_side_stream_ms": round(colour_ms, 4) if overlap else None, "variants": variants},
         "roofline": roofline,
         "measured_ceilings": ceilings,
-        "stage_rooflines": stage_fracs,
+        "stage_rooflines": stage_roofs,
+        "step_roofline": step_roof,
         "cpu_baseline": cpu,
         "multiview": multiview_stats,
         "serving": serving_stats,

@@ -40,7 +40,7 @@ extern "C" {
 #define DARB_API
 #endif
 
-#define DARB_ABI_VERSION 4
+#define DARB_ABI_VERSION 5
 #define DARB_TILE 16
 #define DARB_MAX_VIEWS 16       /* views per multi-view call */
 #define DARB_LOSS_WS_BYTES 4096 /* workspace of darb_image_loss */
@@ -62,7 +62,16 @@ typedef enum {
     DARB_SINC = 3,       /* |sin u|/u, u = sqrt(E)/xi   (modular sinc, beta = 1; xi = 3/pi)         */
     DARB_IMQ = 4,        /* 1/(E/xi + 1)                (inverse quadric of the supplementary code) */
     DARB_IMQ_SQRT = 5,   /* 1/sqrt(E/xi + 1)            (inverse multiquadric of Table 1)           */
-    DARB_PARABOLA = 6    /* 1 - E/xi                    (parabola; xi = 9)                          */
+    DARB_PARABOLA = 6,   /* 1 - E/xi                    (parabola; xi = 9)                          */
+    /* Table 1's modified forms with a generic roll-off beta (darb_kernel.beta > 0):
+     * u = d_M^beta / xi = E^(beta/2) / xi; the support e_max is the caller's
+     * domain limit, E <= (xi U)^(2/beta) for u <= U (U = pi/2 for one
+     * half-cosine lobe, n pi for n raised-cosine pulses, (n+1) pi/2 for n sinc
+     * pulses).  dF/dE at E = 0 is 1/xi dF/du(0) for beta = 2 and 0 otherwise. */
+    DARB_GAUSS_BETA = 7,      /* exp(-u)                                                    */
+    DARB_HALF_COS_BETA = 8,   /* cos(u)                                                     */
+    DARB_RAISED_COS_BETA = 9, /* 0.5 + 0.5 cos(u)                                           */
+    DARB_SINC_BETA = 10       /* |sin u| / u (1 at u = 0)                                   */
 } darb_kernel_kind;
 
 /* Image losses with a per-pixel gradient, each the mean over the 3 W H values
@@ -76,13 +85,19 @@ typedef enum {
 /* A DARBF: profile, scale, correction factor and support.
  * psi multiplies the projected 2x2 covariance (Eq. of the 2x2 covariance
  * projection; Table 2).  A pixel is inside the footprint iff 0 <= E <= e_max
- * (boundaries of DARBFs: one main lobe).  Requires 0 < e_max <= 9, because the
- * binning radius is 3 sqrt(lambda_max) (DARB-Splatting section). */
+ * (boundaries of DARBFs: one main lobe, or n pulses).  The binning radius is
+ * 3 sqrt(lambda_max) (DARB-Splatting section), widened to
+ * sqrt(e_max lambda_max) when e_max > 9.  The fixed kinds 0..6 require
+ * 0 < e_max <= 9 and, for the trigonometric ones, a support inside the main
+ * lobe (E/xi <= pi/2 for DARB_HALF_COS, sqrt(E)/xi <= pi for DARB_RAISED_COS
+ * and DARB_SINC); the modified kinds 7..10 take 0 < beta <= 8 and
+ * 0 < e_max <= 1024 and ignore nothing else.  beta is ignored by kinds 0..6. */
 typedef struct {
     int32_t kind; /* darb_kernel_kind */
     float xi;
     float psi;
     float e_max;
+    float beta; /* roll-off of the modified kinds */
 } darb_kernel;
 
 /* Pinhole camera.  viewmat: world -> camera, row-major 4x4 (rotation R_cw in
@@ -277,6 +292,55 @@ DARB_API darb_status darb_bin_sort(const darb_projected *proj, int64_t n, int32_
                           int32_t *overflow_dev, int64_t *k_host, void *stream);
 
 /*
+ * darb_fit1d -- the 1D signal-reconstruction experiment (Assessing DARBFs
+ * through 1D Simulations; the extended 1D results) for `batch` independent
+ * problems in one launch.  Problem b approximates target[b][0..m) sampled at
+ * x[0..m) by f(x) = sum_k a_k F(E_k(x)), E_k(x) = ((x - mu_k) / sigma_k)^2,
+ * each term zero beyond E > e_max of `kernel` (psi is not used), and runs
+ * `steps` Adam steps on L = (1/m) sum_j (f(x_j) - target[b][j])^2 over
+ * (mu_k, log sigma_k, a_k).
+ *   params  [batch][3][n_comp] in/out: mu, log sigma, amplitude
+ *   adam_m, adam_v [batch][3][n_comp] in/out: first and second moments
+ *   step0   steps taken before (bias corrections 1 - beta^(step0 + s + 1))
+ *   lr      HOST array of 3 learning rates (mu, log sigma, amplitude)
+ *   loss    nullable [batch][steps] out: L before each step
+ * 1 <= n_comp <= 64, 1 <= m <= 4096.  FP32.
+ */
+DARB_API darb_status darb_fit1d(const darb_kernel *kernel, int32_t batch, int32_t n_comp, int32_t m, const float *x,
+                                const float *target, float *params, float *adam_m, float *adam_v, int32_t steps,
+                                int32_t step0, const float *lr, float beta1, float beta2, float eps, float *loss,
+                                void *stream);
+
+/*
+ * darb_psi_calibrate_workspace -- bytes of workspace of darb_psi_calibrate
+ * (24 m grid_n); 0 for unsupported sizes.
+ */
+DARB_API size_t darb_psi_calibrate_workspace(int32_t m, int32_t grid_n);
+
+/*
+ * darb_psi_calibrate -- the correction-factor experiment (Mathematical
+ * Expressions of Monte Carlo Experiments; the psi regression of the extended
+ * results) for the DARBF `kernel`: for each of m 3D covariances the kernel
+ * F(E), E = p^T Sigma^-1 p, restricted to E <= e_max, is sampled on a grid of
+ * grid_n^3 points over the box that holds its support (half-extent
+ * (1 + 2/(grid_n-1)) sqrt(e_max Sigma_aa) on axis a), summed along z with
+ * Simpson's rule (weights 1, 4, 2, ..., 4, 1), and the weighted covariance of
+ * the resulting 2D density is taken (the paper's normalisation by the maximum
+ * does not change it).
+ *   sigma  [m][6] FP64 device: (a, b, c, d, e, f) = (xx, xy, xz, yy, yz, zz) of
+ *          each symmetric positive definite Sigma
+ *   cov2   [m][3] FP64 device out: (a', b', d') = (xx, xy, yy) of each 2D density
+ *   fit    nullable [19] FP64 device out (needs m >= 6): the least-squares linear
+ *          map (a, b, c, d, e, f) -> (a', b', d') without intercept, row r at
+ *          fit[6 r .. 6 r + 5] (r = 0, 1, 2 for a', b', d'), and fit[18] = the
+ *          scalar psi minimising sum |Sigma'_2x2 - psi Sigma_2x2|_F^2
+ *   ws     darb_psi_calibrate_workspace(m, grid_n) bytes
+ * grid_n must be odd, 5..2049; m <= 65535.  FP32 profile values, FP64 sums.
+ */
+DARB_API darb_status darb_psi_calibrate(const darb_kernel *kernel, int32_t m, const double *sigma, int32_t grid_n,
+                                        void *ws, size_t ws_bytes, double *cov2, double *fit, void *stream);
+
+/*
  * darb_raster_fwd -- per-pixel DARBF evaluation and front-to-back alpha
  * compositing (DARB-Splatting section: footprint and alpha blending; the
  * per-kernel forward listings).  For each pixel p of the tile, for the tile's
@@ -431,6 +495,18 @@ DARB_API darb_status darb_densify_stats(const darb_grads2d *g2d, const int32_t *
  */
 DARB_API darb_status darb_preprocess_multi(const darb_view *views, int32_t nv, const darb_kernel *kernel, int64_t n,
                                            const darb_splats *in, void *stream);
+
+/*
+ * darb_preprocess_multi_cam_dev -- darb_preprocess_multi with the cameras read
+ * from DEVICE memory: view v uses cams_dev[v] (an array of nv darb_camera), so
+ * a captured graph of a batch of renders can be replayed for new poses after
+ * the caller rewrites that array (the serving path).  views[v].cam still sizes
+ * view v's tile grid (width, height) and must pass the host checks; the device
+ * cameras are not validated (non-positive fx, fy or near_z cull every splat).
+ */
+DARB_API darb_status darb_preprocess_multi_cam_dev(const darb_view *views, int32_t nv, const darb_camera *cams_dev,
+                                                   const darb_kernel *kernel, int64_t n, const darb_splats *in,
+                                                   void *stream);
 
 /*
  * darb_raster_fwd_multi -- darb_raster_fwd of every view in one launch over

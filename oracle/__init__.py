@@ -79,6 +79,7 @@ def lib():
         L.orc_kernel_deriv_beta.restype = d
         L.orc_kernel_deriv_beta.argtypes = [i32, d, d, d]
         L.orc_kernel_values.argtypes = [i32, d, d, i64, vp, vp]
+        L.orc_kernel_derivs.argtypes = [i32, d, d, i64, vp, vp]
         L.orc_sh_basis.argtypes = [vp, vp, vp]
         L.orc_quat_to_rot.argtypes = [vp, vp]
         L.orc_preprocess.argtypes = [vp, vp, i64, vp, vp, vp, vp, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -89,6 +90,7 @@ def lib():
         L.orc_preprocess_bwd.argtypes = [vp, vp, i64, vp, vp, vp, vp, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp,
                                          vp, vp]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
         L.orc_bin.restype = i64
         L.orc_bin.argtypes = [i64, vp, vp, vp, ctypes.c_int, ctypes.c_int, i64, vp, vp, vp]
         _lib = L
@@ -97,6 +99,11 @@ def lib():
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on."""
+    lib().orc_set_num_threads(int(n))
 
 
 def _p(a: np.ndarray):
@@ -174,6 +181,14 @@ def kernel_values(kind: int, xi: float, E, beta: float = 0.0) -> np.ndarray:
     E = _f64(E)
     out = np.empty_like(E)
     lib().orc_kernel_values(kind, xi, beta, E.size, _p(E), _p(out))
+    return out
+
+
+def kernel_derivs(kind: int, xi: float, E, beta: float = 0.0) -> np.ndarray:
+    """dF/dE at every entry of the array E (same shape)."""
+    E = _f64(E)
+    out = np.empty_like(E)
+    lib().orc_kernel_derivs(kind, xi, beta, E.size, _p(E), _p(out))
     return out
 
 

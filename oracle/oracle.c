@@ -189,10 +189,15 @@ double orc_kernel_deriv_beta(int32_t kind, double xi, double beta, double E) {
     return dF * du;
 }
 
-/* F at n values of E (vectorised for the correction-factor experiment) */
+/* F and dF/dE at n values of E (vectorised for the correction-factor and 1D experiments) */
 void orc_kernel_values(int32_t kind, double xi, double beta, long n, const double *E, double *out) {
 #pragma omp parallel for schedule(static)
     for (long i = 0; i < n; i++) out[i] = orc_kernel_value_beta(kind, xi, beta, E[i]);
+}
+
+void orc_kernel_derivs(int32_t kind, double xi, double beta, long n, const double *E, double *out) {
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < n; i++) out[i] = orc_kernel_deriv_beta(kind, xi, beta, E[i]);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -999,5 +1004,14 @@ int orc_num_threads(void) {
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+/* thread count of the following parallel loops (timing runs on fewer cores) */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
 #endif
 }

@@ -18,6 +18,16 @@ hipError_t launch_probe_copy(const float *src, float *dst, int64_t n, hipStream_
 hipError_t launch_probe_fill(float *dst, int64_t n, hipStream_t s);
 hipError_t launch_probe_fma32(float *out, int64_t threads, int iters, hipStream_t s);
 hipError_t launch_probe_fma64(double *out, int64_t threads, int iters, hipStream_t s);
+// 1D signal reconstruction (fit1d.hip)
+int fit1d_max_components();
+int fit1d_max_samples();
+hipError_t launch_fit1d(int kind, const KParams &kp, int batch, int n, int m, const float *x, const float *target,
+                        float *params, float *adam_m, float *adam_v, int steps, int step0, const float lr[3],
+                        float beta1, float beta2, float eps, float *loss, hipStream_t s);
+// psi calibration (psi.hip)
+size_t psi_workspace(int m, int n);
+hipError_t launch_psi_calibrate(int kind, const KParams &kp, int m, const double *sigma, int n, float margin, void *ws,
+                                double *cov2, double *fit, hipStream_t s);
 }  // namespace darb
 
 namespace {
@@ -50,16 +60,33 @@ darb_status hip_status(hipError_t e, const char *where) {
 
 darb_status check_kernel(const darb_kernel *k, darb::KParams *kp) {
     if (!k) return fail(DARB_ERR_INVALID_ARG, "null pointer: %s", "kernel");
-    if (k->kind < DARB_GAUSS || k->kind > DARB_PARABOLA) return fail(DARB_ERR_INVALID_ARG, "%s", "unknown kernel kind");
+    if (k->kind < DARB_GAUSS || k->kind > DARB_SINC_BETA) return fail(DARB_ERR_INVALID_ARG, "%s", "unknown kernel kind");
     if (!(k->xi > 0.0f) || !isfinite(k->xi)) return fail(DARB_ERR_INVALID_ARG, "%s", "kernel xi must be > 0");
     if (!(k->psi > 0.0f) || !isfinite(k->psi)) return fail(DARB_ERR_INVALID_ARG, "%s", "kernel psi must be > 0");
-    if (!(k->e_max > 0.0f) || !(k->e_max <= 9.0f))
-        return fail(DARB_ERR_INVALID_ARG, "%s", "kernel e_max must be in (0, 9] (binning radius is 3 sqrt(lambda_max))");
+    const bool modified = k->kind >= DARB_GAUSS_BETA;
+    if (modified) {
+        if (!(k->beta > 0.0f) || !(k->beta <= 8.0f))
+            return fail(DARB_ERR_INVALID_ARG, "%s", "modified kernel beta must be in (0, 8]");
+        if (!(k->e_max > 0.0f) || !(k->e_max <= 1024.0f))
+            return fail(DARB_ERR_INVALID_ARG, "%s", "modified kernel e_max must be in (0, 1024]");
+    } else {
+        if (!(k->e_max > 0.0f) || !(k->e_max <= 9.0f))
+            return fail(DARB_ERR_INVALID_ARG, "%s", "kernel e_max must be in (0, 9] for kinds 0..6");
+        // the series of the trigonometric profiles cover the main lobe only
+        const double xi = k->xi, em = k->e_max, tol = 1.0 + 1e-6;
+        if (k->kind == DARB_HALF_COS && em / xi > 0.5 * M_PI * tol)
+            return fail(DARB_ERR_INVALID_ARG, "%s", "half-cosine support beyond E/xi = pi/2 (use DARB_HALF_COS_BETA)");
+        if ((k->kind == DARB_RAISED_COS || k->kind == DARB_SINC) && sqrt(em) / xi > M_PI * tol)
+            return fail(DARB_ERR_INVALID_ARG, "%s", "support beyond sqrt(E)/xi = pi (use the modified kinds)");
+    }
     kp->inv_xi = 1.0f / k->xi;
     kp->inv_xi2 = kp->inv_xi * kp->inv_xi;
     kp->exp2_c = (float)(-1.4426950408889634 / (double)k->xi);
     kp->e_max = k->e_max;
     kp->psi = k->psi;
+    kp->rfac = k->e_max > 9.0f ? sqrtf(k->e_max) : 3.0f;
+    kp->beta_half = modified ? 0.5f * k->beta : 0.0f;
+    kp->family = modified ? k->kind - DARB_GAUSS_BETA : 0;
     return DARB_OK;
 }
 
@@ -255,7 +282,10 @@ darb_status check_views(const darb_view *views, int32_t nv, int64_t n, unsigned 
         it += tile_count(V.cam.width, V.cam.height);
     }
     if (rv) rv->nv = nv;
-    if (cams) cams->nv = nv;
+    if (cams) {
+        cams->nv = nv;
+        cams->dev = nullptr;
+    }
     if (items) *items = it;
     if (cap_total) *cap_total = cap;
     return DARB_OK;
@@ -648,6 +678,23 @@ darb_status darb_preprocess_multi(const darb_view *views, int32_t nv, const darb
                       "darb_preprocess_multi");
 }
 
+darb_status darb_preprocess_multi_cam_dev(const darb_view *views, int32_t nv, const darb_camera *cams_dev,
+                                          const darb_kernel *kernel, int64_t n, const darb_splats *in, void *stream) {
+    darb::KParams kp;
+    darb::Cams cams;
+    TRY(check_n(n));
+    TRY(check_kernel(kernel, &kp));
+    TRY(check_splats(in, n));
+    TRY(check_views(views, nv, n, kNeedProj, nullptr, &cams, nullptr, nullptr));
+    REQUIRE_PTR(cams_dev);
+    cams.dev = cams_dev;
+    darb::Projs outs{};
+    for (int v = 0; v < nv; v++) outs.p[v] = views[v].proj;
+    g_err[0] = 0;
+    return hip_status(darb::launch_preprocess_multi(cams, kp, (int)n, *in, outs, (hipStream_t)stream),
+                      "darb_preprocess_multi_cam_dev");
+}
+
 darb_status darb_raster_fwd_multi(const darb_view *views, int32_t nv, int64_t n, const darb_kernel *kernel,
                                   const darb_raster_opts *opts, void *stream) {
     darb::KParams kp;
@@ -739,3 +786,60 @@ darb_status darb_preprocess_bwd_multi(const darb_view *views, int32_t nv, const 
 }
 
 }  // extern "C"
+
+darb_status darb_fit1d(const darb_kernel *kernel, int32_t batch, int32_t n_comp, int32_t m, const float *x,
+                       const float *target, float *params, float *adam_m, float *adam_v, int32_t steps, int32_t step0,
+                       const float *lr, float beta1, float beta2, float eps, float *loss, void *stream) {
+    darb::KParams kp;
+    TRY(check_kernel(kernel, &kp));
+    if (batch < 0) return fail(DARB_ERR_INVALID_ARG, "%s", "batch must be >= 0");
+    if (n_comp < 1 || n_comp > darb::fit1d_max_components())
+        return fail(DARB_ERR_UNSUPPORTED, "%s", "n_comp must be in [1, 64]");
+    if (m < 1 || m > darb::fit1d_max_samples()) return fail(DARB_ERR_UNSUPPORTED, "%s", "m must be in [1, 4096]");
+    if (steps < 0 || step0 < 0) return fail(DARB_ERR_INVALID_ARG, "%s", "steps and step0 must be >= 0");
+    if (!lr) return fail(DARB_ERR_INVALID_ARG, "null pointer: %s", "lr");
+    if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps >= 0.0f))
+        return fail(DARB_ERR_INVALID_ARG, "%s", "Adam needs 0 <= beta1, beta2 < 1 and eps >= 0");
+    if (batch == 0 || steps == 0) return DARB_OK;
+    REQUIRE_PTR(x);
+    REQUIRE_PTR(target);
+    REQUIRE_PTR(params);
+    REQUIRE_PTR(adam_m);
+    REQUIRE_PTR(adam_v);
+    OPT_PTR(loss);
+    g_err[0] = 0;
+    return hip_status(darb::launch_fit1d(kernel->kind, kp, batch, n_comp, m, x, target, params, adam_m, adam_v, steps,
+                                         step0, lr, beta1, beta2, eps, loss, (hipStream_t)stream),
+                      "darb_fit1d");
+}
+
+size_t darb_psi_calibrate_workspace(int32_t m, int32_t grid_n) {
+    if (m < 0 || m > 65535 || grid_n < 5 || grid_n > 2049 || (grid_n & 1) == 0) return 0;
+    return darb::psi_workspace(m, grid_n);
+}
+
+darb_status darb_psi_calibrate(const darb_kernel *kernel, int32_t m, const double *sigma, int32_t grid_n, void *ws,
+                               size_t ws_bytes, double *cov2, double *fit, void *stream) {
+    darb::KParams kp;
+    TRY(check_kernel(kernel, &kp));
+    if (m < 0 || m > 65535) return fail(DARB_ERR_INVALID_ARG, "%s", "m must be in [0, 65535]");
+    if (grid_n < 5 || grid_n > 2049 || (grid_n & 1) == 0)
+        return fail(DARB_ERR_INVALID_ARG, "%s", "grid_n must be odd, in [5, 2049] (Simpson's rule)");
+    if (fit && m < 6) return fail(DARB_ERR_INVALID_ARG, "%s", "the 6-input fit needs m >= 6 samples");
+    if (m == 0) return DARB_OK;
+    REQUIRE_PTR(sigma);
+    REQUIRE_PTR(ws);
+    REQUIRE_PTR(cov2);
+    OPT_PTR(fit);
+    const size_t need = darb::psi_workspace(m, grid_n);
+    if (ws_bytes < need) {
+        snprintf(g_err, sizeof(g_err), "workspace too small: %zu < %zu bytes", ws_bytes, need);
+        return DARB_ERR_INVALID_ARG;
+    }
+    g_err[0] = 0;
+    const float margin = 1.0f + 2.0f / (float)(grid_n - 1);
+    return hip_status(darb::launch_psi_calibrate(kernel->kind, kp, m, sigma, grid_n, margin, ws, cov2, fit,
+                                                 (hipStream_t)stream),
+                      "darb_psi_calibrate");
+}
+

@@ -26,6 +26,9 @@ struct KParams {
     float exp2_c;   // -log2(e)/xi  (Gaussian: exp(-E/xi) = exp2(E * exp2_c))
     float e_max;
     float psi;
+    float rfac;       // binning radius in units of sqrt(lambda_max): 3, or sqrt(e_max) beyond E = 9
+    float beta_half;  // beta / 2 of the modified kinds
+    int family;       // modified kinds: 0 Gaussian, 1 half-cosine, 2 raised cosine, 3 sinc
 };
 
 struct ROpts {
@@ -118,9 +121,48 @@ __device__ __forceinline__ float sincd_series_full(float v) {
     return fmaf(p, v, -0.3333333333333333f);  // -2/3!
 }
 
+// Modified forms (Table 1, generic roll-off beta): u = E^(beta/2) / xi, one
+// template instantiation for the four families (kp.family is uniform per launch,
+// so the selection is a scalar branch).  sin/cos come from the device math
+// library: u may exceed the Taylor ranges above (several pulses).
+__device__ __forceinline__ float modified_u(float E, const KParams &kp) {
+    return E > 0.0f ? exp2f(kp.beta_half * log2f(E)) * kp.inv_xi : 0.0f;
+}
+
+__device__ __forceinline__ float modified_value(float u, const KParams &kp) {
+    switch (kp.family) {
+    case 0: return exp2f(-1.4426950408889634f * u);
+    case 1: return cosf(u);
+    case 2: return fmaf(0.5f, cosf(u), 0.5f);
+    default: return u < 1e-3f ? fmaf(-u * u, 0.16666666666666666f, 1.0f) : fabsf(sinf(u)) / u;
+    }
+}
+
+// dF/dE of the modified forms: dF/du * du/dE, du/dE = (beta/2) u / E (E > 0);
+// at E = 0: 1/xi dF/du(0) for beta = 2, else 0.
+__device__ __forceinline__ float modified_deriv(float E, float u, float w, const KParams &kp) {
+    float dF;
+    switch (kp.family) {
+    case 0: dF = -w; break;
+    case 1: dF = -sinf(u); break;
+    case 2: dF = -0.5f * sinf(u); break;
+    default: {
+        float s, c;
+        sincosf(u, &s, &c);
+        const float g = u < 1e-3f ? -u * 0.3333333333333333f : (u * c - s) / (u * u);
+        dF = (u < 1e-3f || s >= 0.0f) ? g : -g;
+    }
+    }
+    const float du = E > 0.0f ? kp.beta_half * u / E : (kp.beta_half == 1.0f ? kp.inv_xi : 0.0f);
+    // at E = 0 with beta = 2, dF/du(0) = -1 (Gaussian) or 0 (the trigonometric families)
+    return dF * du;
+}
+
 template <int KIND>
 __device__ __forceinline__ float profile(float E, const KParams &kp) {
-    if constexpr (KIND == DARB_GAUSS) {
+    if constexpr (KIND >= DARB_GAUSS_BETA) {
+        return modified_value(modified_u(E, kp), kp);
+    } else if constexpr (KIND == DARB_GAUSS) {
         return __builtin_amdgcn_exp2f(E * kp.exp2_c);
     } else if constexpr (KIND == DARB_HALF_COS) {
         float x = E * kp.inv_xi;
@@ -141,7 +183,9 @@ __device__ __forceinline__ float profile(float E, const KParams &kp) {
 // dF/dE given E and the profile value w = F(E).
 template <int KIND>
 __device__ __forceinline__ float profile_deriv(float E, float w, const KParams &kp) {
-    if constexpr (KIND == DARB_GAUSS) {
+    if constexpr (KIND >= DARB_GAUSS_BETA) {
+        return modified_deriv(E, modified_u(E, kp), w, kp);
+    } else if constexpr (KIND == DARB_GAUSS) {
         return -w * kp.inv_xi;
     } else if constexpr (KIND == DARB_HALF_COS) {
         float x = E * kp.inv_xi;
@@ -288,6 +332,7 @@ struct RViews {
 struct Cams {
     Cam c[kMaxViews];
     int nv;
+    const darb_camera *dev;  // nullable: cameras read from device memory (c[] then only sizes the grid)
 };
 
 struct Projs {

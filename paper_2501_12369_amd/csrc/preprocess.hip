@@ -263,7 +263,7 @@ __device__ __forceinline__ bool project_rest(const Cam &cam, const KParams &kp, 
     float mid = 0.5f * (P.c00 + P.c11);
     float disc = fmaf(mid, mid, -P.det);
     float lam = mid + sqrtf(fmaxf(disc, 0.0f));
-    P.radius = (int)ceilf(3.0f * sqrtf(lam));
+    P.radius = (int)ceilf(kp.rfac * sqrtf(lam));
     // radius box on the tile grid (same FP32 expression as the binning)
     int gx = (cam.width + kTile - 1) / kTile, gy = (cam.height + kTile - 1) / kTile;
     float r = (float)P.radius;
@@ -484,20 +484,25 @@ __global__ __launch_bounds__(256) void k_preprocess_multi(Cams cams, KParams kp,
         load_sh<NB>(in.sh, n, i, c);
         op = in.opacity[i];
     }
-    for (int v = 0; v < cams.nv; v++) {
-        const Cam &cam = cams.c[v];
+    auto one_view = [&](const Cam &cam, const darb_projected &out) {
         Proj P;
         const bool vis = geom && view_depth(cam, m, P) && project_rest(cam, kp, G, P);
         float col[3] = {0.0f, 0.0f, 0.0f};
         float jac[9] = {};
         uint8_t cl = 0;
         if (vis) {
-            if (outs.p[v].dcolor)
+            if (out.dcolor)
                 sh_colour<NB, true>(cam, m, c, col, cl, jac);
             else
                 sh_colour<NB, false>(cam, m, c, col, cl, jac);
         }
-        store_proj(outs.p[v], n, i, vis, P, vis ? op : 0.0f, col, cl, jac);
+        store_proj(out, n, i, vis, P, vis ? op : 0.0f, col, cl, jac);
+    };
+    for (int v = 0; v < cams.nv; v++) {
+        if (cams.dev)
+            one_view(cam_from_device(cams.dev + v, cams.c[v].width, cams.c[v].height), outs.p[v]);
+        else
+            one_view(cams.c[v], outs.p[v]);
     }
 }
 

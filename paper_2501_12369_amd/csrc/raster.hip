@@ -657,7 +657,8 @@ size_t det_workspace(uint32_t items, uint64_t capacity) { return det_layout(item
     case DARB_SINC: F<DARB_SINC> __VA_ARGS__; break;       \
     case DARB_IMQ: F<DARB_IMQ> __VA_ARGS__; break;         \
     case DARB_IMQ_SQRT: F<DARB_IMQ_SQRT> __VA_ARGS__; break; \
-    default: F<DARB_PARABOLA> __VA_ARGS__; break;          \
+    case DARB_PARABOLA: F<DARB_PARABOLA> __VA_ARGS__; break; \
+    default: F<DARB_GAUSS_BETA> __VA_ARGS__; break;        \
     }
 
 namespace {

@@ -19,14 +19,16 @@ c_float, c_int32, c_int64, c_void_p, c_size_t = (ctypes.c_float, ctypes.c_int32,
 
 DARB_OK, DARB_ERR_INVALID_ARG, DARB_ERR_CAPACITY, DARB_ERR_HIP, DARB_ERR_UNSUPPORTED = range(5)
 GAUSS, HALF_COS, RAISED_COS, SINC, IMQ, IMQ_SQRT, PARABOLA = range(7)
+GAUSS_BETA, HALF_COS_BETA, RAISED_COS_BETA, SINC_BETA = range(7, 11)  # Table 1's modified forms, generic beta
 LOSS_L1, LOSS_L2 = 0, 1
 MAX_VIEWS = 16
 LOSS_WS_BYTES = 4096
 
 EXPORTED = ("darb_version", "darb_status_string", "darb_last_error", "darb_preprocess", "darb_preprocess_parts", "darb_preprocess_cam_dev",
-            "darb_bin_sort_workspace", "darb_bin_sort", "darb_raster_fwd", "darb_raster_bwd",
+            "darb_bin_sort_workspace", "darb_bin_sort", "darb_fit1d", "darb_psi_calibrate_workspace",
+            "darb_psi_calibrate", "darb_raster_fwd", "darb_raster_bwd",
             "darb_raster_bwd_workspace", "darb_preprocess_bwd", "darb_image_loss", "darb_preprocess_multi",
-            "darb_raster_fwd_multi", "darb_raster_bwd_multi", "darb_raster_bwd_multi_workspace",
+            "darb_raster_fwd_multi", "darb_preprocess_multi_cam_dev", "darb_raster_bwd_multi", "darb_raster_bwd_multi_workspace",
             "darb_raster_fwdbwd_multi", "darb_preprocess_bwd_multi", "darb_ssim_loss_workspace", "darb_ssim_loss",
             "darb_adam", "darb_densify_stats", "darb_probe_copy", "darb_probe_fill", "darb_probe_fma")
 MAX_ADAM_GROUPS = 8
@@ -45,7 +47,7 @@ class darb_camera(ctypes.Structure):
 
 
 class darb_kernel(ctypes.Structure):
-    _fields_ = [("kind", c_int32), ("xi", c_float), ("psi", c_float), ("e_max", c_float)]
+    _fields_ = [("kind", c_int32), ("xi", c_float), ("psi", c_float), ("e_max", c_float), ("beta", c_float)]
 
 
 class darb_raster_opts(ctypes.Structure):
@@ -117,6 +119,14 @@ def lib():
         L.darb_bin_sort.restype = c_int32
         L.darb_bin_sort.argtypes = [P(darb_projected), c_int64, c_int32, c_int32, c_int64, c_void_p, c_size_t,
                                     c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, P(c_int64), c_void_p]
+        L.darb_fit1d.restype = c_int32
+        L.darb_fit1d.argtypes = [P(darb_kernel), c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                                 c_void_p, c_int32, c_int32, P(c_float), c_float, c_float, c_float, c_void_p, c_void_p]
+        L.darb_psi_calibrate_workspace.restype = c_size_t
+        L.darb_psi_calibrate_workspace.argtypes = [c_int32, c_int32]
+        L.darb_psi_calibrate.restype = c_int32
+        L.darb_psi_calibrate.argtypes = [P(darb_kernel), c_int32, c_void_p, c_int32, c_void_p, c_size_t, c_void_p,
+                                         c_void_p, c_void_p]
         L.darb_raster_fwd.restype = c_int32
         L.darb_raster_fwd.argtypes = [P(darb_projected), c_int64, c_void_p, c_void_p, c_void_p, c_int32, c_int32,
                                       P(darb_kernel), P(darb_raster_opts), c_void_p, c_void_p, c_void_p, c_void_p,
@@ -142,6 +152,9 @@ def lib():
                                       c_size_t, c_void_p]
         L.darb_preprocess_multi.restype = c_int32
         L.darb_preprocess_multi.argtypes = [P(darb_view), c_int32, P(darb_kernel), c_int64, P(darb_splats), c_void_p]
+        L.darb_preprocess_multi_cam_dev.restype = c_int32
+        L.darb_preprocess_multi_cam_dev.argtypes = [P(darb_view), c_int32, c_void_p, P(darb_kernel), c_int64,
+                                                    P(darb_splats), c_void_p]
         L.darb_raster_fwd_multi.restype = c_int32
         L.darb_raster_fwd_multi.argtypes = [P(darb_view), c_int32, c_int64, P(darb_kernel), P(darb_raster_opts),
                                             c_void_p]
@@ -217,7 +230,7 @@ def camera_struct(cam: dict) -> darb_camera:
 
 
 def kernel_struct(k) -> darb_kernel:
-    return darb_kernel(int(k.kind), float(k.xi), float(k.psi), float(k.e_max))
+    return darb_kernel(int(k.kind), float(k.xi), float(k.psi), float(k.e_max), float(getattr(k, "beta", 0.0)))
 
 
 def opts_struct(o: dict | None = None) -> darb_raster_opts:
@@ -308,6 +321,25 @@ def darb_bin_sort(proj: dict, n: int, width: int, height: int, k_capacity: int, 
     return int(kh.value) if read_k else None
 
 
+def darb_fit1d(kernel, batch: int, n_comp: int, m: int, x, target, params, adam_m, adam_v, steps: int, step0: int,
+               lr, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, loss=None, stream=None):
+    k = kernel_struct(kernel)
+    lr3 = (c_float * 3)(*[float(v) for v in lr])
+    _check(lib().darb_fit1d(ctypes.byref(k), batch, n_comp, m, _ptr(x), _ptr(target), _ptr(params), _ptr(adam_m),
+                            _ptr(adam_v), steps, step0, lr3, beta1, beta2, eps, _ptr(loss), _stream(stream)),
+           "darb_fit1d")
+
+
+def darb_psi_calibrate_workspace(m: int, grid_n: int) -> int:
+    return int(lib().darb_psi_calibrate_workspace(m, grid_n))
+
+
+def darb_psi_calibrate(kernel, m: int, sigma, grid_n: int, ws, cov2, fit=None, stream=None):
+    k = kernel_struct(kernel)
+    _check(lib().darb_psi_calibrate(ctypes.byref(k), m, _ptr(sigma), grid_n, _ptr(ws), _nbytes(ws), _ptr(cov2),
+                                    _ptr(fit), _stream(stream)), "darb_psi_calibrate")
+
+
 def darb_raster_fwd(proj: dict, n: int, vals, ranges, overflow_dev, width: int, height: int, kernel, opts: dict,
                     image, final_T, last, n_contrib=None, zero_g2d: dict | None = None, stream=None):
     p, k, o = projected_struct(proj), kernel_struct(kernel), opts_struct(opts)
@@ -389,6 +421,14 @@ def darb_preprocess_multi(views: list, kernel, n: int, splats: dict, stream=None
     a, k, s = views_array(views), kernel_struct(kernel), splats_struct(splats)
     _check(lib().darb_preprocess_multi(a, len(views), ctypes.byref(k), n, ctypes.byref(s), _stream(stream)),
            "darb_preprocess_multi")
+
+
+def darb_preprocess_multi_cam_dev(views: list, cams_dev, kernel, n: int, splats: dict, stream=None):
+    """darb_preprocess_multi with view v's camera read from cams_dev (device bytes
+    holding len(views) darb_camera structs)."""
+    a, k, s = views_array(views), kernel_struct(kernel), splats_struct(splats)
+    _check(lib().darb_preprocess_multi_cam_dev(a, len(views), _ptr(cams_dev), ctypes.byref(k), n, ctypes.byref(s),
+                                               _stream(stream)), "darb_preprocess_multi_cam_dev")
 
 
 def darb_raster_fwd_multi(views: list, n: int, kernel, opts: dict, stream=None):

@@ -26,6 +26,24 @@ class KernelSpec:
     xi: float
     psi: float
     e_max: float
+    beta: float = 0.0  # roll-off of the modified kinds (GAUSS_BETA .. SINC_BETA)
+
+
+# Domain limit U of u = d_M^beta / xi for the modified forms (Table 1): one
+# half-cosine lobe, n raised-cosine pulses, n sinc pulses; the Gaussian has no
+# limit and keeps the 3-sigma box of the fixed kernels (E <= 9).
+def modified_e_max(kind: int, xi: float, beta: float, pulses: int = 1) -> float:
+    U = {native.HALF_COS_BETA: 0.5 * math.pi, native.RAISED_COS_BETA: pulses * math.pi,
+         native.SINC_BETA: 0.5 * (pulses + 1) * math.pi}.get(kind)
+    if U is None:
+        return 9.0
+    return (xi * U) ** (2.0 / beta)
+
+
+def modified_kernel(kind: int, xi: float, beta: float, psi: float, pulses: int = 1) -> KernelSpec:
+    """A modified DARBF of Table 1 with roll-off ``beta`` and its support of
+    ``pulses`` lobes (raised cosine, sinc)."""
+    return KernelSpec(kind, xi, psi, modified_e_max(kind, xi, beta, pulses), beta)
 
 
 KERNELS = {
@@ -37,6 +55,19 @@ KERNELS = {
     "imq_sqrt": KernelSpec(native.IMQ_SQRT, 1.0, 1.61, 9.0),
     "parabola": KernelSpec(native.PARABOLA, 9.0, 1.3, 9.0),
 }
+# Modified forms of Table 1 (generic roll-off, several pulses).  psi is the
+# marginal-covariance ratio of each form as the correction-factor experiment
+# on the GPU (calibrate.calibrate_psi, 1000 covariances, 97^3 grid) measures it.
+KERNELS.update({
+    # exp(-d_M^4 / 2), the 3-sigma box of the Gaussian
+    "gauss_b4": modified_kernel(native.GAUSS_BETA, 2.0, 4.0, 0.349),
+    # cos(d_M / xi) on its main lobe, xi = 6/pi: the lobe ends at d_M = 3 like the half-cosine's
+    "half_cos_b1": modified_kernel(native.HALF_COS_BETA, 6.0 / math.pi, 1.0, 1.247),
+    # the raised cosine of the listings (beta = 1, xi = 2.5/pi) with two pulses: d_M <= 5
+    "raised_cos_n2": modified_kernel(native.RAISED_COS_BETA, 2.5 / math.pi, 1.0, 6.205, pulses=2),
+    # the modular sinc of the listings (beta = 1, xi = 3/pi) with three pulses: d_M <= 6
+    "sinc_n3": modified_kernel(native.SINC_BETA, 3.0 / math.pi, 1.0, 5.676, pulses=3),
+})
 
 DEFAULT_OPTS = dict(alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4, bg=(0.0, 0.0, 0.0))
 

@@ -253,3 +253,37 @@ def covariances(seed: int, m: int, scale_range=(0.5, 2.0)) -> np.ndarray:
         S = (q * s ** 2) @ q.T
         out[i] = [S[0, 0], S[0, 1], S[0, 2], S[1, 1], S[1, 2], S[2, 2]]
     return out
+
+
+# --------------------------------------------------------------------------
+# 1D signal reconstruction (the paper's 1D simulations): target pulses and
+# initial mixtures
+# --------------------------------------------------------------------------
+
+SIGNALS_1D = ("square", "triangle", "gaussian", "half_sine", "sharp_exponential", "parabola", "trapezoid")
+
+
+def signals1d(m: int = 1024):
+    """x in [-1, 1] (m samples) and the seven target pulses of the paper's 1D
+    simulations (square, triangle, Gaussian, half-sinusoid, sharp exponential,
+    parabolic, trapezoid), each of height 1 centred at 0; FP32."""
+    x = np.linspace(-1.0, 1.0, m)
+    ax = np.abs(x)
+    sig = dict(
+        square=(ax <= 0.4).astype(np.float64),
+        triangle=np.clip(1.0 - ax / 0.6, 0.0, None),
+        gaussian=np.exp(-0.5 * (x / 0.2) ** 2),
+        half_sine=np.where(ax <= 0.5, np.cos(np.pi * x), 0.0),
+        sharp_exponential=np.exp(-ax / 0.1),
+        parabola=np.clip(1.0 - (x / 0.5) ** 2, 0.0, None),
+        trapezoid=np.clip((0.7 - ax) / 0.3, 0.0, 1.0),
+    )
+    return x.astype(np.float32), {k: v.astype(np.float32) for k, v in sig.items()}
+
+
+def fit1d_init(seed: int, n: int) -> np.ndarray:
+    """Initial mixture [3, n]: means uniform in [-0.8, 0.8], log sigma = log 0.15,
+    amplitudes 0.3; FP32."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mu = np.sort(rng.uniform(-0.8, 0.8, n))
+    return np.stack([mu, np.full(n, math.log(0.15)), np.full(n, 0.3)]).astype(np.float32)

@@ -1,20 +1,24 @@
 """Continuous-batching render server (forward only) over libdarb.
 
-Scenes stay resident in HBM.  A request (scene, camera, W x H) runs as one
-replay of a captured HIP graph of preprocess (camera read from a device
-buffer) -> bin/sort (no host readback) -> raster forward on a *render slot*:
-buffers sized for its (scene, W, H) key, a device camera buffer and a stream
-of its own.
+Scenes stay resident in HBM.  Requests of one (scene, W, H) key are batched:
+a *render slot* holds the buffers of up to B views of its key, a device array
+of B cameras, a stream, and one captured HIP graph per batch size b = 1..B of
+the multi-view forward -- one preprocess launch over the b views (cameras read
+from the device array) -> a bin/sort per view (no host readback) -> one raster
+launch over the tiles of all b views.  A replay renders every request of the
+batch; an image in a batch has the bits of the same request rendered alone
+(every launch is atomic-free and per view).
 
-Admission is by memory: a request starts when an idle slot of its key exists,
-or when a new slot fits in the memory budget (idle slots of other keys are
-freed, least recently used first, to make room); otherwise it waits, first in
-first out.  Requests that arrive while others run are admitted as slots and
-memory free up, and their graphs run concurrently on separate streams.  The
-instance count K is decided on the device before any instance is written, so a
-too-small capacity only sets a flag; the server checks it at completion,
-renders that request again outside the graph with a larger capacity, and
-re-captures the slot.
+Admission is by memory: the oldest waiting request starts when an idle slot of
+its key exists, or when a new slot fits in the memory budget (idle slots of
+other keys are freed, least recently used first, to make room), and takes up
+to B-1 more waiting requests of its key into the same replay; otherwise it
+waits, first in first out.  Requests that arrive while others run are admitted
+as slots and memory free up, and the graphs of several slots run concurrently
+on separate streams.  The instance count K is decided on the device before any
+instance is written, so a too-small capacity only sets a flag; the server
+checks it at completion, grows the slot, re-captures its graphs and renders
+that batch again.
 
 The scheduling core (:class:`Scheduler`) takes a slot factory, so the policy can
 be exercised without a GPU.
@@ -96,13 +100,16 @@ def summarize(results, wall_s, retries, peak_slots, peak_bytes, evictions, peak_
 
 
 class Scheduler:
-    """FIFO admission by memory over slots made by ``factory``.
+    """FIFO admission by memory over slots made by ``factory``, with batching.
 
     ``factory(key, capacity_hint)`` returns a slot with attributes ``key``,
-    ``nbytes`` and methods ``launch(request)``, ``poll() -> bool`` (finished),
-    ``finish() -> (ok, K)`` (ok False when the capacity overflowed; then K is
-    the count needed), ``rerun(request, K)`` (blocking re-render with room for K)
-    and ``free()``.  ``need(key)`` estimates a new slot's bytes.
+    ``nbytes``, ``max_batch`` (requests per launch, optional: 1) and methods
+    ``launch(requests)`` (a list of 1..max_batch requests of the slot's key),
+    ``poll() -> bool`` (finished), ``finish() -> (ok, K)`` (ok False when a
+    capacity overflowed; then K is the largest count needed),
+    ``rerun(requests, K)`` (blocking re-render with room for K),
+    ``image_copy(i)`` (image of the i-th request of the batch) and ``free()``.
+    ``need(key)`` estimates a new slot's bytes.
     """
 
     def __init__(self, factory, need, mem_budget: int, max_slots: int = 8, clock=time.perf_counter,
@@ -124,6 +131,8 @@ class Scheduler:
         self.peak_bytes = 0
         self.evictions = 0
         self.retries = 0
+        self.peak_batch = 0
+        self.batch_limit = None  # cap on requests per launch (None: each slot's max_batch)
 
     def _evict_for(self, need_bytes: int, keep_key) -> bool:
         for key in list(self.idle.keys()):
@@ -175,6 +184,7 @@ class Scheduler:
         # statistics of this run only
         retries0, evictions0 = self.retries, self.evictions
         self.peak_slots, self.peak_bytes = self.n_slots, self.mem_used
+        self.peak_batch = 0
         peak_inflight = 0
         t0 = self.clock()
         while pending or queue or self.busy:
@@ -186,7 +196,7 @@ class Scheduler:
             # requests that wait for a busy slot of their key (order kept per key)
             i = 0
             blocked = set()
-            while i < min(len(queue), self.lookahead) and len(self.busy) < self.max_inflight:
+            while i < min(len(queue), self.lookahead) and sum(len(b) for _, b, _ in self.busy) < self.max_inflight:
                 r = queue[i]
                 s = None if r.key in blocked else self.acquire(r)
                 if s is None:
@@ -194,12 +204,25 @@ class Scheduler:
                     i += 1
                     continue
                 del queue[i]
-                s.launch(r)
-                self.busy.append((s, r, self.clock() - t0))
-                peak_inflight = max(peak_inflight, len(self.busy))
+                batch = [r]
+                # continuous batching: waiting requests of the same key join the launch
+                j = i
+                limit = getattr(s, "max_batch", 1)
+                if self.batch_limit is not None:
+                    limit = min(limit, self.batch_limit)
+                while len(batch) < limit and j < min(len(queue), self.lookahead):
+                    if queue[j].key == r.key:
+                        batch.append(queue[j])
+                        del queue[j]
+                    else:
+                        j += 1
+                s.launch(batch)
+                self.busy.append((s, batch, self.clock() - t0))
+                peak_inflight = max(peak_inflight, sum(len(b) for _, b, _ in self.busy))
+                self.peak_batch = max(self.peak_batch, len(batch))
                 progressed = True
             still = []
-            for s, req, start in self.busy:
+            for s, batch, start in self.busy:
                 if s.poll():
                     ok, K = s.finish()
                     retried = False
@@ -207,17 +230,18 @@ class Scheduler:
                         self.retries += 1
                         retried = True
                         old = s.nbytes
-                        s.rerun(req, K)
+                        s.rerun(batch, K)
                         self.mem_used += s.nbytes - old
                         self.peak_bytes = max(self.peak_bytes, self.mem_used)
                     end = self.clock() - t0
-                    results.append(Result(req.rid, req.key, req.arrival, start, end, req.pixels, retried,
-                                          s.image_copy() if keep_images else None,
-                                          s.counts() if hasattr(s, "counts") else None))
+                    for q, req in enumerate(batch):
+                        results.append(Result(req.rid, req.key, req.arrival, start, end, req.pixels, retried,
+                                              s.image_copy(q) if keep_images else None,
+                                              s.counts(q) if hasattr(s, "counts") else None))
                     self.release(s)
                     progressed = True
                 else:
-                    still.append((s, req, start))
+                    still.append((s, batch, start))
             self.busy = still
             if not progressed:
                 if not self.busy and not queue and pending:
@@ -225,8 +249,10 @@ class Scheduler:
                 else:
                     self.sleep(poll_sleep)
         wall = max(r.end for r in results) - min(r.arrival for r in results) if results else 0.0
-        return results, summarize(results, max(wall, 1e-9), self.retries - retries0, self.peak_slots,
-                                  self.peak_bytes, self.evictions - evictions0, peak_inflight)
+        st = summarize(results, max(wall, 1e-9), self.retries - retries0, self.peak_slots, self.peak_bytes,
+                       self.evictions - evictions0, peak_inflight)
+        st.extra["peak_batch"] = self.peak_batch
+        return results, st
 
 
 # ---------------------------------------------------------------------------
@@ -238,7 +264,8 @@ def _round16(n: int) -> int:
 
 
 class RenderSlot:
-    """Buffers, device camera, stream and captured graph of one (scene, W, H) key."""
+    """Buffers of up to ``max_batch`` views of one (scene, W, H) key, a device
+    array of their cameras, a stream, and a captured graph per batch size."""
 
     def __init__(self, server, key, capacity: int):
         import torch
@@ -252,93 +279,124 @@ class RenderSlot:
         self.splats = server.scenes[scene_id]
         self.n = int(self.splats["means"].shape[1])
         self.W, self.H = W, H
+        self.max_batch = server.max_batch
+        B = self.max_batch
         self.stream = torch.cuda.Stream()
-        self.cam_dev = torch.zeros(_round16(native.CAMERA_NBYTES), dtype=torch.uint8, device="cuda")
-        self.cam_host = torch.zeros(_round16(native.CAMERA_NBYTES), dtype=torch.uint8, pin_memory=True)
-        self.ovf_host = torch.zeros(4, dtype=torch.int32, pin_memory=True)
-        self.k_host = torch.zeros(2, dtype=torch.int64, pin_memory=True)
+        cb = native.CAMERA_NBYTES  # a multiple of 16: the array keeps every camera aligned
+        self.cams_dev = torch.zeros(B * cb, dtype=torch.uint8, device="cuda")
+        self.cams_host = torch.zeros(B * cb, dtype=torch.uint8, pin_memory=True)
+        self.ovf_dev = torch.zeros((B, 4), dtype=torch.int32, device="cuda")
+        self.k_dev = torch.zeros((B, 2), dtype=torch.int64, device="cuda")
+        self.ovf_host = torch.zeros((B, 4), dtype=torch.int32, pin_memory=True)
+        self.k_host = torch.zeros((B, 2), dtype=torch.int64, pin_memory=True)
+        # a valid camera of this size for the host-side checks (the device cameras are used)
+        self.template = server.probe_camera(W, H)
         self.done = torch.cuda.Event()
+        self.batch = 0
         self._alloc(capacity)
 
     def _alloc(self, capacity: int):
-        torch, pipeline = self.torch, self.pipeline
-        self.graph = None
-        self.frame = None
-        self.frame = pipeline.alloc_frame(self.n, self.W, self.H, capacity, "cuda", dcolor=False)
-        self.nbytes = self.server.slot_bytes(self.n, self.W, self.H, capacity)
+        pipeline = self.pipeline
+        self.graphs = None
+        self.frames = None
+        self.frames = [pipeline.alloc_frame(self.n, self.W, self.H, capacity, "cuda", dcolor=False)
+                       for _ in range(self.max_batch)]
+        for v, fr in enumerate(self.frames):  # per-view flags and counts in the slot's own arrays
+            fr.overflow = self.ovf_dev[v]
+            fr.k_dev = self.k_dev[v]
+        self.views = [dict(cam=self.template, proj=fr.proj, k_capacity=fr.capacity, vals=fr.vals, ranges=fr.ranges,
+                           overflow_dev=fr.overflow, image=fr.image, final_T=fr.final_T, last=fr.last)
+                      for fr in self.frames]
+        self.nbytes = self.max_batch * self.server.slot_bytes(self.n, self.W, self.H, capacity)
         self._capture()
 
-    def _enqueue(self):
-        native, fr, srv = self.native, self.frame, self.server
-        native.darb_preprocess_cam_dev(self.cam_dev, self.W, self.H, srv.kernel, self.n, self.splats, fr.proj)
-        native.darb_bin_sort(fr.proj, self.n, self.W, self.H, fr.capacity, fr.ws, None, fr.vals, fr.ranges, fr.k_dev,
-                             fr.overflow)
-        native.darb_raster_fwd(fr.proj, self.n, fr.vals, fr.ranges, fr.overflow, self.W, self.H, srv.kernel, srv.opts,
-                               fr.image, fr.final_T, fr.last, None)
+    def _enqueue(self, b: int):
+        native, srv = self.native, self.server
+        native.darb_preprocess_multi_cam_dev(self.views[:b], self.cams_dev, srv.kernel, self.n, self.splats)
+        for fr in self.frames[:b]:
+            native.darb_bin_sort(fr.proj, self.n, self.W, self.H, fr.capacity, fr.ws, None, fr.vals, fr.ranges,
+                                 fr.k_dev, fr.overflow)
+        native.darb_raster_fwd_multi(self.views[:b], self.n, srv.kernel, srv.opts)
 
     def _capture(self):
         torch = self.torch
-        with torch.cuda.stream(self.stream):
-            self._enqueue()  # warm-up outside the graph
-        self.stream.synchronize()
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g, stream=self.stream):
-            self._enqueue()
-        self.graph = g
+        self._write_cameras([self.template] * self.max_batch)
+        self.cams_dev.copy_(self.cams_host)
+        graphs = {}
+        for b in range(1, self.max_batch + 1):
+            with torch.cuda.stream(self.stream):
+                self._enqueue(b)  # warm-up outside the graph
+            self.stream.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=self.stream):
+                self._enqueue(b)
+            graphs[b] = g
+        self.graphs = graphs
 
-    def _write_camera(self, cam: dict):
-        b = np.frombuffer(self.native.camera_bytes(cam), dtype=np.uint8)
-        self.cam_host.numpy()[: len(b)] = b
+    def _write_cameras(self, cams: list):
+        cb = self.native.CAMERA_NBYTES
+        host = self.cams_host.numpy()
+        for v, cam in enumerate(cams):
+            host[v * cb:(v + 1) * cb] = np.frombuffer(self.native.camera_bytes(cam), dtype=np.uint8)
 
-    def launch(self, req: Request):
+    def launch(self, reqs: list):
         torch = self.torch
-        self._write_camera(req.camera)
+        b = len(reqs)
+        self.batch = b
+        self._write_cameras([r.camera for r in reqs])
         with torch.cuda.stream(self.stream):
-            self.cam_dev.copy_(self.cam_host, non_blocking=True)
-            self.graph.replay()
-            self.ovf_host[0:1].copy_(self.frame.overflow[0:1], non_blocking=True)
-            self.k_host.copy_(self.frame.k_dev[0:2], non_blocking=True)
+            self.cams_dev.copy_(self.cams_host, non_blocking=True)
+            self.graphs[b].replay()
+            self.ovf_host.copy_(self.ovf_dev, non_blocking=True)
+            self.k_host.copy_(self.k_dev, non_blocking=True)
             self.done.record(self.stream)
 
     def poll(self) -> bool:
         return self.done.query()
 
     def finish(self):
-        return int(self.ovf_host[0]) == 0, int(self.k_host[0])
+        b = self.batch
+        ok = all(int(self.ovf_host[v, 0]) == 0 for v in range(b))
+        return ok, max(int(self.k_host[v, 0]) for v in range(b))
 
-    def counts(self):
-        """(K, N_v) of the last completed render."""
-        return int(self.k_host[0]), int(self.k_host[1])
+    def counts(self, i: int = 0):
+        """(K, N_v) of the i-th render of the last completed batch."""
+        return int(self.k_host[i, 0]), int(self.k_host[i, 1])
 
-    def rerun(self, req: Request, K: int):
-        """Capacity overflow: grow, re-capture, render again (blocking)."""
+    def rerun(self, reqs: list, K: int):
+        """Capacity overflow: grow, re-capture, render the batch again (blocking)."""
         self.server.cap_hint[self.key] = max(self.server.cap_hint.get(self.key, 0), K)
         self._alloc(int(K * self.server.k_margin) + 4096)
-        self.launch(req)
+        self.launch(reqs)
         self.done.synchronize()
 
-    def image_copy(self):
+    def image_copy(self, i: int = 0):
         # copied on the slot's stream, so the slot's next replay cannot overwrite
         # the image before the copy has read it; returned ready to use
         with self.torch.cuda.stream(self.stream):
-            img = self.frame.image.clone()
+            img = self.frames[i].image.clone()
         self.stream.synchronize()
         return img
 
     def free(self):
-        self.graph = None
-        self.frame = None
+        self.graphs = None
+        self.frames = None
+        self.views = None
 
 
 class RenderServer:
     """Scenes resident on the GPU + a :class:`Scheduler` of :class:`RenderSlot`s."""
 
     def __init__(self, scenes: list, kernel, opts: dict | None = None, mem_budget: int = 24 << 30,
-                 max_slots: int = 8, k_margin: float = 1.5, n_probe: int = 4, max_inflight: int | None = None):
+                 max_slots: int = 8, k_margin: float = 1.5, n_probe: int = 4, max_inflight: int | None = None,
+                 max_batch: int = 4):
         from . import pipeline
 
+        if not 1 <= max_batch <= 16:
+            raise ValueError("max_batch must be in [1, 16] (views per multi-view launch)")
         self.scenes = scenes
         self.kernel = kernel
+        self.max_batch = int(max_batch)
         self.opts = opts or pipeline.DEFAULT_OPTS
         self.k_margin = k_margin
         self.n_probe = n_probe
@@ -380,10 +438,13 @@ class RenderServer:
         rng = np.random.Generator(np.random.PCG64(W * 7919 + H))
         return [scenes.orbit_camera(rng, W, H) for _ in range(n)]
 
+    def probe_camera(self, W: int, H: int) -> dict:
+        return self._probe_cameras(W, H, 1)[0]
+
     def _need(self, key) -> int:
         scene_id, W, H = key
         n = int(self.scenes[scene_id]["means"].shape[1])
-        return self.slot_bytes(n, W, H, self._capacity(key))
+        return self.max_batch * self.slot_bytes(n, W, H, self._capacity(key))
 
     def _make_slot(self, key, _hint):
         return RenderSlot(self, key, self._capacity(key))
@@ -393,15 +454,15 @@ class RenderServer:
 
 
 def sequential_baseline(server: RenderServer, requests, keep_images: bool = False):
-    """One request at a time: the server's own slots and graphs (no new captures
-    once warm), a single request in flight."""
+    """One request at a time: the server's own slots and graphs (the batch-of-one
+    graph, no new captures once warm), a single request in flight."""
     sched = server.sched
-    saved = sched.max_inflight
-    sched.max_inflight = 1
+    saved = sched.max_inflight, sched.batch_limit
+    sched.max_inflight, sched.batch_limit = 1, 1
     try:
         return sched.run(requests, keep_images=keep_images)
     finally:
-        sched.max_inflight = saved
+        sched.max_inflight, sched.batch_limit = saved
 
 
 def make_requests(seed: int, n: int, rate_hz: float, n_scenes: int) -> list:

@@ -22,6 +22,11 @@ ORACLE_KERNELS = {
     "imq": oracle.KernelSpec(oracle.IMQ, 1.0, 1.38, 9.0),
     "imq_sqrt": oracle.KernelSpec(oracle.IMQ_SQRT, 1.0, 1.61, 9.0),
     "parabola": oracle.KernelSpec(oracle.PARABOLA, 9.0, 1.3, 9.0),
+    # Table 1's modified forms: support u = d_M^beta / xi <= U, i.e. E <= (xi U)^(2/beta)
+    "gauss_b4": oracle.KernelSpec(oracle.GAUSS_BETA, 2.0, 0.349, 9.0, 4.0),
+    "half_cos_b1": oracle.KernelSpec(oracle.HALF_COS_BETA, 6.0 / PI, 1.247, (6.0 / PI * PI / 2) ** 2, 1.0),
+    "raised_cos_n2": oracle.KernelSpec(oracle.RAISED_COS_BETA, 2.5 / PI, 6.205, (2.5 / PI * 2 * PI) ** 2, 1.0),
+    "sinc_n3": oracle.KernelSpec(oracle.SINC_BETA, 3.0 / PI, 5.676, (3.0 / PI * 2 * PI) ** 2, 1.0),
 }
 
 
@@ -29,7 +34,7 @@ def oracle_kernel_fp32(name: str) -> oracle.KernelSpec:
     """The oracle's kernel with xi/psi/e_max rounded to FP32, as the GPU receives them."""
     k = ORACLE_KERNELS[name]
     f = lambda v: float(np.float32(v))
-    return oracle.KernelSpec(k.kind, f(k.xi), f(k.psi), f(k.e_max))
+    return oracle.KernelSpec(k.kind, f(k.xi), f(k.psi), f(k.e_max), f(k.beta))
 
 
 def oracle_opts_fp32(opts=None):
@@ -116,3 +121,50 @@ def grad_compare(g_gpu: np.ndarray, g_orc: np.ndarray, rel_l2=1e-3, rel_el=1e-3,
     tol = rel_el * np.abs(b) + abs_frac * np.max(np.abs(b))
     ratio = np.max(np.abs(a - b) / np.maximum(tol, 1e-30))
     return (l2 <= rel_l2) and (ratio <= 1.0), float(l2), float(ratio)
+
+
+def ambiguous_zeroed(G_hw3: np.ndarray, margin: np.ndarray, ambig: float) -> np.ndarray:
+    """The upstream gradient [m, 3] with the rows of decision-ambiguous pixels
+    (oracle margin < ``ambig``) set to zero.  A pixel's backward terms are all
+    products with its G, so both sides then give exactly zero there and every
+    splat's gradient can be compared without exempting any splat."""
+    G = np.array(G_hw3, np.float32, copy=True)
+    G[margin < ambig] = 0.0
+    return G
+
+
+def assert_grads(g_gpu: dict, g_orc: dict, names, label="", **tol):
+    """Every tensor within the gradient rule: relative L2 and elementwise."""
+    for name in names:
+        ok, l2, ratio = grad_compare(g_gpu[name], g_orc[name], **tol)
+        print(f"  {label}{name:8s} relL2={l2:.2e} worst={ratio:.3f}")
+        assert ok, (label, name, l2, ratio)
+
+
+def visibility_ambiguous(sp: dict, cam: dict, o: dict, idx, rel: float = 1e-5) -> np.ndarray:
+    """For the splats ``idx`` whose culling differs between the two sides: True
+    where a culling decision of the oracle lies within ``rel`` (relative) of its
+    threshold -- the near plane, the sign of the 2D determinant, the radius
+    3 sqrt(lambda_max) at an integer, or an edge of the radius box on the
+    image's tile border -- so FP32 rounding may take it either way."""
+    idx = np.atleast_1d(np.asarray(idx, np.int64))
+    V = np.asarray(cam["viewmat"], np.float64)
+    mu = np.asarray(sp["means"], np.float64)[:, idx]
+    t = V[:3, :3] @ mu + V[:3, 3:4]
+    near = float(cam["near_z"])
+    out = np.abs(t[2] - near) <= rel * near
+    cov = o["cov2d"][idx]
+    det = cov[:, 0] * cov[:, 2] - cov[:, 1] ** 2
+    out |= np.abs(det) <= rel * np.abs(cov[:, 0] * cov[:, 2])
+    mid = 0.5 * (cov[:, 0] + cov[:, 2])
+    r3 = 3.0 * np.sqrt(np.maximum(mid + np.sqrt(np.maximum(mid * mid - det, 0.0)), 0.0))
+    out |= np.abs(r3 - np.round(r3)) <= rel * np.maximum(r3, 1.0)
+    R = np.ceil(r3)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        u = float(cam["fx"]) * t[0] / t[2] + float(cam["cx"])
+        v = float(cam["fy"]) * t[1] / t[2] + float(cam["cy"])
+    gx, gy = 16 * ((cam["width"] + 15) // 16), 16 * ((cam["height"] + 15) // 16)
+    scale = np.abs(u) + np.abs(v) + R + 1.0
+    for e in (u + R, u - R - gx, v + R, v - R - gy):
+        out |= np.abs(e) <= rel * scale
+    return out

@@ -44,7 +44,7 @@ def test_library_exports_every_declared_symbol(L):
 def test_version_and_status_strings(L):
     from paper_2501_12369_amd import native
 
-    assert native.darb_version() == 4
+    assert native.darb_version() == 5
     assert L.darb_status_string(0) == b"ok"
     assert L.darb_status_string(2) == b"instance capacity exceeded"
 
@@ -148,3 +148,4 @@ def test_deterministic_workspace_queries(L):
     # nv * n beyond 32-bit keys
     assert L.darb_raster_bwd_multi_workspace(arr, 2, 0x7FFFFFFF) > 0
     assert L.darb_raster_bwd_multi_workspace(arr, 3, 0x7FFFFFFF) == 0
+

@@ -1,0 +1,177 @@
+"""Degenerate inputs through the whole HIP path (preprocess -> bin/sort ->
+raster forward -> raster backward -> preprocess backward, called through the
+C ABI) against the FP64 oracle on the same inputs:
+
+  * splats on, just behind and straddling the near plane (t_z = near is culled:
+    the test is strict);
+  * zero and NaN quaternions, a NaN mean: culled, zero gradients, no NaN in
+    any output;
+  * zero scales with no dilation (a zero 2D covariance: culled) and with the
+    dilation (a point splat of covariance eps I); one zero scale (a flat disc);
+  * opacity at and above the alpha clamp 0.99 (straight-through gradient);
+  * centres beyond the Jacobian clamp whose footprints reach into the image;
+  * boxes entirely off screen and boxes that overlap the border;
+  * E exactly at the support limit e_max (inclusive) for kernels with
+    F(e_max) > 0, where no margin exemption applies: E is exact in FP32.
+
+The camera is the identity view (t = mu exactly in both precisions), so the
+near-plane decisions are exact.  Image tolerance 1e-5 relative + 1e-6; the
+upstream gradient is zeroed on decision-ambiguous pixels on both sides and
+every splat's gradient is held to the elementwise rule.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2501_12369_amd import native, pipeline, scenes
+
+from gpu_util import (ambiguous_zeroed, assert_grads, dev, gpu_bin_raster, image_pixels, last_ids, oracle_kernel_fp32,
+                      oracle_opts_fp32, oracle_projected, to_np)
+
+pytestmark = pytest.mark.gpu
+
+W, H = 96, 64
+FX, FY, CX, CY = 80.0, 90.0, 48.0, 32.0
+LX, LY = 1.3 * 0.5 * W / FX, 1.3 * 0.5 * H / FY
+AMBIG = 1e-4
+G3 = ("means", "scales", "quats", "opacity", "sh")
+
+
+def _edge_scene(eps: float, seed: int = 7):
+    rng = np.random.default_rng(seed)
+    mus, scs, qs, ops = [], [], [], []
+
+    def add(mu, sc, q=None, o=None):
+        if q is None:
+            q = rng.standard_normal(4)
+            q /= np.linalg.norm(q)
+        mus.append(mu)
+        scs.append(sc)
+        qs.append(q)
+        ops.append(rng.uniform(0.2, 0.9) if o is None else o)
+
+    # ordinary splats in the frustum
+    for _ in range(24):
+        z = rng.uniform(2.0, 4.0)
+        add([rng.uniform(-0.55, 0.55) * z, rng.uniform(-0.33, 0.33) * z, z], np.exp(rng.uniform(-3.0, -1.2, 3)))
+    near = float(np.float32(0.2))
+    add([0.1, 0.05, near], [0.05, 0.05, 0.05])             # on the near plane: culled (strict test)
+    add([0.0, 0.0, near - 1e-3], [0.05, 0.05, 0.05])       # just behind: culled
+    add([0.02, -0.01, 0.25], [0.02, 0.015, 0.02])          # just in front: a large footprint
+    add([-0.05, 0.03, 0.3], [0.08, 0.06, 0.5])             # straddles the near plane
+    add([0.3, 0.2, 3.0], [0.1, 0.1, 0.1], q=[0.0, 0.0, 0.0, 0.0])         # zero quaternion
+    add([0.3, -0.2, 3.0], [0.1, 0.1, 0.1], q=[np.nan, 0.1, 0.2, 0.3])     # NaN quaternion
+    add([np.nan, 0.0, 3.0], [0.1, 0.1, 0.1])                              # NaN mean
+    add([-0.4, 0.3, 2.5], [0.0, 0.0, 0.0])                  # zero scales: culled without dilation
+    add([0.5, 0.1, 2.2], [0.0, 0.2, 0.12])                  # one zero scale: a flat disc
+    # opacity at / above the alpha clamp, centred on a pixel (E = 0 exactly there)
+    add([(60 - CX) * 3.0 / FX, (20 - CY) * 3.0 / FY, 3.0], [0.12, 0.1, 0.11], o=1.0)
+    add([(30 - CX) * 2.0 / FX, (44 - CY) * 2.0 / FY, 2.0], [0.08, 0.09, 0.07], o=0.995)
+    # centres beyond the Jacobian clamp, footprints reaching into the image
+    for rx, ry in ((1.15 * LX, 0.1), (-1.2 * LX, -0.05), (0.2, 1.3 * LY), (-0.1, -1.25 * LY)):
+        z = rng.uniform(2.8, 3.2)
+        add([rx * z, ry * z, z], rng.uniform(0.45, 0.7, 3))
+    # off screen: a box far outside (culled by the empty rectangle), and one over the border
+    add([3.0 * 4.0, 0.0, 4.0], [0.05, 0.05, 0.05])
+    add([0.68 * 3.0, -0.3 * 3.0, 3.0], [0.25, 0.25, 0.25])
+    n = len(mus)
+    colours = rng.uniform(0.05, 0.95, (n, 3))
+    sh = ((colours - 0.5) / 0.28209479177387814).T.reshape(1, 3, n)
+    sp = dict(means=np.asarray(mus, np.float32).T.copy(), scales=np.asarray(scs, np.float32).T.copy(),
+              quats=np.asarray(qs, np.float32).T.copy(), opacity=np.asarray(ops, np.float32),
+              sh=np.ascontiguousarray(sh, np.float32), sh_degree=0)
+    cam = scenes.camera(np.eye(4), np.zeros(3), FX, FY, CX, CY, W, H, dilation=eps)
+    return sp, cam
+
+
+@pytest.mark.parametrize("kname", ["half_cos", "gauss"])
+@pytest.mark.parametrize("eps", [0.3, 0.0])
+def test_degenerate_inputs_end_to_end(kname, eps):
+    print(f"edge cases {kname} eps={eps}", flush=True)
+    sp, cam = _edge_scene(eps)
+    n = sp["means"].shape[1]
+    kern = pipeline.KERNELS[kname]
+    spd = pipeline.splats_to_device(sp)
+    fr = pipeline.render(spd, cam, kern, n_contrib=True)
+    torch.cuda.synchronize()
+    ocam, ko, oo = oracle.camera_from_scene(cam), oracle_kernel_fp32(kname), oracle_opts_fp32()
+    proj_o, img_o = oracle.render(ocam, ko, oo, sp)
+    # culling decisions: exactly the oracle's
+    vis_g = to_np(fr.proj["radius"]) > 0
+    vis_o = proj_o["visible"] == 1
+    assert np.array_equal(vis_g, vis_o), np.flatnonzero(vis_g != vis_o)
+    expect_culled = [24, 25, 28, 29, 30, 39] + ([31] if eps == 0.0 else [])
+    assert not vis_o[expect_culled].any()
+    assert vis_o[[26, 27, 32, 33, 34, 35, 36, 37, 38, 40]].all()
+    if eps > 0.0:
+        assert vis_o[31]
+    # image, transmittance, last contributor, count on unambiguous pixels
+    img = image_pixels(to_np(fr.image))
+    assert np.all(np.isfinite(img))
+    ok = img_o["margin"] >= AMBIG
+    assert ok.mean() > 0.98
+    err = np.abs(img - img_o["rgb"])
+    tol = 1e-5 * np.abs(img_o["rgb"]) + 1e-6
+    print(f"  image max err {err[ok].max():.2e} worst ratio {np.max(err[ok] / tol[ok]):.3f}, ambiguous {(~ok).sum()}")
+    assert np.all(err[ok] <= tol[ok])
+    Tg = to_np(fr.final_T).reshape(-1)
+    assert np.all(np.abs(Tg - img_o["T"])[ok] <= 1e-5 * img_o["T"][ok] + 1e-7)
+    assert np.array_equal(last_ids(fr)[ok], img_o["last"][ok])
+    assert np.array_equal(to_np(fr.n_contrib).reshape(-1)[ok], img_o["ncontrib"][ok])
+    # the alpha clamp is active at the centres of the two opaque splats
+    for x, y in ((60, 20), (30, 44)):
+        assert img_o["ncontrib"][y * W + x] >= 1
+    # gradients: G zeroed on ambiguous pixels on both sides; every splat compared
+    G = ambiguous_zeroed(scenes.upstream_grad(8, W, H).reshape(3, -1).T, img_o["margin"], AMBIG)
+    Gchw = np.ascontiguousarray(G.T.reshape(3, H, W))
+    g2d, g3d = pipeline.render_backward(fr, dev(Gchw), spd, cam, kern)
+    torch.cuda.synchronize()
+    _, g2o, g3o = oracle.render_bwd(ocam, ko, oo, sp, G.astype(np.float64))
+    g3 = {k: to_np(v) for k, v in g3d.items()}
+    for k in G3:
+        assert np.all(np.isfinite(g3[k])), k
+        assert np.all(np.take(g3[k], np.flatnonzero(~vis_o), axis=-1) == 0.0), k
+    # 2D gradients: the conic's in the library's convention (a, scalar b, c), as the oracle's
+    assert_grads({k: to_np(v) for k, v in g2d.items()}, g2o, ("xy", "conic", "opacity", "rgb"), label="2D ")
+    assert_grads(g3, g3o, G3, label="3D ")
+
+
+@pytest.mark.parametrize("kname", ["gauss", "imq", "imq_sqrt"])
+def test_support_limit_inclusive(kname):
+    """Pixels at E exactly e_max blend (0 <= E <= e_max), exactly as the oracle;
+    their decisions have zero margin and are compared without exemption."""
+    print(f"E = e_max {kname}", flush=True)
+    ko = oracle_kernel_fp32(kname)
+    r = math.sqrt(ko.e_max)  # 3: the kernels with F(e_max) > 0 share e_max = 9
+    f = r - math.floor(r)
+    # unit conic (l00 = l11 = 1, l01 = 0): E = dx^2 + dy^2, exact in FP32 for these offsets
+    centres = [(10.0 + f, 10.0 + f), (30.0 + f, 12.0 + f), (20.0 + f, 30.0 + f)]
+    n = len(centres)
+    ps = dict(xy=np.asarray(centres, np.float32), depth=np.asarray([2.0, 3.0, 4.0], np.float32),
+              radius=np.full(n, 5, np.int32),
+              conic_o=np.asarray([[1.0, 0.0, 1.0, 0.9]] * n, np.float32),
+              conic_l=np.asarray([[1.0, 0.0, 1.0]] * n, np.float32),
+              rgb=np.asarray([[0.9, 0.2, 0.1], [0.1, 0.8, 0.3], [0.2, 0.3, 0.7]], np.float32), width=48, height=40)
+    fr, K = gpu_bin_raster(ps, kname)
+    orc = oracle.composite(oracle_projected(ps), ps["conic_o"][:, 3].astype(np.float64), ko, oracle_opts_fp32(),
+                           48, 40)
+    img = image_pixels(to_np(fr.image))
+    # the pixels on the support boundary of each splat
+    edge = []
+    for (u, v) in centres:
+        for px, py in ((u + r, v), (u - r, v), (u, v + r), (u, v - r)):
+            assert float(px).is_integer() and float(py).is_integer()
+            edge.append(int(py) * 48 + int(px))
+    edge = np.asarray(edge)
+    w_edge = oracle.kernel_value(ko.kind, ko.xi, ko.e_max)[0]
+    assert 0.9 * w_edge > 1 / 255  # these pixels do blend
+    assert np.all(orc["ncontrib"][edge] >= 1)
+    assert np.array_equal(to_np(fr.n_contrib).reshape(-1)[edge], orc["ncontrib"][edge])
+    assert np.array_equal(last_ids(fr)[edge], orc["last"][edge])
+    err = np.abs(img - orc["rgb"])
+    assert np.all(err[edge] <= 1e-5 * np.abs(orc["rgb"][edge]) + 1e-6)
+    ok = orc["margin"] > 0.0
+    assert np.all(err[ok] <= 1e-5 * np.abs(orc["rgb"][ok]) + 1e-6)

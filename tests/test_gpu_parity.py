@@ -19,30 +19,14 @@ import torch
 import oracle
 from paper_2501_12369_amd import native, pipeline, scenes
 
-from gpu_util import (ORACLE_KERNELS, conic_from_factor, dev, gpu_bin_raster, grad_compare, image_pixels, last_ids,
-                      oracle_kernel_fp32, oracle_opts_fp32, oracle_projected, projected_to_device, to_np)
+from gpu_util import (ORACLE_KERNELS, ambiguous_zeroed, assert_grads, conic_from_factor, dev, gpu_bin_raster,
+                      grad_compare, image_pixels, last_ids, oracle_kernel_fp32, oracle_opts_fp32, oracle_projected,
+                      projected_to_device, to_np, visibility_ambiguous)
 
 pytestmark = pytest.mark.gpu
 
 ALL_KERNELS = list(ORACLE_KERNELS)
 AMBIG = 2e-5
-
-
-def _exempt_splats(ps, orc, ko, W, H):
-    """Splats that are candidates (E <= e_max, with slack) at a decision-ambiguous pixel."""
-    amb = np.flatnonzero(orc["margin"] < AMBIG)
-    n = len(ps["radius"])
-    ex = np.zeros(n, bool)
-    if len(amb) == 0:
-        return ex
-    pix = oracle.full_pixels(W, H)[amb].astype(np.float64)
-    xy = ps["xy"].astype(np.float64)
-    q = conic_from_factor(ps["conic_l"])
-    for p in pix:
-        dx, dy = xy[:, 0] - p[0], xy[:, 1] - p[1]
-        E = q[:, 0] * dx * dx + 2 * q[:, 1] * dx * dy + q[:, 2] * dy * dy
-        ex |= (E <= ko.e_max * 1.001) & (ps["radius"] > 0)
-    return ex
 
 
 # ---------------------------------------------------------------- bin / sort
@@ -116,7 +100,7 @@ def test_bin_sort_all_culled_and_overflow():
 # ---------------------------------------------------------------- raster forward
 
 def _forward_case(kname, n, W, H, seed, opts=None, sigma=(0.5, 12.0)):
-    ps = scenes.projected(seed, n, W, H, sigma_range=sigma)
+    ps = scenes.projected(seed, n, W, H, sigma_range=sigma, e_max=ORACLE_KERNELS[kname].e_max)
     fr, K = gpu_bin_raster(ps, kname, opts=opts)
     ko = oracle_kernel_fp32(kname)
     oo = oracle_opts_fp32(opts)
@@ -168,7 +152,12 @@ def test_raster_bwd_parity(kname):
     print(f"raster_bwd {kname} n={n} {W}x{H}", flush=True)
     opts = dict(pipeline.DEFAULT_OPTS, bg=(0.3, 0.1, 0.2))
     ps, fr, orc = _forward_case(kname, n, W, H, seed, opts=opts)
-    G = scenes.upstream_grad(seed + 1, W, H)
+    # the upstream gradient is zeroed on decision-ambiguous pixels (both sides), so
+    # every splat is compared
+    amb = orc["margin"] < AMBIG
+    assert amb.mean() <= 1e-3
+    Go = ambiguous_zeroed(scenes.upstream_grad(seed + 1, W, H).reshape(3, -1).T, orc["margin"], AMBIG)
+    G = np.ascontiguousarray(Go.T.reshape(3, H, W))
     runs = {}
     for det in (False, True, True):
         g2d, _ = pipeline.alloc_grads(n, 0)
@@ -180,20 +169,10 @@ def test_raster_bwd_parity(kname):
     # the deterministic reduction gives the same bits every run
     for k in runs[True][0]:
         assert np.array_equal(runs[True][0][k], runs[True][1][k]), k
-    Go = G.reshape(3, -1).T.astype(np.float64)
     go = oracle.composite_bwd(oracle_projected(ps), ps["conic_o"][:, 3].astype(np.float64),
-                              oracle_kernel_fp32(kname), oracle_opts_fp32(opts), W, H, Go)
-    # splats that are candidates at an ambiguous pixel are exempt
-    exempt = _exempt_splats(ps, orc, oracle_kernel_fp32(kname), W, H)
-    keep = ~exempt
-    # kernels with F(e_max) > 0 (Gaussian, IMQ) put more pixels near the support jump
-    assert keep.mean() > 0.8
+                              oracle_kernel_fp32(kname), oracle_opts_fp32(opts), W, H, Go.astype(np.float64))
     for det in (False, True):
-        g2d = runs[det][0]
-        for name in ("xy", "conic", "opacity", "rgb"):
-            ok, l2, ratio = grad_compare(g2d[name][keep], go[name][keep])
-            print(f"  det={int(det)} {name:8s} relL2={l2:.2e} worst={ratio:.3f}")
-            assert ok, (det, name, l2, ratio)
+        assert_grads(runs[det][0], go, ("xy", "conic", "opacity", "rgb"), label=f"det={int(det)} ")
 
 
 @pytest.mark.parametrize("n", [1200, 7])
@@ -311,8 +290,10 @@ def test_preprocess_parity(kname, which):
     vis_g = rad > 0
     vis_o = o["visible"] == 1
     both = vis_g & vis_o
-    # visibility may differ only for splats whose radius box touches the image border
-    assert np.sum(vis_g != vis_o) <= max(2, 1e-3 * n)
+    # visibility may differ only where a culling decision is within rounding of its threshold
+    diff = np.flatnonzero(vis_g != vis_o)
+    print(f"  visibility differs for {len(diff)} of {n}")
+    assert np.all(visibility_ambiguous(sp, cam, o, diff)), diff
     assert both.sum() > 0.3 * vis_o.sum() and both.sum() > 10
     xy = to_np(proj["xy"])[both]
     co = to_np(proj["conic_o"])[both]
@@ -372,7 +353,7 @@ def test_preprocess_bwd_parity(kname, ckpt):
         b_v = np.take(b, np.flatnonzero(vis), axis=ax)
         ok, l2, ratio = grad_compare(a_v, b_v, rel_l2=1e-3, rel_el=1e-3, abs_frac=1e-4)
         print(f"  {name:8s} relL2={l2:.2e} worst={ratio:.3f}")
-        assert l2 <= 1e-3, (name, l2)
+        assert ok, (name, l2, ratio)
         assert np.all(np.take(a, np.flatnonzero(~vis), axis=ax) == 0.0)
 
 
@@ -392,23 +373,26 @@ def test_end_to_end_tiny(kname, dilation):
     ko = oracle_kernel_fp32(kname)
     params = {k: v for k, v in sp.items()}
     _, img_o = oracle.render(ocam, ko, oracle_opts_fp32(), params)
-    # upstream gradient: the mean-L1 gradient of the oracle's image against a random target
+    # image: 1e-5 relative + 1e-6 on pixels whose decisions are further than 1e-4
+    # (relative) from their thresholds
+    ok = img_o["margin"] >= 1e-4
+    assert ok.mean() > 0.99
+    err = np.abs(image_pixels(to_np(fr.image)) - img_o["rgb"])
+    tol = 1e-5 * np.abs(img_o["rgb"]) + 1e-6
+    print(f"  image max err {err[ok].max():.2e} worst ratio {np.max(err[ok] / tol[ok]):.3f}, ambiguous {(~ok).sum()}")
+    assert np.all(err[ok] <= tol[ok])
+    # upstream gradient: the mean-L1 gradient of the oracle's image against a random target,
+    # zeroed on the ambiguous pixels on both sides
     target = np.random.default_rng(5).uniform(0, 1, (3, H, W)).astype(np.float32)
     _, Go = oracle.image_loss(img_o["rgb"], image_pixels(target), oracle.LOSS_L1)
-    G = Go.T.reshape(3, H, W).astype(np.float32)
+    Go = ambiguous_zeroed(Go, img_o["margin"], 1e-4)
+    G = np.ascontiguousarray(Go.T.reshape(3, H, W))
     g2d, g3d = pipeline.render_backward(fr, dev(G), spd, cam, pipeline.KERNELS[kname])
     torch.cuda.synchronize()
-    Go = G.reshape(3, -1).T.astype(np.float64)
-    _, g2o, g3o = oracle.render_bwd(ocam, ko, oracle_opts_fp32(), params, Go)
-    # end-to-end tolerance (FP32 projection feeds the composite): 1e-4 relative + 1e-5
-    ok = img_o["margin"] >= 1e-3
-    err = np.abs(image_pixels(to_np(fr.image)) - img_o["rgb"])
-    print(f"  image max err {err[ok].max():.2e}, ambiguous {(~ok).sum()}")
-    assert np.all(err[ok] <= 1e-4 * np.abs(img_o["rgb"][ok]) + 1e-5)
-    for name in ("means", "scales", "quats", "opacity", "sh"):
-        ok_, l2, ratio = grad_compare(to_np(g3d[name]), g3o[name], rel_l2=1e-3)
-        print(f"  {name:8s} relL2={l2:.2e} worst={ratio:.3f}")
-        assert l2 <= 1e-3, (name, l2)
+    _, g2o, g3o = oracle.render_bwd(ocam, ko, oracle_opts_fp32(), params, Go.astype(np.float64))
+    assert_grads({k: to_np(v) for k, v in g2d.items()}, g2o, ("xy", "conic", "opacity", "rgb"), label="2D ")
+    assert_grads({k: to_np(v) for k, v in g3d.items()}, g3o, ("means", "scales", "quats", "opacity", "sh"),
+                 label="3D ")
 
 
 def test_autograd_matches_plain_path():
@@ -456,3 +440,78 @@ def test_rasterizer_steps_match_plain_path():
         for p, name in zip(params, names):
             rel = (p.grad - g3d[name]).norm() / g3d[name].norm()
             assert rel < 1e-5, (step, name, float(rel))
+
+
+def test_rasterize_gradients_match_oracle():
+    """The torch.autograd.Function (checkpointed final T and last position; the
+    backward recomputes every pair) against the FP64 oracle: the image within
+    1e-5 relative + 1e-6, the 3D gradients of a loss sum(G * image) within the
+    gradient rule (G zeroed on decision-ambiguous pixels on both sides)."""
+    from paper_2501_12369_amd.autograd import Rasterizer, rasterize
+
+    sc = scenes.object_scale(seed=12, n=3000, width=160, height=120)
+    sp = sc["splats"]
+    cam = dict(sc["camera"], fx=240.0, fy=240.0, cx=80.0, cy=60.0)
+    W, H = cam["width"], cam["height"]
+    ocam, ko, oo = oracle.camera_from_scene(cam), oracle_kernel_fp32("half_cos"), oracle_opts_fp32()
+    _, img_o = oracle.render(ocam, ko, oo, sp)
+    ok = img_o["margin"] >= 1e-4
+    assert ok.mean() > 0.99
+    Go = ambiguous_zeroed(scenes.upstream_grad(13, W, H).reshape(3, -1).T, img_o["margin"], 1e-4)
+    _, _, g3o = oracle.render_bwd(ocam, ko, oo, sp, Go.astype(np.float64))
+    G = dev(np.ascontiguousarray(Go.T.reshape(3, H, W)))
+    spd = _splats_dev(sp)
+    names = ("means", "scales", "quats", "opacity", "sh")
+    R = Rasterizer("half_cos")
+    for label, fn in (("rasterize", lambda *p: rasterize(*p, cam, "half_cos", sh_degree=3)),
+                      ("Rasterizer", lambda *p: R(*p, cam, sh_degree=3)),
+                      ("Rasterizer again", lambda *p: R(*p, cam, sh_degree=3))):
+        print(label, flush=True)
+        params = [spd[k].clone().requires_grad_(True) for k in names]
+        img = fn(*params)
+        (img * G).sum().backward()
+        torch.cuda.synchronize()
+        err = np.abs(image_pixels(to_np(img)) - img_o["rgb"])
+        assert np.all(err[ok] <= 1e-5 * np.abs(img_o["rgb"][ok]) + 1e-6)
+        assert_grads({k: to_np(p.grad) for k, p in zip(names, params)}, g3o, names, label=f"{label} ")
+
+
+def test_rasterizer_two_forwards_one_backward():
+    """Two views rendered by one Rasterizer before one backward of the summed
+    loss: each forward keeps its own checkpoint, and the gradients equal the
+    sum of the plain path's per-view gradients."""
+    from paper_2501_12369_amd.autograd import Rasterizer
+
+    sc = scenes.object_scale(seed=14, n=20000, width=320, height=240)
+    spd = _splats_dev(sc["splats"])
+    cam1 = dict(sc["camera"], fx=450.0, fy=450.0, cx=160.0, cy=120.0)
+    campos = np.array([0.6, -0.3, -3.9])
+    cam2 = scenes.camera(scenes.look_at(campos, np.zeros(3)), campos, 450.0, 450.0, 160.0, 120.0, 320, 240)
+    names = ("means", "scales", "quats", "opacity", "sh")
+    gen = torch.Generator("cuda").manual_seed(16)
+    G1 = torch.randn((3, 240, 320), device="cuda", generator=gen)
+    G2 = torch.randn((3, 240, 320), device="cuda", generator=gen)
+    kern = pipeline.KERNELS["half_cos"]
+    ref_img, ref_g = [], {k: 0 for k in names}
+    for cam, G in ((cam1, G1), (cam2, G2)):
+        fr = pipeline.render(spd, cam, kern)
+        _, g3d = pipeline.render_backward(fr, G, spd, cam, kern)
+        torch.cuda.synchronize()
+        ref_img.append(fr.image.clone())
+        for k in names:
+            ref_g[k] = ref_g[k] + g3d[k]
+    R = Rasterizer("half_cos")
+    for step in range(3):  # the first step allocates the frames, later ones reuse the pool
+        print(f"two forwards, step {step}", flush=True)
+        params = [spd[k].clone().requires_grad_(True) for k in names]
+        img1 = R(*params, cam1, sh_degree=3)
+        img2 = R(*params, cam2, sh_degree=3)
+        ((img1 * G1).sum() + (img2 * G2).sum()).backward()
+        torch.cuda.synchronize()
+        assert torch.equal(img1.detach(), ref_img[0]) and torch.equal(img2.detach(), ref_img[1])
+        for p, k in zip(params, names):
+            rel = float((p.grad - ref_g[k]).norm() / ref_g[k].norm())
+            assert rel < 1e-5, (step, k, rel)
+    with torch.no_grad():  # a forward without backward returns its frame to the pool at once
+        R(*[spd[k] for k in names], cam1, sh_degree=3)
+    assert sum(len(v) for v in R._pool.values()) == 2

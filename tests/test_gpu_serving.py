@@ -1,7 +1,7 @@
 """GPU tests of the continuous-batching server: every image rendered in the
-mix (concurrent graph replays, shared slots, device camera buffers) equals the
-same request rendered alone with the plain path, bit for bit; the capacity
-overflow path re-renders correctly."""
+mix (batched multi-view graph replays, concurrent slots, device camera arrays)
+equals the same request rendered alone with the plain path, bit for bit; the
+capacity overflow path re-renders correctly."""
 import numpy as np
 import pytest
 import torch
@@ -37,10 +37,11 @@ def test_mix_equals_alone():
     print("serving: burst of 24 requests, 4 slots", flush=True)
     sc = _scenes()
     kern = pipeline.KERNELS["half_cos"]
-    srv = serving.RenderServer(sc, kern, mem_budget=4 << 30, max_slots=4)
+    srv = serving.RenderServer(sc, kern, mem_budget=4 << 30, max_slots=4, max_batch=4)
     reqs = _requests(24)
     results, st = srv.serve(reqs, keep_images=True)
     assert st.n == 24 and st.peak_slots >= 2
+    assert st.extra["peak_batch"] >= 2  # requests of one key shared a replay
     for r in results:
         ref = _alone(sc, reqs[r.rid], kern)
         assert torch.equal(r.image, ref), r.rid
@@ -73,3 +74,29 @@ def test_sequential_baseline_runs():
     assert st.n == 8 and st.peak_inflight == 1
     assert all(b.start >= a.end - 1e-9 for a, b in zip(sorted(results, key=lambda r: r.start),
                                                       sorted(results, key=lambda r: r.start)[1:]))
+
+
+def test_multi_view_preprocess_with_device_cameras():
+    """darb_preprocess_multi_cam_dev: each view's records have the bits of the
+    single-view preprocess with that camera."""
+    from paper_2501_12369_amd import native
+
+    sp = pipeline.splats_to_device(scenes.scene_splats(63, 30000))
+    n = int(sp["means"].shape[1])
+    kern = pipeline.KERNELS["half_cos"]
+    rng = np.random.Generator(np.random.PCG64(3))
+    cams = [scenes.orbit_camera(rng, 320, 200) for _ in range(3)]
+    template = scenes.orbit_camera(rng, 320, 200)
+    projs = [pipeline.alloc_projected(n, dcolor=False) for _ in cams]
+    cb = native.CAMERA_NBYTES
+    host = np.concatenate([np.frombuffer(native.camera_bytes(c), np.uint8) for c in cams])
+    cams_dev = torch.from_numpy(host.copy()).cuda()
+    views = [dict(cam=template, proj=p) for p in projs]
+    native.darb_preprocess_multi_cam_dev(views, cams_dev, kern, n, sp)
+    for cam, p in zip(cams, projs):
+        q = pipeline.alloc_projected(n, dcolor=False)
+        native.darb_preprocess(cam, kern, n, sp, q)
+        torch.cuda.synchronize()
+        for k in ("xy", "depth", "radius", "conic_o", "rgb", "clamped"):
+            assert torch.equal(p[k], q[k]), k
+    assert len(host) == 3 * cb

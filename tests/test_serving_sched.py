@@ -17,33 +17,40 @@ class FakeClock:
 
 
 class FakeSlot:
-    def __init__(self, key, nbytes, clock, service, overflow_once, log):
+    def __init__(self, key, nbytes, clock, service, overflow_once, log, max_batch=1):
         self.key, self.nbytes, self.clock, self.service = key, nbytes, clock, service
         self.overflow_once, self.log = overflow_once, log
+        self.max_batch = max_batch
         self.t_end = None
-        self.req = None
+        self.reqs = None
         self.freed = False
 
-    def launch(self, req):
-        assert not self.freed
-        self.req = req
+    def launch(self, reqs):
+        assert not self.freed and 1 <= len(reqs) <= self.max_batch
+        assert all(r.key == self.key for r in reqs)
+        self.reqs = reqs
         self.t_end = self.clock.t + self.service
-        self.log.append(("start", req.rid, self.clock.t, self.key))
+        for r in reqs:
+            self.log.append(("start", r.rid, self.clock.t, self.key))
+        self.log.append(("batch", len(reqs), self.clock.t, self.key))
 
     def poll(self):
         return self.clock.t >= self.t_end
 
     def finish(self):
-        if self.req.rid in self.overflow_once:
-            self.overflow_once.discard(self.req.rid)
+        over = [r.rid for r in self.reqs if r.rid in self.overflow_once]
+        if over:
+            for rid in over:
+                self.overflow_once.discard(rid)
             return False, 999
         return True, 10
 
-    def rerun(self, req, K):
+    def rerun(self, reqs, K):
         self.nbytes += 1
-        self.log.append(("rerun", req.rid, self.clock.t, self.key))
+        for r in reqs:
+            self.log.append(("rerun", r.rid, self.clock.t, self.key))
 
-    def image_copy(self):
+    def image_copy(self, i=0):
         return None
 
     def free(self):
@@ -51,7 +58,7 @@ class FakeSlot:
         self.log.append(("free", None, self.clock.t, self.key))
 
 
-def make(budget, max_slots=8, service=0.010, per_key_bytes=None, overflow_once=(), max_inflight=None):
+def make(budget, max_slots=8, service=0.010, per_key_bytes=None, overflow_once=(), max_inflight=None, max_batch=1):
     clock = FakeClock()
     log = []
     per_key_bytes = per_key_bytes or {}
@@ -61,7 +68,7 @@ def make(budget, max_slots=8, service=0.010, per_key_bytes=None, overflow_once=(
         return per_key_bytes.get(key, 100)
 
     def factory(key, hint):
-        return FakeSlot(key, need(key), clock, service, ov, log)
+        return FakeSlot(key, need(key), clock, service, ov, log, max_batch)
 
     return (Scheduler(factory, need, budget, max_slots, clock=clock, sleep=clock.sleep, max_inflight=max_inflight),
             clock, log)
@@ -171,3 +178,35 @@ def test_admission_looks_past_a_waiting_key():
     by = {r.rid: r for r in results}
     assert by[2].start < by[0].end <= by[1].start + 1e-9
     assert st.evictions == 0 and st.peak_slots == 2
+
+
+def test_requests_of_one_key_share_a_launch():
+    """Continuous batching: requests of one key waiting together join one launch
+    (up to the slot's batch size); requests arriving while it runs are admitted
+    to the next launch when the slot frees up, in arrival order."""
+    s, clock, log = make(budget=1000, max_slots=1, service=0.010, max_batch=4)
+    rs = [req(i, 0.0) for i in range(10)] + [req(10 + i, 0.005) for i in range(3)]
+    results, st = s.run(rs)
+    assert sorted(r.rid for r in results) == list(range(13))
+    batches = [e[1] for e in log if e[0] == "batch"]
+    assert batches == [4, 4, 4, 1]
+    starts = [e[1] for e in log if e[0] == "start"]
+    assert starts == list(range(13))
+    assert st.extra["peak_batch"] == 4
+    # every request of a launch ends with it
+    ends = {}
+    for r in results:
+        ends.setdefault(r.start, set()).add(r.end)
+    assert all(len(v) == 1 for v in ends.values())
+
+
+def test_batches_keep_to_their_key_and_limit():
+    s, clock, log = make(budget=1000, max_slots=2, service=0.010, max_batch=3)
+    rs = [req(i, 0.0, scene=i % 2) for i in range(8)]
+    results, st = s.run(rs)
+    assert len(results) == 8
+    assert max(e[1] for e in log if e[0] == "batch") == 3
+    s.batch_limit = 1
+    rs2 = [req(20 + i, 0.0) for i in range(4)]
+    s.run(rs2)
+    assert [e[1] for e in log if e[0] == "batch"][-4:] == [1, 1, 1, 1]
