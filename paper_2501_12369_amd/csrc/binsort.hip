@@ -70,6 +70,14 @@ __device__ __forceinline__ int4 tile_rect(float u, float v, int radius, int gx, 
     return make_int4(x0, x1, y0, y1);
 }
 
+// An empty asm use of v: the compiler waits for the loads producing v here, so
+// loads issued before it are in flight together and land before what follows.
+__device__ __forceinline__ void pin4(const uint4 &v) { asm volatile("" ::"v"(v.x), "v"(v.y), "v"(v.z), "v"(v.w)); }
+__device__ __forceinline__ void pin_u32(uint32_t a, uint32_t b) { asm volatile("" ::"v"(a), "v"(b)); }
+__device__ __forceinline__ void pin_u32(uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+    asm volatile("" ::"v"(a), "v"(b), "v"(c), "v"(d));
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt() {
     const int lane = threadIdx.x & 63;
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -114,11 +122,14 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t *in
     uint32_t count = live_count(count_dev, max_count);
     uint32_t base = blockIdx.x * kScanBlock;
     if (base >= count) return;
-    uint32_t s = 0;
+    uint32_t v[kScanItems], s = 0;
+#pragma unroll
     for (int k = 0; k < kScanItems; k++) {
         uint32_t i = base + k * kScanThreads + threadIdx.x;
-        if (i < count) s += in[i];
+        v[k] = i < count ? in[i] : 0u;
     }
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) s += v[k];
     uint32_t tot;
     block_excl_scan(s, lw, &tot);
     if (threadIdx.x == 0) parts[blockIdx.x] = tot;
@@ -199,10 +210,22 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const uint32_t *ke
     h[threadIdx.x] = 0;
     __syncthreads();
     const uint32_t base = blockIdx.x * kRadixTile;
+    // every key load in flight before the first LDS atomic (a load-atomic-load
+    // chain pays the memory latency once per key)
+    // (unconditional loads at clamped indices keep them in one basic block; a
+    // block with n == 0 reads keys[0], which exists whenever the sort runs)
+    uint32_t d[kRadixItems];
+    const uint32_t last = n > 0 ? n - 1 : 0;
+#pragma unroll
+    for (int k = 0; k < kRadixItems; k++) d[k] = keys[min(base + k * kRadixThreads + threadIdx.x, last)];
+#pragma unroll
     for (int k = 0; k < kRadixItems; k++) {
         const uint32_t i = base + k * kRadixThreads + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+        d[k] = i < n ? (d[k] >> shift) & 255u : 256u;
     }
+#pragma unroll
+    for (int k = 0; k < kRadixItems; k++)
+        if (d[k] < 256u) atomicAdd(&h[d[k]], 1u);
     __syncthreads();
     hist[threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];  // digit-major
 }
@@ -275,15 +298,7 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t 
     if (base >= n) return;
     const uint32_t cnt = min((uint32_t)kRadixTile, n - base);
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
-    {
-        // global first slot of digit t for this tile: the digit's start (scan of the
-        // digit totals) plus this tile's prefix within the digit's row
-        uint32_t tot;
-        const uint32_t dstart = block_excl_scan(hist_scan[(size_t)256 * nblk + t], lw, &tot);
-        run[t] = dstart + hist_scan[t * nblk + blockIdx.x];
-    }
-#pragma unroll
-    for (int k = 0; k < kRadixWaves; k++) wcnt[k][t] = 0;
+    // the tile's keys and values, and this thread's digit counts, all in flight at once
     uint32_t key[kRadixItems], val[kRadixItems];
     const uint32_t w0 = (uint32_t)w * kRadixWaveItems;
 #pragma unroll
@@ -292,6 +307,15 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t 
         key[r] = li < cnt ? kin[base + li] : 0u;
         val[r] = li < cnt ? vin[base + li] : 0u;
     }
+    const uint32_t dtotal = hist_scan[(size_t)256 * nblk + t], dprefix = hist_scan[t * nblk + blockIdx.x];
+    {
+        // global first slot of digit t for this tile: the digit's start (scan of the
+        // digit totals) plus this tile's prefix within the digit's row
+        uint32_t tot;
+        run[t] = block_excl_scan(dtotal, lw, &tot) + dprefix;
+    }
+#pragma unroll
+    for (int k = 0; k < kRadixWaves; k++) wcnt[k][t] = 0;
     __syncthreads();
     const uint64_t lt = lanemask_lt();
     uint32_t rank[kRadixItems];
@@ -345,20 +369,28 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t 
     __syncthreads();
     // the tile in digit order: slot i of digit d goes to run[d] + (i - loff[d])
     if constexpr (REC) {
+        // gathers and destinations first; the stores follow once every gather
+        // has landed (a store between two uses of gathered data would make the
+        // second use wait for it: vmcnt counts stores too)
         uint4 rec[kRadixItems];
+        uint32_t g[kRadixItems];
 #pragma unroll
         for (int r = 0; r < kRadixItems; r++) {
             const uint32_t i = r * kRadixThreads + t;
-            if (i < cnt) rec[r] = crec[sv[i]];
+            g[r] = kNone;
+            if (i < cnt) {
+                rec[r] = crec[sv[i]];
+                const uint32_t d = (sk[i] >> shift) & 255u;
+                g[r] = run[d] + (i - loff[d]);
+            }
         }
 #pragma unroll
+        for (int r = 0; r < kRadixItems; r++) pin4(rec[r]);  // every gather lands before the first store
+#pragma unroll
         for (int r = 0; r < kRadixItems; r++) {
-            const uint32_t i = r * kRadixThreads + t;
-            if (i < cnt) {
-                const uint32_t d = (sk[i] >> shift) & 255u;
-                const uint32_t g = run[d] + (i - loff[d]);
-                sid[g] = rec[r].z;
-                sbox[g] = make_uint2(rec[r].x, rec[r].y);
+            if (g[r] != kNone) {
+                sid[g[r]] = rec[r].z;
+                sbox[g[r]] = make_uint2(rec[r].x, rec[r].y);
             }
         }
     } else {
@@ -478,11 +510,15 @@ __global__ __launch_bounds__(256) void k_bin_compact(const float *xy, const int3
     const int base = blockIdx.x * kKeyTile + threadIdx.x;
     int R[kKeyItems];
     float2 p[kKeyItems];
+    uint32_t db[kKeyItems];
+    // every load issued up front: in the store loop below a load would wait for
+    // the stores before it (vmcnt counts both)
 #pragma unroll
     for (int k = 0; k < kKeyItems; k++) {
         const int i = base + k * 256;
         R[k] = i < n ? radius[i] : 0;
         p[k] = i < n ? reinterpret_cast<const float2 *>(xy)[i] : make_float2(0.0f, 0.0f);
+        db[k] = i < n ? __float_as_uint(depth[i]) : 0u;
     }
     uint32_t visbits = 0;
     int4 rect[kKeyItems];
@@ -513,7 +549,7 @@ __global__ __launch_bounds__(256) void k_bin_compact(const float *xy, const int3
         if (vis) {
             const int i = base + k * 256;
             const uint32_t pos = wv[k * 4 + w] + (uint32_t)__popcll(m & lt);
-            keys[pos] = __float_as_uint(depth[i]);
+            keys[pos] = db[k];
             vals[pos] = pos;
             crec[pos] = make_uint4((uint32_t)rect[k].x | ((uint32_t)rect[k].y << 16),
                                    (uint32_t)rect[k].z | ((uint32_t)rect[k].w << 16), (uint32_t)i, 0u);
@@ -584,34 +620,45 @@ __global__ __launch_bounds__(kL1Threads) void k_l1_scatter(const uint32_t *sid, 
     if (*overflow_dev) return;
     const uint32_t c = blockIdx.x, c1 = cnt->c1, nv = cnt->n_visible;
     if (c >= c1) return;
+    // this thread's splat, list lengths and chunk prefixes: every load in flight at once
+    const uint32_t j = c * kL1Threads + threadIdx.x;
+    const uint32_t jc = min(j, nv - 1);  // nv >= 1 here (c < c1)
+    const uint32_t id_in = sid[jc];
+    const uint2 box_in = sbox[jc];
+    const int g0 = 4 * threadIdx.x;
+    uint32_t v[4], b1[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const int g = min(g0 + k, nsuper - 1);
+        v[k] = gtot[g];
+        b1[k] = base1[(size_t)g * c1 + c];
+    }
     for (int k = threadIdx.x; k < nsuper * 8; k += kL1Threads) bits[k] = 0;
     {
         // first slot of this chunk in super-tile g: list start + the chunk's prefix in the row
-        const int g0 = 4 * threadIdx.x;
-        uint32_t v[4], sum = 0;
+        uint32_t sum = 0;
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            v[k] = g0 + k < nsuper ? gtot[g0 + k] : 0u;
+            v[k] = g0 + k < nsuper ? v[k] : 0u;
             sum += v[k];
         }
         uint32_t tot;
         uint32_t off = block_excl_scan(sum, lw, &tot);
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            if (g0 + k < nsuper) first[g0 + k] = off + base1[(size_t)(g0 + k) * c1 + c];
+            if (g0 + k < nsuper) first[g0 + k] = off + b1[k];
             off += v[k];
         }
     }
     __syncthreads();
     const int word = threadIdx.x >> 5;
     const uint32_t bit = 1u << (threadIdx.x & 31);
-    uint32_t j = c * kL1Threads + threadIdx.x;
     uint32_t id = 0;
     int4 r = make_int4(0, 0, 0, 0);
     SuperBox sb{0, -1, 0, -1};
     if (j < nv) {
-        id = sid[j];
-        r = unpack_box(sbox[j]);
+        id = id_in;
+        r = unpack_box(box_in);
         sb = super_box(r);
     }
     for (int gys = sb.sy0; gys <= sb.sy1; gys++)
@@ -791,38 +838,80 @@ __device__ __forceinline__ void l2_counts(const uint64_t *lds_masks, uint32_t *w
     wc[w * 64 + lane] = (uint32_t)__popcll(m);
 }
 
+// The tables the chunk lookup reads (chunk starts, list starts and lengths per
+// super-tile), copied to LDS once per workgroup.
+struct L2Tables {
+    uint32_t c2s[kMaxSuperTiles + 1], l1s[kMaxSuperTiles], l1l[kMaxSuperTiles];
+};
+
+__device__ __forceinline__ void l2_load_tables(L2Tables &T, const uint32_t *chunk2_start, const uint32_t *l1_start,
+                                               const uint32_t *l1_len, int nsuper) {
+    for (int g = threadIdx.x; g <= nsuper; g += kL2Threads) {
+        T.c2s[g] = chunk2_start[g];
+        if (g < nsuper) {
+            T.l1s[g] = l1_start[g];
+            T.l1l[g] = l1_len[g];
+        }
+    }
+}
+
+// Tile (tx, ty) of lane tl of super-tile g, clamped to the image: the clamped
+// tile lies in the same super-tile (every super-tile holds a tile of the
+// image), so indices derived from it stay inside g's part of the count arrays.
+__device__ __forceinline__ int l2_tile_clamped(int g, int tl, int sxn, int gx, int gy, bool &inside) {
+    const int tx = (g % sxn) * kSuper + (tl & (kSuper - 1)), ty = (g / sxn) * kSuper + tl / kSuper;
+    inside = (tx < gx) & (ty < gy);
+    return min(ty, gy - 1) * gx + min(tx, gx - 1);
+}
+
+// A workgroup takes its chunks kL2Batch at a time and issues every global load
+// of a batch (list entries, count offsets) before working on the first chunk,
+// so a batch costs a memory round trip or two instead of several per chunk.
+constexpr int kL2Batch = 8;
+
 __global__ __launch_bounds__(kL2Threads) void k_l2_count(const uint32_t *list1r, const uint32_t *l1_start,
                                                          const uint32_t *l1_len, const uint32_t *chunk2_start,
                                                          const uint32_t *toff, int gx, int gy, int sxn, int nsuper,
                                                          const Counters *cnt, uint32_t *h2,
                                                          const int32_t *overflow_dev) {
     __shared__ uint32_t wc[kSuper * kSuper * kL2Waves];
-    __shared__ uint32_t c2s[kMaxSuperTiles + 1];
+    __shared__ L2Tables T;
     __shared__ uint64_t masks[kL2Waves][2 * kSuper];
     if (*overflow_dev) return;
     const uint32_t total2 = cnt->total2;
-    const int w = threadIdx.x >> 6;
-    for (int g = threadIdx.x; g <= nsuper; g += kL2Threads) c2s[g] = chunk2_start[g];
+    const int w = threadIdx.x >> 6, tl = threadIdx.x & 63;
+    l2_load_tables(T, chunk2_start, l1_start, l1_len, nsuper);
     __syncthreads();
-    for (uint32_t wi = blockIdx.x; wi < total2; wi += gridDim.x) {
-        L2Chunk C = l2_locate(wi, c2s, nsuper, l1_start, l1_len);
-        bool valid = threadIdx.x < C.len;
-        const uint32_t packed = valid ? list1r[C.first + threadIdx.x] : 0u;
-        uint64_t colB[kSuper], rowB[kSuper];
-        l2_colrow(l2_local_rect(valid, packed), colB, rowB, masks[w]);
-        __syncthreads();
-        l2_counts(masks[w], wc);
-        __syncthreads();
-        if (threadIdx.x < kSuper * kSuper) {
-            int tl = threadIdx.x;
-            int tx = (C.g % sxn) * kSuper + (tl & (kSuper - 1)), ty = (C.g / sxn) * kSuper + tl / kSuper;
-            if (tx < gx && ty < gy) {
-                uint32_t s = 0;
-                for (int k = 0; k < kL2Waves; k++) s += wc[k * 64 + tl];
-                h2[toff[ty * gx + tx] + C.c2] = s;
-            }
+    const uint32_t G = gridDim.x;
+    for (uint32_t wi0 = blockIdx.x; wi0 < total2; wi0 += kL2Batch * G) {
+        L2Chunk C[kL2Batch];
+        uint32_t packed[kL2Batch], hoff[kL2Batch];
+        bool tin[kL2Batch];
+#pragma unroll
+        for (int b = 0; b < kL2Batch; b++) {
+            // chunks past the last are looked up as the last one (loaded, not used)
+            C[b] = l2_locate(min(wi0 + b * G, total2 - 1), T.c2s, nsuper, T.l1s, T.l1l);
+            packed[b] = list1r[C[b].first + min((uint32_t)threadIdx.x, C[b].len - 1)];
+            hoff[b] = toff[l2_tile_clamped(C[b].g, tl, sxn, gx, gy, tin[b])];
         }
-        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < kL2Batch; b++) pin_u32(packed[b], hoff[b]);
+#pragma unroll
+        for (int b = 0; b < kL2Batch; b++) {
+            if (wi0 + b * G >= total2) break;  // uniform over the workgroup
+            const bool valid = threadIdx.x < C[b].len;
+            uint64_t colB[kSuper], rowB[kSuper];
+            l2_colrow(l2_local_rect(valid, packed[b]), colB, rowB, masks[w]);
+            __syncthreads();
+            l2_counts(masks[w], wc);
+            __syncthreads();
+            if (threadIdx.x < kSuper * kSuper && tin[b]) {
+                uint32_t sum = 0;
+                for (int k = 0; k < kL2Waves; k++) sum += wc[k * 64 + tl];
+                h2[hoff[b] + C[b].c2] = sum;
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -880,74 +969,91 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_scatter(const uint32_t *list1
                                                            const int32_t *overflow_dev) {
     __shared__ uint32_t wc[kSuper * kSuper * kL2Waves];
     __shared__ uint32_t slot[kSuper * kSuper * kL2Waves];
-    __shared__ uint32_t c2s[kMaxSuperTiles + 1];
+    __shared__ L2Tables T;
     __shared__ uint64_t masks[kL2Waves][2 * kSuper];
     if (*overflow_dev) return;
     const uint32_t total2 = cnt->total2;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int t = blockIdx.x * kL2Threads + threadIdx.x; t < gx * gy; t += gridDim.x * kL2Threads)
         tile_range(base2, toff, t, cnt, ranges);
-    for (int g = threadIdx.x; g <= nsuper; g += kL2Threads) c2s[g] = chunk2_start[g];
+    l2_load_tables(T, chunk2_start, l1_start, l1_len, nsuper);
     __syncthreads();
     const uint32_t cap32 = (uint32_t)min(k_capacity, (int64_t)0xFFFFFFFFll);
-    for (uint32_t wi = blockIdx.x; wi < total2; wi += gridDim.x) {
-        L2Chunk C = l2_locate(wi, c2s, nsuper, l1_start, l1_len);
-        bool valid = threadIdx.x < C.len;
-        uint32_t id = 0, db = 0, packed = 0;
-        if (valid) {
-            id = list1[C.first + threadIdx.x];
-            packed = list1r[C.first + threadIdx.x];
-            if (keys) db = __float_as_uint(depth[id]);  // keys are optional: gather the depth only for them
-        }
-        uint64_t colB[kSuper], rowB[kSuper];
-        l2_colrow(l2_local_rect(valid, packed), colB, rowB, masks[w]);
-        __syncthreads();
-        l2_counts(masks[w], wc);
-        __syncthreads();
-        const int tx0 = (C.g % sxn) * kSuper, ty0 = (C.g / sxn) * kSuper;
-        {
-            // thread (wave ww, tile tl): first slot of wave ww's entries in tile tl
-            static_assert(kSuper * kSuper * kL2Waves == kL2Threads, "one thread per (wave, tile)");
-            const int ww = threadIdx.x >> 6, tl = threadIdx.x & 63;
-            const int tx = tx0 + (tl & (kSuper - 1)), ty = ty0 + tl / kSuper;
-            if (tx < gx && ty < gy) {
-                uint32_t s = base2[toff[ty * gx + tx] + C.c2];
-                for (int k = 0; k < ww; k++) s += wc[k * 64 + tl];
-                slot[threadIdx.x] = s;
-            }
-        }
-        __syncthreads();
-        // lane tl holds this wave's first slot in tile tl; broadcast per tile with v_readlane
-        const uint32_t myslot = slot[w * 64 + lane];
-        bool inside = true;
-        if constexpr (FAST) {
-            // every run of this wave lies inside the capacity (K <= capacity is decided
-            // before any instance is written; this test only guards the stores)
-            const uint32_t myc = wc[w * 64 + lane];
-            uint32_t e = myc ? myslot + myc : 0u;
+    const uint32_t G = gridDim.x;
+    for (uint32_t wi0 = blockIdx.x; wi0 < total2; wi0 += kL2Batch * G) {
+        // every load of the batch: entries (splat index, local rectangle) and the
+        // count offset of this thread's (wave, tile) slot, then the slot bases
+        L2Chunk C[kL2Batch];
+        uint32_t id[kL2Batch], packed[kL2Batch], sbase[kL2Batch], db[kL2Batch];
+        bool tin[kL2Batch];
 #pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) e = max(e, (uint32_t)__shfl_xor((int)e, off, 64));
-            inside = e <= cap32;
+        for (int b = 0; b < kL2Batch; b++) {
+            C[b] = l2_locate(min(wi0 + b * G, total2 - 1), T.c2s, nsuper, T.l1s, T.l1l);
+            const uint32_t e = C[b].first + min((uint32_t)threadIdx.x, C[b].len - 1);
+            id[b] = list1[e];
+            packed[b] = list1r[e];
+            sbase[b] = toff[l2_tile_clamped(C[b].g, lane, sxn, gx, gy, tin[b])];
         }
-        for (int rr = 0; rr < kSuper; rr++) {
-            if (rowB[rr] == 0ull || !inside) continue;  // no lane of this wave covers the row (uniform)
-            for (int cc = 0; cc < kSuper; cc++) {
-                const uint64_t m = colB[cc] & rowB[rr];
-                if (m == 0ull) continue;
-                const int tl = rr * kSuper + cc;
-                const uint32_t s0 = (uint32_t)__builtin_amdgcn_readlane((int)myslot, tl);
-                if constexpr (FAST) {
-                    store_ranked(vals, m, s0 << 2, id);
-                } else if ((m >> lane) & 1ull) {
-                    const uint32_t pos = s0 + rank_below(m);
-                    if (pos < cap32) {
-                        vals[pos] = id;
-                        if (keys) keys[pos] = ((uint64_t)(uint32_t)((ty0 + rr) * gx + tx0 + cc) << 32) | db;
+#pragma unroll
+        for (int b = 0; b < kL2Batch; b++) {
+            sbase[b] = base2[sbase[b] + C[b].c2];
+            db[b] = (!FAST && keys) ? __float_as_uint(depth[id[b]]) : 0u;  // depth only for the optional keys
+        }
+#pragma unroll
+        for (int b = 0; b < kL2Batch; b++) pin_u32(id[b], packed[b], sbase[b], db[b]);
+#pragma unroll
+        for (int b = 0; b < kL2Batch; b++) {
+            if (wi0 + b * G >= total2) break;  // uniform over the workgroup
+            const bool valid = threadIdx.x < C[b].len;
+            uint64_t colB[kSuper], rowB[kSuper];
+            l2_colrow(l2_local_rect(valid, packed[b]), colB, rowB, masks[w]);
+            __syncthreads();
+            l2_counts(masks[w], wc);
+            __syncthreads();
+            const int tx0 = (C[b].g % sxn) * kSuper, ty0 = (C[b].g / sxn) * kSuper;
+            {
+                // thread (wave ww, tile tl): first slot of wave ww's entries in tile tl
+                static_assert(kSuper * kSuper * kL2Waves == kL2Threads, "one thread per (wave, tile)");
+                const int ww = threadIdx.x >> 6, tl = threadIdx.x & 63;
+                if (tin[b]) {
+                    uint32_t sl = sbase[b];
+                    for (int k = 0; k < ww; k++) sl += wc[k * 64 + tl];
+                    slot[threadIdx.x] = sl;
+                }
+            }
+            __syncthreads();
+            // lane tl holds this wave's first slot in tile tl; broadcast per tile with v_readlane
+            const uint32_t myslot = slot[w * 64 + lane];
+            bool inside = true;
+            if constexpr (FAST) {
+                // every run of this wave lies inside the capacity (K <= capacity is decided
+                // before any instance is written; this test only guards the stores)
+                const uint32_t myc = wc[w * 64 + lane];
+                uint32_t e = myc ? myslot + myc : 0u;
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) e = max(e, (uint32_t)__shfl_xor((int)e, off, 64));
+                inside = e <= cap32;
+            }
+            for (int rr = 0; rr < kSuper; rr++) {
+                if (rowB[rr] == 0ull || !inside) continue;  // no lane of this wave covers the row (uniform)
+                for (int cc = 0; cc < kSuper; cc++) {
+                    const uint64_t m = colB[cc] & rowB[rr];
+                    if (m == 0ull) continue;
+                    const int tl = rr * kSuper + cc;
+                    const uint32_t s0 = (uint32_t)__builtin_amdgcn_readlane((int)myslot, tl);
+                    if constexpr (FAST) {
+                        store_ranked(vals, m, s0 << 2, id[b]);
+                    } else if ((m >> lane) & 1ull) {
+                        const uint32_t pos = s0 + rank_below(m);
+                        if (pos < cap32) {
+                            vals[pos] = id[b];
+                            if (keys) keys[pos] = ((uint64_t)(uint32_t)((ty0 + rr) * gx + tx0 + cc) << 32) | db[b];
+                        }
                     }
                 }
             }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 
