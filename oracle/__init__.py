@@ -304,11 +304,40 @@ def bin_sort(xy, radius, depth, width: int, height: int, cap: int | None = None)
 # end-to-end helpers
 # --------------------------------------------------------------------------
 
-def render(cam: Camera, k: KernelSpec, opts: Opts, params: dict, pix=None, use_grid=True):
-    """preprocess + composite.  params: means, scales, quats, opacity, sh, sh_degree."""
+def conic_factor(cov2d) -> np.ndarray:
+    """The triangular factor L = [[l00, l01], [0, l11]] of the conic, Q = L^T L,
+    from the 2D covariance (c00, c01, c11) [n, 3]: Q = Sigma'^-1, so
+    l11 = 1/sqrt(c11), l00 = sqrt(c11/det), l01 = -c01/sqrt(c11 det),
+    det = c00 c11 - c01^2 (the conic's storage form in the projected records)."""
+    c = np.asarray(cov2d, np.float64)
+    det = c[:, 0] * c[:, 2] - c[:, 1] ** 2
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return np.stack([np.sqrt(c[:, 2] / det), -c[:, 1] / np.sqrt(c[:, 2] * det), 1.0 / np.sqrt(c[:, 2])], 1)
+
+
+def records_fp32(proj: dict) -> dict:
+    """The projected records as the C ABI stores them, FP32: mean2D, depth and
+    colour rounded to FP32, and the conic stored as its factor L (conic_factor)
+    with each entry rounded to FP32.  Returned in FP64 for the composite, the
+    conic as L^T L of the rounded factor; culled splats keep zeros."""
+    vis = np.asarray(proj["visible"]) != 0
+    r32 = lambda a: np.asarray(a, np.float64).astype(np.float32).astype(np.float64)
+    L = np.zeros((len(vis), 3))
+    L[vis] = r32(conic_factor(proj["cov2d"][vis]))
+    conic = np.stack([L[:, 0] ** 2, L[:, 0] * L[:, 1], L[:, 1] ** 2 + L[:, 2] ** 2], 1)
+    out = dict(proj)
+    out.update(xy=r32(proj["xy"]), depth=r32(proj["depth"]), rgb=r32(proj["rgb"]), conic=conic, conic_l=L)
+    return out
+
+
+def render(cam: Camera, k: KernelSpec, opts: Opts, params: dict, pix=None, use_grid=True, fp32_records=False):
+    """preprocess + composite.  params: means, scales, quats, opacity, sh, sh_degree.
+    fp32_records: composite the records as the C ABI stores them (records_fp32)
+    instead of the FP64 projection."""
     proj = preprocess(cam, k, params["means"], params["scales"], params["quats"], params["sh"],
                       params["sh_degree"])
-    img = composite(proj, params["opacity"], k, opts, cam.width, cam.height, pix=pix, use_grid=use_grid)
+    src = records_fp32(proj) if fp32_records else proj
+    img = composite(src, params["opacity"], k, opts, cam.width, cam.height, pix=pix, use_grid=use_grid)
     return proj, img
 
 

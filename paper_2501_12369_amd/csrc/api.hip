@@ -109,10 +109,10 @@ darb_status check_camera(const darb_camera *c, darb::Cam *cam) {
     cam->height = c->height;
     cam->near_z = c->near_z;
     if (c->jac_clamp > 0.0f) {
-        cam->lim_x = c->jac_clamp * (0.5f * (float)c->width) / c->fx;
-        cam->lim_y = c->jac_clamp * (0.5f * (float)c->height) / c->fy;
+        cam->lim_x = (double)c->jac_clamp * (0.5 * (double)c->width) / (double)c->fx;
+        cam->lim_y = (double)c->jac_clamp * (0.5 * (double)c->height) / (double)c->fy;
     } else {
-        cam->lim_x = cam->lim_y = 0.0f;
+        cam->lim_x = cam->lim_y = 0.0;
     }
     cam->dilation = c->dilation;
     return DARB_OK;

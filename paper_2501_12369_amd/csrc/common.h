@@ -299,7 +299,8 @@ struct Cam {
     float campos[3];
     float fx, fy, cx, cy;
     int width, height;
-    float near_z, lim_x, lim_y;  // lim <= 0 disables the Jacobian clamp
+    float near_z;
+    double lim_x, lim_y;  // limits of |t_x/t_z|, |t_y/t_z| in J (FP64, as the projection); <= 0: no clamp
     float dilation;
 };
 

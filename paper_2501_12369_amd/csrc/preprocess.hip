@@ -112,45 +112,6 @@ __device__ __forceinline__ void sh_grad(float x, float y, float z, const float *
     out[2] = gz;
 }
 
-// View-independent geometry of a splat: unit quaternion, rotation, 3D covariance.
-struct Geom {
-    float Rq[9];         // rotation of the splat
-    float qn[4], qinv;   // unit quaternion, 1/|q|
-    float s[3];
-    float Sig[6];        // 3D covariance (xx, xy, xz, yy, yz, zz)
-};
-
-// Everything the forward computes for one splat in one view and the backward
-// needs again.
-struct Proj {
-    float t[3];
-    float xt, yt;
-    bool cx_, cy_;       // Jacobian clamp active in x / y
-    float J00, J02, J11, J12;
-    float A[6];          // J R_cw, 2x3
-    float c00, c01, c11; // 2D covariance
-    float det;
-    float a, b, c;       // conic Q = [[a, b], [b, c]]
-    float l00, l01, l11; // Q = L^T L, L = [[l00, l01], [0, l11]]
-    float u, v;          // mean2D
-    int radius;
-};
-
-__device__ __forceinline__ void load_mean(const darb_splats &in, int n, int i, float (&m)[3]) {
-    m[0] = in.means[i];
-    m[1] = in.means[n + i];
-    m[2] = in.means[2 * n + i];
-}
-
-// t = R_cw mu + t_cw; false when the splat is not in front of the near plane.
-__device__ __forceinline__ bool view_depth(const Cam &cam, const float (&m)[3], Proj &P) {
-    const float *R = cam.R;
-    P.t[0] = fmaf(R[0], m[0], fmaf(R[1], m[1], fmaf(R[2], m[2], cam.t[0])));
-    P.t[1] = fmaf(R[3], m[0], fmaf(R[4], m[1], fmaf(R[5], m[2], cam.t[1])));
-    P.t[2] = fmaf(R[6], m[0], fmaf(R[7], m[1], fmaf(R[8], m[2], cam.t[2])));
-    return P.t[2] > cam.near_z;
-}
-
 // A splat's rotation and scale parameters as loaded: quaternion (w, x, y, z), scales.
 struct QS {
     float q[4], s[3];
@@ -163,108 +124,116 @@ __device__ __forceinline__ QS load_qs(const darb_splats &in, int n, int i) {
     return v;
 }
 
-// Rotation and covariance from loaded parameters; false for a zero quaternion.
-__device__ __forceinline__ bool splat_geom_of(const QS &v, Geom &G) {
-    const float qw = v.q[0], qx = v.q[1], qy = v.q[2], qz = v.q[3];
-    float qq = fmaf(qw, qw, fmaf(qx, qx, fmaf(qy, qy, qz * qz)));
-    G.s[0] = v.s[0]; G.s[1] = v.s[1]; G.s[2] = v.s[2];
-    if (!(qq > 0.0f)) return false;
-    float qnorm = sqrtf(qq);
-    G.qinv = 1.0f / qnorm;
-    float w = qw * G.qinv, x = qx * G.qinv, y = qy * G.qinv, z = qz * G.qinv;
+__device__ __forceinline__ void load_mean(const darb_splats &in, int n, int i, float (&m)[3]) {
+    m[0] = in.means[i];
+    m[1] = in.means[n + i];
+    m[2] = in.means[2 * n + i];
+}
+
+// View-independent geometry of a splat in FP64 from its FP32 parameters: unit
+// quaternion, rotation, scales, 3D covariance Sigma = R diag(s^2) R^T (all nine
+// entries, each summed in the order of the definition).
+struct Geom64 {
+    double Rq[9], qn[4], qinv, s[3], S[9];
+};
+
+// false for a zero (or non-finite) quaternion
+__device__ __forceinline__ bool splat_geom64(const QS &v, Geom64 &G) {
+    const double q0 = v.q[0], q1 = v.q[1], q2 = v.q[2], q3 = v.q[3];
+    const double qnorm = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+    G.s[0] = v.s[0];
+    G.s[1] = v.s[1];
+    G.s[2] = v.s[2];
+    if (!(qnorm > 0.0)) return false;
+    G.qinv = 1.0 / qnorm;
+    const double w = q0 / qnorm, x = q1 / qnorm, y = q2 / qnorm, z = q3 / qnorm;
     G.qn[0] = w; G.qn[1] = x; G.qn[2] = y; G.qn[3] = z;
-    float *Rq = G.Rq;
-    Rq[0] = 1.0f - 2.0f * (y * y + z * z);
-    Rq[1] = 2.0f * (x * y - w * z);
-    Rq[2] = 2.0f * (x * z + w * y);
-    Rq[3] = 2.0f * (x * y + w * z);
-    Rq[4] = 1.0f - 2.0f * (x * x + z * z);
-    Rq[5] = 2.0f * (y * z - w * x);
-    Rq[6] = 2.0f * (x * z - w * y);
-    Rq[7] = 2.0f * (y * z + w * x);
-    Rq[8] = 1.0f - 2.0f * (x * x + y * y);
-    float s2[3] = {G.s[0] * G.s[0], G.s[1] * G.s[1], G.s[2] * G.s[2]};
-    // Sigma = Rq diag(s^2) Rq^T (upper triangle)
-    int k = 0;
+    double *Rq = G.Rq;
+    Rq[0] = 1.0 - 2.0 * (y * y + z * z);
+    Rq[1] = 2.0 * (x * y - w * z);
+    Rq[2] = 2.0 * (x * z + w * y);
+    Rq[3] = 2.0 * (x * y + w * z);
+    Rq[4] = 1.0 - 2.0 * (x * x + z * z);
+    Rq[5] = 2.0 * (y * z - w * x);
+    Rq[6] = 2.0 * (x * z - w * y);
+    Rq[7] = 2.0 * (y * z + w * x);
+    Rq[8] = 1.0 - 2.0 * (x * x + y * y);
     for (int r = 0; r < 3; r++)
-        for (int cc = r; cc < 3; cc++) {
-            G.Sig[k++] = fmaf(Rq[r * 3 + 0] * s2[0], Rq[cc * 3 + 0],
-                              fmaf(Rq[r * 3 + 1] * s2[1], Rq[cc * 3 + 1], Rq[r * 3 + 2] * s2[2] * Rq[cc * 3 + 2]));
+        for (int c = 0; c < 3; c++) {
+            double acc = 0.0;
+            for (int l = 0; l < 3; l++) acc += Rq[r * 3 + l] * G.s[l] * G.s[l] * Rq[c * 3 + l];
+            G.S[r * 3 + c] = acc;
         }
     return true;
 }
 
-// Rotation and covariance of splat i; false for a zero quaternion.
-__device__ __forceinline__ bool splat_geom(int n, int i, const darb_splats &in, Geom &G) {
-    return splat_geom_of(load_qs(in, n, i), G);
+// Projection of one splat in one view.  Computed in FP64 from the FP32 inputs
+// and rounded once to the FP32 records (mean2D, depth, conic factor): the
+// records are the correctly rounded values of the projection's definition,
+// so the rasterizer sees the same inputs whatever order a faster FP32 chain
+// would have taken.  The kernel is HBM-bound; the FP64 arithmetic (vector FP64
+// runs at the non-packed FP32 rate on this GPU) is hidden behind the loads.
+struct Proj {
+    double t[3];
+    double xt, yt;        // t_x / t_z, t_y / t_z, clamped for the Jacobian
+    bool cx_, cy_;        // Jacobian clamp active in x / y
+    float u, v;           // mean2D (rounded)
+    float l00, l01, l11;  // Q = L^T L, L = [[l00, l01], [0, l11]] (rounded)
+    int radius;
+};
+
+// t = R_cw mu + t_cw; false when the splat is not in front of the near plane.
+__device__ __forceinline__ bool view_depth(const Cam &cam, const float (&m)[3], Proj &P) {
+    for (int r = 0; r < 3; r++)
+        P.t[r] = (double)cam.R[r * 3] * m[0] + (double)cam.R[r * 3 + 1] * m[1] + (double)cam.R[r * 3 + 2] * m[2] +
+                 (double)cam.t[r];
+    return P.t[2] > (double)cam.near_z;
 }
 
-// Projection of a splat in front of the camera (P.t set); false when culled.
-__device__ __forceinline__ bool project_rest(const Cam &cam, const KParams &kp, const Geom &G, Proj &P) {
-    const float *R = cam.R;
-    float tz = P.t[2], itz = 1.0f / tz;
-    P.xt = P.t[0] * itz;
-    P.yt = P.t[1] * itz;
+// The rest of the projection of a splat in front of the camera (P.t set);
+// false when culled (singular 2D covariance, or a radius box off the tile grid).
+__device__ __forceinline__ bool project_rest(const Cam &cam, const KParams &kp, const Geom64 &G, Proj &P) {
+    const double tz = P.t[2], fx = cam.fx, fy = cam.fy;
+    P.xt = P.t[0] / tz;
+    P.yt = P.t[1] / tz;
     P.cx_ = P.cy_ = false;
-    if (cam.lim_x > 0.0f) {
+    if (cam.lim_x > 0.0) {
         if (P.xt > cam.lim_x) { P.xt = cam.lim_x; P.cx_ = true; }
         if (P.xt < -cam.lim_x) { P.xt = -cam.lim_x; P.cx_ = true; }
         if (P.yt > cam.lim_y) { P.yt = cam.lim_y; P.cy_ = true; }
         if (P.yt < -cam.lim_y) { P.yt = -cam.lim_y; P.cy_ = true; }
     }
-    P.J00 = cam.fx * itz;
-    P.J02 = -cam.fx * P.xt * itz;
-    P.J11 = cam.fy * itz;
-    P.J12 = -cam.fy * P.yt * itz;
-    // A = J R_cw
-    for (int cc = 0; cc < 3; cc++) {
-        P.A[cc] = fmaf(P.J00, R[cc], P.J02 * R[6 + cc]);
-        P.A[3 + cc] = fmaf(P.J11, R[3 + cc], P.J12 * R[6 + cc]);
+    const double J00 = fx / tz, J02 = -fx * P.xt / tz, J11 = fy / tz, J12 = -fy * P.yt / tz;
+    // A = J R_cw (2x3), M = A Sigma A^T
+    double A[6];
+    for (int c = 0; c < 3; c++) {
+        A[c] = J00 * (double)cam.R[c] + J02 * (double)cam.R[6 + c];
+        A[3 + c] = J11 * (double)cam.R[3 + c] + J12 * (double)cam.R[6 + c];
     }
-    // M = A Sigma A^T = B B^T with B = A Rq diag(s) (2x3).  The entries are dot
-    // products of B's rows; the determinant comes from Cauchy-Binet,
-    // det(B B^T) = sum of the squared 2x2 minors of B, each minor with Kahan's
-    // FMA difference: no cancellation, so needle-like footprints (M nearly of
-    // rank 1, the minor axis set by the dilation) keep an accurate conic.
-    float Bm[2][3];
+    double AS[6];
     for (int r = 0; r < 2; r++)
-        for (int cc = 0; cc < 3; cc++)
-            Bm[r][cc] = fmaf(P.A[3 * r], G.Rq[cc], fmaf(P.A[3 * r + 1], G.Rq[3 + cc], P.A[3 * r + 2] * G.Rq[6 + cc])) *
-                        G.s[cc];
-    float M00 = fmaf(Bm[0][0], Bm[0][0], fmaf(Bm[0][1], Bm[0][1], Bm[0][2] * Bm[0][2]));
-    float M01 = fmaf(Bm[0][0], Bm[1][0], fmaf(Bm[0][1], Bm[1][1], Bm[0][2] * Bm[1][2]));
-    float M11 = fmaf(Bm[1][0], Bm[1][0], fmaf(Bm[1][1], Bm[1][1], Bm[1][2] * Bm[1][2]));
-    auto minor2 = [&](int i, int j) {  // Bm[0][i] Bm[1][j] - Bm[0][j] Bm[1][i], Kahan
-        const float w = Bm[0][j] * Bm[1][i];
-        const float e = fmaf(-Bm[0][j], Bm[1][i], w);
-        return fmaf(Bm[0][i], Bm[1][j], -w) + e;
-    };
-    const float m01 = minor2(0, 1), m02 = minor2(0, 2), m12 = minor2(1, 2);
-    const float detM = fmaf(m01, m01, fmaf(m02, m02, m12 * m12));
-    P.c00 = fmaf(kp.psi, M00, cam.dilation);
-    P.c01 = kp.psi * M01;
-    P.c11 = fmaf(kp.psi, M11, cam.dilation);
-    // det(psi M + eps I) = psi^2 det M + eps psi tr M + eps^2
-    const float eps = cam.dilation;
-    P.det = fmaf(kp.psi * kp.psi, detM, eps * fmaf(kp.psi, M00 + M11, eps));
-    if (!(P.det > 0.0f)) return false;
-    float idet = 1.0f / P.det;
-    P.a = P.c11 * idet;
-    P.b = -P.c01 * idet;
-    P.c = P.c00 * idet;
-    // factor of Q from the covariance, no subtraction: l11 = 1/sqrt(c11),
-    // l00 = sqrt(c11/det), l01 = -c01/sqrt(c11 det)
-    const float rc11 = rsqrtf(P.c11);
-    P.l11 = rc11;
-    P.l00 = sqrtf(P.c11 * idet);
-    P.l01 = -P.c01 * rsqrtf(P.c11 * P.det);
-    P.u = fmaf(cam.fx, P.t[0] * itz, cam.cx);
-    P.v = fmaf(cam.fy, P.t[1] * itz, cam.cy);
-    float mid = 0.5f * (P.c00 + P.c11);
-    float disc = fmaf(mid, mid, -P.det);
-    float lam = mid + sqrtf(fmaxf(disc, 0.0f));
-    P.radius = (int)ceilf(kp.rfac * sqrtf(lam));
-    // radius box on the tile grid (same FP32 expression as the binning)
+        for (int c = 0; c < 3; c++)
+            AS[r * 3 + c] = A[r * 3] * G.S[c] + A[r * 3 + 1] * G.S[3 + c] + A[r * 3 + 2] * G.S[6 + c];
+    const double M00 = AS[0] * A[0] + AS[1] * A[1] + AS[2] * A[2];
+    const double M01 = AS[0] * A[3] + AS[1] * A[4] + AS[2] * A[5];
+    const double M11 = AS[3] * A[3] + AS[4] * A[4] + AS[5] * A[5];
+    // Sigma'_2x2 = psi M + eps I, conic Q = Sigma'^-1
+    const double psi = kp.psi, eps = cam.dilation;
+    const double c00 = psi * M00 + eps, c01 = psi * M01, c11 = psi * M11 + eps;
+    const double det = c00 * c11 - c01 * c01;
+    if (!(det > 0.0)) return false;
+    P.l11 = (float)(1.0 / sqrt(c11));
+    P.l00 = (float)sqrt(c11 / det);
+    P.l01 = (float)(-c01 / sqrt(c11 * det));
+    P.u = (float)(fx * P.t[0] / tz + (double)cam.cx);
+    P.v = (float)(fy * P.t[1] / tz + (double)cam.cy);
+    // radius rf sqrt(lambda_max), rf = 3 (or sqrt(e_max) beyond E = 9)
+    const double mid = 0.5 * (c00 + c11);
+    const double disc = mid * mid - det;
+    const double lam = mid + sqrt(disc > 0.0 ? disc : 0.0);
+    const double rf = kp.e_max > 9.0f ? sqrt((double)kp.e_max) : 3.0;
+    P.radius = (int)ceil(rf * sqrt(lam));
+    // radius box on the tile grid (the binning's FP32 expression on the stored mean)
     int gx = (cam.width + kTile - 1) / kTile, gy = (cam.height + kTile - 1) / kTile;
     float r = (float)P.radius;
     float x0 = fminf(fmaxf(floorf((P.u - r) * 0.0625f), 0.0f), (float)gx);
@@ -273,6 +242,37 @@ __device__ __forceinline__ bool project_rest(const Cam &cam, const KParams &kp, 
     float y1 = fminf(fmaxf(floorf((P.v + r) * 0.0625f) + 1.0f, 0.0f), (float)gy);
     if (!((x1 > x0) & (y1 > y0))) return false;
     return true;
+}
+
+// The forward's Jacobian-clamp decisions, as the backward needs them.
+struct Clamp {
+    double xt, yt;  // the clamped t_x / t_z, t_y / t_z (used where the clamp is active)
+    bool cx_, cy_;
+};
+
+// The clamp decisions alone (the splat known to be in front of the camera).
+__device__ __forceinline__ void clamp_of(const Cam &cam, const float (&m)[3], Clamp &cj) {
+    Proj P;
+    view_depth(cam, m, P);
+    cj.xt = P.t[0] / P.t[2];
+    cj.yt = P.t[1] / P.t[2];
+    cj.cx_ = cj.cy_ = false;
+    if (cam.lim_x > 0.0) {
+        if (cj.xt > cam.lim_x) { cj.xt = cam.lim_x; cj.cx_ = true; }
+        if (cj.xt < -cam.lim_x) { cj.xt = -cam.lim_x; cj.cx_ = true; }
+        if (cj.yt > cam.lim_y) { cj.yt = cam.lim_y; cj.cy_ = true; }
+        if (cj.yt < -cam.lim_y) { cj.yt = -cam.lim_y; cj.cy_ = true; }
+    }
+}
+
+// Whether the forward kept the splat, and its clamp decisions.
+__device__ __forceinline__ bool forward_visible(const Cam &cam, const KParams &kp, const float (&m)[3], const QS &qs,
+                                                Clamp &cj) {
+    Proj P;
+    Geom64 G;
+    const bool vis = view_depth(cam, m, P) && splat_geom64(qs, G) && project_rest(cam, kp, G, P);
+    cj = Clamp{P.xt, P.yt, P.cx_, P.cy_};
+    return vis;
 }
 
 // Marks a loaded value as used here.  Loads whose values are used only under a
@@ -318,10 +318,10 @@ __device__ __forceinline__ Cam cam_from_device(const darb_camera *c, int width, 
     m.near_z = c->near_z;
     if (!(m.fx > 0.0f) || !(m.fy > 0.0f) || !(m.near_z > 0.0f)) m.near_z = INFINITY;
     if (c->jac_clamp > 0.0f && m.near_z < INFINITY) {
-        m.lim_x = c->jac_clamp * (0.5f * (float)width) / m.fx;
-        m.lim_y = c->jac_clamp * (0.5f * (float)height) / m.fy;
+        m.lim_x = (double)c->jac_clamp * (0.5 * (double)width) / (double)m.fx;
+        m.lim_y = (double)c->jac_clamp * (0.5 * (double)height) / (double)m.fy;
     } else {
-        m.lim_x = m.lim_y = 0.0f;
+        m.lim_x = m.lim_y = 0.0;
     }
     m.dilation = fmaxf(c->dilation, 0.0f);
     return m;
@@ -363,7 +363,7 @@ __device__ __forceinline__ void sh_colour(const Cam &cam, const float (&m)[3], c
 // geometry part of the record (what the binning reads) ...
 __device__ __forceinline__ void store_geom(const darb_projected &out, int i, bool vis, const Proj &P, float op) {
     reinterpret_cast<float2 *>(out.xy)[i] = vis ? make_float2(P.u, P.v) : make_float2(0.0f, 0.0f);
-    out.depth[i] = vis ? P.t[2] : 0.0f;
+    out.depth[i] = vis ? (float)P.t[2] : 0.0f;
     out.radius[i] = vis ? P.radius : 0;
     reinterpret_cast<float4 *>(out.conic_o)[i] = vis ? make_float4(P.l00, P.l01, P.l11, op) : make_float4(0, 0, 0, 0);
 }
@@ -401,9 +401,9 @@ __global__ __launch_bounds__(256) void k_preprocess(Cam cam_arg, const darb_came
     const QS qs = load_qs(in, n, i);
     const float op_in = in.opacity[i];
     pin_geometry(m, qs);
-    Geom G;
+    Geom64 G;
     Proj P;
-    const bool vis = view_depth(cam, m, P) && splat_geom_of(qs, G) && project_rest(cam, kp, G, P);
+    const bool vis = view_depth(cam, m, P) && splat_geom64(qs, G) && project_rest(cam, kp, G, P);
     float col[3] = {0.0f, 0.0f, 0.0f};
     float jac[9] = {};
     float op = 0.0f;
@@ -432,9 +432,9 @@ __global__ __launch_bounds__(256) void k_preprocess_geom(Cam cam, KParams kp, in
     const QS qs = load_qs(in, n, i);
     const float op_in = in.opacity[i];
     pin_geometry(m, qs);
-    Geom G;
+    Geom64 G;
     Proj P;
-    const bool vis = view_depth(cam, m, P) && splat_geom_of(qs, G) && project_rest(cam, kp, G, P);
+    const bool vis = view_depth(cam, m, P) && splat_geom64(qs, G) && project_rest(cam, kp, G, P);
     store_geom(out, i, vis, P, vis ? op_in : 0.0f);
 }
 
@@ -445,6 +445,10 @@ __global__ __launch_bounds__(256) void k_preprocess_geom(Cam cam, KParams kp, in
 // grid of memory-bound waves would take the compute units from the
 // latency-bound binning kernels and slow them by about its own duration.
 constexpr int kColourThreads = 128;
+#ifndef DARB_COLOUR_WGS_PER_CU
+#define DARB_COLOUR_WGS_PER_CU 1
+#endif
+constexpr int kColourWgsPerCu = DARB_COLOUR_WGS_PER_CU;  // workgroups per compute unit (a tuning constant)
 
 template <int DEG>
 __global__ __launch_bounds__(kColourThreads) void k_preprocess_colour(Cam cam, int n, darb_splats in, darb_projected out) {
@@ -476,8 +480,8 @@ __global__ __launch_bounds__(256) void k_preprocess_multi(Cams cams, KParams kp,
     if (i >= n) return;
     float m[3];
     load_mean(in, n, i, m);
-    Geom G;
-    const bool geom = splat_geom(n, i, in, G);
+    Geom64 G;
+    const bool geom = splat_geom64(load_qs(in, n, i), G);
     float c[NB][3];
     float op = 0.0f;
     if (geom) {
@@ -504,39 +508,6 @@ __global__ __launch_bounds__(256) void k_preprocess_multi(Cams cams, KParams kp,
         else
             one_view(cams.c[v], outs.p[v]);
     }
-}
-
-// FP64 copy of the view-independent geometry (unit quaternion, rotation,
-// scales, 3D covariance), from the FP32 parameters.
-struct Geom64 {
-    double Rq[9], qn[4], qinv, s[3], Sig[6];
-};
-
-// The quaternion is nonzero (the FP32 geometry of a visible splat exists).
-__device__ __forceinline__ void splat_geom64(const QS &v, Geom64 &G) {
-    const double qw = v.q[0], qx = v.q[1], qy = v.q[2], qz = v.q[3];
-    G.s[0] = v.s[0];
-    G.s[1] = v.s[1];
-    G.s[2] = v.s[2];
-    G.qinv = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
-    const double w = qw * G.qinv, x = qx * G.qinv, y = qy * G.qinv, z = qz * G.qinv;
-    G.qn[0] = w; G.qn[1] = x; G.qn[2] = y; G.qn[3] = z;
-    double *Rq = G.Rq;
-    Rq[0] = 1.0 - 2.0 * (y * y + z * z);
-    Rq[1] = 2.0 * (x * y - w * z);
-    Rq[2] = 2.0 * (x * z + w * y);
-    Rq[3] = 2.0 * (x * y + w * z);
-    Rq[4] = 1.0 - 2.0 * (x * x + z * z);
-    Rq[5] = 2.0 * (y * z - w * x);
-    Rq[6] = 2.0 * (x * z - w * y);
-    Rq[7] = 2.0 * (y * z + w * x);
-    Rq[8] = 1.0 - 2.0 * (x * x + y * y);
-    const double s2[3] = {G.s[0] * G.s[0], G.s[1] * G.s[1], G.s[2] * G.s[2]};
-    int k = 0;
-    for (int r = 0; r < 3; r++)
-        for (int cc = r; cc < 3; cc++)
-            G.Sig[k++] = Rq[r * 3] * s2[0] * Rq[cc * 3] + Rq[r * 3 + 1] * s2[1] * Rq[cc * 3 + 1] +
-                         Rq[r * 3 + 2] * s2[2] * Rq[cc * 3 + 2];
 }
 
 // Per-view part of the gradient of one visible splat: the mean (through mu',
@@ -648,7 +619,7 @@ __device__ __forceinline__ G2v load_g2(const darb_grads2d &g2, int i) {
 
 // dmu_sh: the mean's gradient through the view direction (colour part, FP32).
 __device__ __forceinline__ void splat_bwd_view(const Cam &cam, const KParams &kp, const float (&m)[3],
-                                               const G2v &g2, const Geom64 &G, const Proj &P,
+                                               const G2v &g2, const Geom64 &G, const Clamp &P,
                                                const float (&dmu_sh)[3], float (&dmu)[3], float (&dsc)[3],
                                                float (&dqo)[4]) {
 
@@ -670,8 +641,7 @@ __device__ __forceinline__ void splat_bwd_view(const Cam &cam, const KParams &kp
         A[cc] = J00 * R[cc] + J02 * R[6 + cc];
         A[3 + cc] = J11 * R[3 + cc] + J12 * R[6 + cc];
     }
-    const double *Sg = G.Sig;
-    const double Sf[9] = {Sg[0], Sg[1], Sg[2], Sg[1], Sg[3], Sg[4], Sg[2], Sg[4], Sg[5]};
+    const double *Sf = G.S;
     double AS0[3], AS1[3];  // A Sigma (2x3)
     for (int cc = 0; cc < 3; cc++) {
         AS0[cc] = A[0] * Sf[cc] + A[1] * Sf[3 + cc] + A[2] * Sf[6 + cc];
@@ -819,10 +789,18 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(Cam cam, KParams kp, int
             for (int k = 0; k < 9; k++) pin(jac[k]);
             pin(__uint_as_float((uint32_t)cl));
         }
-        Geom G;
-        Proj P;
-        // the FP32 decisions of the forward (recomputed: the same expressions on the same inputs)
-        const bool vis = view_depth(cam, m, P) && splat_geom_of(qs, G) && project_rest(cam, kp, G, P);
+        // the forward's decisions (recomputed: the same expressions on the same
+        // inputs); of the projection only the Jacobian clamp is kept, and the
+        // FP64 geometry is rebuilt for the chain (fewer registers live across
+        // the colour part)
+        Clamp cj;
+        bool vis;
+        if constexpr (CKPT) {
+            vis = true;  // the forward's radius kept it
+            clamp_of(cam, m, cj);
+        } else {
+            vis = forward_visible(cam, kp, m, qs, cj);
+        }
         if (vis) {
             float Y[NB], gv[3], dmu_sh[3];
             if constexpr (CKPT) {
@@ -834,7 +812,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd(Cam cam, KParams kp, int
             }
             Geom64 G64;
             splat_geom64(qs, G64);
-            splat_bwd_view(cam, kp, m, gin, G64, P, dmu_sh, g.dmu, g.dsc, g.dq);
+            splat_bwd_view(cam, kp, m, gin, G64, cj, dmu_sh, g.dmu, g.dsc, g.dq);
             g.dop = gin.op;
 #pragma unroll
             for (int b = 0; b < NB; b++)
@@ -856,11 +834,10 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_multi(Cams cams, KParams
     if (i >= n) return;
     float m[3];
     load_mean(in, n, i, m);
-    // the geometry is rebuilt per view from the loaded parameters (FP32 for the
-    // decisions, FP64 for the chain) instead of kept across the loop: fewer
-    // registers live beside the colour accumulators
+    // the geometry is rebuilt per view from the loaded parameters instead of
+    // kept across the loop: fewer registers live beside the colour accumulators
     const QS qs = load_qs(in, n, i);
-    const bool geom = fmaf(qs.q[0], qs.q[0], fmaf(qs.q[1], qs.q[1], fmaf(qs.q[2], qs.q[2], qs.q[3] * qs.q[3]))) > 0.0f;
+    const bool geom = (qs.q[0] != 0.0f) | (qs.q[1] != 0.0f) | (qs.q[2] != 0.0f) | (qs.q[3] != 0.0f);
     Grad3 tot = {};
     float gsh[NB][3];
 #pragma unroll
@@ -871,9 +848,8 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_multi(Cams cams, KParams
         if constexpr (!CKPT) load_sh<NB>(in.sh, n, i, csh);
         for (int v = 0; v < cams.nv; v++) {
             const Cam &cam = cams.c[v];
-            Proj P;
-            Geom G;
-            if (!(view_depth(cam, m, P) && splat_geom_of(qs, G) && project_rest(cam, kp, G, P))) continue;
+            Clamp cj;
+            if (!forward_visible(cam, kp, m, qs, cj)) continue;
             vmask |= 1u << v;
             const G2v gin = load_g2(g2.g[v], i);
             float Y[NB], gv[3], dmu_sh[3];
@@ -888,7 +864,7 @@ __global__ __launch_bounds__(256) void k_preprocess_bwd_multi(Cams cams, KParams
             Geom64 G64;
             splat_geom64(qs, G64);
             Grad3 g;
-            splat_bwd_view(cam, kp, m, gin, G64, P, dmu_sh, g.dmu, g.dsc, g.dq);
+            splat_bwd_view(cam, kp, m, gin, G64, cj, dmu_sh, g.dmu, g.dsc, g.dq);
             g.dop = gin.op;
 #pragma unroll
             for (int c = 0; c < 3; c++) {
@@ -960,7 +936,8 @@ hipError_t launch_preprocess_parts(const Cam &cam, const KParams &kp, int n, con
                 hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
                 cus = 256;
         }
-        const dim3 gc(std::min<unsigned>((unsigned)((n + kColourThreads - 1) / kColourThreads), (unsigned)cus));
+        const dim3 gc(std::min<unsigned>((unsigned)((n + kColourThreads - 1) / kColourThreads),
+                                         (unsigned)(cus * kColourWgsPerCu)));
         const dim3 bc(kColourThreads);
         switch (in.sh_degree) {
         case 0: hipLaunchKernelGGL(k_preprocess_colour<0>, gc, bc, 0, s, cam, n, in, out); break;

@@ -30,6 +30,19 @@ ORACLE_KERNELS = {
 }
 
 
+def decision_rings(name: str) -> int:
+    """Level sets per footprint where a pixel's decision can flip: the boundaries
+    of the ranges of E in (0, e_max] where o F(E) stays below alpha_min at full
+    opacity, plus the support edge when F does not vanish there (the Gaussian's
+    jump).  One for a single decaying lobe; a kernel with interior zeros (several
+    pulses) adds two per zero.  Ambiguous pixels are capped at 0.1% per ring."""
+    k = ORACLE_KERNELS[name]
+    E = np.linspace(0.0, k.e_max, 200001)
+    low = np.abs(oracle.kernel_values(k.kind, k.xi, E, k.beta)) < 1.0 / 255.0
+    rings = int(np.count_nonzero(low[1:] != low[:-1]))
+    return rings + (0 if low[-1] else 1)
+
+
 def oracle_kernel_fp32(name: str) -> oracle.KernelSpec:
     """The oracle's kernel with xi/psi/e_max rounded to FP32, as the GPU receives them."""
     k = ORACLE_KERNELS[name]
@@ -139,6 +152,26 @@ def assert_grads(g_gpu: dict, g_orc: dict, names, label="", **tol):
         ok, l2, ratio = grad_compare(g_gpu[name], g_orc[name], **tol)
         print(f"  {label}{name:8s} relL2={l2:.2e} worst={ratio:.3f}")
         assert ok, (label, name, l2, ratio)
+
+
+def assert_records_fp32(proj: dict, o: dict, both: np.ndarray, ulps: int = 1, label: str = ""):
+    """The records the library stored (mean2D, depth, conic factor) equal the
+    oracle's FP64 projection rounded to FP32 (oracle.records_fp32) within
+    ``ulps`` units in the last place, on the splats ``both`` sides kept.  The
+    library computes the projection in FP64 and rounds once, so a difference
+    appears only where the FP64 value lies within FP64 rounding of an FP32
+    rounding boundary."""
+    r = oracle.records_fp32(o)
+    pairs = {"xy": (to_np(proj["xy"])[both], r["xy"][both]),
+             "depth": (to_np(proj["depth"])[both], r["depth"][both]),
+             "conic_l": (to_np(proj["conic_o"])[both][:, :3], r["conic_l"][both])}
+    for name, (g, ref) in pairs.items():
+        ref32 = ref.astype(np.float32)
+        d = np.abs(np.asarray(g, np.float32).astype(np.float64) - ref32.astype(np.float64))
+        sp = np.spacing(np.abs(ref32)).astype(np.float64)
+        print(f"  {label}{name}: {int(np.sum(d > 0))} of {d.size} differ from the rounded oracle, "
+              f"worst {np.max(d / sp) if d.size else 0:.1f} ulp")
+        assert np.all(d <= ulps * sp), name
 
 
 def visibility_ambiguous(sp: dict, cam: dict, o: dict, idx, rel: float = 1e-5) -> np.ndarray:

@@ -98,7 +98,7 @@ def test_degenerate_inputs_end_to_end(kname, eps):
     fr = pipeline.render(spd, cam, kern, n_contrib=True)
     torch.cuda.synchronize()
     ocam, ko, oo = oracle.camera_from_scene(cam), oracle_kernel_fp32(kname), oracle_opts_fp32()
-    proj_o, img_o = oracle.render(ocam, ko, oo, sp)
+    proj_o, img_o = oracle.render(ocam, ko, oo, sp, fp32_records=True)
     # culling decisions: exactly the oracle's
     vis_g = to_np(fr.proj["radius"]) > 0
     vis_o = proj_o["visible"] == 1

@@ -136,7 +136,7 @@ def test_multiview_gradients_match_oracle(kname, det):
     assert not pipeline.multiview_overflowed(mf)
     Gs = []
     for v, (oc, t, fr) in enumerate(zip(ocams, targets, mf.frames)):
-        _, img_o = oracle.render(oc, ko, oo, params)
+        _, img_o = oracle.render(oc, ko, oo, params, fp32_records=True)
         ok = img_o["margin"] >= 1e-4
         assert ok.mean() > 0.99
         err = np.abs(image_pixels(to_np(fr.image)) - img_o["rgb"])

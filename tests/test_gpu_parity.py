@@ -19,9 +19,10 @@ import torch
 import oracle
 from paper_2501_12369_amd import native, pipeline, scenes
 
-from gpu_util import (ORACLE_KERNELS, ambiguous_zeroed, assert_grads, conic_from_factor, dev, gpu_bin_raster,
-                      grad_compare, image_pixels, last_ids, oracle_kernel_fp32, oracle_opts_fp32, oracle_projected,
-                      projected_to_device, to_np, visibility_ambiguous)
+from gpu_util import (ORACLE_KERNELS, ambiguous_zeroed, assert_grads, assert_records_fp32, conic_from_factor,
+                      decision_rings, dev,
+                      gpu_bin_raster, grad_compare, image_pixels, last_ids, oracle_kernel_fp32, oracle_opts_fp32,
+                      oracle_projected, projected_to_device, to_np, visibility_ambiguous)
 
 pytestmark = pytest.mark.gpu
 
@@ -118,7 +119,7 @@ def test_raster_fwd_parity(kname, n, W, H, seed):
     Tg = to_np(fr.final_T).reshape(-1)
     amb = orc["margin"] < AMBIG
     ok = ~amb
-    assert amb.mean() <= 1e-3, f"ambiguous fraction {amb.mean()}"
+    assert amb.mean() <= 1e-3 * decision_rings(kname), f"ambiguous fraction {amb.mean()}"
     err = np.abs(img - orc["rgb"])
     tol = 1e-5 * np.abs(orc["rgb"]) + 1e-6
     print(f"  max|dI|={err[ok].max():.3e}  worst ratio={np.max(err[ok] / tol[ok]):.3f}  ambiguous={amb.sum()}")
@@ -155,7 +156,7 @@ def test_raster_bwd_parity(kname):
     # the upstream gradient is zeroed on decision-ambiguous pixels (both sides), so
     # every splat is compared
     amb = orc["margin"] < AMBIG
-    assert amb.mean() <= 1e-3
+    assert amb.mean() <= 1e-3 * decision_rings(kname), f"ambiguous fraction {amb.mean()}"
     Go = ambiguous_zeroed(scenes.upstream_grad(seed + 1, W, H).reshape(3, -1).T, orc["margin"], AMBIG)
     G = np.ascontiguousarray(Go.T.reshape(3, H, W))
     runs = {}
@@ -295,21 +296,12 @@ def test_preprocess_parity(kname, which):
     print(f"  visibility differs for {len(diff)} of {n}")
     assert np.all(visibility_ambiguous(sp, cam, o, diff)), diff
     assert both.sum() > 0.3 * vis_o.sum() and both.sum() > 10
-    xy = to_np(proj["xy"])[both]
+    # mean2D, depth and conic factor: the FP64 projection rounded to FP32, within 1 ulp
+    assert_records_fp32(proj, o, both)
     co = to_np(proj["conic_o"])[both]
-    co = np.concatenate([conic_from_factor(co[:, :3]), co[:, 3:4].astype(np.float64)], 1)  # the factor's conic
     rgb = to_np(proj["rgb"])[both]
-    dep = to_np(proj["depth"])[both]
-    # mu' relative to the pixel scale of the image; depth, rgb relative
-    assert np.max(np.abs(xy - o["xy"][both])) <= 2e-6 * max(cam["width"], cam["height"]) + 1e-4
-    assert np.allclose(dep, o["depth"][both], rtol=2e-6)
+    # colour (FP32 SH evaluation) relative
     assert np.allclose(rgb, o["rgb"][both], rtol=1e-5, atol=1e-6)
-    # conic: relative to its own scale (Frobenius norm)
-    cq = o["conic"][both]
-    scale = np.sqrt(cq[:, 0] ** 2 + 2 * cq[:, 1] ** 2 + cq[:, 2] ** 2)
-    cerr = np.max(np.abs(co[:, :3] - cq), axis=1) / scale
-    print(f"  conic worst rel={cerr.max():.2e}")
-    assert np.all(cerr <= 1e-4)
     assert np.array_equal(co[:, 3], sp["opacity"][both])
     # radius: exact unless 3 sqrt(lambda_max) lies within 1e-4 of an integer
     cov = o["cov2d"][both]
@@ -372,7 +364,7 @@ def test_end_to_end_tiny(kname, dilation):
     ocam = oracle.camera_from_scene(cam)
     ko = oracle_kernel_fp32(kname)
     params = {k: v for k, v in sp.items()}
-    _, img_o = oracle.render(ocam, ko, oracle_opts_fp32(), params)
+    _, img_o = oracle.render(ocam, ko, oracle_opts_fp32(), params, fp32_records=True)
     # image: 1e-5 relative + 1e-6 on pixels whose decisions are further than 1e-4
     # (relative) from their thresholds
     ok = img_o["margin"] >= 1e-4
@@ -454,7 +446,7 @@ def test_rasterize_gradients_match_oracle():
     cam = dict(sc["camera"], fx=240.0, fy=240.0, cx=80.0, cy=60.0)
     W, H = cam["width"], cam["height"]
     ocam, ko, oo = oracle.camera_from_scene(cam), oracle_kernel_fp32("half_cos"), oracle_opts_fp32()
-    _, img_o = oracle.render(ocam, ko, oo, sp)
+    _, img_o = oracle.render(ocam, ko, oo, sp, fp32_records=True)
     ok = img_o["margin"] >= 1e-4
     assert ok.mean() > 0.99
     Go = ambiguous_zeroed(scenes.upstream_grad(13, W, H).reshape(3, -1).T, img_o["margin"], 1e-4)

@@ -202,3 +202,55 @@ def test_degree0_colour_and_culling(orc):
     p2 = orc.preprocess(cam, orc.KernelSpec(oracle.GAUSS, 2.0, 1.0, 9.0), means, sp["scales"], sp["quats"],
                         sp["sh"], 0)
     assert p2["visible"][0] == 0 and p2["radius"][0] == 0
+
+
+def test_conic_factor_is_the_upper_cholesky_factor_of_the_conic():
+    """L from the 2D covariance satisfies L^T L = Sigma'^-1 and equals the
+    transpose of numpy's (lower) Cholesky factor of Q, for well- and
+    ill-conditioned covariances (needle-like footprints included)."""
+    rng = np.random.default_rng(31)
+    covs = []
+    for kappa in (1.0, 10.0, 1e3, 1e6):
+        for _ in range(20):
+            th = rng.uniform(0, np.pi)
+            R = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+            lam = rng.uniform(0.3, 50.0)
+            C = R @ np.diag([lam, lam / kappa]) @ R.T
+            covs.append([C[0, 0], C[0, 1], C[1, 1]])
+    covs = np.array(covs)
+    L = oracle.conic_factor(covs)
+    for c, l in zip(covs, L):
+        S = np.array([[c[0], c[1]], [c[1], c[2]]])
+        Q = np.linalg.inv(S)
+        Lm = np.array([[l[0], l[1]], [0.0, l[2]]])
+        assert np.allclose(Lm.T @ Lm, Q, rtol=1e-9, atol=1e-12 * np.abs(Q).max())
+        Cl = np.linalg.cholesky(Q)
+        assert np.allclose(Lm, Cl.T, rtol=1e-8, atol=1e-10 * np.abs(Cl).max())
+        assert l[0] > 0 and l[2] > 0
+
+
+def test_records_fp32_round_each_stored_field():
+    """The records as stored: mean2D, depth, colour and the conic factor rounded
+    to FP32 (the conic rebuilt from the rounded factor); culled splats zero."""
+    cam = oracle.make_camera(np.eye(4), (0.0, 0.0, 0.0), 64.0, 64.0, 32.0, 32.0, 64, 64)
+    k = oracle.KernelSpec(oracle.HALF_COS, 18.0 / np.pi, 1.36, 9.0)
+    rng = np.random.default_rng(5)
+    n = 40
+    means = np.concatenate([rng.uniform(-1, 1, (2, n)), rng.uniform(2, 4, (1, n))])
+    means[2, :3] = -1.0  # behind the camera: culled
+    scales = np.exp(rng.uniform(np.log(0.02), np.log(0.2), (3, n)))
+    quats = rng.normal(size=(4, n))
+    sh = rng.normal(scale=0.3, size=(1, 3, n))
+    p = oracle.preprocess(cam, k, means, scales, quats, sh, 0)
+    r = oracle.records_fp32(p)
+    vis = p["visible"] != 0
+    assert vis.sum() > 20 and not vis[:3].any()
+    for f in ("xy", "depth", "rgb"):
+        assert np.array_equal(r[f], p[f].astype(np.float32).astype(np.float64))
+    L = r["conic_l"]
+    assert np.array_equal(L[vis], oracle.conic_factor(p["cov2d"][vis]).astype(np.float32).astype(np.float64))
+    assert np.all(L[~vis] == 0) and np.all(r["conic"][~vis] == 0)
+    rebuilt = np.stack([L[:, 0] ** 2, L[:, 0] * L[:, 1], L[:, 1] ** 2 + L[:, 2] ** 2], 1)
+    assert np.array_equal(r["conic"], rebuilt)
+    # the rounded conic stays within FP32 rounding of the FP64 conic
+    assert np.allclose(r["conic"][vis], p["conic"][vis], rtol=1e-6)
