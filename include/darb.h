@@ -40,7 +40,7 @@ extern "C" {
 #define DARB_API
 #endif
 
-#define DARB_ABI_VERSION 5
+#define DARB_ABI_VERSION 6
 #define DARB_TILE 16
 #define DARB_MAX_VIEWS 16       /* views per multi-view call */
 #define DARB_LOSS_WS_BYTES 4096 /* workspace of darb_image_loss */
@@ -290,6 +290,30 @@ DARB_API size_t darb_bin_sort_workspace(int64_t n, int32_t width, int32_t height
 DARB_API darb_status darb_bin_sort(const darb_projected *proj, int64_t n, int32_t width, int32_t height, int64_t k_capacity,
                           void *ws, size_t ws_bytes, uint64_t *keys, uint32_t *vals, uint32_t *ranges, int64_t *k_dev,
                           int32_t *overflow_dev, int64_t *k_host, void *stream);
+
+/*
+ * darb_bin_sort_noalloc -- darb_bin_sort for callers that cannot allocate
+ * device memory or own a workspace: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation.  Same arguments, results
+ * and errors as darb_bin_sort, without ws/ws_bytes: the call runs the same
+ * kernels on the library's own scratch, a device array of
+ * DARB_NOALLOC_SCRATCH_BYTES bytes in the library's code object (one copy on
+ * every GPU the library runs on, held until the process ends).  It calls no
+ * allocating routine.
+ *   Limit: darb_bin_sort_workspace(n, width, height, k_capacity) must not
+ *   exceed DARB_NOALLOC_SCRATCH_BYTES; larger sizes return DARB_ERR_UNSUPPORTED
+ *   with the sizes in darb_status_string's message.
+ *   Sharing: every call on one GPU uses that GPU's one scratch array.  Calls
+ *   that overlap on one GPU (several streams, several host threads) race and
+ *   give wrong results; order them on one stream or with events.  The scratch
+ *   keeps the last call's contents; every call initialises what it reads.
+ *   The first call on each device looks up the array's device address
+ *   (hipGetSymbolAddress); make it outside graph capture.
+ */
+#define DARB_NOALLOC_SCRATCH_BYTES (256ull << 20)
+DARB_API darb_status darb_bin_sort_noalloc(const darb_projected *proj, int64_t n, int32_t width, int32_t height,
+                                           int64_t k_capacity, uint64_t *keys, uint32_t *vals, uint32_t *ranges,
+                                           int64_t *k_dev, int32_t *overflow_dev, int64_t *k_host, void *stream);
 
 /*
  * darb_fit1d -- the 1D signal-reconstruction experiment (Assessing DARBFs

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "common.h"
 
@@ -377,30 +378,17 @@ size_t darb_bin_sort_workspace(int64_t n, int32_t width, int32_t height, int64_t
     return darb::binsort_workspace((int)n, width, height, k_capacity);
 }
 
-darb_status darb_bin_sort(const darb_projected *proj, int64_t n, int32_t width, int32_t height, int64_t k_capacity,
-                          void *ws, size_t ws_bytes, uint64_t *keys, uint32_t *vals, uint32_t *ranges, int64_t *k_dev,
-                          int32_t *overflow_dev, int64_t *k_host, void *stream) {
-    TRY(check_n(n));
-    TRY(check_size(width, height));
-    TRY(check_projected(proj, n, false));
-    if (k_capacity < 0) return fail(DARB_ERR_INVALID_ARG, "%s", "k_capacity must be >= 0");
-    if (k_capacity >= 0xFFFFFFFFll) return fail(DARB_ERR_UNSUPPORTED, "%s", "k_capacity must be < 2^32 - 1");
-    REQUIRE_PTR(ws);
-    REQUIRE_PTR(ranges);
-    REQUIRE_PTR(k_dev);
-    REQUIRE_PTR(overflow_dev);
-    OPT_PTR(keys);
-    if (k_capacity > 0) REQUIRE_PTR(vals);
-    size_t need = darb::binsort_workspace((int)n, width, height, k_capacity);
-    if (ws_bytes < need) {
-        snprintf(g_err, sizeof(g_err), "workspace too small: %zu < %zu bytes", ws_bytes, need);
-        return DARB_ERR_INVALID_ARG;
-    }
+namespace {
+
+// The call behind darb_bin_sort and darb_bin_sort_noalloc: argument checks,
+// the launches on `ws`, the optional blocking readback of K.
+darb_status bin_sort_impl(const char *who, const darb_projected *proj, int64_t n, int32_t width, int32_t height,
+                          int64_t k_capacity, void *ws, size_t ws_bytes, uint64_t *keys, uint32_t *vals,
+                          uint32_t *ranges, int64_t *k_dev, int32_t *overflow_dev, int64_t *k_host, hipStream_t s) {
     g_err[0] = 0;
-    hipStream_t s = (hipStream_t)stream;
     TRY(hip_status(darb::launch_bin_sort(*proj, (int)n, width, height, k_capacity, ws, keys, vals, ranges, k_dev,
                                          overflow_dev, s),
-                   "darb_bin_sort"));
+                   who));
     if (k_host) {
         TRY(hip_status(hipMemcpyAsync(k_host, k_dev, sizeof(int64_t), hipMemcpyDeviceToHost, s), "darb_bin_sort readback"));
         TRY(hip_status(hipStreamSynchronize(s), "darb_bin_sort sync"));
@@ -410,7 +398,85 @@ darb_status darb_bin_sort(const darb_projected *proj, int64_t n, int32_t width, 
             return DARB_ERR_CAPACITY;
         }
     }
+    (void)ws_bytes;
     return DARB_OK;
+}
+
+darb_status check_bin_sort_args(const darb_projected *proj, int64_t n, int32_t width, int32_t height,
+                                int64_t k_capacity, uint32_t *vals, uint32_t *ranges, int64_t *k_dev,
+                                int32_t *overflow_dev, uint64_t *keys) {
+    TRY(check_n(n));
+    TRY(check_size(width, height));
+    TRY(check_projected(proj, n, false));
+    if (k_capacity < 0) return fail(DARB_ERR_INVALID_ARG, "%s", "k_capacity must be >= 0");
+    if (k_capacity >= 0xFFFFFFFFll) return fail(DARB_ERR_UNSUPPORTED, "%s", "k_capacity must be < 2^32 - 1");
+    REQUIRE_PTR(ranges);
+    REQUIRE_PTR(k_dev);
+    REQUIRE_PTR(overflow_dev);
+    OPT_PTR(keys);
+    if (k_capacity > 0) REQUIRE_PTR(vals);
+    return DARB_OK;
+}
+
+// Scratch of darb_bin_sort_noalloc: a file-scope device array, one copy per
+// GPU, allocated with the library's code object.  In host code `scratch` is a
+// host-side stand-in for the symbol, not a device address: the device address
+// of each GPU's copy comes from hipGetSymbolAddress, taken once per device with
+// that device current, and only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[DARB_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+darb_status scratch_address(void **out) {
+    int dev = -1;
+    TRY(hip_status(hipGetDevice(&dev), "darb_bin_sort_noalloc: hipGetDevice"));
+    if (dev < 0 || dev >= kMaxDevices) return fail(DARB_ERR_UNSUPPORTED, "%s", "device ordinal beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        TRY(hip_status(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "darb_bin_sort_noalloc: hipGetSymbolAddress"));
+        if (!p) return fail(DARB_ERR_HIP, "%s", "darb_bin_sort_noalloc: null scratch address");
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return DARB_OK;
+}
+
+}  // namespace
+
+darb_status darb_bin_sort(const darb_projected *proj, int64_t n, int32_t width, int32_t height, int64_t k_capacity,
+                          void *ws, size_t ws_bytes, uint64_t *keys, uint32_t *vals, uint32_t *ranges, int64_t *k_dev,
+                          int32_t *overflow_dev, int64_t *k_host, void *stream) {
+    TRY(check_bin_sort_args(proj, n, width, height, k_capacity, vals, ranges, k_dev, overflow_dev, keys));
+    REQUIRE_PTR(ws);
+    size_t need = darb::binsort_workspace((int)n, width, height, k_capacity);
+    if (ws_bytes < need) {
+        snprintf(g_err, sizeof(g_err), "workspace too small: %zu < %zu bytes", ws_bytes, need);
+        return DARB_ERR_INVALID_ARG;
+    }
+    return bin_sort_impl("darb_bin_sort", proj, n, width, height, k_capacity, ws, ws_bytes, keys, vals, ranges, k_dev,
+                         overflow_dev, k_host, (hipStream_t)stream);
+}
+
+darb_status darb_bin_sort_noalloc(const darb_projected *proj, int64_t n, int32_t width, int32_t height,
+                                  int64_t k_capacity, uint64_t *keys, uint32_t *vals, uint32_t *ranges, int64_t *k_dev,
+                                  int32_t *overflow_dev, int64_t *k_host, void *stream) {
+    TRY(check_bin_sort_args(proj, n, width, height, k_capacity, vals, ranges, k_dev, overflow_dev, keys));
+    const size_t need = darb::binsort_workspace((int)n, width, height, k_capacity);
+    if (need > (size_t)DARB_NOALLOC_SCRATCH_BYTES) {
+        snprintf(g_err, sizeof(g_err),
+                 "darb_bin_sort_noalloc: n = %lld and k_capacity = %lld need %zu bytes of scratch, more than the "
+                 "library's %llu (use darb_bin_sort with a workspace)",
+                 (long long)n, (long long)k_capacity, need, (unsigned long long)DARB_NOALLOC_SCRATCH_BYTES);
+        return DARB_ERR_UNSUPPORTED;
+    }
+    void *ws = nullptr;
+    TRY(scratch_address(&ws));
+    return bin_sort_impl("darb_bin_sort_noalloc", proj, n, width, height, k_capacity, ws,
+                         (size_t)DARB_NOALLOC_SCRATCH_BYTES, keys, vals, ranges, k_dev, overflow_dev, k_host,
+                         (hipStream_t)stream);
 }
 
 darb_status darb_raster_fwd(const darb_projected *proj, int64_t n, const uint32_t *vals, const uint32_t *ranges,

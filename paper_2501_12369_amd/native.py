@@ -23,9 +23,10 @@ GAUSS_BETA, HALF_COS_BETA, RAISED_COS_BETA, SINC_BETA = range(7, 11)  # Table 1'
 LOSS_L1, LOSS_L2 = 0, 1
 MAX_VIEWS = 16
 LOSS_WS_BYTES = 4096
+NOALLOC_SCRATCH_BYTES = 256 << 20  # DARB_NOALLOC_SCRATCH_BYTES: scratch of darb_bin_sort_noalloc
 
 EXPORTED = ("darb_version", "darb_status_string", "darb_last_error", "darb_preprocess", "darb_preprocess_parts", "darb_preprocess_cam_dev",
-            "darb_bin_sort_workspace", "darb_bin_sort", "darb_fit1d", "darb_psi_calibrate_workspace",
+            "darb_bin_sort_workspace", "darb_bin_sort", "darb_bin_sort_noalloc", "darb_fit1d", "darb_psi_calibrate_workspace",
             "darb_psi_calibrate", "darb_raster_fwd", "darb_raster_bwd",
             "darb_raster_bwd_workspace", "darb_preprocess_bwd", "darb_image_loss", "darb_preprocess_multi",
             "darb_raster_fwd_multi", "darb_preprocess_multi_cam_dev", "darb_raster_bwd_multi", "darb_raster_bwd_multi_workspace",
@@ -119,6 +120,9 @@ def lib():
         L.darb_bin_sort.restype = c_int32
         L.darb_bin_sort.argtypes = [P(darb_projected), c_int64, c_int32, c_int32, c_int64, c_void_p, c_size_t,
                                     c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, P(c_int64), c_void_p]
+        L.darb_bin_sort_noalloc.restype = c_int32
+        L.darb_bin_sort_noalloc.argtypes = [P(darb_projected), c_int64, c_int32, c_int32, c_int64, c_void_p, c_void_p,
+                                            c_void_p, c_void_p, c_void_p, P(c_int64), c_void_p]
         L.darb_fit1d.restype = c_int32
         L.darb_fit1d.argtypes = [P(darb_kernel), c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                                  c_void_p, c_int32, c_int32, P(c_float), c_float, c_float, c_float, c_void_p, c_void_p]
@@ -318,6 +322,21 @@ def darb_bin_sort(proj: dict, n: int, width: int, height: int, k_capacity: int, 
     if read_k and st == DARB_ERR_CAPACITY:
         return int(kh.value)
     _check(st, "darb_bin_sort")
+    return int(kh.value) if read_k else None
+
+
+def darb_bin_sort_noalloc(proj: dict, n: int, width: int, height: int, k_capacity: int, keys, vals, ranges, k_dev,
+                          overflow_dev, read_k: bool = False, stream=None):
+    """darb_bin_sort on the library's own scratch (no workspace argument).
+    Returns K when ``read_k`` (blocking readback), else None."""
+    p = projected_struct(proj)
+    kh = c_int64(0)
+    st = lib().darb_bin_sort_noalloc(ctypes.byref(p), n, width, height, k_capacity, _ptr(keys), _ptr(vals),
+                                     _ptr(ranges), _ptr(k_dev), _ptr(overflow_dev),
+                                     ctypes.byref(kh) if read_k else None, _stream(stream))
+    if read_k and st == DARB_ERR_CAPACITY:
+        return int(kh.value)
+    _check(st, "darb_bin_sort_noalloc")
     return int(kh.value) if read_k else None
 
 

@@ -44,7 +44,7 @@ def test_library_exports_every_declared_symbol(L):
 def test_version_and_status_strings(L):
     from paper_2501_12369_amd import native
 
-    assert native.darb_version() == 5
+    assert native.darb_version() == 6
     assert L.darb_status_string(0) == b"ok"
     assert L.darb_status_string(2) == b"instance capacity exceeded"
 
@@ -149,3 +149,29 @@ def test_deterministic_workspace_queries(L):
     assert L.darb_raster_bwd_multi_workspace(arr, 2, 0x7FFFFFFF) > 0
     assert L.darb_raster_bwd_multi_workspace(arr, 3, 0x7FFFFFFF) == 0
 
+
+
+def test_noalloc_bin_sort_rejects_on_host(L):
+    """darb_bin_sort_noalloc checks its arguments and its scratch limit on the
+    host before any HIP call (fake aligned addresses: nothing is launched)."""
+    from paper_2501_12369_amd import native
+
+    pr = native.darb_projected()
+    # null record pointers with n > 0
+    st = L.darb_bin_sort_noalloc(ctypes.byref(pr), 10, 64, 64, 100, None, 4096, 8192, 12288, 16384, None, None)
+    assert st == native.DARB_ERR_INVALID_ARG and b"null pointer" in L.darb_last_error()
+    pr.xy, pr.depth, pr.radius = 16 * 1000, 16 * 2000, 16 * 3000
+    # null ranges
+    st = L.darb_bin_sort_noalloc(ctypes.byref(pr), 10, 64, 64, 100, None, 4096, None, 12288, 16384, None, None)
+    assert st == native.DARB_ERR_INVALID_ARG
+    # sizes whose workspace exceeds the scratch: rejected with the sizes in the message
+    cap = native.NOALLOC_SCRATCH_BYTES // 4
+    assert L.darb_bin_sort_workspace(10, 64, 64, cap) > native.NOALLOC_SCRATCH_BYTES
+    st = L.darb_bin_sort_noalloc(ctypes.byref(pr), 10, 64, 64, cap, None, 4096, 8192, 12288, 16384, None, None)
+    assert st == native.DARB_ERR_UNSUPPORTED and b"scratch" in L.darb_last_error()
+    n = 8_000_000
+    assert L.darb_bin_sort_workspace(n, 1297, 840, 1000) > native.NOALLOC_SCRATCH_BYTES
+    st = L.darb_bin_sort_noalloc(ctypes.byref(pr), n, 1297, 840, 1000, None, 4096, 8192, 12288, 16384, None, None)
+    assert st == native.DARB_ERR_UNSUPPORTED and b"scratch" in L.darb_last_error()
+    # the scratch holds the serving scenes' smaller sizes
+    assert 0 < L.darb_bin_sort_workspace(1_000_000, 1280, 720, 20_000_000) <= native.NOALLOC_SCRATCH_BYTES
