@@ -25,8 +25,10 @@ be exercised without a GPU.
 """
 from __future__ import annotations
 
+import gc
 import math
 import time
+import weakref
 from collections import OrderedDict, deque
 from dataclasses import dataclass, field
 
@@ -273,7 +275,10 @@ class RenderSlot:
         from . import native, pipeline
 
         self.torch, self.native, self.pipeline = torch, native, pipeline
-        self.server = server
+        # the server owns its slots: a weak reference keeps the pair out of a
+        # reference cycle, so a dropped server frees its graphs, streams and
+        # buffers at once instead of whenever the cyclic collector runs
+        self.server = weakref.proxy(server)
         self.key = key
         scene_id, W, H = key
         self.splats = server.scenes[scene_id]
@@ -328,8 +333,17 @@ class RenderSlot:
                 self._enqueue(b)  # warm-up outside the graph
             self.stream.synchronize()
             g = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(g, stream=self.stream):
-                self._enqueue(b)
+            # no cyclic collection inside the capture: a finalizer that destroys a
+            # graph, event or stream, or frees device memory, is rejected while a
+            # stream captures (torch.cuda.graph collects once before it begins)
+            enabled = gc.isenabled()
+            gc.disable()
+            try:
+                with torch.cuda.graph(g, stream=self.stream):
+                    self._enqueue(b)
+            finally:
+                if enabled:
+                    gc.enable()
             graphs[b] = g
         self.graphs = graphs
 
@@ -401,7 +415,9 @@ class RenderServer:
         self.k_margin = k_margin
         self.n_probe = n_probe
         self.cap_hint = {}
-        self.sched = Scheduler(self._make_slot, self._need, mem_budget, max_slots, max_inflight=max_inflight)
+        me = weakref.ref(self)  # the scheduler calls back without holding the server (no reference cycle)
+        self.sched = Scheduler(lambda key, hint: me()._make_slot(key, hint), lambda key: me()._need(key), mem_budget,
+                               max_slots, max_inflight=max_inflight)
 
     @staticmethod
     def slot_bytes(n: int, W: int, H: int, capacity: int) -> int:
