@@ -22,10 +22,11 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Per-unit algorithmic work of the survey's measurement plan: VALU lane-operations
-# per (pixel, splat) pair -- E (5 FMA), the support and alpha tests, one
-# transcendental, the 3 colour FMAs and the T update in the forward; the
-# backward adds the T recovery division, the 9 partial sums and the reduction.
+# The survey's estimate of VALU lane-operations per (pixel, splat) pair -- E (5
+# FMA), the support and alpha tests, one transcendental, the 3 colour FMAs and
+# the T update in the forward; the backward adds the T recovery division, the 9
+# partial sums and the reduction.  Used only when no committed counter summary
+# (VALU instructions per launch) matches the raster sources.
 LANE_OPS_PER_PAIR_FWD = 25
 LANE_OPS_PER_PAIR_BWD = 60
 PEAK_HBM_GBS = 8000.0            # MI355X HBM3E
@@ -127,6 +128,7 @@ def stage_bytes(n, n_vis, split=False):
 
 # kernel of each single-kernel stage, and the sources it is built from
 STAGE_KERNEL = {"preprocess": ("k_preprocess<3>", ("preprocess.hip", "common.h")),
+                "colour": ("k_preprocess_colour<3>", ("preprocess.hip", "common.h")),
                 "preprocess_bwd": ("k_preprocess_bwd<3, true>", ("preprocess.hip", "common.h"))}
 
 
@@ -138,6 +140,26 @@ def sources_digest(files) -> str:
         with open(os.path.join(ROOT, "paper_2501_12369_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+# raster kernels' VALU work: the committed counter summary (profiles/valu.json)
+# holds SQ_INSTS_VALU per dispatch of the scene step's full-size call
+RASTER_KERNEL = {"raster_fwd": ("k_raster_fwd<1, OneView, false>", ("raster.hip", "common.h")),
+                 "raster_bwd": ("k_raster_bwd_split<1, OneView>", ("raster.hip", "common.h"))}
+
+
+def measured_valu_insts(stage: str):
+    """Wave-level VALU instructions of the stage's kernel per launch, from the
+    committed rocprofv3 counter summary, or None when its sources changed since."""
+    path = os.path.join(ROOT, "profiles", "valu.json")
+    if not os.path.exists(path):
+        return None
+    name, files = RASTER_KERNEL[stage]
+    with open(path) as fh:
+        rec = json.load(fh).get(name)
+    if not rec or rec.get("sources_sha256") != sources_digest(files):
+        return None
+    return int(rec["valu_insts"])
 
 
 def measured_traffic(stage: str):
@@ -505,6 +527,8 @@ def main():
                 evc[1].record(side)
         native.darb_bin_sort(frame.proj, n, W, H, frame.capacity, frame.ws, None, frame.vals, frame.ranges,
                              frame.k_dev, frame.overflow)
+        if evc is not None:
+            evc[2].record()  # the binning's own end, before the join
         if overlap:
             main.wait_stream(side)
         if ev is not None:
@@ -525,7 +549,7 @@ def main():
         step()
     torch.cuda.synchronize()
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
-    evcs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+    evcs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for i in range(args.steps):
@@ -538,6 +562,10 @@ def main():
     mpix = P * args.steps / wall / 1e6
     log("per-stage ms: " + ", ".join(f"{k}={v:.3f}" for k, v in per_stage.items()) + f"; step {ms_per_step:.3f} ms")
     colour_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evcs])) if overlap else None
+    # the binning's own kernels (main stream, from the end of the geometry part to
+    # the last binning kernel, before the join with the colour part)
+    bin_own_ms = float(np.mean([e[1].elapsed_time(c[2]) for e, c in zip(evs, evcs)]))
+    log(f"bin/sort kernels on the main stream: {bin_own_ms:.3f} ms (stage to the join {per_stage['bin_sort']:.3f})")
     if overlap:
         log(f"colour part on the side stream (beside bin_sort): {colour_ms:.3f} ms, "
             f"{stage_bytes(n, n_vis, True)['colour'] / (colour_ms * 1e-3) / 1e9:.1f} GB/s")
@@ -569,9 +597,17 @@ def main():
         return r
 
     def valu(stage, t_ms, kernel, ops_per_pair):
-        ops = pairs * ops_per_pair
+        # counted VALU lane-operations (VALU instructions x 64 lanes) when the
+        # committed counter summary matches the sources, else the survey's
+        # per-pair estimate
+        insts = measured_valu_insts(stage)
+        if insts is not None:
+            ops, rule = insts * 64, "counted: SQ_INSTS_VALU x 64 (profiles/valu.json)"
+        else:
+            ops, rule = pairs * ops_per_pair, f"estimated: {ops_per_pair} lane-ops per pair"
         rate = ops / (t_ms * 1e-3)
-        return dict(bound="alu", kernel=kernel, us=round(t_ms * 1e3, 2), pairs=pairs, lane_ops_per_pair=ops_per_pair,
+        return dict(bound="alu", kernel=kernel, us=round(t_ms * 1e3, 2), pairs=pairs, lane_ops=int(ops),
+                    lane_ops_rule=rule, lane_ops_per_pair=round(ops / max(pairs, 1), 2),
                     achieved=round(2 * rate / 1e12, 2), unit="TFLOP/s (FMA-equivalent: 2 x lane-ops)",
                     peak=PEAK_FP32_NONPACKED_TFLOPS, frac=round(rate / PEAK_LANE_OPS, 4),
                     frac_of_packed=round(2 * rate / 1e12 / PEAK_FP32_TFLOPS, 4),
@@ -580,23 +616,26 @@ def main():
     pre_kernel = "k_preprocess_geom" if overlap else "k_preprocess<3>"
     stage_roofs = {
         "preprocess": hbm("preprocess", per_stage["preprocess"], pre_kernel, own["preprocess"]),
-        "bin_sort": hbm("bin_sort", per_stage["bin_sort"], "20 launches (keys .. level-2 scatter)"),
+        "bin_sort": hbm("bin_sort", per_stage["bin_sort"], "20 launches (keys .. level-2 scatter), to the join"),
+        "bin_sort_own": hbm("bin_sort", bin_own_ms, "20 launches (keys .. level-2 scatter), own time"),
         "raster_fwd": valu("raster_fwd", per_stage["raster_fwd"], "k_raster_fwd<1, OneView, false>",
                            LANE_OPS_PER_PAIR_FWD),
-        "raster_bwd": valu("raster_bwd", per_stage["raster_bwd"], "k_raster_bwd<1, false, OneView>",
+        "raster_bwd": valu("raster_bwd", per_stage["raster_bwd"], "k_raster_bwd_split<1, OneView>",
                            LANE_OPS_PER_PAIR_BWD),
         "preprocess_bwd": hbm("preprocess_bwd", per_stage["preprocess_bwd"], "k_preprocess_bwd<3, true>",
                               own["preprocess_bwd"]),
     }
     if overlap:
         stage_roofs["colour_side_stream"] = hbm("colour", colour_ms, "k_preprocess_colour<3>", own["colour"])
-    # the dominant kernel: the longest single kernel on the step's critical path
-    # (the bin/sort stage is ~20 launches, none longer than the stages below;
-    # the colour part runs on the side stream, hidden behind bin/sort)
-    single = ("preprocess", "raster_fwd", "raster_bwd", "preprocess_bwd")
-    dominant = max(single, key=lambda st: per_stage[st])
+    # the dominant kernel: the longest single kernel of the step, the colour part
+    # on the side stream included (the bin/sort stage is ~20 launches, none of
+    # them longer than these)
+    single = ["preprocess", "raster_fwd", "raster_bwd", "preprocess_bwd"] + (["colour_side_stream"] if overlap else [])
+    dominant = max(single, key=lambda st: stage_roofs[st]["us"])
     r = dict(stage_roofs[dominant])
     traffic = measured_traffic(dominant) if dominant in STAGE_KERNEL else None
+    if dominant == "colour_side_stream":
+        traffic = measured_traffic("colour")
     if r["bound"] == "hbm":
         roofline = dict(bound="hbm", achieved=r["achieved"], peak=PEAK_HBM_GBS, unit="GB/s", frac=r["frac"],
                         traffic=traffic, kernel=r["kernel"], kernel_us=r["us"],
@@ -663,7 +702,8 @@ def main():
                    "n_splats": n, "width": W, "height": H, "kernel": args.kernel, "visible": n_vis, "instances": K,
                    "splats_per_s": round(n * args.steps / wall, 1),
                    "stage_ms": {k: round(v, 4) for k, v in per_stage.items()},
-                   "colour_side_stream_ms": round(colour_ms, 4) if overlap else None, "variants": variants},
+                   "colour_side_stream_ms": round(colour_ms, 4) if overlap else None,
+                   "bin_sort_own_ms": round(bin_own_ms, 4), "variants": variants},
         "roofline": roofline,
         "measured_ceilings": ceilings,
         "stage_rooflines": stage_roofs,

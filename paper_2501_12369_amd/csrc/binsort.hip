@@ -501,6 +501,7 @@ __global__ __launch_bounds__(1024) void k_bin_sizes(uint32_t *block_vis, const u
 // reads after the sort instead of gathering the projected splat again.  Same
 // blocking as k_bin_keys; a splat's slot is the block's offset plus the
 // visible splats before it in (round, wave, lane) = index order.
+
 __global__ __launch_bounds__(256) void k_bin_compact(const float *xy, const int32_t *radius, const float *depth, int n,
                                                      int gx, int gy, const uint32_t *block_off, uint32_t *keys,
                                                      uint32_t *vals, uint4 *crec, const int32_t *overflow_dev) {
@@ -864,10 +865,24 @@ __device__ __forceinline__ int l2_tile_clamped(int g, int tl, int sxn, int gx, i
     return min(ty, gy - 1) * gx + min(tx, gx - 1);
 }
 
-// A workgroup takes its chunks kL2Batch at a time and issues every global load
-// of a batch (list entries, count offsets) before working on the first chunk,
-// so a batch costs a memory round trip or two instead of several per chunk.
-constexpr int kL2Batch = 8;
+// Each workgroup walks its chunks one at a time and issues the next chunk's
+// global loads (list entries, count offsets) before it works on the current
+// one; they are waited for just before the current chunk's stores, so a
+// chunk's round trips overlap the previous chunk's work and no load waits
+// behind a store (vmcnt counts both).  One chunk in flight keeps the register
+// count (and the number of resident workgroups) of the plain loop.
+struct L2Next {
+    L2Chunk C;
+    uint32_t packed, hoff;
+    bool tin;
+};
+
+__device__ __forceinline__ void l2_fetch_count(L2Next &x, uint32_t wi, const L2Tables &T, int nsuper,
+                                               const uint32_t *list1r, const uint32_t *toff, int sxn, int gx, int gy) {
+    x.C = l2_locate(wi, T.c2s, nsuper, T.l1s, T.l1l);
+    x.packed = list1r[x.C.first + min((uint32_t)threadIdx.x, x.C.len - 1)];
+    x.hoff = toff[l2_tile_clamped(x.C.g, threadIdx.x & 63, sxn, gx, gy, x.tin)];
+}
 
 __global__ __launch_bounds__(kL2Threads) void k_l2_count(const uint32_t *list1r, const uint32_t *l1_start,
                                                          const uint32_t *l1_len, const uint32_t *chunk2_start,
@@ -880,38 +895,31 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_count(const uint32_t *list1r,
     if (*overflow_dev) return;
     const uint32_t total2 = cnt->total2;
     const int w = threadIdx.x >> 6, tl = threadIdx.x & 63;
+    const uint32_t G = gridDim.x;
+    if (blockIdx.x >= total2) return;
     l2_load_tables(T, chunk2_start, l1_start, l1_len, nsuper);
     __syncthreads();
-    const uint32_t G = gridDim.x;
-    for (uint32_t wi0 = blockIdx.x; wi0 < total2; wi0 += kL2Batch * G) {
-        L2Chunk C[kL2Batch];
-        uint32_t packed[kL2Batch], hoff[kL2Batch];
-        bool tin[kL2Batch];
-#pragma unroll
-        for (int b = 0; b < kL2Batch; b++) {
-            // chunks past the last are looked up as the last one (loaded, not used)
-            C[b] = l2_locate(min(wi0 + b * G, total2 - 1), T.c2s, nsuper, T.l1s, T.l1l);
-            packed[b] = list1r[C[b].first + min((uint32_t)threadIdx.x, C[b].len - 1)];
-            hoff[b] = toff[l2_tile_clamped(C[b].g, tl, sxn, gx, gy, tin[b])];
-        }
-#pragma unroll
-        for (int b = 0; b < kL2Batch; b++) pin_u32(packed[b], hoff[b]);
-#pragma unroll
-        for (int b = 0; b < kL2Batch; b++) {
-            if (wi0 + b * G >= total2) break;  // uniform over the workgroup
-            const bool valid = threadIdx.x < C[b].len;
-            uint64_t colB[kSuper], rowB[kSuper];
-            l2_colrow(l2_local_rect(valid, packed[b]), colB, rowB, masks[w]);
-            __syncthreads();
-            l2_counts(masks[w], wc);
-            __syncthreads();
-            if (threadIdx.x < kSuper * kSuper && tin[b]) {
-                uint32_t sum = 0;
-                for (int k = 0; k < kL2Waves; k++) sum += wc[k * 64 + tl];
-                h2[hoff[b] + C[b].c2] = sum;
-            }
-            __syncthreads();
-        }
+    L2Next cur, nxt;
+    l2_fetch_count(cur, blockIdx.x, T, nsuper, list1r, toff, sxn, gx, gy);
+    for (uint32_t wi = blockIdx.x; wi < total2; wi += G) {
+        const bool more = wi + G < total2;  // uniform over the workgroup
+        if (more) l2_fetch_count(nxt, wi + G, T, nsuper, list1r, toff, sxn, gx, gy);
+        const bool valid = threadIdx.x < cur.C.len;
+        uint64_t colB[kSuper], rowB[kSuper];
+        l2_colrow(l2_local_rect(valid, cur.packed), colB, rowB, masks[w]);
+        __syncthreads();
+        l2_counts(masks[w], wc);
+        __syncthreads();
+        uint32_t sum = 0;
+        if (threadIdx.x < kSuper * kSuper && cur.tin)
+            for (int k = 0; k < kL2Waves; k++) sum += wc[k * 64 + tl];
+        // the next chunk's loads land before this store (pinned on every path: a pin
+        // under the same condition as the loads leaves the wait analysis a path with a
+        // load in flight, and every later store would wait for it)
+        pin_u32(nxt.packed, nxt.hoff);
+        if (threadIdx.x < kSuper * kSuper && cur.tin) h2[cur.hoff + cur.C.c2] = sum;
+        __syncthreads();
+        cur = nxt;
     }
 }
 
@@ -957,6 +965,26 @@ __device__ __forceinline__ void store_ranked(uint32_t *base, uint64_t m, uint32_
         : "memory");
 }
 
+// The next chunk of the level-2 scatter: entries (splat index, local
+// rectangle) and this thread's (wave, tile) slot base.  The slot base is two
+// dependent loads (the tile's count offset, then the scanned count): the
+// offset is fetched with the entries, the base one step later.
+struct L2NextS {
+    L2Chunk C;
+    uint32_t id, packed, sbase;
+    bool tin;
+};
+
+__device__ __forceinline__ void l2_fetch_scatter(L2NextS &x, uint32_t wi, const L2Tables &T, int nsuper,
+                                                 const uint32_t *list1, const uint32_t *list1r, const uint32_t *toff,
+                                                 int sxn, int gx, int gy) {
+    x.C = l2_locate(wi, T.c2s, nsuper, T.l1s, T.l1l);
+    const uint32_t e = x.C.first + min((uint32_t)threadIdx.x, x.C.len - 1);
+    x.id = list1[e];
+    x.packed = list1r[e];
+    x.sbase = toff[l2_tile_clamped(x.C.g, threadIdx.x & 63, sxn, gx, gy, x.tin)];
+}
+
 // FAST: values only, capacity below 2^30 (32-bit byte offsets); otherwise the
 // generic loop, which also writes the optional (tile, depth) keys.
 template <bool FAST>
@@ -976,84 +1004,76 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_scatter(const uint32_t *list1
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int t = blockIdx.x * kL2Threads + threadIdx.x; t < gx * gy; t += gridDim.x * kL2Threads)
         tile_range(base2, toff, t, cnt, ranges);
+    const uint32_t G = gridDim.x;
+    if (blockIdx.x >= total2) return;
     l2_load_tables(T, chunk2_start, l1_start, l1_len, nsuper);
     __syncthreads();
     const uint32_t cap32 = (uint32_t)min(k_capacity, (int64_t)0xFFFFFFFFll);
-    const uint32_t G = gridDim.x;
-    for (uint32_t wi0 = blockIdx.x; wi0 < total2; wi0 += kL2Batch * G) {
-        // every load of the batch: entries (splat index, local rectangle) and the
-        // count offset of this thread's (wave, tile) slot, then the slot bases
-        L2Chunk C[kL2Batch];
-        uint32_t id[kL2Batch], packed[kL2Batch], sbase[kL2Batch], db[kL2Batch];
-        bool tin[kL2Batch];
-#pragma unroll
-        for (int b = 0; b < kL2Batch; b++) {
-            C[b] = l2_locate(min(wi0 + b * G, total2 - 1), T.c2s, nsuper, T.l1s, T.l1l);
-            const uint32_t e = C[b].first + min((uint32_t)threadIdx.x, C[b].len - 1);
-            id[b] = list1[e];
-            packed[b] = list1r[e];
-            sbase[b] = toff[l2_tile_clamped(C[b].g, lane, sxn, gx, gy, tin[b])];
-        }
-#pragma unroll
-        for (int b = 0; b < kL2Batch; b++) {
-            sbase[b] = base2[sbase[b] + C[b].c2];
-            db[b] = (!FAST && keys) ? __float_as_uint(depth[id[b]]) : 0u;  // depth only for the optional keys
-        }
-#pragma unroll
-        for (int b = 0; b < kL2Batch; b++) pin_u32(id[b], packed[b], sbase[b], db[b]);
-#pragma unroll
-        for (int b = 0; b < kL2Batch; b++) {
-            if (wi0 + b * G >= total2) break;  // uniform over the workgroup
-            const bool valid = threadIdx.x < C[b].len;
-            uint64_t colB[kSuper], rowB[kSuper];
-            l2_colrow(l2_local_rect(valid, packed[b]), colB, rowB, masks[w]);
-            __syncthreads();
-            l2_counts(masks[w], wc);
-            __syncthreads();
-            const int tx0 = (C[b].g % sxn) * kSuper, ty0 = (C[b].g / sxn) * kSuper;
-            {
-                // thread (wave ww, tile tl): first slot of wave ww's entries in tile tl
-                static_assert(kSuper * kSuper * kL2Waves == kL2Threads, "one thread per (wave, tile)");
-                const int ww = threadIdx.x >> 6, tl = threadIdx.x & 63;
-                if (tin[b]) {
-                    uint32_t sl = sbase[b];
-                    for (int k = 0; k < ww; k++) sl += wc[k * 64 + tl];
-                    slot[threadIdx.x] = sl;
-                }
+    L2NextS cur, nxt;
+    l2_fetch_scatter(cur, blockIdx.x, T, nsuper, list1, list1r, toff, sxn, gx, gy);
+    cur.sbase = base2[cur.sbase + cur.C.c2];
+    uint32_t db = (!FAST && keys) ? __float_as_uint(depth[cur.id]) : 0u;  // depth only for the optional keys
+    for (uint32_t wi = blockIdx.x; wi < total2; wi += G) {
+        const bool more = wi + G < total2;  // uniform over the workgroup
+        if (more) l2_fetch_scatter(nxt, wi + G, T, nsuper, list1, list1r, toff, sxn, gx, gy);
+        const bool valid = threadIdx.x < cur.C.len;
+        uint64_t colB[kSuper], rowB[kSuper];
+        l2_colrow(l2_local_rect(valid, cur.packed), colB, rowB, masks[w]);
+        __syncthreads();
+        l2_counts(masks[w], wc);
+        __syncthreads();
+        const int tx0 = (cur.C.g % sxn) * kSuper, ty0 = (cur.C.g / sxn) * kSuper;
+        {
+            // thread (wave ww, tile tl): first slot of wave ww's entries in tile tl
+            static_assert(kSuper * kSuper * kL2Waves == kL2Threads, "one thread per (wave, tile)");
+            const int ww = threadIdx.x >> 6, tl = threadIdx.x & 63;
+            if (cur.tin) {
+                uint32_t sl = cur.sbase;
+                for (int k = 0; k < ww; k++) sl += wc[k * 64 + tl];
+                slot[threadIdx.x] = sl;
             }
-            __syncthreads();
-            // lane tl holds this wave's first slot in tile tl; broadcast per tile with v_readlane
-            const uint32_t myslot = slot[w * 64 + lane];
-            bool inside = true;
-            if constexpr (FAST) {
-                // every run of this wave lies inside the capacity (K <= capacity is decided
-                // before any instance is written; this test only guards the stores)
-                const uint32_t myc = wc[w * 64 + lane];
-                uint32_t e = myc ? myslot + myc : 0u;
+        }
+        // the next chunk's slot base (its count offset has landed by now) and depth
+        uint32_t dbn = 0;
+        if (more) {
+            nxt.sbase = base2[nxt.sbase + nxt.C.c2];
+            if (!FAST && keys) dbn = __float_as_uint(depth[nxt.id]);
+        }
+        __syncthreads();
+        // lane tl holds this wave's first slot in tile tl; broadcast per tile with v_readlane
+        const uint32_t myslot = slot[w * 64 + lane];
+        bool inside = true;
+        if constexpr (FAST) {
+            // every run of this wave lies inside the capacity (K <= capacity is decided
+            // before any instance is written; this test only guards the stores)
+            const uint32_t myc = wc[w * 64 + lane];
+            uint32_t e = myc ? myslot + myc : 0u;
 #pragma unroll
-                for (int off = 32; off >= 1; off >>= 1) e = max(e, (uint32_t)__shfl_xor((int)e, off, 64));
-                inside = e <= cap32;
-            }
-            for (int rr = 0; rr < kSuper; rr++) {
-                if (rowB[rr] == 0ull || !inside) continue;  // no lane of this wave covers the row (uniform)
-                for (int cc = 0; cc < kSuper; cc++) {
-                    const uint64_t m = colB[cc] & rowB[rr];
-                    if (m == 0ull) continue;
-                    const int tl = rr * kSuper + cc;
-                    const uint32_t s0 = (uint32_t)__builtin_amdgcn_readlane((int)myslot, tl);
-                    if constexpr (FAST) {
-                        store_ranked(vals, m, s0 << 2, id[b]);
-                    } else if ((m >> lane) & 1ull) {
-                        const uint32_t pos = s0 + rank_below(m);
-                        if (pos < cap32) {
-                            vals[pos] = id[b];
-                            if (keys) keys[pos] = ((uint64_t)(uint32_t)((ty0 + rr) * gx + tx0 + cc) << 32) | db[b];
-                        }
+            for (int off = 32; off >= 1; off >>= 1) e = max(e, (uint32_t)__shfl_xor((int)e, off, 64));
+            inside = e <= cap32;
+        }
+        pin_u32(nxt.id, nxt.packed, nxt.sbase, dbn);  // the next chunk's loads land before the stores (every path)
+        for (int rr = 0; rr < kSuper; rr++) {
+            if (rowB[rr] == 0ull || !inside) continue;  // no lane of this wave covers the row (uniform)
+            for (int cc = 0; cc < kSuper; cc++) {
+                const uint64_t m = colB[cc] & rowB[rr];
+                if (m == 0ull) continue;
+                const int tl = rr * kSuper + cc;
+                const uint32_t s0 = (uint32_t)__builtin_amdgcn_readlane((int)myslot, tl);
+                if constexpr (FAST) {
+                    store_ranked(vals, m, s0 << 2, cur.id);
+                } else if ((m >> lane) & 1ull) {
+                    const uint32_t pos = s0 + rank_below(m);
+                    if (pos < cap32) {
+                        vals[pos] = cur.id;
+                        if (keys) keys[pos] = ((uint64_t)(uint32_t)((ty0 + rr) * gx + tx0 + cc) << 32) | db;
                     }
                 }
             }
-            __syncthreads();
         }
+        __syncthreads();
+        cur = nxt;
+        db = dbn;
     }
 }
 
@@ -1062,8 +1082,8 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_scatter(const uint32_t *list1
 inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct WsLayout {
-    size_t counters, blockvis, blockarea, keysA, valsA, keysB, valsB, crec, sid, sbox, hist, h1, list1, list1r, l1start, l1len, c2start,
-        toff, h2, parts, gtot, total;
+    size_t counters, blockvis, blockarea, keysA, valsA, keysB, valsB, crec, sid, sbox, hist, h1, list1, list1r, l1start,
+        l1len, c2start, toff, h2, parts, gtot, total;
     uint32_t hist_n, h1_n, h2_n;
 };
 

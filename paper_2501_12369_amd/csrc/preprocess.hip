@@ -146,7 +146,7 @@ __device__ __forceinline__ bool splat_geom64(const QS &v, Geom64 &G) {
     G.s[2] = v.s[2];
     if (!(qnorm > 0.0)) return false;
     G.qinv = 1.0 / qnorm;
-    const double w = q0 / qnorm, x = q1 / qnorm, y = q2 / qnorm, z = q3 / qnorm;
+    const double w = q0 * G.qinv, x = q1 * G.qinv, y = q2 * G.qinv, z = q3 * G.qinv;
     G.qn[0] = w; G.qn[1] = x; G.qn[2] = y; G.qn[3] = z;
     double *Rq = G.Rq;
     Rq[0] = 1.0 - 2.0 * (y * y + z * z);
@@ -193,9 +193,11 @@ __device__ __forceinline__ bool view_depth(const Cam &cam, const float (&m)[3], 
 // The rest of the projection of a splat in front of the camera (P.t set);
 // false when culled (singular 2D covariance, or a radius box off the tile grid).
 __device__ __forceinline__ bool project_rest(const Cam &cam, const KParams &kp, const Geom64 &G, Proj &P) {
-    const double tz = P.t[2], fx = cam.fx, fy = cam.fy;
-    P.xt = P.t[0] / tz;
-    P.yt = P.t[1] / tz;
+    // one FP64 division (1/t_z) and reciprocals elsewhere: each product errs by an
+    // FP64 rounding or two, far below the FP32 rounding of the records
+    const double tz = P.t[2], itz = 1.0 / tz, fx = cam.fx, fy = cam.fy;
+    P.xt = P.t[0] * itz;
+    P.yt = P.t[1] * itz;
     P.cx_ = P.cy_ = false;
     if (cam.lim_x > 0.0) {
         if (P.xt > cam.lim_x) { P.xt = cam.lim_x; P.cx_ = true; }
@@ -203,7 +205,7 @@ __device__ __forceinline__ bool project_rest(const Cam &cam, const KParams &kp, 
         if (P.yt > cam.lim_y) { P.yt = cam.lim_y; P.cy_ = true; }
         if (P.yt < -cam.lim_y) { P.yt = -cam.lim_y; P.cy_ = true; }
     }
-    const double J00 = fx / tz, J02 = -fx * P.xt / tz, J11 = fy / tz, J12 = -fy * P.yt / tz;
+    const double J00 = fx * itz, J02 = -fx * P.xt * itz, J11 = fy * itz, J12 = -fy * P.yt * itz;
     // A = J R_cw (2x3), M = A Sigma A^T
     double A[6];
     for (int c = 0; c < 3; c++) {
@@ -222,11 +224,12 @@ __device__ __forceinline__ bool project_rest(const Cam &cam, const KParams &kp, 
     const double c00 = psi * M00 + eps, c01 = psi * M01, c11 = psi * M11 + eps;
     const double det = c00 * c11 - c01 * c01;
     if (!(det > 0.0)) return false;
+    const double rs = 1.0 / sqrt(c11 * det);  // 1 / sqrt(c11 det)
     P.l11 = (float)(1.0 / sqrt(c11));
-    P.l00 = (float)sqrt(c11 / det);
-    P.l01 = (float)(-c01 / sqrt(c11 * det));
-    P.u = (float)(fx * P.t[0] / tz + (double)cam.cx);
-    P.v = (float)(fy * P.t[1] / tz + (double)cam.cy);
+    P.l00 = (float)(c11 * rs);                             // sqrt(c11 / det)
+    P.l01 = (float)(-c01 * rs);
+    P.u = (float)(fx * P.t[0] * itz + (double)cam.cx);
+    P.v = (float)(fy * P.t[1] * itz + (double)cam.cy);
     // radius rf sqrt(lambda_max), rf = 3 (or sqrt(e_max) beyond E = 9)
     const double mid = 0.5 * (c00 + c11);
     const double disc = mid * mid - det;
@@ -254,8 +257,9 @@ struct Clamp {
 __device__ __forceinline__ void clamp_of(const Cam &cam, const float (&m)[3], Clamp &cj) {
     Proj P;
     view_depth(cam, m, P);
-    cj.xt = P.t[0] / P.t[2];
-    cj.yt = P.t[1] / P.t[2];
+    const double itz = 1.0 / P.t[2];  // the forward's expression, so that the decisions agree
+    cj.xt = P.t[0] * itz;
+    cj.yt = P.t[1] * itz;
     cj.cx_ = cj.cy_ = false;
     if (cam.lim_x > 0.0) {
         if (cj.xt > cam.lim_x) { cj.xt = cam.lim_x; cj.cx_ = true; }

@@ -56,9 +56,10 @@ struct LanePix {
     static constexpr int NP = kPix / S;
     int ix, iy0;
     float ylo;  // first row of this wave's pixel block
-    __device__ __forceinline__ LanePix(int tile, int gx) {
+    // part h of the tile (h = the wavefront's index in its workgroup by default)
+    __device__ __forceinline__ LanePix(int tile, int gx, int h = (int)(threadIdx.x >> 6)) {
         const int tx = tile % gx, ty = tile / gx;
-        const int lane = threadIdx.x & 63, h = threadIdx.x >> 6;
+        const int lane = threadIdx.x & 63;
         ix = tx * kTile + (lane & 15);
         ylo = (float)(ty * kTile + h * (kTile / S));
         iy0 = ty * kTile + h * (kTile / S) + (lane >> 4);
@@ -312,10 +313,10 @@ template <int KIND, bool DET, int S>
 __device__ __forceinline__ void tile_bwd(const RView &V, int tile, uint32_t item, int n, const KParams &kp,
                                          const ROpts &o, float (&T)[kPix / S], const uint32_t (&lp)[kPix / S],
                                          const float (&G0)[kPix / S], const float (&G1)[kPix / S],
-                                         const float (&G2)[kPix / S], const DetOut &d) {
+                                         const float (&G2)[kPix / S], const DetOut &d, int h = 0) {
     static_assert(!DET || S == 1, "the deterministic backward keeps one wavefront per tile");
     constexpr int NP = kPix / S;
-    const LanePix<S> P(tile, V.gx);
+    const LanePix<S> P(tile, V.gx, h);
     const int lane = threadIdx.x & 63;
     const int ix = P.ix, iy0 = P.iy0;
     const float px = (float)ix;
@@ -492,6 +493,86 @@ __global__ __launch_bounds__(64) void k_raster_bwd(VS A, int n, KParams kp, ROpt
     uint32_t lp[kPix / S];
     load_checkpoint<S>(V, tile, T, lp, G0, G1, G2);
     tile_bwd<KIND, DET, S>(V, tile, blockIdx.x, n, kp, o, T, lp, G0, G1, G2, d);
+}
+
+// Backward with the long walks split: one four-wavefront workgroup per tile.
+// Wavefront h first reads the checkpointed positions of rows 4h .. 4h+3 (one
+// pixel per lane); the tile's cost is its walk, the largest position past the
+// tile's start.  A walk longer than split2 (split4) instances is shared by two
+// (four) wavefronts, each taking 8 (4) of the tile's rows and walking only to
+// its own pixels' largest position; otherwise wavefront 0 takes the whole tile
+// (four pixels per lane) and the others leave after the one barrier.  So the
+// heaviest tiles no longer run alone at the end of the launch, and consecutive
+// workgroups (which the hardware deals to different XCDs) are different tiles.
+// A one-wavefront lane's k-th pixel (row lane/16 + 4k) is lane `lane` of
+// wavefront k here, and a two-wavefront part h's k-th pixel is wavefront
+// 2h + k's: the positions are shared through LDS.  The sums per splat are
+// those of the one-wavefront backward in another order (atomic accumulation).
+template <int KIND, class VS>
+__global__ __launch_bounds__(256) void k_raster_bwd_split(VS A, int n, KParams kp, ROpts o, uint32_t split2,
+                                                          uint32_t split4) {
+    __shared__ uint32_t lps[4][64];
+    __shared__ uint32_t wmax[4];
+    int tile;
+    const uint32_t item = blockIdx.x;
+    const RView &V = A.get(item, tile);
+    if (V.overflow && *V.overflow) return;
+    const int h = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    {
+        const LanePix<4> P4(tile, V.gx, h);
+        const bool in = P4.ix < V.W && P4.iy0 < V.H;
+        const uint32_t l = in ? V.last[(size_t)P4.iy0 * V.W + P4.ix] : kNone;
+        const uint32_t lp = l == kNone ? 0u : l + 1u;
+        lps[h][lane] = lp;
+        const uint32_t m = wave_max_u32(lp);
+        if (lane == 0) wmax[h] = m;
+    }
+    __syncthreads();
+    const uint32_t start = V.ranges[2 * tile], end = V.ranges[2 * tile + 1];
+    const uint32_t maxl = min(max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3])), end);
+    const uint32_t walk = maxl > start ? maxl - start : 0u;
+    const int parts = walk > split4 ? 4 : (walk > split2 ? 2 : 1);
+    if (h >= parts) return;
+    const size_t plane = (size_t)V.W * V.H;
+    // checkpoint of this part's pixels: T, dL/dI where the pixel blended
+    auto load = [&](int ix, int iy, uint32_t lp, float &T, float &g0, float &g1, float &g2) {
+        T = g0 = g1 = g2 = 0.0f;
+        if (lp != 0u) {
+            const size_t pidx = (size_t)iy * V.W + ix;
+            T = V.final_T[pidx];
+            g0 = V.dL[pidx];
+            g1 = V.dL[plane + pidx];
+            g2 = V.dL[2 * plane + pidx];
+        }
+    };
+    if (parts == 1) {
+        const LanePix<1> P(tile, V.gx, 0);
+        float T[4], G0[4], G1[4], G2[4];
+        uint32_t lp[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            lp[k] = lps[k][lane];
+            load(P.ix, P.iy0 + 4 * k, lp[k], T[k], G0[k], G1[k], G2[k]);
+        }
+        tile_bwd<KIND, false, 1>(V, tile, item, n, kp, o, T, lp, G0, G1, G2, DetOut{}, 0);
+    } else if (parts == 2) {
+        const LanePix<2> P(tile, V.gx, h);
+        float T[2], G0[2], G1[2], G2[2];
+        uint32_t lp[2];
+#pragma unroll
+        for (int k = 0; k < 2; k++) {
+            lp[k] = lps[2 * h + k][lane];
+            load(P.ix, P.iy0 + 4 * k, lp[k], T[k], G0[k], G1[k], G2[k]);
+        }
+        tile_bwd<KIND, false, 2>(V, tile, item, n, kp, o, T, lp, G0, G1, G2, DetOut{}, h);
+    } else {
+        const LanePix<4> P(tile, V.gx, h);
+        float T[1], G0[1], G1[1], G2[1];
+        uint32_t lp[1];
+        lp[0] = lps[h][lane];
+        load(P.ix, P.iy0, lp[0], T[0], G0[0], G1[0], G2[0]);
+        tile_bwd<KIND, false, 4>(V, tile, item, n, kp, o, T, lp, G0, G1, G2, DetOut{}, h);
+    }
 }
 
 // Forward, per-pixel loss gradient and backward of one tile in one wavefront.
@@ -684,23 +765,33 @@ void fwd_launch(const RViews &V, uint32_t items, int n, const KParams &kp, const
     }
 }
 
+// Walks longer than these (instances past the tile's start) are shared by two /
+// four wavefronts in the atomic backward.
+#ifndef DARB_BWD_SPLIT2
+#define DARB_BWD_SPLIT2 512
+#endif
+#ifndef DARB_BWD_SPLIT4
+#define DARB_BWD_SPLIT4 1024
+#endif
+
 template <int KIND>
 void bwd_launch(const RViews &V, uint32_t items, int n, const KParams &kp, const ROpts &o, bool det, const DetOut &d,
                 hipStream_t s) {
+    const uint32_t s2 = DARB_BWD_SPLIT2, s4 = DARB_BWD_SPLIT4;
     if (V.nv == 1) {
         if (det)
             hipLaunchKernelGGL((k_raster_bwd<KIND, true, OneView>), dim3(items), dim3(64), 0, s, OneView{V.v[0]}, n,
                                kp, o, d);
         else
-            hipLaunchKernelGGL((k_raster_bwd<KIND, false, OneView>), dim3(items), dim3(64), 0, s, OneView{V.v[0]}, n,
-                               kp, o, d);
+            hipLaunchKernelGGL((k_raster_bwd_split<KIND, OneView>), dim3(items), dim3(256), 0, s, OneView{V.v[0]}, n,
+                               kp, o, s2, s4);
     } else {
         if (det)
             hipLaunchKernelGGL((k_raster_bwd<KIND, true, ManyViews>), dim3(items), dim3(64), 0, s, ManyViews{V}, n, kp,
                                o, d);
         else
-            hipLaunchKernelGGL((k_raster_bwd<KIND, false, ManyViews>), dim3(items), dim3(64), 0, s, ManyViews{V}, n,
-                               kp, o, d);
+            hipLaunchKernelGGL((k_raster_bwd_split<KIND, ManyViews>), dim3(items), dim3(256), 0, s, ManyViews{V}, n,
+                               kp, o, s2, s4);
     }
 }
 

@@ -176,6 +176,52 @@ def test_raster_bwd_parity(kname):
         assert_grads(runs[det][0], go, ("xy", "conic", "opacity", "rgb"), label=f"det={int(det)} ")
 
 
+@pytest.mark.parametrize("n,lo,hi", [(700, 512, 1024), (2600, 1024, 1 << 30)])
+def test_raster_bwd_long_walks(n, lo, hi):
+    """Dense tiles of faint, wide splats: walks of several hundred to a few
+    thousand instances, so that the atomic backward shares a tile's walk among
+    two (walk > 512) or four (walk > 1024) wavefronts.  The gradients equal
+    the oracle's and the deterministic path's within the gradient rule."""
+    kname, W, H, seed = "half_cos", 56, 40, 29
+    print(f"raster_bwd long walks n={n} {W}x{H}", flush=True)
+    opts = dict(pipeline.DEFAULT_OPTS, bg=(0.2, 0.3, 0.1))
+    # faint opacities, so that thousands of splats blend before a pixel saturates
+    ps = scenes.projected(seed, n, W, H, sigma_range=(6.0, 25.0), opacity_range=(0.005, 0.03))
+    fr, _ = gpu_bin_raster(ps, kname, opts=opts)
+    orc = oracle.composite(oracle_projected(ps), ps["conic_o"][:, 3].astype(np.float64), oracle_kernel_fp32(kname),
+                           oracle_opts_fp32(opts), W, H)
+    # the walks (largest checkpointed position + 1 past the tile's start) span the range
+    gx, gy = (W + 15) // 16, (H + 15) // 16
+    last = to_np(fr.last).reshape(H, W).astype(np.int64) & 0xFFFFFFFF
+    lp = np.where(last == 0xFFFFFFFF, 0, last + 1)
+    rng_t = to_np(fr.ranges).astype(np.int64).reshape(-1, 2)
+    walks = []
+    for ty in range(gy):
+        for tx in range(gx):
+            st, en = rng_t[ty * gx + tx]
+            m = min(int(lp[16 * ty:16 * ty + 16, 16 * tx:16 * tx + 16].max()), int(en))
+            walks.append(max(m - int(st), 0))
+    print(f"  walks {sorted(walks)}")
+    assert any(lo < w <= hi for w in walks), walks
+    amb = orc["margin"] < AMBIG
+    Go = ambiguous_zeroed(scenes.upstream_grad(seed + 1, W, H).reshape(3, -1).T, orc["margin"], AMBIG)
+    G = np.ascontiguousarray(Go.T.reshape(3, H, W))
+    print(f"  ambiguous pixels {int(amb.sum())} of {amb.size}")
+    assert amb.mean() < 0.25
+    runs = {}
+    for det in (False, True):
+        g2d, _ = pipeline.alloc_grads(n, 0)
+        ws = pipeline.det_workspace(fr) if det else None
+        native.darb_raster_bwd(fr.proj, n, fr.vals, fr.ranges, fr.overflow, W, H, pipeline.KERNELS[kname], opts,
+                               dev(G), fr.final_T, fr.last, g2d, deterministic=det, k_capacity=fr.capacity, ws=ws)
+        torch.cuda.synchronize()
+        runs[det] = {k: to_np(v) for k, v in g2d.items()}
+    go = oracle.composite_bwd(oracle_projected(ps), ps["conic_o"][:, 3].astype(np.float64),
+                              oracle_kernel_fp32(kname), oracle_opts_fp32(opts), W, H, Go.astype(np.float64))
+    for det in (False, True):
+        assert_grads(runs[det], go, ("xy", "conic", "opacity", "rgb"), label=f"det={int(det)} ")
+
+
 @pytest.mark.parametrize("n", [1200, 7])
 def test_raster_fwd_clears_g2d(n):
     """zero_g2d: the forward clears the 2D-gradient buffers (also when the
