@@ -135,44 +135,21 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const uint32_t *in
     if (threadIdx.x == 0) parts[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(1024) void k_scan_parts(uint32_t *parts, const uint32_t *count_dev, uint32_t max_count,
-                                                     uint32_t *total_out, const int32_t *skip) {
-    __shared__ uint32_t lw[16];
-    __shared__ uint32_t carry;
-    if (skip && *skip) return;
-    uint32_t count = live_count(count_dev, max_count);
-    uint32_t nb = (count + kScanBlock - 1) / kScanBlock;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (uint32_t base = 0; base < nb; base += 1024) {
-        uint32_t i = base + threadIdx.x;
-        uint32_t v = i < nb ? parts[i] : 0u;
-        uint32_t inc = wave_incl_scan(v);
-        if (lane == 63) lw[w] = inc;
-        __syncthreads();
-        uint32_t woff = 0, tot = 0;
-        for (int k = 0; k < 16; k++) {
-            if (k < w) woff += lw[k];
-            tot += lw[k];
-        }
-        uint32_t c = carry;
-        if (i < nb) parts[i] = c + woff + inc - v;
-        __syncthreads();
-        if (threadIdx.x == 0) carry = c + tot;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0 && total_out) *total_out = carry;
-}
-
+// The down-sweep adds the sum of the block sums before its own block, which it
+// reads itself (at most a few thousand words per block, from L2): no separate
+// launch scans the block sums.  The last live block writes the total.
 __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t *in, uint32_t *out, const uint32_t *count_dev,
                                                             uint32_t max_count, const uint32_t *parts,
-                                                            const int32_t *skip) {
+                                                            uint32_t *total_out, const int32_t *skip) {
     __shared__ uint32_t lw[kScanThreads / 64];
+    __shared__ uint32_t lp[kScanThreads / 64];
     if (skip && *skip) return;
     uint32_t count = live_count(count_dev, max_count);
     uint32_t base = blockIdx.x * kScanBlock;
-    if (base >= count) return;
+    if (base >= count) {
+        if (count == 0 && blockIdx.x == 0 && threadIdx.x == 0 && total_out) *total_out = 0;
+        return;
+    }
     uint32_t v[kScanItems];
     uint32_t s = 0;
     uint32_t b0 = base + threadIdx.x * kScanItems;
@@ -180,12 +157,22 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(const uint32_t *in, 
         v[k] = (b0 + k < count) ? in[b0 + k] : 0u;
         s += v[k];
     }
+    uint32_t pre = 0;
+    for (uint32_t i = threadIdx.x; i < blockIdx.x; i += kScanThreads) pre += parts[i];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) pre += (uint32_t)__shfl_xor((int)pre, off, 64);
+    if ((threadIdx.x & 63) == 0) lp[threadIdx.x >> 6] = pre;
     uint32_t tot;
-    uint32_t off = block_excl_scan(s, lw, &tot) + parts[blockIdx.x];
+    uint32_t off = block_excl_scan(s, lw, &tot);  // (its barriers also publish lp)
+    pre = 0;
+#pragma unroll
+    for (int k = 0; k < kScanThreads / 64; k++) pre += lp[k];
+    off += pre;
     for (int k = 0; k < kScanItems; k++) {
         if (b0 + k < count) out[b0 + k] = off;
         off += v[k];
     }
+    if (total_out && threadIdx.x == 0 && base + kScanBlock >= count) *total_out = pre + tot;
 }
 
 hipError_t scan_exclusive(uint32_t *data, const uint32_t *count_dev, uint32_t max_count, uint32_t *parts,
@@ -193,8 +180,8 @@ hipError_t scan_exclusive(uint32_t *data, const uint32_t *count_dev, uint32_t ma
     if (max_count == 0) return hipSuccess;
     uint32_t nb = (max_count + kScanBlock - 1) / kScanBlock;
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kScanThreads), 0, s, data, count_dev, max_count, parts, skip);
-    hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(1024), 0, s, parts, count_dev, max_count, total_out, skip);
-    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kScanThreads), 0, s, data, data, count_dev, max_count, parts, skip);
+    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(kScanThreads), 0, s, data, data, count_dev, max_count, parts,
+                       total_out, skip);
     return hipGetLastError();
 }
 
@@ -239,11 +226,8 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_hist(const uint32_t *ke
 // row's start (a scan over the few totals) itself, instead of one scan over
 // all entries.
 template <int T>
-__global__ __launch_bounds__(T) void k_rowscan(uint32_t *data, const uint32_t *len_dev, uint32_t len_host,
-                                               uint32_t *totals, const int32_t *skip) {
-    __shared__ uint32_t lw[T / 64];
-    if (*skip) return;
-    const int nblk = (int)(len_dev ? *len_dev : len_host);
+__device__ __forceinline__ void rowscan_row(uint32_t *data, uint32_t len, uint32_t *totals, uint32_t *lw) {
+    const int nblk = (int)len;
     uint32_t *row = data + (size_t)blockIdx.x * nblk;
     uint32_t carry = 0;
     for (int base = 0; base < nblk; base += T * kScanItems) {
@@ -266,6 +250,14 @@ __global__ __launch_bounds__(T) void k_rowscan(uint32_t *data, const uint32_t *l
     if (threadIdx.x == 0) totals[blockIdx.x] = carry;
 }
 
+template <int T>
+__global__ __launch_bounds__(T) void k_rowscan(uint32_t *data, const uint32_t *len_dev, uint32_t len_host,
+                                               uint32_t *totals, const int32_t *skip) {
+    __shared__ uint32_t lw[T / 64];
+    if (*skip) return;
+    rowscan_row<T>(data, len_dev ? *len_dev : len_host, totals, lw);
+}
+
 // One tile of kRadixTile keys per workgroup; wave w owns the contiguous quarter
 // [w * kRadixWaveItems, (w + 1) * kRadixWaveItems) of the tile, held in
 // registers (all loads issued at once).  Each wave ranks its keys by digit on
@@ -276,14 +268,27 @@ __global__ __launch_bounds__(T) void k_rowscan(uint32_t *data, const uint32_t *l
 // stable (digit, wave, round, lane), and each digit's run is written to its
 // global position by consecutive lanes.  Three workgroup barriers in all.
 //
+#ifndef DARB_RADIX_XCD_MAP
+#define DARB_RADIX_XCD_MAP 1
+#endif
+// Key tile of scatter workgroup b.  With the XCD map, the workgroups the
+// hardware deals to one XCD (b = x, x + 8, ...) take consecutive tiles, so the
+// neighbouring runs of a digit are written through one L2.
+__device__ __forceinline__ uint32_t radix_tile_of(uint32_t b, uint32_t nb) {
+    if (!DARB_RADIX_XCD_MAP) return b;
+    const uint32_t x = b & 7u, j = b >> 3, q = nb >> 3, r = nb & 7u;
+    return x * q + min(x, r) + j;
+}
+
 // REC (the last pass of the depth sort): instead of (key, value) the output is
-// the compact record the value indexes -- splat index and packed tile box --
-// gathered while the tile is written out (this replaces a separate gather
-// pass over the sorted values).
-template <bool REC>
-__global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t *kin, const uint32_t *vin,
-                                                                 uint32_t *kout, uint32_t *vout,
-                                                                 const uint32_t *count_dev, int shift,
+// the splat index and tile box of each value, in sorted order.  With 32-bit
+// values (compact indices) they are gathered from the compact records while the
+// tile is written out; with 64-bit values (splat index | box with 8-bit tile
+// coordinates, carried through every pass) they are the value itself, and the
+// last pass reads nothing at random.
+template <class V, bool REC>
+__global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t *kin, const V *vin, uint32_t *kout,
+                                                                 V *vout, const uint32_t *count_dev, int shift,
                                                                  const uint32_t *hist_scan, int nblk,
                                                                  const int32_t *skip, const uint4 *crec,
                                                                  uint32_t *sid, uint2 *sbox) {
@@ -291,23 +296,27 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t 
     __shared__ uint32_t loff[256];                 // first LDS slot of each digit
     __shared__ uint32_t wcnt[kRadixWaves][256];    // per-wave digit counts, then per-wave first slots
     __shared__ uint32_t lw[kRadixWaves];
-    __shared__ uint32_t sk[kRadixTile], sv[kRadixTile];
+    __shared__ uint32_t sk[kRadixTile];
+    __shared__ V sv[kRadixTile];
     if (*skip) return;
     const uint32_t n = *count_dev;
-    const uint32_t base = blockIdx.x * kRadixTile;
-    if (base >= n) return;
+    const uint32_t nlive = (n + kRadixTile - 1) / kRadixTile;  // tiles holding keys
+    if (blockIdx.x >= nlive) return;
+    const uint32_t tile = radix_tile_of(blockIdx.x, nlive);
+    const uint32_t base = tile * kRadixTile;
     const uint32_t cnt = min((uint32_t)kRadixTile, n - base);
     const int t = threadIdx.x, w = t >> 6, lane = t & 63;
     // the tile's keys and values, and this thread's digit counts, all in flight at once
-    uint32_t key[kRadixItems], val[kRadixItems];
+    uint32_t key[kRadixItems];
+    V val[kRadixItems];
     const uint32_t w0 = (uint32_t)w * kRadixWaveItems;
 #pragma unroll
     for (int r = 0; r < kRadixItems; r++) {
         const uint32_t li = w0 + r * 64 + lane;
         key[r] = li < cnt ? kin[base + li] : 0u;
-        val[r] = li < cnt ? vin[base + li] : 0u;
+        val[r] = li < cnt ? vin[base + li] : V{};
     }
-    const uint32_t dtotal = hist_scan[(size_t)256 * nblk + t], dprefix = hist_scan[t * nblk + blockIdx.x];
+    const uint32_t dtotal = hist_scan[(size_t)256 * nblk + t], dprefix = hist_scan[t * nblk + tile];
     {
         // global first slot of digit t for this tile: the digit's start (scan of the
         // digit totals) plus this tile's prefix within the digit's row
@@ -368,7 +377,16 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t 
     }
     __syncthreads();
     // the tile in digit order: slot i of digit d goes to run[d] + (i - loff[d])
-    if constexpr (REC) {
+    if constexpr (REC && sizeof(V) == 8) {
+        for (uint32_t i = t; i < cnt; i += kRadixThreads) {
+            const uint32_t d = (sk[i] >> shift) & 255u;
+            const uint32_t g = run[d] + (i - loff[d]);
+            const uint2 v = reinterpret_cast<const uint2 &>(sv[i]);
+            sid[g] = v.x;
+            sbox[g] = make_uint2((v.y & 0xFFu) | ((v.y >> 8) & 0xFFu) << 16,
+                                 ((v.y >> 16) & 0xFFu) | (v.y >> 24) << 16);
+        }
+    } else if constexpr (REC) {
         // gathers and destinations first; the stores follow once every gather
         // has landed (a store between two uses of gathered data would make the
         // second use wait for it: vmcnt counts stores too)
@@ -502,9 +520,13 @@ __global__ __launch_bounds__(1024) void k_bin_sizes(uint32_t *block_vis, const u
 // blocking as k_bin_keys; a splat's slot is the block's offset plus the
 // visible splats before it in (round, wave, lane) = index order.
 
+// V64 (tile grids of at most 255 x 255): the value is (splat index, box with
+// 8-bit tile coordinates) and no record is written; the sort carries it.
+template <bool V64>
 __global__ __launch_bounds__(256) void k_bin_compact(const float *xy, const int32_t *radius, const float *depth, int n,
                                                      int gx, int gy, const uint32_t *block_off, uint32_t *keys,
-                                                     uint32_t *vals, uint4 *crec, const int32_t *overflow_dev) {
+                                                     uint32_t *vals, uint4 *crec, uint2 *vals64,
+                                                     const int32_t *overflow_dev) {
     __shared__ uint32_t wv[kKeyItems * 4];  // visible count of each (round, wave), then its first slot
     if (*overflow_dev) return;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -551,9 +573,14 @@ __global__ __launch_bounds__(256) void k_bin_compact(const float *xy, const int3
             const int i = base + k * 256;
             const uint32_t pos = wv[k * 4 + w] + (uint32_t)__popcll(m & lt);
             keys[pos] = db[k];
-            vals[pos] = pos;
-            crec[pos] = make_uint4((uint32_t)rect[k].x | ((uint32_t)rect[k].y << 16),
-                                   (uint32_t)rect[k].z | ((uint32_t)rect[k].w << 16), (uint32_t)i, 0u);
+            if constexpr (V64) {
+                vals64[pos] = make_uint2((uint32_t)i, (uint32_t)rect[k].x | ((uint32_t)rect[k].y << 8) |
+                                                          ((uint32_t)rect[k].z << 16) | ((uint32_t)rect[k].w << 24));
+            } else {
+                vals[pos] = pos;
+                crec[pos] = make_uint4((uint32_t)rect[k].x | ((uint32_t)rect[k].y << 16),
+                                       (uint32_t)rect[k].z | ((uint32_t)rect[k].w << 16), (uint32_t)i, 0u);
+            }
         }
     }
 }
@@ -618,6 +645,7 @@ __global__ __launch_bounds__(kL1Threads) void k_l1_scatter(const uint32_t *sid, 
     __shared__ uint32_t lw[kScanThreads / 64];
     uint32_t *bits = lds1;                   // [8][nsuper]: word-major (lanes of a wave hit distinct banks)
     uint32_t *first = lds1 + nsuper * 8;     // [nsuper]
+    uint16_t *pre = reinterpret_cast<uint16_t *>(lds1 + nsuper * 9);  // [8][nsuper]: covering threads of the words before
     if (*overflow_dev) return;
     const uint32_t c = blockIdx.x, c1 = cnt->c1, nv = cnt->n_visible;
     if (c >= c1) return;
@@ -665,12 +693,20 @@ __global__ __launch_bounds__(kL1Threads) void k_l1_scatter(const uint32_t *sid, 
     for (int gys = sb.sy0; gys <= sb.sy1; gys++)
         for (int gxs = sb.sx0; gxs <= sb.sx1; gxs++) atomicOr(&bits[word * nsuper + gys * sxn + gxs], bit);
     __syncthreads();
+    for (int g = threadIdx.x; g < nsuper; g += kL1Threads) {
+        uint32_t c = 0;
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            pre[k * nsuper + g] = (uint16_t)c;
+            c += (uint32_t)__popc(bits[k * nsuper + g]);
+        }
+    }
+    __syncthreads();
     // rank = covering threads of lower index (depth order) -> stable
     for (int gys = sb.sy0; gys <= sb.sy1; gys++)
         for (int gxs = sb.sx0; gxs <= sb.sx1; gxs++) {
             const int g = gys * sxn + gxs;
-            uint32_t rank = (uint32_t)__popc(bits[word * nsuper + g] & (bit - 1u));
-            for (int k = 0; k < word; k++) rank += (uint32_t)__popc(bits[k * nsuper + g]);
+            const uint32_t rank = pre[word * nsuper + g] + (uint32_t)__popc(bits[word * nsuper + g] & (bit - 1u));
             uint32_t pos = first[g] + rank;
             if ((int64_t)pos < list1_cap) {
                 list1[pos] = id;
@@ -684,13 +720,12 @@ __global__ __launch_bounds__(kL1Threads) void k_l1_scatter(const uint32_t *sid, 
 // (tile, chunk) count array in row-major tile order.
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(1024) void k_l2_plan(const uint32_t *gtot, Counters *cnt, int nsuper, int sxn, int gx,
-                                                  int gy, uint32_t *l1_start, uint32_t *l1_len, uint32_t *chunk2_start,
-                                                  uint32_t *toff, const int32_t *overflow_dev) {
+// (one workgroup of 1024 threads; nsuper <= 1024)
+__device__ __forceinline__ void l2_plan(const uint32_t *gtot, Counters *cnt, int nsuper, int sxn, int gx, int gy,
+                                        uint32_t *l1_start, uint32_t *l1_len, uint32_t *chunk2_start, uint32_t *toff) {
     __shared__ uint32_t lw[16];
     __shared__ uint32_t carry;
     __shared__ uint32_t n2s[1024];
-    if (*overflow_dev) return;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     // spans (list lengths and their exclusive scan) and chunk counts (nsuper <= 1024)
     int g = threadIdx.x;
@@ -759,6 +794,13 @@ __global__ __launch_bounds__(1024) void k_l2_plan(const uint32_t *gtot, Counters
         toff[ntile] = carry;
         cnt->h2_count = carry;
     }
+}
+
+__global__ __launch_bounds__(1024) void k_l2_plan(const uint32_t *gtot, Counters *cnt, int nsuper, int sxn, int gx,
+                                                  int gy, uint32_t *l1_start, uint32_t *l1_len, uint32_t *chunk2_start,
+                                                  uint32_t *toff, const int32_t *overflow_dev) {
+    if (*overflow_dev) return;
+    l2_plan(gtot, cnt, nsuper, sxn, gx, gy, l1_start, l1_len, chunk2_start, toff);
 }
 
 // ---------------------------------------------------------------------------
@@ -1047,10 +1089,7 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_scatter(const uint32_t *list1
             // every run of this wave lies inside the capacity (K <= capacity is decided
             // before any instance is written; this test only guards the stores)
             const uint32_t myc = wc[w * 64 + lane];
-            uint32_t e = myc ? myslot + myc : 0u;
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) e = max(e, (uint32_t)__shfl_xor((int)e, off, 64));
-            inside = e <= cap32;
+            inside = __ballot(myc != 0u && myslot + myc > cap32) == 0ull;
         }
         pin_u32(nxt.id, nxt.packed, nxt.sbase, dbn);  // the next chunk's loads land before the stores (every path)
         for (int rr = 0; rr < kSuper; rr++) {
@@ -1151,8 +1190,8 @@ hipError_t radix_sort_pairs(uint32_t *kA, uint32_t *vA, uint32_t *kB, uint32_t *
         hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kRadixThreads), 0, s, ki, count_dev, shift, hist, nblk, skip);
         hipLaunchKernelGGL(k_rowscan<kScanThreads>, dim3(256), dim3(kScanThreads), 0, s, hist, nullptr, (uint32_t)nblk,
                            hist + (size_t)256 * nblk, skip);
-        hipLaunchKernelGGL(k_radix_scatter<false>, dim3(nblk), dim3(kRadixThreads), 0, s, ki, vi, ko, vo, count_dev,
-                           shift, hist, nblk, skip, nullptr, nullptr, nullptr);
+        hipLaunchKernelGGL((k_radix_scatter<uint32_t, false>), dim3(nblk), dim3(kRadixThreads), 0, s, ki, vi, ko, vo,
+                           count_dev, shift, hist, nblk, skip, nullptr, nullptr, nullptr);
         std::swap(ki, ko);
         std::swap(vi, vo);
     }
@@ -1193,26 +1232,44 @@ hipError_t launch_bin_sort(const darb_projected &p, int n, int width, int height
     uint2 *sbox = reinterpret_cast<uint2 *>(base + L.sbox);
     if (n > 0) {
         uint4 *crec = reinterpret_cast<uint4 *>(base + L.crec);
-        hipLaunchKernelGGL(k_bin_compact, dim3(nkb), dim3(256), 0, s, p.xy, p.radius, p.depth, n, gx, gy, blockvis, kA,
-                           vA, crec, overflow_dev);
+        // grids of at most 255 x 255 tiles carry (splat index, box) through the sort
+        // as a 64-bit value (in the record area); larger grids gather the record in
+        // the last pass
+        const bool v64 = gx <= 255 && gy <= 255;
+        uint2 *v64A = reinterpret_cast<uint2 *>(base + L.crec), *v64B = v64A + n;
+        if (v64)
+            hipLaunchKernelGGL(k_bin_compact<true>, dim3(nkb), dim3(256), 0, s, p.xy, p.radius, p.depth, n, gx, gy,
+                               blockvis, kA, nullptr, nullptr, v64A, overflow_dev);
+        else
+            hipLaunchKernelGGL(k_bin_compact<false>, dim3(nkb), dim3(256), 0, s, p.xy, p.radius, p.depth, n, gx, gy,
+                               blockvis, kA, vA, crec, nullptr, overflow_dev);
         // depth sort of the N_v visible keys: 4 passes of 8 bits
         const int nblk = (n + kRadixTile - 1) / kRadixTile;
         uint32_t *ki = kA, *vi = vA, *ko = kB, *vo = vB;
-        // (the last pass writes the splat index and tile box of each compact
-        // index, in (depth, index) order, instead of the sorted pairs)
+        uint2 *wi = v64A, *wo = v64B;
+        // (the last pass writes the splat index and tile box of each value, in
+        // (depth, index) order, instead of the sorted pairs)
         for (int shift = 0; shift < 32; shift += 8) {
             hipLaunchKernelGGL(k_radix_hist, dim3(nblk), dim3(kRadixThreads), 0, s, ki, nvis, shift, hist, nblk,
                                overflow_dev);
             hipLaunchKernelGGL(k_rowscan<kScanThreads>, dim3(256), dim3(kScanThreads), 0, s, hist, nullptr, (uint32_t)nblk,
                                hist + (size_t)256 * nblk, overflow_dev);
-            if (shift < 24)
-                hipLaunchKernelGGL(k_radix_scatter<false>, dim3(nblk), dim3(kRadixThreads), 0, s, ki, vi, ko, vo, nvis,
-                                   shift, hist, nblk, overflow_dev, nullptr, nullptr, nullptr);
+            const bool last = shift == 24;
+            if (v64 && !last)
+                hipLaunchKernelGGL((k_radix_scatter<uint2, false>), dim3(nblk), dim3(kRadixThreads), 0, s, ki, wi, ko,
+                                   wo, nvis, shift, hist, nblk, overflow_dev, nullptr, nullptr, nullptr);
+            else if (v64)
+                hipLaunchKernelGGL((k_radix_scatter<uint2, true>), dim3(nblk), dim3(kRadixThreads), 0, s, ki, wi, ko,
+                                   wo, nvis, shift, hist, nblk, overflow_dev, nullptr, sid, sbox);
+            else if (!last)
+                hipLaunchKernelGGL((k_radix_scatter<uint32_t, false>), dim3(nblk), dim3(kRadixThreads), 0, s, ki, vi,
+                                   ko, vo, nvis, shift, hist, nblk, overflow_dev, nullptr, nullptr, nullptr);
             else
-                hipLaunchKernelGGL(k_radix_scatter<true>, dim3(nblk), dim3(kRadixThreads), 0, s, ki, vi, ko, vo, nvis,
-                                   shift, hist, nblk, overflow_dev, crec, sid, sbox);
+                hipLaunchKernelGGL((k_radix_scatter<uint32_t, true>), dim3(nblk), dim3(kRadixThreads), 0, s, ki, vi, ko,
+                                   vo, nvis, shift, hist, nblk, overflow_dev, crec, sid, sbox);
             std::swap(ki, ko);
             std::swap(vi, vo);
+            std::swap(wi, wo);
         }
         const int c1max = (n + kL1Threads - 1) / kL1Threads;
         const size_t lds1 = (size_t)nsuper * 4;
@@ -1224,7 +1281,7 @@ hipError_t launch_bin_sort(const darb_projected &p, int n, int width, int height
     if (n > 0) {
         const int c1max = (n + kL1Threads - 1) / kL1Threads;
         const size_t lds1 = (size_t)nsuper * 4;
-        hipLaunchKernelGGL(k_l1_scatter, dim3(c1max), dim3(kL1Threads), 9 * lds1, s, sid, sbox, sxn, nsuper, cnt, h1,
+        hipLaunchKernelGGL(k_l1_scatter, dim3(c1max), dim3(kL1Threads), 13 * lds1, s, sid, sbox, sxn, nsuper, cnt, h1,
                            gtot, list1, list1r, std::max<int64_t>(k_capacity, 1), overflow_dev);
     }
     hipLaunchKernelGGL(k_l2_plan, dim3(1), dim3(1024), 0, s, gtot, cnt, nsuper, sxn, gx, gy, l1start, l1len, c2start,

@@ -450,7 +450,7 @@ __global__ __launch_bounds__(256) void k_preprocess_geom(Cam cam, KParams kp, in
 // latency-bound binning kernels and slow them by about its own duration.
 constexpr int kColourThreads = 128;
 #ifndef DARB_COLOUR_WGS_PER_CU
-#define DARB_COLOUR_WGS_PER_CU 1
+#define DARB_COLOUR_WGS_PER_CU 2
 #endif
 constexpr int kColourWgsPerCu = DARB_COLOUR_WGS_PER_CU;  // workgroups per compute unit (a tuning constant)
 

@@ -40,8 +40,12 @@ def _values_only_matches(ps, K_o, vals_o, ranges_o):
     assert np.array_equal(to_np(fr.vals)[:K].view(np.uint32), vals_o)
 
 
+# (tile grids up to 255 x 255 carry the tile box through the depth sort in 8-bit
+# coordinates; 4080 px is the largest such width, 4100 and 4200 px take the
+# record gather instead)
 @pytest.mark.parametrize("n,W,H,seed", [(0, 64, 48, 1), (1, 16, 16, 2), (500, 200, 150, 3), (3000, 37, 21, 4),
-                                        (20000, 640, 360, 5), (5000, 1297, 840, 6)])
+                                        (20000, 640, 360, 5), (5000, 1297, 840, 6), (20000, 4080, 300, 7),
+                                        (20000, 4100, 300, 8), (8000, 200, 4200, 9)])
 def test_bin_sort_bit_exact(n, W, H, seed):
     print(f"bin_sort n={n} {W}x{H} seed={seed}", flush=True)
     ps = scenes.projected(seed, n, W, H, sigma_range=(0.3, 25.0))
