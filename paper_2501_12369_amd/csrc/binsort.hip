@@ -39,7 +39,10 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanBlock = kScanThreads * kScanItems;  // 2048 elements per block
 constexpr int kRadixThreads = 256;
-constexpr int kRadixItems = 16;
+#ifndef DARB_RADIX_ITEMS
+#define DARB_RADIX_ITEMS 16
+#endif
+constexpr int kRadixItems = DARB_RADIX_ITEMS;  // keys per thread of a radix tile
 constexpr int kRadixTile = kRadixThreads * kRadixItems;  // 4096 keys per block
 constexpr int kRadixWaves = kRadixThreads / 64;
 constexpr int kRadixWaveItems = kRadixTile / kRadixWaves;  // keys per wave (16 rounds of 64)
@@ -872,9 +875,17 @@ __device__ __forceinline__ void l2_colrow(const LRect &L, uint64_t (&colB)[kSupe
     }
 }
 
+// The lanes of one wavefront see each other's LDS writes: a wavefront's LDS
+// operations complete in order, so only the compiler has to keep them in place.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // wc[w * 64 + tl] = lanes of wave w covering tile tl (lane tl computes it from
 // the wave's masks in LDS; wave-major, so the lanes write distinct banks).
-// Needs a barrier between l2_colrow and this.
+// The masks are the wave's own: a wave_lds_sync between l2_colrow and this.
 __device__ __forceinline__ void l2_counts(const uint64_t *lds_masks, uint32_t *wc) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint64_t m = lds_masks[lane & (kSuper - 1)] & lds_masks[kSuper + lane / kSuper];
@@ -931,12 +942,15 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_count(const uint32_t *list1r,
                                                          const uint32_t *toff, int gx, int gy, int sxn, int nsuper,
                                                          const Counters *cnt, uint32_t *h2,
                                                          const int32_t *overflow_dev) {
-    __shared__ uint32_t wc[kSuper * kSuper * kL2Waves];
+    // wc is double-buffered by chunk parity: a wave may start the next chunk while
+    // wave 0 still sums this one's counts (one barrier per chunk)
+    __shared__ uint32_t wc[2][kSuper * kSuper * kL2Waves];
     __shared__ L2Tables T;
     __shared__ uint64_t masks[kL2Waves][2 * kSuper];
     if (*overflow_dev) return;
     const uint32_t total2 = cnt->total2;
     const int w = threadIdx.x >> 6, tl = threadIdx.x & 63;
+    int par = 0;
     const uint32_t G = gridDim.x;
     if (blockIdx.x >= total2) return;
     l2_load_tables(T, chunk2_start, l1_start, l1_len, nsuper);
@@ -949,19 +963,19 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_count(const uint32_t *list1r,
         const bool valid = threadIdx.x < cur.C.len;
         uint64_t colB[kSuper], rowB[kSuper];
         l2_colrow(l2_local_rect(valid, cur.packed), colB, rowB, masks[w]);
-        __syncthreads();
-        l2_counts(masks[w], wc);
+        wave_lds_sync();
+        l2_counts(masks[w], wc[par]);
         __syncthreads();
         uint32_t sum = 0;
         if (threadIdx.x < kSuper * kSuper && cur.tin)
-            for (int k = 0; k < kL2Waves; k++) sum += wc[k * 64 + tl];
+            for (int k = 0; k < kL2Waves; k++) sum += wc[par][k * 64 + tl];
         // the next chunk's loads land before this store (pinned on every path: a pin
         // under the same condition as the loads leaves the wait analysis a path with a
         // load in flight, and every later store would wait for it)
         pin_u32(nxt.packed, nxt.hoff);
         if (threadIdx.x < kSuper * kSuper && cur.tin) h2[cur.hoff + cur.C.c2] = sum;
-        __syncthreads();
         cur = nxt;
+        par ^= 1;
     }
 }
 
@@ -986,26 +1000,104 @@ __global__ __launch_bounds__(256) void k_bin_ranges(const uint32_t *base2, const
     tile_range(base2, toff, t, cnt, ranges);
 }
 
-// Stores id at byte offset 4 (s0 + rank of this lane among the lanes of m)
-// from base, for the lanes set in m.  exec is narrowed to m around the two
-// mbcnt, the address and the store and restored right after, so the store
-// costs four vector instructions (a compiler-generated lane test adds three
-// more and a second exec update).  The offset is 32-bit: callers keep
-// positions below 2^30.
-__device__ __forceinline__ void store_ranked(uint32_t *base, uint64_t m, uint32_t s0x4, uint32_t id) {
+// The ranked stores of one wave for all 64 tiles of its super-tile: for tile
+// (r, c) the covering lanes are colB[c] & rowB[r]; exec is set to that mask
+// directly (an empty mask skips the tile), the lane's rank is an mbcnt on exec,
+// and the run's first byte offset is lane tl of slot4 (this wave's first slot
+// in tile tl, times 4).  One scalar instruction and one branch per tile, four
+// vector instructions and a store per covered tile; exec is restored once at
+// the end (the compiled loop spent five scalar instructions per covered tile
+// and three per empty one).  The offsets are 32-bit: callers keep positions
+// below 2^30.
+#define L2_TILE(R, C, T)                                                 \
+    "s_and_b64 exec, %[c" C "], %[r" R "]\n\t"                           \
+    "s_cbranch_execz 1f\n\t"                                             \
+    "v_readlane_b32 %[s0], %[slot4], " T "\n\t"                          \
+    "v_mbcnt_lo_u32_b32 %[off], exec_lo, 0\n\t"                          \
+    "v_mbcnt_hi_u32_b32 %[off], exec_hi, %[off]\n\t"                     \
+    "v_lshl_add_u32 %[off], %[off], 2, %[s0]\n\t"                        \
+    "global_store_dword %[off], %[id], %[base]\n\t"                      \
+    "1:\n\t"
+
+__device__ __forceinline__ void store_all_tiles(uint32_t *base, const uint64_t (&colB)[kSuper],
+                                                const uint64_t (&rowB)[kSuper], uint32_t slot4, uint32_t id) {
     uint64_t saved;
-    uint32_t off;
+    uint32_t off, s0;
     asm volatile(
-        "s_and_saveexec_b64 %0, %2\n\t"
-        "v_mbcnt_lo_u32_b32 %1, %3, 0\n\t"
-        "v_mbcnt_hi_u32_b32 %1, %4, %1\n\t"
-        "v_lshl_add_u32 %1, %1, 2, %5\n\t"
-        "global_store_dword %1, %6, %7\n\t"
-        "s_mov_b64 exec, %0"
-        : "=&s"(saved), "=&v"(off)
-        : "s"(m), "s"((uint32_t)m), "s"((uint32_t)(m >> 32)), "s"(s0x4), "v"(id), "s"(base)
+        "s_mov_b64 %[saved], exec\n\t"
+    L2_TILE("0", "0", "0")
+    L2_TILE("0", "1", "1")
+    L2_TILE("0", "2", "2")
+    L2_TILE("0", "3", "3")
+    L2_TILE("0", "4", "4")
+    L2_TILE("0", "5", "5")
+    L2_TILE("0", "6", "6")
+    L2_TILE("0", "7", "7")
+    L2_TILE("1", "0", "8")
+    L2_TILE("1", "1", "9")
+    L2_TILE("1", "2", "10")
+    L2_TILE("1", "3", "11")
+    L2_TILE("1", "4", "12")
+    L2_TILE("1", "5", "13")
+    L2_TILE("1", "6", "14")
+    L2_TILE("1", "7", "15")
+    L2_TILE("2", "0", "16")
+    L2_TILE("2", "1", "17")
+    L2_TILE("2", "2", "18")
+    L2_TILE("2", "3", "19")
+    L2_TILE("2", "4", "20")
+    L2_TILE("2", "5", "21")
+    L2_TILE("2", "6", "22")
+    L2_TILE("2", "7", "23")
+    L2_TILE("3", "0", "24")
+    L2_TILE("3", "1", "25")
+    L2_TILE("3", "2", "26")
+    L2_TILE("3", "3", "27")
+    L2_TILE("3", "4", "28")
+    L2_TILE("3", "5", "29")
+    L2_TILE("3", "6", "30")
+    L2_TILE("3", "7", "31")
+    L2_TILE("4", "0", "32")
+    L2_TILE("4", "1", "33")
+    L2_TILE("4", "2", "34")
+    L2_TILE("4", "3", "35")
+    L2_TILE("4", "4", "36")
+    L2_TILE("4", "5", "37")
+    L2_TILE("4", "6", "38")
+    L2_TILE("4", "7", "39")
+    L2_TILE("5", "0", "40")
+    L2_TILE("5", "1", "41")
+    L2_TILE("5", "2", "42")
+    L2_TILE("5", "3", "43")
+    L2_TILE("5", "4", "44")
+    L2_TILE("5", "5", "45")
+    L2_TILE("5", "6", "46")
+    L2_TILE("5", "7", "47")
+    L2_TILE("6", "0", "48")
+    L2_TILE("6", "1", "49")
+    L2_TILE("6", "2", "50")
+    L2_TILE("6", "3", "51")
+    L2_TILE("6", "4", "52")
+    L2_TILE("6", "5", "53")
+    L2_TILE("6", "6", "54")
+    L2_TILE("6", "7", "55")
+    L2_TILE("7", "0", "56")
+    L2_TILE("7", "1", "57")
+    L2_TILE("7", "2", "58")
+    L2_TILE("7", "3", "59")
+    L2_TILE("7", "4", "60")
+    L2_TILE("7", "5", "61")
+    L2_TILE("7", "6", "62")
+    L2_TILE("7", "7", "63")
+        "s_mov_b64 exec, %[saved]\n\t"
+        : [saved] "=&s"(saved), [off] "=&v"(off), [s0] "=&s"(s0)
+        : [c0] "s"(colB[0]), [c1] "s"(colB[1]), [c2] "s"(colB[2]), [c3] "s"(colB[3]), [c4] "s"(colB[4]),
+          [c5] "s"(colB[5]), [c6] "s"(colB[6]), [c7] "s"(colB[7]), [r0] "s"(rowB[0]), [r1] "s"(rowB[1]),
+          [r2] "s"(rowB[2]), [r3] "s"(rowB[3]), [r4] "s"(rowB[4]), [r5] "s"(rowB[5]), [r6] "s"(rowB[6]),
+          [r7] "s"(rowB[7]), [slot4] "v"(slot4), [id] "v"(id), [base] "s"(base)
         : "memory");
 }
+#undef L2_TILE
 
 // The next chunk of the level-2 scatter: entries (splat index, local
 // rectangle) and this thread's (wave, tile) slot base.  The slot base is two
@@ -1037,13 +1129,15 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_scatter(const uint32_t *list1
                                                            int sxn, int nsuper, const Counters *cnt, int64_t k_capacity,
                                                            uint64_t *keys, uint32_t *vals, uint32_t *ranges,
                                                            const int32_t *overflow_dev) {
-    __shared__ uint32_t wc[kSuper * kSuper * kL2Waves];
-    __shared__ uint32_t slot[kSuper * kSuper * kL2Waves];
+    // wc is double-buffered by chunk parity: one barrier per chunk (a wave may
+    // start the next chunk while others still read this one's counts)
+    __shared__ uint32_t wc[2][kSuper * kSuper * kL2Waves];
     __shared__ L2Tables T;
     __shared__ uint64_t masks[kL2Waves][2 * kSuper];
     if (*overflow_dev) return;
     const uint32_t total2 = cnt->total2;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int par = 0;
     for (int t = blockIdx.x * kL2Threads + threadIdx.x; t < gx * gy; t += gridDim.x * kL2Threads)
         tile_range(base2, toff, t, cnt, ranges);
     const uint32_t G = gridDim.x;
@@ -1061,37 +1155,30 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_scatter(const uint32_t *list1
         const bool valid = threadIdx.x < cur.C.len;
         uint64_t colB[kSuper], rowB[kSuper];
         l2_colrow(l2_local_rect(valid, cur.packed), colB, rowB, masks[w]);
-        __syncthreads();
-        l2_counts(masks[w], wc);
+        wave_lds_sync();
+        l2_counts(masks[w], wc[par]);
         __syncthreads();
         const int tx0 = (cur.C.g % sxn) * kSuper, ty0 = (cur.C.g / sxn) * kSuper;
-        {
-            // thread (wave ww, tile tl): first slot of wave ww's entries in tile tl
-            static_assert(kSuper * kSuper * kL2Waves == kL2Threads, "one thread per (wave, tile)");
-            const int ww = threadIdx.x >> 6, tl = threadIdx.x & 63;
-            if (cur.tin) {
-                uint32_t sl = cur.sbase;
-                for (int k = 0; k < ww; k++) sl += wc[k * 64 + tl];
-                slot[threadIdx.x] = sl;
-            }
-        }
+        // lane tl: this wave's first slot in tile tl (broadcast per tile with v_readlane)
+        uint32_t myslot = cur.sbase;
+        for (int k = 0; k < w; k++) myslot += wc[par][k * 64 + lane];
         // the next chunk's slot base (its count offset has landed by now) and depth
         uint32_t dbn = 0;
         if (more) {
             nxt.sbase = base2[nxt.sbase + nxt.C.c2];
             if (!FAST && keys) dbn = __float_as_uint(depth[nxt.id]);
         }
-        __syncthreads();
-        // lane tl holds this wave's first slot in tile tl; broadcast per tile with v_readlane
-        const uint32_t myslot = slot[w * 64 + lane];
         bool inside = true;
         if constexpr (FAST) {
             // every run of this wave lies inside the capacity (K <= capacity is decided
             // before any instance is written; this test only guards the stores)
-            const uint32_t myc = wc[w * 64 + lane];
+            const uint32_t myc = wc[par][w * 64 + lane];
             inside = __ballot(myc != 0u && myslot + myc > cap32) == 0ull;
         }
         pin_u32(nxt.id, nxt.packed, nxt.sbase, dbn);  // the next chunk's loads land before the stores (every path)
+        if constexpr (FAST) {
+            if (inside) store_all_tiles(vals, colB, rowB, myslot << 2, cur.id);
+        } else
         for (int rr = 0; rr < kSuper; rr++) {
             if (rowB[rr] == 0ull || !inside) continue;  // no lane of this wave covers the row (uniform)
             for (int cc = 0; cc < kSuper; cc++) {
@@ -1099,9 +1186,7 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_scatter(const uint32_t *list1
                 if (m == 0ull) continue;
                 const int tl = rr * kSuper + cc;
                 const uint32_t s0 = (uint32_t)__builtin_amdgcn_readlane((int)myslot, tl);
-                if constexpr (FAST) {
-                    store_ranked(vals, m, s0 << 2, cur.id);
-                } else if ((m >> lane) & 1ull) {
+                if ((m >> lane) & 1ull) {
                     const uint32_t pos = s0 + rank_below(m);
                     if (pos < cap32) {
                         vals[pos] = cur.id;
@@ -1110,9 +1195,9 @@ __global__ __launch_bounds__(kL2Threads) void k_l2_scatter(const uint32_t *list1
                 }
             }
         }
-        __syncthreads();
         cur = nxt;
         db = dbn;
+        par ^= 1;
     }
 }
 
