@@ -118,15 +118,21 @@ class Frame:
 
 
 def alloc_frame(n: int, width: int, height: int, k_capacity: int, device="cuda", keys: bool = False,
-                n_contrib: bool = False, proj: dict | None = None, dcolor: bool = True) -> Frame:
+                n_contrib: bool = False, proj: dict | None = None, dcolor: bool = True,
+                ws: torch.Tensor | None = None) -> Frame:
+    """Buffers of one render.  ``ws``: a bin/sort workspace to use instead of a
+    new one (at least the size this frame needs); frames whose bin/sorts run one
+    after another on one stream can share it."""
     cap = max(int(k_capacity), 1)
     ws_bytes = native.darb_bin_sort_workspace(n, width, height, cap)
     if ws_bytes == 0:
         raise native.DarbError(native.DARB_ERR_UNSUPPORTED, f"unsupported size n={n} {width}x{height} cap={cap}")
+    if ws is not None and ws.numel() < ws_bytes:
+        raise ValueError(f"shared workspace of {ws.numel()} bytes, {ws_bytes} needed")
     T = n_tiles(width, height)
     return Frame(
         n=n, width=width, height=height, proj=proj if proj is not None else alloc_projected(n, device, dcolor),
-        ws=torch.empty(ws_bytes, dtype=torch.uint8, device=device),
+        ws=ws if ws is not None else torch.empty(ws_bytes, dtype=torch.uint8, device=device),
         vals=torch.empty(cap, dtype=torch.int32, device=device),
         ranges=torch.empty((T, 2), dtype=torch.int32, device=device),
         k_dev=torch.zeros(2, dtype=torch.int64, device=device),

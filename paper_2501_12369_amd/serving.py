@@ -304,15 +304,17 @@ class RenderSlot:
         pipeline = self.pipeline
         self.graphs = None
         self.frames = None
-        self.frames = [pipeline.alloc_frame(self.n, self.W, self.H, capacity, "cuda", dcolor=False)
-                       for _ in range(self.max_batch)]
+        # the batch's bin/sorts run one after another on the slot's stream: one workspace
+        first = pipeline.alloc_frame(self.n, self.W, self.H, capacity, "cuda", dcolor=False)
+        self.frames = [first] + [pipeline.alloc_frame(self.n, self.W, self.H, capacity, "cuda", dcolor=False,
+                                                      ws=first.ws) for _ in range(self.max_batch - 1)]
         for v, fr in enumerate(self.frames):  # per-view flags and counts in the slot's own arrays
             fr.overflow = self.ovf_dev[v]
             fr.k_dev = self.k_dev[v]
         self.views = [dict(cam=self.template, proj=fr.proj, k_capacity=fr.capacity, vals=fr.vals, ranges=fr.ranges,
                            overflow_dev=fr.overflow, image=fr.image, final_T=fr.final_T, last=fr.last)
                       for fr in self.frames]
-        self.nbytes = self.max_batch * self.server.slot_bytes(self.n, self.W, self.H, capacity)
+        self.nbytes = self.server.slot_bytes(self.n, self.W, self.H, capacity, self.max_batch)
         self._capture()
 
     def _enqueue(self, b: int):
@@ -420,11 +422,12 @@ class RenderServer:
                                max_slots, max_inflight=max_inflight)
 
     @staticmethod
-    def slot_bytes(n: int, W: int, H: int, capacity: int) -> int:
+    def slot_bytes(n: int, W: int, H: int, capacity: int, views: int = 1) -> int:
+        """Device bytes of a slot of ``views`` renders sharing one bin/sort workspace."""
         from . import native
 
-        return (native.darb_bin_sort_workspace(n, W, H, capacity) + 4 * capacity + 52 * n
-                + (3 + 1 + 1) * 4 * W * H + 8 * ((W + 15) // 16) * ((H + 15) // 16))
+        return (native.darb_bin_sort_workspace(n, W, H, capacity) + views * (
+            4 * capacity + 52 * n + (3 + 1 + 1) * 4 * W * H + 8 * ((W + 15) // 16) * ((H + 15) // 16)))
 
     def _capacity(self, key) -> int:
         if key not in self.cap_hint:
@@ -460,7 +463,7 @@ class RenderServer:
     def _need(self, key) -> int:
         scene_id, W, H = key
         n = int(self.scenes[scene_id]["means"].shape[1])
-        return self.max_batch * self.slot_bytes(n, W, H, self._capacity(key))
+        return self.slot_bytes(n, W, H, self._capacity(key), self.max_batch)
 
     def _make_slot(self, key, _hint):
         return RenderSlot(self, key, self._capacity(key))
