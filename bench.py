@@ -444,8 +444,8 @@ def multiview_bench(kernel_name: str, n: int, n_views: int, steps: int, warmup: 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--kernel", default="half_cos", choices=["half_cos", "gauss"])
     ap.add_argument("--n", type=int, default=3_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
