@@ -82,7 +82,8 @@ def lib():
         L.orc_kernel_derivs.argtypes = [i32, d, d, i64, vp, vp]
         L.orc_sh_basis.argtypes = [vp, vp, vp]
         L.orc_quat_to_rot.argtypes = [vp, vp]
-        L.orc_preprocess.argtypes = [vp, vp, i64, vp, vp, vp, vp, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.orc_preprocess.argtypes = [vp, vp, i64, vp, vp, vp, vp, ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, vp,
+                                     vp]
         L.orc_composite.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, i64, vp,
                                     ctypes.c_int, vp, vp, vp, vp, vp]
         L.orc_composite_bwd.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, i64, vp,
@@ -211,12 +212,14 @@ def preprocess(cam: Camera, k: KernelSpec, means, scales, quats, sh, deg: int) -
     """means/scales [3,n], quats [4,n], sh [(deg+1)^2, 3, n]."""
     means, scales, quats, sh = _f64(means), _f64(scales), _f64(quats), _f64(sh)
     n = means.shape[1]
-    out = dict(xy=np.zeros((n, 2)), depth=np.zeros(n), radius=np.zeros(n, np.int32), conic=np.zeros((n, 3)),
+    out = dict(xy=np.zeros((n, 2)), depth=np.zeros(n), radius=np.zeros(n, np.int32),
+               extent=np.zeros((n, 2), np.int32), conic=np.zeros((n, 3)),
                rgb=np.zeros((n, 3)), clamped=np.zeros(n, np.uint8), visible=np.zeros(n, np.int32),
                cov2d=np.zeros((n, 3)))
     kc = k.c()
     lib().orc_preprocess(ctypes.byref(cam), ctypes.byref(kc), n, _p(means), _p(scales), _p(quats), _p(sh), deg,
-                         _p(out["xy"]), _p(out["depth"]), _p(out["radius"]), _p(out["conic"]), _p(out["rgb"]),
+                         _p(out["xy"]), _p(out["depth"]), _p(out["radius"]), _p(out["extent"]), _p(out["conic"]),
+                         _p(out["rgb"]),
                          _p(out["clamped"]), _p(out["visible"]), _p(out["cov2d"]))
     return out
 
@@ -281,22 +284,23 @@ def preprocess_bwd(cam: Camera, k: KernelSpec, means, scales, quats, sh, deg: in
     return out
 
 
-def bin_sort(xy, radius, depth, width: int, height: int, cap: int | None = None):
-    """Binning reference on FP32 xy [n,2], int32 radius [n], FP32 depth [n].
+def bin_sort(xy, extent, depth, width: int, height: int, cap: int | None = None):
+    """Binning reference on FP32 xy [n,2], int32 tile-box half-extents [n,2]
+    (rx, ry; 0 = culled), FP32 depth [n].
 
     Returns (K, keys u64[K], vals u32[K], ranges u32[tiles,2])."""
     xy = np.ascontiguousarray(np.asarray(xy, dtype=np.float32))
-    radius = np.ascontiguousarray(np.asarray(radius, dtype=np.int32))
+    extent = np.ascontiguousarray(np.asarray(extent, dtype=np.int32).reshape(-1, 2))
     depth = np.ascontiguousarray(np.asarray(depth, dtype=np.float32))
     n = xy.shape[0]
     gx, gy = (width + 15) // 16, (height + 15) // 16
     ranges = np.zeros((gx * gy, 2), np.uint32)
-    K = lib().orc_bin(n, _p(xy), _p(radius), _p(depth), width, height, 0, None, None, _p(ranges))
+    K = lib().orc_bin(n, _p(xy), _p(extent), _p(depth), width, height, 0, None, None, _p(ranges))
     if cap is None:
         cap = K
     keys = np.zeros(max(K, 1), np.uint64)
     vals = np.zeros(max(K, 1), np.uint32)
-    K = lib().orc_bin(n, _p(xy), _p(radius), _p(depth), width, height, cap, _p(keys), _p(vals), _p(ranges))
+    K = lib().orc_bin(n, _p(xy), _p(extent), _p(depth), width, height, cap, _p(keys), _p(vals), _p(ranges))
     return K, keys[:K], vals[:K], ranges
 
 

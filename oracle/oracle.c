@@ -330,6 +330,7 @@ typedef struct {
     double xy[2];
     double depth;
     int radius;
+    int ext[2];    /* half-extents of the tile box: ceil(rf sqrt(cov_xx)), ceil(rf sqrt(cov_yy)) */
     double dir[3], vlen;
     double rgb[3];
     int clamped[3];
@@ -398,17 +399,25 @@ static void project_one(const orc_camera *cam, const orc_kernel *k, long n, long
     s->depth = tz;
 
     /* R = ceil(3 sqrt(lambda_max)) of the 2D covariance; a support beyond
-     * E = 9 (several pulses) widens the box to ceil(sqrt(e_max lambda_max)) */
+     * E = 9 (several pulses) widens it to ceil(sqrt(e_max lambda_max)) */
     double mid = 0.5 * (s->cov[0] + s->cov[3]);
     double disc = mid * mid - s->det;
     double lam = mid + sqrt(disc > 0.0 ? disc : 0.0);
     double rf = k->e_max > 9.0 ? sqrt(k->e_max) : 3.0;
     s->radius = (int)ceil(rf * sqrt(lam));
 
-    /* bounding rectangle on the 16x16 tile grid; empty => not visible */
+    /* Tile box: the bounding box of the ellipse {d : d^T Sigma'^-1 d <= rf^2},
+     * whose half-extents are rf sqrt(Sigma'_xx) and rf sqrt(Sigma'_yy) (the
+     * largest |d_x| on that ellipse), rounded up to whole pixels.  It holds the
+     * support E <= e_max and lies inside the paper's square of half-side R;
+     * the image does not depend on the box (every pixel tests E itself). */
+    s->ext[0] = (int)ceil(rf * sqrt(s->cov[0]));
+    s->ext[1] = (int)ceil(rf * sqrt(s->cov[3]));
+
+    /* tile rectangle of that box on the 16x16 grid; empty => not visible */
     int gx = (cam->width + 15) / 16, gy = (cam->height + 15) / 16;
-    double x0 = floor((s->xy[0] - s->radius) / 16.0), x1 = floor((s->xy[0] + s->radius) / 16.0) + 1.0;
-    double y0 = floor((s->xy[1] - s->radius) / 16.0), y1 = floor((s->xy[1] + s->radius) / 16.0) + 1.0;
+    double x0 = floor((s->xy[0] - s->ext[0]) / 16.0), x1 = floor((s->xy[0] + s->ext[0]) / 16.0) + 1.0;
+    double y0 = floor((s->xy[1] - s->ext[1]) / 16.0), y1 = floor((s->xy[1] + s->ext[1]) / 16.0) + 1.0;
     x0 = x0 < 0 ? 0 : (x0 > gx ? gx : x0);
     x1 = x1 < 0 ? 0 : (x1 > gx ? gx : x1);
     y0 = y0 < 0 ? 0 : (y0 > gy ? gy : y0);
@@ -435,12 +444,13 @@ static void project_one(const orc_camera *cam, const orc_kernel *k, long n, long
 /*
  * orc_preprocess: per-splat projection.  Inputs SoA ([3][n], [4][n], [n],
  * [(deg+1)^2][3][n]).  Outputs: xy[n][2], depth[n], radius[n] (0 = culled),
+ * extent[n][2] (half-extents of the tile box in pixels, 0 = culled),
  * conic[n][3], rgb[n][3], clamped[n] (bit c set when channel c is clamped),
  * visible[n], cov2d[n][3] (nullable; a, b, c of Sigma'_{2x2}).
  */
 void orc_preprocess(const orc_camera *cam, const orc_kernel *k, long n, const double *means,
                     const double *scales, const double *quats, const double *sh, int deg,
-                    double *xy, double *depth, int32_t *radius, double *conic, double *rgb,
+                    double *xy, double *depth, int32_t *radius, int32_t *extent, double *conic, double *rgb,
                     uint8_t *clamped, int32_t *visible, double *cov2d) {
 #pragma omp parallel for schedule(static)
     for (long i = 0; i < n; i++) {
@@ -451,6 +461,8 @@ void orc_preprocess(const orc_camera *cam, const orc_kernel *k, long n, const do
         xy[2 * i + 1] = s.visible ? s.xy[1] : 0.0;
         depth[i] = s.visible ? s.depth : 0.0;
         radius[i] = s.visible ? s.radius : 0;
+        extent[2 * i] = s.visible ? s.ext[0] : 0;
+        extent[2 * i + 1] = s.visible ? s.ext[1] : 0;
         for (int c = 0; c < 3; c++) {
             conic[3 * i + c] = s.visible ? s.conic[c] : 0.0;
             rgb[3 * i + c] = s.visible ? s.rgb[c] : 0.0;
@@ -931,8 +943,8 @@ static int clamp_tile(float v, int hi) {
 }
 
 /*
- * orc_bin: every splat with radius > 0 covers the tiles
- *   x in [clamp(floor((u - R) / 16)), clamp(floor((u + R) / 16) + 1)), same for y,
+ * orc_bin: every splat with half-extents (rx, ry) > 0 covers the tiles
+ *   x in [clamp(floor((u - rx) / 16)), clamp(floor((u + rx) / 16) + 1)), same for y with ry,
  * evaluated in FP32; one entry per covered tile with key (tile << 32) | bits(depth)
  * and value = splat index.  Entries are ordered by (key, index).  ranges[t] =
  * (#entries with tile < t, #entries with tile <= t).  Returns K; keys/vals are
@@ -942,7 +954,7 @@ static int clamp_tile(float v, int hi) {
  * grouped by tile (the high half of the key) and each tile's group is then
  * sorted on its own, which is the same total order.
  */
-long orc_bin(long n, const float *xy, const int32_t *radius, const float *depth, int width, int height, long cap,
+long orc_bin(long n, const float *xy, const int32_t *extent, const float *depth, int width, int height, long cap,
              uint64_t *keys, uint32_t *vals, uint32_t *ranges) {
     int gx = (width + 15) / 16, gy = (height + 15) / 16;
     long ntile = (long)gx * gy;
@@ -951,12 +963,12 @@ long orc_bin(long n, const float *xy, const int32_t *radius, const float *depth,
     long *cnt = (long *)calloc(ntile + 1, sizeof(long));
     for (long i = 0; i < n; i++) {
         rect[4 * i] = rect[4 * i + 1] = rect[4 * i + 2] = rect[4 * i + 3] = 0;
-        if (radius[i] <= 0) continue;
-        float u = xy[2 * i], v = xy[2 * i + 1], r = (float)radius[i];
-        rect[4 * i] = clamp_tile(floorf((u - r) * 0.0625f), gx);
-        rect[4 * i + 1] = clamp_tile(floorf((u + r) * 0.0625f) + 1.0f, gx);
-        rect[4 * i + 2] = clamp_tile(floorf((v - r) * 0.0625f), gy);
-        rect[4 * i + 3] = clamp_tile(floorf((v + r) * 0.0625f) + 1.0f, gy);
+        if (extent[2 * i] <= 0 || extent[2 * i + 1] <= 0) continue;
+        float u = xy[2 * i], v = xy[2 * i + 1], rx = (float)extent[2 * i], ry = (float)extent[2 * i + 1];
+        rect[4 * i] = clamp_tile(floorf((u - rx) * 0.0625f), gx);
+        rect[4 * i + 1] = clamp_tile(floorf((u + rx) * 0.0625f) + 1.0f, gx);
+        rect[4 * i + 2] = clamp_tile(floorf((v - ry) * 0.0625f), gy);
+        rect[4 * i + 3] = clamp_tile(floorf((v + ry) * 0.0625f) + 1.0f, gy);
         long w = rect[4 * i + 1] - rect[4 * i], h = rect[4 * i + 3] - rect[4 * i + 2];
         if (w <= 0 || h <= 0) continue;
         K += w * h;

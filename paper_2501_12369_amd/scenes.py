@@ -190,8 +190,10 @@ def projected(seed: int, n: int, width: int, height: int, sigma_range=(0.5, 12.0
     stored as (a, b, c, opacity); ``conic_l`` holds its upper-triangular
     factor (l00, l01, l11), Q = L^T L.  ``radius`` is ceil(3 * max(s1, s2)) + 1
     pixels, a bound on the support E <= 9 of the one-lobe kernels (with a
-    larger support ``e_max``: sqrt(e_max) instead of 3); a fraction
-    ``culled_frac`` of splats get radius 0 (culled)."""
+    larger support ``e_max``: sqrt(e_max) instead of 3); ``extent`` [n, 2] is
+    the tile box's half-width and half-height, ceil(3 sqrt(cov_xx)) + 1 and
+    ceil(3 sqrt(cov_yy)) + 1 of the drawn covariance (same factor); a fraction
+    ``culled_frac`` of splats get radius and extent 0 (culled)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     x = rng.uniform(-margin, width + margin, size=n)
     y = rng.uniform(-margin, height + margin, size=n)
@@ -207,13 +209,21 @@ def projected(seed: int, n: int, width: int, height: int, sigma_range=(0.5, 12.0
     opacity = rng.uniform(opacity_range[0], opacity_range[1], size=n)
     rgb = rng.uniform(0.0, 1.0, size=(n, 3))
     depth = rng.uniform(depth_range[0], depth_range[1], size=n)
-    radius = (np.ceil(math.sqrt(max(9.0, e_max)) * np.maximum(s1, s2)) + 1).astype(np.int32)
-    radius[rng.uniform(size=n) < culled_frac] = 0
+    rf = math.sqrt(max(9.0, e_max))
+    radius = (np.ceil(rf * np.maximum(s1, s2)) + 1).astype(np.int32)
+    # covariance R diag(s1^2, s2^2) R^T: diagonal entries
+    cxx = c * c * s1 ** 2 + s * s * s2 ** 2
+    cyy = s * s * s1 ** 2 + c * c * s2 ** 2
+    extent = (np.ceil(rf * np.sqrt(np.stack([cxx, cyy], 1))) + 1).astype(np.int32)
+    culled = rng.uniform(size=n) < culled_frac
+    radius[culled] = 0
+    extent[culled] = 0
     l00 = np.sqrt(qa)
     l01 = qb / l00
     l11 = np.sqrt(i1 * i2 / qa)  # c - b^2/a = det Q / a
     f32 = np.float32
     return dict(xy=np.ascontiguousarray(np.stack([x, y], 1), f32), depth=depth.astype(f32), radius=radius,
+                extent=np.ascontiguousarray(extent),
                 conic_o=np.ascontiguousarray(np.stack([qa, qb, qc, opacity], 1), f32),
                 conic_l=np.ascontiguousarray(np.stack([l00, l01, l11], 1), f32),
                 rgb=np.ascontiguousarray(rgb, f32), width=int(width), height=int(height))

@@ -113,17 +113,17 @@ def test_grid_prefilter_equals_brute_force(orc):
 
 def _brute_bin(ps, W, H):
     """Every (splat, tile) pair tested directly: tile column tx is covered iff
-    16 tx <= fl(u + R) and fl(u - R) < 16 (tx + 1) (FP32), likewise rows."""
+    16 tx <= fl(u + rx) and fl(u - rx) < 16 (tx + 1) (FP32), likewise rows with ry."""
     gx, gy = (W + 15) // 16, (H + 15) // 16
     ent = []
     f32 = np.float32
-    for i in range(len(ps["radius"])):
-        R = ps["radius"][i]
-        if R <= 0:
+    for i in range(len(ps["extent"])):
+        rx, ry = ps["extent"][i]
+        if rx <= 0 or ry <= 0:
             continue
         u, v = ps["xy"][i]
-        lo_x, hi_x = f32(u) - f32(R), f32(u) + f32(R)
-        lo_y, hi_y = f32(v) - f32(R), f32(v) + f32(R)
+        lo_x, hi_x = f32(u) - f32(rx), f32(u) + f32(rx)
+        lo_y, hi_y = f32(v) - f32(ry), f32(v) + f32(ry)
         dbits = int(np.float32(ps["depth"][i]).view(np.uint32))
         for ty in range(gy):
             if not (f32(16 * ty) <= hi_y and lo_y < f32(16 * (ty + 1))):
@@ -139,7 +139,7 @@ def _brute_bin(ps, W, H):
 def test_binning_reference_matches_brute_force(orc, W, H):
     ps = scenes.projected(13, 500, W, H, sigma_range=(0.3, 15.0))
     ps["depth"][::7] = ps["depth"][3]  # equal depths: ties must keep index order
-    K, keys, vals, ranges = orc.bin_sort(ps["xy"], ps["radius"], ps["depth"], W, H)
+    K, keys, vals, ranges = orc.bin_sort(ps["xy"], ps["extent"], ps["depth"], W, H)
     ent, ntile = _brute_bin(ps, W, H)
     assert K == len(ent)
     want_keys = np.array([(t << 32) | d for t, d, _ in ent], np.uint64)
@@ -154,7 +154,7 @@ def test_binning_reference_matches_brute_force(orc, W, H):
 def test_binning_covers_support(orc):
     W, H = 120, 90
     ps = scenes.projected(14, 200, W, H, culled_frac=0.0)
-    K, keys, vals, ranges = orc.bin_sort(ps["xy"], ps["radius"], ps["depth"], W, H)
+    K, keys, vals, ranges = orc.bin_sort(ps["xy"], ps["extent"], ps["depth"], W, H)
     gx = (W + 15) // 16
     covered = set((int(k >> np.uint64(32)), int(v)) for k, v in zip(keys, vals))
     for i in range(200):
@@ -167,6 +167,6 @@ def test_binning_covers_support(orc):
 
 def test_binning_capacity_overflow(orc):
     ps = scenes.projected(15, 100, 64, 64)
-    K, _, _, _ = orc.bin_sort(ps["xy"], ps["radius"], ps["depth"], 64, 64)
-    K2, keys, vals, ranges = orc.bin_sort(ps["xy"], ps["radius"], ps["depth"], 64, 64, cap=K - 1)
+    K, _, _, _ = orc.bin_sort(ps["xy"], ps["extent"], ps["depth"], 64, 64)
+    K2, keys, vals, ranges = orc.bin_sort(ps["xy"], ps["extent"], ps["depth"], 64, 64, cap=K - 1)
     assert K2 == K  # K is still reported; nothing is written beyond capacity

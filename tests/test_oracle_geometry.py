@@ -169,6 +169,79 @@ def test_psi_and_dilation_enter_linearly(orc):
         assert p2["radius"][i] == math.ceil(3 * math.sqrt(lam))
 
 
+def _ellipse_reach(C, rf=3.0, m=20000):
+    """Largest |d_x| and |d_y| on the ellipse d^T C^-1 d = rf^2, by sampling its
+    boundary d = rf Lc (cos t, sin t) with Lc numpy's Cholesky factor of C."""
+    Lc = np.linalg.cholesky(C)
+    t = np.linspace(0.0, 2 * PI, m, endpoint=False)
+    d = rf * Lc @ np.stack([np.cos(t), np.sin(t)])
+    return np.abs(d[0]).max(), np.abs(d[1]).max()
+
+
+def test_tile_box_is_the_support_ellipse_bounding_box(orc):
+    """The tile box's half-extents are the reach of the ellipse E = 9 along x
+    and y rounded up to whole pixels (sampled boundary, within its sampling
+    error), inside the paper's square of half-side R = ceil(3 sqrt(lambda_max));
+    with a support beyond E = 9 (two pulses) the factor is sqrt(e_max)."""
+    sc = scenes.object_scale(seed=7, n=300, width=320, height=320)
+    sp = sc["splats"]
+    cam = orc.camera_from_scene(sc["camera"])
+    args = dict(means=sp["means"], scales=sp["scales"], quats=sp["quats"], sh=sp["sh"], deg=3)
+    checked = 0
+    for e_max in (9.0, 25.0):
+        p = orc.preprocess(cam, orc.KernelSpec(oracle.HALF_COS, 18 / PI, 1.36, e_max), **args)
+        rf = math.sqrt(max(9.0, e_max))
+        for i in np.flatnonzero(p["visible"])[:60]:
+            C = np.array([[p["cov2d"][i, 0], p["cov2d"][i, 1]], [p["cov2d"][i, 1], p["cov2d"][i, 2]]])
+            rx, ry = _ellipse_reach(C, rf)
+            ex, ey = p["extent"][i]
+            for reach, e in ((rx, ex), (ry, ey)):
+                if abs(reach - round(reach)) < 1e-6 * reach:
+                    continue  # an integer reach: the sampled boundary cannot decide the rounding
+                assert e - 1 < reach * (1 + 1e-7) and reach * (1 - 1e-7) <= e
+            assert ex <= p["radius"][i] and ey <= p["radius"][i]
+            checked += 1
+    assert checked > 60
+
+
+def test_culling_by_the_tile_box(orc):
+    """A splat whose ellipse box misses the tile grid is culled even where the
+    paper's square of half-side R would reach it, and no pixel of the image lies
+    in such a splat's support (brute force over the image with the FP64 conic)."""
+    W, H = 96, 64
+    rng = np.random.default_rng(3)
+    n = 400
+    # tall, thin splats just left of the image: the x reach is small, R is large
+    z = rng.uniform(3.0, 6.0, n)
+    u = rng.uniform(-40.0, -2.0, n)
+    v = rng.uniform(0.0, H, n)
+    f = 80.0
+    means = np.stack([(u - W / 2) * z / f, (v - H / 2) * z / f, z]).astype(np.float32)
+    scales = np.stack([rng.uniform(0.005, 0.02, n), rng.uniform(0.3, 0.8, n), rng.uniform(0.005, 0.02, n)])
+    quats = np.tile(np.array([[1.0], [0.0], [0.0], [0.0]]), (1, n))
+    sh = np.zeros((1, 3, n), np.float32)
+    cam = orc.make_camera(np.eye(4), np.zeros(3), f, f, W / 2, H / 2, W, H)
+    p = orc.preprocess(cam, orc.KernelSpec(oracle.HALF_COS, 18 / PI, 1.36, 9.0), means,
+                       scales.astype(np.float32), quats.astype(np.float32), sh, 0)
+    culled_by_box = 0
+    ys, xs = np.mgrid[0:H, 0:W]
+    for i in range(n):
+        a, b, c = p["cov2d"][i]
+        det = a * c - b * b
+        if not det > 0:
+            continue
+        lam = 0.5 * (a + c) + math.sqrt(max(0.25 * (a + c) ** 2 - det, 0.0))
+        R = math.ceil(3 * math.sqrt(lam))
+        x = means[0, i] / means[2, i] * f + W / 2
+        square_reaches = math.floor((np.float64(x) + R) / 16) + 1 > 0
+        if p["visible"][i] == 0 and square_reaches:
+            culled_by_box += 1
+            dx, dy = x - xs, (means[1, i] / means[2, i] * f + H / 2) - ys
+            E = (c * dx * dx - 2 * b * dx * dy + a * dy * dy) / det
+            assert (E > 9.0).all()
+    assert culled_by_box > 20
+
+
 def test_sh_colour_matches_scipy_basis(orc):
     sc = scenes.object_scale(seed=6, n=64, width=320, height=320)
     sp = sc["splats"]
