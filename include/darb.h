@@ -40,7 +40,7 @@ extern "C" {
 #define DARB_API
 #endif
 
-#define DARB_ABI_VERSION 6
+#define DARB_ABI_VERSION 7
 #define DARB_TILE 16
 #define DARB_MAX_VIEWS 16       /* views per multi-view call */
 #define DARB_LOSS_WS_BYTES 4096 /* workspace of darb_image_loss */
@@ -85,9 +85,9 @@ typedef enum {
 /* A DARBF: profile, scale, correction factor and support.
  * psi multiplies the projected 2x2 covariance (Eq. of the 2x2 covariance
  * projection; Table 2).  A pixel is inside the footprint iff 0 <= E <= e_max
- * (boundaries of DARBFs: one main lobe, or n pulses).  The binning radius is
+ * (boundaries of DARBFs: one main lobe, or n pulses).  The radius is
  * 3 sqrt(lambda_max) (DARB-Splatting section), widened to
- * sqrt(e_max lambda_max) when e_max > 9.  The fixed kinds 0..6 require
+ * sqrt(e_max lambda_max) when e_max > 9; the tile box uses the same factor.  The fixed kinds 0..6 require
  * 0 < e_max <= 9 and, for the trigonometric ones, a support inside the main
  * lobe (E/xi <= pi/2 for DARB_HALF_COS, sqrt(E)/xi <= pi for DARB_RAISED_COS
  * and DARB_SINC); the modified kinds 7..10 take 0 < beta <= 8 and
@@ -148,6 +148,11 @@ typedef struct {
  *   xy       [n][2]   projected mean mu' in pixels
  *   depth    [n]      camera-space t_z
  *   radius   [n]      ceil(3 sqrt(lambda_max)) in pixels; 0 = culled (other fields undefined)
+ *   extent   [n][2]   int32 (rx, ry): half-width and half-height of the tile box, the
+ *                     bounding box of the ellipse d^T Sigma'^-1 d <= 9 (the support
+ *                     E <= 9; sqrt(e_max) in place of 3 for a support beyond E = 9):
+ *                     ceil(3 sqrt(Sigma'_xx)), ceil(3 sqrt(Sigma'_yy)) <= radius; 0 = culled.
+ *                     A splat is culled when this box misses the tile grid.
  *   conic_o  [n][4]   (l00, l01, l11, opacity): the conic Q = [[a, b], [b, c]] (inverse 2D
  *                     covariance) as its factor Q = L^T L, L = [[l00, l01], [0, l11]]
  *                     (l00, l11 > 0), so that E = |L d|^2 is a sum of squares
@@ -162,6 +167,7 @@ typedef struct {
     float *xy;
     float *depth;
     int32_t *radius;
+    int32_t *extent;
     float *conic_o;
     float *rgb;
     uint8_t *clamped;
@@ -218,7 +224,9 @@ DARB_API const char *darb_last_error(void);
  * (cull t_z <= near_z); affine Jacobian J at t; Sigma'_2x2 = psi [J R_cw Sigma
  * R_cw^T J^T]_2x2 + dilation I (cull det <= 0); Q = Sigma'_2x2^-1;
  * mu' = (fx t_x/t_z + cx, fy t_y/t_z + cy); radius = ceil(3 sqrt(lambda_max));
- * cull when the radius box covers no tile; rgb = max(0, sum SH * Y(dir) + 0.5)
+ * tile box half-extents ceil(3 sqrt(Sigma'_xx)), ceil(3 sqrt(Sigma'_yy)) (the
+ * bounding box of the support ellipse, inside the radius square); cull when
+ * the tile box covers no tile; rgb = max(0, sum SH * Y(dir) + 0.5)
  * with dir = (mu - campos)/|mu - campos|.  `in` fields are read; every `out`
  * field is written.  n = 0 is a no-op.
  */
@@ -229,7 +237,7 @@ DARB_API darb_status darb_preprocess(const darb_camera *cam, const darb_kernel *
  * darb_preprocess_parts -- darb_preprocess split in two launches with the same
  * arithmetic (together they write the same bits):
  *   DARB_PRE_GEOMETRY  reads means, scales, quats, opacity; writes xy, depth,
- *                      radius and conic_o (what darb_bin_sort reads);
+ *                      radius, extent and conic_o (what darb_bin_sort reads);
  *   DARB_PRE_COLOUR    reads radius (written by the geometry part for the same
  *                      camera and splats: a splat is kept iff radius > 0), means
  *                      and sh; writes rgb, clamped and dcolor (when non-null).
@@ -265,9 +273,9 @@ DARB_API size_t darb_bin_sort_workspace(int64_t n, int32_t width, int32_t height
 
 /*
  * darb_bin_sort -- tile binning and depth sort ("tile-based rasterization"
- * with the radius box, DARBF boundaries section).  Every splat with
- * radius > 0 is duplicated into every 16x16 tile of the box
- *   x in [clamp(floor((u - R)/16)), clamp(floor((u + R)/16) + 1)),  same for y,
+ * with the bounding box, DARBF boundaries section).  Every splat with
+ * extent (rx, ry) > 0 is duplicated into every 16x16 tile of its box
+ *   x in [clamp(floor((u - rx)/16)), clamp(floor((u + rx)/16) + 1)),  same for y with ry,
  * (FP32, clamped to the tile grid); each instance has key (tile << 32) |
  * bits(depth) and value = splat index.  Instances are ordered by (key, index):
  * per tile, front to back, equal depths by index -- a unique order.
@@ -275,7 +283,7 @@ DARB_API size_t darb_bin_sort_workspace(int64_t n, int32_t width, int32_t height
  *   vals      [k_capacity] u32 splat indices in sorted order
  *   ranges    [tiles][2]  u32: ranges[t] = (#instances with tile < t, #instances with tile <= t)
  *   k_dev     [2] int64 device: K, the number of instances, and N_v, the number of
- *             splats with radius > 0 whose box covers a tile (always written)
+ *             splats with extent > 0 whose box covers a tile (always written)
  *   overflow_dev [1] int32 device: 1 when K > k_capacity, else 0 (always written);
  *             with overflow set keys, vals and ranges are not written and the
  *             raster calls given the same flag do nothing
@@ -285,7 +293,7 @@ DARB_API size_t darb_bin_sort_workspace(int64_t n, int32_t width, int32_t height
  *   ws/ws_bytes  workspace of at least darb_bin_sort_workspace(n, width, height, k_capacity) bytes
  * tiles = ceil(width/16) * ceil(height/16) must be <= 16384, and the number of
  * 8x8-tile groups ceil(tiles_x/8) * ceil(tiles_y/8) <= 1024.
- * Splats with radius > 0 must have a finite positive depth.
+ * Splats with extent > 0 must have a finite positive depth.
  */
 DARB_API darb_status darb_bin_sort(const darb_projected *proj, int64_t n, int32_t width, int32_t height, int64_t k_capacity,
                           void *ws, size_t ws_bytes, uint64_t *keys, uint32_t *vals, uint32_t *ranges, int64_t *k_dev,

@@ -161,6 +161,7 @@ darb_status check_projected(const darb_projected *p, int64_t n, bool need_all) {
     REQUIRE_PTR(p->xy);
     REQUIRE_PTR(p->depth);
     REQUIRE_PTR(p->radius);
+    REQUIRE_PTR(p->extent);
     if (need_all) {
         REQUIRE_PTR(p->conic_o);
         REQUIRE_PTR(p->rgb);

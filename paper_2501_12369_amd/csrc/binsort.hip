@@ -5,7 +5,7 @@
 // K-sized array is written once, by runs of consecutive lanes (whole cache
 // lines: partial-line stores to HBM3E turn into read-modify-writes):
 //
-//   keys      one thread per splat: radius box on the 16x16 tile grid, per-block
+//   keys      one thread per splat: tile box on the 16x16 tile grid, per-block
 //             visible counts and box areas.  K (sum of the areas) is known here,
 //             so the capacity overflow is decided before any instance is written.
 //   compact   visible splats -> (depth bits, index) in index order.
@@ -23,7 +23,7 @@
 //             (chunk, tile) run written contiguously.
 //
 // Ranks come from ballots in lane order, so every step is stable and the result
-// is unique.  The radius box is recomputed from (xy, radius) with the same FP32
+// is unique.  The tile box is recomputed from (xy, extent) with the same FP32
 // expression everywhere.  HBM-bound.
 #include <algorithm>
 
@@ -64,12 +64,14 @@ struct Counters {
     unsigned long long K;
 };
 
-__device__ __forceinline__ int4 tile_rect(float u, float v, int radius, int gx, int gy) {
-    float r = (float)radius;
-    int x0 = (int)fminf(fmaxf(floorf((u - r) * 0.0625f), 0.0f), (float)gx);
-    int x1 = (int)fminf(fmaxf(floorf((u + r) * 0.0625f) + 1.0f, 0.0f), (float)gx);
-    int y0 = (int)fminf(fmaxf(floorf((v - r) * 0.0625f), 0.0f), (float)gy);
-    int y1 = (int)fminf(fmaxf(floorf((v + r) * 0.0625f) + 1.0f, 0.0f), (float)gy);
+// Tile rectangle [x0, x1) x [y0, y1) of a box of half-extents e = (rx, ry)
+// around (u, v), clamped to the grid.
+__device__ __forceinline__ int4 tile_rect(float u, float v, int2 e, int gx, int gy) {
+    const float rx = (float)e.x, ry = (float)e.y;
+    int x0 = (int)fminf(fmaxf(floorf((u - rx) * 0.0625f), 0.0f), (float)gx);
+    int x1 = (int)fminf(fmaxf(floorf((u + rx) * 0.0625f) + 1.0f, 0.0f), (float)gx);
+    int y0 = (int)fminf(fmaxf(floorf((v - ry) * 0.0625f), 0.0f), (float)gy);
+    int y1 = (int)fminf(fmaxf(floorf((v + ry) * 0.0625f) + 1.0f, 0.0f), (float)gy);
     return make_int4(x0, x1, y0, y1);
 }
 
@@ -431,22 +433,22 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t 
 
 // Per block of kKeyTile splats (kKeyItems per thread, all loads issued
 // together): number of visible splats and the sum of their box areas.
-__global__ __launch_bounds__(256) void k_bin_keys(const float *xy, const int32_t *radius, int n, int gx, int gy,
+__global__ __launch_bounds__(256) void k_bin_keys(const float *xy, const int2 *extent, int n, int gx, int gy,
                                                   uint32_t *block_vis, uint32_t *block_area) {
     __shared__ uint32_t wv[4], wa[4];
     const int base = blockIdx.x * kKeyTile + threadIdx.x;
-    int R[kKeyItems];
+    int2 R[kKeyItems];
     float2 p[kKeyItems];
 #pragma unroll
     for (int k = 0; k < kKeyItems; k++) {
         const int i = base + k * 256;
-        R[k] = i < n ? radius[i] : 0;
+        R[k] = i < n ? extent[i] : make_int2(0, 0);
         p[k] = i < n ? reinterpret_cast<const float2 *>(xy)[i] : make_float2(0.0f, 0.0f);
     }
     uint32_t vis = 0, area = 0;
 #pragma unroll
     for (int k = 0; k < kKeyItems; k++) {
-        if (R[k] <= 0) continue;
+        if ((R[k].x <= 0) | (R[k].y <= 0)) continue;
         const int4 r = tile_rect(p[k].x, p[k].y, R[k], gx, gy);
         if ((r.y > r.x) & (r.w > r.z)) {
             vis++;
@@ -526,7 +528,7 @@ __global__ __launch_bounds__(1024) void k_bin_sizes(uint32_t *block_vis, const u
 // V64 (tile grids of at most 255 x 255): the value is (splat index, box with
 // 8-bit tile coordinates) and no record is written; the sort carries it.
 template <bool V64>
-__global__ __launch_bounds__(256) void k_bin_compact(const float *xy, const int32_t *radius, const float *depth, int n,
+__global__ __launch_bounds__(256) void k_bin_compact(const float *xy, const int2 *extent, const float *depth, int n,
                                                      int gx, int gy, const uint32_t *block_off, uint32_t *keys,
                                                      uint32_t *vals, uint4 *crec, uint2 *vals64,
                                                      const int32_t *overflow_dev) {
@@ -534,7 +536,7 @@ __global__ __launch_bounds__(256) void k_bin_compact(const float *xy, const int3
     if (*overflow_dev) return;
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int base = blockIdx.x * kKeyTile + threadIdx.x;
-    int R[kKeyItems];
+    int2 R[kKeyItems];
     float2 p[kKeyItems];
     uint32_t db[kKeyItems];
     // every load issued up front: in the store loop below a load would wait for
@@ -542,7 +544,7 @@ __global__ __launch_bounds__(256) void k_bin_compact(const float *xy, const int3
 #pragma unroll
     for (int k = 0; k < kKeyItems; k++) {
         const int i = base + k * 256;
-        R[k] = i < n ? radius[i] : 0;
+        R[k] = i < n ? extent[i] : make_int2(0, 0);
         p[k] = i < n ? reinterpret_cast<const float2 *>(xy)[i] : make_float2(0.0f, 0.0f);
         db[k] = i < n ? __float_as_uint(depth[i]) : 0u;
     }
@@ -552,7 +554,7 @@ __global__ __launch_bounds__(256) void k_bin_compact(const float *xy, const int3
     for (int k = 0; k < kKeyItems; k++) {
         rect[k] = make_int4(0, 0, 0, 0);
         bool vis = false;
-        if (R[k] > 0) {
+        if ((R[k].x > 0) & (R[k].y > 0)) {
             rect[k] = tile_rect(p[k].x, p[k].y, R[k], gx, gy);
             vis = (rect[k].y > rect[k].x) & (rect[k].w > rect[k].z);
         }
@@ -1310,7 +1312,8 @@ hipError_t launch_bin_sort(const darb_projected &p, int n, int width, int height
     hipError_t e;
 
     const int nkb = (n + kKeyTile - 1) / kKeyTile;
-    if (n > 0) hipLaunchKernelGGL(k_bin_keys, dim3(nkb), dim3(256), 0, s, p.xy, p.radius, n, gx, gy, blockvis, blockarea);
+    const int2 *ext = reinterpret_cast<const int2 *>(p.extent);
+    if (n > 0) hipLaunchKernelGGL(k_bin_keys, dim3(nkb), dim3(256), 0, s, p.xy, ext, n, gx, gy, blockvis, blockarea);
     hipLaunchKernelGGL(k_bin_sizes, dim3(1), dim3(1024), 0, s, blockvis, blockarea, nkb, cnt, k_capacity, k_dev,
                        overflow_dev);
     uint32_t *sid = U(L.sid);
@@ -1323,10 +1326,10 @@ hipError_t launch_bin_sort(const darb_projected &p, int n, int width, int height
         const bool v64 = gx <= 255 && gy <= 255;
         uint2 *v64A = reinterpret_cast<uint2 *>(base + L.crec), *v64B = v64A + n;
         if (v64)
-            hipLaunchKernelGGL(k_bin_compact<true>, dim3(nkb), dim3(256), 0, s, p.xy, p.radius, p.depth, n, gx, gy,
+            hipLaunchKernelGGL(k_bin_compact<true>, dim3(nkb), dim3(256), 0, s, p.xy, ext, p.depth, n, gx, gy,
                                blockvis, kA, nullptr, nullptr, v64A, overflow_dev);
         else
-            hipLaunchKernelGGL(k_bin_compact<false>, dim3(nkb), dim3(256), 0, s, p.xy, p.radius, p.depth, n, gx, gy,
+            hipLaunchKernelGGL(k_bin_compact<false>, dim3(nkb), dim3(256), 0, s, p.xy, ext, p.depth, n, gx, gy,
                                blockvis, kA, vA, crec, nullptr, overflow_dev);
         // depth sort of the N_v visible keys: 4 passes of 8 bits
         const int nblk = (n + kRadixTile - 1) / kRadixTile;

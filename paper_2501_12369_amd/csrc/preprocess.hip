@@ -180,6 +180,7 @@ struct Proj {
     float u, v;           // mean2D (rounded)
     float l00, l01, l11;  // Q = L^T L, L = [[l00, l01], [0, l11]] (rounded)
     int radius;
+    int ex, ey;           // half-extents of the tile box
 };
 
 // t = R_cw mu + t_cw; false when the splat is not in front of the near plane.
@@ -191,7 +192,7 @@ __device__ __forceinline__ bool view_depth(const Cam &cam, const float (&m)[3], 
 }
 
 // The rest of the projection of a splat in front of the camera (P.t set);
-// false when culled (singular 2D covariance, or a radius box off the tile grid).
+// false when culled (singular 2D covariance, or a tile box off the tile grid).
 __device__ __forceinline__ bool project_rest(const Cam &cam, const KParams &kp, const Geom64 &G, Proj &P) {
     // one FP64 division (1/t_z) and reciprocals elsewhere: each product errs by an
     // FP64 rounding or two, far below the FP32 rounding of the records
@@ -236,13 +237,19 @@ __device__ __forceinline__ bool project_rest(const Cam &cam, const KParams &kp, 
     const double lam = mid + sqrt(disc > 0.0 ? disc : 0.0);
     const double rf = kp.e_max > 9.0f ? sqrt((double)kp.e_max) : 3.0;
     P.radius = (int)ceil(rf * sqrt(lam));
-    // radius box on the tile grid (the binning's FP32 expression on the stored mean)
+    // Tile box: the bounding box of the ellipse {d : d^T Sigma'^-1 d <= rf^2},
+    // half-extents rf sqrt(Sigma'_xx), rf sqrt(Sigma'_yy) rounded up to whole
+    // pixels.  It holds the support E <= e_max and lies inside the square of
+    // half-side R; the image does not depend on it (every pixel tests E).
+    P.ex = (int)ceil(rf * sqrt(c00));
+    P.ey = (int)ceil(rf * sqrt(c11));
+    // its rectangle on the tile grid (the binning's FP32 expression on the stored mean)
     int gx = (cam.width + kTile - 1) / kTile, gy = (cam.height + kTile - 1) / kTile;
-    float r = (float)P.radius;
-    float x0 = fminf(fmaxf(floorf((P.u - r) * 0.0625f), 0.0f), (float)gx);
-    float x1 = fminf(fmaxf(floorf((P.u + r) * 0.0625f) + 1.0f, 0.0f), (float)gx);
-    float y0 = fminf(fmaxf(floorf((P.v - r) * 0.0625f), 0.0f), (float)gy);
-    float y1 = fminf(fmaxf(floorf((P.v + r) * 0.0625f) + 1.0f, 0.0f), (float)gy);
+    const float rx = (float)P.ex, ry = (float)P.ey;
+    float x0 = fminf(fmaxf(floorf((P.u - rx) * 0.0625f), 0.0f), (float)gx);
+    float x1 = fminf(fmaxf(floorf((P.u + rx) * 0.0625f) + 1.0f, 0.0f), (float)gx);
+    float y0 = fminf(fmaxf(floorf((P.v - ry) * 0.0625f), 0.0f), (float)gy);
+    float y1 = fminf(fmaxf(floorf((P.v + ry) * 0.0625f) + 1.0f, 0.0f), (float)gy);
     if (!((x1 > x0) & (y1 > y0))) return false;
     return true;
 }
@@ -369,6 +376,7 @@ __device__ __forceinline__ void store_geom(const darb_projected &out, int i, boo
     reinterpret_cast<float2 *>(out.xy)[i] = vis ? make_float2(P.u, P.v) : make_float2(0.0f, 0.0f);
     out.depth[i] = vis ? (float)P.t[2] : 0.0f;
     out.radius[i] = vis ? P.radius : 0;
+    reinterpret_cast<int2 *>(out.extent)[i] = vis ? make_int2(P.ex, P.ey) : make_int2(0, 0);
     reinterpret_cast<float4 *>(out.conic_o)[i] = vis ? make_float4(P.l00, P.l01, P.l11, op) : make_float4(0, 0, 0, 0);
 }
 
@@ -426,7 +434,7 @@ __global__ __launch_bounds__(256) void k_preprocess(Cam cam_arg, const darb_came
 
 // The two parts of k_preprocess as separate launches, each with the same
 // arithmetic (so together they give its bits).  Geometry: the record the
-// binning reads (xy, depth, radius, conic and opacity).
+// binning reads (xy, depth, radius, tile box, conic and opacity).
 __global__ __launch_bounds__(256) void k_preprocess_geom(Cam cam, KParams kp, int n, darb_splats in,
                                                          darb_projected out) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;

@@ -49,6 +49,12 @@ constexpr int kPix = 4;    // pixels per lane with one wavefront per tile
 // splat passes their test and the walk needs no separate per-pixel state.
 constexpr float kFar = 3.0e30f;
 constexpr int kSplit = 2;  // wavefronts per tile in the forward kernel
+// The forward also tests for saturation inside a batch, after every this many
+// footprints that meet the wave's pixels (0: once per batch of 64 instances).
+#ifndef DARB_FWD_SAT_CHECK
+#define DARB_FWD_SAT_CHECK 4
+#endif
+constexpr int kFwdSatCheck = DARB_FWD_SAT_CHECK;
 
 // Pixels of this lane: column ix, rows iy0 + 4k for k < kPix / S.
 template <int S>
@@ -176,6 +182,8 @@ __device__ __forceinline__ void tile_fwd(const RView &V, int tile, int n, const 
         Rec R = load_rec(V.p, V.vals, j, j < end, n, kp.e_max, (float)(ix - (lane & 15)), P.ylo,
                          (float)(kTile / S - 1));
         int nb = (int)min(64u, end - base);
+        int since = 0;  // hit instances since the last saturation check (uniform)
+        bool fin = false;
         for (int s = 0; s < nb; s++) {
             if (!readlane_i(R.hit, s)) continue;  // footprint misses this tile (uniform)
             float sx = readlane_f(R.x, s), sy = readlane_f(R.y, s);
@@ -199,7 +207,22 @@ __device__ __forceinline__ void tile_fwd(const RView &V, int tile, int n, const 
                 F.lst[k] = ok ? pos : F.lst[k];
                 if constexpr (CNT) F.cnt[k] += ok ? 1u : 0u;
             }
+            // every kFwdSatCheck footprints, leave once all the wave's pixels
+            // saturated (no later instance changes them)
+            if constexpr (kFwdSatCheck > 0) {
+                if (++since == kFwdSatCheck) {
+                    since = 0;
+                    bool ad = true;
+#pragma unroll
+                    for (int k = 0; k < NP; k++) ad &= py[k] == kFar;
+                    if (__ballot(!ad) == 0) {
+                        fin = true;
+                        break;
+                    }
+                }
+            }
         }
+        if (fin) break;
     }
     Fout = F;
 }
@@ -795,7 +818,7 @@ void fwd_launch(const RViews &V, uint32_t items, int n, const KParams &kp, const
 #define DARB_BWD_HEAVY0 0
 #endif
 #ifndef DARB_BWD_HEAVY1
-#define DARB_BWD_HEAVY1 96
+#define DARB_BWD_HEAVY1 48
 #endif
 
 template <int KIND>

@@ -61,8 +61,8 @@ class darb_splats(ctypes.Structure):
 
 
 class darb_projected(ctypes.Structure):
-    _fields_ = [("xy", c_void_p), ("depth", c_void_p), ("radius", c_void_p), ("conic_o", c_void_p),
-                ("rgb", c_void_p), ("clamped", c_void_p), ("dcolor", c_void_p)]
+    _fields_ = [("xy", c_void_p), ("depth", c_void_p), ("radius", c_void_p), ("extent", c_void_p),
+                ("conic_o", c_void_p), ("rgb", c_void_p), ("clamped", c_void_p), ("dcolor", c_void_p)]
 
 
 class darb_grads2d(ctypes.Structure):
@@ -255,8 +255,8 @@ def splats_struct(sp: dict) -> darb_splats:
 
 
 def projected_struct(p: dict) -> darb_projected:
-    return darb_projected(_ptr(p["xy"]), _ptr(p["depth"]), _ptr(p["radius"]), _ptr(p.get("conic_o")),
-                          _ptr(p.get("rgb")), _ptr(p.get("clamped")), _ptr(p.get("dcolor")))
+    return darb_projected(_ptr(p["xy"]), _ptr(p["depth"]), _ptr(p["radius"]), _ptr(p["extent"]),
+                          _ptr(p.get("conic_o")), _ptr(p.get("rgb")), _ptr(p.get("clamped")), _ptr(p.get("dcolor")))
 
 
 def grads2d_struct(g: dict) -> darb_grads2d:

@@ -87,7 +87,8 @@ def alloc_projected(n: int, device="cuda", dcolor: bool = True) -> dict:
     backward reads instead of the SH coefficients (forward-only users skip it)."""
     f = dict(dtype=torch.float32, device=device)
     return dict(xy=torch.empty((n, 2), **f), depth=torch.empty(n, **f),
-                radius=torch.empty(n, dtype=torch.int32, device=device), conic_o=torch.empty((n, 4), **f),
+                radius=torch.empty(n, dtype=torch.int32, device=device),
+                extent=torch.empty((n, 2), dtype=torch.int32, device=device), conic_o=torch.empty((n, 4), **f),
                 rgb=torch.empty((n, 3), **f), clamped=torch.empty(n, dtype=torch.uint8, device=device),
                 dcolor=torch.empty((9, n), **f) if dcolor else None)
 

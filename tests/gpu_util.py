@@ -74,7 +74,8 @@ def projected_to_device(ps: dict) -> dict:
     """The device records: the conic as its factor (what the library stores)."""
     n = len(ps["radius"])
     co = np.concatenate([ps["conic_l"], ps["conic_o"][:, 3:4]], 1).astype(np.float32)
-    return dict(xy=dev(ps["xy"]), depth=dev(ps["depth"]), radius=dev(ps["radius"]), conic_o=dev(co),
+    return dict(xy=dev(ps["xy"]), depth=dev(ps["depth"]), radius=dev(ps["radius"]),
+                extent=dev(np.asarray(ps["extent"], np.int32).reshape(n, 2)), conic_o=dev(co),
                 rgb=dev(ps["rgb"]), clamped=torch.zeros(max(n, 1), dtype=torch.uint8, device="cuda")[:n])
 
 
@@ -177,9 +178,10 @@ def assert_records_fp32(proj: dict, o: dict, both: np.ndarray, ulps: int = 1, la
 def visibility_ambiguous(sp: dict, cam: dict, o: dict, idx, rel: float = 1e-5) -> np.ndarray:
     """For the splats ``idx`` whose culling differs between the two sides: True
     where a culling decision of the oracle lies within ``rel`` (relative) of its
-    threshold -- the near plane, the sign of the 2D determinant, the radius
-    3 sqrt(lambda_max) at an integer, or an edge of the radius box on the
-    image's tile border -- so FP32 rounding may take it either way."""
+    threshold -- the near plane, the sign of the 2D determinant, a tile-box
+    half-extent 3 sqrt(Sigma'_xx) or 3 sqrt(Sigma'_yy) at an integer, or an
+    edge of the tile box on the image's tile border -- so FP32 rounding may
+    take it either way."""
     idx = np.atleast_1d(np.asarray(idx, np.int64))
     V = np.asarray(cam["viewmat"], np.float64)
     mu = np.asarray(sp["means"], np.float64)[:, idx]
@@ -189,15 +191,29 @@ def visibility_ambiguous(sp: dict, cam: dict, o: dict, idx, rel: float = 1e-5) -
     cov = o["cov2d"][idx]
     det = cov[:, 0] * cov[:, 2] - cov[:, 1] ** 2
     out |= np.abs(det) <= rel * np.abs(cov[:, 0] * cov[:, 2])
-    mid = 0.5 * (cov[:, 0] + cov[:, 2])
-    r3 = 3.0 * np.sqrt(np.maximum(mid + np.sqrt(np.maximum(mid * mid - det, 0.0)), 0.0))
-    out |= np.abs(r3 - np.round(r3)) <= rel * np.maximum(r3, 1.0)
-    R = np.ceil(r3)
+    rx3 = 3.0 * np.sqrt(np.maximum(cov[:, 0], 0.0))
+    ry3 = 3.0 * np.sqrt(np.maximum(cov[:, 2], 0.0))
+    for r3 in (rx3, ry3):
+        out |= np.abs(r3 - np.round(r3)) <= rel * np.maximum(r3, 1.0)
+    RX, RY = np.ceil(rx3), np.ceil(ry3)
     with np.errstate(divide="ignore", invalid="ignore"):
         u = float(cam["fx"]) * t[0] / t[2] + float(cam["cx"])
         v = float(cam["fy"]) * t[1] / t[2] + float(cam["cy"])
     gx, gy = 16 * ((cam["width"] + 15) // 16), 16 * ((cam["height"] + 15) // 16)
-    scale = np.abs(u) + np.abs(v) + R + 1.0
-    for e in (u + R, u - R - gx, v + R, v - R - gy):
+    scale = np.abs(u) + np.abs(v) + RX + RY + 1.0
+    for e in (u + RX, u - RX - gx, v + RY, v - RY - gy):
         out |= np.abs(e) <= rel * scale
     return out
+
+
+def assert_extent(ext_gpu, ext_orc, cov, rf: float = 3.0) -> None:
+    """Tile-box half-extents [m, 2] of kept splats: equal to the oracle's unless
+    rf sqrt(Sigma'_xx) (or _yy) of the oracle's FP64 covariance ``cov`` [m, 3]
+    lies within 1e-4 (relative) of an integer, where the two FP64 chains may
+    round it to either side."""
+    ext_gpu, ext_orc = np.asarray(ext_gpu), np.asarray(ext_orc)
+    for j, c in ((0, 0), (1, 2)):
+        r = rf * np.sqrt(cov[:, c])
+        near_int = np.abs(r - np.round(r)) < 1e-4 * r
+        assert np.array_equal(ext_gpu[~near_int, j], ext_orc[~near_int, j]), j
+        assert np.all(np.abs(ext_gpu[near_int, j] - ext_orc[near_int, j]) <= 1), j

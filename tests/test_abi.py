@@ -44,7 +44,7 @@ def test_library_exports_every_declared_symbol(L):
 def test_version_and_status_strings(L):
     from paper_2501_12369_amd import native
 
-    assert native.darb_version() == 6
+    assert native.darb_version() == 7
     assert L.darb_status_string(0) == b"ok"
     assert L.darb_status_string(2) == b"instance capacity exceeded"
 
@@ -160,7 +160,7 @@ def test_noalloc_bin_sort_rejects_on_host(L):
     # null record pointers with n > 0
     st = L.darb_bin_sort_noalloc(ctypes.byref(pr), 10, 64, 64, 100, None, 4096, 8192, 12288, 16384, None, None)
     assert st == native.DARB_ERR_INVALID_ARG and b"null pointer" in L.darb_last_error()
-    pr.xy, pr.depth, pr.radius = 16 * 1000, 16 * 2000, 16 * 3000
+    pr.xy, pr.depth, pr.radius, pr.extent = 16 * 1000, 16 * 2000, 16 * 3000, 16 * 4000
     # null ranges
     st = L.darb_bin_sort_noalloc(ctypes.byref(pr), 10, 64, 64, 100, None, 4096, None, 12288, 16384, None, None)
     assert st == native.DARB_ERR_INVALID_ARG

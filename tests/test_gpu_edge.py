@@ -151,7 +151,7 @@ def test_support_limit_inclusive(kname):
     centres = [(10.0 + f, 10.0 + f), (30.0 + f, 12.0 + f), (20.0 + f, 30.0 + f)]
     n = len(centres)
     ps = dict(xy=np.asarray(centres, np.float32), depth=np.asarray([2.0, 3.0, 4.0], np.float32),
-              radius=np.full(n, 5, np.int32),
+              radius=np.full(n, 5, np.int32), extent=np.full((n, 2), 5, np.int32),
               conic_o=np.asarray([[1.0, 0.0, 1.0, 0.9]] * n, np.float32),
               conic_l=np.asarray([[1.0, 0.0, 1.0]] * n, np.float32),
               rgb=np.asarray([[0.9, 0.2, 0.1], [0.1, 0.8, 0.3], [0.2, 0.3, 0.7]], np.float32), width=48, height=40)

@@ -13,7 +13,7 @@ times (the plain render + render_backward path):
 Pixels whose oracle decisions sit within MARGIN (relative) of a threshold are
 left out of the samples, so both sides take the same decisions; images are held
 to 1e-5 relative + 1e-6.  Bin/sort is compared bit for bit on the full scene
-list (3M splats, about 86M instances) and the preprocess records element by
+list (3M splats, about 43M instances) and the preprocess records element by
 element at the scene size.
 
 The 3D gradients of scale and rotation of a needle-like footprint are small
@@ -30,7 +30,7 @@ import torch
 import oracle
 from paper_2501_12369_amd import pipeline, scenes
 
-from gpu_util import (assert_grads, assert_records_fp32, conic_from_factor, dev, grad_compare, oracle_kernel_fp32,
+from gpu_util import (assert_extent, assert_grads, assert_records_fp32, conic_from_factor, dev, grad_compare, oracle_kernel_fp32,
                       oracle_opts_fp32, to_np, visibility_ambiguous)
 
 pytestmark = pytest.mark.gpu
@@ -171,7 +171,7 @@ def test_scene_scale_sampled_image_and_sparse_gradients(kname):
 
 
 def test_scene_bin_sort_bit_exact():
-    """darb_bin_sort at the scene size (3M splats, 1297x840, about 86M
+    """darb_bin_sort at the scene size (3M splats, 1297x840, about 43M
     instances), bit for bit against the oracle's binning: K, every key and
     value, every tile range.  Both sides bin the oracle's projected records
     (its FP64 projection rounded to the FP32 boundary)."""
@@ -183,10 +183,11 @@ def test_scene_bin_sort_bit_exact():
                           sp["quats"], sp["sh"], 3)
     n = len(o["radius"])
     xy, depth, radius = o["xy"].astype(np.float32), o["depth"].astype(np.float32), o["radius"].astype(np.int32)
-    K_o, keys_o, vals_o, ranges_o = oracle.bin_sort(xy, radius, depth, W, H)
+    extent = o["extent"].astype(np.int32)
+    K_o, keys_o, vals_o, ranges_o = oracle.bin_sort(xy, extent, depth, W, H)
     print(f"  oracle K={K_o}", flush=True)
-    assert K_o > 50_000_000
-    proj = dict(xy=dev(xy), depth=dev(depth), radius=dev(radius),
+    assert K_o > 30_000_000
+    proj = dict(xy=dev(xy), depth=dev(depth), radius=dev(radius), extent=dev(extent),
                 conic_o=torch.zeros((n, 4), dtype=torch.float32, device="cuda"),
                 rgb=torch.zeros((n, 3), dtype=torch.float32, device="cuda"),
                 clamped=torch.zeros(n, dtype=torch.uint8, device="cuda"))
@@ -202,7 +203,7 @@ def test_scene_bin_sort_bit_exact():
 
 def test_scene_preprocess_records():
     """darb_preprocess at the scene size, every record element by element
-    against the oracle: mean2D, depth, colour, conic, opacity, radius; culling
+    against the oracle: mean2D, depth, colour, conic, opacity, radius, tile box; culling
     differs only where a decision is within rounding of its threshold."""
     print("full size: scene 3M preprocess records", flush=True)
     sc = scenes.scene(seed=3)
@@ -234,6 +235,7 @@ def test_scene_preprocess_records():
     r3 = 3 * np.sqrt(lam)
     near_int = np.abs(r3 - np.round(r3)) < 1e-4 * r3
     assert np.array_equal(rad[both][~near_int], o["radius"][both][~near_int])
+    assert_extent(to_np(proj["extent"])[both], o["extent"][both], cov)
     # colour clamp bits: equal unless the channel's value is within rounding of 0
     rgb_g, rgb_o = to_np(proj["rgb"])[both], o["rgb"][both]
     bits_g = (to_np(proj["clamped"])[both][:, None] >> np.arange(3)) & 1

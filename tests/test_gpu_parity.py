@@ -19,7 +19,7 @@ import torch
 import oracle
 from paper_2501_12369_amd import native, pipeline, scenes
 
-from gpu_util import (ORACLE_KERNELS, ambiguous_zeroed, assert_grads, assert_records_fp32, conic_from_factor,
+from gpu_util import (assert_extent, ORACLE_KERNELS, ambiguous_zeroed, assert_grads, assert_records_fp32, conic_from_factor,
                       decision_rings, dev,
                       gpu_bin_raster, grad_compare, image_pixels, last_ids, oracle_kernel_fp32, oracle_opts_fp32,
                       oracle_projected, projected_to_device, to_np, visibility_ambiguous)
@@ -51,7 +51,7 @@ def test_bin_sort_bit_exact(n, W, H, seed):
     ps = scenes.projected(seed, n, W, H, sigma_range=(0.3, 25.0))
     if n > 10:
         ps["depth"][::5] = ps["depth"][1]  # ties: equal depth keys must keep index order
-    K_o, keys_o, vals_o, ranges_o = oracle.bin_sort(ps["xy"], ps["radius"], ps["depth"], W, H)
+    K_o, keys_o, vals_o, ranges_o = oracle.bin_sort(ps["xy"], ps["extent"], ps["depth"], W, H)
     fr, K = gpu_bin_raster(ps, "half_cos", keys=True, cap=max(K_o, 1))
     assert K == K_o
     assert int(to_np(fr.k_dev)[0]) == K_o
@@ -67,7 +67,7 @@ def test_bin_sort_bit_exact_large_boxes(n, W, H, seed, sigma):
     # boxes spanning many 8x8-tile groups, and group lists longer than one chunk
     print(f"bin_sort large boxes n={n} {W}x{H} sigma={sigma}", flush=True)
     ps = scenes.projected(seed, n, W, H, sigma_range=sigma)
-    K_o, keys_o, vals_o, ranges_o = oracle.bin_sort(ps["xy"], ps["radius"], ps["depth"], W, H)
+    K_o, keys_o, vals_o, ranges_o = oracle.bin_sort(ps["xy"], ps["extent"], ps["depth"], W, H)
     fr, K = gpu_bin_raster(ps, "half_cos", keys=True, cap=K_o)
     assert K == K_o
     assert np.array_equal(to_np(fr.ranges).view(np.uint32), ranges_o)
@@ -79,12 +79,13 @@ def test_bin_sort_bit_exact_large_boxes(n, W, H, seed, sigma):
 def test_bin_sort_all_culled_and_overflow():
     ps = scenes.projected(7, 300, 96, 64)
     ps["radius"][:] = 0
+    ps["extent"][:] = 0
     fr, K = gpu_bin_raster(ps, "gauss", cap=16)
     assert K == 0 and np.all(to_np(fr.ranges) == 0)
     assert np.all(to_np(fr.final_T) == 1.0) and np.all(to_np(fr.image) == 0.0)
     # capacity overflow: flag set, K reported, raster writes nothing
     ps = scenes.projected(8, 300, 96, 64)
-    K_o, _, _, _ = oracle.bin_sort(ps["xy"], ps["radius"], ps["depth"], 96, 64)
+    K_o, _, _, _ = oracle.bin_sort(ps["xy"], ps["extent"], ps["depth"], 96, 64)
     proj = projected_to_device(ps)
     fr = pipeline.alloc_frame(300, 96, 64, K_o - 1, "cuda", proj=proj)
     # without the readback the call does not block and reports the overflow on the device
@@ -360,6 +361,8 @@ def test_preprocess_parity(kname, which):
     r3 = 3 * np.sqrt(lam)
     near_int = np.abs(r3 - np.round(r3)) < 1e-4 * r3
     assert np.array_equal(rad[both][~near_int], o["radius"][both][~near_int])
+    # tile box: exact unless 3 sqrt(Sigma'_xx) or 3 sqrt(Sigma'_yy) lies within 1e-4 of an integer
+    assert_extent(to_np(proj["extent"])[both], o["extent"][both], cov)
 
 
 @pytest.mark.parametrize("kname,ckpt", [("gauss", False), ("half_cos", False), ("parabola", False),

@@ -97,6 +97,6 @@ def test_multi_view_preprocess_with_device_cameras():
         q = pipeline.alloc_projected(n, dcolor=False)
         native.darb_preprocess(cam, kern, n, sp, q)
         torch.cuda.synchronize()
-        for k in ("xy", "depth", "radius", "conic_o", "rgb", "clamped"):
+        for k in ("xy", "depth", "radius", "extent", "conic_o", "rgb", "clamped"):
             assert torch.equal(p[k], q[k]), k
     assert len(host) == 3 * cb

@@ -22,7 +22,7 @@ def to_np(t):
 def run_both(ps, keys: bool):
     n = len(ps["radius"])
     W, H = ps["width"], ps["height"]
-    K_o, keys_o, vals_o, ranges_o = oracle.bin_sort(ps["xy"], ps["radius"], ps["depth"], W, H)
+    K_o, keys_o, vals_o, ranges_o = oracle.bin_sort(ps["xy"], ps["extent"], ps["depth"], W, H)
     cap = max(K_o, 1)
     proj = projected_to_device(ps)
     ref = pipeline.alloc_frame(n, W, H, cap, "cuda", keys=keys, proj=proj)
@@ -67,7 +67,7 @@ def test_noalloc_matches_workspace_call_twice(keys):
 def test_noalloc_rejects_beyond_scratch_and_reports_overflow():
     # beyond the scratch: a host-side error before any launch
     ps = scenes.projected(23, 64, 64, 64)
-    K_o, _, _, _ = oracle.bin_sort(ps["xy"], ps["radius"], ps["depth"], 64, 64)
+    K_o, _, _, _ = oracle.bin_sort(ps["xy"], ps["extent"], ps["depth"], 64, 64)
     assert K_o > 1
     proj = projected_to_device(ps)
     fr = pipeline.alloc_frame(64, 64, 64, K_o, "cuda", proj=proj)
