@@ -84,7 +84,7 @@ def measure_ceilings(reps: int = 5):
                 arch=getattr(props, "gcnArchName", ""))
 
 
-def survey_bytes(n, n_vis, K, P, pairs):
+def survey_bytes(n, n_vis, K, P, pairs, split=False):
     """Algorithmic bytes per stage as the survey's measurement plan counts them
     (one read of each needed input, one write of each output; the sort as one
     read + write pass of K keys and values):
@@ -94,11 +94,21 @@ def survey_bytes(n, n_vis, K, P, pairs):
       a4 raster forward    40 K_trav + 20 P
       a5 raster backward   76 K_trav + 32 P
       a6 preprocess bwd    308 N_v + 236 N
+    With the preprocess in two launches (split=True) a1 is divided between them
+    by what each moves of it: the geometry part reads the mean and cull data of
+    every splat (16 N) and scale, quaternion and opacity (32 B) of each visible
+    one, and writes the geometric 36 B of its record (xy, conic and opacity,
+    depth, radius, tile box); the colour part reads the 48 SH coefficients
+    (192 B) and writes the colour (12 B) of each visible splat:
+      geometry 16 N + 68 N_v,  colour 204 N_v  (together a1's 16 N + 272 N_v).
     K_trav, the instances a tile list traverses, is taken as the pairs up to each
     pixel's last blend divided by the 256 pixels of a tile."""
     k_trav = pairs / 256.0
-    return dict(preprocess=16 * n + 272 * n_vis, bin_sort=20 * n_vis + 36 * K, raster_fwd=40 * k_trav + 20 * P,
-                raster_bwd=76 * k_trav + 32 * P, preprocess_bwd=308 * n_vis + 236 * n)
+    d = dict(preprocess=16 * n + 272 * n_vis, bin_sort=20 * n_vis + 36 * K, raster_fwd=40 * k_trav + 20 * P,
+             raster_bwd=76 * k_trav + 32 * P, preprocess_bwd=308 * n_vis + 236 * n)
+    if split:
+        d.update(preprocess=16 * n + 68 * n_vis, colour=204 * n_vis)
+    return d
 
 
 def stage_bytes(n, n_vis, split=False):
@@ -108,11 +118,11 @@ def stage_bytes(n, n_vis, split=False):
       preprocess      12 B mean + 4 B cull data of every splat; 224 B of parameters
                       (scale, quaternion, opacity, 48 SH) read and 48 B of projected
                       record written per visible splat; the 36 B colour checkpoint
-                      (d colour / d direction) written for every splat:
-                                                                  52 N + 272 N_v
+                      (d colour / d direction) and the 8 B tile box written for
+                      every splat:                                60 N + 272 N_v
       split in two launches (split=True), the stage is the geometry part: mean,
-      scale, quaternion and opacity read (44 B), xy, depth, radius and conic_o
-      written (32 B), for every splat:                            76 N
+      scale, quaternion and opacity read (44 B), xy, depth, radius, tile box and
+      conic_o written (40 B), for every splat:                    84 N
       and the colour part beside the binning reads the radius (4 B) of every splat
       and the mean and 48 SH (204 B) of each visible one, and writes rgb, clamp
       bits and the colour checkpoint (49 B) of every splat:       53 N + 204 N_v
@@ -122,8 +132,8 @@ def stage_bytes(n, n_vis, split=False):
                       every splat (236 B):                        113 N_v + 240 N
     """
     if split:
-        return dict(preprocess=76 * n, colour=53 * n + 204 * n_vis, preprocess_bwd=113 * n_vis + 240 * n)
-    return dict(preprocess=52 * n + 272 * n_vis, preprocess_bwd=113 * n_vis + 240 * n)
+        return dict(preprocess=84 * n, colour=53 * n + 204 * n_vis, preprocess_bwd=113 * n_vis + 240 * n)
+    return dict(preprocess=60 * n + 272 * n_vis, preprocess_bwd=113 * n_vis + 240 * n)
 
 
 # kernel of each single-kernel stage, and the sources it is built from
@@ -606,7 +616,7 @@ def main():
     has = last != 0xFFFFFFFF
     pairs = int(torch.where(has, last - start + 1, torch.zeros_like(last)).sum())
     own = stage_bytes(n, n_vis, overlap)
-    svy = survey_bytes(n, n_vis, K, P, pairs)
+    svy = survey_bytes(n, n_vis, K, P, pairs, overlap)
     ceilings = measure_ceilings()
     log("measured ceilings: " + ", ".join(f"{k}={v}" for k, v in ceilings.items()))
 
