@@ -310,6 +310,17 @@ __device__ __forceinline__ void load_sh(const float *sh, int n, int i, float (&c
         for (int ch = 0; ch < 3; ch++) c[b][ch] = sh[(size_t)(b * 3 + ch) * n + i];
 }
 
+// The same loads marked non-temporal: the colour part beside the binning streams
+// its 576 MB of coefficients (3M splats, degree 3) without displacing the
+// binning kernels' working set from the caches.
+template <int NB>
+__device__ __forceinline__ void load_sh_nt(const float *sh, int n, int i, float (&c)[NB][3]) {
+#pragma unroll
+    for (int b = 0; b < NB; b++)
+#pragma unroll
+        for (int ch = 0; ch < 3; ch++) c[b][ch] = __builtin_nontemporal_load(sh + (size_t)(b * 3 + ch) * n + i);
+}
+
 // Camera constants from a darb_camera in device memory (same derivation as the
 // host path); the tile grid keeps the caller's width/height.  A camera with
 // non-positive focal lengths or near plane culls every splat.
@@ -380,12 +391,20 @@ __device__ __forceinline__ void store_geom(const darb_projected &out, int i, boo
     reinterpret_cast<float4 *>(out.conic_o)[i] = vis ? make_float4(P.l00, P.l01, P.l11, op) : make_float4(0, 0, 0, 0);
 }
 
-// ... and its colour part.
+// ... and its colour part (NT: the checkpoint, read only by the backward, is
+// stored non-temporal).
+template <bool NT = false>
 __device__ __forceinline__ void store_colour(const darb_projected &out, int n, int i, bool vis, const float (&col)[3],
                                              uint8_t cl, const float (&jac)[9]) {
     if (out.dcolor) {
 #pragma unroll
-        for (int k = 0; k < 9; k++) out.dcolor[(size_t)k * n + i] = vis ? jac[k] : 0.0f;
+        for (int k = 0; k < 9; k++) {
+            float *p = out.dcolor + (size_t)k * n + i;
+            if constexpr (NT)
+                __builtin_nontemporal_store(vis ? jac[k] : 0.0f, p);
+            else
+                *p = vis ? jac[k] : 0.0f;
+        }
     }
     out.rgb[3 * i] = col[0];
     out.rgb[3 * i + 1] = col[1];
@@ -474,13 +493,13 @@ __global__ __launch_bounds__(kColourThreads) void k_preprocess_colour(Cam cam, i
             float m[3];
             load_mean(in, n, i, m);
             float c[NB][3];
-            load_sh<NB>(in.sh, n, i, c);
+            load_sh_nt<NB>(in.sh, n, i, c);
             if (out.dcolor)
                 sh_colour<NB, true>(cam, m, c, col, cl, jac);
             else
                 sh_colour<NB, false>(cam, m, c, col, cl, jac);
         }
-        store_colour(out, n, i, vis, col, cl, jac);
+        store_colour<true>(out, n, i, vis, col, cl, jac);
     }
 }
 

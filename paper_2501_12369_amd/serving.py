@@ -180,6 +180,18 @@ class Scheduler:
         self.idle.move_to_end(s.key)
 
     def run(self, requests, keep_images: bool = False, poll_sleep: float = 20e-6):
+        # no cyclic garbage collection while requests are timed (a full collection
+        # over the process's tensors stalls the loop for milliseconds); it runs
+        # once the run is over
+        enabled = gc.isenabled()
+        gc.disable()
+        try:
+            return self._run(requests, keep_images, poll_sleep)
+        finally:
+            if enabled:
+                gc.enable()
+
+    def _run(self, requests, keep_images: bool, poll_sleep: float):
         pending = deque(sorted(requests, key=lambda r: r.arrival))
         queue = deque()
         results = []
@@ -404,7 +416,7 @@ class RenderServer:
     """Scenes resident on the GPU + a :class:`Scheduler` of :class:`RenderSlot`s."""
 
     def __init__(self, scenes: list, kernel, opts: dict | None = None, mem_budget: int = 24 << 30,
-                 max_slots: int = 8, k_margin: float = 1.5, n_probe: int = 4, max_inflight: int | None = None,
+                 max_slots: int = 8, k_margin: float = 2.0, n_probe: int = 16, max_inflight: int | None = None,
                  max_batch: int = 4):
         from . import pipeline
 
