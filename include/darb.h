@@ -87,8 +87,9 @@ typedef enum {
  * projection; Table 2).  A pixel is inside the footprint iff 0 <= E <= e_max
  * (boundaries of DARBFs: one main lobe, or n pulses).  The radius is
  * 3 sqrt(lambda_max) (DARB-Splatting section), widened to
- * sqrt(e_max lambda_max) when e_max > 9; the tile box uses the same factor.  The fixed kinds 0..6 require
- * 0 < e_max <= 9 and, for the trigonometric ones, a support inside the main
+ * sqrt(e_max lambda_max) when e_max > 9; the tile box uses the same factor.
+ * The fixed kinds 0..6 require 0 < e_max <= 9 and, for the trigonometric
+ * ones, a support inside the main
  * lobe (E/xi <= pi/2 for DARB_HALF_COS, sqrt(E)/xi <= pi for DARB_RAISED_COS
  * and DARB_SINC); the modified kinds 7..10 take 0 < beta <= 8 and
  * 0 < e_max <= 1024 and ignore nothing else.  beta is ignored by kinds 0..6. */
