@@ -312,6 +312,8 @@ static void transpose(const double *A, double *At, int r, int c) {
 /* projection; bounding radius of the DARBF boundaries section).            */
 /* ------------------------------------------------------------------------ */
 
+#define ORC_MAX_BOX_PX 1073741824.0 /* 2^30: the largest radius or tile-box half-extent */
+
 typedef struct {
     int visible;
     double t[3];   /* camera-space mean */
@@ -404,15 +406,16 @@ static void project_one(const orc_camera *cam, const orc_kernel *k, long n, long
     double disc = mid * mid - s->det;
     double lam = mid + sqrt(disc > 0.0 ? disc : 0.0);
     double rf = k->e_max > 9.0 ? sqrt(k->e_max) : 3.0;
-    s->radius = (int)ceil(rf * sqrt(lam));
+    /* sizes capped at 2^30 px (beyond any image): the int conversion stays defined */
+    s->radius = (int)ceil(fmin(rf * sqrt(lam), ORC_MAX_BOX_PX));
 
     /* Tile box: the bounding box of the ellipse {d : d^T Sigma'^-1 d <= rf^2},
      * whose half-extents are rf sqrt(Sigma'_xx) and rf sqrt(Sigma'_yy) (the
      * largest |d_x| on that ellipse), rounded up to whole pixels.  It holds the
      * support E <= e_max and lies inside the paper's square of half-side R;
      * the image does not depend on the box (every pixel tests E itself). */
-    s->ext[0] = (int)ceil(rf * sqrt(s->cov[0]));
-    s->ext[1] = (int)ceil(rf * sqrt(s->cov[3]));
+    s->ext[0] = (int)ceil(fmin(rf * sqrt(s->cov[0]), ORC_MAX_BOX_PX));
+    s->ext[1] = (int)ceil(fmin(rf * sqrt(s->cov[3]), ORC_MAX_BOX_PX));
 
     /* tile rectangle of that box on the 16x16 grid; empty => not visible */
     int gx = (cam->width + 15) / 16, gy = (cam->height + 15) / 16;

@@ -183,6 +183,8 @@ struct Proj {
     int ex, ey;           // half-extents of the tile box
 };
 
+constexpr double kMaxBoxPx = 1073741824.0;  // 2^30: the largest radius or tile-box half-extent
+
 // t = R_cw mu + t_cw; false when the splat is not in front of the near plane.
 __device__ __forceinline__ bool view_depth(const Cam &cam, const float (&m)[3], Proj &P) {
     for (int r = 0; r < 3; r++)
@@ -236,13 +238,15 @@ __device__ __forceinline__ bool project_rest(const Cam &cam, const KParams &kp, 
     const double disc = mid * mid - det;
     const double lam = mid + sqrt(disc > 0.0 ? disc : 0.0);
     const double rf = kp.e_max > 9.0f ? sqrt((double)kp.e_max) : 3.0;
-    P.radius = (int)ceil(rf * sqrt(lam));
+    // (sizes are capped at 2^30 px, beyond any image, so the conversion to int
+    // is defined for every finite covariance)
+    P.radius = (int)ceil(fmin(rf * sqrt(lam), kMaxBoxPx));
     // Tile box: the bounding box of the ellipse {d : d^T Sigma'^-1 d <= rf^2},
     // half-extents rf sqrt(Sigma'_xx), rf sqrt(Sigma'_yy) rounded up to whole
     // pixels.  It holds the support E <= e_max and lies inside the square of
     // half-side R; the image does not depend on it (every pixel tests E).
-    P.ex = (int)ceil(rf * sqrt(c00));
-    P.ey = (int)ceil(rf * sqrt(c11));
+    P.ex = (int)ceil(fmin(rf * sqrt(c00), kMaxBoxPx));
+    P.ey = (int)ceil(fmin(rf * sqrt(c11), kMaxBoxPx));
     // its rectangle on the tile grid (the binning's FP32 expression on the stored mean)
     int gx = (cam.width + kTile - 1) / kTile, gy = (cam.height + kTile - 1) / kTile;
     const float rx = (float)P.ex, ry = (float)P.ey;

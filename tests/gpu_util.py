@@ -175,11 +175,11 @@ def assert_records_fp32(proj: dict, o: dict, both: np.ndarray, ulps: int = 1, la
         assert np.all(d <= ulps * sp), name
 
 
-def visibility_ambiguous(sp: dict, cam: dict, o: dict, idx, rel: float = 1e-5) -> np.ndarray:
+def visibility_ambiguous(sp: dict, cam: dict, o: dict, idx, rel: float = 1e-5, rf: float = 3.0) -> np.ndarray:
     """For the splats ``idx`` whose culling differs between the two sides: True
     where a culling decision of the oracle lies within ``rel`` (relative) of its
     threshold -- the near plane, the sign of the 2D determinant, a tile-box
-    half-extent 3 sqrt(Sigma'_xx) or 3 sqrt(Sigma'_yy) at an integer, or an
+    half-extent rf sqrt(Sigma'_xx) or rf sqrt(Sigma'_yy) at an integer, or an
     edge of the tile box on the image's tile border -- so FP32 rounding may
     take it either way."""
     idx = np.atleast_1d(np.asarray(idx, np.int64))
@@ -191,8 +191,8 @@ def visibility_ambiguous(sp: dict, cam: dict, o: dict, idx, rel: float = 1e-5) -
     cov = o["cov2d"][idx]
     det = cov[:, 0] * cov[:, 2] - cov[:, 1] ** 2
     out |= np.abs(det) <= rel * np.abs(cov[:, 0] * cov[:, 2])
-    rx3 = 3.0 * np.sqrt(np.maximum(cov[:, 0], 0.0))
-    ry3 = 3.0 * np.sqrt(np.maximum(cov[:, 2], 0.0))
+    rx3 = rf * np.sqrt(np.maximum(cov[:, 0], 0.0))
+    ry3 = rf * np.sqrt(np.maximum(cov[:, 2], 0.0))
     for r3 in (rx3, ry3):
         out |= np.abs(r3 - np.round(r3)) <= rel * np.maximum(r3, 1.0)
     RX, RY = np.ceil(rx3), np.ceil(ry3)

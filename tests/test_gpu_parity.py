@@ -326,9 +326,10 @@ def test_preprocess_parts_bits(deg):
         assert np.array_equal(to_np(one[name]), to_np(two[name])), name
 
 
-@pytest.mark.parametrize("kname", ["gauss", "half_cos", "raised_cos"])
+@pytest.mark.parametrize("kname", ["gauss", "half_cos", "raised_cos", "raised_cos_n2"])
 @pytest.mark.parametrize("which", ["tiny", "object"])
 def test_preprocess_parity(kname, which):
+    # raised_cos_n2: two pulses, support E <= 25, so radius and tile box use sqrt(25) = 5 for 3
     sc = scenes.tiny(seed=1) if which == "tiny" else scenes.object_scale(seed=2, n=20000, width=800, height=800)
     sp, cam = sc["splats"], sc["camera"]
     n = sp["means"].shape[1]
@@ -345,7 +346,8 @@ def test_preprocess_parity(kname, which):
     # visibility may differ only where a culling decision is within rounding of its threshold
     diff = np.flatnonzero(vis_g != vis_o)
     print(f"  visibility differs for {len(diff)} of {n}")
-    assert np.all(visibility_ambiguous(sp, cam, o, diff)), diff
+    rf = math.sqrt(max(9.0, oracle_kernel_fp32(kname).e_max))
+    assert np.all(visibility_ambiguous(sp, cam, o, diff, rf=rf)), diff
     assert both.sum() > 0.3 * vis_o.sum() and both.sum() > 10
     # mean2D, depth and conic factor: the FP64 projection rounded to FP32, within 1 ulp
     assert_records_fp32(proj, o, both)
@@ -354,15 +356,44 @@ def test_preprocess_parity(kname, which):
     # colour (FP32 SH evaluation) relative
     assert np.allclose(rgb, o["rgb"][both], rtol=1e-5, atol=1e-6)
     assert np.array_equal(co[:, 3], sp["opacity"][both])
-    # radius: exact unless 3 sqrt(lambda_max) lies within 1e-4 of an integer
+    # radius: exact unless rf sqrt(lambda_max) lies within 1e-4 of an integer
     cov = o["cov2d"][both]
     mid = 0.5 * (cov[:, 0] + cov[:, 2])
     lam = mid + np.sqrt(np.maximum(mid * mid - (cov[:, 0] * cov[:, 2] - cov[:, 1] ** 2), 0))
-    r3 = 3 * np.sqrt(lam)
+    r3 = rf * np.sqrt(lam)
     near_int = np.abs(r3 - np.round(r3)) < 1e-4 * r3
     assert np.array_equal(rad[both][~near_int], o["radius"][both][~near_int])
-    # tile box: exact unless 3 sqrt(Sigma'_xx) or 3 sqrt(Sigma'_yy) lies within 1e-4 of an integer
-    assert_extent(to_np(proj["extent"])[both], o["extent"][both], cov)
+    # tile box: exact unless rf sqrt(Sigma'_xx) or rf sqrt(Sigma'_yy) lies within 1e-4 of an integer
+    assert_extent(to_np(proj["extent"])[both], o["extent"][both], cov, rf=rf)
+    ext = to_np(proj["extent"])[both]
+    assert np.all(ext <= rad[both][:, None]) and np.all(ext >= 1)
+
+
+def test_preprocess_huge_footprints():
+    """Footprints far larger than the image: radius and tile box capped at
+    2^30 px on both sides, the splat kept, its box covering the whole grid (the
+    records equal the oracle's; no integer conversion overflows)."""
+    n = 6
+    means = np.array([[0.0] * n, [0.0] * n, [1.0, 2.0, 5.0, 1.0, 3.0, 2.0]], np.float32)
+    scales = np.array([[1e7, 1e9, 1e5, 0.01, 1e12, 3.0]] * 3, np.float32)
+    quats = np.tile(np.array([[1.0], [0.2], [0.0], [0.0]], np.float32), (1, n))
+    sp = dict(means=means, scales=scales, quats=quats, opacity=np.full(n, 0.5, np.float32),
+              sh=np.zeros((1, 3, n), np.float32), sh_degree=0)
+    cam = scenes.camera(np.eye(4, dtype=np.float32), np.zeros(3, np.float32), 500.0, 500.0, 320.0, 240.0, 640, 480)
+    proj = pipeline.alloc_projected(n)
+    native.darb_preprocess(cam, pipeline.KERNELS["half_cos"], n, _splats_dev(sp), proj)
+    torch.cuda.synchronize()
+    o = oracle.preprocess(oracle.camera_from_scene(cam), oracle_kernel_fp32("half_cos"), means, scales, quats,
+                          sp["sh"], 0)
+    assert (o["visible"] == 1).all() and (to_np(proj["radius"]) > 0).all()
+    cap = 1 << 30
+    assert to_np(proj["radius"])[4] == cap and (to_np(proj["extent"])[4] == cap).all()
+    assert_extent(to_np(proj["extent"]), o["extent"], o["cov2d"])
+    # the capped splat covers every tile of the grid
+    fr = pipeline.alloc_frame(n, 640, 480, 1 << 16, "cuda", proj=proj)
+    K = pipeline.bin_sort(fr, read_k=True)
+    K_o, _, _, _ = oracle.bin_sort(to_np(proj["xy"]), to_np(proj["extent"]), to_np(proj["depth"]), 640, 480)
+    assert K == K_o and K >= pipeline.n_tiles(640, 480)
 
 
 @pytest.mark.parametrize("kname,ckpt", [("gauss", False), ("half_cos", False), ("parabola", False),

@@ -327,3 +327,28 @@ def test_records_fp32_round_each_stored_field():
     assert np.array_equal(r["conic"], rebuilt)
     # the rounded conic stays within FP32 rounding of the FP64 conic
     assert np.allclose(r["conic"][vis], p["conic"][vis], rtol=1e-6)
+
+
+def test_box_sizes_capped_for_huge_footprints(orc):
+    """Radius and tile-box half-extents are capped at 2^30 px (beyond any image),
+    so a huge footprint stays visible with a box covering the whole grid and
+    the integer sizes are defined; below the cap they are the plain values."""
+    n = 6
+    means = np.array([[0.0] * n, [0.0] * n, [1.0, 2.0, 5.0, 1.0, 3.0, 2.0]], np.float32)
+    scales = np.array([[1e7, 1e9, 1e5, 0.01, 1e12, 3.0]] * 3, np.float32)
+    quats = np.tile(np.array([[1.0], [0.2], [0.0], [0.0]], np.float32), (1, n))
+    sh = np.zeros((1, 3, n), np.float32)
+    cam = orc.make_camera(np.eye(4), np.zeros(3), 500.0, 500.0, 320.0, 240.0, 640, 480)
+    p = orc.preprocess(cam, orc.KernelSpec(oracle.HALF_COS, 18 / PI, 1.36, 9.0), means, scales, quats, sh, 0)
+    cap = 1 << 30
+    assert p["visible"].all()
+    for i in range(n):
+        a, b, c = p["cov2d"][i]
+        lam = 0.5 * (a + c) + math.sqrt(max(0.25 * (a - c) ** 2 + b * b, 0.0))
+        want_r = min(math.ceil(3 * math.sqrt(lam)), cap)
+        want_x, want_y = min(math.ceil(3 * math.sqrt(a)), cap), min(math.ceil(3 * math.sqrt(c)), cap)
+        assert abs(int(p["radius"][i]) - want_r) <= (0 if want_r == cap else 1)
+        assert abs(int(p["extent"][i, 0]) - want_x) <= (0 if want_x == cap else 1)
+        assert abs(int(p["extent"][i, 1]) - want_y) <= (0 if want_y == cap else 1)
+    assert p["radius"][4] == cap and (p["extent"][4] == cap).all()
+    assert 0 < p["radius"][3] < 100
