@@ -404,6 +404,66 @@ def variants_bench(spd, cam, steps: int, warmup: int):
     return out
 
 
+def small_configs_bench(steps: int, warmup: int, cpu: bool):
+    """The tiny (64 splats, 64x64; Gaussian and half-cosine) and object-scale
+    (100k splats, 800x800, SH degree 3, half-cosine) workloads: the GPU step
+    (preprocess, bin/sort, raster forward and backward, preprocess backward,
+    one stream) beside the FP64 oracle on all host threads and on one thread
+    (median of three runs each; the object's composite on a row sample, scaled
+    to the full view)."""
+    import torch
+
+    import oracle
+    from paper_2501_12369_amd import native, pipeline, scenes
+
+    rows = []
+    for name, sc, kname, every_all, every_one in (("tiny", scenes.tiny(seed=1), "gauss", 1, 1),
+                                                  ("tiny", scenes.tiny(seed=1), "half_cos", 1, 1),
+                                                  ("object", scenes.object_scale(seed=2), "half_cos", 4, 32)):
+        cam, kern = sc["camera"], pipeline.KERNELS[kname]
+        W, H = cam["width"], cam["height"]
+        spd = pipeline.splats_to_device(sc["splats"])
+        n = int(spd["means"].shape[1])
+        fr = pipeline.render(spd, cam, kern, k_capacity=max(64 * n, 1 << 16))
+        frame = pipeline.alloc_frame(n, W, H, int(fr.K * 1.1) + 4096, "cuda")
+        del fr
+        K = int(pipeline.render(spd, cam, kern, frame=frame, read_k=True).K)
+        G = torch.randn((3, H, W), device="cuda", generator=torch.Generator("cuda").manual_seed(3)) * 1e-4
+        grads = pipeline.alloc_grads(n, int(spd["sh_degree"]))
+
+        def step():
+            pipeline.render(spd, cam, kern, frame=frame, read_k=False, zero_g2d=grads[0])
+            pipeline.render_backward(frame, G, spd, cam, kern, grads=grads, g2d_zeroed=True)
+
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        gpu_s = (time.perf_counter() - t) / steps
+        assert int(frame.overflow[0].item()) == 0
+        row = dict(config=name, kernel=kname, n_splats=n, width=W, height=H, instances=K,
+                   gpu_ms=round(gpu_s * 1e3, 4), gpu_mpix_per_s=round(W * H / gpu_s / 1e6, 2))
+        if cpu:
+            nt = oracle.num_threads()
+            full = [cpu_oracle_run(sc, kname, every_all, nt, log_fn=lambda *a: None) for _ in range(3)]
+            one = [cpu_oracle_run(sc, kname, every_one, 1, log_fn=lambda *a: None) for _ in range(3)]
+            oracle.set_num_threads(nt)
+            v_all = float(np.median([r[0] for r in full]))
+            v_one = float(np.median([r[0] for r in one]))
+            row.update(cpu_all_mpix_per_s=round(v_all, 5), cpu_threads=nt, cpu_1core_mpix_per_s=round(v_one, 5),
+                       cpu_rows_every=(every_all, every_one),
+                       gpu_over_cpu_all=round(W * H / gpu_s / 1e6 / v_all, 1))
+        rows.append(row)
+        log(f"{name} {kname}: GPU {gpu_s*1e3:.3f} ms/step ({row['gpu_mpix_per_s']} Mpix/s, K={row['instances']})"
+            + (f"; oracle {row['cpu_all_mpix_per_s']} Mpix/s on {row['cpu_threads']} threads, "
+               f"{row['cpu_1core_mpix_per_s']} on 1" if cpu else ""))
+        del frame, grads, spd
+    return rows
+
+
 def multiview_bench(kernel_name: str, n: int, n_views: int, steps: int, warmup: int):
     """Batched multi-view training step: n clustered splats, n_views views at uneven
     resolutions, mean-L1 loss to random targets.  The multi-view step (one
@@ -469,6 +529,7 @@ def main():
     ap.add_argument("--no-overlap", action="store_true",
                     help="run the preprocess as one kernel instead of its colour part beside the binning")
     ap.add_argument("--cpu-rows-every", type=int, default=16)
+    ap.add_argument("--small-configs", type=int, default=1, help="0 skips the tiny and object-scale legs")
     ap.add_argument("--serve-seconds", type=float, default=5.0, help="0 disables the serving leg")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-mem-gb", type=float, default=96.0)
@@ -714,6 +775,14 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(sc, args.kernel, args.cpu_rows_every)
+        # the same view with the Gaussian profile (the oracle on all threads)
+        import oracle
+
+        other = "gauss" if args.kernel == "half_cos" else "half_cos"
+        v, sample, _ = cpu_oracle_run(sc, other, args.cpu_rows_every, oracle.num_threads())
+        cpu["other_kernel"] = dict(kernel=other, value=round(v, 6), unit="Mpix/s", cores=oracle.num_threads(),
+                                   sample=sample)
+    small = small_configs_bench(max(10, args.steps), 3, not args.no_cpu_baseline) if args.small_configs else None
     del frame, grads, spd
     torch.cuda.empty_cache()
     multiview_stats = None
@@ -753,6 +822,7 @@ def main():
         "stage_rooflines": stage_roofs,
         "step_roofline": step_roof,
         "cpu_baseline": cpu,
+        "small_configs": small,
         "multiview": multiview_stats,
         "serving": serving_stats,
     }
