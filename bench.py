@@ -22,7 +22,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# The survey's estimate of VALU lane-operations per (pixel, splat) pair -- E (5
+# An estimate of VALU lane-operations per (pixel, splat) pair -- E (5
 # FMA), the support and alpha tests, one transcendental, the 3 colour FMAs and
 # the T update in the forward; the backward adds the T recovery division, the 9
 # partial sums and the reduction.  Used only when no committed counter summary
@@ -84,10 +84,10 @@ def measure_ceilings(reps: int = 5):
                 arch=getattr(props, "gcnArchName", ""))
 
 
-def survey_bytes(n, n_vis, K, P, pairs, split=False):
-    """Algorithmic bytes per stage as the survey's measurement plan counts them
-    (one read of each needed input, one write of each output; the sort as one
-    read + write pass of K keys and values):
+def algorithmic_bytes(n, n_vis, K, P, pairs, split=False):
+    """Algorithmic bytes per stage by per-unit counts of what the method must
+    move (one read of each needed input, one write of each output; the sort as
+    one read + write pass of K keys and values):
       a1 preprocess        12 N + 224 N_v + 48 N_v + 4 N
       a2 duplicate         20 N_v + 12 K
       a3 sort              24 K
@@ -112,7 +112,7 @@ def survey_bytes(n, n_vis, K, P, pairs, split=False):
 
 
 def stage_bytes(n, n_vis, split=False):
-    """This build's own algorithmic HBM bytes per launch of the single-kernel
+    """The kernels' own algorithmic HBM bytes per launch of the single-kernel
     stages (one read of each input it needs, one write of each output), per
     splat / per visible splat:
       preprocess      12 B mean + 4 B cull data of every splat; 224 B of parameters
@@ -542,7 +542,7 @@ def main():
                     help="run a plain elementwise copy of this size (counter calibration for profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build has no multi-GPU path (requested --gpus {args.gpus}); "
+        print(f"bench.py measures one GPU: it has no multi-GPU path (requested --gpus {args.gpus}); "
               f"run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
@@ -684,7 +684,7 @@ def main():
     has = last != 0xFFFFFFFF
     pairs = int(torch.where(has, last - start + 1, torch.zeros_like(last)).sum())
     own = stage_bytes(n, n_vis, overlap)
-    svy = survey_bytes(n, n_vis, K, P, pairs, overlap)
+    svy = algorithmic_bytes(n, n_vis, K, P, pairs, overlap)
     ceilings = measure_ceilings()
     log("measured ceilings: " + ", ".join(f"{k}={v}" for k, v in ceilings.items()))
 
@@ -701,7 +701,7 @@ def main():
 
     def valu(stage, t_ms, kernel, ops_per_pair):
         # counted VALU lane-operations (VALU instructions x 64 lanes) when the
-        # committed counter summary matches the sources, else the survey's
+        # committed counter summary matches the sources, else the
         # per-pair estimate
         insts = measured_valu_insts(stage)
         if insts is not None:
@@ -742,7 +742,7 @@ def main():
     if r["bound"] == "hbm":
         roofline = dict(bound="hbm", achieved=r["achieved"], peak=PEAK_HBM_GBS, unit="GB/s", frac=r["frac"],
                         traffic=traffic, kernel=r["kernel"], kernel_us=r["us"],
-                        algorithmic_bytes=r["algorithmic_bytes"], bytes_rule="survey per-unit counts",
+                        algorithmic_bytes=r["algorithmic_bytes"], bytes_rule="per-unit algorithmic counts",
                         own_bytes=r.get("own_bytes"), own_frac=r.get("own_frac"),
                         measured_peak=ceilings["copy_gbs"], frac_of_measured=r["frac_of_measured"])
     else:

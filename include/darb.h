@@ -50,7 +50,7 @@ typedef enum {
     DARB_ERR_INVALID_ARG = 1, /* null/misaligned pointer, negative count, bad size, unknown kind */
     DARB_ERR_CAPACITY = 2,    /* instance count exceeds the capacity (only reported by a blocking call) */
     DARB_ERR_HIP = 3,         /* a HIP runtime call failed; darb_last_error() names it */
-    DARB_ERR_UNSUPPORTED = 4  /* valid request outside what this build implements */
+    DARB_ERR_UNSUPPORTED = 4  /* valid request outside what the library implements */
 } darb_status;
 
 /* Kernel profiles F(E), E = d_M^2 (Table 1 and the per-kernel supplementary
