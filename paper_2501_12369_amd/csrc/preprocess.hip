@@ -476,12 +476,15 @@ __global__ __launch_bounds__(256) void k_preprocess_geom(Cam cam, KParams kp, in
 // Colour: the SH colour, clamp bits and colour checkpoint of the splats the
 // geometry part kept (radius > 0; a kept splat's radius is at least 1).  It is
 // meant to run beside the binning on a second stream, so it is launched with
-// one two-wavefront workgroup per compute unit looping over the splats: a full
-// grid of memory-bound waves would take the compute units from the
+// three one-wavefront workgroups per compute unit looping over the splats: a
+// full grid of memory-bound waves would take the compute units from the
 // latency-bound binning kernels and slow them by about its own duration.
-constexpr int kColourThreads = 128;
+#ifndef DARB_COLOUR_THREADS
+#define DARB_COLOUR_THREADS 64
+#endif
+constexpr int kColourThreads = DARB_COLOUR_THREADS;  // threads per workgroup (a tuning constant)
 #ifndef DARB_COLOUR_WGS_PER_CU
-#define DARB_COLOUR_WGS_PER_CU 2
+#define DARB_COLOUR_WGS_PER_CU 3
 #endif
 constexpr int kColourWgsPerCu = DARB_COLOUR_WGS_PER_CU;  // workgroups per compute unit (a tuning constant)
 
