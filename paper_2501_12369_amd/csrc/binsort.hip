@@ -50,7 +50,10 @@ constexpr int kSuper = 8;                                 // super-tile = 8x8 ti
 constexpr int kL1Threads = 256;                           // splats per level-1 chunk
 constexpr int kL2Threads = 256;                           // list entries per level-2 chunk
 constexpr int kL2Waves = kL2Threads / 64;
-constexpr int kL2Grid = 8192;                             // persistent level-2 workgroups
+#ifndef DARB_L2_GRID
+#define DARB_L2_GRID 8192
+#endif
+constexpr int kL2Grid = DARB_L2_GRID;                     // persistent level-2 workgroups (a tuning constant)
 
 struct Counters {
     uint32_t n_visible;  // N_v
