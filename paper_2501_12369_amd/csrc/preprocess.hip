@@ -791,8 +791,13 @@ struct Ckpt {
     const int32_t *radius;  // kept iff radius > 0
 };
 
+#ifndef DARB_PBWD_THREADS
+#define DARB_PBWD_THREADS 256
+#endif
+constexpr int kPbwdThreads = DARB_PBWD_THREADS;  // threads per workgroup (a tuning constant)
+
 template <int DEG, bool CKPT>
-__global__ __launch_bounds__(256) void k_preprocess_bwd(Cam cam, KParams kp, int n, darb_splats in, Ckpt ck,
+__global__ __launch_bounds__(kPbwdThreads) void k_preprocess_bwd(Cam cam, KParams kp, int n, darb_splats in, Ckpt ck,
                                                         darb_grads2d g2, darb_grads3d g3, int accumulate) {
     constexpr int NB = (DEG + 1) * (DEG + 1);
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -995,25 +1000,27 @@ hipError_t launch_preprocess_multi(const Cams &cams, const KParams &kp, int n, c
     return hipGetLastError();
 }
 
-#define DARB_DEG_SWITCH_B(deg, K, B, grid, s, ...)                                          \
+#define DARB_DEG_SWITCH_B(deg, K, B, grid, T, s, ...)                                       \
     switch (deg) {                                                                          \
-    case 0: hipLaunchKernelGGL((K<0, B>), grid, dim3(256), 0, s, __VA_ARGS__); break;       \
-    case 1: hipLaunchKernelGGL((K<1, B>), grid, dim3(256), 0, s, __VA_ARGS__); break;       \
-    case 2: hipLaunchKernelGGL((K<2, B>), grid, dim3(256), 0, s, __VA_ARGS__); break;       \
-    default: hipLaunchKernelGGL((K<3, B>), grid, dim3(256), 0, s, __VA_ARGS__); break;      \
+    case 0: hipLaunchKernelGGL((K<0, B>), grid, dim3(T), 0, s, __VA_ARGS__); break;         \
+    case 1: hipLaunchKernelGGL((K<1, B>), grid, dim3(T), 0, s, __VA_ARGS__); break;         \
+    case 2: hipLaunchKernelGGL((K<2, B>), grid, dim3(T), 0, s, __VA_ARGS__); break;         \
+    default: hipLaunchKernelGGL((K<3, B>), grid, dim3(T), 0, s, __VA_ARGS__); break;        \
     }
 
 hipError_t launch_preprocess_bwd(const Cam &cam, const KParams &kp, int n, const darb_splats &in,
                                  const darb_projected *ckpt, const darb_grads2d &g2d, const darb_grads3d &g3d,
                                  bool accumulate, hipStream_t s) {
     if (n == 0) return hipSuccess;
-    dim3 grid((n + 255) / 256);
+    dim3 grid((n + kPbwdThreads - 1) / kPbwdThreads);
     const int acc = accumulate ? 1 : 0;
     const Ckpt ck{ckpt ? ckpt->dcolor : nullptr, ckpt ? ckpt->clamped : nullptr, ckpt ? ckpt->radius : nullptr};
     if (ck.dcolor && ck.clamped && ck.radius) {
-        DARB_DEG_SWITCH_B(in.sh_degree, k_preprocess_bwd, true, grid, s, cam, kp, n, in, ck, g2d, g3d, acc)
+        DARB_DEG_SWITCH_B(in.sh_degree, k_preprocess_bwd, true, grid, kPbwdThreads, s, cam, kp, n, in, ck, g2d, g3d,
+                          acc)
     } else {
-        DARB_DEG_SWITCH_B(in.sh_degree, k_preprocess_bwd, false, grid, s, cam, kp, n, in, ck, g2d, g3d, acc)
+        DARB_DEG_SWITCH_B(in.sh_degree, k_preprocess_bwd, false, grid, kPbwdThreads, s, cam, kp, n, in, ck, g2d, g3d,
+                          acc)
     }
     return hipGetLastError();
 }
@@ -1025,9 +1032,9 @@ hipError_t launch_preprocess_bwd_multi(const Cams &cams, const KParams &kp, int 
     bool ckpt = true;
     for (int v = 0; v < cams.nv; v++) ckpt = ckpt && g2.dcolor[v] && g2.clamped[v];
     if (ckpt) {
-        DARB_DEG_SWITCH_B(in.sh_degree, k_preprocess_bwd_multi, true, grid, s, cams, kp, n, in, g2, g3d)
+        DARB_DEG_SWITCH_B(in.sh_degree, k_preprocess_bwd_multi, true, grid, 256, s, cams, kp, n, in, g2, g3d)
     } else {
-        DARB_DEG_SWITCH_B(in.sh_degree, k_preprocess_bwd_multi, false, grid, s, cams, kp, n, in, g2, g3d)
+        DARB_DEG_SWITCH_B(in.sh_degree, k_preprocess_bwd_multi, false, grid, 256, s, cams, kp, n, in, g2, g3d)
     }
     return hipGetLastError();
 }
