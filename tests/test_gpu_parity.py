@@ -435,9 +435,11 @@ def test_preprocess_bwd_parity(kname, ckpt):
 
 # ---------------------------------------------------------------- end to end (tiny)
 
-@pytest.mark.parametrize("kname", ["gauss", "half_cos"])
-@pytest.mark.parametrize("dilation", [0.3, 0.0])
+@pytest.mark.parametrize("kname,dilation", [(k, e) for k in ("gauss", "half_cos") for e in (0.3, 0.0)] +
+                         [(k, 0.3) for k in ("gauss_b4", "half_cos_b1", "raised_cos_n2", "sinc_n3")])
 def test_end_to_end_tiny(kname, dilation):
+    # the modified forms run the whole path too: their tile boxes take the factor
+    # sqrt(e_max) beyond E = 9 (two raised-cosine pulses: 5, three sinc pulses: 6)
     sc = scenes.tiny(seed=1, dilation=dilation)
     sp, cam = sc["splats"], sc["camera"]
     n = sp["means"].shape[1]
