@@ -181,11 +181,12 @@ __device__ __forceinline__ void tile_fwd(const RView &V, int tile, int n, const 
         uint32_t j = base + lane;
         Rec R = load_rec(V.p, V.vals, j, j < end, n, kp.e_max, (float)(ix - (lane & 15)), P.ylo,
                          (float)(kTile / S - 1));
-        int nb = (int)min(64u, end - base);
         int since = 0;  // hit instances since the last saturation check (uniform)
         bool fin = false;
-        for (int s = 0; s < nb; s++) {
-            if (!readlane_i(R.hit, s)) continue;  // footprint misses this tile (uniform)
+        // the batch's footprints that meet this wave's pixels, in list order: the
+        // set bits of one ballot (the walk skips the others without a test each)
+        for (uint64_t hm = __ballot(R.hit != 0); hm != 0; hm &= hm - 1) {
+            const int s = (int)__builtin_ctzll(hm);
             float sx = readlane_f(R.x, s), sy = readlane_f(R.y, s);
             float sa = readlane_f(R.a, s), sb = readlane_f(R.b, s), sc = readlane_f(R.c, s);
             float so = readlane_f(R.o, s);
@@ -368,8 +369,9 @@ __device__ __forceinline__ void tile_bwd(const RView &V, int tile, uint32_t item
         // lane s keeps the reduced partials of the batch's s-th instance
         float m[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         uint64_t touched = 0;  // lanes whose instance received a contribution (uniform)
-        for (int s = 0; s < (int)cntb; s++) {
-            if (!readlane_i(R.hit, s)) continue;  // footprint misses this tile (uniform)
+        // the batch's footprints that meet this wave's pixels, in walk order
+        for (uint64_t hm = __ballot(R.hit != 0); hm != 0; hm &= hm - 1) {
+            const int s = (int)__builtin_ctzll(hm);
             float sx = readlane_f(R.x, s), sy = readlane_f(R.y, s);
             float sa = readlane_f(R.a, s), sb = readlane_f(R.b, s), sc = readlane_f(R.c, s);
             float so = readlane_f(R.o, s);
