@@ -464,10 +464,11 @@ def small_configs_bench(steps: int, warmup: int, cpu: bool):
     return rows
 
 
-def multiview_bench(kernel_name: str, n: int, n_views: int, steps: int, warmup: int):
+def multiview_bench(kernel_name: str, n: int, n_views: int, steps: int, warmup: int, bin_streams: int = 4):
     """Batched multi-view training step: n clustered splats, n_views views at uneven
     resolutions, mean-L1 loss to random targets.  The multi-view step (one
-    preprocess launch, a bin/sort per view, one fused forward+loss+backward launch
+    preprocess launch, the views' bin/sorts on ``bin_streams`` concurrent
+    streams, one fused forward+loss+backward launch
     over all views' tiles, one summed preprocess backward) against the same step
     as single-view calls made view after view."""
     import torch
@@ -503,8 +504,8 @@ def multiview_bench(kernel_name: str, n: int, n_views: int, steps: int, warmup: 
         assert not pipeline.multiview_overflowed(mf), "instance capacity overflow during timing"
         return dt
 
-    fused = timed(lambda: pipeline.multiview_step(spd, mf, targets, kern, g3d, fused=True))
-    split = timed(lambda: pipeline.multiview_step(spd, mf, targets, kern, g3d, fused=False))
+    fused = timed(lambda: pipeline.multiview_step(spd, mf, targets, kern, g3d, fused=True, bin_streams=bin_streams))
+    split = timed(lambda: pipeline.multiview_step(spd, mf, targets, kern, g3d, fused=False, bin_streams=bin_streams))
     seq = timed(lambda: pipeline.sequential_step(spd, mf, targets, kern, g3d))
     K = sum(fr.K for fr in mf.frames)
     log(f"multiview {n_views} views, {pix/1e6:.2f} Mpix, K={K}: fused {fused*1e3:.3f} ms, "
@@ -513,6 +514,7 @@ def multiview_bench(kernel_name: str, n: int, n_views: int, steps: int, warmup: 
     return dict(workload=f"{n} clustered splats (SH degree 3), {n_views} views at uneven resolutions "
                          f"{sizes}, {kernel_name} DARBF, mean-L1 loss, fwd+bwd training step",
                 pixels=pix, instances=int(K),
+                bin_streams=bin_streams,
                 fused_ms=round(fused * 1e3, 4), multi_ms=round(split * 1e3, 4), sequential_ms=round(seq * 1e3, 4),
                 fused_mpix_per_s=round(pix / fused / 1e6, 2), sequential_mpix_per_s=round(pix / seq / 1e6, 2),
                 speedup_vs_sequential=round(seq / fused, 3))
@@ -537,6 +539,8 @@ def main():
     ap.add_argument("--serve-batch", type=int, default=4, help="requests per multi-view graph replay")
     ap.add_argument("--multiview-views", type=int, default=8, help="0 disables the multi-view leg")
     ap.add_argument("--multiview-n", type=int, default=2_000_000)
+    ap.add_argument("--multiview-bin-streams", type=int, default=4,
+                    help="concurrent streams for the views' bin/sorts in the multi-view step")
     ap.add_argument("--variants", type=int, default=1, help="0 skips the Gaussian and autograd steps")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="run a plain elementwise copy of this size (counter calibration for profiling runs)")
@@ -788,7 +792,7 @@ def main():
     multiview_stats = None
     if args.multiview_views > 0:
         multiview_stats = multiview_bench(args.kernel, args.multiview_n, args.multiview_views, max(3, args.steps // 2),
-                                          2)
+                                          2, bin_streams=args.multiview_bin_streams)
         torch.cuda.empty_cache()
     serving_stats = None
     if args.serve_seconds > 0:

@@ -263,6 +263,7 @@ class MultiFrame:
     g2d: list
     dL: list
     det_ws: torch.Tensor | None = None
+    side: list | None = None  # side streams of the concurrent per-view bin/sorts
 
     @property
     def n(self) -> int:
@@ -308,11 +309,38 @@ def multiview_overflowed(mf: MultiFrame) -> bool:
     return again
 
 
+def multiview_bin_sort(mf: MultiFrame, bin_streams: int = 4, stream=None):
+    """Bin/sort of every view.  The views' bin/sorts are independent (each frame
+    has its own workspace, lists and counters) and each is a chain of ~20 small,
+    latency-bound launches, so with ``bin_streams`` > 1 they run on that many
+    side streams (default priority), forked from and joined to ``stream``
+    (default: the current stream); the lists are the same either way."""
+    n = mf.n
+    main = stream if stream is not None else torch.cuda.current_stream()
+    k = min(int(bin_streams), len(mf.frames))
+    if k <= 1:
+        for fr in mf.frames:
+            native.darb_bin_sort(fr.proj, n, fr.width, fr.height, fr.capacity, fr.ws, None, fr.vals, fr.ranges,
+                                 fr.k_dev, fr.overflow, stream=main)
+        return
+    if mf.side is None or len(mf.side) < k:
+        mf.side = [torch.cuda.Stream(device=mf.frames[0].vals.device) for _ in range(k)]
+    side = mf.side[:k]
+    for s in side:
+        s.wait_stream(main)
+    for v, fr in enumerate(mf.frames):
+        native.darb_bin_sort(fr.proj, n, fr.width, fr.height, fr.capacity, fr.ws, None, fr.vals, fr.ranges, fr.k_dev,
+                             fr.overflow, stream=side[v % k])
+    for s in side:
+        main.wait_stream(s)
+
+
 def multiview_step(splats: dict, mf: MultiFrame, targets: list, kernel: KernelSpec, g3d: dict,
                    opts: dict | None = None, loss_kind: int = native.LOSS_L1, fused: bool = True,
-                   deterministic: bool = False, stream=None):
+                   deterministic: bool = False, stream=None, bin_streams: int = 4):
     """One training step over all views: preprocess (one launch) -> bin/sort per
-    view -> raster forward + loss + backward (one fused launch, or forward launch,
+    view (concurrently on ``bin_streams`` side streams, :func:`multiview_bin_sort`)
+    -> raster forward + loss + backward (one fused launch, or forward launch,
     per-view loss and backward launch) -> preprocess backward summed over the
     views (one launch) into ``g3d``.  Nothing is read back; a view whose list
     overflowed is skipped (check with :func:`multiview_overflowed`)."""
@@ -320,9 +348,7 @@ def multiview_step(splats: dict, mf: MultiFrame, targets: list, kernel: KernelSp
     n = mf.n
     views = multiview_views(mf, targets=targets, with_dL=not fused or deterministic)
     native.darb_preprocess_multi(views, kernel, n, splats, stream=stream)
-    for fr in mf.frames:
-        native.darb_bin_sort(fr.proj, n, fr.width, fr.height, fr.capacity, fr.ws, None, fr.vals, fr.ranges, fr.k_dev,
-                             fr.overflow, stream=stream)
+    multiview_bin_sort(mf, bin_streams, stream=stream)
     if fused and not deterministic:
         native.darb_raster_fwdbwd_multi(views, n, kernel, opts, loss_kind, stream=stream)
     else:
